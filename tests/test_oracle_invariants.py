@@ -1,0 +1,208 @@
+"""Method-level pins of the oracle (CPU only): free-stream preservation,
+discrete conservation, the closed forms of the time marching, the S1O2
+residual identity behind the multigrid fixed point, and the design order
+of accuracy on a smooth solution."""
+import numpy as np
+import pytest
+
+import oracle
+import paper_2109_09965_amd.inputs as I
+
+
+def run_cycles(mesh, params, W, dW, n):
+    s = oracle.Solver(oracle.Mesh(mesh), params)
+    res = [s.cycle(W, dW) for _ in range(n)]
+    return s, res
+
+
+@pytest.mark.parametrize("mk,mach,aoa,mu,Pr", [
+    (lambda: I.cylinder_mesh(32, 16, wall=I.BC_FARFIELD), 0.2, 3.0, 0.0, 1.0),
+    (lambda: I.sphere_mesh(8, 16, 8, 3, 2, wall=I.BC_FARFIELD), 0.25, 10.0, 0.01, 0.72),
+    (lambda: I.box2d_mesh(8, perturb=0.3, seed=2), 0.5, 30.0, 0.02, 0.72),
+    (lambda: I.box3d_mesh((3, 3, 5), periodic=True, perturb=0.2, seed=4), 0.4, 20.0, 0.01, 0.72),
+])
+def test_free_stream_is_preserved(mk, mach, aoa, mu, Pr):
+    mesh = mk()
+    d = mesh["dim"]
+    Winf = I.free_stream(d, mach, aoa)
+    W, dW = I.uniform_state(mesh, Winf)
+    _, res = run_cycles(mesh, oracle.Params(W_inf=Winf, mu=mu, Pr=Pr), W, dW, 20)
+    assert np.abs(W - Winf[:, None]).max() <= 1e-13
+    assert np.abs(dW).max() <= 1e-12
+    assert max(res) <= 1e-14
+
+
+@pytest.mark.parametrize("mk", [lambda: I.box2d_mesh(8, perturb=0.3, seed=2),
+                                lambda: I.box3d_mesh((3, 3, 5), periodic=True, perturb=0.2, seed=4)])
+@pytest.mark.parametrize("scheme", [oracle.S2O4, oracle.S1O2])
+def test_periodic_conservation(mk, scheme):
+    """Each face flux enters its two cells with opposite signs: the high-order
+    stages conserve sum |V| W and the residuals of both levels sum to zero."""
+    mesh = mk()
+    d = mesh["dim"]
+    Winf = I.free_stream(d, 0.3, 15.0)
+    W, dW = I.smooth_state(mesh, Winf, seed=3, amp=0.05)
+    om = oracle.Mesh(mesh)
+    vol = om.cells()["vol"]
+    s = oracle.Solver(om, oracle.Params(W_inf=Winf, mu=0.01, Pr=0.72, time_scheme=scheme))
+    tot0 = W @ vol
+    s.stage(0, W, dW)
+    np.testing.assert_allclose(W @ vol, tot0, rtol=1e-14, atol=1e-14)
+    if scheme == oracle.S2O4:
+        s.stage(1, W, dW)
+        np.testing.assert_allclose(W @ vol, tot0, rtol=1e-14, atol=1e-14)
+    R1 = s.residual_high(W, dW)
+    R0 = s.residual_low(W)
+    assert np.abs(R1.sum(1)).max() <= 1e-13 * np.abs(R1).sum()
+    assert np.abs(R0.sum(1)).max() <= 1e-13 * np.abs(R0).sum()
+
+
+@pytest.mark.parametrize("mk,bc", [
+    (lambda bc: I.box2d_mesh(8, periodic=False, perturb=0.3, seed=2, bc=bc), I.BC_SLIP_WALL),
+    (lambda bc: I.box3d_mesh((3, 3, 5), perturb=0.2, seed=4, bc=bc), I.BC_SLIP_WALL),
+    (lambda bc: I.box3d_mesh((3, 3, 5), perturb=0.2, seed=4, bc=bc), I.BC_NOSLIP_ISOTHERMAL),
+])
+def test_walls_carry_no_mass(mk, bc):
+    """A closed box with slip walls conserves mass and energy in the
+    high-order stages (the mirrored interface state has no normal mass or
+    energy flux); with no-slip isothermal walls mass is conserved."""
+    mesh = mk(bc)
+    d = mesh["dim"]
+    Winf = I.free_stream(d, 0.3, 15.0)
+    W, dW = I.smooth_state(mesh, Winf, seed=5, amp=0.05)
+    om = oracle.Mesh(mesh)
+    vol = om.cells()["vol"]
+    s = oracle.Solver(om, oracle.Params(W_inf=Winf, mu=0.01, Pr=0.72))
+    tot0 = W @ vol
+    s.stage(0, W, dW)
+    s.stage(1, W, dW)
+    tot = W @ vol
+    assert tot[0] == pytest.approx(tot0[0], rel=1e-14)
+    if bc == I.BC_SLIP_WALL:
+        assert tot[-1] == pytest.approx(tot0[-1], rel=1e-14)
+    R1 = s.residual_high(W, dW)
+    assert abs(R1[0].sum()) <= 1e-13 * np.abs(R1[0]).sum()
+
+
+@pytest.mark.parametrize("z", [-0.9, -0.3, 0.05, 0.5, 1.2])
+def test_time_marching_closed_forms(z):
+    """y' = lam y with L = lam y and L_t = lam^2 y: S2O4 reproduces the
+    fourth-order Taylor polynomial, S1O2 the second-order one."""
+    lam, y, dt = 1.7, 1.3, z / 1.7
+    ys = oracle.stage_combine(oracle.S2O4, 0, dt, y, lam * y, lam * lam * y)
+    y1 = oracle.stage_combine(oracle.S2O4, 1, dt, y, lam * y, lam * lam * y, lam * lam * ys)
+    assert y1 == pytest.approx(y * (1 + z + z * z / 2 + z ** 3 / 6 + z ** 4 / 24), rel=1e-14)
+    y2 = oracle.stage_combine(oracle.S1O2, 0, dt, y, lam * y, lam * lam * y)
+    assert y2 == pytest.approx(y * (1 + z + z * z / 2), rel=1e-14)
+
+
+@pytest.mark.parametrize("mk", [lambda: I.cylinder_mesh(32, 16), lambda: I.sphere_mesh(6, 12, 6, 2, 2)])
+def test_s1o2_residual_is_the_step_increment(mk):
+    """R1 is the time-averaged net flux over one step, so with one time step
+    |V|^-1 dt R1 is exactly the S1O2 increment from the same state.  Hence a
+    state the explicit S1O2 scheme leaves unchanged has R1 = 0, the forcing
+    makes the low level start at its own steady state and the correction
+    vanishes: the multigrid fixed point is the explicit one."""
+    mesh = mk()
+    d = mesh["dim"]
+    Winf = I.free_stream(d, 0.2, 5.0)
+    W, dW = I.smooth_state(mesh, Winf, seed=7, amp=0.03)
+    om = oracle.Mesh(mesh)
+    vol = om.cells()["vol"]
+    P = oracle.Params(W_inf=Winf, mu=0.01 if d == 3 else 0.0, Pr=0.72, time_scheme=oracle.S1O2, dt_fixed=2e-3)
+    s = oracle.Solver(om, P)
+    W1, dW1 = W.copy(), dW.copy()
+    s.stage(0, W1, dW1)
+    R1 = s.residual_high(W, dW)
+    np.testing.assert_allclose(W1 - W, P.dt_fixed * R1 / vol, rtol=0, atol=1e-15 * np.abs(W).max())
+    # with R1 = 0 the forcing is S = -R0(W): the first implicit step has a
+    # zero right-hand side and the correction vanishes
+    Wl = W.copy()
+    s.lowlevel(Wl, np.zeros_like(W))
+    np.testing.assert_allclose(Wl, W, rtol=0, atol=1e-14)
+
+
+def tri_cell_vertices(mesh):
+    """Vertex coordinates of each triangle (2-D), neighbour copies shifted."""
+    n = mesh["n_cell"]
+    pts = [[] for _ in range(n)]
+    ptr, fv = mesh["face_vert_ptr"], mesh["face_vert"]
+    for f in range(len(mesh["face_owner"])):
+        X = mesh["xyz"][fv[ptr[f]:ptr[f + 1]]]
+        pts[mesh["face_owner"][f]].extend(list(X))
+        nb = mesh["face_neigh"][f]
+        if nb >= 0:
+            pts[nb].extend(list(X - mesh["face_shift"][f]))
+    out = np.zeros((n, 3, 2))
+    for i in range(n):
+        P = np.unique(np.round(np.array(pts[i]), 12), axis=0)
+        assert len(P) == 3
+        out[i] = P
+    return out
+
+
+def tri_average(P, fn, nq=8):
+    """Exact-to-high-degree cell averages over triangles (collapsed Gauss)."""
+    x, w = np.polynomial.legendre.leggauss(nq)
+    x, w = 0.5 * (x + 1), 0.5 * w
+    s, t = np.meshgrid(x, x, indexing="ij")
+    ws = np.outer(w, w) * (1 - s)
+    a, b = s, t * (1 - s)
+    X = (P[:, 0, None, None, :] * (1 - a - b)[None, :, :, None] + P[:, 1, None, None, :] * a[None, :, :, None]
+         + P[:, 2, None, None, :] * b[None, :, :, None])
+    v = fn(X)
+    return (v * ws[None, ..., None]).sum((1, 2)) / ws.sum() if v.ndim == 4 else (v * ws[None]).sum((1, 2)) / ws.sum()
+
+
+def wave_fields(X, t=0.0):
+    """rho = 1 + 0.2 sin(pi (x + y - 2t)), U = (1, 1), p = 1 as (W, dW)."""
+    ph = np.pi * (X[..., 0] + X[..., 1] - 2 * t)
+    rho = 1 + 0.2 * np.sin(ph)
+    dr = 0.2 * np.pi * np.cos(ph)
+    W = np.stack([rho, rho, rho, 1 / 0.4 + rho], -1)
+    dWx = np.stack([dr, dr, dr, dr], -1)
+    return W, dWx
+
+
+@pytest.mark.parametrize("scheme", [oracle.S2O4])
+def test_design_order_density_wave(scheme):
+    """One period of a density wave on perturbed periodic triangle meshes:
+    the L1 error of the cell averages falls at third order."""
+    errs = []
+    for n in (8, 16, 32):
+        mesh = I.box2d_mesh(n, L=2.0, periodic=True, perturb=0.2, seed=3)
+        P = tri_cell_vertices(mesh)
+        Wav = tri_average(P, lambda X: wave_fields(X)[0])
+        dav = tri_average(P, lambda X: wave_fields(X)[1])
+        W = np.ascontiguousarray(Wav.T)
+        dW = np.ascontiguousarray(np.stack([dav.T, dav.T]))
+        om = oracle.Mesh(mesh)
+        ce = om.cells()
+        dt0 = 0.3 * ce["h"].min() / (np.sqrt(2) + np.sqrt(1.4 / 0.8))
+        nst = int(np.ceil(1.0 / dt0))
+        s = oracle.Solver(om, oracle.Params(W_inf=np.array([1, 1, 1, 3.5]), time_scheme=scheme, explicit_only=1,
+                                            dt_fixed=1.0 / nst))
+        for _ in range(nst):
+            s.cycle(W, dW)
+        err = (np.abs(W[0] - Wav[:, 0]) * ce["vol"]).sum() / 4.0
+        errs.append(err)
+    orders = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert orders[-1] > 2.6, (errs, orders)
+
+
+def test_multigrid_accelerates_viscous_cylinder():
+    """Steady viscous cylinder (Re 40, Ma 0.15, no-slip isothermal wall):
+    the two-level cycle drives the density residual down far faster per
+    cycle than explicit marching alone, the paper's central observation."""
+    mesh = I.cylinder_mesh(32, 16, wall=I.BC_NOSLIP_ISOTHERMAL)
+    Ma, Re = 0.15, 40.0
+    Winf = I.free_stream(2, Ma)
+    drops = {}
+    for expl in (0, 1):
+        W, dW = I.uniform_state(mesh, Winf)
+        s = oracle.Solver(oracle.Mesh(mesh), oracle.Params(W_inf=Winf, mu=Ma / Re, Pr=0.72,
+                                                           time_scheme=oracle.S1O2, explicit_only=expl))
+        res = [s.cycle(W, dW) for _ in range(150)]
+        drops[expl] = res[-1] / res[0]
+    assert drops[0] < 1e-4
+    assert drops[0] < 1e-2 * drops[1], drops
