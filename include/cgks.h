@@ -1,0 +1,215 @@
+/*
+ * cgks.h -- C ABI of the MI355X p-multigrid compact gas-kinetic scheme
+ * (CGKS) library, libcgks.so.
+ *
+ * The library computes the two-level p-multigrid cycle of "A p-multigrid
+ * compact gas-kinetic scheme for steady-state acceleration" (Ji, Shyy, Xu):
+ * on the high-order level the compact reconstruction, the smooth-flow
+ * gas-kinetic flux at every face Gauss point and the Gauss-Green update of
+ * cell averages and cell-averaged gradients under two-stage fourth-order
+ * (S2O4) or one-step second-order (S1O2) time marching (Secs. 2.1-2.4);
+ * on the low-order level the first-order KFVS residual with forcing and
+ * the implicit backward-Euler point-relaxation smoother with local time
+ * steps (Sec. 3, Algorithm 1), run in a multicolour order.
+ *
+ * Conventions (every entry point):
+ *  - All functions are extern "C", return a cgks_status and never throw.
+ *  - Pointers named *_host are host memory; *_dev are device (HBM) pointers;
+ *    stream is a hipStream_t passed as void* (NULL = default stream).
+ *  - The caller owns every device buffer.  The library copies what it needs
+ *    from host inputs during the call; handles own only host memory.
+ *  - Device work is stream ordered; host outputs of *_download calls are
+ *    valid when the call returns (they synchronise the stream).
+ *  - Arrays of per-cell quantities are structure-of-arrays, variable-major:
+ *    W[v][cell] (v = 0..dim+1: rho, rho U_1..rho U_dim, rho E) and
+ *    dW[a][v][cell] (a = axis).  Host arrays use the caller's cell order;
+ *    device arrays use the library order (cgks_mesh_permutation).
+ *  - Handles are not thread safe.  Distinct batches on distinct streams are.
+ */
+#ifndef CGKS_H
+#define CGKS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    CGKS_OK = 0,
+    CGKS_EINVAL = 1,      /* bad argument (null pointer, size, index, state of the handle) */
+    CGKS_ENOMEM = 2,      /* host allocation failed or device buffer too small */
+    CGKS_EDEVICE = 3,     /* a HIP call failed */
+    CGKS_EMESH = 4,       /* invalid mesh: non-positive volume, face shared by > 2 cells,
+                             unsupported face shape, stencil that fixes no linear fit */
+    CGKS_ENONPHYS = 5,    /* density or pressure <= 0 met during a cycle */
+    CGKS_EDIVERGED = 6,   /* residual grew by 1e3 over its running minimum */
+    CGKS_ENOTCONV = 7,    /* cgks_solve hit max_cycles before the tolerance */
+    CGKS_EUNSUPPORTED = 8 /* valid but not implemented (e.g. adiabatic wall tag) */
+} cgks_status;
+
+/* boundary tags of boundary faces (interior faces carry 0) */
+enum {
+    CGKS_BC_INTERIOR = 0,
+    CGKS_BC_SLIP_WALL = 1,          /* inviscid reflecting wall */
+    CGKS_BC_NOSLIP_ISOTHERMAL = 2,  /* no-slip wall at temperature T_wall */
+    CGKS_BC_NOSLIP_ADIABATIC = 3,   /* reserved: returns CGKS_EUNSUPPORTED */
+    CGKS_BC_FARFIELD = 4            /* characteristic (Riemann invariant) far field */
+};
+
+enum { CGKS_S2O4 = 0, CGKS_S1O2 = 1 };
+enum { CGKS_FP64 = 0, CGKS_MIXED32 = 1 };
+enum { CGKS_RESIDUAL_HIGH = 0, CGKS_RESIDUAL_LOW = 1, CGKS_RESIDUAL_NORM = 2 };
+
+/*
+ * Face-based mesh (Sec. 2.1: the boundary of a cell is a union of faces).
+ * Linear elements: 2-D faces are straight edges (2 vertex ids), 3-D faces are
+ * planar triangles (3 ids) or bilinear quadrilaterals (4 ids, cyclic).  The
+ * vertex order makes the normal point out of face_owner (counter-clockwise
+ * owner boundary in 2-D, right-hand rule in 3-D).  face_neigh = -1 marks a
+ * boundary face, whose face_bc is one of the CGKS_BC_* tags.  face_shift
+ * (may be NULL) holds, per face, the translation [dim] that carries the
+ * neighbour next to the owner across a periodic seam (zero elsewhere).
+ * All arrays are host memory, read during cgks_mesh_create only.
+ */
+typedef struct {
+    int dim;                        /* 2 or 3 */
+    int64_t n_vert;
+    const double *xyz;              /* [n_vert][dim] */
+    int64_t n_cell;
+    int64_t n_face;
+    const int64_t *face_vert_ptr;   /* [n_face + 1] CSR offsets into face_vert */
+    const int64_t *face_vert;
+    const int64_t *face_owner;      /* [n_face] in [0, n_cell) */
+    const int64_t *face_neigh;      /* [n_face] in [0, n_cell) or -1 */
+    const int32_t *face_bc;         /* [n_face] */
+    const double *face_shift;       /* [n_face][dim] or NULL */
+} cgks_mesh_desc;
+
+typedef struct {
+    int dim, n_colour;
+    int64_t n_cell, n_face, n_gp, n_boundary_face;
+    int64_t n_linear_cells;         /* cells whose stencil only fixes a linear fit */
+} cgks_mesh_info;
+
+/*
+ * Flow and solver parameters of one case.  Non-dimensional gas with R = 1:
+ * T = p / rho.  mu is the constant dynamic viscosity (0 = inviscid); the
+ * collision time is tau = mu / p at each Gauss point (Sec. 2.2).  Pr != 1
+ * adds (1/Pr - 1) times the Fourier heat flux of the interface state to the
+ * energy flux (BGK alone gives Pr = 1).  cfl_high sets the global explicit
+ * step dt = cfl_high min_i h_i / (|U_i| + c_i + 2 mu / (rho_i h_i)); cfl_low
+ * sets the local steps of the low level (the paper uses 0.3-0.5 and 1000,
+ * Sec. 4).  n_implicit backward-Euler steps of n_sweeps point-relaxation
+ * sweeps each (6 and 2 in the paper, Sec. 3).  dt_fixed > 0 replaces the
+ * CFL rule by a fixed global step.  explicit_only = 1 runs the high-order
+ * level alone (the explicit CGKS the paper compares against).
+ */
+typedef struct {
+    double gamma, mu, Pr, T_wall;
+    double W_inf[5];                /* free-stream conservative state (first dim+2 used) */
+    double cfl_high, cfl_low;
+    int32_t n_implicit, n_sweeps;
+    int32_t time_scheme;            /* CGKS_S2O4 or CGKS_S1O2 */
+    int32_t explicit_only;
+    double dt_fixed;
+} cgks_params;
+
+typedef struct cgks_mesh cgks_mesh;
+typedef struct cgks_batch cgks_batch;
+
+/* Build faces' Gauss points (3 per triangle, 4 per quadrilateral with a
+   normal at each point, 2 per 2-D edge), cell volumes, centroids and second
+   moments, the reconstruction operators, the multicolour classes (greedy,
+   smallest free colour, in caller cell order) and the library cell order.
+   Host work only.  *out receives a handle (free with cgks_mesh_destroy).
+   Errors: CGKS_EINVAL (null/size), CGKS_EMESH, CGKS_ENOMEM. */
+cgks_status cgks_mesh_create(const cgks_mesh_desc *desc, cgks_mesh **out);
+cgks_status cgks_mesh_query(const cgks_mesh *mesh, cgks_mesh_info *info);
+/* lib_to_caller[n_cell]: caller cell id of each library cell; colour[n_cell]
+   (may be NULL): colour of each caller cell. Host arrays. */
+cgks_status cgks_mesh_permutation(const cgks_mesh *mesh, int64_t *lib_to_caller, int32_t *colour);
+/* Cell geometry in caller order (host arrays, any may be NULL): vol[n_cell],
+   centroid[n_cell][dim], h[n_cell] = 2 dim |V| / sum_f S_f, linear[n_cell]
+   (1 where the reconstruction stencil only fixes a linear fit). */
+cgks_status cgks_mesh_geometry(const cgks_mesh *mesh, double *vol, double *centroid, double *h, int32_t *linear);
+cgks_status cgks_mesh_destroy(cgks_mesh *mesh);
+
+/* A batch is n_case (mesh, params) pairs stepped together: every kernel
+   launch covers all cases; per-case reductions (dt, Res) never mix cases.
+   The meshes must outlive the batch.  precision: CGKS_FP64 (the only value
+   accepted so far).  Errors: CGKS_EINVAL, CGKS_EUNSUPPORTED, CGKS_ENOMEM. */
+cgks_status cgks_batch_create(const cgks_mesh *const *meshes, const cgks_params *params, int32_t n_case,
+                              int32_t precision, cgks_batch **out);
+/* Device bytes the batch needs (geometry, state, work arrays). */
+cgks_status cgks_batch_query(const cgks_batch *batch, size_t *device_bytes);
+/* Bind a caller-owned device buffer of at least cgks_batch_query bytes
+   (256-byte aligned) and upload the geometry into it on stream. */
+cgks_status cgks_batch_bind(cgks_batch *batch, void *dev_buf, size_t bytes, void *stream);
+cgks_status cgks_batch_destroy(cgks_batch *batch);
+
+/* Set / read the state of case c from host arrays in caller cell order:
+   W_host [dim+2][n_cell], dW_host [dim][dim+2][n_cell] (NULL = zero on
+   upload, skipped on download).  Synchronous on stream. */
+cgks_status cgks_state_upload(cgks_batch *batch, int32_t c, const double *W_host, const double *dW_host,
+                              void *stream);
+cgks_status cgks_state_download(cgks_batch *batch, int32_t c, double *W_host, double *dW_host, void *stream);
+/* Device pointers to case c's W [dim+2][n_cell] and dW [dim][dim+2][n_cell]
+   (library order, leading dimension n_cell of that case) and its cell count. */
+cgks_status cgks_state_device(cgks_batch *batch, int32_t c, double **W_dev, double **dW_dev, int64_t *n_cell);
+
+/* One high-order stage on every case, in place (Secs. 2.2-2.4).  stage 0
+   first computes the global step dt of each case from W, keeps W^n, and
+   applies the first S2O4 stage (or the whole S1O2 step); stage 1 applies the
+   second S2O4 stage (CGKS_EINVAL for S1O2 cases). */
+cgks_status cgks_highorder_stage(cgks_batch *batch, int32_t stage, void *stream);
+
+/* Residuals (Sec. 3).  kind = CGKS_RESIDUAL_HIGH: R1 = -sum_f s sum_g wJ
+   (F0 + dt/2 F_t), the time-averaged high-order net flux at the current
+   state with the dt of the last stage 0 (step 2 of the cycle), extensive.
+   kind = CGKS_RESIDUAL_LOW: R0 = -sum_f s S_f F_KFVS, the first-order net
+   flux at the current state.  Both write out_dev [batch cells][dim+2] in the
+   library's batch-concatenated layout (case c starts at its cell offset,
+   variable-major within the case: out_dev + 5*off_c is [nv][n_c]).
+   kind = CGKS_RESIDUAL_NORM: out_dev[c] = Res of the last cycle of case c,
+   sum |rho_new - rho_old| / sum rho_old (Sec. 4). */
+cgks_status cgks_residual(cgks_batch *batch, int32_t kind, double *out_dev, void *stream);
+
+/* Low level of the cycle (Sec. 3 steps 2-5) on every case: W_p0 = W,
+   forcing S = R1 - R0(W_p0), n_implicit backward-Euler steps solved by
+   multicolour point relaxation, W += U - W_p0.  R1_dev as written by
+   cgks_residual(CGKS_RESIDUAL_HIGH).  Also computes Res (cgks_residual
+   CGKS_RESIDUAL_NORM) against W^n of the last stage 0. */
+cgks_status cgks_lowlevel_smooth(cgks_batch *batch, const double *R1_dev, void *stream);
+
+/* One full two-level cycle on every case (stage 0, stage 1 for S2O4, R1,
+   low level; high-order step only when explicit_only).  res_dev (may be
+   NULL) receives Res per case. */
+cgks_status cgks_cycle(cgks_batch *batch, double *res_dev, void *stream);
+
+typedef struct {
+    int32_t max_cycles;
+    double tol;            /* stop a case when Res_k / Res_1 <= tol (tol_abs = 0) ... */
+    int32_t tol_abs;       /* ... or when Res_k <= tol (tol_abs = 1) */
+    int32_t check_every;   /* cycles between host checks of Res (>= 1) */
+    double *res_history;   /* optional host [n_case][max_cycles] */
+} cgks_solve_opts;
+
+typedef struct {
+    int32_t cycles;
+    int32_t converged;
+    double res_first, res_last;
+    cgks_status status;    /* CGKS_OK, CGKS_ENOTCONV, CGKS_ENONPHYS, CGKS_EDIVERGED */
+} cgks_solve_report;
+
+/* Cycle until every case meets its tolerance or max_cycles; report[n_case]
+   (host).  Cases that finish stop being updated. */
+cgks_status cgks_solve(cgks_batch *batch, const cgks_solve_opts *opts, cgks_solve_report *report, void *stream);
+
+const char *cgks_status_string(cgks_status s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CGKS_H */

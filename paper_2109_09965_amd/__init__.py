@@ -1,0 +1,278 @@
+"""MI355X p-multigrid compact gas-kinetic scheme (CGKS).
+
+Thin ctypes binding of libcgks.so (see include/cgks.h).  Every step of the
+cycle runs in the library's HIP kernels; this module only marshals arguments.
+PyTorch supplies device memory (a uint8 tensor per batch) and the stream.
+Importing works without a GPU; creating a bound batch needs one, and every
+call fails loudly if the native library is missing.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcgks.so")
+_lib = None
+
+OK, EINVAL, ENOMEM, EDEVICE, EMESH, ENONPHYS, EDIVERGED, ENOTCONV, EUNSUPPORTED = range(9)
+S2O4, S1O2 = 0, 1
+FP64, MIXED32 = 0, 1
+RESIDUAL_HIGH, RESIDUAL_LOW, RESIDUAL_NORM = 0, 1, 2
+
+EXPORTS = ["cgks_status_string", "cgks_mesh_create", "cgks_mesh_query", "cgks_mesh_permutation",
+           "cgks_mesh_geometry", "cgks_mesh_destroy", "cgks_batch_create", "cgks_batch_query", "cgks_batch_bind", "cgks_batch_destroy",
+           "cgks_state_upload", "cgks_state_download", "cgks_state_device", "cgks_highorder_stage",
+           "cgks_residual", "cgks_lowlevel_smooth", "cgks_cycle", "cgks_solve"]
+
+
+class CgksError(RuntimeError):
+    def __init__(self, status, what):
+        self.status = status
+        msg = lib().cgks_status_string(status).decode() if _lib is not None else str(status)
+        super().__init__(f"{what}: {msg} ({status})")
+
+
+class _Desc(C.Structure):
+    _fields_ = [("dim", C.c_int), ("n_vert", C.c_int64), ("xyz", C.c_void_p), ("n_cell", C.c_int64),
+                ("n_face", C.c_int64), ("face_vert_ptr", C.c_void_p), ("face_vert", C.c_void_p),
+                ("face_owner", C.c_void_p), ("face_neigh", C.c_void_p), ("face_bc", C.c_void_p),
+                ("face_shift", C.c_void_p)]
+
+
+class _Info(C.Structure):
+    _fields_ = [("dim", C.c_int), ("n_colour", C.c_int), ("n_cell", C.c_int64), ("n_face", C.c_int64),
+                ("n_gp", C.c_int64), ("n_boundary_face", C.c_int64), ("n_linear_cells", C.c_int64)]
+
+
+class _Params(C.Structure):
+    _fields_ = [("gamma", C.c_double), ("mu", C.c_double), ("Pr", C.c_double), ("T_wall", C.c_double),
+                ("W_inf", C.c_double * 5), ("cfl_high", C.c_double), ("cfl_low", C.c_double),
+                ("n_implicit", C.c_int32), ("n_sweeps", C.c_int32), ("time_scheme", C.c_int32),
+                ("explicit_only", C.c_int32), ("dt_fixed", C.c_double)]
+
+
+class _SolveOpts(C.Structure):
+    _fields_ = [("max_cycles", C.c_int32), ("tol", C.c_double), ("tol_abs", C.c_int32),
+                ("check_every", C.c_int32), ("res_history", C.c_void_p)]
+
+
+class _SolveReport(C.Structure):
+    _fields_ = [("cycles", C.c_int32), ("converged", C.c_int32), ("res_first", C.c_double),
+                ("res_last", C.c_double), ("status", C.c_int)]
+
+
+def lib():
+    """Load libcgks.so; raises if it has not been built.
+
+    torch is imported first when present: libcgks.so then binds to the HIP
+    runtime torch already loaded (same soname), so device pointers and
+    streams from torch are valid in the library.  Without torch the library
+    uses the system ROCm runtime."""
+    global _lib
+    if _lib is None:
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"libcgks.so not built ({LIB_PATH}); run paper_2109_09965_amd/build.py")
+        L = C.CDLL(LIB_PATH)
+        P, i32 = C.c_void_p, C.c_int32
+        L.cgks_status_string.restype = C.c_char_p
+        L.cgks_status_string.argtypes = [C.c_int]
+        L.cgks_mesh_create.argtypes = [C.POINTER(_Desc), C.POINTER(P)]
+        L.cgks_mesh_query.argtypes = [P, C.POINTER(_Info)]
+        L.cgks_mesh_permutation.argtypes = [P, P, P]
+        L.cgks_mesh_geometry.argtypes = [P, P, P, P, P]
+        L.cgks_mesh_destroy.argtypes = [P]
+        L.cgks_batch_create.argtypes = [P, P, i32, i32, C.POINTER(P)]
+        L.cgks_batch_query.argtypes = [P, C.POINTER(C.c_size_t)]
+        L.cgks_batch_bind.argtypes = [P, P, C.c_size_t, P]
+        L.cgks_batch_destroy.argtypes = [P]
+        L.cgks_state_upload.argtypes = [P, i32, P, P, P]
+        L.cgks_state_download.argtypes = [P, i32, P, P, P]
+        L.cgks_state_device.argtypes = [P, i32, C.POINTER(P), C.POINTER(P), C.POINTER(C.c_int64)]
+        L.cgks_highorder_stage.argtypes = [P, i32, P]
+        L.cgks_residual.argtypes = [P, i32, P, P]
+        L.cgks_lowlevel_smooth.argtypes = [P, P, P]
+        L.cgks_cycle.argtypes = [P, P, P]
+        L.cgks_solve.argtypes = [P, C.POINTER(_SolveOpts), P, P]
+        for name in EXPORTS:
+            getattr(L, name).restype = C.c_int if name != "cgks_status_string" else C.c_char_p
+        _lib = L
+    return _lib
+
+
+def _check(st, what):
+    if st != OK:
+        raise CgksError(st, what)
+
+
+def _ptr(a):
+    return a.ctypes.data_as(C.c_void_p) if a is not None else None
+
+
+@dataclass
+class Params:
+    """Per-case parameters (cgks_params); W_inf holds dim+2 conservative values."""
+    W_inf: np.ndarray
+    gamma: float = 1.4
+    mu: float = 0.0
+    Pr: float = 1.0
+    T_wall: float = 1.0 / 1.4
+    cfl_high: float = 0.4
+    cfl_low: float = 1000.0
+    n_implicit: int = 6
+    n_sweeps: int = 2
+    time_scheme: int = S2O4
+    explicit_only: int = 0
+    dt_fixed: float = 0.0
+
+    def c(self):
+        p = _Params()
+        p.gamma, p.mu, p.Pr, p.T_wall = self.gamma, self.mu, self.Pr, self.T_wall
+        w = np.zeros(5)
+        w[:len(self.W_inf)] = self.W_inf
+        p.W_inf = (C.c_double * 5)(*w)
+        p.cfl_high, p.cfl_low = self.cfl_high, self.cfl_low
+        p.n_implicit, p.n_sweeps = self.n_implicit, self.n_sweeps
+        p.time_scheme, p.explicit_only, p.dt_fixed = self.time_scheme, self.explicit_only, self.dt_fixed
+        return p
+
+
+class Mesh:
+    """Host-side mesh handle (cgks_mesh_create) from a face-based mesh dict."""
+
+    def __init__(self, m: dict):
+        L = lib()
+        self.dim = int(m["dim"])
+        self.nv = self.dim + 2
+        keep = dict(xyz=np.ascontiguousarray(m["xyz"], np.float64),
+                    ptr=np.ascontiguousarray(m["face_vert_ptr"], np.int64),
+                    fv=np.ascontiguousarray(m["face_vert"], np.int64),
+                    own=np.ascontiguousarray(m["face_owner"], np.int64),
+                    nb=np.ascontiguousarray(m["face_neigh"], np.int64),
+                    bc=np.ascontiguousarray(m["face_bc"], np.int32),
+                    sh=np.ascontiguousarray(m["face_shift"], np.float64))
+        d = _Desc(self.dim, len(keep["xyz"]), _ptr(keep["xyz"]), int(m["n_cell"]), len(keep["own"]),
+                  _ptr(keep["ptr"]), _ptr(keep["fv"]), _ptr(keep["own"]), _ptr(keep["nb"]), _ptr(keep["bc"]),
+                  _ptr(keep["sh"]))
+        h = C.c_void_p()
+        _check(L.cgks_mesh_create(C.byref(d), C.byref(h)), "cgks_mesh_create")
+        self.h = h
+        info = _Info()
+        _check(L.cgks_mesh_query(h, C.byref(info)), "cgks_mesh_query")
+        self.info = info
+        self.n_cell, self.n_face, self.n_gp = info.n_cell, info.n_face, info.n_gp
+        self.n_colour = info.n_colour
+        self.lib2caller = np.zeros(self.n_cell, np.int64)
+        self.colour = np.zeros(self.n_cell, np.int32)
+        _check(L.cgks_mesh_permutation(h, _ptr(self.lib2caller), _ptr(self.colour)), "cgks_mesh_permutation")
+
+    def geometry(self):
+        """Caller-order (vol, centroid, h, linear) computed by the library."""
+        n = self.n_cell
+        vol, ctr, h = np.zeros(n), np.zeros((n, self.dim)), np.zeros(n)
+        lin = np.zeros(n, np.int32)
+        _check(lib().cgks_mesh_geometry(self.h, _ptr(vol), _ptr(ctr), _ptr(h), _ptr(lin)), "cgks_mesh_geometry")
+        return vol, ctr, h, lin
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.cgks_mesh_destroy(self.h)
+            self.h = None
+
+
+def _stream(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+class Batch:
+    """A batch of cases bound to one device arena (a torch uint8 tensor)."""
+
+    def __init__(self, meshes, params, precision=FP64, device="cuda", stream=None):
+        import torch
+        L = lib()
+        self.meshes = list(meshes)
+        self.params = list(params)
+        n = len(self.meshes)
+        arr_m = (C.c_void_p * n)(*[m.h.value for m in self.meshes])
+        arr_p = (_Params * n)(*[p.c() for p in self.params])
+        self._keep = (arr_m, arr_p)
+        h = C.c_void_p()
+        _check(L.cgks_batch_create(arr_m, arr_p, n, precision, C.byref(h)), "cgks_batch_create")
+        self.h = h
+        nb = C.c_size_t()
+        _check(L.cgks_batch_query(h, C.byref(nb)), "cgks_batch_query")
+        self.nbytes = nb.value
+        self.arena = torch.empty(self.nbytes + 256, dtype=torch.uint8, device=device)
+        base = self.arena.data_ptr()
+        self._base = (base + 255) & ~255
+        self.stream = stream
+        _check(L.cgks_batch_bind(h, C.c_void_p(self._base), self.nbytes, _stream(stream)), "cgks_batch_bind")
+        self.n_case = n
+        self.dim = self.meshes[0].dim
+        self.nv = self.dim + 2
+        self.cell_off = np.concatenate([[0], np.cumsum([m.n_cell for m in self.meshes])]).astype(np.int64)
+        self.NC = int(self.cell_off[-1])
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.cgks_batch_destroy(self.h)
+            self.h = None
+
+    def upload(self, c, W, dW=None):
+        W = np.ascontiguousarray(W, np.float64)
+        dW = None if dW is None else np.ascontiguousarray(dW, np.float64)
+        _check(lib().cgks_state_upload(self.h, c, _ptr(W), _ptr(dW), _stream(self.stream)), "cgks_state_upload")
+
+    def download(self, c):
+        m = self.meshes[c]
+        W = np.zeros((self.nv, m.n_cell))
+        dW = np.zeros((self.dim, self.nv, m.n_cell))
+        _check(lib().cgks_state_download(self.h, c, _ptr(W), _ptr(dW), _stream(self.stream)), "cgks_state_download")
+        return W, dW
+
+    def highorder_stage(self, stage):
+        _check(lib().cgks_highorder_stage(self.h, stage, _stream(self.stream)), "cgks_highorder_stage")
+
+    def residual(self, kind):
+        """Device tensor: [nv, NC] for HIGH/LOW (library order), [n_case] for NORM."""
+        import torch
+        n = self.n_case if kind == RESIDUAL_NORM else self.nv * self.NC
+        out = torch.empty(n, dtype=torch.float64, device=self.arena.device)
+        _check(lib().cgks_residual(self.h, kind, C.c_void_p(out.data_ptr()), _stream(self.stream)), "cgks_residual")
+        return out if kind == RESIDUAL_NORM else out.view(self.nv, self.NC)
+
+    def to_caller(self, c, X):
+        """[k, NC] library-order array (numpy) -> [k, n_c] in case c's caller order."""
+        m = self.meshes[c]
+        out = np.empty((X.shape[0], m.n_cell))
+        out[:, m.lib2caller] = X[:, self.cell_off[c]:self.cell_off[c + 1]]
+        return out
+
+    def lowlevel_smooth(self, R1):
+        _check(lib().cgks_lowlevel_smooth(self.h, C.c_void_p(R1.data_ptr()), _stream(self.stream)),
+               "cgks_lowlevel_smooth")
+
+    def cycle(self, res=None):
+        ptr = C.c_void_p(res.data_ptr()) if res is not None else None
+        _check(lib().cgks_cycle(self.h, ptr, _stream(self.stream)), "cgks_cycle")
+
+    def solve(self, max_cycles, tol, tol_abs=False, check_every=10, history=False):
+        opts = _SolveOpts(max_cycles, tol, int(tol_abs), check_every, None)
+        hist = None
+        if history:
+            hist = np.zeros((self.n_case, max_cycles))
+            opts.res_history = hist.ctypes.data_as(C.c_void_p)
+        rep = (_SolveReport * self.n_case)()
+        _check(lib().cgks_solve(self.h, C.byref(opts), rep, _stream(self.stream)), "cgks_solve")
+        out = [dict(cycles=r.cycles, converged=bool(r.converged), res_first=r.res_first, res_last=r.res_last,
+                    status=r.status) for r in rep]
+        return out, hist

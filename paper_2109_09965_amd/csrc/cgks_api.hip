@@ -1,0 +1,678 @@
+// C ABI of libcgks.so: batches of cases, device arena layout, uploads and the
+// launch sequence of one two-level p-multigrid cycle.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "cgks_internal.h"
+#include "kernels.h"
+
+using namespace cgks;
+
+namespace {
+
+constexpr int kRedChunk = 1024;   // cells per reduction block (never straddles cases)
+
+struct Arena {
+    size_t off = 0;
+    template <class T> size_t take(size_t n) {
+        off = (off + 255) & ~size_t(255);
+        const size_t o = off;
+        off += n * sizeof(T) + 0;
+        return o;
+    }
+};
+
+}  // namespace
+
+struct cgks_batch {
+    int n_case = 0, dim = 0, precision = 0;
+    std::vector<const cgks_mesh *> meshes;
+    std::vector<cgks_params> params;
+    int64_t NC = 0, NF = 0, NG = 0, NB = 0;
+    std::vector<int64_t> cell_off, face_off, gp_base, b_off;
+    int max_colour = 0;
+    // sweep blocks per colour
+    std::vector<int32_t> cb_start, cb_count;
+    std::vector<int64_t> colour_blk_off;   // [max_colour + 1]
+    // reduction blocks
+    std::vector<int32_t> rb_start, rb_count, rb_case, case_rb_off;
+    int n_implicit = 6, n_sweeps = 2, scheme = 0, explicit_only = 0;
+    // arena
+    size_t bytes = 0;
+    char *base = nullptr;
+    struct {
+        size_t W, dW, Wn, L0, Lt0, G0, coef, vol, h, ctr, sec, minv, slot_face, slot_nb, cell_case;
+        size_t fL, fR, fbc, fcase, gp_off, bslot, avec, S, shift, gavg;
+        size_t gx, gn, gw, gface, gF0, gFt, gWc, gWt;
+        size_t U, dU, Sf, RHS, D, R1, lam, Flow;
+        size_t prm, dt, res, flag, rb_start, rb_count, rb_case, case_rb_off, part0, part1, cb_start, cb_count;
+    } o{};
+    Dev dev{};
+    int32_t *d_cb_start = nullptr, *d_cb_count = nullptr;
+};
+
+namespace {
+
+template <class T> T *at(cgks_batch *b, size_t off) { return reinterpret_cast<T *>(b->base + off); }
+
+void layout(cgks_batch *b) {
+    const int d = b->dim, nv = d + 2, nk = ncoef_of(d), nq = nquad_of(d), ns = d == 2 ? 4 : 8;
+    const size_t NC = b->NC, NF = b->NF, NG = b->NG, NB = std::max<int64_t>(b->NB, 1);
+    Arena a;
+    auto &o = b->o;
+    o.W = a.take<double>(nv * NC);
+    o.dW = a.take<double>(d * nv * NC);
+    o.Wn = a.take<double>(nv * NC);
+    o.L0 = a.take<double>(nv * NC);
+    o.Lt0 = a.take<double>(nv * NC);
+    o.G0 = a.take<double>(d * nv * NC);
+    o.coef = a.take<double>(nk * nv * NC);
+    o.vol = a.take<double>(NC);
+    o.h = a.take<double>(NC);
+    o.ctr = a.take<double>(d * NC);
+    o.sec = a.take<double>(nq * NC);
+    o.minv = a.take<double>(nk * (nk + 1) / 2 * NC);
+    o.slot_face = a.take<int32_t>(ns * NC);
+    o.slot_nb = a.take<int32_t>(ns * NC);
+    o.cell_case = a.take<int32_t>(NC);
+    o.fL = a.take<int32_t>(NF);
+    o.fR = a.take<int32_t>(NF);
+    o.fbc = a.take<int32_t>(NF);
+    o.fcase = a.take<int32_t>(NF);
+    o.gp_off = a.take<int32_t>(NF + 1);
+    o.bslot = a.take<int32_t>(NF);
+    o.avec = a.take<double>(d * NF);
+    o.S = a.take<double>(NF);
+    o.shift = a.take<double>(d * NF);
+    o.gavg = a.take<double>(nk * NB);
+    o.gx = a.take<double>(d * NG);
+    o.gn = a.take<double>(d * NG);
+    o.gw = a.take<double>(NG);
+    o.gface = a.take<int32_t>(NG);
+    o.gF0 = a.take<double>(nv * NG);
+    o.gFt = a.take<double>(nv * NG);
+    o.gWc = a.take<double>(nv * NG);
+    o.gWt = a.take<double>(nv * NG);
+    o.U = a.take<double>(nv * NC);
+    o.dU = a.take<double>(nv * NC);
+    o.Sf = a.take<double>(nv * NC);
+    o.RHS = a.take<double>(nv * NC);
+    o.D = a.take<double>(NC);
+    o.R1 = a.take<double>(nv * NC);
+    o.lam = a.take<double>(NF);
+    o.Flow = a.take<double>(nv * NF);
+    o.prm = a.take<DevParams>(b->n_case);
+    o.dt = a.take<double>(b->n_case);
+    o.res = a.take<double>(b->n_case);
+    o.flag = a.take<int32_t>(b->n_case);
+    o.rb_start = a.take<int32_t>(b->rb_start.size());
+    o.rb_count = a.take<int32_t>(b->rb_start.size());
+    o.rb_case = a.take<int32_t>(b->rb_start.size());
+    o.case_rb_off = a.take<int32_t>(b->n_case + 1);
+    o.part0 = a.take<double>(b->rb_start.size());
+    o.part1 = a.take<double>(b->rb_start.size());
+    o.cb_start = a.take<int32_t>(std::max<size_t>(b->cb_start.size(), 1));
+    o.cb_count = a.take<int32_t>(std::max<size_t>(b->cb_start.size(), 1));
+    b->bytes = (a.off + 255) & ~size_t(255);
+}
+
+DevParams dev_params(const cgks_params &p, int dim) {
+    DevParams q{};
+    q.gamma = p.gamma;
+    q.mu = p.mu;
+    q.Pr = p.Pr;
+    q.T_wall = p.T_wall;
+    for (int v = 0; v < 5; ++v) q.W_inf[v] = p.W_inf[v];
+    q.cfl_high = p.cfl_high;
+    q.cfl_low = p.cfl_low;
+    q.dt_fixed = p.dt_fixed;
+    q.K = dim == 3 ? (5.0 - 3.0 * p.gamma) / (p.gamma - 1.0) : (4.0 - 2.0 * p.gamma) / (p.gamma - 1.0);
+    q.scheme = p.time_scheme;
+    q.explicit_only = p.explicit_only;
+    q.active = 1;
+    return q;
+}
+
+void fill_dev(cgks_batch *b) {
+    auto &o = b->o;
+    Dev &d = b->dev;
+    d.NC = int32_t(b->NC);
+    d.NF = int32_t(b->NF);
+    d.NG = int32_t(b->NG);
+    d.NB = int32_t(std::max<int64_t>(b->NB, 1));
+    d.W = at<double>(b, o.W); d.dW = at<double>(b, o.dW); d.Wn = at<double>(b, o.Wn);
+    d.L0 = at<double>(b, o.L0); d.Lt0 = at<double>(b, o.Lt0); d.G0 = at<double>(b, o.G0);
+    d.coef = at<double>(b, o.coef);
+    d.vol = at<double>(b, o.vol); d.h = at<double>(b, o.h); d.ctr = at<double>(b, o.ctr);
+    d.sec = at<double>(b, o.sec); d.minv = at<double>(b, o.minv);
+    d.slot_face = at<int32_t>(b, o.slot_face); d.slot_nb = at<int32_t>(b, o.slot_nb);
+    d.cell_case = at<int32_t>(b, o.cell_case);
+    d.fL = at<int32_t>(b, o.fL); d.fR = at<int32_t>(b, o.fR); d.fbc = at<int32_t>(b, o.fbc);
+    d.fcase = at<int32_t>(b, o.fcase); d.gp_off = at<int32_t>(b, o.gp_off); d.bslot = at<int32_t>(b, o.bslot);
+    d.avec = at<double>(b, o.avec); d.S = at<double>(b, o.S); d.shift = at<double>(b, o.shift);
+    d.gavg = at<double>(b, o.gavg);
+    d.gx = at<double>(b, o.gx); d.gn = at<double>(b, o.gn); d.gw = at<double>(b, o.gw);
+    d.gface = at<int32_t>(b, o.gface);
+    d.gF0 = at<double>(b, o.gF0); d.gFt = at<double>(b, o.gFt); d.gWc = at<double>(b, o.gWc);
+    d.gWt = at<double>(b, o.gWt);
+    d.U = at<double>(b, o.U); d.dU = at<double>(b, o.dU); d.Sf = at<double>(b, o.Sf);
+    d.RHS = at<double>(b, o.RHS); d.D = at<double>(b, o.D); d.R1 = at<double>(b, o.R1);
+    d.lam = at<double>(b, o.lam); d.Flow = at<double>(b, o.Flow);
+    d.prm = at<DevParams>(b, o.prm); d.dt = at<double>(b, o.dt); d.res = at<double>(b, o.res);
+    d.flag = at<int32_t>(b, o.flag);
+    d.rb_start = at<int32_t>(b, o.rb_start); d.rb_count = at<int32_t>(b, o.rb_count);
+    d.rb_case = at<int32_t>(b, o.rb_case); d.case_rb_off = at<int32_t>(b, o.case_rb_off);
+    d.part0 = at<double>(b, o.part0); d.part1 = at<double>(b, o.part1);
+    b->d_cb_start = at<int32_t>(b, o.cb_start);
+    b->d_cb_count = at<int32_t>(b, o.cb_count);
+}
+
+template <class T> hipError_t put(cgks_batch *b, size_t off, const std::vector<T> &v, hipStream_t s) {
+    if (v.empty()) return hipSuccess;
+    return hipMemcpyAsync(b->base + off, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s);
+}
+
+inline unsigned nblk(int64_t n) { return unsigned((n + kBlock - 1) / kBlock); }
+
+#define HIP_TRY(x)                                      \
+    do {                                                \
+        if ((x) != hipSuccess) return CGKS_EDEVICE;     \
+    } while (0)
+
+template <int D> cgks_status launch_highorder(cgks_batch *b, int mode, hipStream_t s) {
+    const Dev &d = b->dev;
+    if (mode == MODE_STAGE0) {
+        hipLaunchKernelGGL(k_dt_partial<D>, dim3(b->rb_start.size()), dim3(kBlock), 0, s, d);
+        hipLaunchKernelGGL(k_dt_final, dim3(nblk(b->n_case)), dim3(kBlock), 0, s, d, b->n_case);
+    }
+    hipLaunchKernelGGL(k_recon<D>, dim3(nblk(b->NC)), dim3(kBlock), 0, s, d);
+    hipLaunchKernelGGL(k_flux<D>, dim3(nblk(b->NG)), dim3(kBlock), 0, s, d);
+    hipLaunchKernelGGL(k_cell<D>, dim3(nblk(b->NC)), dim3(kBlock), 0, s, d, mode);
+    HIP_TRY(hipGetLastError());
+    return CGKS_OK;
+}
+
+// ascending then descending colours, n_sweeps times, consecutive repeats of
+// a colour dropped (a repeated pass reproduces the same increments)
+std::vector<int> sweep_order(int ncol, int nsweeps) {
+    std::vector<int> seq;
+    for (int sw = 0; sw < nsweeps; ++sw) {
+        for (int c = 0; c < ncol; ++c) seq.push_back(c);
+        for (int c = ncol - 1; c >= 0; --c) seq.push_back(c);
+    }
+    std::vector<int> out;
+    for (int c : seq)
+        if (out.empty() || out.back() != c) out.push_back(c);
+    return out;
+}
+
+template <int D> cgks_status launch_lowlevel(cgks_batch *b, const double *R1, hipStream_t s) {
+    Dev d = b->dev;
+    if (R1 != d.R1)
+        HIP_TRY(hipMemcpyAsync(d.R1, R1, sizeof(double) * (D + 2) * b->NC, hipMemcpyDeviceToDevice, s));
+    hipLaunchKernelGGL(k_low_face<D>, dim3(nblk(b->NF)), dim3(kBlock), 0, s, d, (const double *)d.W,
+                       (const double *)nullptr);
+    hipLaunchKernelGGL(k_low_cell<D>, dim3(nblk(b->NC)), dim3(kBlock), 0, s, d, (int)LOW_FORCE, (double *)nullptr);
+    const std::vector<int> order = sweep_order(b->max_colour, b->n_sweeps);
+    for (int k = 0; k < b->n_implicit; ++k) {
+        hipLaunchKernelGGL(k_low_face<D>, dim3(nblk(b->NF)), dim3(kBlock), 0, s, d, (const double *)d.U,
+                           (const double *)(k ? d.dU : nullptr));
+        hipLaunchKernelGGL(k_low_cell<D>, dim3(nblk(b->NC)), dim3(kBlock), 0, s, d,
+                           (int)(k ? LOW_STEP : LOW_STEP_FIRST), (double *)nullptr);
+        for (int c : order) {
+            const int64_t b0 = b->colour_blk_off[c], nb = b->colour_blk_off[c + 1] - b0;
+            if (nb == 0) continue;
+            hipLaunchKernelGGL(k_sweep<D>, dim3(unsigned(nb)), dim3(kBlock), 0, s, d,
+                               (const int32_t *)(b->d_cb_start + b0), (const int32_t *)(b->d_cb_count + b0));
+        }
+    }
+    hipLaunchKernelGGL(k_prolong_res<D>, dim3(b->rb_start.size()), dim3(kBlock), 0, s, d, 1);
+    hipLaunchKernelGGL(k_res_final, dim3(nblk(b->n_case)), dim3(kBlock), 0, s, d, b->n_case);
+    HIP_TRY(hipGetLastError());
+    return CGKS_OK;
+}
+
+template <int D> cgks_status launch_cycle(cgks_batch *b, hipStream_t s) {
+    cgks_status st = launch_highorder<D>(b, MODE_STAGE0, s);
+    if (st) return st;
+    if (b->scheme == CGKS_S2O4) {
+        st = launch_highorder<D>(b, MODE_STAGE1, s);
+        if (st) return st;
+    }
+    if (b->explicit_only) {
+        hipLaunchKernelGGL(k_prolong_res<D>, dim3(b->rb_start.size()), dim3(kBlock), 0, s, b->dev, 0);
+        hipLaunchKernelGGL(k_res_final, dim3(nblk(b->n_case)), dim3(kBlock), 0, s, b->dev, b->n_case);
+        HIP_TRY(hipGetLastError());
+        return CGKS_OK;
+    }
+    st = launch_highorder<D>(b, MODE_R1, s);
+    if (st) return st;
+    return launch_lowlevel<D>(b, b->dev.R1, s);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *cgks_status_string(cgks_status s) {
+    switch (s) {
+        case CGKS_OK: return "ok";
+        case CGKS_EINVAL: return "invalid argument";
+        case CGKS_ENOMEM: return "out of memory or device buffer too small";
+        case CGKS_EDEVICE: return "HIP call failed";
+        case CGKS_EMESH: return "invalid mesh";
+        case CGKS_ENONPHYS: return "non-physical state (density or pressure <= 0)";
+        case CGKS_EDIVERGED: return "residual diverged";
+        case CGKS_ENOTCONV: return "not converged within max_cycles";
+        case CGKS_EUNSUPPORTED: return "unsupported";
+    }
+    return "unknown status";
+}
+
+cgks_status cgks_mesh_create(const cgks_mesh_desc *desc, cgks_mesh **out) {
+    if (!out) return CGKS_EINVAL;
+    *out = nullptr;
+    cgks_mesh *m = new (std::nothrow) cgks_mesh;
+    if (!m) return CGKS_ENOMEM;
+    cgks_status st;
+    try {
+        st = build_host_mesh(desc, m->hm);
+    } catch (const std::bad_alloc &) {
+        st = CGKS_ENOMEM;
+    }
+    if (st != CGKS_OK) {
+        delete m;
+        return st;
+    }
+    *out = m;
+    return CGKS_OK;
+}
+
+cgks_status cgks_mesh_query(const cgks_mesh *mesh, cgks_mesh_info *info) {
+    if (!mesh || !info) return CGKS_EINVAL;
+    const HostMesh &m = mesh->hm;
+    info->dim = m.dim;
+    info->n_colour = m.n_colour;
+    info->n_cell = m.n_cell;
+    info->n_face = m.n_face;
+    info->n_gp = m.n_gp;
+    info->n_boundary_face = m.n_bface;
+    int64_t nl = 0;
+    for (auto v : m.linear) nl += v;
+    info->n_linear_cells = nl;
+    return CGKS_OK;
+}
+
+cgks_status cgks_mesh_permutation(const cgks_mesh *mesh, int64_t *lib_to_caller, int32_t *colour) {
+    if (!mesh || !lib_to_caller) return CGKS_EINVAL;
+    const HostMesh &m = mesh->hm;
+    std::copy(m.lib2caller.begin(), m.lib2caller.end(), lib_to_caller);
+    if (colour) std::copy(m.colour.begin(), m.colour.end(), colour);
+    return CGKS_OK;
+}
+
+cgks_status cgks_mesh_geometry(const cgks_mesh *mesh, double *vol, double *centroid, double *h, int32_t *linear) {
+    if (!mesh) return CGKS_EINVAL;
+    const HostMesh &m = mesh->hm;
+    if (vol) std::copy(m.vol.begin(), m.vol.end(), vol);
+    if (centroid) std::copy(m.ctr.begin(), m.ctr.end(), centroid);
+    if (h) std::copy(m.h.begin(), m.h.end(), h);
+    if (linear)
+        for (int64_t i = 0; i < m.n_cell; ++i) linear[i] = m.linear[i];
+    return CGKS_OK;
+}
+
+cgks_status cgks_mesh_destroy(cgks_mesh *mesh) {
+    delete mesh;
+    return CGKS_OK;
+}
+
+cgks_status cgks_batch_create(const cgks_mesh *const *meshes, const cgks_params *params, int32_t n_case,
+                              int32_t precision, cgks_batch **out) {
+    if (!out || !meshes || !params || n_case <= 0) return CGKS_EINVAL;
+    *out = nullptr;
+    if (precision != CGKS_FP64) return CGKS_EUNSUPPORTED;
+    try {
+        cgks_batch *b = new cgks_batch;
+        b->n_case = n_case;
+        b->precision = precision;
+        b->dim = meshes[0] ? meshes[0]->hm.dim : 0;
+        b->n_implicit = params[0].n_implicit;
+        b->n_sweeps = params[0].n_sweeps;
+        b->scheme = params[0].time_scheme;
+        b->explicit_only = params[0].explicit_only;
+        for (int c = 0; c < n_case; ++c) {
+            const cgks_mesh *m = meshes[c];
+            const cgks_params &p = params[c];
+            if (!m || m->hm.dim != b->dim || p.n_implicit != b->n_implicit || p.n_sweeps != b->n_sweeps ||
+                p.time_scheme != b->scheme || p.explicit_only != b->explicit_only || p.n_implicit < 0 ||
+                p.n_sweeps < 0 || (p.time_scheme != CGKS_S2O4 && p.time_scheme != CGKS_S1O2) || !(p.gamma > 1.0) ||
+                p.mu < 0 || !(p.Pr > 0) || !(p.T_wall > 0) || !(p.cfl_high > 0) || !(p.cfl_low > 0)) {
+                delete b;
+                return CGKS_EINVAL;
+            }
+            b->meshes.push_back(m);
+            b->params.push_back(p);
+            b->cell_off.push_back(b->NC);
+            b->face_off.push_back(b->NF);
+            b->gp_base.push_back(b->NG);
+            b->b_off.push_back(b->NB);
+            b->NC += m->hm.n_cell;
+            b->NF += m->hm.n_face;
+            b->NG += m->hm.n_gp;
+            b->NB += m->hm.n_bface;
+            b->max_colour = std::max(b->max_colour, m->hm.n_colour);
+        }
+        if (b->NC >= INT32_MAX || b->NG >= INT32_MAX) {
+            delete b;
+            return CGKS_EINVAL;
+        }
+        // sweep blocks: for each colour, every case's cells of that colour in
+        // chunks of kBlock (library order is colour-major within a case)
+        b->colour_blk_off.assign(b->max_colour + 1, 0);
+        for (int col = 0; col < b->max_colour; ++col) {
+            for (int c = 0; c < n_case; ++c) {
+                const HostMesh &m = meshes[c]->hm;
+                if (col >= m.n_colour) continue;
+                int64_t start = b->cell_off[c];
+                for (int k = 0; k < col; ++k) start += m.colour_count[k];
+                const int64_t n = m.colour_count[col];
+                for (int64_t q = 0; q < n; q += kBlock) {
+                    b->cb_start.push_back(int32_t(start + q));
+                    b->cb_count.push_back(int32_t(std::min<int64_t>(kBlock, n - q)));
+                }
+            }
+            b->colour_blk_off[col + 1] = b->cb_start.size();
+        }
+        // reduction blocks: per case, chunks of kRedChunk cells
+        b->case_rb_off.push_back(0);
+        for (int c = 0; c < n_case; ++c) {
+            const int64_t n = meshes[c]->hm.n_cell;
+            for (int64_t q = 0; q < n; q += kRedChunk) {
+                b->rb_start.push_back(int32_t(b->cell_off[c] + q));
+                b->rb_count.push_back(int32_t(std::min<int64_t>(kRedChunk, n - q)));
+                b->rb_case.push_back(c);
+            }
+            b->case_rb_off.push_back(int32_t(b->rb_start.size()));
+        }
+        layout(b);
+        *out = b;
+    } catch (const std::bad_alloc &) {
+        return CGKS_ENOMEM;
+    }
+    return CGKS_OK;
+}
+
+cgks_status cgks_batch_query(const cgks_batch *b, size_t *bytes) {
+    if (!b || !bytes) return CGKS_EINVAL;
+    *bytes = b->bytes;
+    return CGKS_OK;
+}
+
+cgks_status cgks_batch_bind(cgks_batch *b, void *buf, size_t bytes, void *stream) {
+    if (!b || !buf || (reinterpret_cast<uintptr_t>(buf) & 255)) return CGKS_EINVAL;
+    if (bytes < b->bytes) return CGKS_ENOMEM;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    b->base = static_cast<char *>(buf);
+    fill_dev(b);
+    const int d = b->dim, nv = d + 2, nk = ncoef_of(d), nq = nquad_of(d), ns = d == 2 ? 4 : 8;
+    const int nsym = nk * (nk + 1) / 2;
+    const size_t NC = b->NC, NF = b->NF, NG = b->NG, NB = std::max<int64_t>(b->NB, 1);
+    try {
+        std::vector<double> vol(NC), h(NC), ctr(d * NC), sec(nq * NC), minv(nsym * NC);
+        std::vector<int32_t> slot_face(ns * NC, 0), slot_nb(ns * NC, -1), cell_case(NC);
+        std::vector<int32_t> fL(NF), fR(NF), fbc(NF), fcase(NF), gp_off(NF + 1), bslot(NF, -1), gface(NG);
+        std::vector<double> avec(d * NF), S(NF), shift(d * NF), gavg(nk * NB, 0.0), gx(d * NG), gn(d * NG), gw(NG);
+        std::vector<DevParams> prm;
+        for (int c = 0; c < b->n_case; ++c) {
+            const HostMesh &m = b->meshes[c]->hm;
+            const int64_t co = b->cell_off[c], fo = b->face_off[c], go = b->gp_base[c], bo = b->b_off[c];
+            prm.push_back(dev_params(b->params[c], d));
+            for (int64_t l = 0; l < m.n_cell; ++l) {
+                const int64_t i = m.lib2caller[l];
+                const int64_t I = co + l;
+                vol[I] = m.vol[i];
+                h[I] = m.h[i];
+                cell_case[I] = c;
+                for (int a = 0; a < d; ++a) ctr[a * NC + I] = m.ctr[i * d + a];
+                for (int q = 0; q < nq; ++q) sec[q * NC + I] = m.sec[i * nq + q];
+                int k = 0;
+                for (int r = 0; r < nk; ++r)
+                    for (int t = r; t < nk; ++t) minv[(k++) * NC + I] = m.minv[i * nk * nk + r * nk + t];
+                int sl = 0;
+                for (int64_t q = m.cf_ptr[i]; q < m.cf_ptr[i + 1]; ++q, ++sl) {
+                    const int64_t f = m.cf_face[q];
+                    const int side = m.cf_side[q];
+                    slot_face[sl * NC + I] = side ? -int32_t(fo + f + 1) : int32_t(fo + f + 1);
+                    const int64_t nb = side ? m.owner[f] : m.neigh[f];
+                    slot_nb[sl * NC + I] = nb >= 0 ? int32_t(co + m.caller2lib[nb]) : -1;
+                }
+            }
+            int64_t bcount = 0;
+            for (int64_t f = 0; f < m.n_face; ++f) {
+                const int64_t F = fo + f;
+                fL[F] = int32_t(co + m.caller2lib[m.owner[f]]);
+                fR[F] = m.neigh[f] >= 0 ? int32_t(co + m.caller2lib[m.neigh[f]]) : -1;
+                fbc[F] = m.neigh[f] >= 0 ? 0 : m.bc[f];
+                fcase[F] = c;
+                gp_off[F] = int32_t(go + m.gp_off[f]);
+                for (int a = 0; a < d; ++a) {
+                    avec[a * NF + F] = m.avec[f * d + a];
+                    shift[a * NF + F] = m.shift[f * d + a];
+                }
+                S[F] = m.S[f];
+                if (m.neigh[f] < 0) {
+                    const int64_t B = bo + bcount++;
+                    bslot[F] = int32_t(B);
+                    for (int k = 0; k < nk; ++k) gavg[k * NB + B] = m.gavg[f * nk + k];
+                }
+                for (int64_t g = m.gp_off[f]; g < m.gp_off[f + 1]; ++g) gface[go + g] = int32_t(F);
+            }
+            for (int64_t g = 0; g < m.n_gp; ++g) {
+                for (int a = 0; a < d; ++a) {
+                    gx[a * NG + go + g] = m.gx[g * d + a];
+                    gn[a * NG + go + g] = m.gn[g * d + a];
+                }
+                gw[go + g] = m.gw[g];
+            }
+        }
+        gp_off[NF] = int32_t(NG);
+        std::vector<int32_t> zero_flag(b->n_case, 0);
+        std::vector<double> zero_case(b->n_case, 0.0);
+        auto &o = b->o;
+        HIP_TRY(put(b, o.vol, vol, s)); HIP_TRY(put(b, o.h, h, s)); HIP_TRY(put(b, o.ctr, ctr, s));
+        HIP_TRY(put(b, o.sec, sec, s)); HIP_TRY(put(b, o.minv, minv, s));
+        HIP_TRY(put(b, o.slot_face, slot_face, s)); HIP_TRY(put(b, o.slot_nb, slot_nb, s));
+        HIP_TRY(put(b, o.cell_case, cell_case, s));
+        HIP_TRY(put(b, o.fL, fL, s)); HIP_TRY(put(b, o.fR, fR, s)); HIP_TRY(put(b, o.fbc, fbc, s));
+        HIP_TRY(put(b, o.fcase, fcase, s)); HIP_TRY(put(b, o.gp_off, gp_off, s)); HIP_TRY(put(b, o.bslot, bslot, s));
+        HIP_TRY(put(b, o.avec, avec, s)); HIP_TRY(put(b, o.S, S, s)); HIP_TRY(put(b, o.shift, shift, s));
+        HIP_TRY(put(b, o.gavg, gavg, s));
+        HIP_TRY(put(b, o.gx, gx, s)); HIP_TRY(put(b, o.gn, gn, s)); HIP_TRY(put(b, o.gw, gw, s));
+        HIP_TRY(put(b, o.gface, gface, s));
+        HIP_TRY(put(b, o.prm, prm, s)); HIP_TRY(put(b, o.flag, zero_flag, s));
+        HIP_TRY(put(b, o.dt, zero_case, s)); HIP_TRY(put(b, o.res, zero_case, s));
+        HIP_TRY(put(b, o.rb_start, b->rb_start, s)); HIP_TRY(put(b, o.rb_count, b->rb_count, s));
+        HIP_TRY(put(b, o.rb_case, b->rb_case, s)); HIP_TRY(put(b, o.case_rb_off, b->case_rb_off, s));
+        HIP_TRY(put(b, o.cb_start, b->cb_start, s)); HIP_TRY(put(b, o.cb_count, b->cb_count, s));
+        // zero state and work arrays so that a cycle never reads garbage
+        HIP_TRY(hipMemsetAsync(b->base + o.W, 0, o.vol - o.W, s));
+        HIP_TRY(hipMemsetAsync(b->base + o.U, 0, o.prm - o.U, s));
+        HIP_TRY(hipStreamSynchronize(s));
+    } catch (const std::bad_alloc &) {
+        return CGKS_ENOMEM;
+    }
+    return CGKS_OK;
+}
+
+cgks_status cgks_batch_destroy(cgks_batch *b) {
+    delete b;
+    return CGKS_OK;
+}
+
+static cgks_status state_xfer(cgks_batch *b, int32_t c, double *W, double *dW, void *stream, bool up) {
+    if (!b || !b->base || c < 0 || c >= b->n_case || (up && !W)) return CGKS_EINVAL;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const HostMesh &m = b->meshes[c]->hm;
+    const int d = b->dim, nv = d + 2;
+    const int64_t n = m.n_cell, NC = b->NC, co = b->cell_off[c];
+    std::vector<double> buf(n);
+    auto rows = [&](double *dev_rows, double *host, int nrow) -> cgks_status {
+        for (int r = 0; r < nrow; ++r) {
+            double *dp = dev_rows + r * NC + co;
+            if (up) {
+                for (int64_t l = 0; l < n; ++l) buf[l] = host ? host[r * n + m.lib2caller[l]] : 0.0;
+                HIP_TRY(hipMemcpyAsync(dp, buf.data(), n * sizeof(double), hipMemcpyHostToDevice, s));
+                HIP_TRY(hipStreamSynchronize(s));
+            } else if (host) {
+                HIP_TRY(hipMemcpyAsync(buf.data(), dp, n * sizeof(double), hipMemcpyDeviceToHost, s));
+                HIP_TRY(hipStreamSynchronize(s));
+                for (int64_t l = 0; l < n; ++l) host[r * n + m.lib2caller[l]] = buf[l];
+            }
+        }
+        return CGKS_OK;
+    };
+    cgks_status st = rows(b->dev.W, W, nv);
+    if (st) return st;
+    return rows(b->dev.dW, dW, d * nv);
+}
+
+cgks_status cgks_state_upload(cgks_batch *b, int32_t c, const double *W, const double *dW, void *stream) {
+    return state_xfer(b, c, const_cast<double *>(W), const_cast<double *>(dW), stream, true);
+}
+
+cgks_status cgks_state_download(cgks_batch *b, int32_t c, double *W, double *dW, void *stream) {
+    return state_xfer(b, c, W, dW, stream, false);
+}
+
+cgks_status cgks_state_device(cgks_batch *b, int32_t c, double **W, double **dW, int64_t *n_cell) {
+    if (!b || !b->base || c < 0 || c >= b->n_case) return CGKS_EINVAL;
+    if (W) *W = b->dev.W + b->cell_off[c];
+    if (dW) *dW = b->dev.dW + b->cell_off[c];
+    if (n_cell) *n_cell = b->meshes[c]->hm.n_cell;
+    return CGKS_OK;
+}
+
+cgks_status cgks_highorder_stage(cgks_batch *b, int32_t stage, void *stream) {
+    if (!b || !b->base || stage < 0 || stage > 1 || (stage == 1 && b->scheme != CGKS_S2O4)) return CGKS_EINVAL;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int mode = stage == 0 ? MODE_STAGE0 : MODE_STAGE1;
+    return b->dim == 2 ? launch_highorder<2>(b, mode, s) : launch_highorder<3>(b, mode, s);
+}
+
+cgks_status cgks_residual(cgks_batch *b, int32_t kind, double *out, void *stream) {
+    if (!b || !b->base || !out) return CGKS_EINVAL;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int nv = b->dim + 2;
+    if (kind == CGKS_RESIDUAL_HIGH) {
+        cgks_status st = b->dim == 2 ? launch_highorder<2>(b, MODE_R1, s) : launch_highorder<3>(b, MODE_R1, s);
+        if (st) return st;
+        HIP_TRY(hipMemcpyAsync(out, b->dev.R1, sizeof(double) * nv * b->NC, hipMemcpyDeviceToDevice, s));
+        return CGKS_OK;
+    }
+    if (kind == CGKS_RESIDUAL_LOW) {
+        if (b->dim == 2) {
+            hipLaunchKernelGGL(k_low_face<2>, dim3(nblk(b->NF)), dim3(kBlock), 0, s, b->dev, (const double *)b->dev.W,
+                               (const double *)nullptr);
+            hipLaunchKernelGGL(k_low_cell<2>, dim3(nblk(b->NC)), dim3(kBlock), 0, s, b->dev, (int)LOW_R0_OUT, out);
+        } else {
+            hipLaunchKernelGGL(k_low_face<3>, dim3(nblk(b->NF)), dim3(kBlock), 0, s, b->dev, (const double *)b->dev.W,
+                               (const double *)nullptr);
+            hipLaunchKernelGGL(k_low_cell<3>, dim3(nblk(b->NC)), dim3(kBlock), 0, s, b->dev, (int)LOW_R0_OUT, out);
+        }
+        HIP_TRY(hipGetLastError());
+        return CGKS_OK;
+    }
+    if (kind == CGKS_RESIDUAL_NORM) {
+        HIP_TRY(hipMemcpyAsync(out, b->dev.res, sizeof(double) * b->n_case, hipMemcpyDeviceToDevice, s));
+        return CGKS_OK;
+    }
+    return CGKS_EINVAL;
+}
+
+cgks_status cgks_lowlevel_smooth(cgks_batch *b, const double *R1, void *stream) {
+    if (!b || !b->base || !R1) return CGKS_EINVAL;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    return b->dim == 2 ? launch_lowlevel<2>(b, R1, s) : launch_lowlevel<3>(b, R1, s);
+}
+
+cgks_status cgks_cycle(cgks_batch *b, double *res, void *stream) {
+    if (!b || !b->base) return CGKS_EINVAL;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    cgks_status st = b->dim == 2 ? launch_cycle<2>(b, s) : launch_cycle<3>(b, s);
+    if (st) return st;
+    if (res) HIP_TRY(hipMemcpyAsync(res, b->dev.res, sizeof(double) * b->n_case, hipMemcpyDeviceToDevice, s));
+    return CGKS_OK;
+}
+
+cgks_status cgks_solve(cgks_batch *b, const cgks_solve_opts *opts, cgks_solve_report *rep, void *stream) {
+    if (!b || !b->base || !opts || !rep || opts->max_cycles <= 0) return CGKS_EINVAL;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int n = b->n_case;
+    const int every = std::max(1, opts->check_every);
+    std::vector<double> res(n), first(n, 0.0), best(n, INFINITY);
+    std::vector<int32_t> flag(n);
+    std::vector<char> done(n, 0);
+    for (int c = 0; c < n; ++c) {
+        rep[c] = cgks_solve_report{0, 0, 0.0, 0.0, CGKS_ENOTCONV};
+    }
+    std::vector<DevParams> prm(n);
+    HIP_TRY(hipMemcpyAsync(prm.data(), b->dev.prm, sizeof(DevParams) * n, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    int remaining = n;
+    for (int k = 0; k < opts->max_cycles && remaining > 0;) {
+        const int todo = std::min(every, opts->max_cycles - k);
+        std::vector<double> hist(size_t(todo) * n);
+        for (int j = 0; j < todo; ++j) {
+            cgks_status st = b->dim == 2 ? launch_cycle<2>(b, s) : launch_cycle<3>(b, s);
+            if (st) return st;
+            HIP_TRY(hipMemcpyAsync(hist.data() + size_t(j) * n, b->dev.res, sizeof(double) * n,
+                                   hipMemcpyDeviceToHost, s));
+        }
+        HIP_TRY(hipMemcpyAsync(flag.data(), b->dev.flag, sizeof(int32_t) * n, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        bool changed = false;
+        for (int j = 0; j < todo; ++j) {
+            for (int c = 0; c < n; ++c) {
+                if (done[c]) continue;
+                const double r = hist[size_t(j) * n + c];
+                const int cyc = k + j + 1;
+                rep[c].cycles = cyc;
+                rep[c].res_last = r;
+                if (cyc == 1) rep[c].res_first = first[c] = r;
+                if (opts->res_history) opts->res_history[size_t(c) * opts->max_cycles + cyc - 1] = r;
+                best[c] = std::min(best[c], r);
+                cgks_status cst = CGKS_OK;
+                if (flag[c] & 1 || !std::isfinite(r)) cst = CGKS_ENONPHYS;
+                else if (r > 1e3 * best[c]) cst = CGKS_EDIVERGED;
+                const bool conv = opts->tol_abs ? r <= opts->tol : (first[c] > 0 && r / first[c] <= opts->tol);
+                if (cst != CGKS_OK || conv) {
+                    done[c] = 1;
+                    --remaining;
+                    rep[c].converged = conv && cst == CGKS_OK;
+                    rep[c].status = cst == CGKS_OK ? CGKS_OK : cst;
+                    prm[c].active = 0;
+                    changed = true;
+                }
+            }
+        }
+        if (changed) {
+            HIP_TRY(hipMemcpyAsync((void *)b->dev.prm, prm.data(), sizeof(DevParams) * n, hipMemcpyHostToDevice, s));
+            HIP_TRY(hipStreamSynchronize(s));
+        }
+        k += todo;
+    }
+    // leave every case active again for later calls
+    for (int c = 0; c < n; ++c) prm[c].active = 1;
+    HIP_TRY(hipMemcpyAsync((void *)b->dev.prm, prm.data(), sizeof(DevParams) * n, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return CGKS_OK;
+}
+
+}  // extern "C"

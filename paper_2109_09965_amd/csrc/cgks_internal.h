@@ -1,0 +1,53 @@
+// Internal declarations shared by the host preprocessing and the HIP entry
+// points of libcgks.so.  Not part of the C ABI.
+#pragma once
+#include <cstdint>
+#include <vector>
+
+#include "../../include/cgks.h"
+
+namespace cgks {
+
+constexpr int kMaxGP = 4;     // Gauss points per face (3-D quad)
+constexpr int kMaxSlots = 8;  // faces per cell kept in the padded slot table
+constexpr double kRankTol = 1e-8;
+
+inline int ncoef_of(int dim) { return dim == 2 ? 5 : 9; }
+inline int nquad_of(int dim) { return dim == 2 ? 3 : 6; }
+
+// Host-side mesh: geometry in caller order plus the library cell order.
+struct HostMesh {
+    int dim = 0, nv = 0, nk = 0, nq = 0;
+    int64_t n_cell = 0, n_face = 0, n_gp = 0, n_bface = 0;
+    // input topology
+    std::vector<double> xyz;
+    std::vector<int64_t> fptr, fvert, owner, neigh;
+    std::vector<int32_t> bc;
+    std::vector<double> shift;      // [face][dim]
+    // faces
+    std::vector<int32_t> ngp;       // per face
+    std::vector<int64_t> gp_off;    // [n_face + 1]
+    std::vector<double> gx, gn, gw; // [gp][dim], [gp][dim], [gp]
+    std::vector<double> avec, S;    // [face][dim], [face]
+    // cells (caller order)
+    std::vector<double> vol, ctr, sec, h;   // sec [cell][nq] central second moments
+    std::vector<int64_t> cf_ptr, cf_face;   // faces of each cell, increasing face index
+    std::vector<int8_t> cf_side;            // 0 owner, 1 neighbour
+    std::vector<int32_t> colour;
+    int n_colour = 0;
+    // reconstruction
+    std::vector<double> minv;               // [cell][nk*nk] (M^T M)^-1, linear block only on fallback
+    std::vector<uint8_t> linear;            // 1 = linear fallback
+    std::vector<double> gavg;               // [face][nk] ghost basis averages (boundary faces)
+    // library order
+    std::vector<int64_t> lib2caller, caller2lib;
+    std::vector<int64_t> colour_count;      // cells per colour
+};
+
+cgks_status build_host_mesh(const cgks_mesh_desc *d, HostMesh &m);
+
+}  // namespace cgks
+
+struct cgks_mesh {
+    cgks::HostMesh hm;
+};

@@ -1,0 +1,1099 @@
+// Device code of the p-multigrid CGKS cycle for gfx950.  Included once, by
+// cgks_api.hip.
+//
+// Layout: every per-cell array is structure-of-arrays over the batch's
+// concatenated library cell order, [component][NC]; per-face arrays are
+// [component][NF]; per-Gauss-point arrays [component][NG].  Indices are
+// int32.  One thread per cell, face or Gauss point; all gathers follow a
+// fixed slot order, so every result is bitwise reproducible run to run (no
+// floating-point atomics anywhere).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+namespace cgks {
+
+constexpr int kBlock = 256;
+
+struct DevParams {
+    double gamma, mu, Pr, T_wall;
+    double W_inf[5];
+    double cfl_high, cfl_low, dt_fixed;
+    double K;          // internal degrees of freedom of the gas
+    int32_t scheme;    // 0 S2O4, 1 S1O2
+    int32_t explicit_only;
+    int32_t active;    // 0: the case is frozen (finished), kernels leave it untouched
+    int32_t pad;
+};
+
+struct Dev {
+    int32_t NC, NF, NG, NB;
+    // cells
+    double *W, *dW, *Wn, *L0, *Lt0, *G0, *coef;
+    const double *vol, *h, *ctr, *sec, *minv;
+    const int32_t *slot_face, *slot_nb, *cell_case;
+    // faces
+    const int32_t *fL, *fR, *fbc, *fcase, *gp_off, *bslot;
+    const double *avec, *S, *shift, *gavg;
+    // gauss points
+    const double *gx, *gn, *gw;
+    const int32_t *gface;
+    double *gF0, *gFt, *gWc, *gWt;
+    // low level
+    double *U, *dU, *Sf, *RHS, *D, *R1, *lam, *Flow;
+    // per case
+    const DevParams *prm;
+    double *dt, *res;
+    int32_t *flag;     // per case: bit 0 non-physical state met
+    // reductions
+    const int32_t *rb_start, *rb_count, *rb_case, *case_rb_off;
+    double *part0, *part1;
+};
+
+template <int D> struct Dim {
+    static constexpr int nv = D + 2;
+    static constexpr int nk = D == 2 ? 5 : 9;
+    static constexpr int nq = D == 2 ? 3 : 6;
+    static constexpr int ns = D == 2 ? 4 : 8;   // slots per cell
+    static constexpr int nsym = nk * (nk + 1) / 2;
+};
+
+// quadratic basis (a, b) pairs: 2-D (00, 01, 11); 3-D (00, 11, 22, 01, 02, 12)
+template <int D> __device__ __forceinline__ int qa(int q) {
+    if (D == 2) return q == 2 ? 1 : 0;
+    return q < 3 ? q : (q == 5 ? 1 : 0);
+}
+template <int D> __device__ __forceinline__ int qb(int q) {
+    if (D == 2) return q == 0 ? 0 : 1;
+    return q < 3 ? q : (q == 3 ? 1 : 2);
+}
+// packed index of the symmetric pair (a, b) in the second-moment arrays
+template <int D> __device__ __forceinline__ int sidx(int a, int b) {
+    if (a > b) { int t = a; a = b; b = t; }
+    if (D == 2) return a + b;
+    return a == 0 ? b : (a == 1 ? 2 + b : 5);
+}
+// packed upper-triangle index of (j, k) in an nk x nk symmetric matrix
+template <int D> __device__ __forceinline__ int midx(int j, int k) {
+    if (j > k) { int t = j; j = k; k = t; }
+    return j * Dim<D>::nk - (j * (j - 1)) / 2 + (k - j);
+}
+
+// ---------------------------------------------------------------------
+// Local face frame (n, t1, t2): an orthonormal basis built without
+// branches on the normal (Duff et al., "Building an orthonormal basis,
+// revisited", 2017).  The flux is frame invariant.
+// ---------------------------------------------------------------------
+template <int D> struct Frame {
+    double e[D][D];
+    __device__ __forceinline__ void build(const double *n) {
+        if constexpr (D == 2) {
+            e[0][0] = n[0]; e[0][1] = n[1];
+            e[1][0] = -n[1]; e[1][1] = n[0];
+        } else {
+            const double s = copysign(1.0, n[2]);
+            const double a = -1.0 / (s + n[2]);
+            const double b = n[0] * n[1] * a;
+            e[0][0] = n[0]; e[0][1] = n[1]; e[0][2] = n[2];
+            e[1][0] = 1.0 + s * n[0] * n[0] * a; e[1][1] = s * b; e[1][2] = -s * n[0];
+            e[2][0] = b; e[2][1] = s + n[1] * n[1] * a; e[2][2] = -n[1];
+        }
+    }
+    // vector components of a state (momentum) global -> local
+    __device__ __forceinline__ void to_local(const double *W, double *Wl) const {
+        constexpr int nv = D + 2;
+        Wl[0] = W[0];
+        Wl[nv - 1] = W[nv - 1];
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            double s = 0;
+#pragma unroll
+            for (int b = 0; b < D; ++b) s += e[a][b] * W[1 + b];
+            Wl[1 + a] = s;
+        }
+    }
+    __device__ __forceinline__ void to_global(const double *Wl, double *W) const {
+        constexpr int nv = D + 2;
+        W[0] = Wl[0];
+        W[nv - 1] = Wl[nv - 1];
+#pragma unroll
+        for (int b = 0; b < D; ++b) {
+            double s = 0;
+#pragma unroll
+            for (int a = 0; a < D; ++a) s += e[a][b] * Wl[1 + a];
+            W[1 + b] = s;
+        }
+    }
+    // gradient G[axis][v] global -> derivatives along local axes of local components
+    __device__ __forceinline__ void grad_to_local(const double G[D][D + 2], double Gl[D][D + 2]) const {
+        constexpr int nv = D + 2;
+        double T[D][nv];
+#pragma unroll
+        for (int a = 0; a < D; ++a)
+#pragma unroll
+            for (int v = 0; v < nv; ++v) {
+                double s = 0;
+#pragma unroll
+                for (int b = 0; b < D; ++b) s += e[a][b] * G[b][v];
+                T[a][v] = s;
+            }
+#pragma unroll
+        for (int a = 0; a < D; ++a) to_local(T[a], Gl[a]);
+    }
+};
+
+// ---------------------------------------------------------------------
+// Maxwellian moments (per unit density) in the local frame.
+// ---------------------------------------------------------------------
+template <int D> struct Moments {
+    double mu[7], mv[6], mw[6], xi[3];
+    __device__ __forceinline__ void full(const double *U, double lam, double K) {
+        const double il = 0.5 / lam;
+        mu[0] = 1.0; mu[1] = U[0];
+#pragma unroll
+        for (int k = 2; k < 7; ++k) mu[k] = U[0] * mu[k - 1] + (k - 1) * il * mu[k - 2];
+        mv[0] = 1.0; mv[1] = U[1];
+#pragma unroll
+        for (int k = 2; k < 6; ++k) mv[k] = U[1] * mv[k - 1] + (k - 1) * il * mv[k - 2];
+        if (D == 3) {
+            mw[0] = 1.0; mw[1] = U[D - 1];
+#pragma unroll
+            for (int k = 2; k < 6; ++k) mw[k] = U[D - 1] * mw[k - 1] + (k - 1) * il * mw[k - 2];
+        }
+        xi[0] = 1.0;
+        xi[1] = K * il;
+        xi[2] = (K * K + 2.0 * K) * il * il;
+    }
+    __device__ __forceinline__ double M(int i, int j, int l, int e) const {
+        return D == 3 ? mu[i] * mv[j] * mw[l] * xi[e] : mu[i] * mv[j] * xi[e];
+    }
+};
+
+// micro-slope coefficients a = a0 + a_u u + a_v v (+ a_w w) + a_E (u^2 + .. + xi^2)/2
+// solving <a psi> = b in closed form (b per unit density)
+template <int D> __device__ __forceinline__ void micro_slope(const double *b, const double *U, double lam, double N,
+                                                             double *a) {
+    constexpr int nv = D + 2;
+    double U2 = 0, Ub = 0;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        U2 += U[k] * U[k];
+        Ub += U[k] * b[1 + k];
+    }
+    const double aE = 4.0 * lam * lam / N * (2.0 * b[nv - 1] - 2.0 * Ub + (U2 - N / (2.0 * lam)) * b[0]);
+    double aU = 0;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        a[1 + k] = 2.0 * lam * (b[1 + k] - U[k] * b[0]) - aE * U[k];
+        aU += a[1 + k] * U[k];
+    }
+    a[nv - 1] = aE;
+    a[0] = b[0] - aU - 0.5 * aE * (U2 + N / (2.0 * lam));
+}
+
+// E[a u^i v^j w^l xi^(2e)]
+template <int D> __device__ __forceinline__ double Ea(const Moments<D> &m, const double *a, int i, int j, int l, int e) {
+    double s = a[0] * m.M(i, j, l, e) + a[1] * m.M(i + 1, j, l, e) + a[2] * m.M(i, j + 1, l, e);
+    double q = m.M(i + 2, j, l, e) + m.M(i, j + 2, l, e) + m.M(i, j, l, e + 1);
+    if constexpr (D == 3) {
+        s += a[3] * m.M(i, j, l + 1, e);
+        q += m.M(i, j, l + 2, e);
+    }
+    return s + 0.5 * a[D + 1] * q;
+}
+
+// out[p] = E[psi_p a u^i v^j w^l]
+template <int D> __device__ __forceinline__ void Epsi(const Moments<D> &m, const double *a, int i, int j, int l,
+                                                      double *out) {
+    constexpr int nv = D + 2;
+    out[0] = Ea<D>(m, a, i, j, l, 0);
+    out[1] = Ea<D>(m, a, i + 1, j, l, 0);
+    out[2] = Ea<D>(m, a, i, j + 1, l, 0);
+    double q = Ea<D>(m, a, i + 2, j, l, 0) + Ea<D>(m, a, i, j + 2, l, 0) + Ea<D>(m, a, i, j, l, 1);
+    if constexpr (D == 3) {
+        out[3] = Ea<D>(m, a, i, j, l + 1, 0);
+        q += Ea<D>(m, a, i, j, l + 2, 0);
+    }
+    out[nv - 1] = 0.5 * q;
+}
+
+// primitive variables of a local-frame state
+template <int D> struct Prim {
+    double rho, U[D], p, lam;
+    __device__ __forceinline__ void from(const double *W, double gamma) {
+        rho = W[0];
+        double ke = 0;
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            U[a] = W[1 + a] / rho;
+            ke += U[a] * U[a];
+        }
+        p = (gamma - 1.0) * (W[D + 1] - 0.5 * rho * ke);
+        lam = rho / (2.0 * p);
+    }
+};
+
+// Smooth-flow gas-kinetic flux (local frame, axis 0 = normal):
+//   f = g^c [1 - tau (a.u + A) + A t]
+// F0 = flux at t = 0, Ft = its time derivative, Wt = rho <A psi>.
+// Returns false for a non-physical interface state.
+template <int D> __device__ bool gks_flux(const double *Wc, const double Gc[D][D + 2], const DevParams &P, double *F0,
+                                          double *Ft, double *Wt) {
+    constexpr int nv = D + 2;
+    Prim<D> q;
+    q.from(Wc, P.gamma);
+    if (!(q.rho > 0.0) || !(q.p > 0.0)) return false;
+    const double N = P.K + D;
+    double Uf[3] = {0, 0, 0};
+#pragma unroll
+    for (int a = 0; a < D; ++a) Uf[a] = q.U[a];
+    Moments<D> m;
+    m.full(Uf, q.lam, P.K);
+    const double tau = P.mu / q.p;
+    const double ir = 1.0 / q.rho;
+    double a[D][nv], b[nv], A[nv], t0[nv], t1[nv];
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+#pragma unroll
+        for (int v = 0; v < nv; ++v) b[v] = Gc[j][v] * ir;
+        micro_slope<D>(b, q.U, q.lam, N, a[j]);
+    }
+    // compatibility: <A psi> = -<(a^n u + a^t1 v [+ a^t2 w]) psi>
+    Epsi<D>(m, a[0], 1, 0, 0, t0);
+    Epsi<D>(m, a[1], 0, 1, 0, t1);
+#pragma unroll
+    for (int v = 0; v < nv; ++v) b[v] = -(t0[v] + t1[v]);
+    if constexpr (D == 3) {
+        Epsi<D>(m, a[D - 1], 0, 0, 1, t0);
+#pragma unroll
+        for (int v = 0; v < nv; ++v) b[v] -= t0[v];
+    }
+    micro_slope<D>(b, q.U, q.lam, N, A);
+    // E[u psi (A)] gives the time derivative of the flux
+    double eA[nv];
+    Epsi<D>(m, A, 1, 0, 0, eA);
+    // E[u psi (a.u)]
+    double tt[nv];
+    Epsi<D>(m, a[0], 2, 0, 0, tt);
+    Epsi<D>(m, a[1], 1, 1, 0, t1);
+#pragma unroll
+    for (int v = 0; v < nv; ++v) tt[v] += t1[v];
+    if constexpr (D == 3) {
+        Epsi<D>(m, a[D - 1], 1, 0, 1, t1);
+#pragma unroll
+        for (int v = 0; v < nv; ++v) tt[v] += t1[v];
+    }
+    // E[u psi]
+    double eu[nv];
+    eu[0] = m.mu[1];
+    eu[1] = m.mu[2];
+    eu[2] = m.mu[1] * m.mv[1];
+    double ep = m.mu[3] + m.mu[1] * (m.mv[2] + m.xi[1]);
+    if (D == 3) {
+        eu[3] = m.mu[1] * m.mw[1];
+        ep += m.mu[1] * m.mw[2];
+    }
+    eu[nv - 1] = 0.5 * ep;
+#pragma unroll
+    for (int v = 0; v < nv; ++v) {
+        F0[v] = q.rho * (eu[v] - tau * (tt[v] + eA[v]));
+        Ft[v] = q.rho * eA[v];
+        Wt[v] = q.rho * b[v];
+    }
+    if (P.Pr != 1.0 && P.mu != 0.0) {
+        // Fourier heat flux of the interface state along the normal (R = 1, T = p/rho)
+        double ke = 0, ked = 0;
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            ke += q.U[k] * q.U[k];
+            ked += q.U[k] * Gc[0][1 + k];
+        }
+        const double pn = (P.gamma - 1.0) * (Gc[0][nv - 1] - ked + 0.5 * ke * Gc[0][0]);
+        const double Tn = (pn * q.rho - q.p * Gc[0][0]) / (q.rho * q.rho);
+        F0[nv - 1] += (1.0 / P.Pr - 1.0) * (-P.mu * P.gamma / (P.gamma - 1.0) * Tn);
+    }
+    return true;
+}
+
+// half-range moments <u^k>_{u >< 0}, k = 0..3
+__device__ __forceinline__ void half_moments(double U, double lam, double sgn, double *m) {
+    m[0] = 0.5 * erfc(-sgn * sqrt(lam) * U);
+    m[1] = U * m[0] + sgn * 0.5 * exp(-lam * U * U) * rsqrt(M_PI * lam);
+    m[2] = U * m[1] + 0.5 / lam * m[0];
+    m[3] = U * m[2] + 1.0 / lam * m[1];
+}
+
+// accumulate rho <psi>_{half} (state) and rho <u psi>_{half} (flux) of one side
+template <int D> __device__ __forceinline__ bool half_side(const double *W, const DevParams &P, double sgn,
+                                                           double *Wacc, double *Facc) {
+    constexpr int nv = D + 2;
+    Prim<D> q;
+    q.from(W, P.gamma);
+    if (!(q.rho > 0.0) || !(q.p > 0.0)) return false;
+    double m[4];
+    half_moments(q.U[0], q.lam, sgn, m);
+    double ut2 = 0;
+#pragma unroll
+    for (int a = 1; a < D; ++a) ut2 += q.U[a] * q.U[a];
+    const double rest = ut2 + (P.K + D - 1) * 0.5 / q.lam;   // <v^2> + <w^2> + <xi^2>
+    if (Wacc) {
+        Wacc[0] += q.rho * m[0];
+        Wacc[1] += q.rho * m[1];
+#pragma unroll
+        for (int a = 1; a < D; ++a) Wacc[1 + a] += q.rho * m[0] * q.U[a];
+        Wacc[nv - 1] += 0.5 * q.rho * (m[2] + m[0] * rest);
+    }
+    if (Facc) {
+        Facc[0] += q.rho * m[1];
+        Facc[1] += q.rho * m[2];
+#pragma unroll
+        for (int a = 1; a < D; ++a) Facc[1 + a] += q.rho * m[1] * q.U[a];
+        Facc[nv - 1] += 0.5 * q.rho * (m[3] + m[1] * rest);
+    }
+    return true;
+}
+
+// characteristic far-field state (local frame, axis 0 outward)
+template <int D> __device__ void farfield_state(const double *Wl, const double *Wo, double gamma, double *Wb) {
+    constexpr int nv = D + 2;
+    Prim<D> I, O;
+    I.from(Wl, gamma);
+    O.from(Wo, gamma);
+    const double cI = sqrt(gamma * I.p / I.rho), cO = sqrt(gamma * O.p / O.rho);
+    if (O.U[0] <= -cO) {
+#pragma unroll
+        for (int v = 0; v < nv; ++v) Wb[v] = Wo[v];
+        return;
+    }
+    if (I.U[0] >= cI) {
+#pragma unroll
+        for (int v = 0; v < nv; ++v) Wb[v] = Wl[v];
+        return;
+    }
+    const double Rp = I.U[0] + 2.0 * cI / (gamma - 1.0);
+    const double Rm = O.U[0] - 2.0 * cO / (gamma - 1.0);
+    const double Un = 0.5 * (Rp + Rm);
+    const double c = 0.25 * (gamma - 1.0) * (Rp - Rm);
+    const Prim<D> &up = Un > 0 ? I : O;
+    const double s = up.p / pow(up.rho, gamma);
+    const double rho = pow(c * c / (gamma * s), 1.0 / (gamma - 1.0));
+    const double p = rho * c * c / gamma;
+    double ke = Un * Un;
+    Wb[0] = rho;
+    Wb[1] = rho * Un;
+#pragma unroll
+    for (int a = 1; a < D; ++a) {
+        Wb[1 + a] = rho * up.U[a];
+        ke += up.U[a] * up.U[a];
+    }
+    Wb[nv - 1] = p / (gamma - 1.0) + 0.5 * rho * ke;
+}
+
+// normal Euler flux of U along unit n (global frame)
+template <int D> __device__ __forceinline__ void euler_flux(const double *U, const double *n, double gamma, double *F) {
+    constexpr int nv = D + 2;
+    const double rho = U[0];
+    double ke = 0, un = 0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        ke += U[1 + a] * U[1 + a];
+        un += U[1 + a] * n[a];
+    }
+    un /= rho;
+    const double p = (gamma - 1.0) * (U[nv - 1] - 0.5 * ke / rho);
+    F[0] = rho * un;
+#pragma unroll
+    for (int a = 0; a < D; ++a) F[1 + a] = U[1 + a] * un + p * n[a];
+    F[nv - 1] = (U[nv - 1] + p) * un;
+}
+
+// ---------------------------------------------------------------------
+// Global time step: per-block minimum over a case's cells, then per case.
+// ---------------------------------------------------------------------
+template <int D> __device__ __forceinline__ double cell_dt(const double *W, int i, int NC, double h, double cfl,
+                                                           const DevParams &P) {
+    constexpr int nv = D + 2;
+    const double rho = W[i];
+    double ke = 0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        const double u = W[(1 + a) * NC + i] / rho;
+        ke += u * u;
+    }
+    const double p = (P.gamma - 1.0) * (W[(nv - 1) * NC + i] - 0.5 * rho * ke);
+    const double c = sqrt(P.gamma * p / rho);
+    return cfl * h / (sqrt(ke) + c + 2.0 * P.mu / rho / h);
+}
+
+__device__ __forceinline__ double block_reduce_sum(double v, double *sh) {
+    const int t = threadIdx.x;
+    sh[t] = v;
+    __syncthreads();
+    for (int s = kBlock / 2; s > 0; s >>= 1) {
+        if (t < s) sh[t] += sh[t + s];
+        __syncthreads();
+    }
+    const double r = sh[0];
+    __syncthreads();
+    return r;
+}
+__device__ __forceinline__ double block_reduce_min(double v, double *sh) {
+    const int t = threadIdx.x;
+    sh[t] = v;
+    __syncthreads();
+    for (int s = kBlock / 2; s > 0; s >>= 1) {
+        if (t < s) sh[t] = fmin(sh[t], sh[t + s]);
+        __syncthreads();
+    }
+    const double r = sh[0];
+    __syncthreads();
+    return r;
+}
+
+template <int D> __global__ __launch_bounds__(kBlock) void k_dt_partial(Dev d) {
+    __shared__ double sh[kBlock];
+    const int b = blockIdx.x;
+    const int c = d.rb_case[b];
+    const DevParams &P = d.prm[c];
+    const int n = d.rb_count[b];
+    double v = INFINITY;
+    for (int k = threadIdx.x; k < n; k += kBlock) {
+        const int i = d.rb_start[b] + k;
+        v = fmin(v, cell_dt<D>(d.W, i, d.NC, d.h[i], P.cfl_high, P));
+    }
+    v = block_reduce_min(v, sh);
+    if (threadIdx.x == 0) d.part0[b] = v;
+}
+
+// one thread per case: sequential min / sums in block order (fixed shape)
+__global__ void k_dt_final(Dev d, int n_case) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n_case) return;
+    const DevParams &P = d.prm[c];
+    if (!P.active) return;
+    double v = INFINITY;
+    for (int b = d.case_rb_off[c]; b < d.case_rb_off[c + 1]; ++b) v = fmin(v, d.part0[b]);
+    d.dt[c] = P.dt_fixed > 0 ? P.dt_fixed : v;
+}
+
+// ---------------------------------------------------------------------
+// Compact reconstruction: c = (M^T M)^-1 M^T b per cell, with the rows of
+// M generated here from the cell geometry (face neighbours, mirror ghosts
+// of boundary faces, own gradient) and (M^T M)^-1 precomputed on the host.
+// ---------------------------------------------------------------------
+template <int D> __device__ __forceinline__ void ghost_data(int bc, const double *n, const double *Wi,
+                                                            const double Gi[D][D + 2], const DevParams &P, double *Wg,
+                                                            double Gg[D][D + 2]) {
+    constexpr int nv = D + 2;
+    if (bc == 4) {  // far field
+        Frame<D> fr;
+        fr.build(n);
+        double Wl[nv], Wo[nv], Wo_g[nv], Wb[nv];
+#pragma unroll
+        for (int v = 0; v < nv; ++v) Wo_g[v] = P.W_inf[v];
+        fr.to_local(Wi, Wl);
+        fr.to_local(Wo_g, Wo);
+        farfield_state<D>(Wl, Wo, P.gamma, Wb);
+        fr.to_global(Wb, Wg);
+#pragma unroll
+        for (int a = 0; a < D; ++a)
+#pragma unroll
+            for (int v = 0; v < nv; ++v) Gg[a][v] = 0.0;
+        return;
+    }
+    // slip (M = R on momentum) or no-slip (M = -I on momentum); R = I - 2 n n^T
+    const bool slip = bc == 1;
+    double R[D][D];
+#pragma unroll
+    for (int a = 0; a < D; ++a)
+#pragma unroll
+        for (int b = 0; b < D; ++b) R[a][b] = (a == b ? 1.0 : 0.0) - 2.0 * n[a] * n[b];
+    Wg[0] = Wi[0];
+    Wg[nv - 1] = Wi[nv - 1];
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        double s = 0;
+#pragma unroll
+        for (int b = 0; b < D; ++b) s += (slip ? R[a][b] : (a == b ? -1.0 : 0.0)) * Wi[1 + b];
+        Wg[1 + a] = s;
+    }
+    // MG[b][v] = (M G_i[b])_v, then Gg[a][v] = sum_b R[a][b] MG[b][v]
+    double MG[D][nv];
+#pragma unroll
+    for (int b = 0; b < D; ++b) {
+        MG[b][0] = Gi[b][0];
+        MG[b][nv - 1] = Gi[b][nv - 1];
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            double s = 0;
+#pragma unroll
+            for (int c = 0; c < D; ++c) s += (slip ? R[a][c] : (a == c ? -1.0 : 0.0)) * Gi[b][1 + c];
+            MG[b][1 + a] = s;
+        }
+    }
+#pragma unroll
+    for (int a = 0; a < D; ++a)
+#pragma unroll
+        for (int v = 0; v < nv; ++v) {
+            double s = 0;
+#pragma unroll
+            for (int b = 0; b < D; ++b) s += R[a][b] * MG[b][v];
+            Gg[a][v] = s;
+        }
+}
+
+template <int D> __global__ __launch_bounds__(kBlock) void k_recon(Dev d) {
+    using T = Dim<D>;
+    constexpr int nv = T::nv, nk = T::nk, nq = T::nq;
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= d.NC) return;
+    const int NC = d.NC;
+    const DevParams &P = d.prm[d.cell_case[i]];
+    const double h = d.h[i], ih = 1.0 / h;
+    double xc[D], Wi[nv], Gi[D][nv], own[nq];
+#pragma unroll
+    for (int a = 0; a < D; ++a) xc[a] = d.ctr[a * NC + i];
+#pragma unroll
+    for (int v = 0; v < nv; ++v) Wi[v] = d.W[v * NC + i];
+#pragma unroll
+    for (int a = 0; a < D; ++a)
+#pragma unroll
+        for (int v = 0; v < nv; ++v) Gi[a][v] = d.dW[(a * nv + v) * NC + i];
+#pragma unroll
+    for (int q = 0; q < nq; ++q) own[q] = d.sec[sidx<D>(qa<D>(q), qb<D>(q)) * NC + i] * ih * ih;
+    double rhs[nk][nv];
+#pragma unroll
+    for (int k = 0; k < nk; ++k)
+#pragma unroll
+        for (int v = 0; v < nv; ++v) rhs[k][v] = 0.0;
+#pragma unroll 1
+    for (int s = 0; s < T::ns; ++s) {
+        const int code = d.slot_face[s * NC + i];
+        if (code == 0) break;
+        const int f = (code > 0 ? code : -code) - 1;
+        const int nb = d.slot_nb[s * NC + i];
+        double avg[nk], Wm[nv], Gm[D][nv];
+        if (nb >= 0) {
+            const double sg = code > 0 ? 1.0 : -1.0;
+            double dx[D];
+#pragma unroll
+            for (int a = 0; a < D; ++a) {
+                dx[a] = d.ctr[a * NC + nb] + sg * d.shift[a * d.NF + f] - xc[a];
+                avg[a] = dx[a] * ih;
+            }
+#pragma unroll
+            for (int q = 0; q < nq; ++q) {
+                const int a = qa<D>(q), b = qb<D>(q);
+                avg[D + q] = (d.sec[sidx<D>(a, b) * NC + nb] + dx[a] * dx[b]) * ih * ih;
+            }
+#pragma unroll
+            for (int v = 0; v < nv; ++v) Wm[v] = d.W[v * NC + nb];
+#pragma unroll
+            for (int a = 0; a < D; ++a)
+#pragma unroll
+                for (int v = 0; v < nv; ++v) Gm[a][v] = d.dW[(a * nv + v) * NC + nb];
+        } else {
+            const int bs = d.bslot[f];
+#pragma unroll
+            for (int k = 0; k < nk; ++k) avg[k] = d.gavg[k * d.NB + bs];
+            double n[D];
+            const double iS = 1.0 / d.S[f];
+#pragma unroll
+            for (int a = 0; a < D; ++a) n[a] = d.avec[a * d.NF + f] * iS;
+            ghost_data<D>(d.fbc[f], n, Wi, Gi, P, Wm, Gm);
+        }
+        // average row
+#pragma unroll
+        for (int v = 0; v < nv; ++v) {
+            const double bv = Wm[v] - Wi[v];
+#pragma unroll
+            for (int a = 0; a < D; ++a) rhs[a][v] += avg[a] * bv;
+#pragma unroll
+            for (int q = 0; q < nq; ++q) rhs[D + q][v] += (avg[D + q] - own[q]) * bv;
+        }
+        // gradient rows
+#pragma unroll
+        for (int a = 0; a < D; ++a)
+#pragma unroll
+            for (int v = 0; v < nv; ++v) {
+                const double bv = h * Gm[a][v];
+                rhs[a][v] += bv;
+#pragma unroll
+                for (int q = 0; q < nq; ++q) {
+                    const int p = qa<D>(q), r = qb<D>(q);
+                    const double row = (p == a ? avg[r] : 0.0) + (r == a ? avg[p] : 0.0);
+                    rhs[D + q][v] += row * bv;
+                }
+            }
+    }
+    // own-gradient rows
+#pragma unroll
+    for (int a = 0; a < D; ++a)
+#pragma unroll
+        for (int v = 0; v < nv; ++v) rhs[a][v] += h * Gi[a][v];
+    // c = Minv rhs
+#pragma unroll
+    for (int k = 0; k < nk; ++k) {
+        double c[nv];
+#pragma unroll
+        for (int v = 0; v < nv; ++v) c[v] = 0.0;
+#pragma unroll
+        for (int j = 0; j < nk; ++j) {
+            const double mkj = d.minv[midx<D>(k, j) * NC + i];
+#pragma unroll
+            for (int v = 0; v < nv; ++v) c[v] += mkj * rhs[j][v];
+        }
+#pragma unroll
+        for (int v = 0; v < nv; ++v) d.coef[(k * nv + v) * NC + i] = c[v];
+    }
+}
+
+// value and gradient of P_i at x (x in cell i's frame)
+template <int D> __device__ __forceinline__ void recon_eval(const Dev &d, int i, const double *x, double *Wx,
+                                                            double G[D][D + 2]) {
+    using T = Dim<D>;
+    constexpr int nv = T::nv, nq = T::nq;
+    const int NC = d.NC;
+    const double h = d.h[i], ih = 1.0 / h;
+    double y[D];
+#pragma unroll
+    for (int a = 0; a < D; ++a) y[a] = (x[a] - d.ctr[a * NC + i]) * ih;
+#pragma unroll
+    for (int v = 0; v < nv; ++v) {
+        Wx[v] = d.W[v * NC + i];
+#pragma unroll
+        for (int a = 0; a < D; ++a) G[a][v] = 0.0;
+    }
+#pragma unroll
+    for (int a = 0; a < D; ++a)
+#pragma unroll
+        for (int v = 0; v < nv; ++v) {
+            const double c = d.coef[(a * nv + v) * NC + i];
+            Wx[v] += c * y[a];
+            G[a][v] += c;
+        }
+#pragma unroll
+    for (int q = 0; q < nq; ++q) {
+        const int a = qa<D>(q), b = qb<D>(q);
+        const double phi = y[a] * y[b] - d.sec[sidx<D>(a, b) * NC + i] * ih * ih;
+#pragma unroll
+        for (int v = 0; v < nv; ++v) {
+            const double c = d.coef[((D + q) * nv + v) * NC + i];
+            Wx[v] += c * phi;
+            G[a][v] += c * y[b];
+            G[b][v] += c * y[a];
+        }
+    }
+#pragma unroll
+    for (int a = 0; a < D; ++a)
+#pragma unroll
+        for (int v = 0; v < nv; ++v) G[a][v] *= ih;
+}
+
+// ---------------------------------------------------------------------
+// Face flux at every Gauss point: interface states, boundary states,
+// kinetic interface equilibrium, smooth gas-kinetic flux.  Outputs are
+// weighted by wJ and in the global frame.
+// ---------------------------------------------------------------------
+template <int D> __global__ __launch_bounds__(kBlock) void k_flux(Dev d) {
+    constexpr int nv = D + 2;
+    const int g = blockIdx.x * kBlock + threadIdx.x;
+    if (g >= d.NG) return;
+    const int f = d.gface[g];
+    const int cs = d.fcase[f];
+    const DevParams &P = d.prm[cs];
+    const int L = d.fL[f], R = d.fR[f];
+    double x[D], n[D];
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        x[a] = d.gx[a * d.NG + g];
+        n[a] = d.gn[a * d.NG + g];
+    }
+    const double wJ = d.gw[g];
+    Frame<D> fr;
+    fr.build(n);
+    double Wg[nv], GL[D][nv], WL[nv], GLl[D][nv];
+    recon_eval<D>(d, L, x, Wg, GL);
+    fr.to_local(Wg, WL);
+    fr.grad_to_local(GL, GLl);
+    double Wc[nv], Gc[D][nv];
+    bool ok = true;
+    const int bc = d.fbc[f];
+    if (R >= 0 || bc != 2) {
+        double WR[nv], GRl[D][nv];
+        if (R >= 0) {
+            double xr[D], WRg[nv], GR[D][nv];
+#pragma unroll
+            for (int a = 0; a < D; ++a) xr[a] = x[a] - d.shift[a * d.NF + f];
+            recon_eval<D>(d, R, xr, WRg, GR);
+            fr.to_local(WRg, WR);
+            fr.grad_to_local(GR, GRl);
+        } else if (bc == 1) {
+            // mirror: normal momentum reversed; normal derivatives change sign
+            // except that of the normal momentum
+#pragma unroll
+            for (int v = 0; v < nv; ++v) WR[v] = WL[v];
+            WR[1] = -WL[1];
+#pragma unroll
+            for (int a = 0; a < D; ++a)
+#pragma unroll
+                for (int v = 0; v < nv; ++v) {
+                    const double sa = (a == 0) ? -1.0 : 1.0;
+                    GRl[a][v] = (v == 1 ? -sa : sa) * GLl[a][v];
+                }
+        } else {
+            double Wo_g[nv], Wo[nv];
+#pragma unroll
+            for (int v = 0; v < nv; ++v) Wo_g[v] = P.W_inf[v];
+            fr.to_local(Wo_g, Wo);
+            farfield_state<D>(WL, Wo, P.gamma, WR);
+#pragma unroll
+            for (int a = 0; a < D; ++a)
+#pragma unroll
+                for (int v = 0; v < nv; ++v) GRl[a][v] = 0.0;
+        }
+#pragma unroll
+        for (int v = 0; v < nv; ++v) Wc[v] = 0.0;
+        ok = half_side<D>(WL, P, 1.0, Wc, nullptr) && half_side<D>(WR, P, -1.0, Wc, nullptr);
+#pragma unroll
+        for (int a = 0; a < D; ++a)
+#pragma unroll
+            for (int v = 0; v < nv; ++v) Gc[a][v] = 0.5 * (GLl[a][v] + GRl[a][v]);
+    } else {
+        // no-slip isothermal wall: (p_L / T_w, 0, p_L), interior gradient
+        Prim<D> q;
+        q.from(WL, P.gamma);
+#pragma unroll
+        for (int v = 0; v < nv; ++v) Wc[v] = 0.0;
+        Wc[0] = q.p / P.T_wall;
+        Wc[nv - 1] = q.p / (P.gamma - 1.0);
+#pragma unroll
+        for (int a = 0; a < D; ++a)
+#pragma unroll
+            for (int v = 0; v < nv; ++v) Gc[a][v] = GLl[a][v];
+    }
+    double F0[nv], Ft[nv], Wt[nv];
+    if (ok) ok = gks_flux<D>(Wc, Gc, P, F0, Ft, Wt);
+    if (!ok) {
+        atomicOr(d.flag + cs, 1);
+#pragma unroll
+        for (int v = 0; v < nv; ++v) F0[v] = Ft[v] = Wt[v] = 0.0;
+    }
+    if (R < 0 && bc == 2) {
+        F0[0] = 0.0;
+        Ft[0] = 0.0;
+#pragma unroll
+        for (int v = 0; v < nv; ++v) Wt[v] = 0.0;
+    }
+    double o[nv];
+    fr.to_global(F0, o);
+#pragma unroll
+    for (int v = 0; v < nv; ++v) d.gF0[v * d.NG + g] = wJ * o[v];
+    fr.to_global(Ft, o);
+#pragma unroll
+    for (int v = 0; v < nv; ++v) d.gFt[v * d.NG + g] = wJ * o[v];
+    fr.to_global(Wc, o);
+#pragma unroll
+    for (int v = 0; v < nv; ++v) d.gWc[v * d.NG + g] = wJ * o[v];
+    fr.to_global(Wt, o);
+#pragma unroll
+    for (int v = 0; v < nv; ++v) d.gWt[v * d.NG + g] = wJ * o[v];
+}
+
+// ---------------------------------------------------------------------
+// Per-cell gather of the face Gauss-point results and the stage update.
+// ---------------------------------------------------------------------
+enum { MODE_STAGE0 = 0, MODE_STAGE1 = 1, MODE_R1 = 2 };
+
+template <int D> __global__ __launch_bounds__(kBlock) void k_cell(Dev d, int mode) {
+    using T = Dim<D>;
+    constexpr int nv = T::nv;
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= d.NC) return;
+    const int NC = d.NC, NG = d.NG;
+    const int cs = d.cell_case[i];
+    const DevParams &P = d.prm[cs];
+    if (!P.active) return;
+    double F0s[nv], Fts[nv], G0s[D][nv], Gts[D][nv];
+#pragma unroll
+    for (int v = 0; v < nv; ++v) {
+        F0s[v] = Fts[v] = 0.0;
+#pragma unroll
+        for (int a = 0; a < D; ++a) G0s[a][v] = Gts[a][v] = 0.0;
+    }
+#pragma unroll 1
+    for (int s = 0; s < T::ns; ++s) {
+        const int code = d.slot_face[s * NC + i];
+        if (code == 0) break;
+        const int f = (code > 0 ? code : -code) - 1;
+        const double sg = code > 0 ? 1.0 : -1.0;
+        const bool want_g = mode != MODE_R1;
+        for (int g = d.gp_off[f]; g < d.gp_off[f + 1]; ++g) {
+            double n[D];
+            if (want_g) {
+#pragma unroll
+                for (int a = 0; a < D; ++a) n[a] = d.gn[a * NG + g];
+            }
+#pragma unroll
+            for (int v = 0; v < nv; ++v) {
+                F0s[v] += sg * d.gF0[v * NG + g];
+                Fts[v] += sg * d.gFt[v * NG + g];
+                if (want_g) {
+                    const double wc = sg * d.gWc[v * NG + g], wt = sg * d.gWt[v * NG + g];
+#pragma unroll
+                    for (int a = 0; a < D; ++a) {
+                        G0s[a][v] += wc * n[a];
+                        Gts[a][v] += wt * n[a];
+                    }
+                }
+            }
+        }
+    }
+    const double dt = d.dt[cs];
+    if (mode == MODE_R1) {
+#pragma unroll
+        for (int v = 0; v < nv; ++v) d.R1[v * NC + i] = -(F0s[v] + 0.5 * dt * Fts[v]);
+        return;
+    }
+    const double V = d.vol[i];
+#pragma unroll
+    for (int v = 0; v < nv; ++v) {
+        const double L = -F0s[v] / V, Lt = -Fts[v] / V;
+        if (mode == MODE_STAGE0) {
+            const double w = d.W[v * NC + i];
+            d.Wn[v * NC + i] = w;
+            d.L0[v * NC + i] = L;
+            d.Lt0[v * NC + i] = Lt;
+            d.W[v * NC + i] = P.scheme == 0 ? w + 0.5 * dt * L + 0.125 * dt * dt * Lt : w + dt * L + 0.5 * dt * dt * Lt;
+        } else {
+            d.W[v * NC + i] = d.Wn[v * NC + i] + dt * d.L0[v * NC + i] + dt * dt / 6.0 * (d.Lt0[v * NC + i] + 2.0 * Lt);
+        }
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            const int k = (a * nv + v) * NC + i;
+            const double G = G0s[a][v] / V, Gt = Gts[a][v] / V;
+            if (mode == MODE_STAGE0) {
+                d.G0[k] = G;
+                d.dW[k] = P.scheme == 0 ? G + 0.5 * dt * Gt : G + dt * Gt;
+            } else {
+                d.dW[k] = d.G0[k] + dt * Gt;
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------
+// Low level: first-order KFVS face flux, spectral radius, cell setup,
+// multicolour point relaxation, prolongation and the residual norm.
+// ---------------------------------------------------------------------
+template <int D> __device__ __forceinline__ void load_state(const double *U, const double *dU, int i, int NC, double *out) {
+    constexpr int nv = D + 2;
+#pragma unroll
+    for (int v = 0; v < nv; ++v) out[v] = dU ? U[v * NC + i] + dU[v * NC + i] : U[v * NC + i];
+}
+
+template <int D> __device__ __forceinline__ double side_radius(const double *U, const double *n, double Sf, double V,
+                                                               const DevParams &P) {
+    constexpr int nv = D + 2;
+    const double rho = U[0];
+    double un = 0, ke = 0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        const double u = U[1 + a] / rho;
+        un += u * n[a];
+        ke += u * u;
+    }
+    const double p = (P.gamma - 1.0) * (U[nv - 1] - 0.5 * rho * ke);
+    return fabs(un) + sqrt(P.gamma * p / rho) + 2.0 * P.mu / rho * Sf / V;
+}
+
+// Flow[v][f] = S_f F_kfvs(U_L, U_R; n_f); lam[f] = larger side radius.
+// U_eff = U (+ dU when dU != nullptr).
+template <int D> __global__ __launch_bounds__(kBlock) void k_low_face(Dev d, const double *U, const double *dU) {
+    constexpr int nv = D + 2;
+    const int f = blockIdx.x * kBlock + threadIdx.x;
+    if (f >= d.NF) return;
+    const int cs = d.fcase[f];
+    const DevParams &P = d.prm[cs];
+    if (!P.active) return;
+    const int L = d.fL[f], R = d.fR[f];
+    const double Sf = d.S[f], iS = 1.0 / Sf;
+    double n[D];
+#pragma unroll
+    for (int a = 0; a < D; ++a) n[a] = d.avec[a * d.NF + f] * iS;
+    Frame<D> fr;
+    fr.build(n);
+    double UL[nv], Ul[nv], Ur[nv];
+    load_state<D>(U, dU, L, d.NC, UL);
+    fr.to_local(UL, Ul);
+    double lam = side_radius<D>(UL, n, Sf, d.vol[L], P);
+    if (R >= 0) {
+        double UR[nv];
+        load_state<D>(U, dU, R, d.NC, UR);
+        fr.to_local(UR, Ur);
+        lam = fmax(lam, side_radius<D>(UR, n, Sf, d.vol[R], P));
+    } else {
+        const int bc = d.fbc[f];
+#pragma unroll
+        for (int v = 0; v < nv; ++v) Ur[v] = Ul[v];
+        if (bc == 1) {
+            Ur[1] = -Ul[1];
+        } else if (bc == 2) {
+#pragma unroll
+            for (int a = 0; a < D; ++a) Ur[1 + a] = -Ul[1 + a];
+        } else {
+            double Wo_g[nv], Wo[nv];
+#pragma unroll
+            for (int v = 0; v < nv; ++v) Wo_g[v] = P.W_inf[v];
+            fr.to_local(Wo_g, Wo);
+            farfield_state<D>(Ul, Wo, P.gamma, Ur);
+        }
+    }
+    double Fl[nv], F[nv];
+#pragma unroll
+    for (int v = 0; v < nv; ++v) Fl[v] = 0.0;
+    const bool ok = half_side<D>(Ul, P, 1.0, nullptr, Fl) && half_side<D>(Ur, P, -1.0, nullptr, Fl);
+    if (!ok) atomicOr(d.flag + cs, 1);
+    fr.to_global(Fl, F);
+#pragma unroll
+    for (int v = 0; v < nv; ++v) d.Flow[v * d.NF + f] = ok ? Sf * F[v] : 0.0;
+    d.lam[f] = lam;
+}
+
+enum { LOW_FORCE = 0, LOW_STEP_FIRST = 1, LOW_STEP = 2, LOW_R0_OUT = 3 };
+
+template <int D> __global__ __launch_bounds__(kBlock) void k_low_cell(Dev d, int mode, double *out) {
+    using T = Dim<D>;
+    constexpr int nv = T::nv;
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= d.NC) return;
+    const int NC = d.NC;
+    const DevParams &P = d.prm[d.cell_case[i]];
+    if (!P.active) return;
+    double R0[nv], lS = 0.0;
+#pragma unroll
+    for (int v = 0; v < nv; ++v) R0[v] = 0.0;
+#pragma unroll 1
+    for (int s = 0; s < T::ns; ++s) {
+        const int code = d.slot_face[s * NC + i];
+        if (code == 0) break;
+        const int f = (code > 0 ? code : -code) - 1;
+        const double sg = code > 0 ? 1.0 : -1.0;
+#pragma unroll
+        for (int v = 0; v < nv; ++v) R0[v] -= sg * d.Flow[v * d.NF + f];
+        lS += d.lam[f] * d.S[f];
+    }
+    if (mode == LOW_R0_OUT) {
+#pragma unroll
+        for (int v = 0; v < nv; ++v) out[v * NC + i] = R0[v];
+        return;
+    }
+    if (mode == LOW_FORCE) {
+#pragma unroll
+        for (int v = 0; v < nv; ++v) {
+            d.Sf[v * NC + i] = d.R1[v * NC + i] - R0[v];
+            d.U[v * NC + i] = d.W[v * NC + i];
+            d.dU[v * NC + i] = 0.0;
+        }
+        return;
+    }
+    double Ui[nv];
+#pragma unroll
+    for (int v = 0; v < nv; ++v) {
+        Ui[v] = mode == LOW_STEP ? d.U[v * NC + i] + d.dU[v * NC + i] : d.U[v * NC + i];
+        d.U[v * NC + i] = Ui[v];
+        d.RHS[v * NC + i] = R0[v] + d.Sf[v * NC + i];
+        d.dU[v * NC + i] = 0.0;
+    }
+    const double dti = cell_dt<D>(d.U, i, NC, d.h[i], P.cfl_low, P);
+    d.D[i] = d.vol[i] / dti + 0.5 * lS;
+}
+
+// one colour class: blocks listed in (start, count) tables
+template <int D> __global__ __launch_bounds__(kBlock) void k_sweep(Dev d, const int32_t *blk_start,
+                                                                   const int32_t *blk_count) {
+    using T = Dim<D>;
+    constexpr int nv = T::nv;
+    const int b = blockIdx.x;
+    if ((int)threadIdx.x >= blk_count[b]) return;
+    const int i = blk_start[b] + threadIdx.x;
+    const int NC = d.NC;
+    const DevParams &P = d.prm[d.cell_case[i]];
+    if (!P.active) return;
+    double acc[nv];
+#pragma unroll
+    for (int v = 0; v < nv; ++v) acc[v] = d.RHS[v * NC + i];
+#pragma unroll 1
+    for (int s = 0; s < T::ns; ++s) {
+        const int code = d.slot_face[s * NC + i];
+        if (code == 0) break;
+        const int nb = d.slot_nb[s * NC + i];
+        if (nb < 0) continue;
+        const int f = (code > 0 ? code : -code) - 1;
+        const double sg = code > 0 ? 1.0 : -1.0;
+        const double Sf = d.S[f], iS = 1.0 / Sf, lam = d.lam[f];
+        double n[D], Um[nv], Up[nv], Fa[nv], Fb[nv];
+#pragma unroll
+        for (int a = 0; a < D; ++a) n[a] = sg * d.avec[a * d.NF + f] * iS;
+#pragma unroll
+        for (int v = 0; v < nv; ++v) {
+            Um[v] = d.U[v * NC + nb];
+            Up[v] = Um[v] + d.dU[v * NC + nb];
+        }
+        euler_flux<D>(Up, n, P.gamma, Fa);
+        euler_flux<D>(Um, n, P.gamma, Fb);
+#pragma unroll
+        for (int v = 0; v < nv; ++v) acc[v] -= Sf * (0.5 * (Fa[v] - lam * Up[v]) - 0.5 * (Fb[v] - lam * Um[v]));
+    }
+    const double iD = d.D[i];
+#pragma unroll
+    for (int v = 0; v < nv; ++v) d.dU[v * NC + i] = acc[v] / iD;
+}
+
+// W += (U + dU) - W_p0 (W_p0 = W); partial sums of |rho - rho^n| and rho^n.
+// prolong = 0: sums only (explicit cycle).
+template <int D> __global__ __launch_bounds__(kBlock) void k_prolong_res(Dev d, int prolong) {
+    constexpr int nv = D + 2;
+    __shared__ double sh[kBlock];
+    const int b = blockIdx.x;
+    const int cs = d.rb_case[b];
+    const DevParams &P = d.prm[cs];
+    const int n = d.rb_count[b];
+    const int NC = d.NC;
+    double s0 = 0, s1 = 0;
+    for (int k = threadIdx.x; k < n; k += kBlock) {
+        const int i = d.rb_start[b] + k;
+        if (prolong && P.active) {
+#pragma unroll
+            for (int v = 0; v < nv; ++v) {
+                const double u6 = d.U[v * NC + i] + d.dU[v * NC + i];
+                const double w = d.W[v * NC + i];
+                d.W[v * NC + i] = w + (u6 - w);
+            }
+        }
+        s0 += fabs(d.W[i] - d.Wn[i]);
+        s1 += d.Wn[i];
+    }
+    s0 = block_reduce_sum(s0, sh);
+    s1 = block_reduce_sum(s1, sh);
+    if (threadIdx.x == 0) {
+        d.part0[b] = s0;
+        d.part1[b] = s1;
+    }
+}
+
+__global__ void k_res_final(Dev d, int n_case) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n_case) return;
+    if (!d.prm[c].active) return;
+    double a = 0, b = 0;
+    for (int k = d.case_rb_off[c]; k < d.case_rb_off[c + 1]; ++k) {
+        a += d.part0[k];
+        b += d.part1[k];
+    }
+    d.res[c] = a / b;
+}
+
+}  // namespace cgks

@@ -1,0 +1,520 @@
+// Host preprocessing of a face-based hybrid mesh: face Gauss points, cell
+// geometry, compact-reconstruction operators, multicolour classes and the
+// library cell order.  Runs once per mesh on the host (FP64, long double for
+// the small dense factorisations).
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "cgks_internal.h"
+
+namespace cgks {
+namespace {
+
+struct V3 {
+    double x[3] = {0, 0, 0};
+};
+
+inline void sub(const double *a, const double *b, double *c, int d) {
+    for (int k = 0; k < d; ++k) c[k] = a[k] - b[k];
+}
+inline void cross(const double *a, const double *b, double *c) {
+    c[0] = a[1] * b[2] - a[2] * b[1];
+    c[1] = a[2] * b[0] - a[0] * b[2];
+    c[2] = a[0] * b[1] - a[1] * b[0];
+}
+inline double norm(const double *a, int d) {
+    double s = 0;
+    for (int k = 0; k < d; ++k) s += a[k] * a[k];
+    return std::sqrt(s);
+}
+
+// Vertex k of face f in the frame of the cell on `side` (neighbour frame =
+// owner frame minus the periodic shift).
+void face_pt(const HostMesh &m, int64_t f, int k, int side, double *x) {
+    const int64_t v = m.fvert[m.fptr[f] + k];
+    for (int a = 0; a < m.dim; ++a) {
+        x[a] = m.xyz[v * m.dim + a];
+        if (side) x[a] -= m.shift[f * m.dim + a];
+    }
+}
+
+// Point and unnormalised normal of the bilinear map of a quad at (s, t).
+void quad_map(const double P[4][3], double s, double t, double *x, double *N) {
+    double xs[3], xt[3];
+    for (int a = 0; a < 3; ++a) {
+        x[a] = P[0][a] + s * (P[1][a] - P[0][a]) + t * (P[3][a] - P[0][a]) +
+               s * t * (P[0][a] - P[1][a] + P[2][a] - P[3][a]);
+        xs[a] = (P[1][a] - P[0][a]) + t * (P[0][a] - P[1][a] + P[2][a] - P[3][a]);
+        xt[a] = (P[3][a] - P[0][a]) + s * (P[0][a] - P[1][a] + P[2][a] - P[3][a]);
+    }
+    cross(xs, xt, N);
+}
+
+// Face quadrature used by the scheme (Sec. 2.1): 2-point Gauss-Legendre on
+// edges, the 3-point interior rule on triangles, 2x2 Gauss-Legendre on the
+// bilinear quad with the Jacobian and normal of each point.
+cgks_status face_quadrature(HostMesh &m) {
+    const int d = m.dim;
+    const double r3 = 1.0 / std::sqrt(3.0);
+    const double gl2[2] = {0.5 * (1.0 - r3), 0.5 * (1.0 + r3)};
+    m.ngp.assign(m.n_face, 0);
+    m.gp_off.assign(m.n_face + 1, 0);
+    for (int64_t f = 0; f < m.n_face; ++f) {
+        const int nfv = int(m.fptr[f + 1] - m.fptr[f]);
+        int n = 0;
+        if (d == 2 && nfv == 2) n = 2;
+        else if (d == 3 && nfv == 3) n = 3;
+        else if (d == 3 && nfv == 4) n = 4;
+        else return CGKS_EMESH;
+        m.ngp[f] = n;
+        m.gp_off[f + 1] = m.gp_off[f] + n;
+    }
+    m.n_gp = m.gp_off[m.n_face];
+    m.gx.assign(m.n_gp * d, 0.0);
+    m.gn.assign(m.n_gp * d, 0.0);
+    m.gw.assign(m.n_gp, 0.0);
+    m.avec.assign(m.n_face * d, 0.0);
+    m.S.assign(m.n_face, 0.0);
+    for (int64_t f = 0; f < m.n_face; ++f) {
+        double P[4][3] = {};
+        const int nfv = int(m.fptr[f + 1] - m.fptr[f]);
+        for (int k = 0; k < nfv; ++k) face_pt(m, f, k, 0, P[k]);
+        const int64_t g0 = m.gp_off[f];
+        if (d == 2) {
+            const double e[2] = {P[1][0] - P[0][0], P[1][1] - P[0][1]};
+            const double len = std::hypot(e[0], e[1]);
+            if (!(len > 0)) return CGKS_EMESH;
+            for (int g = 0; g < 2; ++g) {
+                m.gx[(g0 + g) * 2 + 0] = P[0][0] + gl2[g] * e[0];
+                m.gx[(g0 + g) * 2 + 1] = P[0][1] + gl2[g] * e[1];
+                m.gn[(g0 + g) * 2 + 0] = e[1] / len;
+                m.gn[(g0 + g) * 2 + 1] = -e[0] / len;
+                m.gw[g0 + g] = 0.5 * len;
+            }
+        } else if (nfv == 3) {
+            double e1[3], e2[3], N[3];
+            sub(P[1], P[0], e1, 3);
+            sub(P[2], P[0], e2, 3);
+            cross(e1, e2, N);
+            const double twoA = norm(N, 3);
+            if (!(twoA > 0)) return CGKS_EMESH;
+            for (int g = 0; g < 3; ++g) {
+                // barycentric weight 2/3 on vertex g, 1/6 on the other two
+                for (int a = 0; a < 3; ++a) {
+                    const double s = P[0][a] + P[1][a] + P[2][a];
+                    m.gx[(g0 + g) * 3 + a] = (s + 3.0 * P[g][a]) / 6.0;
+                    m.gn[(g0 + g) * 3 + a] = N[a] / twoA;
+                }
+                m.gw[g0 + g] = twoA / 6.0;
+            }
+        } else {
+            int g = 0;
+            for (int jt = 0; jt < 2; ++jt)
+                for (int js = 0; js < 2; ++js, ++g) {
+                    double x[3], N[3];
+                    quad_map(P, gl2[js], gl2[jt], x, N);
+                    const double J = norm(N, 3);
+                    if (!(J > 0)) return CGKS_EMESH;
+                    for (int a = 0; a < 3; ++a) {
+                        m.gx[(g0 + g) * 3 + a] = x[a];
+                        m.gn[(g0 + g) * 3 + a] = N[a] / J;
+                    }
+                    m.gw[g0 + g] = 0.25 * J;
+                }
+        }
+        double s2 = 0;
+        for (int a = 0; a < d; ++a) {
+            double acc = 0;
+            for (int g = 0; g < m.ngp[f]; ++g) acc += m.gw[g0 + g] * m.gn[(g0 + g) * d + a];
+            m.avec[f * d + a] = acc;
+            s2 += acc * acc;
+        }
+        m.S[f] = std::sqrt(s2);
+    }
+    return CGKS_OK;
+}
+
+// Moments of a polyhedral / polygonal cell by the divergence theorem:
+//   |V| = 1/d  oint y.n,  int y_a = oint y_a^2/2 n_a,
+//   int y_a^2 = oint y_a^3/3 n_a,  int y_a y_b = oint y_a^2 y_b / 2 n_a,
+// with y relative to a vertex of the cell.  The face integrals of these
+// cubics are exact with Simpson's rule on edges, a collapsed 3x3
+// Gauss-Legendre rule on triangles and 4x4 Gauss-Legendre on bilinear quads.
+struct Moments {
+    double V = 0, M1[3] = {0, 0, 0}, M2[3][3] = {{0}};
+    void add(int d, const double *y, const double *nw) {
+        for (int a = 0; a < d; ++a) {
+            V += y[a] * nw[a] / d;
+            M1[a] += 0.5 * y[a] * y[a] * nw[a];
+            for (int b = 0; b < d; ++b)
+                M2[a][b] += (a == b ? y[a] * y[a] * y[a] / 3.0 : 0.5 * y[a] * y[a] * y[b]) * nw[a];
+        }
+    }
+};
+
+cgks_status cell_geometry(HostMesh &m) {
+    const int d = m.dim;
+    const double q3x[3] = {0.5 - 0.5 * std::sqrt(0.6), 0.5, 0.5 + 0.5 * std::sqrt(0.6)};
+    const double q3w[3] = {5.0 / 18.0, 8.0 / 18.0, 5.0 / 18.0};
+    const double a4 = std::sqrt(3.0 / 7.0 - 2.0 / 7.0 * std::sqrt(1.2));
+    const double b4 = std::sqrt(3.0 / 7.0 + 2.0 / 7.0 * std::sqrt(1.2));
+    const double wa = (18.0 + std::sqrt(30.0)) / 36.0, wb = (18.0 - std::sqrt(30.0)) / 36.0;
+    const double q4x[4] = {0.5 * (1 - b4), 0.5 * (1 - a4), 0.5 * (1 + a4), 0.5 * (1 + b4)};
+    const double q4w[4] = {0.5 * wb, 0.5 * wa, 0.5 * wa, 0.5 * wb};
+    m.vol.assign(m.n_cell, 0.0);
+    m.ctr.assign(m.n_cell * d, 0.0);
+    m.sec.assign(m.n_cell * m.nq, 0.0);
+    m.h.assign(m.n_cell, 0.0);
+    for (int64_t i = 0; i < m.n_cell; ++i) {
+        double ref[3] = {0, 0, 0};
+        {
+            const int64_t f = m.cf_face[m.cf_ptr[i]];
+            face_pt(m, f, 0, m.cf_side[m.cf_ptr[i]], ref);
+        }
+        Moments mo;
+        double sumS = 0;
+        for (int64_t q = m.cf_ptr[i]; q < m.cf_ptr[i + 1]; ++q) {
+            const int64_t f = m.cf_face[q];
+            const int side = m.cf_side[q];
+            const double sg = side ? -1.0 : 1.0;
+            const int nfv = int(m.fptr[f + 1] - m.fptr[f]);
+            double P[4][3] = {};
+            for (int k = 0; k < nfv; ++k) {
+                face_pt(m, f, k, side, P[k]);
+                for (int a = 0; a < d; ++a) P[k][a] -= ref[a];
+            }
+            sumS += m.S[f];
+            if (d == 2) {
+                const double n[2] = {sg * (P[1][1] - P[0][1]), -sg * (P[1][0] - P[0][0])};  // |n| = length
+                const double sw[3] = {1.0 / 6.0, 4.0 / 6.0, 1.0 / 6.0};
+                for (int k = 0; k < 3; ++k) {
+                    const double t = 0.5 * k;
+                    const double y[2] = {P[0][0] + t * (P[1][0] - P[0][0]), P[0][1] + t * (P[1][1] - P[0][1])};
+                    const double nw[2] = {n[0] * sw[k], n[1] * sw[k]};
+                    mo.add(2, y, nw);
+                }
+            } else if (nfv == 3) {
+                double e1[3], e2[3], N[3];
+                sub(P[1], P[0], e1, 3);
+                sub(P[2], P[0], e2, 3);
+                cross(e1, e2, N);  // |N| = 2A
+                for (int js = 0; js < 3; ++js)
+                    for (int jt = 0; jt < 3; ++jt) {
+                        const double s = q3x[js], t = q3x[jt];
+                        const double a = s, b = t * (1.0 - s);
+                        const double w = q3w[js] * q3w[jt] * (1.0 - s);
+                        double y[3], nw[3];
+                        for (int c = 0; c < 3; ++c) {
+                            y[c] = P[0][c] + a * e1[c] + b * e2[c];
+                            nw[c] = sg * N[c] * w;
+                        }
+                        mo.add(3, y, nw);
+                    }
+            } else {
+                for (int js = 0; js < 4; ++js)
+                    for (int jt = 0; jt < 4; ++jt) {
+                        double y[3], N[3], nw[3];
+                        quad_map(P, q4x[js], q4x[jt], y, N);
+                        for (int c = 0; c < 3; ++c) nw[c] = sg * N[c] * q4w[js] * q4w[jt];
+                        mo.add(3, y, nw);
+                    }
+            }
+        }
+        if (!(mo.V > 0)) return CGKS_EMESH;
+        m.vol[i] = mo.V;
+        double yc[3];
+        for (int a = 0; a < d; ++a) {
+            yc[a] = mo.M1[a] / mo.V;
+            m.ctr[i * d + a] = ref[a] + yc[a];
+        }
+        int q = 0;
+        for (int a = 0; a < d; ++a)
+            for (int b = a; b < d; ++b) m.sec[i * m.nq + q++] = mo.M2[a][b] / mo.V - yc[a] * yc[b];
+        m.h[i] = 2.0 * d * mo.V / sumS;
+    }
+    return CGKS_OK;
+}
+
+// index of (a, b), a <= b, in the packed second-moment arrays
+inline int qidx(int d, int a, int b) {
+    if (a > b) std::swap(a, b);
+    if (d == 2) return a + b;
+    return a == 0 ? b : (a == 1 ? 2 + b : 5);
+}
+// quadratic basis order: 2-D (00, 01, 11); 3-D (00, 11, 22, 01, 02, 12)
+const int kQa[2][6] = {{0, 0, 1, 0, 0, 0}, {0, 1, 2, 0, 0, 1}};
+const int kQb[2][6] = {{0, 1, 1, 0, 0, 0}, {0, 1, 2, 1, 2, 2}};
+
+// Basis averages <phi_k> over a cell with centroid c and central second
+// moments s (packed), in the scaled frame of cell i (centre xc, size h).
+void basis_avg(int d, const double *c, const double *s, const double *xc, double h, double *avg) {
+    double dx[3];
+    for (int a = 0; a < d; ++a) {
+        dx[a] = c[a] - xc[a];
+        avg[a] = dx[a] / h;
+    }
+    for (int q = 0; q < nquad_of(d); ++q) {
+        const int a = kQa[d - 2][q], b = kQb[d - 2][q];
+        avg[d + q] = (s[qidx(d, a, b)] + dx[a] * dx[b]) / (h * h);
+    }
+}
+
+// Ghost basis averages of boundary face f for its owner: the owner mirrored
+// in the plane through the face centroid normal to the face.
+void ghost_avg(const HostMesh &m, int64_t f, double *avg) {
+    const int d = m.dim;
+    const int64_t i = m.owner[f];
+    double n[3] = {0, 0, 0}, xf[3] = {0, 0, 0}, sw = 0;
+    for (int a = 0; a < d; ++a) n[a] = m.avec[f * d + a] / m.S[f];
+    for (int64_t g = m.gp_off[f]; g < m.gp_off[f + 1]; ++g) {
+        sw += m.gw[g];
+        for (int a = 0; a < d; ++a) xf[a] += m.gw[g] * m.gx[g * d + a];
+    }
+    double dist = 0;
+    for (int a = 0; a < d; ++a) dist += (xf[a] / sw - m.ctr[i * d + a]) * n[a];
+    double cg[3], S[3][3], RS[3][3], sg[6];
+    for (int a = 0; a < d; ++a) cg[a] = m.ctr[i * d + a] + 2.0 * dist * n[a];
+    for (int a = 0; a < d; ++a)
+        for (int b = 0; b < d; ++b) S[a][b] = m.sec[i * m.nq + qidx(d, a, b)];
+    // R S R with R = I - 2 n n^T
+    for (int a = 0; a < d; ++a)
+        for (int b = 0; b < d; ++b) {
+            double acc = 0;
+            for (int k = 0; k < d; ++k) acc += ((a == k) - 2.0 * n[a] * n[k]) * S[k][b];
+            RS[a][b] = acc;
+        }
+    for (int a = 0; a < d; ++a)
+        for (int b = a; b < d; ++b) {
+            double acc = 0;
+            for (int k = 0; k < d; ++k) acc += RS[a][k] * ((k == b) - 2.0 * n[k] * n[b]);
+            sg[qidx(d, a, b)] = acc;
+        }
+    basis_avg(d, cg, sg, m.ctr.data() + i * d, m.h[i], avg);
+}
+
+// Householder QR of A [nr][nc] in long double; returns R's diagonal ratio and
+// leaves R in the upper triangle.
+long double qr_ratio(int nr, int nc, std::vector<long double> &A) {
+    for (int k = 0; k < nc; ++k) {
+        long double nrm = 0;
+        for (int r = k; r < nr; ++r) nrm += A[r * nc + k] * A[r * nc + k];
+        nrm = std::sqrt(nrm);
+        if (nrm == 0) continue;
+        const long double alpha = A[k * nc + k] > 0 ? -nrm : nrm;
+        std::vector<long double> v(nr, 0);
+        for (int r = k; r < nr; ++r) v[r] = A[r * nc + k];
+        v[k] -= alpha;
+        long double vv = 0;
+        for (int r = k; r < nr; ++r) vv += v[r] * v[r];
+        if (vv == 0) continue;
+        for (int j = k; j < nc; ++j) {
+            long double s = 0;
+            for (int r = k; r < nr; ++r) s += v[r] * A[r * nc + j];
+            s = 2 * s / vv;
+            for (int r = k; r < nr; ++r) A[r * nc + j] -= s * v[r];
+        }
+    }
+    long double mn = INFINITY, mx = 0;
+    for (int k = 0; k < nc; ++k) {
+        const long double r = std::fabs(A[k * nc + k]);
+        mn = std::min(mn, r);
+        mx = std::max(mx, r);
+    }
+    return mx > 0 ? mn / mx : 0;
+}
+
+// (R^T R)^-1 = R^-1 R^-T from the upper triangle of A [..][nc], into out
+// (an nk x nk block at offset 0)
+void inverse_normal(int nc, const std::vector<long double> &A, int nk, double *out) {
+    std::vector<long double> X(nc * nc, 0);  // X = R^-1 (upper)
+    for (int j = 0; j < nc; ++j) {
+        X[j * nc + j] = 1.0L / A[j * nc + j];
+        for (int i = j - 1; i >= 0; --i) {
+            long double s = 0;
+            for (int k = i + 1; k <= j; ++k) s += A[i * nc + k] * X[k * nc + j];
+            X[i * nc + j] = -s / A[i * nc + i];
+        }
+    }
+    for (int i = 0; i < nk * nk; ++i) out[i] = 0.0;
+    for (int i = 0; i < nc; ++i)
+        for (int j = 0; j < nc; ++j) {
+            long double s = 0;
+            for (int k = std::max(i, j); k < nc; ++k) s += X[i * nc + k] * X[j * nc + k];
+            out[i * nk + j] = double(s);
+        }
+}
+
+// Least-squares rows of cell i (slot order = increasing face index):
+// per face neighbour (or ghost) one average row and d gradient rows, then
+// d own-gradient rows.  Mirrors the device-side row generation.
+void recon_rows(const HostMesh &m, int64_t i, std::vector<long double> &A, int &nr) {
+    const int d = m.dim, nk = m.nk;
+    const double *xc = m.ctr.data() + i * d;
+    const double h = m.h[i];
+    double own[9];
+    basis_avg(d, xc, m.sec.data() + i * m.nq, xc, h, own);
+    nr = 0;
+    A.clear();
+    auto push_block = [&](const double *avg) {
+        A.resize((nr + 1 + d) * nk);
+        for (int k = 0; k < nk; ++k) A[nr * nk + k] = avg[k] - own[k];
+        ++nr;
+        for (int a = 0; a < d; ++a, ++nr) {
+            for (int k = 0; k < nk; ++k) A[nr * nk + k] = 0;
+            A[nr * nk + a] = 1.0;
+            for (int q = 0; q < nquad_of(d); ++q) {
+                const int p = kQa[d - 2][q], r = kQb[d - 2][q];
+                A[nr * nk + d + q] = (p == a ? avg[r] : 0.0) + (r == a ? avg[p] : 0.0);
+            }
+        }
+    };
+    for (int64_t q = m.cf_ptr[i]; q < m.cf_ptr[i + 1]; ++q) {
+        const int64_t f = m.cf_face[q];
+        double avg[9];
+        if (m.neigh[f] >= 0) {
+            const int side = m.cf_side[q];
+            const int64_t nb = side ? m.owner[f] : m.neigh[f];
+            double c[3];
+            for (int a = 0; a < d; ++a)
+                c[a] = m.ctr[nb * d + a] + (side ? -m.shift[f * d + a] : m.shift[f * d + a]);
+            basis_avg(d, c, m.sec.data() + nb * m.nq, xc, h, avg);
+        } else {
+            for (int k = 0; k < nk; ++k) avg[k] = m.gavg[f * nk + k];
+        }
+        push_block(avg);
+    }
+    A.resize((nr + d) * nk);
+    for (int a = 0; a < d; ++a, ++nr) {
+        for (int k = 0; k < nk; ++k) A[nr * nk + k] = 0;
+        A[nr * nk + a] = 1.0;
+    }
+}
+
+cgks_status recon_setup(HostMesh &m) {
+    const int nk = m.nk, d = m.dim;
+    m.gavg.assign(m.n_face * nk, 0.0);
+    for (int64_t f = 0; f < m.n_face; ++f)
+        if (m.neigh[f] < 0) ghost_avg(m, f, m.gavg.data() + f * nk);
+    m.minv.assign(m.n_cell * nk * nk, 0.0);
+    m.linear.assign(m.n_cell, 0);
+    std::vector<long double> A;
+    for (int64_t i = 0; i < m.n_cell; ++i) {
+        int nr = 0;
+        recon_rows(m, i, A, nr);
+        std::vector<long double> Q(A);
+        if (nr >= nk && qr_ratio(nr, nk, Q) > kRankTol) {
+            inverse_normal(nk, Q, nk, m.minv.data() + i * nk * nk);
+            continue;
+        }
+        // linear fallback: the same rows restricted to the linear columns
+        std::vector<long double> L(nr * d);
+        for (int r = 0; r < nr; ++r)
+            for (int a = 0; a < d; ++a) L[r * d + a] = A[r * nk + a];
+        if (!(qr_ratio(nr, d, L) > kRankTol)) return CGKS_EMESH;
+        inverse_normal(d, L, nk, m.minv.data() + i * nk * nk);
+        m.linear[i] = 1;
+    }
+    return CGKS_OK;
+}
+
+void colour_and_order(HostMesh &m) {
+    m.colour.assign(m.n_cell, -1);
+    int ncol = 0;
+    std::vector<char> used;
+    for (int64_t i = 0; i < m.n_cell; ++i) {
+        used.assign(ncol + 1, 0);
+        for (int64_t q = m.cf_ptr[i]; q < m.cf_ptr[i + 1]; ++q) {
+            const int64_t f = m.cf_face[q];
+            const int64_t nb = m.cf_side[q] ? m.owner[f] : m.neigh[f];
+            if (nb >= 0 && m.colour[nb] >= 0) used[m.colour[nb]] = 1;
+        }
+        int c = 0;
+        while (used[c]) ++c;
+        m.colour[i] = c;
+        ncol = std::max(ncol, c + 1);
+    }
+    m.n_colour = ncol;
+    m.colour_count.assign(ncol, 0);
+    for (int64_t i = 0; i < m.n_cell; ++i) m.colour_count[m.colour[i]]++;
+    std::vector<int64_t> start(ncol + 1, 0);
+    for (int c = 0; c < ncol; ++c) start[c + 1] = start[c] + m.colour_count[c];
+    m.lib2caller.assign(m.n_cell, 0);
+    m.caller2lib.assign(m.n_cell, 0);
+    for (int64_t i = 0; i < m.n_cell; ++i) {
+        const int64_t l = start[m.colour[i]]++;
+        m.lib2caller[l] = i;
+        m.caller2lib[i] = l;
+    }
+}
+
+}  // namespace
+
+cgks_status build_host_mesh(const cgks_mesh_desc *ds, HostMesh &m) {
+    if (!ds || (ds->dim != 2 && ds->dim != 3) || ds->n_cell <= 0 || ds->n_face <= 0 || ds->n_vert <= 0 ||
+        !ds->xyz || !ds->face_vert_ptr || !ds->face_vert || !ds->face_owner || !ds->face_neigh || !ds->face_bc)
+        return CGKS_EINVAL;
+    const int d = ds->dim;
+    m.dim = d;
+    m.nv = d + 2;
+    m.nk = ncoef_of(d);
+    m.nq = nquad_of(d);
+    m.n_cell = ds->n_cell;
+    m.n_face = ds->n_face;
+    m.xyz.assign(ds->xyz, ds->xyz + ds->n_vert * d);
+    m.fptr.assign(ds->face_vert_ptr, ds->face_vert_ptr + ds->n_face + 1);
+    if (m.fptr[0] != 0) return CGKS_EINVAL;
+    m.fvert.assign(ds->face_vert, ds->face_vert + m.fptr[m.n_face]);
+    m.owner.assign(ds->face_owner, ds->face_owner + m.n_face);
+    m.neigh.assign(ds->face_neigh, ds->face_neigh + m.n_face);
+    m.bc.assign(ds->face_bc, ds->face_bc + m.n_face);
+    m.shift.assign(m.n_face * d, 0.0);
+    if (ds->face_shift) m.shift.assign(ds->face_shift, ds->face_shift + m.n_face * d);
+    for (int64_t v : m.fvert)
+        if (v < 0 || v >= ds->n_vert) return CGKS_EMESH;
+    m.n_bface = 0;
+    for (int64_t f = 0; f < m.n_face; ++f) {
+        if (m.owner[f] < 0 || m.owner[f] >= m.n_cell || m.neigh[f] >= m.n_cell || m.neigh[f] == m.owner[f])
+            return CGKS_EMESH;
+        if (m.neigh[f] < 0) {
+            ++m.n_bface;
+            if (m.bc[f] == CGKS_BC_NOSLIP_ADIABATIC) return CGKS_EUNSUPPORTED;
+            if (m.bc[f] != CGKS_BC_SLIP_WALL && m.bc[f] != CGKS_BC_NOSLIP_ISOTHERMAL && m.bc[f] != CGKS_BC_FARFIELD)
+                return CGKS_EMESH;
+        }
+    }
+    // faces of each cell in increasing face index
+    m.cf_ptr.assign(m.n_cell + 1, 0);
+    for (int64_t f = 0; f < m.n_face; ++f) {
+        m.cf_ptr[m.owner[f] + 1]++;
+        if (m.neigh[f] >= 0) m.cf_ptr[m.neigh[f] + 1]++;
+    }
+    for (int64_t i = 0; i < m.n_cell; ++i) {
+        if (m.cf_ptr[i + 1] < d + 1 || m.cf_ptr[i + 1] > (d == 2 ? 4 : kMaxSlots)) return CGKS_EMESH;
+        m.cf_ptr[i + 1] += m.cf_ptr[i];
+    }
+    m.cf_face.assign(m.cf_ptr[m.n_cell], 0);
+    m.cf_side.assign(m.cf_ptr[m.n_cell], 0);
+    {
+        std::vector<int64_t> fill(m.cf_ptr.begin(), m.cf_ptr.end() - 1);
+        for (int64_t f = 0; f < m.n_face; ++f) {
+            const int64_t o = m.owner[f];
+            m.cf_face[fill[o]] = f;
+            m.cf_side[fill[o]++] = 0;
+            if (m.neigh[f] >= 0) {
+                const int64_t r = m.neigh[f];
+                m.cf_face[fill[r]] = f;
+                m.cf_side[fill[r]++] = 1;
+            }
+        }
+    }
+    cgks_status st = face_quadrature(m);
+    if (st != CGKS_OK) return st;
+    st = cell_geometry(m);
+    if (st != CGKS_OK) return st;
+    colour_and_order(m);
+    return recon_setup(m);
+}
+
+}  // namespace cgks

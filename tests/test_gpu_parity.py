@@ -1,0 +1,176 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Every comparison is element by element on the same seeded inputs.  The bar
+is the relative FP64 tolerance of one cycle: |x_gpu - x_oracle|_max <=
+1e-11 |x_oracle|_max for cell averages and residuals (1e-10 for the
+Gauss-Green gradients, which divide face sums by small cell volumes).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import paper_2109_09965_amd as cg
+import paper_2109_09965_amd.inputs as I
+
+pytestmark = pytest.mark.gpu
+
+TOL_W = 1e-11
+TOL_G = 1e-10
+
+
+def make_case(name):
+    """(mesh, params kwargs, W, dW) of a named parity case."""
+    if name == "cyl2d_slip":
+        m = I.cylinder_mesh(32, 16)
+        Winf = I.free_stream(2, 0.2, 3.0)
+        kw = dict(W_inf=Winf)
+    elif name == "cyl2d_visc":
+        m = I.cylinder_mesh(32, 16, wall=I.BC_NOSLIP_ISOTHERMAL)
+        Winf = I.free_stream(2, 0.15)
+        kw = dict(W_inf=Winf, mu=0.15 / 40, Pr=0.72)
+    elif name == "box2d_per":
+        m = I.box2d_mesh(10, perturb=0.3, seed=2)
+        Winf = I.free_stream(2, 0.4, 30.0)
+        kw = dict(W_inf=Winf, mu=0.01, Pr=0.72)
+    elif name == "box3d_per":
+        m = I.box3d_mesh((3, 3, 5), periodic=True, perturb=0.2, seed=4)
+        Winf = I.free_stream(3, 0.4, 20.0)
+        kw = dict(W_inf=Winf, mu=0.01, Pr=0.72)
+    elif name == "box3d_slip":
+        m = I.box3d_mesh((4, 3, 5), perturb=0.2, seed=6, bc=I.BC_SLIP_WALL)
+        Winf = I.free_stream(3, 0.3, 15.0)
+        kw = dict(W_inf=Winf)
+    elif name == "sphere":
+        m = I.sphere_mesh(8, 16, 8, 3, 2)
+        Winf = I.free_stream(3, 0.25)
+        kw = dict(W_inf=Winf, mu=0.25 / 100, Pr=0.72)
+    else:
+        raise KeyError(name)
+    W, dW = I.smooth_state(m, Winf, seed=11, amp=0.04)
+    return m, kw, W, dW
+
+
+CASES = ["cyl2d_slip", "cyl2d_visc", "box2d_per", "box3d_per", "box3d_slip", "sphere"]
+
+
+class Pair:
+    """Oracle solver and a one-case GPU batch on the same mesh and params."""
+
+    def __init__(self, name, **over):
+        m, kw, W, dW = make_case(name)
+        kw.update(over)
+        self.mesh = m
+        self.W0, self.dW0 = W, dW
+        self.om = oracle.Mesh(m)
+        self.os = oracle.Solver(self.om, oracle.Params(**kw))
+        self.lm = cg.Mesh(m)
+        self.b = cg.Batch([self.lm], [cg.Params(**kw)])
+        self.b.upload(0, W, dW)
+
+    def lib_order(self, X):
+        return np.ascontiguousarray(X[:, self.lm.lib2caller])
+
+
+def rel(a, b):
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+
+
+def check_state(p, W, dW, tag):
+    Wg, dWg = p.b.download(0)
+    e_w, e_g = rel(Wg, W), rel(dWg, dW)
+    print(f"{tag}: W rel err {e_w:.2e}, dW rel err {e_g:.2e}", flush=True)
+    assert e_w <= TOL_W, (tag, e_w)
+    assert e_g <= TOL_G, (tag, e_g)
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_highorder_stages(name):
+    p = Pair(name)
+    W, dW = p.W0.copy(), p.dW0.copy()
+    p.os.stage(0, W, dW)
+    p.b.highorder_stage(0)
+    check_state(p, W, dW, f"{name} stage0")
+    p.os.stage(1, W, dW)
+    p.b.highorder_stage(1)
+    check_state(p, W, dW, f"{name} stage1")
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_residuals(name):
+    p = Pair(name)
+    W, dW = p.W0.copy(), p.dW0.copy()
+    p.os.stage(0, W, dW)
+    p.b.highorder_stage(0)
+    p.b.upload(0, W, dW)          # same state on both sides; dt from stage 0
+    R1 = p.os.residual_high(W, dW)
+    R1g = p.b.to_caller(0, p.b.residual(cg.RESIDUAL_HIGH).cpu().numpy())
+    e1 = rel(R1g, R1)
+    R0 = p.os.residual_low(W)
+    R0g = p.b.to_caller(0, p.b.residual(cg.RESIDUAL_LOW).cpu().numpy())
+    e0 = rel(R0g, R0)
+    print(f"{name}: R1 rel err {e1:.2e}, R0 rel err {e0:.2e}", flush=True)
+    assert e1 <= TOL_W and e0 <= TOL_W
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_lowlevel(name):
+    import torch
+    p = Pair(name)
+    W, dW = p.W0.copy(), p.dW0.copy()
+    p.os.stage(0, W, dW)
+    p.b.highorder_stage(0)
+    p.b.upload(0, W, dW)
+    R1 = p.os.residual_high(W, dW)
+    R1d = torch.from_numpy(p.lib_order(R1)).cuda()
+    p.b.lowlevel_smooth(R1d)
+    p.os.lowlevel(W, R1)
+    check_state(p, W, dW, f"{name} lowlevel")
+
+
+@pytest.mark.parametrize("name", CASES)
+@pytest.mark.parametrize("scheme", [cg.S2O4, cg.S1O2])
+def test_cycles(name, scheme):
+    import torch
+    p = Pair(name, time_scheme=scheme)
+    W, dW = p.W0.copy(), p.dW0.copy()
+    res = torch.zeros(1, dtype=torch.float64, device="cuda")
+    for k in range(3):
+        r_or = p.os.cycle(W, dW)
+        p.b.cycle(res)
+        check_state(p, W, dW, f"{name} s{scheme} cycle{k}")
+        r_g = float(res.cpu()[0])
+        assert abs(r_g - r_or) <= 1e-9 * r_or, (r_g, r_or)
+
+
+def test_explicit_only_cycles():
+    p = Pair("cyl2d_visc", explicit_only=1)
+    W, dW = p.W0.copy(), p.dW0.copy()
+    for k in range(3):
+        p.os.cycle(W, dW)
+        p.b.cycle()
+    check_state(p, W, dW, "explicit")
+
+
+def test_free_stream_on_device():
+    m = I.sphere_mesh(8, 16, 8, 3, 2, wall=I.BC_FARFIELD)
+    Winf = I.free_stream(3, 0.25, 10.0)
+    W, dW = I.uniform_state(m, Winf)
+    b = cg.Batch([cg.Mesh(m)], [cg.Params(W_inf=Winf, mu=0.01, Pr=0.72)])
+    b.upload(0, W, dW)
+    for _ in range(20):
+        b.cycle()
+    Wg, dWg = b.download(0)
+    assert np.abs(Wg - Winf[:, None]).max() <= 1e-13
+    assert np.abs(dWg).max() <= 1e-12
+
+
+def test_run_to_run_bitwise():
+    p = Pair("sphere")
+    for _ in range(2):
+        p.b.cycle()
+    Wa, dWa = p.b.download(0)
+    p.b.upload(0, p.W0, p.dW0)
+    for _ in range(2):
+        p.b.cycle()
+    Wb, dWb = p.b.download(0)
+    assert np.array_equal(Wa, Wb) and np.array_equal(dWa, dWb)
