@@ -207,6 +207,26 @@ typedef struct {
    (host).  Cases that finish stop being updated. */
 cgks_status cgks_solve(cgks_batch *batch, const cgks_solve_opts *opts, cgks_solve_report *report, void *stream);
 
+/* Kernel timing.  enable = 1 brackets every kernel launch of the batch with
+   a pair of HIP events recorded on the launch stream; cgks_timing_read
+   synchronises those events and returns, per kernel kind, the summed
+   duration in milliseconds and the number of launches since the previous
+   read (then starts a new interval).  ms and launches are host arrays of
+   CGKS_KERNEL_KINDS entries. */
+enum {
+    CGKS_K_DT = 0,        /* global time-step reduction */
+    CGKS_K_RECON = 1,     /* compact reconstruction */
+    CGKS_K_FLUX = 2,      /* gas-kinetic flux at face Gauss points */
+    CGKS_K_CELL = 3,      /* Gauss-Green gather, stage update, R1 */
+    CGKS_K_LOWFACE = 4,   /* first-order KFVS face flux and spectral radius */
+    CGKS_K_LOWCELL = 5,   /* forcing and implicit-step setup */
+    CGKS_K_SWEEP = 6,     /* one colour pass of point relaxation */
+    CGKS_K_PROLONG = 7,   /* prolongation and residual norm */
+    CGKS_KERNEL_KINDS = 8
+};
+cgks_status cgks_timing_enable(cgks_batch *batch, int32_t enable);
+cgks_status cgks_timing_read(cgks_batch *batch, double *ms, int64_t *launches);
+
 const char *cgks_status_string(cgks_status s);
 
 #ifdef __cplusplus

@@ -26,7 +26,9 @@ RESIDUAL_HIGH, RESIDUAL_LOW, RESIDUAL_NORM = 0, 1, 2
 EXPORTS = ["cgks_status_string", "cgks_mesh_create", "cgks_mesh_query", "cgks_mesh_permutation",
            "cgks_mesh_geometry", "cgks_mesh_destroy", "cgks_batch_create", "cgks_batch_query", "cgks_batch_bind", "cgks_batch_destroy",
            "cgks_state_upload", "cgks_state_download", "cgks_state_device", "cgks_highorder_stage",
-           "cgks_residual", "cgks_lowlevel_smooth", "cgks_cycle", "cgks_solve"]
+           "cgks_residual", "cgks_lowlevel_smooth", "cgks_cycle", "cgks_solve", "cgks_timing_enable",
+           "cgks_timing_read"]
+KERNEL_KINDS = ["dt", "recon", "flux", "cell", "low_face", "low_cell", "sweep", "prolong"]
 
 
 class CgksError(RuntimeError):
@@ -101,6 +103,8 @@ def lib():
         L.cgks_lowlevel_smooth.argtypes = [P, P, P]
         L.cgks_cycle.argtypes = [P, P, P]
         L.cgks_solve.argtypes = [P, C.POINTER(_SolveOpts), P, P]
+        L.cgks_timing_enable.argtypes = [P, i32]
+        L.cgks_timing_read.argtypes = [P, P, P]
         for name in EXPORTS:
             getattr(L, name).restype = C.c_int if name != "cgks_status_string" else C.c_char_p
         _lib = L
@@ -264,6 +268,16 @@ class Batch:
     def cycle(self, res=None):
         ptr = C.c_void_p(res.data_ptr()) if res is not None else None
         _check(lib().cgks_cycle(self.h, ptr, _stream(self.stream)), "cgks_cycle")
+
+    def timing(self, enable=True):
+        _check(lib().cgks_timing_enable(self.h, int(enable)), "cgks_timing_enable")
+
+    def timing_read(self):
+        """{kind: (total ms, launches)} since the previous read."""
+        ms = np.zeros(len(KERNEL_KINDS))
+        n = np.zeros(len(KERNEL_KINDS), np.int64)
+        _check(lib().cgks_timing_read(self.h, _ptr(ms), _ptr(n)), "cgks_timing_read")
+        return {k: (float(ms[i]), int(n[i])) for i, k in enumerate(KERNEL_KINDS)}
 
     def solve(self, max_cycles, tol, tol_abs=False, check_every=10, history=False):
         opts = _SolveOpts(max_cycles, tol, int(tol_abs), check_every, None)

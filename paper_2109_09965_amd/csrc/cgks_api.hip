@@ -55,6 +55,13 @@ struct cgks_batch {
     } o{};
     Dev dev{};
     int32_t *d_cb_start = nullptr, *d_cb_count = nullptr;
+    // kernel timing: event pairs recorded around launches
+    bool timing = false;
+    std::vector<hipEvent_t> events;
+    std::vector<std::pair<int, size_t>> recs;   // (kind, index of the start event)
+    ~cgks_batch() {
+        for (hipEvent_t e : events) (void)hipEventDestroy(e);
+    }
 };
 
 namespace {
@@ -180,6 +187,27 @@ template <class T> hipError_t put(cgks_batch *b, size_t off, const std::vector<T
 
 inline unsigned nblk(int64_t n) { return unsigned((n + kBlock - 1) / kBlock); }
 
+// Launch `launch()` bracketed by two events when timing is enabled.
+template <class F> void timed(cgks_batch *b, int kind, hipStream_t s, F &&launch) {
+    if (!b->timing) {
+        launch();
+        return;
+    }
+    const size_t k = b->recs.size() * 2;
+    while (b->events.size() < k + 2) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) {
+            launch();
+            return;
+        }
+        b->events.push_back(e);
+    }
+    (void)hipEventRecord(b->events[k], s);
+    launch();
+    (void)hipEventRecord(b->events[k + 1], s);
+    b->recs.emplace_back(kind, k);
+}
+
 #define HIP_TRY(x)                                      \
     do {                                                \
         if ((x) != hipSuccess) return CGKS_EDEVICE;     \
@@ -188,12 +216,15 @@ inline unsigned nblk(int64_t n) { return unsigned((n + kBlock - 1) / kBlock); }
 template <int D> cgks_status launch_highorder(cgks_batch *b, int mode, hipStream_t s) {
     const Dev &d = b->dev;
     if (mode == MODE_STAGE0) {
-        hipLaunchKernelGGL(k_dt_partial<D>, dim3(b->rb_start.size()), dim3(kBlock), 0, s, d);
-        hipLaunchKernelGGL(k_dt_final, dim3(nblk(b->n_case)), dim3(kBlock), 0, s, d, b->n_case);
+        timed(b, CGKS_K_DT, s, [&] {
+            hipLaunchKernelGGL(k_dt_partial<D>, dim3(b->rb_start.size()), dim3(kBlock), 0, s, d);
+            hipLaunchKernelGGL(k_dt_final, dim3(nblk(b->n_case)), dim3(kBlock), 0, s, d, b->n_case);
+        });
     }
-    hipLaunchKernelGGL(k_recon<D>, dim3(nblk(b->NC)), dim3(kBlock), 0, s, d);
-    hipLaunchKernelGGL(k_flux<D>, dim3(nblk(b->NG)), dim3(kBlock), 0, s, d);
-    hipLaunchKernelGGL(k_cell<D>, dim3(nblk(b->NC)), dim3(kBlock), 0, s, d, mode);
+    timed(b, CGKS_K_RECON, s, [&] { hipLaunchKernelGGL(k_recon<D>, dim3(nblk(b->NC)), dim3(kBlock), 0, s, d); });
+    timed(b, CGKS_K_FLUX, s, [&] { hipLaunchKernelGGL(k_flux<D>, dim3(nblk(b->NG)), dim3(kBlock), 0, s, d); });
+    timed(b, CGKS_K_CELL, s,
+          [&] { hipLaunchKernelGGL(k_cell<D>, dim3(nblk(b->NC)), dim3(kBlock), 0, s, d, mode); });
     HIP_TRY(hipGetLastError());
     return CGKS_OK;
 }
@@ -216,24 +247,37 @@ template <int D> cgks_status launch_lowlevel(cgks_batch *b, const double *R1, hi
     Dev d = b->dev;
     if (R1 != d.R1)
         HIP_TRY(hipMemcpyAsync(d.R1, R1, sizeof(double) * (D + 2) * b->NC, hipMemcpyDeviceToDevice, s));
-    hipLaunchKernelGGL(k_low_face<D>, dim3(nblk(b->NF)), dim3(kBlock), 0, s, d, (const double *)d.W,
-                       (const double *)nullptr);
-    hipLaunchKernelGGL(k_low_cell<D>, dim3(nblk(b->NC)), dim3(kBlock), 0, s, d, (int)LOW_FORCE, (double *)nullptr);
+    timed(b, CGKS_K_LOWFACE, s, [&] {
+        hipLaunchKernelGGL(k_low_face<D>, dim3(nblk(b->NF)), dim3(kBlock), 0, s, d, (const double *)d.W,
+                           (const double *)nullptr);
+    });
+    timed(b, CGKS_K_LOWCELL, s, [&] {
+        hipLaunchKernelGGL(k_low_cell<D>, dim3(nblk(b->NC)), dim3(kBlock), 0, s, d, (int)LOW_FORCE,
+                           (double *)nullptr);
+    });
     const std::vector<int> order = sweep_order(b->max_colour, b->n_sweeps);
     for (int k = 0; k < b->n_implicit; ++k) {
-        hipLaunchKernelGGL(k_low_face<D>, dim3(nblk(b->NF)), dim3(kBlock), 0, s, d, (const double *)d.U,
-                           (const double *)(k ? d.dU : nullptr));
-        hipLaunchKernelGGL(k_low_cell<D>, dim3(nblk(b->NC)), dim3(kBlock), 0, s, d,
-                           (int)(k ? LOW_STEP : LOW_STEP_FIRST), (double *)nullptr);
+        timed(b, CGKS_K_LOWFACE, s, [&] {
+            hipLaunchKernelGGL(k_low_face<D>, dim3(nblk(b->NF)), dim3(kBlock), 0, s, d, (const double *)d.U,
+                               (const double *)(k ? d.dU : nullptr));
+        });
+        timed(b, CGKS_K_LOWCELL, s, [&] {
+            hipLaunchKernelGGL(k_low_cell<D>, dim3(nblk(b->NC)), dim3(kBlock), 0, s, d,
+                               (int)(k ? LOW_STEP : LOW_STEP_FIRST), (double *)nullptr);
+        });
         for (int c : order) {
             const int64_t b0 = b->colour_blk_off[c], nb = b->colour_blk_off[c + 1] - b0;
             if (nb == 0) continue;
-            hipLaunchKernelGGL(k_sweep<D>, dim3(unsigned(nb)), dim3(kBlock), 0, s, d,
-                               (const int32_t *)(b->d_cb_start + b0), (const int32_t *)(b->d_cb_count + b0));
+            timed(b, CGKS_K_SWEEP, s, [&] {
+                hipLaunchKernelGGL(k_sweep<D>, dim3(unsigned(nb)), dim3(kBlock), 0, s, d,
+                                   (const int32_t *)(b->d_cb_start + b0), (const int32_t *)(b->d_cb_count + b0));
+            });
         }
     }
-    hipLaunchKernelGGL(k_prolong_res<D>, dim3(b->rb_start.size()), dim3(kBlock), 0, s, d, 1);
-    hipLaunchKernelGGL(k_res_final, dim3(nblk(b->n_case)), dim3(kBlock), 0, s, d, b->n_case);
+    timed(b, CGKS_K_PROLONG, s, [&] {
+        hipLaunchKernelGGL(k_prolong_res<D>, dim3(b->rb_start.size()), dim3(kBlock), 0, s, d, 1);
+        hipLaunchKernelGGL(k_res_final, dim3(nblk(b->n_case)), dim3(kBlock), 0, s, d, b->n_case);
+    });
     HIP_TRY(hipGetLastError());
     return CGKS_OK;
 }
@@ -246,8 +290,10 @@ template <int D> cgks_status launch_cycle(cgks_batch *b, hipStream_t s) {
         if (st) return st;
     }
     if (b->explicit_only) {
-        hipLaunchKernelGGL(k_prolong_res<D>, dim3(b->rb_start.size()), dim3(kBlock), 0, s, b->dev, 0);
-        hipLaunchKernelGGL(k_res_final, dim3(nblk(b->n_case)), dim3(kBlock), 0, s, b->dev, b->n_case);
+        timed(b, CGKS_K_PROLONG, s, [&] {
+            hipLaunchKernelGGL(k_prolong_res<D>, dim3(b->rb_start.size()), dim3(kBlock), 0, s, b->dev, 0);
+            hipLaunchKernelGGL(k_res_final, dim3(nblk(b->n_case)), dim3(kBlock), 0, s, b->dev, b->n_case);
+        });
         HIP_TRY(hipGetLastError());
         return CGKS_OK;
     }
@@ -672,6 +718,30 @@ cgks_status cgks_solve(cgks_batch *b, const cgks_solve_opts *opts, cgks_solve_re
     for (int c = 0; c < n; ++c) prm[c].active = 1;
     HIP_TRY(hipMemcpyAsync((void *)b->dev.prm, prm.data(), sizeof(DevParams) * n, hipMemcpyHostToDevice, s));
     HIP_TRY(hipStreamSynchronize(s));
+    return CGKS_OK;
+}
+
+cgks_status cgks_timing_enable(cgks_batch *b, int32_t enable) {
+    if (!b) return CGKS_EINVAL;
+    b->timing = enable != 0;
+    b->recs.clear();
+    return CGKS_OK;
+}
+
+cgks_status cgks_timing_read(cgks_batch *b, double *ms, int64_t *launches) {
+    if (!b || !ms || !launches) return CGKS_EINVAL;
+    for (int k = 0; k < CGKS_KERNEL_KINDS; ++k) {
+        ms[k] = 0.0;
+        launches[k] = 0;
+    }
+    for (auto &r : b->recs) {
+        HIP_TRY(hipEventSynchronize(b->events[r.second + 1]));
+        float t = 0.0f;
+        HIP_TRY(hipEventElapsedTime(&t, b->events[r.second], b->events[r.second + 1]));
+        ms[r.first] += t;
+        launches[r.first] += 1;
+    }
+    b->recs.clear();
     return CGKS_OK;
 }
 
