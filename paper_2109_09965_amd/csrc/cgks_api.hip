@@ -47,10 +47,10 @@ struct cgks_batch {
     size_t bytes = 0;
     char *base = nullptr;
     struct {
-        size_t W, dW, Wn, L0, Lt0, G0, coef, vol, h, ctr, sec, minv, slot_face, slot_nb, cell_case;
-        size_t fL, fR, fbc, fcase, gp_off, bslot, avec, S, shift, gavg;
-        size_t gx, gn, gw, gface, gF0, gFt, gWc, gWt;
-        size_t U, dU, Sf, RHS, D, R1, lam, Flow;
+        size_t W, dW, Wn, L0, Lt0, G0, coef, vol, h, ctr, sec, minv, slot, cell_case;
+        size_t fL, fR, fbc, fcase, gp_off, bslot, avec, S, shift, gavg, bface, gdat;
+        size_t gx, gn, gw, fsum;
+        size_t U, dU, Sf, RHS, D, R1, lowf, swp;
         size_t prm, dt, res, flag, rb_start, rb_count, rb_case, case_rb_off, part0, part1, cb_start, cb_count;
     } o{};
     Dev dev{};
@@ -85,8 +85,7 @@ void layout(cgks_batch *b) {
     o.ctr = a.take<double>(d * NC);
     o.sec = a.take<double>(nq * NC);
     o.minv = a.take<double>(nk * (nk + 1) / 2 * NC);
-    o.slot_face = a.take<int32_t>(ns * NC);
-    o.slot_nb = a.take<int32_t>(ns * NC);
+    o.slot = a.take<int2>(ns * NC);
     o.cell_case = a.take<int32_t>(NC);
     o.fL = a.take<int32_t>(NF);
     o.fR = a.take<int32_t>(NF);
@@ -98,22 +97,20 @@ void layout(cgks_batch *b) {
     o.S = a.take<double>(NF);
     o.shift = a.take<double>(d * NF);
     o.gavg = a.take<double>(nk * NB);
+    o.bface = a.take<int32_t>(NB);
+    o.gdat = a.take<double>((nv + d * nv) * NB);
     o.gx = a.take<double>(d * NG);
     o.gn = a.take<double>(d * NG);
     o.gw = a.take<double>(NG);
-    o.gface = a.take<int32_t>(NG);
-    o.gF0 = a.take<double>(nv * NG);
-    o.gFt = a.take<double>(nv * NG);
-    o.gWc = a.take<double>(nv * NG);
-    o.gWt = a.take<double>(nv * NG);
+    o.fsum = a.take<double>((2 * nv + 2 * d * nv) * NF);
     o.U = a.take<double>(nv * NC);
     o.dU = a.take<double>(nv * NC);
     o.Sf = a.take<double>(nv * NC);
     o.RHS = a.take<double>(nv * NC);
     o.D = a.take<double>(NC);
     o.R1 = a.take<double>(nv * NC);
-    o.lam = a.take<double>(NF);
-    o.Flow = a.take<double>(nv * NF);
+    o.lowf = a.take<double>(nv * NF);
+    o.swp = a.take<double>(4 * NF);
     o.prm = a.take<DevParams>(b->n_case);
     o.dt = a.take<double>(b->n_case);
     o.res = a.take<double>(b->n_case);
@@ -158,19 +155,20 @@ void fill_dev(cgks_batch *b) {
     d.coef = at<double>(b, o.coef);
     d.vol = at<double>(b, o.vol); d.h = at<double>(b, o.h); d.ctr = at<double>(b, o.ctr);
     d.sec = at<double>(b, o.sec); d.minv = at<double>(b, o.minv);
-    d.slot_face = at<int32_t>(b, o.slot_face); d.slot_nb = at<int32_t>(b, o.slot_nb);
+    d.slot = at<int2>(b, o.slot);
     d.cell_case = at<int32_t>(b, o.cell_case);
     d.fL = at<int32_t>(b, o.fL); d.fR = at<int32_t>(b, o.fR); d.fbc = at<int32_t>(b, o.fbc);
     d.fcase = at<int32_t>(b, o.fcase); d.gp_off = at<int32_t>(b, o.gp_off); d.bslot = at<int32_t>(b, o.bslot);
     d.avec = at<double>(b, o.avec); d.S = at<double>(b, o.S); d.shift = at<double>(b, o.shift);
     d.gavg = at<double>(b, o.gavg);
+    d.bface = at<int32_t>(b, o.bface);
+    d.gdat = at<double>(b, o.gdat);
+    d.NB_real = int32_t(b->NB);
     d.gx = at<double>(b, o.gx); d.gn = at<double>(b, o.gn); d.gw = at<double>(b, o.gw);
-    d.gface = at<int32_t>(b, o.gface);
-    d.gF0 = at<double>(b, o.gF0); d.gFt = at<double>(b, o.gFt); d.gWc = at<double>(b, o.gWc);
-    d.gWt = at<double>(b, o.gWt);
+    d.fsum = at<double>(b, o.fsum);
     d.U = at<double>(b, o.U); d.dU = at<double>(b, o.dU); d.Sf = at<double>(b, o.Sf);
     d.RHS = at<double>(b, o.RHS); d.D = at<double>(b, o.D); d.R1 = at<double>(b, o.R1);
-    d.lam = at<double>(b, o.lam); d.Flow = at<double>(b, o.Flow);
+    d.lowf = at<double>(b, o.lowf); d.swp = at<double>(b, o.swp);
     d.prm = at<DevParams>(b, o.prm); d.dt = at<double>(b, o.dt); d.res = at<double>(b, o.res);
     d.flag = at<int32_t>(b, o.flag);
     d.rb_start = at<int32_t>(b, o.rb_start); d.rb_count = at<int32_t>(b, o.rb_count);
@@ -221,8 +219,14 @@ template <int D> cgks_status launch_highorder(cgks_batch *b, int mode, hipStream
             hipLaunchKernelGGL(k_dt_final, dim3(nblk(b->n_case)), dim3(kBlock), 0, s, d, b->n_case);
         });
     }
-    timed(b, CGKS_K_RECON, s, [&] { hipLaunchKernelGGL(k_recon<D>, dim3(nblk(b->NC)), dim3(kBlock), 0, s, d); });
-    timed(b, CGKS_K_FLUX, s, [&] { hipLaunchKernelGGL(k_flux<D>, dim3(nblk(b->NG)), dim3(kBlock), 0, s, d); });
+    timed(b, CGKS_K_RECON, s, [&] {
+        if (b->NB > 0) hipLaunchKernelGGL(k_ghost<D>, dim3(nblk(b->NB)), dim3(kBlock), 0, s, d);
+        hipLaunchKernelGGL(k_recon<D>, dim3(nblk(b->NC)), dim3(kBlock), 0, s, d);
+    });
+    timed(b, CGKS_K_FLUX, s, [&] {
+        hipLaunchKernelGGL(k_flux<D>, dim3(nblk(b->NF * Dim<D>::lanes)), dim3(kBlock), 0, s, d,
+                           (int)(mode != MODE_R1));
+    });
     timed(b, CGKS_K_CELL, s,
           [&] { hipLaunchKernelGGL(k_cell<D>, dim3(nblk(b->NC)), dim3(kBlock), 0, s, d, mode); });
     HIP_TRY(hipGetLastError());
@@ -249,7 +253,7 @@ template <int D> cgks_status launch_lowlevel(cgks_batch *b, const double *R1, hi
         HIP_TRY(hipMemcpyAsync(d.R1, R1, sizeof(double) * (D + 2) * b->NC, hipMemcpyDeviceToDevice, s));
     timed(b, CGKS_K_LOWFACE, s, [&] {
         hipLaunchKernelGGL(k_low_face<D>, dim3(nblk(b->NF)), dim3(kBlock), 0, s, d, (const double *)d.W,
-                           (const double *)nullptr);
+                           (const double *)nullptr, 1);
     });
     timed(b, CGKS_K_LOWCELL, s, [&] {
         hipLaunchKernelGGL(k_low_cell<D>, dim3(nblk(b->NC)), dim3(kBlock), 0, s, d, (int)LOW_FORCE,
@@ -259,7 +263,7 @@ template <int D> cgks_status launch_lowlevel(cgks_batch *b, const double *R1, hi
     for (int k = 0; k < b->n_implicit; ++k) {
         timed(b, CGKS_K_LOWFACE, s, [&] {
             hipLaunchKernelGGL(k_low_face<D>, dim3(nblk(b->NF)), dim3(kBlock), 0, s, d, (const double *)d.U,
-                               (const double *)(k ? d.dU : nullptr));
+                               (const double *)(k ? d.dU : nullptr), 0);
         });
         timed(b, CGKS_K_LOWCELL, s, [&] {
             hipLaunchKernelGGL(k_low_cell<D>, dim3(nblk(b->NC)), dim3(kBlock), 0, s, d,
@@ -472,9 +476,11 @@ cgks_status cgks_batch_bind(cgks_batch *b, void *buf, size_t bytes, void *stream
     const size_t NC = b->NC, NF = b->NF, NG = b->NG, NB = std::max<int64_t>(b->NB, 1);
     try {
         std::vector<double> vol(NC), h(NC), ctr(d * NC), sec(nq * NC), minv(nsym * NC);
-        std::vector<int32_t> slot_face(ns * NC, 0), slot_nb(ns * NC, -1), cell_case(NC);
-        std::vector<int32_t> fL(NF), fR(NF), fbc(NF), fcase(NF), gp_off(NF + 1), bslot(NF, -1), gface(NG);
+        std::vector<int2> slot(ns * NC, make_int2(0, -1));
+        std::vector<int32_t> cell_case(NC);
+        std::vector<int32_t> fL(NF), fR(NF), fbc(NF), fcase(NF), gp_off(NF + 1), bslot(NF, -1);
         std::vector<double> avec(d * NF), S(NF), shift(d * NF), gavg(nk * NB, 0.0), gx(d * NG), gn(d * NG), gw(NG);
+        std::vector<int32_t> bface(NB, 0);
         std::vector<DevParams> prm;
         for (int c = 0; c < b->n_case; ++c) {
             const HostMesh &m = b->meshes[c]->hm;
@@ -495,9 +501,9 @@ cgks_status cgks_batch_bind(cgks_batch *b, void *buf, size_t bytes, void *stream
                 for (int64_t q = m.cf_ptr[i]; q < m.cf_ptr[i + 1]; ++q, ++sl) {
                     const int64_t f = m.cf_face[q];
                     const int side = m.cf_side[q];
-                    slot_face[sl * NC + I] = side ? -int32_t(fo + f + 1) : int32_t(fo + f + 1);
                     const int64_t nb = side ? m.owner[f] : m.neigh[f];
-                    slot_nb[sl * NC + I] = nb >= 0 ? int32_t(co + m.caller2lib[nb]) : -1;
+                    slot[sl * NC + I] = make_int2(side ? -int32_t(fo + f + 1) : int32_t(fo + f + 1),
+                                                  nb >= 0 ? int32_t(co + m.caller2lib[nb]) : -1);
                 }
             }
             int64_t bcount = 0;
@@ -516,9 +522,9 @@ cgks_status cgks_batch_bind(cgks_batch *b, void *buf, size_t bytes, void *stream
                 if (m.neigh[f] < 0) {
                     const int64_t B = bo + bcount++;
                     bslot[F] = int32_t(B);
+                    bface[B] = int32_t(F);
                     for (int k = 0; k < nk; ++k) gavg[k * NB + B] = m.gavg[f * nk + k];
                 }
-                for (int64_t g = m.gp_off[f]; g < m.gp_off[f + 1]; ++g) gface[go + g] = int32_t(F);
             }
             for (int64_t g = 0; g < m.n_gp; ++g) {
                 for (int a = 0; a < d; ++a) {
@@ -534,14 +540,14 @@ cgks_status cgks_batch_bind(cgks_batch *b, void *buf, size_t bytes, void *stream
         auto &o = b->o;
         HIP_TRY(put(b, o.vol, vol, s)); HIP_TRY(put(b, o.h, h, s)); HIP_TRY(put(b, o.ctr, ctr, s));
         HIP_TRY(put(b, o.sec, sec, s)); HIP_TRY(put(b, o.minv, minv, s));
-        HIP_TRY(put(b, o.slot_face, slot_face, s)); HIP_TRY(put(b, o.slot_nb, slot_nb, s));
+        HIP_TRY(put(b, o.slot, slot, s));
         HIP_TRY(put(b, o.cell_case, cell_case, s));
         HIP_TRY(put(b, o.fL, fL, s)); HIP_TRY(put(b, o.fR, fR, s)); HIP_TRY(put(b, o.fbc, fbc, s));
         HIP_TRY(put(b, o.fcase, fcase, s)); HIP_TRY(put(b, o.gp_off, gp_off, s)); HIP_TRY(put(b, o.bslot, bslot, s));
         HIP_TRY(put(b, o.avec, avec, s)); HIP_TRY(put(b, o.S, S, s)); HIP_TRY(put(b, o.shift, shift, s));
         HIP_TRY(put(b, o.gavg, gavg, s));
+        HIP_TRY(put(b, o.bface, bface, s));
         HIP_TRY(put(b, o.gx, gx, s)); HIP_TRY(put(b, o.gn, gn, s)); HIP_TRY(put(b, o.gw, gw, s));
-        HIP_TRY(put(b, o.gface, gface, s));
         HIP_TRY(put(b, o.prm, prm, s)); HIP_TRY(put(b, o.flag, zero_flag, s));
         HIP_TRY(put(b, o.dt, zero_case, s)); HIP_TRY(put(b, o.res, zero_case, s));
         HIP_TRY(put(b, o.rb_start, b->rb_start, s)); HIP_TRY(put(b, o.rb_count, b->rb_count, s));
@@ -625,11 +631,11 @@ cgks_status cgks_residual(cgks_batch *b, int32_t kind, double *out, void *stream
     if (kind == CGKS_RESIDUAL_LOW) {
         if (b->dim == 2) {
             hipLaunchKernelGGL(k_low_face<2>, dim3(nblk(b->NF)), dim3(kBlock), 0, s, b->dev, (const double *)b->dev.W,
-                               (const double *)nullptr);
+                               (const double *)nullptr, 1);
             hipLaunchKernelGGL(k_low_cell<2>, dim3(nblk(b->NC)), dim3(kBlock), 0, s, b->dev, (int)LOW_R0_OUT, out);
         } else {
             hipLaunchKernelGGL(k_low_face<3>, dim3(nblk(b->NF)), dim3(kBlock), 0, s, b->dev, (const double *)b->dev.W,
-                               (const double *)nullptr);
+                               (const double *)nullptr, 1);
             hipLaunchKernelGGL(k_low_cell<3>, dim3(nblk(b->NC)), dim3(kBlock), 0, s, b->dev, (int)LOW_R0_OUT, out);
         }
         HIP_TRY(hipGetLastError());

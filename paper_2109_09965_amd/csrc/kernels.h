@@ -29,20 +29,25 @@ struct DevParams {
 };
 
 struct Dev {
-    int32_t NC, NF, NG, NB;
+    int32_t NC, NF, NG, NB;   // NB >= 1 (array extent); NB_real boundary faces
+    int32_t NB_real;
     // cells
     double *W, *dW, *Wn, *L0, *Lt0, *G0, *coef;
     const double *vol, *h, *ctr, *sec, *minv;
-    const int32_t *slot_face, *slot_nb, *cell_case;
+    const int2 *slot;         // [ns][NC]: (x) face code +-(f + 1), 0 = none; (y) neighbour cell or -1
+    const int32_t *cell_case;
     // faces
     const int32_t *fL, *fR, *fbc, *fcase, *gp_off, *bslot;
     const double *avec, *S, *shift, *gavg;
+    const int32_t *bface;     // [NB] face of each boundary slot
+    double *gdat;             // [NB][nv + D nv] ghost cell average and gradient
     // gauss points
     const double *gx, *gn, *gw;
-    const int32_t *gface;
-    double *gF0, *gFt, *gWc, *gWt;
-    // low level
-    double *U, *dU, *Sf, *RHS, *D, *R1, *lam, *Flow;
+    double *fsum;      // per face [NF][2 nv + 2 D nv]: sum_g wJ (F0, Ft, W_c n, W_t n)
+    // low level: U, dU cell-major [NC][nv] (gathered by neighbours), Sf, RHS, R1 [nv][NC]
+    double *U, *dU, *Sf, *RHS, *D, *R1;
+    double *lowf;      // [NF][nv]: S_f F_kfvs
+    double *swp;       // [NF][4]: area vector S_f n_f (D values), S_f lam_f
     // per case
     const DevParams *prm;
     double *dt, *res;
@@ -58,6 +63,8 @@ template <int D> struct Dim {
     static constexpr int nq = D == 2 ? 3 : 6;
     static constexpr int ns = D == 2 ? 4 : 8;   // slots per cell
     static constexpr int nsym = nk * (nk + 1) / 2;
+    static constexpr int lanes = D == 2 ? 2 : 4;   // threads per face (one per Gauss point)
+    static constexpr int fs = 2 * nv + 2 * D * nv; // face sums per face
 };
 
 // quadratic basis (a, b) pairs: 2-D (00, 01, 11); 3-D (00, 11, 22, 01, 02, 12)
@@ -249,49 +256,54 @@ template <int D> __device__ bool gks_flux(const double *Wc, const double Gc[D][D
     double Uf[3] = {0, 0, 0};
 #pragma unroll
     for (int a = 0; a < D; ++a) Uf[a] = q.U[a];
+    // Fourier heat flux of the interface state along the normal (R = 1,
+    // T = p / rho), used for the Prandtl-number correction
+    double qcorr = 0.0;
+    if (P.Pr != 1.0 && P.mu != 0.0) {
+        double ke = 0, ked = 0;
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            ke += q.U[k] * q.U[k];
+            ked += q.U[k] * Gc[0][1 + k];
+        }
+        const double pn = (P.gamma - 1.0) * (Gc[0][nv - 1] - ked + 0.5 * ke * Gc[0][0]);
+        const double Tn = (pn * q.rho - q.p * Gc[0][0]) / (q.rho * q.rho);
+        qcorr = (1.0 / P.Pr - 1.0) * (-P.mu * P.gamma / (P.gamma - 1.0) * Tn);
+    }
     Moments<D> m;
     m.full(Uf, q.lam, P.K);
     const double tau = P.mu / q.p;
     const double ir = 1.0 / q.rho;
-    double a[D][nv], b[nv], A[nv], t0[nv], t1[nv];
+    // one direction at a time: micro-slope a^(j), its share of the
+    // compatibility sum b = -<(sum_j a^(j) u_j) psi> and of the collision term
+    // tt = <u psi (sum_j a^(j) u_j)>
+    double b[nv], tt[nv];
+#pragma unroll
+    for (int v = 0; v < nv; ++v) b[v] = tt[v] = 0.0;
 #pragma unroll
     for (int j = 0; j < D; ++j) {
+        double g[nv], a[nv], t0[nv];
 #pragma unroll
-        for (int v = 0; v < nv; ++v) b[v] = Gc[j][v] * ir;
-        micro_slope<D>(b, q.U, q.lam, N, a[j]);
-    }
-    // compatibility: <A psi> = -<(a^n u + a^t1 v [+ a^t2 w]) psi>
-    Epsi<D>(m, a[0], 1, 0, 0, t0);
-    Epsi<D>(m, a[1], 0, 1, 0, t1);
-#pragma unroll
-    for (int v = 0; v < nv; ++v) b[v] = -(t0[v] + t1[v]);
-    if constexpr (D == 3) {
-        Epsi<D>(m, a[D - 1], 0, 0, 1, t0);
+        for (int v = 0; v < nv; ++v) g[v] = Gc[j][v] * ir;
+        micro_slope<D>(g, q.U, q.lam, N, a);
+        Epsi<D>(m, a, j == 0 ? 1 : 0, j == 1 ? 1 : 0, j == 2 ? 1 : 0, t0);
 #pragma unroll
         for (int v = 0; v < nv; ++v) b[v] -= t0[v];
+        Epsi<D>(m, a, j == 0 ? 2 : 1, j == 1 ? 1 : 0, j == 2 ? 1 : 0, t0);
+#pragma unroll
+        for (int v = 0; v < nv; ++v) tt[v] += t0[v];
     }
+    double A[nv], eA[nv];
     micro_slope<D>(b, q.U, q.lam, N, A);
-    // E[u psi (A)] gives the time derivative of the flux
-    double eA[nv];
+    // E[u psi A] gives the time derivative of the flux
     Epsi<D>(m, A, 1, 0, 0, eA);
-    // E[u psi (a.u)]
-    double tt[nv];
-    Epsi<D>(m, a[0], 2, 0, 0, tt);
-    Epsi<D>(m, a[1], 1, 1, 0, t1);
-#pragma unroll
-    for (int v = 0; v < nv; ++v) tt[v] += t1[v];
-    if constexpr (D == 3) {
-        Epsi<D>(m, a[D - 1], 1, 0, 1, t1);
-#pragma unroll
-        for (int v = 0; v < nv; ++v) tt[v] += t1[v];
-    }
     // E[u psi]
     double eu[nv];
     eu[0] = m.mu[1];
     eu[1] = m.mu[2];
     eu[2] = m.mu[1] * m.mv[1];
     double ep = m.mu[3] + m.mu[1] * (m.mv[2] + m.xi[1]);
-    if (D == 3) {
+    if constexpr (D == 3) {
         eu[3] = m.mu[1] * m.mw[1];
         ep += m.mu[1] * m.mw[2];
     }
@@ -302,18 +314,7 @@ template <int D> __device__ bool gks_flux(const double *Wc, const double Gc[D][D
         Ft[v] = q.rho * eA[v];
         Wt[v] = q.rho * b[v];
     }
-    if (P.Pr != 1.0 && P.mu != 0.0) {
-        // Fourier heat flux of the interface state along the normal (R = 1, T = p/rho)
-        double ke = 0, ked = 0;
-#pragma unroll
-        for (int k = 0; k < D; ++k) {
-            ke += q.U[k] * q.U[k];
-            ked += q.U[k] * Gc[0][1 + k];
-        }
-        const double pn = (P.gamma - 1.0) * (Gc[0][nv - 1] - ked + 0.5 * ke * Gc[0][0]);
-        const double Tn = (pn * q.rho - q.p * Gc[0][0]) / (q.rho * q.rho);
-        F0[nv - 1] += (1.0 / P.Pr - 1.0) * (-P.mu * P.gamma / (P.gamma - 1.0) * Tn);
-    }
+    F0[nv - 1] += qcorr;
     return true;
 }
 
@@ -544,37 +545,67 @@ template <int D> __device__ __forceinline__ void ghost_data(int bc, const double
         }
 }
 
-template <int D> __global__ __launch_bounds__(kBlock) void k_recon(Dev d) {
-    using T = Dim<D>;
-    constexpr int nv = T::nv, nk = T::nk, nq = T::nq;
-    const int i = blockIdx.x * kBlock + threadIdx.x;
-    if (i >= d.NC) return;
+// ghost cell data of every boundary face, from its owner's current state
+template <int D> __global__ __launch_bounds__(kBlock) void k_ghost(Dev d) {
+    constexpr int nv = D + 2;
+    const int B = blockIdx.x * kBlock + threadIdx.x;
+    if (B >= d.NB_real) return;
+    const int f = d.bface[B];
+    const int i = d.fL[f];
     const int NC = d.NC;
-    const DevParams &P = d.prm[d.cell_case[i]];
-    const double h = d.h[i], ih = 1.0 / h;
-    double xc[D], Wi[nv], Gi[D][nv], own[nq];
-#pragma unroll
-    for (int a = 0; a < D; ++a) xc[a] = d.ctr[a * NC + i];
+    const DevParams &P = d.prm[d.fcase[f]];
+    double Wi[nv], Gi[D][nv], Wg[nv], Gg[D][nv], n[D];
 #pragma unroll
     for (int v = 0; v < nv; ++v) Wi[v] = d.W[v * NC + i];
 #pragma unroll
     for (int a = 0; a < D; ++a)
 #pragma unroll
         for (int v = 0; v < nv; ++v) Gi[a][v] = d.dW[(a * nv + v) * NC + i];
+    const double iS = 1.0 / d.S[f];
+#pragma unroll
+    for (int a = 0; a < D; ++a) n[a] = d.avec[a * d.NF + f] * iS;
+    ghost_data<D>(d.fbc[f], n, Wi, Gi, P, Wg, Gg);
+    double *o = d.gdat + size_t(B) * (nv + D * nv);
+#pragma unroll
+    for (int v = 0; v < nv; ++v) o[v] = Wg[v];
+#pragma unroll
+    for (int a = 0; a < D; ++a)
+#pragma unroll
+        for (int v = 0; v < nv; ++v) o[nv + a * nv + v] = Gg[a][v];
+}
+
+// One thread per cell, all conservative variables: c = Minv M^T b.
+template <int D> __global__ __launch_bounds__(kBlock) void k_recon(Dev d) {
+    using T = Dim<D>;
+    constexpr int nv = T::nv, nk = T::nk, nq = T::nq;
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= d.NC) return;
+    const int NC = d.NC;
+    const double h = d.h[i], ih = 1.0 / h;
+    double xc[D], own[nq], Wi[nv];
+    double rhs[nk][nv];
+    // own-gradient rows first: they only touch the linear coefficients
+#pragma unroll
+    for (int v = 0; v < nv; ++v) {
+        Wi[v] = d.W[v * NC + i];
+#pragma unroll
+        for (int a = 0; a < D; ++a) rhs[a][v] = h * d.dW[(a * nv + v) * NC + i];
+#pragma unroll
+        for (int q = 0; q < nq; ++q) rhs[D + q][v] = 0.0;
+    }
+#pragma unroll
+    for (int a = 0; a < D; ++a) xc[a] = d.ctr[a * NC + i];
 #pragma unroll
     for (int q = 0; q < nq; ++q) own[q] = d.sec[sidx<D>(qa<D>(q), qb<D>(q)) * NC + i] * ih * ih;
-    double rhs[nk][nv];
-#pragma unroll
-    for (int k = 0; k < nk; ++k)
-#pragma unroll
-        for (int v = 0; v < nv; ++v) rhs[k][v] = 0.0;
 #pragma unroll 1
     for (int s = 0; s < T::ns; ++s) {
-        const int code = d.slot_face[s * NC + i];
+        const int2 sl = d.slot[s * NC + i];
+        const int code = sl.x;
         if (code == 0) break;
         const int f = (code > 0 ? code : -code) - 1;
-        const int nb = d.slot_nb[s * NC + i];
-        double avg[nk], Wm[nv], Gm[D][nv];
+        const int nb = sl.y;
+        double avg[nk];
+        const double *gd = nullptr;
         if (nb >= 0) {
             const double sg = code > 0 ? 1.0 : -1.0;
             double dx[D];
@@ -588,51 +619,34 @@ template <int D> __global__ __launch_bounds__(kBlock) void k_recon(Dev d) {
                 const int a = qa<D>(q), b = qb<D>(q);
                 avg[D + q] = (d.sec[sidx<D>(a, b) * NC + nb] + dx[a] * dx[b]) * ih * ih;
             }
-#pragma unroll
-            for (int v = 0; v < nv; ++v) Wm[v] = d.W[v * NC + nb];
-#pragma unroll
-            for (int a = 0; a < D; ++a)
-#pragma unroll
-                for (int v = 0; v < nv; ++v) Gm[a][v] = d.dW[(a * nv + v) * NC + nb];
         } else {
             const int bs = d.bslot[f];
 #pragma unroll
             for (int k = 0; k < nk; ++k) avg[k] = d.gavg[k * d.NB + bs];
-            double n[D];
-            const double iS = 1.0 / d.S[f];
-#pragma unroll
-            for (int a = 0; a < D; ++a) n[a] = d.avec[a * d.NF + f] * iS;
-            ghost_data<D>(d.fbc[f], n, Wi, Gi, P, Wm, Gm);
+            gd = d.gdat + size_t(bs) * (nv + D * nv);
         }
-        // average row
 #pragma unroll
         for (int v = 0; v < nv; ++v) {
-            const double bv = Wm[v] - Wi[v];
+            // average row
+            const double bv = (gd ? gd[v] : d.W[v * NC + nb]) - Wi[v];
 #pragma unroll
             for (int a = 0; a < D; ++a) rhs[a][v] += avg[a] * bv;
 #pragma unroll
             for (int q = 0; q < nq; ++q) rhs[D + q][v] += (avg[D + q] - own[q]) * bv;
-        }
-        // gradient rows
+            // gradient rows
 #pragma unroll
-        for (int a = 0; a < D; ++a)
-#pragma unroll
-            for (int v = 0; v < nv; ++v) {
-                const double bv = h * Gm[a][v];
-                rhs[a][v] += bv;
+            for (int a = 0; a < D; ++a) {
+                const double bg = h * (gd ? gd[nv + a * nv + v] : d.dW[(a * nv + v) * NC + nb]);
+                rhs[a][v] += bg;
 #pragma unroll
                 for (int q = 0; q < nq; ++q) {
                     const int p = qa<D>(q), r = qb<D>(q);
                     const double row = (p == a ? avg[r] : 0.0) + (r == a ? avg[p] : 0.0);
-                    rhs[D + q][v] += row * bv;
+                    rhs[D + q][v] += row * bg;
                 }
             }
+        }
     }
-    // own-gradient rows
-#pragma unroll
-    for (int a = 0; a < D; ++a)
-#pragma unroll
-        for (int v = 0; v < nv; ++v) rhs[a][v] += h * Gi[a][v];
     // c = Minv rhs
 #pragma unroll
     for (int k = 0; k < nk; ++k) {
@@ -697,11 +711,28 @@ template <int D> __device__ __forceinline__ void recon_eval(const Dev &d, int i,
 // kinetic interface equilibrium, smooth gas-kinetic flux.  Outputs are
 // weighted by wJ and in the global frame.
 // ---------------------------------------------------------------------
-template <int D> __global__ __launch_bounds__(kBlock) void k_flux(Dev d) {
-    constexpr int nv = D + 2;
-    const int g = blockIdx.x * kBlock + threadIdx.x;
-    if (g >= d.NG) return;
-    const int f = d.gface[g];
+// sum of v over the G consecutive lanes of a face group (every lane gets it)
+template <int G> __device__ __forceinline__ double group_sum(double v) {
+#pragma unroll
+    for (int m = 1; m < G; m <<= 1) v += __shfl_xor(v, m, G);
+    return v;
+}
+
+// One group of Dim<D>::lanes threads per face, one thread per Gauss point;
+// a lane without a Gauss point (triangles in 3-D) repeats the first point
+// with weight 0, so every lane runs the same code.  The face sums
+//   sum_g wJ (F0, Ft, W_c n, W_t n)   (global frame)
+// are reduced across the group and written face-major by its first lane.
+template <int D> __global__ __launch_bounds__(kBlock) void k_flux(Dev d, int want_grad) {
+    using T = Dim<D>;
+    constexpr int nv = T::nv, G = T::lanes, FS = T::fs;
+    const int t = blockIdx.x * kBlock + threadIdx.x;
+    const int fr_raw = t / G, q = t % G;
+    const bool face_ok = fr_raw < d.NF;
+    const int f = face_ok ? fr_raw : d.NF - 1;
+    const int g0 = d.gp_off[f], g1 = d.gp_off[f + 1];
+    const bool gp_ok = face_ok && g0 + q < g1;
+    const int g = gp_ok ? g0 + q : g0;
     const int cs = d.fcase[f];
     const DevParams &P = d.prm[cs];
     const int L = d.fL[f], R = d.fR[f];
@@ -711,73 +742,91 @@ template <int D> __global__ __launch_bounds__(kBlock) void k_flux(Dev d) {
         x[a] = d.gx[a * d.NG + g];
         n[a] = d.gn[a * d.NG + g];
     }
-    const double wJ = d.gw[g];
+    const double wJ = gp_ok ? d.gw[g] : 0.0;
     Frame<D> fr;
     fr.build(n);
-    double Wg[nv], GL[D][nv], WL[nv], GLl[D][nv];
-    recon_eval<D>(d, L, x, Wg, GL);
-    fr.to_local(Wg, WL);
-    fr.grad_to_local(GL, GLl);
     double Wc[nv], Gc[D][nv];
     bool ok = true;
     const int bc = d.fbc[f];
-    if (R >= 0 || bc != 2) {
-        double WR[nv], GRl[D][nv];
-        if (R >= 0) {
-            double xr[D], WRg[nv], GR[D][nv];
+    {
+        double Wg[nv], GL[D][nv], WL[nv], GLl[D][nv];
+        recon_eval<D>(d, L, x, Wg, GL);
+        fr.to_local(Wg, WL);
+        fr.grad_to_local(GL, GLl);
+        if (R >= 0 || bc != 2) {
+            double WR[nv], GRl[D][nv];
+            if (R >= 0) {
+                double xr[D], WRg[nv], GR[D][nv];
 #pragma unroll
-            for (int a = 0; a < D; ++a) xr[a] = x[a] - d.shift[a * d.NF + f];
-            recon_eval<D>(d, R, xr, WRg, GR);
-            fr.to_local(WRg, WR);
-            fr.grad_to_local(GR, GRl);
-        } else if (bc == 1) {
-            // mirror: normal momentum reversed; normal derivatives change sign
-            // except that of the normal momentum
+                for (int a = 0; a < D; ++a) xr[a] = x[a] - d.shift[a * d.NF + f];
+                recon_eval<D>(d, R, xr, WRg, GR);
+                fr.to_local(WRg, WR);
+                fr.grad_to_local(GR, GRl);
+            } else if (bc == 1) {
+                // mirror: normal momentum reversed; normal derivatives change sign
+                // except that of the normal momentum
 #pragma unroll
-            for (int v = 0; v < nv; ++v) WR[v] = WL[v];
-            WR[1] = -WL[1];
+                for (int v = 0; v < nv; ++v) WR[v] = WL[v];
+                WR[1] = -WL[1];
+#pragma unroll
+                for (int a = 0; a < D; ++a)
+#pragma unroll
+                    for (int v = 0; v < nv; ++v) {
+                        const double sa = (a == 0) ? -1.0 : 1.0;
+                        GRl[a][v] = (v == 1 ? -sa : sa) * GLl[a][v];
+                    }
+            } else {
+                double Wo_g[nv], Wo[nv];
+#pragma unroll
+                for (int v = 0; v < nv; ++v) Wo_g[v] = P.W_inf[v];
+                fr.to_local(Wo_g, Wo);
+                farfield_state<D>(WL, Wo, P.gamma, WR);
+#pragma unroll
+                for (int a = 0; a < D; ++a)
+#pragma unroll
+                    for (int v = 0; v < nv; ++v) GRl[a][v] = 0.0;
+            }
+#pragma unroll
+            for (int v = 0; v < nv; ++v) Wc[v] = 0.0;
+            ok = half_side<D>(WL, P, 1.0, Wc, nullptr) && half_side<D>(WR, P, -1.0, Wc, nullptr);
 #pragma unroll
             for (int a = 0; a < D; ++a)
 #pragma unroll
-                for (int v = 0; v < nv; ++v) {
-                    const double sa = (a == 0) ? -1.0 : 1.0;
-                    GRl[a][v] = (v == 1 ? -sa : sa) * GLl[a][v];
-                }
+                for (int v = 0; v < nv; ++v) Gc[a][v] = 0.5 * (GLl[a][v] + GRl[a][v]);
         } else {
-            double Wo_g[nv], Wo[nv];
+            // no-slip isothermal wall: (p_L / T_w, 0, p_L), interior gradient
+            Prim<D> pq;
+            pq.from(WL, P.gamma);
 #pragma unroll
-            for (int v = 0; v < nv; ++v) Wo_g[v] = P.W_inf[v];
-            fr.to_local(Wo_g, Wo);
-            farfield_state<D>(WL, Wo, P.gamma, WR);
+            for (int v = 0; v < nv; ++v) Wc[v] = 0.0;
+            Wc[0] = pq.p / P.T_wall;
+            Wc[nv - 1] = pq.p / (P.gamma - 1.0);
 #pragma unroll
             for (int a = 0; a < D; ++a)
 #pragma unroll
-                for (int v = 0; v < nv; ++v) GRl[a][v] = 0.0;
+                for (int v = 0; v < nv; ++v) Gc[a][v] = GLl[a][v];
         }
+    }
+    double *dst = d.fsum + size_t(f) * FS;
+    const bool writer = face_ok && q == 0;
+    double o[nv];
+    // Gauss-Green sums of the interface state at t = 0
+    if (want_grad) {
+        fr.to_global(Wc, o);
 #pragma unroll
-        for (int v = 0; v < nv; ++v) Wc[v] = 0.0;
-        ok = half_side<D>(WL, P, 1.0, Wc, nullptr) && half_side<D>(WR, P, -1.0, Wc, nullptr);
+        for (int v = 0; v < nv; ++v) {
+            const double w = ok ? wJ * o[v] : 0.0;
 #pragma unroll
-        for (int a = 0; a < D; ++a)
-#pragma unroll
-            for (int v = 0; v < nv; ++v) Gc[a][v] = 0.5 * (GLl[a][v] + GRl[a][v]);
-    } else {
-        // no-slip isothermal wall: (p_L / T_w, 0, p_L), interior gradient
-        Prim<D> q;
-        q.from(WL, P.gamma);
-#pragma unroll
-        for (int v = 0; v < nv; ++v) Wc[v] = 0.0;
-        Wc[0] = q.p / P.T_wall;
-        Wc[nv - 1] = q.p / (P.gamma - 1.0);
-#pragma unroll
-        for (int a = 0; a < D; ++a)
-#pragma unroll
-            for (int v = 0; v < nv; ++v) Gc[a][v] = GLl[a][v];
+            for (int a = 0; a < D; ++a) {
+                const double sum = group_sum<G>(w * n[a]);
+                if (writer) dst[2 * nv + a * nv + v] = sum;
+            }
+        }
     }
     double F0[nv], Ft[nv], Wt[nv];
     if (ok) ok = gks_flux<D>(Wc, Gc, P, F0, Ft, Wt);
     if (!ok) {
-        atomicOr(d.flag + cs, 1);
+        if (gp_ok) atomicOr(d.flag + cs, 1);
 #pragma unroll
         for (int v = 0; v < nv; ++v) F0[v] = Ft[v] = Wt[v] = 0.0;
     }
@@ -787,19 +836,30 @@ template <int D> __global__ __launch_bounds__(kBlock) void k_flux(Dev d) {
 #pragma unroll
         for (int v = 0; v < nv; ++v) Wt[v] = 0.0;
     }
-    double o[nv];
     fr.to_global(F0, o);
 #pragma unroll
-    for (int v = 0; v < nv; ++v) d.gF0[v * d.NG + g] = wJ * o[v];
+    for (int v = 0; v < nv; ++v) {
+        const double sum = group_sum<G>(wJ * o[v]);
+        if (writer) dst[v] = sum;
+    }
     fr.to_global(Ft, o);
 #pragma unroll
-    for (int v = 0; v < nv; ++v) d.gFt[v * d.NG + g] = wJ * o[v];
-    fr.to_global(Wc, o);
+    for (int v = 0; v < nv; ++v) {
+        const double sum = group_sum<G>(wJ * o[v]);
+        if (writer) dst[nv + v] = sum;
+    }
+    if (want_grad) {
+        fr.to_global(Wt, o);
 #pragma unroll
-    for (int v = 0; v < nv; ++v) d.gWc[v * d.NG + g] = wJ * o[v];
-    fr.to_global(Wt, o);
+        for (int v = 0; v < nv; ++v) {
+            const double w = wJ * o[v];
 #pragma unroll
-    for (int v = 0; v < nv; ++v) d.gWt[v * d.NG + g] = wJ * o[v];
+            for (int a = 0; a < D; ++a) {
+                const double sum = group_sum<G>(w * n[a]);
+                if (writer) dst[2 * nv + D * nv + a * nv + v] = sum;
+            }
+        }
+    }
 }
 
 // ---------------------------------------------------------------------
@@ -812,7 +872,7 @@ template <int D> __global__ __launch_bounds__(kBlock) void k_cell(Dev d, int mod
     constexpr int nv = T::nv;
     const int i = blockIdx.x * kBlock + threadIdx.x;
     if (i >= d.NC) return;
-    const int NC = d.NC, NG = d.NG;
+    const int NC = d.NC;
     const int cs = d.cell_case[i];
     const DevParams &P = d.prm[cs];
     if (!P.active) return;
@@ -823,32 +883,27 @@ template <int D> __global__ __launch_bounds__(kBlock) void k_cell(Dev d, int mod
 #pragma unroll
         for (int a = 0; a < D; ++a) G0s[a][v] = Gts[a][v] = 0.0;
     }
+    const bool want_g = mode != MODE_R1;
 #pragma unroll 1
     for (int s = 0; s < T::ns; ++s) {
-        const int code = d.slot_face[s * NC + i];
+        const int code = d.slot[s * NC + i].x;
         if (code == 0) break;
         const int f = (code > 0 ? code : -code) - 1;
         const double sg = code > 0 ? 1.0 : -1.0;
-        const bool want_g = mode != MODE_R1;
-        for (int g = d.gp_off[f]; g < d.gp_off[f + 1]; ++g) {
-            double n[D];
-            if (want_g) {
+        const double *src = d.fsum + size_t(f) * T::fs;
 #pragma unroll
-                for (int a = 0; a < D; ++a) n[a] = d.gn[a * NG + g];
-            }
+        for (int v = 0; v < nv; ++v) {
+            F0s[v] += sg * src[v];
+            Fts[v] += sg * src[nv + v];
+        }
+        if (want_g) {
 #pragma unroll
-            for (int v = 0; v < nv; ++v) {
-                F0s[v] += sg * d.gF0[v * NG + g];
-                Fts[v] += sg * d.gFt[v * NG + g];
-                if (want_g) {
-                    const double wc = sg * d.gWc[v * NG + g], wt = sg * d.gWt[v * NG + g];
+            for (int a = 0; a < D; ++a)
 #pragma unroll
-                    for (int a = 0; a < D; ++a) {
-                        G0s[a][v] += wc * n[a];
-                        Gts[a][v] += wt * n[a];
-                    }
+                for (int v = 0; v < nv; ++v) {
+                    G0s[a][v] += sg * src[2 * nv + a * nv + v];
+                    Gts[a][v] += sg * src[2 * nv + D * nv + a * nv + v];
                 }
-            }
         }
     }
     const double dt = d.dt[cs];
@@ -888,12 +943,6 @@ template <int D> __global__ __launch_bounds__(kBlock) void k_cell(Dev d, int mod
 // Low level: first-order KFVS face flux, spectral radius, cell setup,
 // multicolour point relaxation, prolongation and the residual norm.
 // ---------------------------------------------------------------------
-template <int D> __device__ __forceinline__ void load_state(const double *U, const double *dU, int i, int NC, double *out) {
-    constexpr int nv = D + 2;
-#pragma unroll
-    for (int v = 0; v < nv; ++v) out[v] = dU ? U[v * NC + i] + dU[v * NC + i] : U[v * NC + i];
-}
-
 template <int D> __device__ __forceinline__ double side_radius(const double *U, const double *n, double Sf, double V,
                                                                const DevParams &P) {
     constexpr int nv = D + 2;
@@ -909,9 +958,36 @@ template <int D> __device__ __forceinline__ double side_radius(const double *U, 
     return fabs(un) + sqrt(P.gamma * p / rho) + 2.0 * P.mu / rho * Sf / V;
 }
 
-// Flow[v][f] = S_f F_kfvs(U_L, U_R; n_f); lam[f] = larger side radius.
-// U_eff = U (+ dU when dU != nullptr).
-template <int D> __global__ __launch_bounds__(kBlock) void k_low_face(Dev d, const double *U, const double *dU) {
+template <int D> __device__ __forceinline__ double state_dt(const double *U, double h, double cfl, const DevParams &P) {
+    constexpr int nv = D + 2;
+    const double rho = U[0];
+    double ke = 0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        const double u = U[1 + a] / rho;
+        ke += u * u;
+    }
+    const double p = (P.gamma - 1.0) * (U[nv - 1] - 0.5 * rho * ke);
+    const double c = sqrt(P.gamma * p / rho);
+    return cfl * h / (sqrt(ke) + c + 2.0 * P.mu / rho / h);
+}
+
+// state of cell i: from the SoA cell averages W (soa = 1) or the cell-major
+// low-level state U (+ dU when dU != nullptr)
+template <int D> __device__ __forceinline__ void low_state(const Dev &d, const double *U, const double *dU, int soa,
+                                                           int i, double *out) {
+    constexpr int nv = D + 2;
+    if (soa) {
+#pragma unroll
+        for (int v = 0; v < nv; ++v) out[v] = U[v * d.NC + i];
+    } else {
+#pragma unroll
+        for (int v = 0; v < nv; ++v) out[v] = dU ? U[i * nv + v] + dU[i * nv + v] : U[i * nv + v];
+    }
+}
+
+// lowf[f] = S_f F_kfvs(U_L, U_R; n_f); swp[f] = (S_f n_f, S_f lam_f).
+template <int D> __global__ __launch_bounds__(kBlock) void k_low_face(Dev d, const double *U, const double *dU, int soa) {
     constexpr int nv = D + 2;
     const int f = blockIdx.x * kBlock + threadIdx.x;
     if (f >= d.NF) return;
@@ -926,12 +1002,12 @@ template <int D> __global__ __launch_bounds__(kBlock) void k_low_face(Dev d, con
     Frame<D> fr;
     fr.build(n);
     double UL[nv], Ul[nv], Ur[nv];
-    load_state<D>(U, dU, L, d.NC, UL);
+    low_state<D>(d, U, dU, soa, L, UL);
     fr.to_local(UL, Ul);
     double lam = side_radius<D>(UL, n, Sf, d.vol[L], P);
     if (R >= 0) {
         double UR[nv];
-        load_state<D>(U, dU, R, d.NC, UR);
+        low_state<D>(d, U, dU, soa, R, UR);
         fr.to_local(UR, Ur);
         lam = fmax(lam, side_radius<D>(UR, n, Sf, d.vol[R], P));
     } else {
@@ -958,8 +1034,11 @@ template <int D> __global__ __launch_bounds__(kBlock) void k_low_face(Dev d, con
     if (!ok) atomicOr(d.flag + cs, 1);
     fr.to_global(Fl, F);
 #pragma unroll
-    for (int v = 0; v < nv; ++v) d.Flow[v * d.NF + f] = ok ? Sf * F[v] : 0.0;
-    d.lam[f] = lam;
+    for (int v = 0; v < nv; ++v) d.lowf[size_t(f) * nv + v] = ok ? Sf * F[v] : 0.0;
+    double *w = d.swp + size_t(f) * 4;
+#pragma unroll
+    for (int a = 0; a < D; ++a) w[a] = d.avec[a * d.NF + f];
+    w[D] = Sf * lam;
 }
 
 enum { LOW_FORCE = 0, LOW_STEP_FIRST = 1, LOW_STEP = 2, LOW_R0_OUT = 3 };
@@ -977,41 +1056,44 @@ template <int D> __global__ __launch_bounds__(kBlock) void k_low_cell(Dev d, int
     for (int v = 0; v < nv; ++v) R0[v] = 0.0;
 #pragma unroll 1
     for (int s = 0; s < T::ns; ++s) {
-        const int code = d.slot_face[s * NC + i];
+        const int code = d.slot[s * NC + i].x;
         if (code == 0) break;
         const int f = (code > 0 ? code : -code) - 1;
         const double sg = code > 0 ? 1.0 : -1.0;
+        const double *lf = d.lowf + size_t(f) * nv;
 #pragma unroll
-        for (int v = 0; v < nv; ++v) R0[v] -= sg * d.Flow[v * d.NF + f];
-        lS += d.lam[f] * d.S[f];
+        for (int v = 0; v < nv; ++v) R0[v] -= sg * lf[v];
+        lS += d.swp[size_t(f) * 4 + D];
     }
     if (mode == LOW_R0_OUT) {
 #pragma unroll
         for (int v = 0; v < nv; ++v) out[v * NC + i] = R0[v];
         return;
     }
+    double *Ui = d.U + size_t(i) * nv, *dUi = d.dU + size_t(i) * nv;
     if (mode == LOW_FORCE) {
 #pragma unroll
         for (int v = 0; v < nv; ++v) {
             d.Sf[v * NC + i] = d.R1[v * NC + i] - R0[v];
-            d.U[v * NC + i] = d.W[v * NC + i];
-            d.dU[v * NC + i] = 0.0;
+            Ui[v] = d.W[v * NC + i];
+            dUi[v] = 0.0;
         }
         return;
     }
-    double Ui[nv];
+    double u[nv];
 #pragma unroll
     for (int v = 0; v < nv; ++v) {
-        Ui[v] = mode == LOW_STEP ? d.U[v * NC + i] + d.dU[v * NC + i] : d.U[v * NC + i];
-        d.U[v * NC + i] = Ui[v];
+        u[v] = mode == LOW_STEP ? Ui[v] + dUi[v] : Ui[v];
+        Ui[v] = u[v];
         d.RHS[v * NC + i] = R0[v] + d.Sf[v * NC + i];
-        d.dU[v * NC + i] = 0.0;
+        dUi[v] = 0.0;
     }
-    const double dti = cell_dt<D>(d.U, i, NC, d.h[i], P.cfl_low, P);
-    d.D[i] = d.vol[i] / dti + 0.5 * lS;
+    d.D[i] = d.vol[i] / state_dt<D>(u, d.h[i], P.cfl_low, P) + 0.5 * lS;
 }
 
-// one colour class: blocks listed in (start, count) tables
+// one colour class: blocks listed in (start, count) tables.  With A = s S_f n_f
+// (outward from i) the delta flux of a neighbour is
+//   S_f [F-(U_m + dU_m) - F-(U_m)] = 1/2 (F_A(U_m + dU_m) - F_A(U_m)) - 1/2 S_f lam_f dU_m.
 template <int D> __global__ __launch_bounds__(kBlock) void k_sweep(Dev d, const int32_t *blk_start,
                                                                    const int32_t *blk_count) {
     using T = Dim<D>;
@@ -1027,29 +1109,31 @@ template <int D> __global__ __launch_bounds__(kBlock) void k_sweep(Dev d, const 
     for (int v = 0; v < nv; ++v) acc[v] = d.RHS[v * NC + i];
 #pragma unroll 1
     for (int s = 0; s < T::ns; ++s) {
-        const int code = d.slot_face[s * NC + i];
-        if (code == 0) break;
-        const int nb = d.slot_nb[s * NC + i];
+        const int2 sl = d.slot[s * NC + i];
+        if (sl.x == 0) break;
+        const int nb = sl.y;
         if (nb < 0) continue;
-        const int f = (code > 0 ? code : -code) - 1;
-        const double sg = code > 0 ? 1.0 : -1.0;
-        const double Sf = d.S[f], iS = 1.0 / Sf, lam = d.lam[f];
-        double n[D], Um[nv], Up[nv], Fa[nv], Fb[nv];
+        const int f = (sl.x > 0 ? sl.x : -sl.x) - 1;
+        const double sg = sl.x > 0 ? 1.0 : -1.0;
+        const double *w = d.swp + size_t(f) * 4;
+        double A[D], Um[nv], dUm[nv], Up[nv], Fa[nv], Fb[nv];
 #pragma unroll
-        for (int a = 0; a < D; ++a) n[a] = sg * d.avec[a * d.NF + f] * iS;
+        for (int a = 0; a < D; ++a) A[a] = sg * w[a];
+        const double sl_lam = w[D];
 #pragma unroll
         for (int v = 0; v < nv; ++v) {
-            Um[v] = d.U[v * NC + nb];
-            Up[v] = Um[v] + d.dU[v * NC + nb];
+            Um[v] = d.U[size_t(nb) * nv + v];
+            dUm[v] = d.dU[size_t(nb) * nv + v];
+            Up[v] = Um[v] + dUm[v];
         }
-        euler_flux<D>(Up, n, P.gamma, Fa);
-        euler_flux<D>(Um, n, P.gamma, Fb);
+        euler_flux<D>(Up, A, P.gamma, Fa);
+        euler_flux<D>(Um, A, P.gamma, Fb);
 #pragma unroll
-        for (int v = 0; v < nv; ++v) acc[v] -= Sf * (0.5 * (Fa[v] - lam * Up[v]) - 0.5 * (Fb[v] - lam * Um[v]));
+        for (int v = 0; v < nv; ++v) acc[v] -= 0.5 * (Fa[v] - Fb[v]) - 0.5 * sl_lam * dUm[v];
     }
-    const double iD = d.D[i];
+    const double Di = d.D[i];
 #pragma unroll
-    for (int v = 0; v < nv; ++v) d.dU[v * NC + i] = acc[v] / iD;
+    for (int v = 0; v < nv; ++v) d.dU[size_t(i) * nv + v] = acc[v] / Di;
 }
 
 // W += (U + dU) - W_p0 (W_p0 = W); partial sums of |rho - rho^n| and rho^n.
@@ -1068,7 +1152,7 @@ template <int D> __global__ __launch_bounds__(kBlock) void k_prolong_res(Dev d, 
         if (prolong && P.active) {
 #pragma unroll
             for (int v = 0; v < nv; ++v) {
-                const double u6 = d.U[v * NC + i] + d.dU[v * NC + i];
+                const double u6 = d.U[size_t(i) * nv + v] + d.dU[size_t(i) * nv + v];
                 const double w = d.W[v * NC + i];
                 d.W[v * NC + i] = w + (u6 - w);
             }
