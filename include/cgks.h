@@ -20,10 +20,11 @@
  *    from host inputs during the call; handles own only host memory.
  *  - Device work is stream ordered; host outputs of *_download calls are
  *    valid when the call returns (they synchronise the stream).
- *  - Arrays of per-cell quantities are structure-of-arrays, variable-major:
- *    W[v][cell] (v = 0..dim+1: rho, rho U_1..rho U_dim, rho E) and
- *    dW[a][v][cell] (a = axis).  Host arrays use the caller's cell order;
- *    device arrays use the library order (cgks_mesh_permutation).
+ *  - Host state arrays are structure-of-arrays, variable-major: W[v][cell]
+ *    (v = 0..dim+1: rho, rho U_1..rho U_dim, rho E) and dW[a][v][cell]
+ *    (a = axis), in the caller's cell order.  Device residual arrays are
+ *    [v][batch cells] in the library order (cgks_mesh_permutation); the
+ *    device state is cell-major (cgks_state_device).
  *  - Handles are not thread safe.  Distinct batches on distinct streams are.
  */
 #ifndef CGKS_H
@@ -155,9 +156,10 @@ cgks_status cgks_batch_destroy(cgks_batch *batch);
 cgks_status cgks_state_upload(cgks_batch *batch, int32_t c, const double *W_host, const double *dW_host,
                               void *stream);
 cgks_status cgks_state_download(cgks_batch *batch, int32_t c, double *W_host, double *dW_host, void *stream);
-/* Device pointers to case c's W [dim+2][n_cell] and dW [dim][dim+2][n_cell]
-   (library order, leading dimension n_cell of that case) and its cell count. */
-cgks_status cgks_state_device(cgks_batch *batch, int32_t c, double **W_dev, double **dW_dev, int64_t *n_cell);
+/* Device pointer to case c's state records: n_cell records (library order)
+   of rec_len = (dim+2)(dim+1) doubles each, W[v] then dW[axis][v].  The
+   records of a batch are contiguous, case after case. */
+cgks_status cgks_state_device(cgks_batch *batch, int32_t c, double **rec, int32_t *rec_len, int64_t *n_cell);
 
 /* One high-order stage on every case, in place (Secs. 2.2-2.4).  stage 0
    first computes the global step dt of each case from W, keeps W^n, and

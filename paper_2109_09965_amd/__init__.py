@@ -97,7 +97,7 @@ def lib():
         L.cgks_batch_destroy.argtypes = [P]
         L.cgks_state_upload.argtypes = [P, i32, P, P, P]
         L.cgks_state_download.argtypes = [P, i32, P, P, P]
-        L.cgks_state_device.argtypes = [P, i32, C.POINTER(P), C.POINTER(P), C.POINTER(C.c_int64)]
+        L.cgks_state_device.argtypes = [P, i32, C.POINTER(P), C.POINTER(C.c_int32), C.POINTER(C.c_int64)]
         L.cgks_highorder_stage.argtypes = [P, i32, P]
         L.cgks_residual.argtypes = [P, i32, P, P]
         L.cgks_lowlevel_smooth.argtypes = [P, P, P]

@@ -47,7 +47,7 @@ struct cgks_batch {
     size_t bytes = 0;
     char *base = nullptr;
     struct {
-        size_t W, dW, Wn, L0, Lt0, G0, coef, vol, h, ctr, sec, minv, slot, cell_case;
+        size_t st, ev, Wn, L0, Lt0, G0, geo, vol, h, minv, slot, cell_case;
         size_t fL, fR, fbc, fcase, gp_off, bslot, avec, S, shift, gavg, bface, gdat;
         size_t gx, gn, gw, fsum;
         size_t U, dU, Sf, RHS, D, R1, lowf, swp;
@@ -73,17 +73,16 @@ void layout(cgks_batch *b) {
     const size_t NC = b->NC, NF = b->NF, NG = b->NG, NB = std::max<int64_t>(b->NB, 1);
     Arena a;
     auto &o = b->o;
-    o.W = a.take<double>(nv * NC);
-    o.dW = a.take<double>(d * nv * NC);
+    const int sr = nv + d * nv, er = d + 1 + nq + nv + nk * nv, gr = d + nq + 1;
+    o.st = a.take<double>(sr * NC);
+    o.ev = a.take<double>(er * NC);
     o.Wn = a.take<double>(nv * NC);
     o.L0 = a.take<double>(nv * NC);
     o.Lt0 = a.take<double>(nv * NC);
     o.G0 = a.take<double>(d * nv * NC);
-    o.coef = a.take<double>(nk * nv * NC);
+    o.geo = a.take<double>(gr * NC);
     o.vol = a.take<double>(NC);
     o.h = a.take<double>(NC);
-    o.ctr = a.take<double>(d * NC);
-    o.sec = a.take<double>(nq * NC);
     o.minv = a.take<double>(nk * (nk + 1) / 2 * NC);
     o.slot = a.take<int2>(ns * NC);
     o.cell_case = a.take<int32_t>(NC);
@@ -150,11 +149,10 @@ void fill_dev(cgks_batch *b) {
     d.NF = int32_t(b->NF);
     d.NG = int32_t(b->NG);
     d.NB = int32_t(std::max<int64_t>(b->NB, 1));
-    d.W = at<double>(b, o.W); d.dW = at<double>(b, o.dW); d.Wn = at<double>(b, o.Wn);
+    d.st = at<double>(b, o.st); d.ev = at<double>(b, o.ev); d.Wn = at<double>(b, o.Wn);
     d.L0 = at<double>(b, o.L0); d.Lt0 = at<double>(b, o.Lt0); d.G0 = at<double>(b, o.G0);
-    d.coef = at<double>(b, o.coef);
-    d.vol = at<double>(b, o.vol); d.h = at<double>(b, o.h); d.ctr = at<double>(b, o.ctr);
-    d.sec = at<double>(b, o.sec); d.minv = at<double>(b, o.minv);
+    d.geo = at<double>(b, o.geo);
+    d.vol = at<double>(b, o.vol); d.h = at<double>(b, o.h); d.minv = at<double>(b, o.minv);
     d.slot = at<int2>(b, o.slot);
     d.cell_case = at<int32_t>(b, o.cell_case);
     d.fL = at<int32_t>(b, o.fL); d.fR = at<int32_t>(b, o.fR); d.fbc = at<int32_t>(b, o.fbc);
@@ -221,14 +219,16 @@ template <int D> cgks_status launch_highorder(cgks_batch *b, int mode, hipStream
     }
     timed(b, CGKS_K_RECON, s, [&] {
         if (b->NB > 0) hipLaunchKernelGGL(k_ghost<D>, dim3(nblk(b->NB)), dim3(kBlock), 0, s, d);
-        hipLaunchKernelGGL(k_recon<D>, dim3(nblk(b->NC)), dim3(kBlock), 0, s, d);
+        hipLaunchKernelGGL(k_recon<D>, dim3(unsigned((b->NC + kReconBlock - 1) / kReconBlock)), dim3(kReconBlock),
+                           0, s, d);
     });
     timed(b, CGKS_K_FLUX, s, [&] {
         hipLaunchKernelGGL(k_flux<D>, dim3(nblk(b->NF * Dim<D>::lanes)), dim3(kBlock), 0, s, d,
                            (int)(mode != MODE_R1));
     });
-    timed(b, CGKS_K_CELL, s,
-          [&] { hipLaunchKernelGGL(k_cell<D>, dim3(nblk(b->NC)), dim3(kBlock), 0, s, d, mode); });
+    timed(b, CGKS_K_CELL, s, [&] {
+        hipLaunchKernelGGL(k_cell<D>, dim3(nblk(b->NC * Dim<D>::sl)), dim3(kBlock), 0, s, d, mode);
+    });
     HIP_TRY(hipGetLastError());
     return CGKS_OK;
 }
@@ -252,11 +252,11 @@ template <int D> cgks_status launch_lowlevel(cgks_batch *b, const double *R1, hi
     if (R1 != d.R1)
         HIP_TRY(hipMemcpyAsync(d.R1, R1, sizeof(double) * (D + 2) * b->NC, hipMemcpyDeviceToDevice, s));
     timed(b, CGKS_K_LOWFACE, s, [&] {
-        hipLaunchKernelGGL(k_low_face<D>, dim3(nblk(b->NF)), dim3(kBlock), 0, s, d, (const double *)d.W,
+        hipLaunchKernelGGL(k_low_face<D>, dim3(nblk(b->NF)), dim3(kBlock), 0, s, d, (const double *)d.st,
                            (const double *)nullptr, 1);
     });
     timed(b, CGKS_K_LOWCELL, s, [&] {
-        hipLaunchKernelGGL(k_low_cell<D>, dim3(nblk(b->NC)), dim3(kBlock), 0, s, d, (int)LOW_FORCE,
+        hipLaunchKernelGGL(k_low_cell<D>, dim3(nblk(b->NC * Dim<D>::sl)), dim3(kBlock), 0, s, d, (int)LOW_FORCE,
                            (double *)nullptr);
     });
     const std::vector<int> order = sweep_order(b->max_colour, b->n_sweeps);
@@ -266,7 +266,7 @@ template <int D> cgks_status launch_lowlevel(cgks_batch *b, const double *R1, hi
                                (const double *)(k ? d.dU : nullptr), 0);
         });
         timed(b, CGKS_K_LOWCELL, s, [&] {
-            hipLaunchKernelGGL(k_low_cell<D>, dim3(nblk(b->NC)), dim3(kBlock), 0, s, d,
+            hipLaunchKernelGGL(k_low_cell<D>, dim3(nblk(b->NC * Dim<D>::sl)), dim3(kBlock), 0, s, d,
                                (int)(k ? LOW_STEP : LOW_STEP_FIRST), (double *)nullptr);
         });
         for (int c : order) {
@@ -433,9 +433,10 @@ cgks_status cgks_batch_create(const cgks_mesh *const *meshes, const cgks_params 
                 int64_t start = b->cell_off[c];
                 for (int k = 0; k < col; ++k) start += m.colour_count[k];
                 const int64_t n = m.colour_count[col];
-                for (int64_t q = 0; q < n; q += kBlock) {
+                const int64_t chunk = kBlock / 4;   // Dim<D>::sl lanes per cell
+                for (int64_t q = 0; q < n; q += chunk) {
                     b->cb_start.push_back(int32_t(start + q));
-                    b->cb_count.push_back(int32_t(std::min<int64_t>(kBlock, n - q)));
+                    b->cb_count.push_back(int32_t(std::min<int64_t>(chunk, n - q)));
                 }
             }
             b->colour_blk_off[col + 1] = b->cb_start.size();
@@ -475,7 +476,8 @@ cgks_status cgks_batch_bind(cgks_batch *b, void *buf, size_t bytes, void *stream
     const int nsym = nk * (nk + 1) / 2;
     const size_t NC = b->NC, NF = b->NF, NG = b->NG, NB = std::max<int64_t>(b->NB, 1);
     try {
-        std::vector<double> vol(NC), h(NC), ctr(d * NC), sec(nq * NC), minv(nsym * NC);
+        const int gr = d + nq + 1;
+        std::vector<double> vol(NC), h(NC), geo(gr * NC), minv(nsym * NC);
         std::vector<int2> slot(ns * NC, make_int2(0, -1));
         std::vector<int32_t> cell_case(NC);
         std::vector<int32_t> fL(NF), fR(NF), fbc(NF), fcase(NF), gp_off(NF + 1), bslot(NF, -1);
@@ -492,8 +494,9 @@ cgks_status cgks_batch_bind(cgks_batch *b, void *buf, size_t bytes, void *stream
                 vol[I] = m.vol[i];
                 h[I] = m.h[i];
                 cell_case[I] = c;
-                for (int a = 0; a < d; ++a) ctr[a * NC + I] = m.ctr[i * d + a];
-                for (int q = 0; q < nq; ++q) sec[q * NC + I] = m.sec[i * nq + q];
+                for (int a = 0; a < d; ++a) geo[I * gr + a] = m.ctr[i * d + a];
+                for (int q = 0; q < nq; ++q) geo[I * gr + d + q] = m.sec[i * nq + q];
+                geo[I * gr + d + nq] = m.h[i];
                 int k = 0;
                 for (int r = 0; r < nk; ++r)
                     for (int t = r; t < nk; ++t) minv[(k++) * NC + I] = m.minv[i * nk * nk + r * nk + t];
@@ -538,8 +541,8 @@ cgks_status cgks_batch_bind(cgks_batch *b, void *buf, size_t bytes, void *stream
         std::vector<int32_t> zero_flag(b->n_case, 0);
         std::vector<double> zero_case(b->n_case, 0.0);
         auto &o = b->o;
-        HIP_TRY(put(b, o.vol, vol, s)); HIP_TRY(put(b, o.h, h, s)); HIP_TRY(put(b, o.ctr, ctr, s));
-        HIP_TRY(put(b, o.sec, sec, s)); HIP_TRY(put(b, o.minv, minv, s));
+        HIP_TRY(put(b, o.vol, vol, s)); HIP_TRY(put(b, o.h, h, s)); HIP_TRY(put(b, o.geo, geo, s));
+        HIP_TRY(put(b, o.minv, minv, s));
         HIP_TRY(put(b, o.slot, slot, s));
         HIP_TRY(put(b, o.cell_case, cell_case, s));
         HIP_TRY(put(b, o.fL, fL, s)); HIP_TRY(put(b, o.fR, fR, s)); HIP_TRY(put(b, o.fbc, fbc, s));
@@ -554,7 +557,7 @@ cgks_status cgks_batch_bind(cgks_batch *b, void *buf, size_t bytes, void *stream
         HIP_TRY(put(b, o.rb_case, b->rb_case, s)); HIP_TRY(put(b, o.case_rb_off, b->case_rb_off, s));
         HIP_TRY(put(b, o.cb_start, b->cb_start, s)); HIP_TRY(put(b, o.cb_count, b->cb_count, s));
         // zero state and work arrays so that a cycle never reads garbage
-        HIP_TRY(hipMemsetAsync(b->base + o.W, 0, o.vol - o.W, s));
+        HIP_TRY(hipMemsetAsync(b->base + o.st, 0, o.geo - o.st, s));
         HIP_TRY(hipMemsetAsync(b->base + o.U, 0, o.prm - o.U, s));
         HIP_TRY(hipStreamSynchronize(s));
     } catch (const std::bad_alloc &) {
@@ -572,27 +575,30 @@ static cgks_status state_xfer(cgks_batch *b, int32_t c, double *W, double *dW, v
     if (!b || !b->base || c < 0 || c >= b->n_case || (up && !W)) return CGKS_EINVAL;
     hipStream_t s = static_cast<hipStream_t>(stream);
     const HostMesh &m = b->meshes[c]->hm;
-    const int d = b->dim, nv = d + 2;
-    const int64_t n = m.n_cell, NC = b->NC, co = b->cell_off[c];
-    std::vector<double> buf(n);
-    auto rows = [&](double *dev_rows, double *host, int nrow) -> cgks_status {
-        for (int r = 0; r < nrow; ++r) {
-            double *dp = dev_rows + r * NC + co;
-            if (up) {
-                for (int64_t l = 0; l < n; ++l) buf[l] = host ? host[r * n + m.lib2caller[l]] : 0.0;
-                HIP_TRY(hipMemcpyAsync(dp, buf.data(), n * sizeof(double), hipMemcpyHostToDevice, s));
-                HIP_TRY(hipStreamSynchronize(s));
-            } else if (host) {
-                HIP_TRY(hipMemcpyAsync(buf.data(), dp, n * sizeof(double), hipMemcpyDeviceToHost, s));
-                HIP_TRY(hipStreamSynchronize(s));
-                for (int64_t l = 0; l < n; ++l) host[r * n + m.lib2caller[l]] = buf[l];
-            }
+    const int d = b->dim, nv = d + 2, sr = nv + d * nv;
+    const int64_t n = m.n_cell, co = b->cell_off[c];
+    std::vector<double> buf(size_t(n) * sr);
+    double *dev = b->dev.st + size_t(co) * sr;
+    if (up) {
+        for (int64_t l = 0; l < n; ++l) {
+            const int64_t i = m.lib2caller[l];
+            for (int r = 0; r < nv; ++r) buf[l * sr + r] = W[r * n + i];
+            for (int r = 0; r < d * nv; ++r) buf[l * sr + nv + r] = dW ? dW[r * n + i] : 0.0;
         }
+        HIP_TRY(hipMemcpyAsync(dev, buf.data(), buf.size() * sizeof(double), hipMemcpyHostToDevice, s));
+        HIP_TRY(hipStreamSynchronize(s));
         return CGKS_OK;
-    };
-    cgks_status st = rows(b->dev.W, W, nv);
-    if (st) return st;
-    return rows(b->dev.dW, dW, d * nv);
+    }
+    HIP_TRY(hipMemcpyAsync(buf.data(), dev, buf.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    for (int64_t l = 0; l < n; ++l) {
+        const int64_t i = m.lib2caller[l];
+        if (W)
+            for (int r = 0; r < nv; ++r) W[r * n + i] = buf[l * sr + r];
+        if (dW)
+            for (int r = 0; r < d * nv; ++r) dW[r * n + i] = buf[l * sr + nv + r];
+    }
+    return CGKS_OK;
 }
 
 cgks_status cgks_state_upload(cgks_batch *b, int32_t c, const double *W, const double *dW, void *stream) {
@@ -603,10 +609,11 @@ cgks_status cgks_state_download(cgks_batch *b, int32_t c, double *W, double *dW,
     return state_xfer(b, c, W, dW, stream, false);
 }
 
-cgks_status cgks_state_device(cgks_batch *b, int32_t c, double **W, double **dW, int64_t *n_cell) {
+cgks_status cgks_state_device(cgks_batch *b, int32_t c, double **rec, int32_t *rec_len, int64_t *n_cell) {
     if (!b || !b->base || c < 0 || c >= b->n_case) return CGKS_EINVAL;
-    if (W) *W = b->dev.W + b->cell_off[c];
-    if (dW) *dW = b->dev.dW + b->cell_off[c];
+    const int nv = b->dim + 2, sr = nv + b->dim * nv;
+    if (rec) *rec = b->dev.st + size_t(b->cell_off[c]) * sr;
+    if (rec_len) *rec_len = sr;
     if (n_cell) *n_cell = b->meshes[c]->hm.n_cell;
     return CGKS_OK;
 }
@@ -630,13 +637,15 @@ cgks_status cgks_residual(cgks_batch *b, int32_t kind, double *out, void *stream
     }
     if (kind == CGKS_RESIDUAL_LOW) {
         if (b->dim == 2) {
-            hipLaunchKernelGGL(k_low_face<2>, dim3(nblk(b->NF)), dim3(kBlock), 0, s, b->dev, (const double *)b->dev.W,
+            hipLaunchKernelGGL(k_low_face<2>, dim3(nblk(b->NF)), dim3(kBlock), 0, s, b->dev, (const double *)b->dev.st,
                                (const double *)nullptr, 1);
-            hipLaunchKernelGGL(k_low_cell<2>, dim3(nblk(b->NC)), dim3(kBlock), 0, s, b->dev, (int)LOW_R0_OUT, out);
+            hipLaunchKernelGGL(k_low_cell<2>, dim3(nblk(b->NC * Dim<2>::sl)), dim3(kBlock), 0, s, b->dev,
+                               (int)LOW_R0_OUT, out);
         } else {
-            hipLaunchKernelGGL(k_low_face<3>, dim3(nblk(b->NF)), dim3(kBlock), 0, s, b->dev, (const double *)b->dev.W,
+            hipLaunchKernelGGL(k_low_face<3>, dim3(nblk(b->NF)), dim3(kBlock), 0, s, b->dev, (const double *)b->dev.st,
                                (const double *)nullptr, 1);
-            hipLaunchKernelGGL(k_low_cell<3>, dim3(nblk(b->NC)), dim3(kBlock), 0, s, b->dev, (int)LOW_R0_OUT, out);
+            hipLaunchKernelGGL(k_low_cell<3>, dim3(nblk(b->NC * Dim<3>::sl)), dim3(kBlock), 0, s, b->dev,
+                               (int)LOW_R0_OUT, out);
         }
         HIP_TRY(hipGetLastError());
         return CGKS_OK;

@@ -31,9 +31,13 @@ struct DevParams {
 struct Dev {
     int32_t NC, NF, NG, NB;   // NB >= 1 (array extent); NB_real boundary faces
     int32_t NB_real;
-    // cells
-    double *W, *dW, *Wn, *L0, *Lt0, *G0, *coef;
-    const double *vol, *h, *ctr, *sec, *minv;
+    // cells: cell-major records (Rec<D>) for everything gathered from
+    // neighbours, SoA [component][NC] for what only the cell itself reads
+    double *st;               // [NC][sr]: W (nv), grad W [axis][v]
+    const double *geo;        // [NC][gr]: centroid (D), central second moments (nq), h
+    double *ev;               // [NC][er]: centroid, 1/h, <phi_quad>, W, coefficients [k][v]
+    double *Wn, *L0, *Lt0, *G0;
+    const double *vol, *h, *minv;
     const int2 *slot;         // [ns][NC]: (x) face code +-(f + 1), 0 = none; (y) neighbour cell or -1
     const int32_t *cell_case;
     // faces
@@ -57,6 +61,18 @@ struct Dev {
     double *part0, *part1;
 };
 
+template <int D> struct Dim;
+
+// record layouts of the cell-major arrays
+template <int D> struct Rec {
+    static constexpr int nv = D + 2, nk = D == 2 ? 5 : 9, nq = D == 2 ? 3 : 6;
+    static constexpr int sr = nv + D * nv;            // W, grad W
+    static constexpr int gr = D + nq + 1;             // centroid, second moments, h
+    static constexpr int OW = D + 1 + nq;             // offset of W in the evaluation record
+    static constexpr int OC = OW + nv;                // offset of the coefficients
+    static constexpr int er = OC + nk * nv;
+};
+
 template <int D> struct Dim {
     static constexpr int nv = D + 2;
     static constexpr int nk = D == 2 ? 5 : 9;
@@ -64,6 +80,7 @@ template <int D> struct Dim {
     static constexpr int ns = D == 2 ? 4 : 8;   // slots per cell
     static constexpr int nsym = nk * (nk + 1) / 2;
     static constexpr int lanes = D == 2 ? 2 : 4;   // threads per face (one per Gauss point)
+    static constexpr int sl = 4;                   // threads per cell in the slot gathers
     static constexpr int fs = 2 * nv + 2 * D * nv; // face sums per face
 };
 
@@ -413,17 +430,16 @@ template <int D> __device__ __forceinline__ void euler_flux(const double *U, con
 // ---------------------------------------------------------------------
 // Global time step: per-block minimum over a case's cells, then per case.
 // ---------------------------------------------------------------------
-template <int D> __device__ __forceinline__ double cell_dt(const double *W, int i, int NC, double h, double cfl,
-                                                           const DevParams &P) {
+template <int D> __device__ __forceinline__ double state_dt(const double *U, double h, double cfl, const DevParams &P) {
     constexpr int nv = D + 2;
-    const double rho = W[i];
+    const double rho = U[0];
     double ke = 0;
 #pragma unroll
     for (int a = 0; a < D; ++a) {
-        const double u = W[(1 + a) * NC + i] / rho;
+        const double u = U[1 + a] / rho;
         ke += u * u;
     }
-    const double p = (P.gamma - 1.0) * (W[(nv - 1) * NC + i] - 0.5 * rho * ke);
+    const double p = (P.gamma - 1.0) * (U[nv - 1] - 0.5 * rho * ke);
     const double c = sqrt(P.gamma * p / rho);
     return cfl * h / (sqrt(ke) + c + 2.0 * P.mu / rho / h);
 }
@@ -462,7 +478,7 @@ template <int D> __global__ __launch_bounds__(kBlock) void k_dt_partial(Dev d) {
     double v = INFINITY;
     for (int k = threadIdx.x; k < n; k += kBlock) {
         const int i = d.rb_start[b] + k;
-        v = fmin(v, cell_dt<D>(d.W, i, d.NC, d.h[i], P.cfl_high, P));
+        v = fmin(v, state_dt<D>(d.st + size_t(i) * Rec<D>::sr, d.h[i], P.cfl_high, P));
     }
     v = block_reduce_min(v, sh);
     if (threadIdx.x == 0) d.part0[b] = v;
@@ -555,12 +571,14 @@ template <int D> __global__ __launch_bounds__(kBlock) void k_ghost(Dev d) {
     const int NC = d.NC;
     const DevParams &P = d.prm[d.fcase[f]];
     double Wi[nv], Gi[D][nv], Wg[nv], Gg[D][nv], n[D];
+    const double *si = d.st + size_t(i) * Rec<D>::sr;
 #pragma unroll
-    for (int v = 0; v < nv; ++v) Wi[v] = d.W[v * NC + i];
+    for (int v = 0; v < nv; ++v) Wi[v] = si[v];
 #pragma unroll
     for (int a = 0; a < D; ++a)
 #pragma unroll
-        for (int v = 0; v < nv; ++v) Gi[a][v] = d.dW[(a * nv + v) * NC + i];
+        for (int v = 0; v < nv; ++v) Gi[a][v] = si[nv + a * nv + v];
+    (void)NC;
     const double iS = 1.0 / d.S[f];
 #pragma unroll
     for (int a = 0; a < D; ++a) n[a] = d.avec[a * d.NF + f] * iS;
@@ -574,29 +592,39 @@ template <int D> __global__ __launch_bounds__(kBlock) void k_ghost(Dev d) {
         for (int v = 0; v < nv; ++v) o[nv + a * nv + v] = Gg[a][v];
 }
 
-// One thread per cell, all conservative variables: c = Minv M^T b.
-template <int D> __global__ __launch_bounds__(kBlock) void k_recon(Dev d) {
+// One thread per cell, all conservative variables: c = Minv M^T b.  The
+// evaluation records of the block's cells are assembled in LDS and written
+// out as one contiguous, coalesced range.
+constexpr int kReconBlock = 64;
+template <int D> __global__ __launch_bounds__(kReconBlock) void k_recon(Dev d) {
     using T = Dim<D>;
     constexpr int nv = T::nv, nk = T::nk, nq = T::nq;
-    const int i = blockIdx.x * kBlock + threadIdx.x;
-    if (i >= d.NC) return;
+    constexpr int ERP = Rec<D>::er + 1;   // padded LDS row
+    __shared__ double rec_lds[kReconBlock * ERP];
+    const int i0 = blockIdx.x * kReconBlock;
+    const int i = i0 + threadIdx.x;
     const int NC = d.NC;
-    const double h = d.h[i], ih = 1.0 / h;
+    const int ncell = min(kReconBlock, NC - i0);
+    if (i < NC) {
+    using RC = Rec<D>;
+    const double *gi = d.geo + size_t(i) * RC::gr;
+    const double *si = d.st + size_t(i) * RC::sr;
+    const double h = gi[D + nq], ih = 1.0 / h;
     double xc[D], own[nq], Wi[nv];
     double rhs[nk][nv];
     // own-gradient rows first: they only touch the linear coefficients
 #pragma unroll
     for (int v = 0; v < nv; ++v) {
-        Wi[v] = d.W[v * NC + i];
+        Wi[v] = si[v];
 #pragma unroll
-        for (int a = 0; a < D; ++a) rhs[a][v] = h * d.dW[(a * nv + v) * NC + i];
+        for (int a = 0; a < D; ++a) rhs[a][v] = h * si[nv + a * nv + v];
 #pragma unroll
         for (int q = 0; q < nq; ++q) rhs[D + q][v] = 0.0;
     }
 #pragma unroll
-    for (int a = 0; a < D; ++a) xc[a] = d.ctr[a * NC + i];
+    for (int a = 0; a < D; ++a) xc[a] = gi[a];
 #pragma unroll
-    for (int q = 0; q < nq; ++q) own[q] = d.sec[sidx<D>(qa<D>(q), qb<D>(q)) * NC + i] * ih * ih;
+    for (int q = 0; q < nq; ++q) own[q] = gi[D + sidx<D>(qa<D>(q), qb<D>(q))] * ih * ih;
 #pragma unroll 1
     for (int s = 0; s < T::ns; ++s) {
         const int2 sl = d.slot[s * NC + i];
@@ -605,20 +633,22 @@ template <int D> __global__ __launch_bounds__(kBlock) void k_recon(Dev d) {
         const int f = (code > 0 ? code : -code) - 1;
         const int nb = sl.y;
         double avg[nk];
-        const double *gd = nullptr;
+        const double *gd;
         if (nb >= 0) {
             const double sg = code > 0 ? 1.0 : -1.0;
+            const double *gm = d.geo + size_t(nb) * RC::gr;
             double dx[D];
 #pragma unroll
             for (int a = 0; a < D; ++a) {
-                dx[a] = d.ctr[a * NC + nb] + sg * d.shift[a * d.NF + f] - xc[a];
+                dx[a] = gm[a] + sg * d.shift[a * d.NF + f] - xc[a];
                 avg[a] = dx[a] * ih;
             }
 #pragma unroll
             for (int q = 0; q < nq; ++q) {
                 const int a = qa<D>(q), b = qb<D>(q);
-                avg[D + q] = (d.sec[sidx<D>(a, b) * NC + nb] + dx[a] * dx[b]) * ih * ih;
+                avg[D + q] = (gm[D + sidx<D>(a, b)] + dx[a] * dx[b]) * ih * ih;
             }
+            gd = d.st + size_t(nb) * RC::sr;
         } else {
             const int bs = d.bslot[f];
 #pragma unroll
@@ -628,7 +658,7 @@ template <int D> __global__ __launch_bounds__(kBlock) void k_recon(Dev d) {
 #pragma unroll
         for (int v = 0; v < nv; ++v) {
             // average row
-            const double bv = (gd ? gd[v] : d.W[v * NC + nb]) - Wi[v];
+            const double bv = gd[v] - Wi[v];
 #pragma unroll
             for (int a = 0; a < D; ++a) rhs[a][v] += avg[a] * bv;
 #pragma unroll
@@ -636,7 +666,7 @@ template <int D> __global__ __launch_bounds__(kBlock) void k_recon(Dev d) {
             // gradient rows
 #pragma unroll
             for (int a = 0; a < D; ++a) {
-                const double bg = h * (gd ? gd[nv + a * nv + v] : d.dW[(a * nv + v) * NC + nb]);
+                const double bg = h * gd[nv + a * nv + v];
                 rhs[a][v] += bg;
 #pragma unroll
                 for (int q = 0; q < nq; ++q) {
@@ -647,7 +677,15 @@ template <int D> __global__ __launch_bounds__(kBlock) void k_recon(Dev d) {
             }
         }
     }
-    // c = Minv rhs
+    // evaluation record: centroid, 1/h, <phi_quad>_i, W, c = Minv rhs
+    double *e = rec_lds + threadIdx.x * ERP;
+#pragma unroll
+    for (int a = 0; a < D; ++a) e[a] = xc[a];
+    e[D] = ih;
+#pragma unroll
+    for (int q = 0; q < nq; ++q) e[D + 1 + q] = own[q];
+#pragma unroll
+    for (int v = 0; v < nv; ++v) e[RC::OW + v] = Wi[v];
 #pragma unroll
     for (int k = 0; k < nk; ++k) {
         double c[nv];
@@ -660,44 +698,63 @@ template <int D> __global__ __launch_bounds__(kBlock) void k_recon(Dev d) {
             for (int v = 0; v < nv; ++v) c[v] += mkj * rhs[j][v];
         }
 #pragma unroll
-        for (int v = 0; v < nv; ++v) d.coef[(k * nv + v) * NC + i] = c[v];
+        for (int v = 0; v < nv; ++v) e[RC::OC + k * nv + v] = c[v];
+    }
+    }
+    __syncthreads();
+    double *dst = d.ev + size_t(i0) * Rec<D>::er;
+    const int total = ncell * Rec<D>::er;
+    for (int k = threadIdx.x; k < total; k += kReconBlock) {
+        const int c = k / Rec<D>::er, j = k - c * Rec<D>::er;
+        dst[k] = rec_lds[c * ERP + j];
     }
 }
 
-// value and gradient of P_i at x (x in cell i's frame)
+// value and gradient of P_i at x (x in cell i's frame), from the cell's
+// evaluation record (read with 16-byte loads)
 template <int D> __device__ __forceinline__ void recon_eval(const Dev &d, int i, const double *x, double *Wx,
                                                             double G[D][D + 2]) {
     using T = Dim<D>;
+    using RC = Rec<D>;
     constexpr int nv = T::nv, nq = T::nq;
-    const int NC = d.NC;
-    const double h = d.h[i], ih = 1.0 / h;
+    const double2 *r2 = reinterpret_cast<const double2 *>(d.ev + size_t(i) * RC::er);
+    double r[RC::OC];
+#pragma unroll
+    for (int k = 0; k < RC::OC / 2; ++k) {
+        const double2 t = r2[k];
+        r[2 * k] = t.x;
+        r[2 * k + 1] = t.y;
+    }
+    if constexpr (RC::OC % 2) r[RC::OC - 1] = d.ev[size_t(i) * RC::er + RC::OC - 1];
+    const double ih = r[D];
     double y[D];
 #pragma unroll
-    for (int a = 0; a < D; ++a) y[a] = (x[a] - d.ctr[a * NC + i]) * ih;
+    for (int a = 0; a < D; ++a) y[a] = (x[a] - r[a]) * ih;
 #pragma unroll
     for (int v = 0; v < nv; ++v) {
-        Wx[v] = d.W[v * NC + i];
+        Wx[v] = r[RC::OW + v];
 #pragma unroll
         for (int a = 0; a < D; ++a) G[a][v] = 0.0;
     }
+    const double *c = d.ev + size_t(i) * RC::er + RC::OC;
 #pragma unroll
     for (int a = 0; a < D; ++a)
 #pragma unroll
         for (int v = 0; v < nv; ++v) {
-            const double c = d.coef[(a * nv + v) * NC + i];
-            Wx[v] += c * y[a];
-            G[a][v] += c;
+            const double ck = c[a * nv + v];
+            Wx[v] += ck * y[a];
+            G[a][v] += ck;
         }
 #pragma unroll
     for (int q = 0; q < nq; ++q) {
         const int a = qa<D>(q), b = qb<D>(q);
-        const double phi = y[a] * y[b] - d.sec[sidx<D>(a, b) * NC + i] * ih * ih;
+        const double phi = y[a] * y[b] - r[D + 1 + q];
 #pragma unroll
         for (int v = 0; v < nv; ++v) {
-            const double c = d.coef[((D + q) * nv + v) * NC + i];
-            Wx[v] += c * phi;
-            G[a][v] += c * y[b];
-            G[b][v] += c * y[a];
+            const double ck = c[(D + q) * nv + v];
+            Wx[v] += ck * phi;
+            G[a][v] += ck * y[b];
+            G[b][v] += ck * y[a];
         }
     }
 #pragma unroll
@@ -867,15 +924,19 @@ template <int D> __global__ __launch_bounds__(kBlock) void k_flux(Dev d, int wan
 // ---------------------------------------------------------------------
 enum { MODE_STAGE0 = 0, MODE_STAGE1 = 1, MODE_R1 = 2 };
 
+// Dim<D>::sl lanes per cell: lane q gathers slots q, q + sl, ...; the sums
+// are reduced across the group and lane q then owns variables q, q + sl.
 template <int D> __global__ __launch_bounds__(kBlock) void k_cell(Dev d, int mode) {
     using T = Dim<D>;
-    constexpr int nv = T::nv;
-    const int i = blockIdx.x * kBlock + threadIdx.x;
-    if (i >= d.NC) return;
+    constexpr int nv = T::nv, SL = T::sl;
+    const int t = blockIdx.x * kBlock + threadIdx.x;
+    const int ir = t / SL, q = t % SL;
+    const bool ok = ir < d.NC;
+    const int i = ok ? ir : d.NC - 1;
     const int NC = d.NC;
     const int cs = d.cell_case[i];
     const DevParams &P = d.prm[cs];
-    if (!P.active) return;
+    const bool want_g = mode != MODE_R1;
     double F0s[nv], Fts[nv], G0s[D][nv], Gts[D][nv];
 #pragma unroll
     for (int v = 0; v < nv; ++v) {
@@ -883,47 +944,63 @@ template <int D> __global__ __launch_bounds__(kBlock) void k_cell(Dev d, int mod
 #pragma unroll
         for (int a = 0; a < D; ++a) G0s[a][v] = Gts[a][v] = 0.0;
     }
-    const bool want_g = mode != MODE_R1;
-#pragma unroll 1
-    for (int s = 0; s < T::ns; ++s) {
+#pragma unroll
+    for (int s = q; s < T::ns; s += SL) {
         const int code = d.slot[s * NC + i].x;
-        if (code == 0) break;
-        const int f = (code > 0 ? code : -code) - 1;
-        const double sg = code > 0 ? 1.0 : -1.0;
-        const double *src = d.fsum + size_t(f) * T::fs;
+        if (code != 0) {
+            const int f = (code > 0 ? code : -code) - 1;
+            const double sg = code > 0 ? 1.0 : -1.0;
+            const double *src = d.fsum + size_t(f) * T::fs;
 #pragma unroll
-        for (int v = 0; v < nv; ++v) {
-            F0s[v] += sg * src[v];
-            Fts[v] += sg * src[nv + v];
-        }
-        if (want_g) {
+            for (int v = 0; v < nv; ++v) {
+                F0s[v] += sg * src[v];
+                Fts[v] += sg * src[nv + v];
+            }
+            if (want_g) {
 #pragma unroll
-            for (int a = 0; a < D; ++a)
+                for (int a = 0; a < D; ++a)
 #pragma unroll
-                for (int v = 0; v < nv; ++v) {
-                    G0s[a][v] += sg * src[2 * nv + a * nv + v];
-                    Gts[a][v] += sg * src[2 * nv + D * nv + a * nv + v];
-                }
+                    for (int v = 0; v < nv; ++v) {
+                        G0s[a][v] += sg * src[2 * nv + a * nv + v];
+                        Gts[a][v] += sg * src[2 * nv + D * nv + a * nv + v];
+                    }
+            }
         }
     }
+#pragma unroll
+    for (int v = 0; v < nv; ++v) {
+        F0s[v] = group_sum<SL>(F0s[v]);
+        Fts[v] = group_sum<SL>(Fts[v]);
+    }
+    if (want_g) {
+#pragma unroll
+        for (int a = 0; a < D; ++a)
+#pragma unroll
+            for (int v = 0; v < nv; ++v) {
+                G0s[a][v] = group_sum<SL>(G0s[a][v]);
+                Gts[a][v] = group_sum<SL>(Gts[a][v]);
+            }
+    }
+    if (!ok || !P.active) return;
     const double dt = d.dt[cs];
-    if (mode == MODE_R1) {
-#pragma unroll
-        for (int v = 0; v < nv; ++v) d.R1[v * NC + i] = -(F0s[v] + 0.5 * dt * Fts[v]);
-        return;
-    }
     const double V = d.vol[i];
 #pragma unroll
     for (int v = 0; v < nv; ++v) {
+        if (v % SL != q) continue;
+        if (mode == MODE_R1) {
+            d.R1[v * NC + i] = -(F0s[v] + 0.5 * dt * Fts[v]);
+            continue;
+        }
         const double L = -F0s[v] / V, Lt = -Fts[v] / V;
+        double *si = d.st + size_t(i) * Rec<D>::sr;
         if (mode == MODE_STAGE0) {
-            const double w = d.W[v * NC + i];
+            const double w = si[v];
             d.Wn[v * NC + i] = w;
             d.L0[v * NC + i] = L;
             d.Lt0[v * NC + i] = Lt;
-            d.W[v * NC + i] = P.scheme == 0 ? w + 0.5 * dt * L + 0.125 * dt * dt * Lt : w + dt * L + 0.5 * dt * dt * Lt;
+            si[v] = P.scheme == 0 ? w + 0.5 * dt * L + 0.125 * dt * dt * Lt : w + dt * L + 0.5 * dt * dt * Lt;
         } else {
-            d.W[v * NC + i] = d.Wn[v * NC + i] + dt * d.L0[v * NC + i] + dt * dt / 6.0 * (d.Lt0[v * NC + i] + 2.0 * Lt);
+            si[v] = d.Wn[v * NC + i] + dt * d.L0[v * NC + i] + dt * dt / 6.0 * (d.Lt0[v * NC + i] + 2.0 * Lt);
         }
 #pragma unroll
         for (int a = 0; a < D; ++a) {
@@ -931,9 +1008,9 @@ template <int D> __global__ __launch_bounds__(kBlock) void k_cell(Dev d, int mod
             const double G = G0s[a][v] / V, Gt = Gts[a][v] / V;
             if (mode == MODE_STAGE0) {
                 d.G0[k] = G;
-                d.dW[k] = P.scheme == 0 ? G + 0.5 * dt * Gt : G + dt * Gt;
+                si[nv + a * nv + v] = P.scheme == 0 ? G + 0.5 * dt * Gt : G + dt * Gt;
             } else {
-                d.dW[k] = d.G0[k] + dt * Gt;
+                si[nv + a * nv + v] = d.G0[k] + dt * Gt;
             }
         }
     }
@@ -958,28 +1035,14 @@ template <int D> __device__ __forceinline__ double side_radius(const double *U, 
     return fabs(un) + sqrt(P.gamma * p / rho) + 2.0 * P.mu / rho * Sf / V;
 }
 
-template <int D> __device__ __forceinline__ double state_dt(const double *U, double h, double cfl, const DevParams &P) {
-    constexpr int nv = D + 2;
-    const double rho = U[0];
-    double ke = 0;
-#pragma unroll
-    for (int a = 0; a < D; ++a) {
-        const double u = U[1 + a] / rho;
-        ke += u * u;
-    }
-    const double p = (P.gamma - 1.0) * (U[nv - 1] - 0.5 * rho * ke);
-    const double c = sqrt(P.gamma * p / rho);
-    return cfl * h / (sqrt(ke) + c + 2.0 * P.mu / rho / h);
-}
-
-// state of cell i: from the SoA cell averages W (soa = 1) or the cell-major
-// low-level state U (+ dU when dU != nullptr)
-template <int D> __device__ __forceinline__ void low_state(const Dev &d, const double *U, const double *dU, int soa,
+// state of cell i: from the state records (rec = 1, U = d.st) or the
+// cell-major low-level state U (+ dU when dU != nullptr)
+template <int D> __device__ __forceinline__ void low_state(const Dev &d, const double *U, const double *dU, int rec,
                                                            int i, double *out) {
     constexpr int nv = D + 2;
-    if (soa) {
+    if (rec) {
 #pragma unroll
-        for (int v = 0; v < nv; ++v) out[v] = U[v * d.NC + i];
+        for (int v = 0; v < nv; ++v) out[v] = U[size_t(i) * Rec<D>::sr + v];
     } else {
 #pragma unroll
         for (int v = 0; v < nv; ++v) out[v] = dU ? U[i * nv + v] + dU[i * nv + v] : U[i * nv + v];
@@ -1045,50 +1108,60 @@ enum { LOW_FORCE = 0, LOW_STEP_FIRST = 1, LOW_STEP = 2, LOW_R0_OUT = 3 };
 
 template <int D> __global__ __launch_bounds__(kBlock) void k_low_cell(Dev d, int mode, double *out) {
     using T = Dim<D>;
-    constexpr int nv = T::nv;
-    const int i = blockIdx.x * kBlock + threadIdx.x;
-    if (i >= d.NC) return;
+    constexpr int nv = T::nv, SL = T::sl;
+    const int t = blockIdx.x * kBlock + threadIdx.x;
+    const int ir = t / SL, q = t % SL;
+    const bool ok = ir < d.NC;
+    const int i = ok ? ir : d.NC - 1;
     const int NC = d.NC;
     const DevParams &P = d.prm[d.cell_case[i]];
-    if (!P.active) return;
     double R0[nv], lS = 0.0;
 #pragma unroll
     for (int v = 0; v < nv; ++v) R0[v] = 0.0;
-#pragma unroll 1
-    for (int s = 0; s < T::ns; ++s) {
-        const int code = d.slot[s * NC + i].x;
-        if (code == 0) break;
-        const int f = (code > 0 ? code : -code) - 1;
-        const double sg = code > 0 ? 1.0 : -1.0;
-        const double *lf = d.lowf + size_t(f) * nv;
 #pragma unroll
-        for (int v = 0; v < nv; ++v) R0[v] -= sg * lf[v];
-        lS += d.swp[size_t(f) * 4 + D];
+    for (int s = q; s < T::ns; s += SL) {
+        const int code = d.slot[s * NC + i].x;
+        if (code != 0) {
+            const int f = (code > 0 ? code : -code) - 1;
+            const double sg = code > 0 ? 1.0 : -1.0;
+            const double *lf = d.lowf + size_t(f) * nv;
+#pragma unroll
+            for (int v = 0; v < nv; ++v) R0[v] -= sg * lf[v];
+            lS += d.swp[size_t(f) * 4 + D];
+        }
     }
+#pragma unroll
+    for (int v = 0; v < nv; ++v) R0[v] = group_sum<SL>(R0[v]);
+    lS = group_sum<SL>(lS);
+    if (!ok || !P.active) return;
+    double *Ui = d.U + size_t(i) * nv, *dUi = d.dU + size_t(i) * nv;
     if (mode == LOW_R0_OUT) {
 #pragma unroll
-        for (int v = 0; v < nv; ++v) out[v * NC + i] = R0[v];
+        for (int v = 0; v < nv; ++v)
+            if (v % SL == q) out[v * NC + i] = R0[v];
         return;
     }
-    double *Ui = d.U + size_t(i) * nv, *dUi = d.dU + size_t(i) * nv;
     if (mode == LOW_FORCE) {
 #pragma unroll
-        for (int v = 0; v < nv; ++v) {
-            d.Sf[v * NC + i] = d.R1[v * NC + i] - R0[v];
-            Ui[v] = d.W[v * NC + i];
-            dUi[v] = 0.0;
-        }
+        for (int v = 0; v < nv; ++v)
+            if (v % SL == q) {
+                d.Sf[v * NC + i] = d.R1[v * NC + i] - R0[v];
+                Ui[v] = d.st[size_t(i) * Rec<D>::sr + v];
+                dUi[v] = 0.0;
+            }
         return;
     }
     double u[nv];
 #pragma unroll
-    for (int v = 0; v < nv; ++v) {
-        u[v] = mode == LOW_STEP ? Ui[v] + dUi[v] : Ui[v];
-        Ui[v] = u[v];
-        d.RHS[v * NC + i] = R0[v] + d.Sf[v * NC + i];
-        dUi[v] = 0.0;
-    }
-    d.D[i] = d.vol[i] / state_dt<D>(u, d.h[i], P.cfl_low, P) + 0.5 * lS;
+    for (int v = 0; v < nv; ++v) u[v] = mode == LOW_STEP ? Ui[v] + dUi[v] : Ui[v];
+#pragma unroll
+    for (int v = 0; v < nv; ++v)
+        if (v % SL == q) {
+            Ui[v] = u[v];
+            d.RHS[v * NC + i] = R0[v] + d.Sf[v * NC + i];
+            dUi[v] = 0.0;
+        }
+    if (q == 0) d.D[i] = d.vol[i] / state_dt<D>(u, d.h[i], P.cfl_low, P) + 0.5 * lS;
 }
 
 // one colour class: blocks listed in (start, count) tables.  With A = s S_f n_f
@@ -1097,43 +1170,47 @@ template <int D> __global__ __launch_bounds__(kBlock) void k_low_cell(Dev d, int
 template <int D> __global__ __launch_bounds__(kBlock) void k_sweep(Dev d, const int32_t *blk_start,
                                                                    const int32_t *blk_count) {
     using T = Dim<D>;
-    constexpr int nv = T::nv;
+    constexpr int nv = T::nv, SL = T::sl;
     const int b = blockIdx.x;
-    if ((int)threadIdx.x >= blk_count[b]) return;
-    const int i = blk_start[b] + threadIdx.x;
+    const int lc = threadIdx.x / SL, q = threadIdx.x % SL;
+    const bool ok = lc < blk_count[b];
+    const int i = blk_start[b] + (ok ? lc : 0);
     const int NC = d.NC;
     const DevParams &P = d.prm[d.cell_case[i]];
-    if (!P.active) return;
     double acc[nv];
 #pragma unroll
-    for (int v = 0; v < nv; ++v) acc[v] = d.RHS[v * NC + i];
-#pragma unroll 1
-    for (int s = 0; s < T::ns; ++s) {
+    for (int v = 0; v < nv; ++v) acc[v] = 0.0;
+#pragma unroll
+    for (int s = q; s < T::ns; s += SL) {
         const int2 sl = d.slot[s * NC + i];
-        if (sl.x == 0) break;
-        const int nb = sl.y;
-        if (nb < 0) continue;
-        const int f = (sl.x > 0 ? sl.x : -sl.x) - 1;
-        const double sg = sl.x > 0 ? 1.0 : -1.0;
-        const double *w = d.swp + size_t(f) * 4;
-        double A[D], Um[nv], dUm[nv], Up[nv], Fa[nv], Fb[nv];
+        if (sl.x != 0 && sl.y >= 0) {
+            const int nb = sl.y;
+            const int f = (sl.x > 0 ? sl.x : -sl.x) - 1;
+            const double sg = sl.x > 0 ? 1.0 : -1.0;
+            const double *w = d.swp + size_t(f) * 4;
+            double A[D], Um[nv], dUm[nv], Up[nv], Fa[nv], Fb[nv];
 #pragma unroll
-        for (int a = 0; a < D; ++a) A[a] = sg * w[a];
-        const double sl_lam = w[D];
+            for (int a = 0; a < D; ++a) A[a] = sg * w[a];
+            const double sl_lam = w[D];
 #pragma unroll
-        for (int v = 0; v < nv; ++v) {
-            Um[v] = d.U[size_t(nb) * nv + v];
-            dUm[v] = d.dU[size_t(nb) * nv + v];
-            Up[v] = Um[v] + dUm[v];
+            for (int v = 0; v < nv; ++v) {
+                Um[v] = d.U[size_t(nb) * nv + v];
+                dUm[v] = d.dU[size_t(nb) * nv + v];
+                Up[v] = Um[v] + dUm[v];
+            }
+            euler_flux<D>(Up, A, P.gamma, Fa);
+            euler_flux<D>(Um, A, P.gamma, Fb);
+#pragma unroll
+            for (int v = 0; v < nv; ++v) acc[v] += 0.5 * (Fa[v] - Fb[v]) - 0.5 * sl_lam * dUm[v];
         }
-        euler_flux<D>(Up, A, P.gamma, Fa);
-        euler_flux<D>(Um, A, P.gamma, Fb);
-#pragma unroll
-        for (int v = 0; v < nv; ++v) acc[v] -= 0.5 * (Fa[v] - Fb[v]) - 0.5 * sl_lam * dUm[v];
     }
+#pragma unroll
+    for (int v = 0; v < nv; ++v) acc[v] = group_sum<SL>(acc[v]);
+    if (!ok || !P.active) return;
     const double Di = d.D[i];
 #pragma unroll
-    for (int v = 0; v < nv; ++v) d.dU[size_t(i) * nv + v] = acc[v] / Di;
+    for (int v = 0; v < nv; ++v)
+        if (v % SL == q) d.dU[size_t(i) * nv + v] = (d.RHS[v * NC + i] - acc[v]) / Di;
 }
 
 // W += (U + dU) - W_p0 (W_p0 = W); partial sums of |rho - rho^n| and rho^n.
@@ -1153,11 +1230,11 @@ template <int D> __global__ __launch_bounds__(kBlock) void k_prolong_res(Dev d, 
 #pragma unroll
             for (int v = 0; v < nv; ++v) {
                 const double u6 = d.U[size_t(i) * nv + v] + d.dU[size_t(i) * nv + v];
-                const double w = d.W[v * NC + i];
-                d.W[v * NC + i] = w + (u6 - w);
+                const double w = d.st[size_t(i) * Rec<D>::sr + v];
+                d.st[size_t(i) * Rec<D>::sr + v] = w + (u6 - w);
             }
         }
-        s0 += fabs(d.W[i] - d.Wn[i]);
+        s0 += fabs(d.st[size_t(i) * Rec<D>::sr] - d.Wn[i]);
         s1 += d.Wn[i];
     }
     s0 = block_reduce_sum(s0, sh);
