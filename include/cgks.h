@@ -190,6 +190,18 @@ cgks_status cgks_lowlevel_smooth(cgks_batch *batch, const double *R1_dev, void *
    NULL) receives Res per case. */
 cgks_status cgks_cycle(cgks_batch *batch, double *res_dev, void *stream);
 
+/* Capture n_cycles (1..64) consecutive cycles of every case into a HIP
+   graph held by the batch (replacing any previous one).  Capture runs on a
+   private stream after the work queued on `stream`; the captured kernels
+   read dt, Res and the parameters from device memory, so replays need no
+   host work.  The graph also records each cycle's Res per case. */
+cgks_status cgks_graph_create(cgks_batch *batch, int32_t n_cycles, void *stream);
+/* Replay the captured cycles on stream.  res_history_dev (may be NULL)
+   receives [n_cycles][n_case] Res values (device).  CGKS_EINVAL when no
+   graph has been captured. */
+cgks_status cgks_graph_launch(cgks_batch *batch, double *res_history_dev, void *stream);
+cgks_status cgks_graph_destroy(cgks_batch *batch);
+
 typedef struct {
     int32_t max_cycles;
     double tol;            /* stop a case when Res_k / Res_1 <= tol (tol_abs = 0) ... */
@@ -206,7 +218,10 @@ typedef struct {
 } cgks_solve_report;
 
 /* Cycle until every case meets its tolerance or max_cycles; report[n_case]
-   (host).  Cases that finish stop being updated. */
+   (host).  Res is checked on the host every check_every cycles; with
+   2 <= check_every <= 8 those cycles run as one captured graph (this
+   replaces a graph made by cgks_graph_create).  A case that meets its tolerance, or is
+   found non-physical or diverging, stops being updated at that check. */
 cgks_status cgks_solve(cgks_batch *batch, const cgks_solve_opts *opts, cgks_solve_report *report, void *stream);
 
 /* Kernel timing.  enable = 1 brackets every kernel launch of the batch with

@@ -27,7 +27,7 @@ EXPORTS = ["cgks_status_string", "cgks_mesh_create", "cgks_mesh_query", "cgks_me
            "cgks_mesh_geometry", "cgks_mesh_destroy", "cgks_batch_create", "cgks_batch_query", "cgks_batch_bind", "cgks_batch_destroy",
            "cgks_state_upload", "cgks_state_download", "cgks_state_device", "cgks_highorder_stage",
            "cgks_residual", "cgks_lowlevel_smooth", "cgks_cycle", "cgks_solve", "cgks_timing_enable",
-           "cgks_timing_read"]
+           "cgks_timing_read", "cgks_graph_create", "cgks_graph_launch", "cgks_graph_destroy"]
 KERNEL_KINDS = ["dt", "recon", "flux", "cell", "low_face", "low_cell", "sweep", "prolong"]
 
 
@@ -104,6 +104,9 @@ def lib():
         L.cgks_cycle.argtypes = [P, P, P]
         L.cgks_solve.argtypes = [P, C.POINTER(_SolveOpts), P, P]
         L.cgks_timing_enable.argtypes = [P, i32]
+        L.cgks_graph_create.argtypes = [P, i32, P]
+        L.cgks_graph_launch.argtypes = [P, P, P]
+        L.cgks_graph_destroy.argtypes = [P]
         L.cgks_timing_read.argtypes = [P, P, P]
         for name in EXPORTS:
             getattr(L, name).restype = C.c_int if name != "cgks_status_string" else C.c_char_p
@@ -268,6 +271,16 @@ class Batch:
     def cycle(self, res=None):
         ptr = C.c_void_p(res.data_ptr()) if res is not None else None
         _check(lib().cgks_cycle(self.h, ptr, _stream(self.stream)), "cgks_cycle")
+
+    def graph_create(self, n_cycles):
+        """Capture n_cycles cycles of every case as one replayable HIP graph."""
+        _check(lib().cgks_graph_create(self.h, n_cycles, _stream(self.stream)), "cgks_graph_create")
+        self.graph_cycles = n_cycles
+
+    def graph_launch(self, res_history=None):
+        """Replay the captured cycles; res_history: device float64 [n_cycles * n_case] or None."""
+        ptr = C.c_void_p(res_history.data_ptr()) if res_history is not None else None
+        _check(lib().cgks_graph_launch(self.h, ptr, _stream(self.stream)), "cgks_graph_launch")
 
     def timing(self, enable=True):
         _check(lib().cgks_timing_enable(self.h, int(enable)), "cgks_timing_enable")

@@ -17,6 +17,7 @@ using namespace cgks;
 namespace {
 
 constexpr int kRedChunk = 1024;   // cells per reduction block (never straddles cases)
+constexpr int kMaxGraphCycles = 64;   // cycles one captured graph may hold
 
 struct Arena {
     size_t off = 0;
@@ -52,6 +53,7 @@ struct cgks_batch {
         size_t gx, gn, gw, fsum;
         size_t U, dU, Sf, RHS, D, R1, lowf, swp;
         size_t prm, dt, res, flag, rb_start, rb_count, rb_case, case_rb_off, part0, part1, cb_start, cb_count;
+        size_t res_hist;
     } o{};
     Dev dev{};
     int32_t *d_cb_start = nullptr, *d_cb_count = nullptr;
@@ -59,7 +61,21 @@ struct cgks_batch {
     bool timing = false;
     std::vector<hipEvent_t> events;
     std::vector<std::pair<int, size_t>> recs;   // (kind, index of the start event)
+    // captured cycles
+    hipGraphExec_t graph_exec = nullptr;
+    hipGraph_t graph = nullptr;
+    int graph_cycles = 0;
+    double *res_hist = nullptr;                 // device [graph_cycles][n_case], inside the arena
+    size_t res_hist_len = 0;
+    void drop_graph() {
+        if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        graph_exec = nullptr;
+        graph = nullptr;
+        graph_cycles = 0;
+    }
     ~cgks_batch() {
+        drop_graph();
         for (hipEvent_t e : events) (void)hipEventDestroy(e);
     }
 };
@@ -122,6 +138,8 @@ void layout(cgks_batch *b) {
     o.part1 = a.take<double>(b->rb_start.size());
     o.cb_start = a.take<int32_t>(std::max<size_t>(b->cb_start.size(), 1));
     o.cb_count = a.take<int32_t>(std::max<size_t>(b->cb_start.size(), 1));
+    b->res_hist_len = size_t(kMaxGraphCycles) * b->n_case;
+    o.res_hist = a.take<double>(b->res_hist_len);
     b->bytes = (a.off + 255) & ~size_t(255);
 }
 
@@ -174,6 +192,7 @@ void fill_dev(cgks_batch *b) {
     d.part0 = at<double>(b, o.part0); d.part1 = at<double>(b, o.part1);
     b->d_cb_start = at<int32_t>(b, o.cb_start);
     b->d_cb_count = at<int32_t>(b, o.cb_count);
+    b->res_hist = at<double>(b, o.res_hist);
 }
 
 template <class T> hipError_t put(cgks_batch *b, size_t off, const std::vector<T> &v, hipStream_t s) {
@@ -687,16 +706,27 @@ cgks_status cgks_solve(cgks_batch *b, const cgks_solve_opts *opts, cgks_solve_re
     HIP_TRY(hipMemcpyAsync(prm.data(), b->dev.prm, sizeof(DevParams) * n, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     int remaining = n;
+    // blocks of `every` cycles run as one captured graph (one host round trip
+    // per block); a shorter final block runs eagerly
+    const bool use_graph = every > 1 && every <= 8;
+    if (use_graph) {
+        cgks_status st = cgks_graph_create(b, every, stream);
+        if (st) return st;
+    }
     for (int k = 0; k < opts->max_cycles && remaining > 0;) {
         const int todo = std::min(every, opts->max_cycles - k);
         std::vector<double> hist(size_t(todo) * n);
-        for (int j = 0; j < todo; ++j) {
-            cgks_status st = b->dim == 2 ? launch_cycle<2>(b, s) : launch_cycle<3>(b, s);
-            if (st) return st;
-            HIP_TRY(hipMemcpyAsync(hist.data() + size_t(j) * n, b->dev.res, sizeof(double) * n,
-                                   hipMemcpyDeviceToHost, s));
-        }
-        HIP_TRY(hipMemcpyAsync(flag.data(), b->dev.flag, sizeof(int32_t) * n, hipMemcpyDeviceToHost, s));
+        if (use_graph && todo == every) {
+            HIP_TRY(hipGraphLaunch(b->graph_exec, s));
+            HIP_TRY(hipMemcpyAsync(hist.data(), b->res_hist, sizeof(double) * todo * n, hipMemcpyDeviceToHost, s));
+        } else {
+            for (int j = 0; j < todo; ++j) {
+                cgks_status st = b->dim == 2 ? launch_cycle<2>(b, s) : launch_cycle<3>(b, s);
+                if (st) return st;
+                HIP_TRY(hipMemcpyAsync(hist.data() + size_t(j) * n, b->dev.res, sizeof(double) * n,
+                                       hipMemcpyDeviceToHost, s));
+            }
+        }        HIP_TRY(hipMemcpyAsync(flag.data(), b->dev.flag, sizeof(int32_t) * n, hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
         bool changed = false;
         for (int j = 0; j < todo; ++j) {
@@ -733,6 +763,59 @@ cgks_status cgks_solve(cgks_batch *b, const cgks_solve_opts *opts, cgks_solve_re
     for (int c = 0; c < n; ++c) prm[c].active = 1;
     HIP_TRY(hipMemcpyAsync((void *)b->dev.prm, prm.data(), sizeof(DevParams) * n, hipMemcpyHostToDevice, s));
     HIP_TRY(hipStreamSynchronize(s));
+    return CGKS_OK;
+}
+
+cgks_status cgks_graph_create(cgks_batch *b, int32_t n_cycles, void *stream) {
+    if (!b || !b->base || n_cycles <= 0 || n_cycles > kMaxGraphCycles) return CGKS_EINVAL;
+    b->drop_graph();
+    hipStream_t cap;
+    HIP_TRY(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+    // the capture stream starts after all work already queued on `stream`
+    hipEvent_t ready;
+    HIP_TRY(hipEventCreateWithFlags(&ready, hipEventDisableTiming));
+    HIP_TRY(hipEventRecord(ready, static_cast<hipStream_t>(stream)));
+    HIP_TRY(hipStreamWaitEvent(cap, ready, 0));
+    HIP_TRY(hipStreamSynchronize(cap));
+    const bool timing = b->timing;
+    b->timing = false;
+    cgks_status st = CGKS_OK;
+    if (hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal) != hipSuccess) st = CGKS_EDEVICE;
+    for (int k = 0; k < n_cycles && st == CGKS_OK; ++k) {
+        st = b->dim == 2 ? launch_cycle<2>(b, cap) : launch_cycle<3>(b, cap);
+        if (st == CGKS_OK)
+            hipLaunchKernelGGL(k_res_store, dim3(nblk(b->n_case)), dim3(kBlock), 0, cap, (const double *)b->dev.res,
+                               b->res_hist + size_t(k) * b->n_case, b->n_case);
+    }
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(cap, &g);
+    b->timing = timing;
+    if (st == CGKS_OK && (e != hipSuccess || !g)) st = CGKS_EDEVICE;
+    if (st == CGKS_OK && hipGraphInstantiate(&b->graph_exec, g, nullptr, nullptr, 0) != hipSuccess) st = CGKS_EDEVICE;
+    if (st == CGKS_OK) {
+        b->graph = g;
+        b->graph_cycles = n_cycles;
+    } else if (g) {
+        (void)hipGraphDestroy(g);
+    }
+    (void)hipEventDestroy(ready);
+    (void)hipStreamDestroy(cap);
+    return st;
+}
+
+cgks_status cgks_graph_launch(cgks_batch *b, double *res_history_dev, void *stream) {
+    if (!b || !b->graph_exec) return CGKS_EINVAL;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    HIP_TRY(hipGraphLaunch(b->graph_exec, s));
+    if (res_history_dev)
+        HIP_TRY(hipMemcpyAsync(res_history_dev, b->res_hist, sizeof(double) * b->graph_cycles * b->n_case,
+                               hipMemcpyDeviceToDevice, s));
+    return CGKS_OK;
+}
+
+cgks_status cgks_graph_destroy(cgks_batch *b) {
+    if (!b) return CGKS_EINVAL;
+    b->drop_graph();
     return CGKS_OK;
 }
 

@@ -1245,6 +1245,12 @@ template <int D> __global__ __launch_bounds__(kBlock) void k_prolong_res(Dev d, 
     }
 }
 
+// copy the per-case Res of the last cycle into slot k of a device history
+__global__ void k_res_store(const double *res, double *hist, int n_case) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < n_case) hist[c] = res[c];
+}
+
 __global__ void k_res_final(Dev d, int n_case) {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= n_case) return;
