@@ -139,8 +139,11 @@ cgks_status cgks_mesh_destroy(cgks_mesh *mesh);
 
 /* A batch is n_case (mesh, params) pairs stepped together: every kernel
    launch covers all cases; per-case reductions (dt, Res) never mix cases.
-   The meshes must outlive the batch.  precision: CGKS_FP64 (the only value
-   accepted so far).  Errors: CGKS_EINVAL, CGKS_EUNSUPPORTED, CGKS_ENOMEM. */
+   The meshes must outlive the batch.  precision: CGKS_FP64, or
+   CGKS_MIXED32: reconstruction coefficients, interface states, the
+   gas-kinetic flux and the face sums in FP32; cell averages, gradients,
+   the stage accumulation, R1, the low level, Res and dt in FP64.
+   Errors: CGKS_EINVAL, CGKS_ENOMEM. */
 cgks_status cgks_batch_create(const cgks_mesh *const *meshes, const cgks_params *params, int32_t n_case,
                               int32_t precision, cgks_batch **out);
 /* Device bytes the batch needs (geometry, state, work arrays). */

@@ -50,7 +50,7 @@ struct cgks_batch {
     struct {
         size_t st, ev, Wn, L0, Lt0, G0, geo, vol, h, minv, slot, cell_case;
         size_t fL, fR, fbc, fcase, gp_off, bslot, avec, S, shift, gavg, bface, gdat;
-        size_t gx, gn, gw, fsum;
+        size_t gx, gn, gw, fsum, fsum32, ev32, minv32;
         size_t U, dU, Sf, RHS, D, R1, lowf, swp;
         size_t prm, dt, res, flag, rb_start, rb_count, rb_case, case_rb_off, part0, part1, cb_start, cb_count;
         size_t res_hist;
@@ -90,8 +90,9 @@ void layout(cgks_batch *b) {
     Arena a;
     auto &o = b->o;
     const int sr = nv + d * nv, er = d + 1 + nq + nv + nk * nv, gr = d + nq + 1;
+    const bool mixed = b->precision == CGKS_MIXED32;
     o.st = a.take<double>(sr * NC);
-    o.ev = a.take<double>(er * NC);
+    o.ev = a.take<double>(mixed ? 0 : er * NC);
     o.Wn = a.take<double>(nv * NC);
     o.L0 = a.take<double>(nv * NC);
     o.Lt0 = a.take<double>(nv * NC);
@@ -117,7 +118,10 @@ void layout(cgks_batch *b) {
     o.gx = a.take<double>(d * NG);
     o.gn = a.take<double>(d * NG);
     o.gw = a.take<double>(NG);
-    o.fsum = a.take<double>((2 * nv + 2 * d * nv) * NF);
+    o.fsum = a.take<double>(mixed ? 0 : (2 * nv + 2 * d * nv) * NF);
+    o.fsum32 = a.take<float>(mixed ? (2 * nv + 2 * d * nv) * NF : 0);
+    o.ev32 = a.take<float>(mixed ? er * NC : 0);
+    o.minv32 = a.take<float>(mixed ? nk * (nk + 1) / 2 * NC : 0);
     o.U = a.take<double>(nv * NC);
     o.dU = a.take<double>(nv * NC);
     o.Sf = a.take<double>(nv * NC);
@@ -182,6 +186,9 @@ void fill_dev(cgks_batch *b) {
     d.NB_real = int32_t(b->NB);
     d.gx = at<double>(b, o.gx); d.gn = at<double>(b, o.gn); d.gw = at<double>(b, o.gw);
     d.fsum = at<double>(b, o.fsum);
+    d.fsum32 = at<float>(b, o.fsum32);
+    d.ev32 = at<float>(b, o.ev32);
+    d.minv32 = at<float>(b, o.minv32);
     d.U = at<double>(b, o.U); d.dU = at<double>(b, o.dU); d.Sf = at<double>(b, o.Sf);
     d.RHS = at<double>(b, o.RHS); d.D = at<double>(b, o.D); d.R1 = at<double>(b, o.R1);
     d.lowf = at<double>(b, o.lowf); d.swp = at<double>(b, o.swp);
@@ -228,6 +235,22 @@ template <class F> void timed(cgks_batch *b, int kind, hipStream_t s, F &&launch
         if ((x) != hipSuccess) return CGKS_EDEVICE;     \
     } while (0)
 
+template <int D, typename R> void launch_ho_kernels(cgks_batch *b, int mode, hipStream_t s) {
+    const Dev &d = b->dev;
+    timed(b, CGKS_K_RECON, s, [&] {
+        if (b->NB > 0) hipLaunchKernelGGL(k_ghost<D>, dim3(nblk(b->NB)), dim3(kBlock), 0, s, d);
+        hipLaunchKernelGGL((k_recon<D, R>), dim3(unsigned((b->NC + kReconBlock - 1) / kReconBlock)),
+                           dim3(kReconBlock), 0, s, d);
+    });
+    timed(b, CGKS_K_FLUX, s, [&] {
+        hipLaunchKernelGGL((k_flux<D, R>), dim3(nblk(b->NF * Dim<D>::lanes)), dim3(kBlock), 0, s, d,
+                           (int)(mode != MODE_R1));
+    });
+    timed(b, CGKS_K_CELL, s, [&] {
+        hipLaunchKernelGGL((k_cell<D, R>), dim3(nblk(b->NC * Dim<D>::sl)), dim3(kBlock), 0, s, d, mode);
+    });
+}
+
 template <int D> cgks_status launch_highorder(cgks_batch *b, int mode, hipStream_t s) {
     const Dev &d = b->dev;
     if (mode == MODE_STAGE0) {
@@ -236,18 +259,8 @@ template <int D> cgks_status launch_highorder(cgks_batch *b, int mode, hipStream
             hipLaunchKernelGGL(k_dt_final, dim3(nblk(b->n_case)), dim3(kBlock), 0, s, d, b->n_case);
         });
     }
-    timed(b, CGKS_K_RECON, s, [&] {
-        if (b->NB > 0) hipLaunchKernelGGL(k_ghost<D>, dim3(nblk(b->NB)), dim3(kBlock), 0, s, d);
-        hipLaunchKernelGGL(k_recon<D>, dim3(unsigned((b->NC + kReconBlock - 1) / kReconBlock)), dim3(kReconBlock),
-                           0, s, d);
-    });
-    timed(b, CGKS_K_FLUX, s, [&] {
-        hipLaunchKernelGGL(k_flux<D>, dim3(nblk(b->NF * Dim<D>::lanes)), dim3(kBlock), 0, s, d,
-                           (int)(mode != MODE_R1));
-    });
-    timed(b, CGKS_K_CELL, s, [&] {
-        hipLaunchKernelGGL(k_cell<D>, dim3(nblk(b->NC * Dim<D>::sl)), dim3(kBlock), 0, s, d, mode);
-    });
+    if (b->precision == CGKS_MIXED32) launch_ho_kernels<D, float>(b, mode, s);
+    else launch_ho_kernels<D, double>(b, mode, s);
     HIP_TRY(hipGetLastError());
     return CGKS_OK;
 }
@@ -406,7 +419,7 @@ cgks_status cgks_batch_create(const cgks_mesh *const *meshes, const cgks_params 
                               int32_t precision, cgks_batch **out) {
     if (!out || !meshes || !params || n_case <= 0) return CGKS_EINVAL;
     *out = nullptr;
-    if (precision != CGKS_FP64) return CGKS_EUNSUPPORTED;
+    if (precision != CGKS_FP64 && precision != CGKS_MIXED32) return CGKS_EINVAL;
     try {
         cgks_batch *b = new cgks_batch;
         b->n_case = n_case;
@@ -562,6 +575,10 @@ cgks_status cgks_batch_bind(cgks_batch *b, void *buf, size_t bytes, void *stream
         auto &o = b->o;
         HIP_TRY(put(b, o.vol, vol, s)); HIP_TRY(put(b, o.h, h, s)); HIP_TRY(put(b, o.geo, geo, s));
         HIP_TRY(put(b, o.minv, minv, s));
+        if (b->precision == CGKS_MIXED32) {
+            std::vector<float> m32(minv.begin(), minv.end());
+            HIP_TRY(put(b, o.minv32, m32, s));
+        }
         HIP_TRY(put(b, o.slot, slot, s));
         HIP_TRY(put(b, o.cell_case, cell_case, s));
         HIP_TRY(put(b, o.fL, fL, s)); HIP_TRY(put(b, o.fR, fR, s)); HIP_TRY(put(b, o.fbc, fbc, s));

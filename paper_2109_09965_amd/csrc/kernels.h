@@ -36,8 +36,10 @@ struct Dev {
     double *st;               // [NC][sr]: W (nv), grad W [axis][v]
     const double *geo;        // [NC][gr]: centroid (D), central second moments (nq), h
     double *ev;               // [NC][er]: centroid, 1/h, <phi_quad>, W, coefficients [k][v]
+    float *ev32;              // the same records in FP32 (mixed-precision batches)
     double *Wn, *L0, *Lt0, *G0;
     const double *vol, *h, *minv;
+    const float *minv32;      // FP32 copy of minv (mixed-precision batches)
     const int2 *slot;         // [ns][NC]: (x) face code +-(f + 1), 0 = none; (y) neighbour cell or -1
     const int32_t *cell_case;
     // faces
@@ -48,6 +50,7 @@ struct Dev {
     // gauss points
     const double *gx, *gn, *gw;
     double *fsum;      // per face [NF][2 nv + 2 D nv]: sum_g wJ (F0, Ft, W_c n, W_t n)
+    float *fsum32;     // the same in FP32 (mixed-precision batches)
     // low level: U, dU cell-major [NC][nv] (gathered by neighbours), Sf, RHS, R1 [nv][NC]
     double *U, *dU, *Sf, *RHS, *D, *R1;
     double *lowf;      // [NF][nv]: S_f F_kfvs
@@ -62,6 +65,19 @@ struct Dev {
 };
 
 template <int D> struct Dim;
+
+// precision-dependent arrays of the high-order pass
+template <typename R> struct HoArrays;
+template <> struct HoArrays<double> {
+    static __device__ __forceinline__ double *ev(const Dev &d) { return d.ev; }
+    static __device__ __forceinline__ double *fsum(const Dev &d) { return d.fsum; }
+    static __device__ __forceinline__ const double *minv(const Dev &d) { return d.minv; }
+};
+template <> struct HoArrays<float> {
+    static __device__ __forceinline__ float *ev(const Dev &d) { return d.ev32; }
+    static __device__ __forceinline__ float *fsum(const Dev &d) { return d.fsum32; }
+    static __device__ __forceinline__ const float *minv(const Dev &d) { return d.minv32; }
+};
 
 // record layouts of the cell-major arrays
 template <int D> struct Rec {
@@ -110,55 +126,55 @@ template <int D> __device__ __forceinline__ int midx(int j, int k) {
 // branches on the normal (Duff et al., "Building an orthonormal basis,
 // revisited", 2017).  The flux is frame invariant.
 // ---------------------------------------------------------------------
-template <int D> struct Frame {
-    double e[D][D];
-    __device__ __forceinline__ void build(const double *n) {
+template <int D, typename R> struct Frame {
+    R e[D][D];
+    __device__ __forceinline__ void build(const R *n) {
         if constexpr (D == 2) {
             e[0][0] = n[0]; e[0][1] = n[1];
             e[1][0] = -n[1]; e[1][1] = n[0];
         } else {
-            const double s = copysign(1.0, n[2]);
-            const double a = -1.0 / (s + n[2]);
-            const double b = n[0] * n[1] * a;
+            const R s = copysign(R(1.0), n[2]);
+            const R a = -R(1.0) / (s + n[2]);
+            const R b = n[0] * n[1] * a;
             e[0][0] = n[0]; e[0][1] = n[1]; e[0][2] = n[2];
-            e[1][0] = 1.0 + s * n[0] * n[0] * a; e[1][1] = s * b; e[1][2] = -s * n[0];
+            e[1][0] = R(1.0) + s * n[0] * n[0] * a; e[1][1] = s * b; e[1][2] = -s * n[0];
             e[2][0] = b; e[2][1] = s + n[1] * n[1] * a; e[2][2] = -n[1];
         }
     }
     // vector components of a state (momentum) global -> local
-    __device__ __forceinline__ void to_local(const double *W, double *Wl) const {
+    __device__ __forceinline__ void to_local(const R *W, R *Wl) const {
         constexpr int nv = D + 2;
         Wl[0] = W[0];
         Wl[nv - 1] = W[nv - 1];
 #pragma unroll
         for (int a = 0; a < D; ++a) {
-            double s = 0;
+            R s = 0;
 #pragma unroll
             for (int b = 0; b < D; ++b) s += e[a][b] * W[1 + b];
             Wl[1 + a] = s;
         }
     }
-    __device__ __forceinline__ void to_global(const double *Wl, double *W) const {
+    __device__ __forceinline__ void to_global(const R *Wl, R *W) const {
         constexpr int nv = D + 2;
         W[0] = Wl[0];
         W[nv - 1] = Wl[nv - 1];
 #pragma unroll
         for (int b = 0; b < D; ++b) {
-            double s = 0;
+            R s = 0;
 #pragma unroll
             for (int a = 0; a < D; ++a) s += e[a][b] * Wl[1 + a];
             W[1 + b] = s;
         }
     }
     // gradient G[axis][v] global -> derivatives along local axes of local components
-    __device__ __forceinline__ void grad_to_local(const double G[D][D + 2], double Gl[D][D + 2]) const {
+    __device__ __forceinline__ void grad_to_local(const R G[D][D + 2], R Gl[D][D + 2]) const {
         constexpr int nv = D + 2;
-        double T[D][nv];
+        R T[D][nv];
 #pragma unroll
         for (int a = 0; a < D; ++a)
 #pragma unroll
             for (int v = 0; v < nv; ++v) {
-                double s = 0;
+                R s = 0;
 #pragma unroll
                 for (int b = 0; b < D; ++b) s += e[a][b] * G[b][v];
                 T[a][v] = s;
@@ -171,91 +187,91 @@ template <int D> struct Frame {
 // ---------------------------------------------------------------------
 // Maxwellian moments (per unit density) in the local frame.
 // ---------------------------------------------------------------------
-template <int D> struct Moments {
-    double mu[7], mv[6], mw[6], xi[3];
-    __device__ __forceinline__ void full(const double *U, double lam, double K) {
-        const double il = 0.5 / lam;
-        mu[0] = 1.0; mu[1] = U[0];
+template <int D, typename R> struct Moments {
+    R mu[7], mv[6], mw[6], xi[3];
+    __device__ __forceinline__ void full(const R *U, R lam, R K) {
+        const R il = R(0.5) / lam;
+        mu[0] = R(1.0); mu[1] = U[0];
 #pragma unroll
         for (int k = 2; k < 7; ++k) mu[k] = U[0] * mu[k - 1] + (k - 1) * il * mu[k - 2];
-        mv[0] = 1.0; mv[1] = U[1];
+        mv[0] = R(1.0); mv[1] = U[1];
 #pragma unroll
         for (int k = 2; k < 6; ++k) mv[k] = U[1] * mv[k - 1] + (k - 1) * il * mv[k - 2];
         if (D == 3) {
-            mw[0] = 1.0; mw[1] = U[D - 1];
+            mw[0] = R(1.0); mw[1] = U[D - 1];
 #pragma unroll
             for (int k = 2; k < 6; ++k) mw[k] = U[D - 1] * mw[k - 1] + (k - 1) * il * mw[k - 2];
         }
-        xi[0] = 1.0;
+        xi[0] = R(1.0);
         xi[1] = K * il;
-        xi[2] = (K * K + 2.0 * K) * il * il;
+        xi[2] = (K * K + R(2.0) * K) * il * il;
     }
-    __device__ __forceinline__ double M(int i, int j, int l, int e) const {
+    __device__ __forceinline__ R M(int i, int j, int l, int e) const {
         return D == 3 ? mu[i] * mv[j] * mw[l] * xi[e] : mu[i] * mv[j] * xi[e];
     }
 };
 
 // micro-slope coefficients a = a0 + a_u u + a_v v (+ a_w w) + a_E (u^2 + .. + xi^2)/2
 // solving <a psi> = b in closed form (b per unit density)
-template <int D> __device__ __forceinline__ void micro_slope(const double *b, const double *U, double lam, double N,
-                                                             double *a) {
+template <int D, typename R> __device__ __forceinline__ void micro_slope(const R *b, const R *U, R lam, R N,
+                                                             R *a) {
     constexpr int nv = D + 2;
-    double U2 = 0, Ub = 0;
+    R U2 = 0, Ub = 0;
 #pragma unroll
     for (int k = 0; k < D; ++k) {
         U2 += U[k] * U[k];
         Ub += U[k] * b[1 + k];
     }
-    const double aE = 4.0 * lam * lam / N * (2.0 * b[nv - 1] - 2.0 * Ub + (U2 - N / (2.0 * lam)) * b[0]);
-    double aU = 0;
+    const R aE = R(4.0) * lam * lam / N * (R(2.0) * b[nv - 1] - R(2.0) * Ub + (U2 - N / (R(2.0) * lam)) * b[0]);
+    R aU = 0;
 #pragma unroll
     for (int k = 0; k < D; ++k) {
-        a[1 + k] = 2.0 * lam * (b[1 + k] - U[k] * b[0]) - aE * U[k];
+        a[1 + k] = R(2.0) * lam * (b[1 + k] - U[k] * b[0]) - aE * U[k];
         aU += a[1 + k] * U[k];
     }
     a[nv - 1] = aE;
-    a[0] = b[0] - aU - 0.5 * aE * (U2 + N / (2.0 * lam));
+    a[0] = b[0] - aU - R(0.5) * aE * (U2 + N / (R(2.0) * lam));
 }
 
 // E[a u^i v^j w^l xi^(2e)]
-template <int D> __device__ __forceinline__ double Ea(const Moments<D> &m, const double *a, int i, int j, int l, int e) {
-    double s = a[0] * m.M(i, j, l, e) + a[1] * m.M(i + 1, j, l, e) + a[2] * m.M(i, j + 1, l, e);
-    double q = m.M(i + 2, j, l, e) + m.M(i, j + 2, l, e) + m.M(i, j, l, e + 1);
+template <int D, typename R> __device__ __forceinline__ R Ea(const Moments<D, R> &m, const R *a, int i, int j, int l, int e) {
+    R s = a[0] * m.M(i, j, l, e) + a[1] * m.M(i + 1, j, l, e) + a[2] * m.M(i, j + 1, l, e);
+    R q = m.M(i + 2, j, l, e) + m.M(i, j + 2, l, e) + m.M(i, j, l, e + 1);
     if constexpr (D == 3) {
         s += a[3] * m.M(i, j, l + 1, e);
         q += m.M(i, j, l + 2, e);
     }
-    return s + 0.5 * a[D + 1] * q;
+    return s + R(0.5) * a[D + 1] * q;
 }
 
 // out[p] = E[psi_p a u^i v^j w^l]
-template <int D> __device__ __forceinline__ void Epsi(const Moments<D> &m, const double *a, int i, int j, int l,
-                                                      double *out) {
+template <int D, typename R> __device__ __forceinline__ void Epsi(const Moments<D, R> &m, const R *a, int i, int j, int l,
+                                                      R *out) {
     constexpr int nv = D + 2;
-    out[0] = Ea<D>(m, a, i, j, l, 0);
-    out[1] = Ea<D>(m, a, i + 1, j, l, 0);
-    out[2] = Ea<D>(m, a, i, j + 1, l, 0);
-    double q = Ea<D>(m, a, i + 2, j, l, 0) + Ea<D>(m, a, i, j + 2, l, 0) + Ea<D>(m, a, i, j, l, 1);
+    out[0] = Ea<D, R>(m, a, i, j, l, 0);
+    out[1] = Ea<D, R>(m, a, i + 1, j, l, 0);
+    out[2] = Ea<D, R>(m, a, i, j + 1, l, 0);
+    R q = Ea<D, R>(m, a, i + 2, j, l, 0) + Ea<D, R>(m, a, i, j + 2, l, 0) + Ea<D, R>(m, a, i, j, l, 1);
     if constexpr (D == 3) {
-        out[3] = Ea<D>(m, a, i, j, l + 1, 0);
-        q += Ea<D>(m, a, i, j, l + 2, 0);
+        out[3] = Ea<D, R>(m, a, i, j, l + 1, 0);
+        q += Ea<D, R>(m, a, i, j, l + 2, 0);
     }
-    out[nv - 1] = 0.5 * q;
+    out[nv - 1] = R(0.5) * q;
 }
 
 // primitive variables of a local-frame state
-template <int D> struct Prim {
-    double rho, U[D], p, lam;
-    __device__ __forceinline__ void from(const double *W, double gamma) {
+template <int D, typename R> struct Prim {
+    R rho, U[D], p, lam;
+    __device__ __forceinline__ void from(const R *W, R gamma) {
         rho = W[0];
-        double ke = 0;
+        R ke = 0;
 #pragma unroll
         for (int a = 0; a < D; ++a) {
             U[a] = W[1 + a] / rho;
             ke += U[a] * U[a];
         }
-        p = (gamma - 1.0) * (W[D + 1] - 0.5 * rho * ke);
-        lam = rho / (2.0 * p);
+        p = (gamma - R(1.0)) * (W[D + 1] - R(0.5) * rho * ke);
+        lam = rho / (R(2.0) * p);
     }
 };
 
@@ -263,68 +279,68 @@ template <int D> struct Prim {
 //   f = g^c [1 - tau (a.u + A) + A t]
 // F0 = flux at t = 0, Ft = its time derivative, Wt = rho <A psi>.
 // Returns false for a non-physical interface state.
-template <int D> __device__ bool gks_flux(const double *Wc, const double Gc[D][D + 2], const DevParams &P, double *F0,
-                                          double *Ft, double *Wt) {
+template <int D, typename R> __device__ bool gks_flux(const R *Wc, const R Gc[D][D + 2], const DevParams &P, R *F0,
+                                          R *Ft, R *Wt) {
     constexpr int nv = D + 2;
-    Prim<D> q;
-    q.from(Wc, P.gamma);
-    if (!(q.rho > 0.0) || !(q.p > 0.0)) return false;
-    const double N = P.K + D;
-    double Uf[3] = {0, 0, 0};
+    Prim<D, R> q;
+    q.from(Wc, R(P.gamma));
+    if (!(q.rho > R(0.0)) || !(q.p > R(0.0))) return false;
+    const R N = R(P.K) + D;
+    R Uf[3] = {0, 0, 0};
 #pragma unroll
     for (int a = 0; a < D; ++a) Uf[a] = q.U[a];
     // Fourier heat flux of the interface state along the normal (R = 1,
     // T = p / rho), used for the Prandtl-number correction
-    double qcorr = 0.0;
-    if (P.Pr != 1.0 && P.mu != 0.0) {
-        double ke = 0, ked = 0;
+    R qcorr = R(0.0);
+    if (R(P.Pr) != R(1.0) && R(P.mu) != R(0.0)) {
+        R ke = 0, ked = 0;
 #pragma unroll
         for (int k = 0; k < D; ++k) {
             ke += q.U[k] * q.U[k];
             ked += q.U[k] * Gc[0][1 + k];
         }
-        const double pn = (P.gamma - 1.0) * (Gc[0][nv - 1] - ked + 0.5 * ke * Gc[0][0]);
-        const double Tn = (pn * q.rho - q.p * Gc[0][0]) / (q.rho * q.rho);
-        qcorr = (1.0 / P.Pr - 1.0) * (-P.mu * P.gamma / (P.gamma - 1.0) * Tn);
+        const R pn = (R(P.gamma) - R(1.0)) * (Gc[0][nv - 1] - ked + R(0.5) * ke * Gc[0][0]);
+        const R Tn = (pn * q.rho - q.p * Gc[0][0]) / (q.rho * q.rho);
+        qcorr = (R(1.0) / R(P.Pr) - R(1.0)) * (-R(P.mu) * R(P.gamma) / (R(P.gamma) - R(1.0)) * Tn);
     }
-    Moments<D> m;
-    m.full(Uf, q.lam, P.K);
-    const double tau = P.mu / q.p;
-    const double ir = 1.0 / q.rho;
+    Moments<D, R> m;
+    m.full(Uf, q.lam, R(P.K));
+    const R tau = R(P.mu) / q.p;
+    const R ir = R(1.0) / q.rho;
     // one direction at a time: micro-slope a^(j), its share of the
     // compatibility sum b = -<(sum_j a^(j) u_j) psi> and of the collision term
     // tt = <u psi (sum_j a^(j) u_j)>
-    double b[nv], tt[nv];
+    R b[nv], tt[nv];
 #pragma unroll
-    for (int v = 0; v < nv; ++v) b[v] = tt[v] = 0.0;
+    for (int v = 0; v < nv; ++v) b[v] = tt[v] = R(0.0);
 #pragma unroll
     for (int j = 0; j < D; ++j) {
-        double g[nv], a[nv], t0[nv];
+        R g[nv], a[nv], t0[nv];
 #pragma unroll
         for (int v = 0; v < nv; ++v) g[v] = Gc[j][v] * ir;
-        micro_slope<D>(g, q.U, q.lam, N, a);
-        Epsi<D>(m, a, j == 0 ? 1 : 0, j == 1 ? 1 : 0, j == 2 ? 1 : 0, t0);
+        micro_slope<D, R>(g, q.U, q.lam, N, a);
+        Epsi<D, R>(m, a, j == 0 ? 1 : 0, j == 1 ? 1 : 0, j == 2 ? 1 : 0, t0);
 #pragma unroll
         for (int v = 0; v < nv; ++v) b[v] -= t0[v];
-        Epsi<D>(m, a, j == 0 ? 2 : 1, j == 1 ? 1 : 0, j == 2 ? 1 : 0, t0);
+        Epsi<D, R>(m, a, j == 0 ? 2 : 1, j == 1 ? 1 : 0, j == 2 ? 1 : 0, t0);
 #pragma unroll
         for (int v = 0; v < nv; ++v) tt[v] += t0[v];
     }
-    double A[nv], eA[nv];
-    micro_slope<D>(b, q.U, q.lam, N, A);
+    R A[nv], eA[nv];
+    micro_slope<D, R>(b, q.U, q.lam, N, A);
     // E[u psi A] gives the time derivative of the flux
-    Epsi<D>(m, A, 1, 0, 0, eA);
+    Epsi<D, R>(m, A, 1, 0, 0, eA);
     // E[u psi]
-    double eu[nv];
+    R eu[nv];
     eu[0] = m.mu[1];
     eu[1] = m.mu[2];
     eu[2] = m.mu[1] * m.mv[1];
-    double ep = m.mu[3] + m.mu[1] * (m.mv[2] + m.xi[1]);
+    R ep = m.mu[3] + m.mu[1] * (m.mv[2] + m.xi[1]);
     if constexpr (D == 3) {
         eu[3] = m.mu[1] * m.mw[1];
         ep += m.mu[1] * m.mw[2];
     }
-    eu[nv - 1] = 0.5 * ep;
+    eu[nv - 1] = R(0.5) * ep;
 #pragma unroll
     for (int v = 0; v < nv; ++v) {
         F0[v] = q.rho * (eu[v] - tau * (tt[v] + eA[v]));
@@ -336,50 +352,50 @@ template <int D> __device__ bool gks_flux(const double *Wc, const double Gc[D][D
 }
 
 // half-range moments <u^k>_{u >< 0}, k = 0..3
-__device__ __forceinline__ void half_moments(double U, double lam, double sgn, double *m) {
-    m[0] = 0.5 * erfc(-sgn * sqrt(lam) * U);
-    m[1] = U * m[0] + sgn * 0.5 * exp(-lam * U * U) * rsqrt(M_PI * lam);
-    m[2] = U * m[1] + 0.5 / lam * m[0];
-    m[3] = U * m[2] + 1.0 / lam * m[1];
+template <typename R> __device__ __forceinline__ void half_moments(R U, R lam, R sgn, R *m) {
+    m[0] = R(0.5) * erfc(-sgn * sqrt(lam) * U);
+    m[1] = U * m[0] + sgn * R(0.5) * exp(-lam * U * U) * rsqrt(R(M_PI) * lam);
+    m[2] = U * m[1] + R(0.5) / lam * m[0];
+    m[3] = U * m[2] + R(1.0) / lam * m[1];
 }
 
 // accumulate rho <psi>_{half} (state) and rho <u psi>_{half} (flux) of one side
-template <int D> __device__ __forceinline__ bool half_side(const double *W, const DevParams &P, double sgn,
-                                                           double *Wacc, double *Facc) {
+template <int D, typename R> __device__ __forceinline__ bool half_side(const R *W, const DevParams &P, R sgn,
+                                                           R *Wacc, R *Facc) {
     constexpr int nv = D + 2;
-    Prim<D> q;
-    q.from(W, P.gamma);
-    if (!(q.rho > 0.0) || !(q.p > 0.0)) return false;
-    double m[4];
-    half_moments(q.U[0], q.lam, sgn, m);
-    double ut2 = 0;
+    Prim<D, R> q;
+    q.from(W, R(P.gamma));
+    if (!(q.rho > R(0.0)) || !(q.p > R(0.0))) return false;
+    R m[4];
+    half_moments<R>(q.U[0], q.lam, sgn, m);
+    R ut2 = 0;
 #pragma unroll
     for (int a = 1; a < D; ++a) ut2 += q.U[a] * q.U[a];
-    const double rest = ut2 + (P.K + D - 1) * 0.5 / q.lam;   // <v^2> + <w^2> + <xi^2>
+    const R rest = ut2 + (R(P.K) + D - 1) * R(0.5) / q.lam;   // <v^2> + <w^2> + <xi^2>
     if (Wacc) {
         Wacc[0] += q.rho * m[0];
         Wacc[1] += q.rho * m[1];
 #pragma unroll
         for (int a = 1; a < D; ++a) Wacc[1 + a] += q.rho * m[0] * q.U[a];
-        Wacc[nv - 1] += 0.5 * q.rho * (m[2] + m[0] * rest);
+        Wacc[nv - 1] += R(0.5) * q.rho * (m[2] + m[0] * rest);
     }
     if (Facc) {
         Facc[0] += q.rho * m[1];
         Facc[1] += q.rho * m[2];
 #pragma unroll
         for (int a = 1; a < D; ++a) Facc[1 + a] += q.rho * m[1] * q.U[a];
-        Facc[nv - 1] += 0.5 * q.rho * (m[3] + m[1] * rest);
+        Facc[nv - 1] += R(0.5) * q.rho * (m[3] + m[1] * rest);
     }
     return true;
 }
 
 // characteristic far-field state (local frame, axis 0 outward)
-template <int D> __device__ void farfield_state(const double *Wl, const double *Wo, double gamma, double *Wb) {
+template <int D, typename R> __device__ void farfield_state(const R *Wl, const R *Wo, R gamma, R *Wb) {
     constexpr int nv = D + 2;
-    Prim<D> I, O;
+    Prim<D, R> I, O;
     I.from(Wl, gamma);
     O.from(Wo, gamma);
-    const double cI = sqrt(gamma * I.p / I.rho), cO = sqrt(gamma * O.p / O.rho);
+    const R cI = sqrt(gamma * I.p / I.rho), cO = sqrt(gamma * O.p / O.rho);
     if (O.U[0] <= -cO) {
 #pragma unroll
         for (int v = 0; v < nv; ++v) Wb[v] = Wo[v];
@@ -390,15 +406,15 @@ template <int D> __device__ void farfield_state(const double *Wl, const double *
         for (int v = 0; v < nv; ++v) Wb[v] = Wl[v];
         return;
     }
-    const double Rp = I.U[0] + 2.0 * cI / (gamma - 1.0);
-    const double Rm = O.U[0] - 2.0 * cO / (gamma - 1.0);
-    const double Un = 0.5 * (Rp + Rm);
-    const double c = 0.25 * (gamma - 1.0) * (Rp - Rm);
-    const Prim<D> &up = Un > 0 ? I : O;
-    const double s = up.p / pow(up.rho, gamma);
-    const double rho = pow(c * c / (gamma * s), 1.0 / (gamma - 1.0));
-    const double p = rho * c * c / gamma;
-    double ke = Un * Un;
+    const R Rp = I.U[0] + R(2.0) * cI / (gamma - R(1.0));
+    const R Rm = O.U[0] - R(2.0) * cO / (gamma - R(1.0));
+    const R Un = R(0.5) * (Rp + Rm);
+    const R c = R(0.25) * (gamma - R(1.0)) * (Rp - Rm);
+    const Prim<D, R> &up = Un > 0 ? I : O;
+    const R s = up.p / pow(up.rho, gamma);
+    const R rho = pow(c * c / (gamma * s), R(1.0) / (gamma - R(1.0)));
+    const R p = rho * c * c / gamma;
+    R ke = Un * Un;
     Wb[0] = rho;
     Wb[1] = rho * Un;
 #pragma unroll
@@ -406,7 +422,7 @@ template <int D> __device__ void farfield_state(const double *Wl, const double *
         Wb[1 + a] = rho * up.U[a];
         ke += up.U[a] * up.U[a];
     }
-    Wb[nv - 1] = p / (gamma - 1.0) + 0.5 * rho * ke;
+    Wb[nv - 1] = p / (gamma - R(1.0)) + R(0.5) * rho * ke;
 }
 
 // normal Euler flux of U along unit n (global frame)
@@ -505,14 +521,14 @@ template <int D> __device__ __forceinline__ void ghost_data(int bc, const double
                                                             double Gg[D][D + 2]) {
     constexpr int nv = D + 2;
     if (bc == 4) {  // far field
-        Frame<D> fr;
+        Frame<D, double> fr;
         fr.build(n);
         double Wl[nv], Wo[nv], Wo_g[nv], Wb[nv];
 #pragma unroll
         for (int v = 0; v < nv; ++v) Wo_g[v] = P.W_inf[v];
         fr.to_local(Wi, Wl);
         fr.to_local(Wo_g, Wo);
-        farfield_state<D>(Wl, Wo, P.gamma, Wb);
+        farfield_state<D, double>(Wl, Wo, P.gamma, Wb);
         fr.to_global(Wb, Wg);
 #pragma unroll
         for (int a = 0; a < D; ++a)
@@ -596,11 +612,11 @@ template <int D> __global__ __launch_bounds__(kBlock) void k_ghost(Dev d) {
 // evaluation records of the block's cells are assembled in LDS and written
 // out as one contiguous, coalesced range.
 constexpr int kReconBlock = 64;
-template <int D> __global__ __launch_bounds__(kReconBlock) void k_recon(Dev d) {
+template <int D, typename R> __global__ __launch_bounds__(kReconBlock) void k_recon(Dev d) {
     using T = Dim<D>;
     constexpr int nv = T::nv, nk = T::nk, nq = T::nq;
     constexpr int ERP = Rec<D>::er + 1;   // padded LDS row
-    __shared__ double rec_lds[kReconBlock * ERP];
+    __shared__ R rec_lds[kReconBlock * ERP];
     const int i0 = blockIdx.x * kReconBlock;
     const int i = i0 + threadIdx.x;
     const int NC = d.NC;
@@ -611,15 +627,15 @@ template <int D> __global__ __launch_bounds__(kReconBlock) void k_recon(Dev d) {
     const double *si = d.st + size_t(i) * RC::sr;
     const double h = gi[D + nq], ih = 1.0 / h;
     double xc[D], own[nq], Wi[nv];
-    double rhs[nk][nv];
+    R rhs[nk][nv];
     // own-gradient rows first: they only touch the linear coefficients
 #pragma unroll
     for (int v = 0; v < nv; ++v) {
         Wi[v] = si[v];
 #pragma unroll
-        for (int a = 0; a < D; ++a) rhs[a][v] = h * si[nv + a * nv + v];
+        for (int a = 0; a < D; ++a) rhs[a][v] = R(h * si[nv + a * nv + v]);
 #pragma unroll
-        for (int q = 0; q < nq; ++q) rhs[D + q][v] = 0.0;
+        for (int q = 0; q < nq; ++q) rhs[D + q][v] = R(0.0);
     }
 #pragma unroll
     for (int a = 0; a < D; ++a) xc[a] = gi[a];
@@ -632,7 +648,7 @@ template <int D> __global__ __launch_bounds__(kReconBlock) void k_recon(Dev d) {
         if (code == 0) break;
         const int f = (code > 0 ? code : -code) - 1;
         const int nb = sl.y;
-        double avg[nk];
+        R avg[nk];
         const double *gd;
         if (nb >= 0) {
             const double sg = code > 0 ? 1.0 : -1.0;
@@ -641,59 +657,60 @@ template <int D> __global__ __launch_bounds__(kReconBlock) void k_recon(Dev d) {
 #pragma unroll
             for (int a = 0; a < D; ++a) {
                 dx[a] = gm[a] + sg * d.shift[a * d.NF + f] - xc[a];
-                avg[a] = dx[a] * ih;
+                avg[a] = R(dx[a] * ih);
             }
 #pragma unroll
             for (int q = 0; q < nq; ++q) {
                 const int a = qa<D>(q), b = qb<D>(q);
-                avg[D + q] = (gm[D + sidx<D>(a, b)] + dx[a] * dx[b]) * ih * ih;
+                avg[D + q] = R((gm[D + sidx<D>(a, b)] + dx[a] * dx[b]) * ih * ih);
             }
             gd = d.st + size_t(nb) * RC::sr;
         } else {
             const int bs = d.bslot[f];
 #pragma unroll
-            for (int k = 0; k < nk; ++k) avg[k] = d.gavg[k * d.NB + bs];
+            for (int k = 0; k < nk; ++k) avg[k] = R(d.gavg[k * d.NB + bs]);
             gd = d.gdat + size_t(bs) * (nv + D * nv);
         }
 #pragma unroll
         for (int v = 0; v < nv; ++v) {
             // average row
-            const double bv = gd[v] - Wi[v];
+            const R bv = R(gd[v] - Wi[v]);
 #pragma unroll
             for (int a = 0; a < D; ++a) rhs[a][v] += avg[a] * bv;
 #pragma unroll
-            for (int q = 0; q < nq; ++q) rhs[D + q][v] += (avg[D + q] - own[q]) * bv;
+            for (int q = 0; q < nq; ++q) rhs[D + q][v] += (avg[D + q] - R(own[q])) * bv;
             // gradient rows
 #pragma unroll
             for (int a = 0; a < D; ++a) {
-                const double bg = h * gd[nv + a * nv + v];
+                const R bg = R(h * gd[nv + a * nv + v]);
                 rhs[a][v] += bg;
 #pragma unroll
                 for (int q = 0; q < nq; ++q) {
                     const int p = qa<D>(q), r = qb<D>(q);
-                    const double row = (p == a ? avg[r] : 0.0) + (r == a ? avg[p] : 0.0);
+                    const R row = (p == a ? avg[r] : R(0.0)) + (r == a ? avg[p] : R(0.0));
                     rhs[D + q][v] += row * bg;
                 }
             }
         }
     }
     // evaluation record: centroid, 1/h, <phi_quad>_i, W, c = Minv rhs
-    double *e = rec_lds + threadIdx.x * ERP;
+    R *e = rec_lds + threadIdx.x * ERP;
 #pragma unroll
-    for (int a = 0; a < D; ++a) e[a] = xc[a];
-    e[D] = ih;
+    for (int a = 0; a < D; ++a) e[a] = R(xc[a]);
+    e[D] = R(ih);
 #pragma unroll
-    for (int q = 0; q < nq; ++q) e[D + 1 + q] = own[q];
+    for (int q = 0; q < nq; ++q) e[D + 1 + q] = R(own[q]);
 #pragma unroll
-    for (int v = 0; v < nv; ++v) e[RC::OW + v] = Wi[v];
+    for (int v = 0; v < nv; ++v) e[RC::OW + v] = R(Wi[v]);
+    const R *minv = HoArrays<R>::minv(d);
 #pragma unroll
     for (int k = 0; k < nk; ++k) {
-        double c[nv];
+        R c[nv];
 #pragma unroll
-        for (int v = 0; v < nv; ++v) c[v] = 0.0;
+        for (int v = 0; v < nv; ++v) c[v] = R(0.0);
 #pragma unroll
         for (int j = 0; j < nk; ++j) {
-            const double mkj = d.minv[midx<D>(k, j) * NC + i];
+            const R mkj = minv[midx<D>(k, j) * NC + i];
 #pragma unroll
             for (int v = 0; v < nv; ++v) c[v] += mkj * rhs[j][v];
         }
@@ -702,7 +719,7 @@ template <int D> __global__ __launch_bounds__(kReconBlock) void k_recon(Dev d) {
     }
     }
     __syncthreads();
-    double *dst = d.ev + size_t(i0) * Rec<D>::er;
+    R *dst = HoArrays<R>::ev(d) + size_t(i0) * Rec<D>::er;
     const int total = ncell * Rec<D>::er;
     for (int k = threadIdx.x; k < total; k += kReconBlock) {
         const int c = k / Rec<D>::er, j = k - c * Rec<D>::er;
@@ -712,46 +729,58 @@ template <int D> __global__ __launch_bounds__(kReconBlock) void k_recon(Dev d) {
 
 // value and gradient of P_i at x (x in cell i's frame), from the cell's
 // evaluation record (read with 16-byte loads)
-template <int D> __device__ __forceinline__ void recon_eval(const Dev &d, int i, const double *x, double *Wx,
-                                                            double G[D][D + 2]) {
+template <typename R> struct Vec16;
+template <> struct Vec16<double> {
+    using T = double2;
+    static constexpr int n = 2;
+    static __device__ __forceinline__ void unpack(const T &t, double *o) { o[0] = t.x; o[1] = t.y; }
+};
+template <> struct Vec16<float> {
+    using T = float4;
+    static constexpr int n = 4;
+    static __device__ __forceinline__ void unpack(const T &t, float *o) { o[0] = t.x; o[1] = t.y; o[2] = t.z; o[3] = t.w; }
+};
+
+template <int D, typename R> __device__ __forceinline__ void recon_eval(const Dev &d, int i, const R *x, R *Wx,
+                                                                        R G[D][D + 2]) {
     using T = Dim<D>;
     using RC = Rec<D>;
+    using V = Vec16<R>;
     constexpr int nv = T::nv, nq = T::nq;
-    const double2 *r2 = reinterpret_cast<const double2 *>(d.ev + size_t(i) * RC::er);
-    double r[RC::OC];
+    const R *base = HoArrays<R>::ev(d) + size_t(i) * RC::er;
+    const typename V::T *rv = reinterpret_cast<const typename V::T *>(base);
+    constexpr int NV = RC::OC / V::n;
+    R r[RC::OC];
 #pragma unroll
-    for (int k = 0; k < RC::OC / 2; ++k) {
-        const double2 t = r2[k];
-        r[2 * k] = t.x;
-        r[2 * k + 1] = t.y;
-    }
-    if constexpr (RC::OC % 2) r[RC::OC - 1] = d.ev[size_t(i) * RC::er + RC::OC - 1];
-    const double ih = r[D];
-    double y[D];
+    for (int k = 0; k < NV; ++k) V::unpack(rv[k], r + V::n * k);
+#pragma unroll
+    for (int k = NV * V::n; k < RC::OC; ++k) r[k] = base[k];
+    const R ih = r[D];
+    R y[D];
 #pragma unroll
     for (int a = 0; a < D; ++a) y[a] = (x[a] - r[a]) * ih;
 #pragma unroll
     for (int v = 0; v < nv; ++v) {
         Wx[v] = r[RC::OW + v];
 #pragma unroll
-        for (int a = 0; a < D; ++a) G[a][v] = 0.0;
+        for (int a = 0; a < D; ++a) G[a][v] = R(0.0);
     }
-    const double *c = d.ev + size_t(i) * RC::er + RC::OC;
+    const R *c = base + RC::OC;
 #pragma unroll
     for (int a = 0; a < D; ++a)
 #pragma unroll
         for (int v = 0; v < nv; ++v) {
-            const double ck = c[a * nv + v];
+            const R ck = c[a * nv + v];
             Wx[v] += ck * y[a];
             G[a][v] += ck;
         }
 #pragma unroll
     for (int q = 0; q < nq; ++q) {
         const int a = qa<D>(q), b = qb<D>(q);
-        const double phi = y[a] * y[b] - r[D + 1 + q];
+        const R phi = y[a] * y[b] - r[D + 1 + q];
 #pragma unroll
         for (int v = 0; v < nv; ++v) {
-            const double ck = c[(D + q) * nv + v];
+            const R ck = c[(D + q) * nv + v];
             Wx[v] += ck * phi;
             G[a][v] += ck * y[b];
             G[b][v] += ck * y[a];
@@ -768,8 +797,22 @@ template <int D> __device__ __forceinline__ void recon_eval(const Dev &d, int i,
 // kinetic interface equilibrium, smooth gas-kinetic flux.  Outputs are
 // weighted by wJ and in the global frame.
 // ---------------------------------------------------------------------
+// Sets bit 0 of flag[c] for the case c of every lane whose state is not
+// physical: one atomic per (wave, case), not one per lane, so a case that
+// has gone bad does not stall the launch on a single contended address.
+// Called by every active lane of the wave.
+__device__ inline void flag_nonphysical(int32_t *flag, bool bad, int c) {
+    unsigned long long m = __ballot(bad);
+    while (m) {
+        const int l = __ffsll(m) - 1;
+        const int cl = __shfl(c, l);
+        if (int(__lane_id()) == l) atomicOr(flag + cl, 1);
+        m &= ~__ballot(bad && c == cl);
+    }
+}
+
 // sum of v over the G consecutive lanes of a face group (every lane gets it)
-template <int G> __device__ __forceinline__ double group_sum(double v) {
+template <int G, typename T> __device__ __forceinline__ T group_sum(T v) {
 #pragma unroll
     for (int m = 1; m < G; m <<= 1) v += __shfl_xor(v, m, G);
     return v;
@@ -780,7 +823,7 @@ template <int G> __device__ __forceinline__ double group_sum(double v) {
 // with weight 0, so every lane runs the same code.  The face sums
 //   sum_g wJ (F0, Ft, W_c n, W_t n)   (global frame)
 // are reduced across the group and written face-major by its first lane.
-template <int D> __global__ __launch_bounds__(kBlock) void k_flux(Dev d, int want_grad) {
+template <int D, typename R> __global__ __launch_bounds__(kBlock) void k_flux(Dev d, int want_grad) {
     using T = Dim<D>;
     constexpr int nv = T::nv, G = T::lanes, FS = T::fs;
     const int t = blockIdx.x * kBlock + threadIdx.x;
@@ -792,31 +835,31 @@ template <int D> __global__ __launch_bounds__(kBlock) void k_flux(Dev d, int wan
     const int g = gp_ok ? g0 + q : g0;
     const int cs = d.fcase[f];
     const DevParams &P = d.prm[cs];
-    const int L = d.fL[f], R = d.fR[f];
-    double x[D], n[D];
+    const int cL = d.fL[f], cR = d.fR[f];
+    R x[D], n[D];
 #pragma unroll
     for (int a = 0; a < D; ++a) {
-        x[a] = d.gx[a * d.NG + g];
-        n[a] = d.gn[a * d.NG + g];
+        x[a] = R(d.gx[a * d.NG + g]);
+        n[a] = R(d.gn[a * d.NG + g]);
     }
-    const double wJ = gp_ok ? d.gw[g] : 0.0;
-    Frame<D> fr;
+    const R wJ = gp_ok ? R(d.gw[g]) : R(0.0);
+    Frame<D, R> fr;
     fr.build(n);
-    double Wc[nv], Gc[D][nv];
+    R Wc[nv], Gc[D][nv];
     bool ok = true;
     const int bc = d.fbc[f];
     {
-        double Wg[nv], GL[D][nv], WL[nv], GLl[D][nv];
-        recon_eval<D>(d, L, x, Wg, GL);
+        R Wg[nv], GL[D][nv], WL[nv], GLl[D][nv];
+        recon_eval<D, R>(d, cL, x, Wg, GL);
         fr.to_local(Wg, WL);
         fr.grad_to_local(GL, GLl);
-        if (R >= 0 || bc != 2) {
-            double WR[nv], GRl[D][nv];
-            if (R >= 0) {
-                double xr[D], WRg[nv], GR[D][nv];
+        if (cR >= 0 || bc != 2) {
+            R WR[nv], GRl[D][nv];
+            if (cR >= 0) {
+                R xr[D], WRg[nv], GR[D][nv];
 #pragma unroll
-                for (int a = 0; a < D; ++a) xr[a] = x[a] - d.shift[a * d.NF + f];
-                recon_eval<D>(d, R, xr, WRg, GR);
+                for (int a = 0; a < D; ++a) xr[a] = x[a] - R(d.shift[a * d.NF + f]);
+                recon_eval<D, R>(d, cR, xr, WRg, GR);
                 fr.to_local(WRg, WR);
                 fr.grad_to_local(GR, GRl);
             } else if (bc == 1) {
@@ -829,90 +872,90 @@ template <int D> __global__ __launch_bounds__(kBlock) void k_flux(Dev d, int wan
                 for (int a = 0; a < D; ++a)
 #pragma unroll
                     for (int v = 0; v < nv; ++v) {
-                        const double sa = (a == 0) ? -1.0 : 1.0;
+                        const R sa = (a == 0) ? -R(1.0) : R(1.0);
                         GRl[a][v] = (v == 1 ? -sa : sa) * GLl[a][v];
                     }
             } else {
-                double Wo_g[nv], Wo[nv];
+                R Wo_g[nv], Wo[nv];
 #pragma unroll
-                for (int v = 0; v < nv; ++v) Wo_g[v] = P.W_inf[v];
+                for (int v = 0; v < nv; ++v) Wo_g[v] = R(P.W_inf[v]);
                 fr.to_local(Wo_g, Wo);
-                farfield_state<D>(WL, Wo, P.gamma, WR);
+                farfield_state<D, R>(WL, Wo, R(P.gamma), WR);
 #pragma unroll
                 for (int a = 0; a < D; ++a)
 #pragma unroll
-                    for (int v = 0; v < nv; ++v) GRl[a][v] = 0.0;
+                    for (int v = 0; v < nv; ++v) GRl[a][v] = R(0.0);
             }
 #pragma unroll
-            for (int v = 0; v < nv; ++v) Wc[v] = 0.0;
-            ok = half_side<D>(WL, P, 1.0, Wc, nullptr) && half_side<D>(WR, P, -1.0, Wc, nullptr);
+            for (int v = 0; v < nv; ++v) Wc[v] = R(0.0);
+            ok = half_side<D, R>(WL, P, R(1.0), Wc, nullptr) && half_side<D, R>(WR, P, -R(1.0), Wc, nullptr);
 #pragma unroll
             for (int a = 0; a < D; ++a)
 #pragma unroll
-                for (int v = 0; v < nv; ++v) Gc[a][v] = 0.5 * (GLl[a][v] + GRl[a][v]);
+                for (int v = 0; v < nv; ++v) Gc[a][v] = R(0.5) * (GLl[a][v] + GRl[a][v]);
         } else {
             // no-slip isothermal wall: (p_L / T_w, 0, p_L), interior gradient
-            Prim<D> pq;
-            pq.from(WL, P.gamma);
+            Prim<D, R> pq;
+            pq.from(WL, R(P.gamma));
 #pragma unroll
-            for (int v = 0; v < nv; ++v) Wc[v] = 0.0;
-            Wc[0] = pq.p / P.T_wall;
-            Wc[nv - 1] = pq.p / (P.gamma - 1.0);
+            for (int v = 0; v < nv; ++v) Wc[v] = R(0.0);
+            Wc[0] = pq.p / R(P.T_wall);
+            Wc[nv - 1] = pq.p / (R(P.gamma) - R(1.0));
 #pragma unroll
             for (int a = 0; a < D; ++a)
 #pragma unroll
                 for (int v = 0; v < nv; ++v) Gc[a][v] = GLl[a][v];
         }
     }
-    double *dst = d.fsum + size_t(f) * FS;
+    R *dst = HoArrays<R>::fsum(d) + size_t(f) * FS;
     const bool writer = face_ok && q == 0;
-    double o[nv];
+    R o[nv];
     // Gauss-Green sums of the interface state at t = 0
     if (want_grad) {
         fr.to_global(Wc, o);
 #pragma unroll
         for (int v = 0; v < nv; ++v) {
-            const double w = ok ? wJ * o[v] : 0.0;
+            const R w = ok ? wJ * o[v] : R(0.0);
 #pragma unroll
             for (int a = 0; a < D; ++a) {
-                const double sum = group_sum<G>(w * n[a]);
+                const R sum = group_sum<G, R>(w * n[a]);
                 if (writer) dst[2 * nv + a * nv + v] = sum;
             }
         }
     }
-    double F0[nv], Ft[nv], Wt[nv];
-    if (ok) ok = gks_flux<D>(Wc, Gc, P, F0, Ft, Wt);
+    R F0[nv], Ft[nv], Wt[nv];
+    if (ok) ok = gks_flux<D, R>(Wc, Gc, P, F0, Ft, Wt);
+    flag_nonphysical(d.flag, !ok && gp_ok, cs);
     if (!ok) {
-        if (gp_ok) atomicOr(d.flag + cs, 1);
 #pragma unroll
-        for (int v = 0; v < nv; ++v) F0[v] = Ft[v] = Wt[v] = 0.0;
+        for (int v = 0; v < nv; ++v) F0[v] = Ft[v] = Wt[v] = R(0.0);
     }
-    if (R < 0 && bc == 2) {
-        F0[0] = 0.0;
-        Ft[0] = 0.0;
+    if (cR < 0 && bc == 2) {
+        F0[0] = R(0.0);
+        Ft[0] = R(0.0);
 #pragma unroll
-        for (int v = 0; v < nv; ++v) Wt[v] = 0.0;
+        for (int v = 0; v < nv; ++v) Wt[v] = R(0.0);
     }
     fr.to_global(F0, o);
 #pragma unroll
     for (int v = 0; v < nv; ++v) {
-        const double sum = group_sum<G>(wJ * o[v]);
+        const R sum = group_sum<G, R>(wJ * o[v]);
         if (writer) dst[v] = sum;
     }
     fr.to_global(Ft, o);
 #pragma unroll
     for (int v = 0; v < nv; ++v) {
-        const double sum = group_sum<G>(wJ * o[v]);
+        const R sum = group_sum<G, R>(wJ * o[v]);
         if (writer) dst[nv + v] = sum;
     }
     if (want_grad) {
         fr.to_global(Wt, o);
 #pragma unroll
         for (int v = 0; v < nv; ++v) {
-            const double w = wJ * o[v];
+            const R w = wJ * o[v];
 #pragma unroll
             for (int a = 0; a < D; ++a) {
-                const double sum = group_sum<G>(w * n[a]);
+                const R sum = group_sum<G, R>(w * n[a]);
                 if (writer) dst[2 * nv + D * nv + a * nv + v] = sum;
             }
         }
@@ -926,7 +969,7 @@ enum { MODE_STAGE0 = 0, MODE_STAGE1 = 1, MODE_R1 = 2 };
 
 // Dim<D>::sl lanes per cell: lane q gathers slots q, q + sl, ...; the sums
 // are reduced across the group and lane q then owns variables q, q + sl.
-template <int D> __global__ __launch_bounds__(kBlock) void k_cell(Dev d, int mode) {
+template <int D, typename R> __global__ __launch_bounds__(kBlock) void k_cell(Dev d, int mode) {
     using T = Dim<D>;
     constexpr int nv = T::nv, SL = T::sl;
     const int t = blockIdx.x * kBlock + threadIdx.x;
@@ -950,35 +993,35 @@ template <int D> __global__ __launch_bounds__(kBlock) void k_cell(Dev d, int mod
         if (code != 0) {
             const int f = (code > 0 ? code : -code) - 1;
             const double sg = code > 0 ? 1.0 : -1.0;
-            const double *src = d.fsum + size_t(f) * T::fs;
+            const R *src = HoArrays<R>::fsum(d) + size_t(f) * T::fs;
 #pragma unroll
             for (int v = 0; v < nv; ++v) {
-                F0s[v] += sg * src[v];
-                Fts[v] += sg * src[nv + v];
+                F0s[v] += sg * double(src[v]);
+                Fts[v] += sg * double(src[nv + v]);
             }
             if (want_g) {
 #pragma unroll
                 for (int a = 0; a < D; ++a)
 #pragma unroll
                     for (int v = 0; v < nv; ++v) {
-                        G0s[a][v] += sg * src[2 * nv + a * nv + v];
-                        Gts[a][v] += sg * src[2 * nv + D * nv + a * nv + v];
+                        G0s[a][v] += sg * double(src[2 * nv + a * nv + v]);
+                        Gts[a][v] += sg * double(src[2 * nv + D * nv + a * nv + v]);
                     }
             }
         }
     }
 #pragma unroll
     for (int v = 0; v < nv; ++v) {
-        F0s[v] = group_sum<SL>(F0s[v]);
-        Fts[v] = group_sum<SL>(Fts[v]);
+        F0s[v] = group_sum<SL, double>(F0s[v]);
+        Fts[v] = group_sum<SL, double>(Fts[v]);
     }
     if (want_g) {
 #pragma unroll
         for (int a = 0; a < D; ++a)
 #pragma unroll
             for (int v = 0; v < nv; ++v) {
-                G0s[a][v] = group_sum<SL>(G0s[a][v]);
-                Gts[a][v] = group_sum<SL>(Gts[a][v]);
+                G0s[a][v] = group_sum<SL, double>(G0s[a][v]);
+                Gts[a][v] = group_sum<SL, double>(Gts[a][v]);
             }
     }
     if (!ok || !P.active) return;
@@ -1062,7 +1105,7 @@ template <int D> __global__ __launch_bounds__(kBlock) void k_low_face(Dev d, con
     double n[D];
 #pragma unroll
     for (int a = 0; a < D; ++a) n[a] = d.avec[a * d.NF + f] * iS;
-    Frame<D> fr;
+    Frame<D, double> fr;
     fr.build(n);
     double UL[nv], Ul[nv], Ur[nv];
     low_state<D>(d, U, dU, soa, L, UL);
@@ -1087,14 +1130,14 @@ template <int D> __global__ __launch_bounds__(kBlock) void k_low_face(Dev d, con
 #pragma unroll
             for (int v = 0; v < nv; ++v) Wo_g[v] = P.W_inf[v];
             fr.to_local(Wo_g, Wo);
-            farfield_state<D>(Ul, Wo, P.gamma, Ur);
+            farfield_state<D, double>(Ul, Wo, P.gamma, Ur);
         }
     }
     double Fl[nv], F[nv];
 #pragma unroll
     for (int v = 0; v < nv; ++v) Fl[v] = 0.0;
-    const bool ok = half_side<D>(Ul, P, 1.0, nullptr, Fl) && half_side<D>(Ur, P, -1.0, nullptr, Fl);
-    if (!ok) atomicOr(d.flag + cs, 1);
+    const bool ok = half_side<D, double>(Ul, P, 1.0, nullptr, Fl) && half_side<D, double>(Ur, P, -1.0, nullptr, Fl);
+    flag_nonphysical(d.flag, !ok, cs);
     fr.to_global(Fl, F);
 #pragma unroll
     for (int v = 0; v < nv; ++v) d.lowf[size_t(f) * nv + v] = ok ? Sf * F[v] : 0.0;
@@ -1131,8 +1174,8 @@ template <int D> __global__ __launch_bounds__(kBlock) void k_low_cell(Dev d, int
         }
     }
 #pragma unroll
-    for (int v = 0; v < nv; ++v) R0[v] = group_sum<SL>(R0[v]);
-    lS = group_sum<SL>(lS);
+    for (int v = 0; v < nv; ++v) R0[v] = group_sum<SL, double>(R0[v]);
+    lS = group_sum<SL, double>(lS);
     if (!ok || !P.active) return;
     double *Ui = d.U + size_t(i) * nv, *dUi = d.dU + size_t(i) * nv;
     if (mode == LOW_R0_OUT) {
@@ -1205,7 +1248,7 @@ template <int D> __global__ __launch_bounds__(kBlock) void k_sweep(Dev d, const 
         }
     }
 #pragma unroll
-    for (int v = 0; v < nv; ++v) acc[v] = group_sum<SL>(acc[v]);
+    for (int v = 0; v < nv; ++v) acc[v] = group_sum<SL, double>(acc[v]);
     if (!ok || !P.active) return;
     const double Di = d.D[i];
 #pragma unroll

@@ -286,14 +286,18 @@ def _fast_ctr(ncell, cell_vs, xyz):
     return ctr
 
 
-def _hybrid_grid(ni, nj, layer_types, gid, tid, coords, classify):
+def _hybrid_grid(ni, nj, layer_types, gid, tid, coords, classify, cells=None):
     """Cells from a structured (i, j, k) hex index space.  layer_types[k] in
     LAYER_TEMPLATES; gid/tid(i, j, k) give geometric/topological vertex ids;
     coords(ids) -> xyz.  Collapsed vertices (poles) are handled generically:
     repeated vertices are removed from each face, faces with < 3 vertices and
-    cells with < 4 faces are dropped."""
-    I, J = np.meshgrid(np.arange(ni), np.arange(nj), indexing="ij")
-    I, J = I.ravel(), J.ravel()
+    cells with < 4 faces are dropped.  cells = (I, J) restricts the surface
+    index pairs used (default: all ni x nj)."""
+    if cells is None:
+        I, J = np.meshgrid(np.arange(ni), np.arange(nj), indexing="ij")
+        I, J = I.ravel(), J.ravel()
+    else:
+        I, J = (np.asarray(c, np.int64) for c in cells)
     faces, cof, cell_vs = [], [], []
     ncell = 0
     for k, lt in enumerate(layer_types):
@@ -400,6 +404,62 @@ def sphere_mesh(n_theta=48, n_phi=96, n_layers=40, n_hex=20, n_prism=10, r_wall=
     lt = sphere_layer_types(n_layers, n_hex, n_prism)
     m = _hybrid_grid(n_theta, n_phi, lt, gid, lambda ids: ids, coords, classify)
     m["name"] = f"sphere_{n_theta}x{n_phi}x{n_layers}"
+    m["r"] = r
+    return m
+
+
+def cubed_sphere_mesh(n=28, n_layers=40, n_hex=20, n_prism=10, r_wall=0.5, r_far=15.0, ratio=1.08,
+                      first_spacing=None, wall=BC_NOSLIP_ISOTHERMAL):
+    """3-D hybrid O-grid around a sphere on a cubed-sphere surface grid: the
+    six faces of a cube, each n x n quads (equiangular gnomonic map), pushed
+    onto the sphere, then extruded through n_layers radial layers of
+    hexahedra, prisms and tetrahedra (see sphere_layer_types).  No surface
+    vertex is singular (at the 8 cube corners three quads meet).  Every
+    patch runs its two index directions along the positive global axes, so
+    the face diagonals of the Kuhn tetrahedra agree across patch edges."""
+    if first_spacing is not None:
+        r = r_wall + first_spacing * (ratio ** np.arange(n_layers + 1) - 1.0) / (ratio - 1.0)
+    else:
+        r = radial_stations(r_wall, r_far, n_layers, ratio)
+    # patch p: (normal axis, sign, i axis, j axis)
+    patches = [(0, -1.0, 1, 2), (0, 1.0, 1, 2), (1, -1.0, 0, 2), (1, 1.0, 0, 2), (2, -1.0, 0, 1), (2, 1.0, 0, 1)]
+    a = np.arange(n + 1)
+    t = np.tan(-0.25 * np.pi + 0.5 * np.pi * a / n)
+    t[0], t[-1] = -1.0, 1.0
+    t[n - a[a > n // 2]] = -t[a > n // 2]          # exact antisymmetry
+    pts = np.zeros((6, n + 1, n + 1, 3))
+    A, B = np.meshgrid(a, a, indexing="ij")
+    for p, (ax, sg, ai, aj) in enumerate(patches):
+        pts[p, :, :, ax] = sg
+        pts[p, :, :, ai] = t[A]
+        pts[p, :, :, aj] = t[B]
+    flat = pts.reshape(-1, 3)
+    key = np.round(flat * (1 << 30)).astype(np.int64)
+    uniq, inv = np.unique(key, axis=0, return_inverse=True)
+    inv = inv.reshape(6, n + 1, n + 1)
+    dirs = np.zeros((len(uniq), 3))
+    dirs[inv.ravel()] = flat
+    dirs /= np.linalg.norm(dirs, axis=1, keepdims=True)
+    n_surf = len(uniq)
+    assert n_surf == 6 * n * n + 2
+
+    def gid(i, j, k):
+        i, j, k = np.broadcast_arrays(np.asarray(i), np.asarray(j), np.asarray(k))
+        return (k * n_surf + inv[i // (n + 1), i % (n + 1), j]).astype(np.int64)
+
+    def coords(ids):
+        return dirs[ids % n_surf] * r[ids // n_surf][:, None]
+
+    rmid = 0.5 * (r[0] + r[-1])
+
+    def classify(fc):
+        return np.where(np.linalg.norm(fc, axis=1) < rmid, wall, BC_FARFIELD)
+
+    P, Ai, Bj = np.meshgrid(np.arange(6), np.arange(n), np.arange(n), indexing="ij")
+    cells = (P.ravel() * (n + 1) + Ai.ravel(), Bj.ravel())
+    lt = sphere_layer_types(n_layers, n_hex, n_prism)
+    m = _hybrid_grid(6 * (n + 1), n + 1, lt, gid, lambda ids: ids, coords, classify, cells=cells)
+    m["name"] = f"cubed_sphere_6x{n}x{n}x{n_layers}"
     m["r"] = r
     return m
 
@@ -551,9 +611,11 @@ def cylinder_case_mesh():
 
 
 def sphere_case_mesh():
-    """48 x 96 x 40 hybrid sphere O-grid, first spacing 0.05597, ratio 1.08,
-    outer radius 15; layers 1-20 hex, 21-30 prisms, 31-40 tets."""
-    return sphere_mesh(48, 96, 40, 20, 10, 0.5, 15.0, 1.08, first_spacing=0.05597)
+    """Cubed-sphere hybrid O-grid, 6 x 28 x 28 surface quads (about the 4608
+    quads of a 48 x 96 latitude-longitude grid, without its polar slivers),
+    40 layers, first spacing 0.05597, ratio 1.08, outer radius 15; layers
+    1-20 hex, 21-30 prisms, 31-40 tets (470,400 cells)."""
+    return cubed_sphere_mesh(28, 40, 20, 10, 0.5, 15.0, 1.08, first_spacing=0.05597)
 
 
 def batch_cases(n_cases=64, seed=2109):

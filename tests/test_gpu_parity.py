@@ -44,13 +44,17 @@ def make_case(name):
         m = I.sphere_mesh(8, 16, 8, 3, 2)
         Winf = I.free_stream(3, 0.25)
         kw = dict(W_inf=Winf, mu=0.25 / 100, Pr=0.72)
+    elif name == "cubed_sphere":
+        m = I.cubed_sphere_mesh(4, 8, 3, 2)
+        Winf = I.free_stream(3, 0.3, 4.0)
+        kw = dict(W_inf=Winf, mu=0.3 / 100, Pr=0.72)
     else:
         raise KeyError(name)
     W, dW = I.smooth_state(m, Winf, seed=11, amp=0.04)
     return m, kw, W, dW
 
 
-CASES = ["cyl2d_slip", "cyl2d_visc", "box2d_per", "box3d_per", "box3d_slip", "sphere"]
+CASES = ["cyl2d_slip", "cyl2d_visc", "box2d_per", "box3d_per", "box3d_slip", "sphere", "cubed_sphere"]
 
 
 class Pair:

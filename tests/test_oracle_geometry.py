@@ -15,6 +15,7 @@ def meshes_3d():
         I.box3d_mesh((2, 3, 5), L=(1.0, 1.5, 2.0)),
         I.box3d_mesh((3, 3, 5), perturb=0.25, seed=3),
         I.sphere_mesh(6, 12, 6, 2, 2, wall=I.BC_FARFIELD),
+        I.cubed_sphere_mesh(3, 6, 2, 2, wall=I.BC_FARFIELD),
     ]
 
 
@@ -148,6 +149,7 @@ def cell_face_sums(mesh, fa, fn):
 @pytest.mark.parametrize("mk", [lambda: I.box3d_mesh((3, 3, 5), perturb=0.3, seed=9),
                                 lambda: I.box3d_mesh((3, 3, 5), perturb=0.2, seed=8, periodic=True),
                                 lambda: I.sphere_mesh(6, 12, 6, 2, 2),
+                                lambda: I.cubed_sphere_mesh(4, 6, 2, 2),
                                 lambda: I.box2d_mesh(5, perturb=0.3, seed=1),
                                 lambda: I.cylinder_mesh(12, 6)])
 def test_closure_and_gauss_green_on_linear_field(mk):
@@ -164,6 +166,7 @@ def test_closure_and_gauss_green_on_linear_field(mk):
 
 @pytest.mark.parametrize("mk", [lambda: I.box3d_mesh((3, 3, 5), perturb=0.3, seed=9),
                                 lambda: I.sphere_mesh(6, 12, 8, 3, 2),
+                                lambda: I.cubed_sphere_mesh(3, 8, 3, 2),
                                 lambda: I.box2d_mesh(6, periodic=False, perturb=0.3, seed=1),
                                 lambda: I.cylinder_mesh(12, 6)])
 def test_reconstruction_exact_for_quadratics(mk):
@@ -231,7 +234,8 @@ def test_reconstruction_exact_for_linear_data_everywhere(mk):
     np.testing.assert_allclose(dWx, np.broadcast_to(G.T[None], dWx.shape), rtol=0, atol=1e-11)
 
 
-@pytest.mark.parametrize("mk", [I.cylinder_case_mesh, lambda: I.sphere_mesh(12, 24, 40)])
+@pytest.mark.parametrize("mk", [I.cylinder_case_mesh, lambda: I.sphere_mesh(12, 24, 40),
+                                lambda: I.cubed_sphere_mesh(8, 40)])
 def test_workload_stencils_are_full_rank(mk):
     """With ghost rows every cell of the cylinder and sphere O-grids fixes a
     full quadratic (no linear fallback)."""
@@ -239,6 +243,7 @@ def test_workload_stencils_are_full_rank(mk):
 
 
 @pytest.mark.parametrize("mk", [I.cylinder_case_mesh, lambda: I.sphere_mesh(8, 16, 8, 3, 2),
+                                lambda: I.cubed_sphere_mesh(4, 8, 3, 2),
                                 lambda: I.box3d_mesh((3, 3, 5), periodic=True)])
 def test_colouring_is_an_independent_set(mk):
     mesh = mk()
@@ -247,3 +252,45 @@ def test_colouring_is_an_independent_set(mk):
     ok = mesh["face_neigh"] >= 0
     assert np.all(col[mesh["face_owner"][ok]] != col[mesh["face_neigh"][ok]])
     assert om.n_colour == col.max() + 1
+
+
+@pytest.mark.parametrize("n,layers", [(3, (6, 2, 2)), (5, (8, 3, 2))])
+def test_cubed_sphere_is_a_valid_conforming_mesh(n, layers):
+    """The cubed-sphere O-grid: every interior face joins exactly two cells
+    (no hanging triangle at patch edges), positive volumes summing to the
+    polyhedral shell, and the expected counts of cells and boundary faces."""
+    nl, nh, npr = layers
+    mesh = I.cubed_sphere_mesh(n, nl, nh, npr, r_far=3.0)
+    nt = nl - nh - npr
+    assert mesh["n_cell"] == 6 * n * n * (nh + 2 * npr + 6 * nt)
+    own, nb, bc = mesh["face_owner"], mesh["face_neigh"], mesh["face_bc"]
+    assert np.all(own >= 0)
+    # boundary faces: 6n^2 wall quads, 12n^2 far-field triangles (tet layer)
+    assert (bc == I.BC_NOSLIP_ISOTHERMAL).sum() == 6 * n * n
+    assert (bc == I.BC_FARFIELD).sum() == 12 * n * n
+    assert np.all((nb < 0) == (bc > 0))
+    cnt = np.bincount(np.concatenate([own, nb[nb >= 0]]), minlength=mesh["n_cell"])
+    assert cnt.min() >= 4
+    ce = oracle.Mesh(mesh).cells()
+    assert ce["vol"].min() > 0
+    # total volume = (1/3) of the boundary integral of x.n over the bilinear
+    # boundary faces (3x3 Gauss, exact for the cubic integrand), computed here
+    # from the vertices alone
+    xyz, ptr, fv = mesh["xyz"], mesh["face_vert_ptr"], mesh["face_vert"]
+    gl = np.array([0.5 - np.sqrt(0.15), 0.5, 0.5 + np.sqrt(0.15)])
+    gw = np.array([5.0, 8.0, 5.0]) / 18.0
+    vol = 0.0
+    for f in np.nonzero(nb < 0)[0]:
+        P = xyz[fv[ptr[f]:ptr[f + 1]]]
+        if len(P) == 3:
+            vol += P[0] @ np.cross(P[1] - P[0], P[2] - P[0]) / 6.0
+            continue
+        for u, wu in zip(gl, gw):
+            for v, wv in zip(gl, gw):
+                x = (1 - u) * (1 - v) * P[0] + u * (1 - v) * P[1] + u * v * P[2] + (1 - u) * v * P[3]
+                xu = (1 - v) * (P[1] - P[0]) + v * (P[2] - P[3])
+                xv = (1 - u) * (P[3] - P[0]) + u * (P[2] - P[1])
+                vol += wu * wv * (x @ np.cross(xu, xv)) / 3.0
+    assert ce["vol"].sum() == pytest.approx(vol, rel=1e-12)
+    # the outer boundary is inscribed in the sphere of radius 3
+    assert vol < 4.0 / 3.0 * np.pi * (3.0 ** 3 - 0.5 ** 3)
