@@ -44,23 +44,82 @@ def workload(name):
     return mesh, kw, desc
 
 
-def algorithmic_bytes(kind, d, NC, NF, NG, NB):
-    """Distinct array elements each kernel reads or writes per launch (FP64
-    values 8 B, int32 indices 4 B), no credit for cache reuse."""
+def layout_sizes(d):
     nv = d + 2
     nk = 5 if d == 2 else 9
     nq = 3 if d == 2 else 6
-    ns = 4 if d == 2 else 8
-    nsym = nk * (nk + 1) // 2
-    if kind == "flux":
-        return (NG * (8 * (2 * d + 1 + 4 * nv) + 4) + NF * (4 * 4 + 8 * d)
-                + NC * 8 * (nv + nk * nv + d + 1 + nq))
-    if kind == "recon":
-        return (NC * (8 * (nv + d * nv + d + 1 + nq + nsym + nk * nv) + 4 * (2 * ns + 1))
-                + NF * 8 * d + NB * (8 * (nk + d + 1) + 8))
-    if kind == "cell":  # stage-0 variant
-        return (NC * (4 * (ns + 1) + 8 * (1 + 5 * nv + 2 * d * nv)) + NG * 8 * (4 * nv + d) + NF * 4)
-    raise KeyError(kind)
+    return dict(nv=nv, nk=nk, nq=nq, ns=4 if d == 2 else 8, nsym=nk * (nk + 1) // 2, sr=nv + d * nv,
+                gr=d + nq + 1, er=d + 1 + nq + nv + nk * nv, fs=2 * nv + 2 * d * nv)
+
+
+def sweep_sequence(n_colour, n_sweeps=2):
+    """Colour classes visited by the sweeps of one implicit step (ascending,
+    descending, repeated; a colour repeated back to back is visited once)."""
+    seq = []
+    for _ in range(n_sweeps):
+        seq += list(range(n_colour)) + list(range(n_colour - 1, -1, -1))
+    out = []
+    for c in seq:
+        if not out or out[-1] != c:
+            out.append(c)
+    return out
+
+
+def algorithmic_bytes(mesh, lm, rbytes):
+    """Bytes per launch of each kernel kind, averaged over its launches in
+    one S2O4 cycle: every distinct array element the kernel reads or writes
+    by definition counted once per launch (no credit for cache re-reads, no
+    charge for misses).  FP64 8 B, high-order arrays rbytes (8 FP64, 4
+    mixed), int32 4 B, int2 8 B.  Returns {kind: (bytes, launches)}."""
+    d = mesh["dim"]
+    z = layout_sizes(d)
+    nv, ns, sr, gr, er, fs, nk = z["nv"], z["ns"], z["sr"], z["gr"], z["er"], z["fs"], z["nk"]
+    NC, NF, NG, NB = lm.n_cell, lm.n_face, lm.n_gp, lm.info.n_boundary_face
+    R = rbytes
+    out = {}
+    out["dt"] = (NC * (8 * nv + 8 + 4), 1)
+    ghost = NB * (8 * sr + 4 + 4 + 4 + 8 * d + 8 + 8 * (nv + d * nv))
+    recon = (NC * (8 * sr + 8 * gr + R * z["nsym"] + 8 * ns + R * er) + NB * (8 * nk + 8 * (nv + d * nv)))
+    out["recon"] = (recon + ghost, 3)          # ghost pre-pass timed with the reconstruction
+    face_idx = NF * (5 * 4 + 8 * d) + 4
+    gp = NG * 8 * (2 * d + 1)
+    flux_grad = NC * R * er + gp + face_idx + NF * R * fs
+    flux_r1 = NC * R * er + gp + face_idx + NF * R * 2 * nv
+    out["flux"] = ((2 * flux_grad + flux_r1) / 3.0, 3)
+    cell_common = NC * (8 * ns + 4 + 8)
+    st0 = cell_common + NF * R * fs + NC * 8 * (nv + 3 * nv + sr + d * nv)
+    st1 = cell_common + NF * R * fs + NC * 8 * (3 * nv + d * nv + sr)
+    r1 = cell_common + NF * R * 2 * nv + NC * 8 * nv
+    out["cell"] = ((st0 + st1 + r1) / 3.0, 3)
+    own, nb = mesh["face_owner"], mesh["face_neigh"]
+    nint = NF - NB
+    lf_common = NF * (4 * 3 + 8 + 8 * d) + 8 * NF * (nv + d + 1)   # indices, S, avec; lowf, swp writes
+    lf_force = lf_common + 8 * nv * (NF + nint)                   # W of both sides
+    lf_first = lf_force
+    lf_step = lf_common + 16 * nv * (NF + nint)                   # U and dU of both sides
+    out["low_face"] = ((lf_force + lf_first + 5 * lf_step) / 7.0, 7)
+    lc_common = NC * (8 * ns + 4) + NF * 8 * (nv + 1)
+    lc_force = lc_common + NC * 8 * (nv + nv + nv + nv + nv)      # R1, W; Sf, U, dU
+    lc_first = lc_common + NC * 8 * (nv + nv + nv + nv + nv + 2 + 1)   # U, Sf; U, RHS, dU; vol, h; D
+    lc_step = lc_first + NC * 8 * nv                              # + dU read
+    out["low_cell"] = ((lc_force + lc_first + 5 * lc_step) / 7.0, 7)
+    # sweeps, per colour class c: per cell of c its slots, case, RHS, D and
+    # the dU write; the face record of every interior face of c (faces of an
+    # independent set are distinct); the U, dU record of every distinct
+    # neighbour
+    colour = np.asarray(lm.colour)
+    inner = nb >= 0
+    a, b2 = own[inner], nb[inner]
+    n_face_c = np.bincount(colour[a], minlength=lm.n_colour) + np.bincount(colour[b2], minlength=lm.n_colour)
+    # distinct (colour of the cell, neighbour) pairs
+    pairs = np.unique(np.concatenate([colour[a].astype(np.int64) * NC + b2, colour[b2].astype(np.int64) * NC + a]))
+    n_nb_c = np.bincount(pairs // NC, minlength=lm.n_colour)
+    n_cell_c = np.bincount(colour, minlength=lm.n_colour)
+    by_colour = n_cell_c * (8 * ns + 4 + 8 * nv + 8 + 8 * nv) + n_face_c * 8 * (d + 1) + n_nb_c * 16 * nv
+    seq = sweep_sequence(lm.n_colour)
+    out["sweep"] = (float(sum(by_colour[c] for c in seq)) / len(seq), 6 * len(seq))
+    out["prolong"] = (NC * 8 * (2 * nv + 2 * nv + 1), 1)
+    return out
 
 
 def cpu_baseline(seconds_hint=30.0):
@@ -159,18 +218,22 @@ def main():
     NC, NF, NG, NB = lm.n_cell, lm.n_face, lm.n_gp, lm.info.n_boundary_face
     d = mesh["dim"]
     value = NC * args.steps / t_clean
-    # dominant kernel by total time
+    # dominant kernel by total time; every kernel's achieved bandwidth
     dom = max(kt, key=lambda k: kt[k][0])
     tot_ms = sum(v[0] for v in kt.values())
-    rf = None
-    if dom in ("flux", "recon", "cell"):
-        avg_ms = kt[dom][0] / kt[dom][1]
-        byt = algorithmic_bytes(dom, d, NC, NF, NG, NB)
-        ach = byt / (avg_ms * 1e-3) / 1e9
-        rf = dict(bound="hbm", kernel=dom, achieved=ach, peak=HBM_PEAK_GBS, unit="GB/s", frac=ach / HBM_PEAK_GBS,
-                  traffic=None, bytes_per_launch=byt, avg_launch_ms=avg_ms)
+    model = algorithmic_bytes(mesh, lm, 8 if prec == cg.FP64 else 4)
+    per_kernel_gbs = {}
+    for k, (ms, n) in kt.items():
+        if n and k in model:
+            per_kernel_gbs[k] = model[k][0] / (ms / n * 1e-3) / 1e9
+    avg_ms = kt[dom][0] / kt[dom][1]
+    byt = model[dom][0]
+    ach = byt / (avg_ms * 1e-3) / 1e9
+    rf = dict(bound="hbm", kernel=dom, achieved=ach, peak=HBM_PEAK_GBS, unit="GB/s", frac=ach / HBM_PEAK_GBS,
+              traffic=None, bytes_per_launch=byt, avg_launch_ms=avg_ms)
     breakdown = {k: dict(ms_per_step=v[0] / args.steps, launches_per_step=v[1] / args.steps,
-                         share=v[0] / tot_ms if tot_ms else 0.0) for k, v in kt.items()}
+                         share=v[0] / tot_ms if tot_ms else 0.0, alg_gbs=per_kernel_gbs.get(k))
+                 for k, v in kt.items()}
     out = dict(metric="cell-updates/s per p-MG cycle", value=value, unit="cell-updates/s", n_gpus=1,
                steps=args.steps, warmup=args.warmup, ms_per_step=1e3 * t_clean / args.steps,
                higher_is_better=True, scaling="weak", vs_baseline=None,

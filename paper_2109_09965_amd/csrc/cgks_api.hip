@@ -51,7 +51,7 @@ struct cgks_batch {
         size_t st, ev, Wn, L0, Lt0, G0, geo, vol, h, minv, slot, cell_case;
         size_t fL, fR, fbc, fcase, gp_off, bslot, avec, S, shift, gavg, bface, gdat;
         size_t gx, gn, gw, fsum, fsum32, ev32, minv32;
-        size_t U, dU, Sf, RHS, D, R1, lowf, swp;
+        size_t U, Sf, RHS, D, R1, lowf, swp;
         size_t prm, dt, res, flag, rb_start, rb_count, rb_case, case_rb_off, part0, part1, cb_start, cb_count;
         size_t res_hist;
     } o{};
@@ -122,8 +122,7 @@ void layout(cgks_batch *b) {
     o.fsum32 = a.take<float>(mixed ? (2 * nv + 2 * d * nv) * NF : 0);
     o.ev32 = a.take<float>(mixed ? er * NC : 0);
     o.minv32 = a.take<float>(mixed ? nk * (nk + 1) / 2 * NC : 0);
-    o.U = a.take<double>(nv * NC);
-    o.dU = a.take<double>(nv * NC);
+    o.U = a.take<double>(2 * nv * NC);
     o.Sf = a.take<double>(nv * NC);
     o.RHS = a.take<double>(nv * NC);
     o.D = a.take<double>(NC);
@@ -189,7 +188,7 @@ void fill_dev(cgks_batch *b) {
     d.fsum32 = at<float>(b, o.fsum32);
     d.ev32 = at<float>(b, o.ev32);
     d.minv32 = at<float>(b, o.minv32);
-    d.U = at<double>(b, o.U); d.dU = at<double>(b, o.dU); d.Sf = at<double>(b, o.Sf);
+    d.U = at<double>(b, o.U); d.dU = d.U + (b->dim + 2); d.Sf = at<double>(b, o.Sf);
     d.RHS = at<double>(b, o.RHS); d.D = at<double>(b, o.D); d.R1 = at<double>(b, o.R1);
     d.lowf = at<double>(b, o.lowf); d.swp = at<double>(b, o.swp);
     d.prm = at<DevParams>(b, o.prm); d.dt = at<double>(b, o.dt); d.res = at<double>(b, o.res);
@@ -256,7 +255,7 @@ template <int D> cgks_status launch_highorder(cgks_batch *b, int mode, hipStream
     if (mode == MODE_STAGE0) {
         timed(b, CGKS_K_DT, s, [&] {
             hipLaunchKernelGGL(k_dt_partial<D>, dim3(b->rb_start.size()), dim3(kBlock), 0, s, d);
-            hipLaunchKernelGGL(k_dt_final, dim3(nblk(b->n_case)), dim3(kBlock), 0, s, d, b->n_case);
+            hipLaunchKernelGGL(k_dt_final, dim3(b->n_case), dim3(kBlock), 0, s, d, b->n_case);
         });
     }
     if (b->precision == CGKS_MIXED32) launch_ho_kernels<D, float>(b, mode, s);
@@ -312,7 +311,7 @@ template <int D> cgks_status launch_lowlevel(cgks_batch *b, const double *R1, hi
     }
     timed(b, CGKS_K_PROLONG, s, [&] {
         hipLaunchKernelGGL(k_prolong_res<D>, dim3(b->rb_start.size()), dim3(kBlock), 0, s, d, 1);
-        hipLaunchKernelGGL(k_res_final, dim3(nblk(b->n_case)), dim3(kBlock), 0, s, d, b->n_case);
+        hipLaunchKernelGGL(k_res_final, dim3(b->n_case), dim3(kBlock), 0, s, d, b->n_case);
     });
     HIP_TRY(hipGetLastError());
     return CGKS_OK;
@@ -328,7 +327,7 @@ template <int D> cgks_status launch_cycle(cgks_batch *b, hipStream_t s) {
     if (b->explicit_only) {
         timed(b, CGKS_K_PROLONG, s, [&] {
             hipLaunchKernelGGL(k_prolong_res<D>, dim3(b->rb_start.size()), dim3(kBlock), 0, s, b->dev, 0);
-            hipLaunchKernelGGL(k_res_final, dim3(nblk(b->n_case)), dim3(kBlock), 0, s, b->dev, b->n_case);
+            hipLaunchKernelGGL(k_res_final, dim3(b->n_case), dim3(kBlock), 0, s, b->dev, b->n_case);
         });
         HIP_TRY(hipGetLastError());
         return CGKS_OK;

@@ -51,7 +51,9 @@ struct Dev {
     const double *gx, *gn, *gw;
     double *fsum;      // per face [NF][2 nv + 2 D nv]: sum_g wJ (F0, Ft, W_c n, W_t n)
     float *fsum32;     // the same in FP32 (mixed-precision batches)
-    // low level: U, dU cell-major [NC][nv] (gathered by neighbours), Sf, RHS, R1 [nv][NC]
+    // low level: U and dU interleaved cell-major [NC][2 nv] (U = base, dU =
+    // base + nv, stride 2 nv; a neighbour gather reads one 80-byte record),
+    // Sf, RHS, R1 [nv][NC]
     double *U, *dU, *Sf, *RHS, *D, *R1;
     double *lowf;      // [NF][nv]: S_f F_kfvs
     double *swp;       // [NF][4]: area vector S_f n_f (D values), S_f lam_f
@@ -98,6 +100,7 @@ template <int D> struct Dim {
     static constexpr int lanes = D == 2 ? 2 : 4;   // threads per face (one per Gauss point)
     static constexpr int sl = 4;                   // threads per cell in the slot gathers
     static constexpr int fs = 2 * nv + 2 * D * nv; // face sums per face
+    static constexpr int us = 2 * nv;              // stride of the interleaved U, dU records
 };
 
 // quadratic basis (a, b) pairs: 2-D (00, 01, 11); 3-D (00, 11, 22, 01, 02, 12)
@@ -460,6 +463,17 @@ template <int D> __device__ __forceinline__ double state_dt(const double *U, dou
     return cfl * h / (sqrt(ke) + c + 2.0 * P.mu / rho / h);
 }
 
+// Workgroups are handed to the 8 XCDs round-robin (block b runs on XCD
+// b mod 8), each XCD with its own L2.  xcd_block renumbers the launch so
+// that every XCD works through one contiguous range of logical blocks:
+// neighbouring cells and faces, which share gathered records, then meet
+// in the same L2.  A bijection of [0, nb).
+constexpr int kXcd = 8;
+__device__ __forceinline__ int xcd_block(int b, int nb) {
+    const int x = b % kXcd, k = b / kXcd, per = nb / kXcd, rem = nb % kXcd;
+    return x * per + min(x, rem) + k;
+}
+
 __device__ __forceinline__ double block_reduce_sum(double v, double *sh) {
     const int t = threadIdx.x;
     sh[t] = v;
@@ -500,15 +514,17 @@ template <int D> __global__ __launch_bounds__(kBlock) void k_dt_partial(Dev d) {
     if (threadIdx.x == 0) d.part0[b] = v;
 }
 
-// one thread per case: sequential min / sums in block order (fixed shape)
-__global__ void k_dt_final(Dev d, int n_case) {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= n_case) return;
+// one block per case: thread t folds the case's block partials t, t + kBlock,
+// ... in order, then a block tree; the shape depends only on the case
+__global__ __launch_bounds__(kBlock) void k_dt_final(Dev d, int n_case) {
+    __shared__ double sh[kBlock];
+    const int c = blockIdx.x;
     const DevParams &P = d.prm[c];
     if (!P.active) return;
     double v = INFINITY;
-    for (int b = d.case_rb_off[c]; b < d.case_rb_off[c + 1]; ++b) v = fmin(v, d.part0[b]);
-    d.dt[c] = P.dt_fixed > 0 ? P.dt_fixed : v;
+    for (int b = d.case_rb_off[c] + threadIdx.x; b < d.case_rb_off[c + 1]; b += kBlock) v = fmin(v, d.part0[b]);
+    v = block_reduce_min(v, sh);
+    if (threadIdx.x == 0) d.dt[c] = P.dt_fixed > 0 ? P.dt_fixed : v;
 }
 
 // ---------------------------------------------------------------------
@@ -617,7 +633,7 @@ template <int D, typename R> __global__ __launch_bounds__(kReconBlock) void k_re
     constexpr int nv = T::nv, nk = T::nk, nq = T::nq;
     constexpr int ERP = Rec<D>::er + 1;   // padded LDS row
     __shared__ R rec_lds[kReconBlock * ERP];
-    const int i0 = blockIdx.x * kReconBlock;
+    const int i0 = xcd_block(blockIdx.x, gridDim.x) * kReconBlock;
     const int i = i0 + threadIdx.x;
     const int NC = d.NC;
     const int ncell = min(kReconBlock, NC - i0);
@@ -826,7 +842,7 @@ template <int G, typename T> __device__ __forceinline__ T group_sum(T v) {
 template <int D, typename R> __global__ __launch_bounds__(kBlock) void k_flux(Dev d, int want_grad) {
     using T = Dim<D>;
     constexpr int nv = T::nv, G = T::lanes, FS = T::fs;
-    const int t = blockIdx.x * kBlock + threadIdx.x;
+    const int t = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
     const int fr_raw = t / G, q = t % G;
     const bool face_ok = fr_raw < d.NF;
     const int f = face_ok ? fr_raw : d.NF - 1;
@@ -972,7 +988,7 @@ enum { MODE_STAGE0 = 0, MODE_STAGE1 = 1, MODE_R1 = 2 };
 template <int D, typename R> __global__ __launch_bounds__(kBlock) void k_cell(Dev d, int mode) {
     using T = Dim<D>;
     constexpr int nv = T::nv, SL = T::sl;
-    const int t = blockIdx.x * kBlock + threadIdx.x;
+    const int t = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
     const int ir = t / SL, q = t % SL;
     const bool ok = ir < d.NC;
     const int i = ok ? ir : d.NC - 1;
@@ -1088,14 +1104,15 @@ template <int D> __device__ __forceinline__ void low_state(const Dev &d, const d
         for (int v = 0; v < nv; ++v) out[v] = U[size_t(i) * Rec<D>::sr + v];
     } else {
 #pragma unroll
-        for (int v = 0; v < nv; ++v) out[v] = dU ? U[i * nv + v] + dU[i * nv + v] : U[i * nv + v];
+        for (int v = 0; v < nv; ++v)
+            out[v] = dU ? U[size_t(i) * 2 * nv + v] + dU[size_t(i) * 2 * nv + v] : U[size_t(i) * 2 * nv + v];
     }
 }
 
 // lowf[f] = S_f F_kfvs(U_L, U_R; n_f); swp[f] = (S_f n_f, S_f lam_f).
 template <int D> __global__ __launch_bounds__(kBlock) void k_low_face(Dev d, const double *U, const double *dU, int soa) {
     constexpr int nv = D + 2;
-    const int f = blockIdx.x * kBlock + threadIdx.x;
+    const int f = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
     if (f >= d.NF) return;
     const int cs = d.fcase[f];
     const DevParams &P = d.prm[cs];
@@ -1152,7 +1169,7 @@ enum { LOW_FORCE = 0, LOW_STEP_FIRST = 1, LOW_STEP = 2, LOW_R0_OUT = 3 };
 template <int D> __global__ __launch_bounds__(kBlock) void k_low_cell(Dev d, int mode, double *out) {
     using T = Dim<D>;
     constexpr int nv = T::nv, SL = T::sl;
-    const int t = blockIdx.x * kBlock + threadIdx.x;
+    const int t = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
     const int ir = t / SL, q = t % SL;
     const bool ok = ir < d.NC;
     const int i = ok ? ir : d.NC - 1;
@@ -1177,7 +1194,7 @@ template <int D> __global__ __launch_bounds__(kBlock) void k_low_cell(Dev d, int
     for (int v = 0; v < nv; ++v) R0[v] = group_sum<SL, double>(R0[v]);
     lS = group_sum<SL, double>(lS);
     if (!ok || !P.active) return;
-    double *Ui = d.U + size_t(i) * nv, *dUi = d.dU + size_t(i) * nv;
+    double *Ui = d.U + size_t(i) * T::us, *dUi = d.dU + size_t(i) * T::us;
     if (mode == LOW_R0_OUT) {
 #pragma unroll
         for (int v = 0; v < nv; ++v)
@@ -1214,7 +1231,7 @@ template <int D> __global__ __launch_bounds__(kBlock) void k_sweep(Dev d, const 
                                                                    const int32_t *blk_count) {
     using T = Dim<D>;
     constexpr int nv = T::nv, SL = T::sl;
-    const int b = blockIdx.x;
+    const int b = xcd_block(blockIdx.x, gridDim.x);
     const int lc = threadIdx.x / SL, q = threadIdx.x % SL;
     const bool ok = lc < blk_count[b];
     const int i = blk_start[b] + (ok ? lc : 0);
@@ -1237,8 +1254,8 @@ template <int D> __global__ __launch_bounds__(kBlock) void k_sweep(Dev d, const 
             const double sl_lam = w[D];
 #pragma unroll
             for (int v = 0; v < nv; ++v) {
-                Um[v] = d.U[size_t(nb) * nv + v];
-                dUm[v] = d.dU[size_t(nb) * nv + v];
+                Um[v] = d.U[size_t(nb) * T::us + v];
+                dUm[v] = d.dU[size_t(nb) * T::us + v];
                 Up[v] = Um[v] + dUm[v];
             }
             euler_flux<D>(Up, A, P.gamma, Fa);
@@ -1253,7 +1270,7 @@ template <int D> __global__ __launch_bounds__(kBlock) void k_sweep(Dev d, const 
     const double Di = d.D[i];
 #pragma unroll
     for (int v = 0; v < nv; ++v)
-        if (v % SL == q) d.dU[size_t(i) * nv + v] = (d.RHS[v * NC + i] - acc[v]) / Di;
+        if (v % SL == q) d.dU[size_t(i) * T::us + v] = (d.RHS[v * NC + i] - acc[v]) / Di;
 }
 
 // W += (U + dU) - W_p0 (W_p0 = W); partial sums of |rho - rho^n| and rho^n.
@@ -1272,7 +1289,7 @@ template <int D> __global__ __launch_bounds__(kBlock) void k_prolong_res(Dev d, 
         if (prolong && P.active) {
 #pragma unroll
             for (int v = 0; v < nv; ++v) {
-                const double u6 = d.U[size_t(i) * nv + v] + d.dU[size_t(i) * nv + v];
+                const double u6 = d.U[size_t(i) * 2 * nv + v] + d.dU[size_t(i) * 2 * nv + v];
                 const double w = d.st[size_t(i) * Rec<D>::sr + v];
                 d.st[size_t(i) * Rec<D>::sr + v] = w + (u6 - w);
             }
@@ -1294,16 +1311,18 @@ __global__ void k_res_store(const double *res, double *hist, int n_case) {
     if (c < n_case) hist[c] = res[c];
 }
 
-__global__ void k_res_final(Dev d, int n_case) {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= n_case) return;
+__global__ __launch_bounds__(kBlock) void k_res_final(Dev d, int n_case) {
+    __shared__ double sh[kBlock];
+    const int c = blockIdx.x;
     if (!d.prm[c].active) return;
     double a = 0, b = 0;
-    for (int k = d.case_rb_off[c]; k < d.case_rb_off[c + 1]; ++k) {
+    for (int k = d.case_rb_off[c] + threadIdx.x; k < d.case_rb_off[c + 1]; k += kBlock) {
         a += d.part0[k];
         b += d.part1[k];
     }
-    d.res[c] = a / b;
+    a = block_reduce_sum(a, sh);
+    b = block_reduce_sum(b, sh);
+    if (threadIdx.x == 0) d.res[c] = a / b;
 }
 
 }  // namespace cgks
