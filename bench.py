@@ -20,7 +20,29 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
-FP64_VECTOR_TFLOPS = 78.6      # MI355X FP64 vector
+VALU_PEAK_TFLOPS = {"fp64": 78.6, "mixed32": 157.3}   # MI355X vector FP64 / FP32 (published)
+
+# Floating-point operations of the high-order flux kernel per Gauss point
+# (FMA = 2), from the VALU instruction counters of one launch on the
+# sphere workload (SQ_INSTS_VALU_{FMA,MUL,ADD,TRANS}_F64 resp. _F32, x 64
+# lanes), charged to the lanes that carry a Gauss point.
+FLUX_FLOP_PER_GP = {"fp64": 2899.0, "mixed32": 2696.0}
+
+# HBM bytes per launch from rocprofv3 FETCH_SIZE (x 2.0) and WRITE_SIZE
+# (x 1.0) on the sphere workload, each factor from a plain device copy of
+# known size.  Valid only for the kernel source they were taken on (its
+# SHA-256); any other source reports null.
+PROFILED_KERNELS_SHA256 = "3d63e21862689c12b96f12bd270a60d2f73d35d323e1ee6899e5aeed104fe1a3"
+PROFILED_TRAFFIC = {           # (kernel kind, precision) -> bytes per launch
+    ("dt", "fp64"): 79179622.0,
+    ("recon", "fp64"): 970351085.0 + 6110348.0,     # reconstruction + boundary ghost pre-pass
+    ("flux", "fp64"): 1141701316.0,
+    ("cell", "fp64"): 878857194.0,
+    ("low_face", "fp64"): 209826079.0,
+    ("low_cell", "fp64"): 396982122.0,
+    ("sweep", "fp64"): 53889279.0,
+    ("prolong", "fp64"): 173899913.0,
+}
 
 
 def workload(name):
@@ -42,6 +64,13 @@ def workload(name):
     else:
         raise SystemExit(f"unknown workload {name}")
     return mesh, kw, desc
+
+
+def kernels_sha256():
+    import hashlib
+    path = os.path.join(ROOT, "paper_2109_09965_amd", "csrc", "kernels.h")
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
 
 
 def layout_sizes(d):
@@ -227,10 +256,18 @@ def main():
         if n and k in model:
             per_kernel_gbs[k] = model[k][0] / (ms / n * 1e-3) / 1e9
     avg_ms = kt[dom][0] / kt[dom][1]
-    byt = model[dom][0]
-    ach = byt / (avg_ms * 1e-3) / 1e9
-    rf = dict(bound="hbm", kernel=dom, achieved=ach, peak=HBM_PEAK_GBS, unit="GB/s", frac=ach / HBM_PEAK_GBS,
-              traffic=None, bytes_per_launch=byt, avg_launch_ms=avg_ms)
+    traffic = PROFILED_TRAFFIC.get((dom, args.precision)) if kernels_sha256() == PROFILED_KERNELS_SHA256 else None
+    if dom == "flux":
+        flop = FLUX_FLOP_PER_GP[args.precision] * NG
+        ach = flop / (avg_ms * 1e-3) / 1e12
+        peak = VALU_PEAK_TFLOPS[args.precision]
+        rf = dict(bound="alu", kernel=dom, achieved=ach, peak=peak, unit="TFLOP/s", frac=ach / peak,
+                  traffic=traffic, flop_per_launch=flop, alg_bytes_per_launch=model[dom][0], avg_launch_ms=avg_ms)
+    else:
+        byt = model[dom][0]
+        ach = byt / (avg_ms * 1e-3) / 1e9
+        rf = dict(bound="hbm", kernel=dom, achieved=ach, peak=HBM_PEAK_GBS, unit="GB/s", frac=ach / HBM_PEAK_GBS,
+                  traffic=traffic, bytes_per_launch=byt, avg_launch_ms=avg_ms)
     breakdown = {k: dict(ms_per_step=v[0] / args.steps, launches_per_step=v[1] / args.steps,
                          share=v[0] / tot_ms if tot_ms else 0.0, alg_gbs=per_kernel_gbs.get(k))
                  for k, v in kt.items()}

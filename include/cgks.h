@@ -227,12 +227,16 @@ typedef struct {
    found non-physical or diverging, stops being updated at that check. */
 cgks_status cgks_solve(cgks_batch *batch, const cgks_solve_opts *opts, cgks_solve_report *report, void *stream);
 
-/* Kernel timing.  enable = 1 brackets every kernel launch of the batch with
-   a pair of HIP events recorded on the launch stream; cgks_timing_read
+/* Kernel timing.  enable = 1 brackets the kernel launches of the batch with
+   pairs of HIP events recorded on the launch stream: one pair per launch,
+   except that the back-to-back colour passes of one implicit step share
+   one pair (their span, gaps between the passes included).  The reduction
+   kinds count their final per-case kernel with them, and RECON counts the
+   boundary ghost pre-pass with the reconstruction.  cgks_timing_read
    synchronises those events and returns, per kernel kind, the summed
-   duration in milliseconds and the number of launches since the previous
-   read (then starts a new interval).  ms and launches are host arrays of
-   CGKS_KERNEL_KINDS entries. */
+   duration in milliseconds and the number of launches of the kind's main
+   kernel since the previous read (then starts a new interval).  ms and
+   launches are host arrays of CGKS_KERNEL_KINDS entries. */
 enum {
     CGKS_K_DT = 0,        /* global time-step reduction */
     CGKS_K_RECON = 1,     /* compact reconstruction */

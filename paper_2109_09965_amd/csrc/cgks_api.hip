@@ -60,7 +60,12 @@ struct cgks_batch {
     // kernel timing: event pairs recorded around launches
     bool timing = false;
     std::vector<hipEvent_t> events;
-    std::vector<std::pair<int, size_t>> recs;   // (kind, index of the start event)
+    struct TimingRec {
+        int kind;
+        size_t ev;        // index of the start event; the end event follows
+        int launches;     // kernel launches between the two events
+    };
+    std::vector<TimingRec> recs;
     // captured cycles
     hipGraphExec_t graph_exec = nullptr;
     hipGraph_t graph = nullptr;
@@ -208,8 +213,9 @@ template <class T> hipError_t put(cgks_batch *b, size_t off, const std::vector<T
 
 inline unsigned nblk(int64_t n) { return unsigned((n + kBlock - 1) / kBlock); }
 
-// Launch `launch()` bracketed by two events when timing is enabled.
-template <class F> void timed(cgks_batch *b, int kind, hipStream_t s, F &&launch) {
+// Launch `launch()` (which issues `launches` kernels back to back)
+// bracketed by two events when timing is enabled.
+template <class F> void timed(cgks_batch *b, int kind, hipStream_t s, F &&launch, int launches = 1) {
     if (!b->timing) {
         launch();
         return;
@@ -226,7 +232,7 @@ template <class F> void timed(cgks_batch *b, int kind, hipStream_t s, F &&launch
     (void)hipEventRecord(b->events[k], s);
     launch();
     (void)hipEventRecord(b->events[k + 1], s);
-    b->recs.emplace_back(kind, k);
+    b->recs.push_back({kind, k, launches});
 }
 
 #define HIP_TRY(x)                                      \
@@ -300,14 +306,21 @@ template <int D> cgks_status launch_lowlevel(cgks_batch *b, const double *R1, hi
             hipLaunchKernelGGL(k_low_cell<D>, dim3(nblk(b->NC * Dim<D>::sl)), dim3(kBlock), 0, s, d,
                                (int)(k ? LOW_STEP : LOW_STEP_FIRST), (double *)nullptr);
         });
-        for (int c : order) {
-            const int64_t b0 = b->colour_blk_off[c], nb = b->colour_blk_off[c + 1] - b0;
-            if (nb == 0) continue;
-            timed(b, CGKS_K_SWEEP, s, [&] {
-                hipLaunchKernelGGL(k_sweep<D>, dim3(unsigned(nb)), dim3(kBlock), 0, s, d,
-                                   (const int32_t *)(b->d_cb_start + b0), (const int32_t *)(b->d_cb_count + b0));
-            });
-        }
+        // the colour passes of one step run back to back: one timing span
+        int n_pass = 0;
+        for (int c : order) n_pass += b->colour_blk_off[c + 1] > b->colour_blk_off[c];
+        timed(
+            b, CGKS_K_SWEEP, s,
+            [&] {
+                for (int c : order) {
+                    const int64_t b0 = b->colour_blk_off[c], nb = b->colour_blk_off[c + 1] - b0;
+                    if (nb == 0) continue;
+                    hipLaunchKernelGGL(k_sweep<D>, dim3(unsigned(nb)), dim3(kBlock), 0, s, d,
+                                       (const int32_t *)(b->d_cb_start + b0),
+                                       (const int32_t *)(b->d_cb_count + b0));
+                }
+            },
+            n_pass);
     }
     timed(b, CGKS_K_PROLONG, s, [&] {
         hipLaunchKernelGGL(k_prolong_res<D>, dim3(b->rb_start.size()), dim3(kBlock), 0, s, d, 1);
@@ -849,11 +862,11 @@ cgks_status cgks_timing_read(cgks_batch *b, double *ms, int64_t *launches) {
         launches[k] = 0;
     }
     for (auto &r : b->recs) {
-        HIP_TRY(hipEventSynchronize(b->events[r.second + 1]));
+        HIP_TRY(hipEventSynchronize(b->events[r.ev + 1]));
         float t = 0.0f;
-        HIP_TRY(hipEventElapsedTime(&t, b->events[r.second], b->events[r.second + 1]));
-        ms[r.first] += t;
-        launches[r.first] += 1;
+        HIP_TRY(hipEventElapsedTime(&t, b->events[r.ev], b->events[r.ev + 1]));
+        ms[r.kind] += t;
+        launches[r.kind] += r.launches;
     }
     b->recs.clear();
     return CGKS_OK;
