@@ -218,6 +218,7 @@ typedef struct {
     int32_t converged;
     double res_first, res_last;
     cgks_status status;    /* CGKS_OK, CGKS_ENOTCONV, CGKS_ENONPHYS, CGKS_EDIVERGED */
+    double force[3];       /* wall force at the start of the case's last cycle (see cgks_wall_force) */
 } cgks_solve_report;
 
 /* Cycle until every case meets its tolerance or max_cycles; report[n_case]
@@ -226,6 +227,19 @@ typedef struct {
    replaces a graph made by cgks_graph_create).  A case that meets its tolerance, or is
    found non-physical or diverging, stops being updated at that check. */
 cgks_status cgks_solve(cgks_batch *batch, const cgks_solve_opts *opts, cgks_solve_report *report, void *stream);
+
+/* Force of the gas on the walls of each case (Sec. 4, sphere and cylinder
+   drag): the sum over slip and no-slip boundary faces of the face-quadrature
+   sum of the momentum components of the smooth flux F0, that is pressure
+   plus viscous stress, with the face normal pointing out of the fluid.  It
+   is taken in the first high-order pass (stage 0) of every cycle, at the
+   state the cycle starts from; a case frozen by cgks_solve keeps the force
+   of its last cycle.  force: host [n_case][3] (the z entry is 0 in 2-D),
+   written after the work queued on stream has finished.  The drag
+   coefficient is force . e_inf / (1/2 rho_inf |U_inf|^2 A_ref).  MIXED32
+   batches sum FP32 face sums (in FP64).  CGKS_EINVAL on a NULL argument or
+   an unbound batch. */
+cgks_status cgks_wall_force(cgks_batch *batch, double *force, void *stream);
 
 /* Kernel timing.  enable = 1 brackets the kernel launches of the batch with
    pairs of HIP events recorded on the launch stream: one pair per launch,

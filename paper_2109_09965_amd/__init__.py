@@ -27,7 +27,7 @@ EXPORTS = ["cgks_status_string", "cgks_mesh_create", "cgks_mesh_query", "cgks_me
            "cgks_mesh_geometry", "cgks_mesh_destroy", "cgks_batch_create", "cgks_batch_query", "cgks_batch_bind", "cgks_batch_destroy",
            "cgks_state_upload", "cgks_state_download", "cgks_state_device", "cgks_highorder_stage",
            "cgks_residual", "cgks_lowlevel_smooth", "cgks_cycle", "cgks_solve", "cgks_timing_enable",
-           "cgks_timing_read", "cgks_graph_create", "cgks_graph_launch", "cgks_graph_destroy"]
+           "cgks_timing_read", "cgks_graph_create", "cgks_graph_launch", "cgks_graph_destroy", "cgks_wall_force"]
 KERNEL_KINDS = ["dt", "recon", "flux", "cell", "low_face", "low_cell", "sweep", "prolong"]
 
 
@@ -64,7 +64,7 @@ class _SolveOpts(C.Structure):
 
 class _SolveReport(C.Structure):
     _fields_ = [("cycles", C.c_int32), ("converged", C.c_int32), ("res_first", C.c_double),
-                ("res_last", C.c_double), ("status", C.c_int)]
+                ("res_last", C.c_double), ("status", C.c_int), ("force", C.c_double * 3)]
 
 
 def lib():
@@ -108,6 +108,7 @@ def lib():
         L.cgks_graph_launch.argtypes = [P, P, P]
         L.cgks_graph_destroy.argtypes = [P]
         L.cgks_timing_read.argtypes = [P, P, P]
+        L.cgks_wall_force.argtypes = [P, P, P]
         for name in EXPORTS:
             getattr(L, name).restype = C.c_int if name != "cgks_status_string" else C.c_char_p
         _lib = L
@@ -282,6 +283,12 @@ class Batch:
         ptr = C.c_void_p(res_history.data_ptr()) if res_history is not None else None
         _check(lib().cgks_graph_launch(self.h, ptr, _stream(self.stream)), "cgks_graph_launch")
 
+    def wall_force(self):
+        """[n_case, 3] force of the gas on the walls at the start of the latest cycle."""
+        f = np.zeros((self.n_case, 3))
+        _check(lib().cgks_wall_force(self.h, _ptr(f), _stream(self.stream)), "cgks_wall_force")
+        return f
+
     def timing(self, enable=True):
         _check(lib().cgks_timing_enable(self.h, int(enable)), "cgks_timing_enable")
 
@@ -301,5 +308,15 @@ class Batch:
         rep = (_SolveReport * self.n_case)()
         _check(lib().cgks_solve(self.h, C.byref(opts), rep, _stream(self.stream)), "cgks_solve")
         out = [dict(cycles=r.cycles, converged=bool(r.converged), res_first=r.res_first, res_last=r.res_last,
-                    status=r.status) for r in rep]
+                    status=r.status, force=np.array(r.force[:])) for r in rep]
         return out, hist
+
+
+def drag_coefficient(force, W_inf, area):
+    """Cd = F . e_inf / (1/2 rho_inf |U_inf|^2 A_ref) from a wall force."""
+    W_inf = np.asarray(W_inf, float)
+    d = len(W_inf) - 2
+    rho = W_inf[0]
+    U = W_inf[1:1 + d] / rho
+    q = 0.5 * rho * float(U @ U)
+    return float(np.asarray(force)[:d] @ (U / np.sqrt(U @ U))) / (q * area)

@@ -52,7 +52,8 @@ struct cgks_batch {
         size_t fL, fR, fbc, fcase, gp_off, bslot, avec, S, shift, gavg, bface, gdat;
         size_t gx, gn, gw, fsum, fsum32, ev32, minv32;
         size_t U, Sf, RHS, D, R1, lowf, swp;
-        size_t prm, dt, res, flag, rb_start, rb_count, rb_case, case_rb_off, part0, part1, cb_start, cb_count;
+        size_t prm, dt, res, force, case_b_off, flag, rb_start, rb_count, rb_case, case_rb_off, part0, part1,
+            cb_start, cb_count;
         size_t res_hist;
     } o{};
     Dev dev{};
@@ -137,6 +138,8 @@ void layout(cgks_batch *b) {
     o.prm = a.take<DevParams>(b->n_case);
     o.dt = a.take<double>(b->n_case);
     o.res = a.take<double>(b->n_case);
+    o.force = a.take<double>(3 * size_t(b->n_case));
+    o.case_b_off = a.take<int32_t>(b->n_case + 1);
     o.flag = a.take<int32_t>(b->n_case);
     o.rb_start = a.take<int32_t>(b->rb_start.size());
     o.rb_count = a.take<int32_t>(b->rb_start.size());
@@ -198,6 +201,7 @@ void fill_dev(cgks_batch *b) {
     d.lowf = at<double>(b, o.lowf); d.swp = at<double>(b, o.swp);
     d.prm = at<DevParams>(b, o.prm); d.dt = at<double>(b, o.dt); d.res = at<double>(b, o.res);
     d.flag = at<int32_t>(b, o.flag);
+    d.force = at<double>(b, o.force); d.case_b_off = at<int32_t>(b, o.case_b_off);
     d.rb_start = at<int32_t>(b, o.rb_start); d.rb_count = at<int32_t>(b, o.rb_count);
     d.rb_case = at<int32_t>(b, o.rb_case); d.case_rb_off = at<int32_t>(b, o.case_rb_off);
     d.part0 = at<double>(b, o.part0); d.part1 = at<double>(b, o.part1);
@@ -251,6 +255,8 @@ template <int D, typename R> void launch_ho_kernels(cgks_batch *b, int mode, hip
         hipLaunchKernelGGL((k_flux<D, R>), dim3(nblk(b->NF * Dim<D>::lanes)), dim3(kBlock), 0, s, d,
                            (int)(mode != MODE_R1));
     });
+    if (mode == MODE_STAGE0 && b->NB > 0)
+        hipLaunchKernelGGL((k_wall_force<D, R>), dim3(b->n_case), dim3(kBlock), 0, s, d);
     timed(b, CGKS_K_CELL, s, [&] {
         hipLaunchKernelGGL((k_cell<D, R>), dim3(nblk(b->NC * Dim<D>::sl)), dim3(kBlock), 0, s, d, mode);
     });
@@ -600,6 +606,11 @@ cgks_status cgks_batch_bind(cgks_batch *b, void *buf, size_t bytes, void *stream
         HIP_TRY(put(b, o.bface, bface, s));
         HIP_TRY(put(b, o.gx, gx, s)); HIP_TRY(put(b, o.gn, gn, s)); HIP_TRY(put(b, o.gw, gw, s));
         HIP_TRY(put(b, o.prm, prm, s)); HIP_TRY(put(b, o.flag, zero_flag, s));
+        std::vector<int32_t> case_b_off(b->b_off.begin(), b->b_off.end());
+        case_b_off.push_back(int32_t(b->NB));
+        HIP_TRY(put(b, o.case_b_off, case_b_off, s));
+        std::vector<double> zero_force(3 * size_t(b->n_case), 0.0);   // alive until the sync below
+        HIP_TRY(put(b, o.force, zero_force, s));
         HIP_TRY(put(b, o.dt, zero_case, s)); HIP_TRY(put(b, o.res, zero_case, s));
         HIP_TRY(put(b, o.rb_start, b->rb_start, s)); HIP_TRY(put(b, o.rb_count, b->rb_count, s));
         HIP_TRY(put(b, o.rb_case, b->rb_case, s)); HIP_TRY(put(b, o.case_rb_off, b->case_rb_off, s));
@@ -729,7 +740,7 @@ cgks_status cgks_solve(cgks_batch *b, const cgks_solve_opts *opts, cgks_solve_re
     std::vector<int32_t> flag(n);
     std::vector<char> done(n, 0);
     for (int c = 0; c < n; ++c) {
-        rep[c] = cgks_solve_report{0, 0, 0.0, 0.0, CGKS_ENOTCONV};
+        rep[c] = cgks_solve_report{0, 0, 0.0, 0.0, CGKS_ENOTCONV, {0.0, 0.0, 0.0}};
     }
     std::vector<DevParams> prm(n);
     HIP_TRY(hipMemcpyAsync(prm.data(), b->dev.prm, sizeof(DevParams) * n, hipMemcpyDeviceToHost, s));
@@ -788,9 +799,23 @@ cgks_status cgks_solve(cgks_batch *b, const cgks_solve_opts *opts, cgks_solve_re
         }
         k += todo;
     }
+    // wall force of each case's last active stage-0 pass
+    std::vector<double> force(3 * size_t(n));
+    HIP_TRY(hipMemcpyAsync(force.data(), b->dev.force, sizeof(double) * 3 * n, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    for (int c = 0; c < n; ++c)
+        for (int a = 0; a < 3; ++a) rep[c].force[a] = force[3 * size_t(c) + a];
     // leave every case active again for later calls
     for (int c = 0; c < n; ++c) prm[c].active = 1;
     HIP_TRY(hipMemcpyAsync((void *)b->dev.prm, prm.data(), sizeof(DevParams) * n, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return CGKS_OK;
+}
+
+cgks_status cgks_wall_force(cgks_batch *b, double *force, void *stream) {
+    if (!b || !b->base || !force) return CGKS_EINVAL;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    HIP_TRY(hipMemcpyAsync(force, b->dev.force, sizeof(double) * 3 * b->n_case, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     return CGKS_OK;
 }

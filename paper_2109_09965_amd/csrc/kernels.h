@@ -60,6 +60,8 @@ struct Dev {
     // per case
     const DevParams *prm;
     double *dt, *res;
+    double *force;     // per case [3]: wall force of the latest stage-0 pass
+    const int32_t *case_b_off;   // [n_case + 1] boundary-slot range of each case
     int32_t *flag;     // per case: bit 0 non-physical state met
     // reductions
     const int32_t *rb_start, *rb_count, *rb_case, *case_rb_off;
@@ -1309,6 +1311,33 @@ template <int D> __global__ __launch_bounds__(kBlock) void k_prolong_res(Dev d, 
 __global__ void k_res_store(const double *res, double *hist, int n_case) {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c < n_case) hist[c] = res[c];
+}
+
+// Force of the gas on the walls (slip and no-slip boundary faces) of each
+// case: the momentum components of the face sums sum_g wJ F0 of the latest
+// flux pass, one block per case over its boundary faces in slot order.
+template <int D, typename R> __global__ __launch_bounds__(kBlock) void k_wall_force(Dev d) {
+    __shared__ double sh[kBlock];
+    const int c = blockIdx.x;
+    if (!d.prm[c].active) return;
+    constexpr int FS = Dim<D>::fs;
+    double f[D];
+#pragma unroll
+    for (int a = 0; a < D; ++a) f[a] = 0.0;
+    for (int B = d.case_b_off[c] + threadIdx.x; B < d.case_b_off[c + 1]; B += kBlock) {
+        const int F = d.bface[B];
+        const int bc = d.fbc[F];
+        if (bc != 1 && bc != 2) continue;
+        const R *src = HoArrays<R>::fsum(d) + size_t(F) * FS;
+#pragma unroll
+        for (int a = 0; a < D; ++a) f[a] += double(src[1 + a]);
+    }
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        const double t = block_reduce_sum(f[a], sh);
+        if (threadIdx.x == 0) d.force[3 * c + a] = t;
+    }
+    if (D == 2 && threadIdx.x == 0) d.force[3 * c + 2] = 0.0;
 }
 
 __global__ __launch_bounds__(kBlock) void k_res_final(Dev d, int n_case) {

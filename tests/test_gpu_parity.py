@@ -178,3 +178,48 @@ def test_run_to_run_bitwise():
         p.b.cycle()
     Wb, dWb = p.b.download(0)
     assert np.array_equal(Wa, Wb) and np.array_equal(dWa, dWb)
+
+
+@pytest.mark.parametrize("name", ["cyl2d_slip", "cyl2d_visc", "box3d_slip", "sphere", "cubed_sphere"])
+def test_wall_force(name):
+    """The device wall force of the stage-0 pass equals the oracle's, on the
+    first cycle and after two more."""
+    p = Pair(name)
+    W, dW = p.W0.copy(), p.dW0.copy()
+    for k in range(3):
+        p.os.cycle(W, dW)
+        p.b.cycle()
+        fo, fg = p.os.force(), p.b.wall_force()[0]
+        scale = max(np.abs(fo).max(), 1e-300)
+        print(f"{name} cycle{k}: force {fg} oracle {fo}", flush=True)
+        assert np.abs(fg - fo).max() <= 1e-11 * scale, (k, fg, fo)
+
+
+def test_wall_force_open_box_on_device():
+    """Gas at rest in a box with a far-field top: the force on the walls is
+    -p0 * (top area) * e_z (the oracle's pin, here through the C ABI)."""
+    m = I.box3d_mesh((3, 3, 5), perturb=0.2, seed=6, bc=I.BC_NOSLIP_ISOTHERMAL)
+    bc = m["face_bc"].copy()
+    ptr, fv, xyz = m["face_vert_ptr"], m["face_vert"], m["xyz"]
+    for f in np.nonzero(m["face_neigh"] < 0)[0]:
+        if np.allclose(xyz[fv[ptr[f]:ptr[f + 1]], 2], 1.0):
+            bc[f] = I.BC_FARFIELD
+    m = dict(m, face_bc=bc)
+    Winf = I.free_stream(3, 0.0)
+    W, dW = I.uniform_state(m, Winf)
+    b = cg.Batch([cg.Mesh(m)], [cg.Params(W_inf=Winf, mu=0.01, Pr=0.72)])
+    b.upload(0, W, dW)
+    b.cycle()
+    np.testing.assert_allclose(b.wall_force()[0], [0.0, 0.0, -1.0 / 1.4], rtol=0, atol=1e-13)
+
+
+def test_solve_reports_wall_force():
+    p = Pair("cyl2d_visc")
+    rep, _ = p.b.solve(max_cycles=3, tol=0.0, check_every=1)
+    W, dW = p.W0.copy(), p.dW0.copy()
+    for _ in range(3):
+        p.os.cycle(W, dW)
+    fo = p.os.force()
+    assert np.abs(rep[0]["force"] - fo).max() <= 1e-11 * np.abs(fo).max()
+    cd = cg.drag_coefficient(rep[0]["force"], I.free_stream(2, 0.15), 1.0)
+    assert np.isfinite(cd)

@@ -84,6 +84,43 @@ def test_walls_carry_no_mass(mk, bc):
     assert abs(R1[0].sum()) <= 1e-13 * np.abs(R1[0]).sum()
 
 
+def open_top_box(mesh, top):
+    """The box's boundary faces on the plane x[d-1] = top become far field."""
+    d = mesh["dim"]
+    ptr, fv, xyz = mesh["face_vert_ptr"], mesh["face_vert"], mesh["xyz"]
+    bc = mesh["face_bc"].copy()
+    for f in np.nonzero(mesh["face_neigh"] < 0)[0]:
+        if np.allclose(xyz[fv[ptr[f]:ptr[f + 1]], d - 1], top):
+            bc[f] = I.BC_FARFIELD
+    out = dict(mesh)
+    out["face_bc"] = bc
+    return out
+
+
+@pytest.mark.parametrize("mk,top,area", [
+    (lambda bc: I.box2d_mesh(6, periodic=False, perturb=0.3, seed=3, bc=bc), 2.0, 2.0),
+    (lambda bc: I.box3d_mesh((3, 3, 5), perturb=0.2, seed=6, bc=bc), 1.0, 1.0),
+])
+@pytest.mark.parametrize("bc", [I.BC_SLIP_WALL, I.BC_NOSLIP_ISOTHERMAL])
+def test_wall_force_of_gas_at_rest_in_an_open_box(mk, top, area, bc):
+    """Gas at rest at the free-stream pressure in a box whose top side is
+    far field and whose other sides are walls: the wall momentum flux is
+    the pressure alone and the walls form a closed surface less the top,
+    so the force on them is -p0 * (top area) * e_top, to round-off.  Also
+    pins the sign (force of the gas on the walls) and that far-field faces
+    do not count."""
+    mesh = open_top_box(mk(bc), top)
+    d = mesh["dim"]
+    Winf = I.free_stream(d, 0.0)
+    W, dW = I.uniform_state(mesh, Winf)
+    s = oracle.Solver(oracle.Mesh(mesh), oracle.Params(W_inf=Winf, mu=0.01, Pr=0.72))
+    s.stage(0, W, dW)
+    p0 = 1.0 / 1.4
+    expect = np.zeros(d)
+    expect[-1] = -p0 * area
+    np.testing.assert_allclose(s.force()[:d], expect, rtol=0, atol=1e-13)
+
+
 @pytest.mark.parametrize("z", [-0.9, -0.3, 0.05, 0.5, 1.2])
 def test_time_marching_closed_forms(z):
     """y' = lam y with L = lam y and L_t = lam^2 y: S2O4 reproduces the
