@@ -60,7 +60,7 @@ enum {
 };
 
 enum { CGKS_S2O4 = 0, CGKS_S1O2 = 1 };
-enum { CGKS_FP64 = 0, CGKS_MIXED32 = 1 };
+enum { CGKS_FP64 = 0, CGKS_MIXED32 = 1, CGKS_MIXED32_R64 = 2 };
 enum { CGKS_RESIDUAL_HIGH = 0, CGKS_RESIDUAL_LOW = 1, CGKS_RESIDUAL_NORM = 2 };
 
 /*
@@ -139,11 +139,16 @@ cgks_status cgks_mesh_destroy(cgks_mesh *mesh);
 
 /* A batch is n_case (mesh, params) pairs stepped together: every kernel
    launch covers all cases; per-case reductions (dt, Res) never mix cases.
-   The meshes must outlive the batch.  precision: CGKS_FP64, or
-   CGKS_MIXED32: reconstruction coefficients, interface states, the
-   gas-kinetic flux and the face sums in FP32; cell averages, gradients,
-   the stage accumulation, R1, the low level, Res and dt in FP64.
-   Errors: CGKS_EINVAL, CGKS_ENOMEM. */
+   The meshes must outlive the batch.  precision: CGKS_FP64 (everything in
+   FP64); CGKS_MIXED32: reconstruction coefficients, interface states, the
+   gas-kinetic flux, the face sums and the relaxation sweeps (increments dU
+   and their flux changes) in FP32; cell averages, gradients, the stage
+   accumulation, R1's accumulation, the low-level state U, its KFVS flux and
+   right-hand side, Res and dt in FP64; CGKS_MIXED32_R64: as CGKS_MIXED32,
+   but the residual pass R1 (reconstruction, flux, face sums) in FP64, so
+   the FP32 parts no longer perturb the cycle's fixed point (R1 = 0) and
+   the residual falls below the FP32 noise floor.  Errors: CGKS_EINVAL,
+   CGKS_ENOMEM. */
 cgks_status cgks_batch_create(const cgks_mesh *const *meshes, const cgks_params *params, int32_t n_case,
                               int32_t precision, cgks_batch **out);
 /* Device bytes the batch needs (geometry, state, work arrays). */

@@ -20,7 +20,7 @@ _lib = None
 
 OK, EINVAL, ENOMEM, EDEVICE, EMESH, ENONPHYS, EDIVERGED, ENOTCONV, EUNSUPPORTED = range(9)
 S2O4, S1O2 = 0, 1
-FP64, MIXED32 = 0, 1
+FP64, MIXED32, MIXED32_R64 = 0, 1, 2
 RESIDUAL_HIGH, RESIDUAL_LOW, RESIDUAL_NORM = 0, 1, 2
 
 EXPORTS = ["cgks_status_string", "cgks_mesh_create", "cgks_mesh_query", "cgks_mesh_permutation",

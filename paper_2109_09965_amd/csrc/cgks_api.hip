@@ -96,9 +96,10 @@ void layout(cgks_batch *b) {
     Arena a;
     auto &o = b->o;
     const int sr = nv + d * nv, er = d + 1 + nq + nv + nk * nv, gr = d + nq + 1;
-    const bool mixed = b->precision == CGKS_MIXED32;
+    const bool mixed = b->precision != CGKS_FP64;           // FP32 high-order arrays
+    const bool ho64 = b->precision != CGKS_MIXED32;         // FP64 high-order arrays
     o.st = a.take<double>(sr * NC);
-    o.ev = a.take<double>(mixed ? 0 : er * NC);
+    o.ev = a.take<double>(ho64 ? er * NC : 0);
     o.Wn = a.take<double>(nv * NC);
     o.L0 = a.take<double>(nv * NC);
     o.Lt0 = a.take<double>(nv * NC);
@@ -124,11 +125,12 @@ void layout(cgks_batch *b) {
     o.gx = a.take<double>(d * NG);
     o.gn = a.take<double>(d * NG);
     o.gw = a.take<double>(NG);
-    o.fsum = a.take<double>(mixed ? 0 : (2 * nv + 2 * d * nv) * NF);
+    o.fsum = a.take<double>(ho64 ? (2 * nv + 2 * d * nv) * NF : 0);
     o.fsum32 = a.take<float>(mixed ? (2 * nv + 2 * d * nv) * NF : 0);
     o.ev32 = a.take<float>(mixed ? er * NC : 0);
     o.minv32 = a.take<float>(mixed ? nk * (nk + 1) / 2 * NC : 0);
-    o.U = a.take<double>(2 * nv * NC);
+    // low-level records: U (FP64) + dU (FP64, or FP32 padded to 16 bytes)
+    o.U = a.take<double>(size_t(mixed ? (nv + (nv + 1) / 2 + 1) / 2 * 2 : 2 * nv) * NC);
     o.Sf = a.take<double>(nv * NC);
     o.RHS = a.take<double>(nv * NC);
     o.D = a.take<double>(NC);
@@ -196,7 +198,7 @@ void fill_dev(cgks_batch *b) {
     d.fsum32 = at<float>(b, o.fsum32);
     d.ev32 = at<float>(b, o.ev32);
     d.minv32 = at<float>(b, o.minv32);
-    d.U = at<double>(b, o.U); d.dU = d.U + (b->dim + 2); d.Sf = at<double>(b, o.Sf);
+    d.U = at<double>(b, o.U); d.Sf = at<double>(b, o.Sf);
     d.RHS = at<double>(b, o.RHS); d.D = at<double>(b, o.D); d.R1 = at<double>(b, o.R1);
     d.lowf = at<double>(b, o.lowf); d.swp = at<double>(b, o.swp);
     d.prm = at<DevParams>(b, o.prm); d.dt = at<double>(b, o.dt); d.res = at<double>(b, o.res);
@@ -270,7 +272,9 @@ template <int D> cgks_status launch_highorder(cgks_batch *b, int mode, hipStream
             hipLaunchKernelGGL(k_dt_final, dim3(b->n_case), dim3(kBlock), 0, s, d, b->n_case);
         });
     }
-    if (b->precision == CGKS_MIXED32) launch_ho_kernels<D, float>(b, mode, s);
+    // MIXED32_R64 evaluates the residual pass R1 in FP64
+    if (b->precision == CGKS_MIXED32 || (b->precision == CGKS_MIXED32_R64 && mode != MODE_R1))
+        launch_ho_kernels<D, float>(b, mode, s);
     else launch_ho_kernels<D, double>(b, mode, s);
     HIP_TRY(hipGetLastError());
     return CGKS_OK;
@@ -290,26 +294,25 @@ std::vector<int> sweep_order(int ncol, int nsweeps) {
     return out;
 }
 
-template <int D> cgks_status launch_lowlevel(cgks_batch *b, const double *R1, hipStream_t s) {
+template <int D, typename S> cgks_status launch_lowlevel_s(cgks_batch *b, const double *R1, hipStream_t s) {
     Dev d = b->dev;
     if (R1 != d.R1)
         HIP_TRY(hipMemcpyAsync(d.R1, R1, sizeof(double) * (D + 2) * b->NC, hipMemcpyDeviceToDevice, s));
     timed(b, CGKS_K_LOWFACE, s, [&] {
-        hipLaunchKernelGGL(k_low_face<D>, dim3(nblk(b->NF)), dim3(kBlock), 0, s, d, (const double *)d.st,
-                           (const double *)nullptr, 1);
+        hipLaunchKernelGGL((k_low_face<D, S>), dim3(nblk(b->NF)), dim3(kBlock), 0, s, d, (int)LOW_SRC_W);
     });
     timed(b, CGKS_K_LOWCELL, s, [&] {
-        hipLaunchKernelGGL(k_low_cell<D>, dim3(nblk(b->NC * Dim<D>::sl)), dim3(kBlock), 0, s, d, (int)LOW_FORCE,
-                           (double *)nullptr);
+        hipLaunchKernelGGL((k_low_cell<D, S>), dim3(nblk(b->NC * Dim<D>::sl)), dim3(kBlock), 0, s, d,
+                           (int)LOW_FORCE, (double *)nullptr);
     });
     const std::vector<int> order = sweep_order(b->max_colour, b->n_sweeps);
     for (int k = 0; k < b->n_implicit; ++k) {
         timed(b, CGKS_K_LOWFACE, s, [&] {
-            hipLaunchKernelGGL(k_low_face<D>, dim3(nblk(b->NF)), dim3(kBlock), 0, s, d, (const double *)d.U,
-                               (const double *)(k ? d.dU : nullptr), 0);
+            hipLaunchKernelGGL((k_low_face<D, S>), dim3(nblk(b->NF)), dim3(kBlock), 0, s, d,
+                               (int)(k ? LOW_SRC_U_DU : LOW_SRC_U));
         });
         timed(b, CGKS_K_LOWCELL, s, [&] {
-            hipLaunchKernelGGL(k_low_cell<D>, dim3(nblk(b->NC * Dim<D>::sl)), dim3(kBlock), 0, s, d,
+            hipLaunchKernelGGL((k_low_cell<D, S>), dim3(nblk(b->NC * Dim<D>::sl)), dim3(kBlock), 0, s, d,
                                (int)(k ? LOW_STEP : LOW_STEP_FIRST), (double *)nullptr);
         });
         // the colour passes of one step run back to back: one timing span
@@ -321,7 +324,7 @@ template <int D> cgks_status launch_lowlevel(cgks_batch *b, const double *R1, hi
                 for (int c : order) {
                     const int64_t b0 = b->colour_blk_off[c], nb = b->colour_blk_off[c + 1] - b0;
                     if (nb == 0) continue;
-                    hipLaunchKernelGGL(k_sweep<D>, dim3(unsigned(nb)), dim3(kBlock), 0, s, d,
+                    hipLaunchKernelGGL((k_sweep<D, S>), dim3(unsigned(nb)), dim3(kBlock), 0, s, d,
                                        (const int32_t *)(b->d_cb_start + b0),
                                        (const int32_t *)(b->d_cb_count + b0));
                 }
@@ -329,11 +332,17 @@ template <int D> cgks_status launch_lowlevel(cgks_batch *b, const double *R1, hi
             n_pass);
     }
     timed(b, CGKS_K_PROLONG, s, [&] {
-        hipLaunchKernelGGL(k_prolong_res<D>, dim3(b->rb_start.size()), dim3(kBlock), 0, s, d, 1);
+        hipLaunchKernelGGL((k_prolong_res<D, S>), dim3(b->rb_start.size()), dim3(kBlock), 0, s, d, 1);
         hipLaunchKernelGGL(k_res_final, dim3(b->n_case), dim3(kBlock), 0, s, d, b->n_case);
     });
     HIP_TRY(hipGetLastError());
     return CGKS_OK;
+}
+
+// MIXED32 batches run the relaxation sweeps in FP32 (dU stored in FP32)
+template <int D> cgks_status launch_lowlevel(cgks_batch *b, const double *R1, hipStream_t s) {
+    return b->precision != CGKS_FP64 ? launch_lowlevel_s<D, float>(b, R1, s)
+                                     : launch_lowlevel_s<D, double>(b, R1, s);
 }
 
 template <int D> cgks_status launch_cycle(cgks_batch *b, hipStream_t s) {
@@ -345,7 +354,7 @@ template <int D> cgks_status launch_cycle(cgks_batch *b, hipStream_t s) {
     }
     if (b->explicit_only) {
         timed(b, CGKS_K_PROLONG, s, [&] {
-            hipLaunchKernelGGL(k_prolong_res<D>, dim3(b->rb_start.size()), dim3(kBlock), 0, s, b->dev, 0);
+            hipLaunchKernelGGL((k_prolong_res<D, double>), dim3(b->rb_start.size()), dim3(kBlock), 0, s, b->dev, 0);
             hipLaunchKernelGGL(k_res_final, dim3(b->n_case), dim3(kBlock), 0, s, b->dev, b->n_case);
         });
         HIP_TRY(hipGetLastError());
@@ -437,7 +446,7 @@ cgks_status cgks_batch_create(const cgks_mesh *const *meshes, const cgks_params 
                               int32_t precision, cgks_batch **out) {
     if (!out || !meshes || !params || n_case <= 0) return CGKS_EINVAL;
     *out = nullptr;
-    if (precision != CGKS_FP64 && precision != CGKS_MIXED32) return CGKS_EINVAL;
+    if (precision != CGKS_FP64 && precision != CGKS_MIXED32 && precision != CGKS_MIXED32_R64) return CGKS_EINVAL;
     try {
         cgks_batch *b = new cgks_batch;
         b->n_case = n_case;
@@ -593,7 +602,7 @@ cgks_status cgks_batch_bind(cgks_batch *b, void *buf, size_t bytes, void *stream
         auto &o = b->o;
         HIP_TRY(put(b, o.vol, vol, s)); HIP_TRY(put(b, o.h, h, s)); HIP_TRY(put(b, o.geo, geo, s));
         HIP_TRY(put(b, o.minv, minv, s));
-        if (b->precision == CGKS_MIXED32) {
+        if (b->precision != CGKS_FP64) {
             std::vector<float> m32(minv.begin(), minv.end());
             HIP_TRY(put(b, o.minv32, m32, s));
         }
@@ -696,14 +705,14 @@ cgks_status cgks_residual(cgks_batch *b, int32_t kind, double *out, void *stream
     }
     if (kind == CGKS_RESIDUAL_LOW) {
         if (b->dim == 2) {
-            hipLaunchKernelGGL(k_low_face<2>, dim3(nblk(b->NF)), dim3(kBlock), 0, s, b->dev, (const double *)b->dev.st,
-                               (const double *)nullptr, 1);
-            hipLaunchKernelGGL(k_low_cell<2>, dim3(nblk(b->NC * Dim<2>::sl)), dim3(kBlock), 0, s, b->dev,
+            hipLaunchKernelGGL((k_low_face<2, double>), dim3(nblk(b->NF)), dim3(kBlock), 0, s, b->dev,
+                               (int)LOW_SRC_W);
+            hipLaunchKernelGGL((k_low_cell<2, double>), dim3(nblk(b->NC * Dim<2>::sl)), dim3(kBlock), 0, s, b->dev,
                                (int)LOW_R0_OUT, out);
         } else {
-            hipLaunchKernelGGL(k_low_face<3>, dim3(nblk(b->NF)), dim3(kBlock), 0, s, b->dev, (const double *)b->dev.st,
-                               (const double *)nullptr, 1);
-            hipLaunchKernelGGL(k_low_cell<3>, dim3(nblk(b->NC * Dim<3>::sl)), dim3(kBlock), 0, s, b->dev,
+            hipLaunchKernelGGL((k_low_face<3, double>), dim3(nblk(b->NF)), dim3(kBlock), 0, s, b->dev,
+                               (int)LOW_SRC_W);
+            hipLaunchKernelGGL((k_low_cell<3, double>), dim3(nblk(b->NC * Dim<3>::sl)), dim3(kBlock), 0, s, b->dev,
                                (int)LOW_R0_OUT, out);
         }
         HIP_TRY(hipGetLastError());

@@ -12,6 +12,7 @@
 
 #include <cmath>
 #include <cstdint>
+#include <type_traits>
 
 namespace cgks {
 
@@ -51,10 +52,10 @@ struct Dev {
     const double *gx, *gn, *gw;
     double *fsum;      // per face [NF][2 nv + 2 D nv]: sum_g wJ (F0, Ft, W_c n, W_t n)
     float *fsum32;     // the same in FP32 (mixed-precision batches)
-    // low level: U and dU interleaved cell-major [NC][2 nv] (U = base, dU =
-    // base + nv, stride 2 nv; a neighbour gather reads one 80-byte record),
-    // Sf, RHS, R1 [nv][NC]
-    double *U, *dU, *Sf, *RHS, *D, *R1;
+    // low level: U and dU in one cell-major record per cell (LowRec: U in
+    // FP64, then dU in the sweep precision; a neighbour gather reads one
+    // record), Sf, RHS, R1 [nv][NC]
+    double *U, *Sf, *RHS, *D, *R1;
     double *lowf;      // [NF][nv]: S_f F_kfvs
     double *swp;       // [NF][4]: area vector S_f n_f (D values), S_f lam_f
     // per case
@@ -102,7 +103,6 @@ template <int D> struct Dim {
     static constexpr int lanes = D == 2 ? 2 : 4;   // threads per face (one per Gauss point)
     static constexpr int sl = 4;                   // threads per cell in the slot gathers
     static constexpr int fs = 2 * nv + 2 * D * nv; // face sums per face
-    static constexpr int us = 2 * nv;              // stride of the interleaved U, dU records
 };
 
 // quadratic basis (a, b) pairs: 2-D (00, 01, 11); 3-D (00, 11, 22, 01, 02, 12)
@@ -447,6 +447,53 @@ template <int D> __device__ __forceinline__ void euler_flux(const double *U, con
     for (int a = 0; a < D; ++a) F[1 + a] = U[1 + a] * un + p * n[a];
     F[nv - 1] = (U[nv - 1] + p) * un;
 }
+
+// The same flux's change F_A(U + dU) - F_A(U), written so that no two large
+// terms are subtracted: with u' = (m + dm)/(rho + drho), du = u' - u,
+//   d(rho u.A) = dm.A,   d(m u.A) = dm (u'.A) + m (du.A) + dp A,
+//   d((E + p) u.A) = (dE + dp)(u'.A) + (E + p)(du.A),
+//   dp = (gamma - 1)(dE - (dm.u' + m.du)/2).
+// Accurate relative to |dU| in any precision (used by FP32 sweeps).
+template <int D, typename S>
+__device__ __forceinline__ void euler_dflux(const S *U, const S *dU, const S *A, S gamma, S *dF) {
+    constexpr int nv = D + 2;
+    const S rho = U[0], rho1 = U[0] + dU[0];
+    S u[D], du[D], un1 = S(0), dun = S(0), mu = S(0), dmu = S(0), dmA = S(0);
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        u[a] = U[1 + a] / rho;
+        du[a] = (dU[1 + a] - u[a] * dU[0]) / rho1;
+        un1 += (u[a] + du[a]) * A[a];
+        dun += du[a] * A[a];
+        mu += U[1 + a] * u[a];
+        dmu += dU[1 + a] * (u[a] + du[a]) + U[1 + a] * du[a];
+        dmA += dU[1 + a] * A[a];
+    }
+    const S p = (gamma - S(1)) * (U[nv - 1] - S(0.5) * mu);
+    const S dp = (gamma - S(1)) * (dU[nv - 1] - S(0.5) * dmu);
+    dF[0] = dmA;
+#pragma unroll
+    for (int a = 0; a < D; ++a) dF[1 + a] = dU[1 + a] * un1 + U[1 + a] * dun + dp * A[a];
+    dF[nv - 1] = (dU[nv - 1] + dp) * un1 + (U[nv - 1] + p) * dun;
+}
+
+// Low-level state records, one per cell, [cell][stride] doubles: U (nv
+// FP64 values), then dU (nv values in the sweep precision S).  FP64 sweeps:
+// stride 2 nv.  FP32 sweeps: nv doubles + nv floats padded to 16 bytes
+// (3-D: 64 bytes, one memory sector per neighbour gather).
+template <int D, typename S> struct LowRec;
+template <int D> struct LowRec<D, double> {
+    static constexpr int nv = D + 2, stride = 2 * nv;
+    static __device__ __forceinline__ double *U(const Dev &d, size_t i) { return d.U + i * stride; }
+    static __device__ __forceinline__ double *dU(const Dev &d, size_t i) { return d.U + i * stride + nv; }
+};
+template <int D> struct LowRec<D, float> {
+    static constexpr int nv = D + 2, stride = (nv + (nv + 1) / 2 + 1) / 2 * 2;
+    static __device__ __forceinline__ double *U(const Dev &d, size_t i) { return d.U + i * stride; }
+    static __device__ __forceinline__ float *dU(const Dev &d, size_t i) {
+        return reinterpret_cast<float *>(d.U + i * stride + nv);
+    }
+};
 
 // ---------------------------------------------------------------------
 // Global time step: per-block minimum over a case's cells, then per case.
@@ -1096,23 +1143,24 @@ template <int D> __device__ __forceinline__ double side_radius(const double *U, 
     return fabs(un) + sqrt(P.gamma * p / rho) + 2.0 * P.mu / rho * Sf / V;
 }
 
-// state of cell i: from the state records (rec = 1, U = d.st) or the
-// cell-major low-level state U (+ dU when dU != nullptr)
-template <int D> __device__ __forceinline__ void low_state(const Dev &d, const double *U, const double *dU, int rec,
-                                                           int i, double *out) {
+enum { LOW_SRC_W = 0, LOW_SRC_U = 1, LOW_SRC_U_DU = 2 };
+
+// state of cell i: W from the state records, the low-level U, or U + dU
+template <int D, typename S> __device__ __forceinline__ void low_state(const Dev &d, int src, int i, double *out) {
     constexpr int nv = D + 2;
-    if (rec) {
+    if (src == LOW_SRC_W) {
 #pragma unroll
-        for (int v = 0; v < nv; ++v) out[v] = U[size_t(i) * Rec<D>::sr + v];
+        for (int v = 0; v < nv; ++v) out[v] = d.st[size_t(i) * Rec<D>::sr + v];
     } else {
+        const double *U = LowRec<D, S>::U(d, i);
+        const S *dU = LowRec<D, S>::dU(d, i);
 #pragma unroll
-        for (int v = 0; v < nv; ++v)
-            out[v] = dU ? U[size_t(i) * 2 * nv + v] + dU[size_t(i) * 2 * nv + v] : U[size_t(i) * 2 * nv + v];
+        for (int v = 0; v < nv; ++v) out[v] = src == LOW_SRC_U_DU ? U[v] + double(dU[v]) : U[v];
     }
 }
 
 // lowf[f] = S_f F_kfvs(U_L, U_R; n_f); swp[f] = (S_f n_f, S_f lam_f).
-template <int D> __global__ __launch_bounds__(kBlock) void k_low_face(Dev d, const double *U, const double *dU, int soa) {
+template <int D, typename S> __global__ __launch_bounds__(kBlock) void k_low_face(Dev d, int src) {
     constexpr int nv = D + 2;
     const int f = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
     if (f >= d.NF) return;
@@ -1127,12 +1175,12 @@ template <int D> __global__ __launch_bounds__(kBlock) void k_low_face(Dev d, con
     Frame<D, double> fr;
     fr.build(n);
     double UL[nv], Ul[nv], Ur[nv];
-    low_state<D>(d, U, dU, soa, L, UL);
+    low_state<D, S>(d, src, L, UL);
     fr.to_local(UL, Ul);
     double lam = side_radius<D>(UL, n, Sf, d.vol[L], P);
     if (R >= 0) {
         double UR[nv];
-        low_state<D>(d, U, dU, soa, R, UR);
+        low_state<D, S>(d, src, R, UR);
         fr.to_local(UR, Ur);
         lam = fmax(lam, side_radius<D>(UR, n, Sf, d.vol[R], P));
     } else {
@@ -1168,7 +1216,7 @@ template <int D> __global__ __launch_bounds__(kBlock) void k_low_face(Dev d, con
 
 enum { LOW_FORCE = 0, LOW_STEP_FIRST = 1, LOW_STEP = 2, LOW_R0_OUT = 3 };
 
-template <int D> __global__ __launch_bounds__(kBlock) void k_low_cell(Dev d, int mode, double *out) {
+template <int D, typename S> __global__ __launch_bounds__(kBlock) void k_low_cell(Dev d, int mode, double *out) {
     using T = Dim<D>;
     constexpr int nv = T::nv, SL = T::sl;
     const int t = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
@@ -1196,7 +1244,8 @@ template <int D> __global__ __launch_bounds__(kBlock) void k_low_cell(Dev d, int
     for (int v = 0; v < nv; ++v) R0[v] = group_sum<SL, double>(R0[v]);
     lS = group_sum<SL, double>(lS);
     if (!ok || !P.active) return;
-    double *Ui = d.U + size_t(i) * T::us, *dUi = d.dU + size_t(i) * T::us;
+    double *Ui = LowRec<D, S>::U(d, i);
+    S *dUi = LowRec<D, S>::dU(d, i);
     if (mode == LOW_R0_OUT) {
 #pragma unroll
         for (int v = 0; v < nv; ++v)
@@ -1209,19 +1258,19 @@ template <int D> __global__ __launch_bounds__(kBlock) void k_low_cell(Dev d, int
             if (v % SL == q) {
                 d.Sf[v * NC + i] = d.R1[v * NC + i] - R0[v];
                 Ui[v] = d.st[size_t(i) * Rec<D>::sr + v];
-                dUi[v] = 0.0;
+                dUi[v] = S(0);
             }
         return;
     }
     double u[nv];
 #pragma unroll
-    for (int v = 0; v < nv; ++v) u[v] = mode == LOW_STEP ? Ui[v] + dUi[v] : Ui[v];
+    for (int v = 0; v < nv; ++v) u[v] = mode == LOW_STEP ? Ui[v] + double(dUi[v]) : Ui[v];
 #pragma unroll
     for (int v = 0; v < nv; ++v)
         if (v % SL == q) {
             Ui[v] = u[v];
             d.RHS[v * NC + i] = R0[v] + d.Sf[v * NC + i];
-            dUi[v] = 0.0;
+            dUi[v] = S(0);
         }
     if (q == 0) d.D[i] = d.vol[i] / state_dt<D>(u, d.h[i], P.cfl_low, P) + 0.5 * lS;
 }
@@ -1229,8 +1278,10 @@ template <int D> __global__ __launch_bounds__(kBlock) void k_low_cell(Dev d, int
 // one colour class: blocks listed in (start, count) tables.  With A = s S_f n_f
 // (outward from i) the delta flux of a neighbour is
 //   S_f [F-(U_m + dU_m) - F-(U_m)] = 1/2 (F_A(U_m + dU_m) - F_A(U_m)) - 1/2 S_f lam_f dU_m.
-template <int D> __global__ __launch_bounds__(kBlock) void k_sweep(Dev d, const int32_t *blk_start,
-                                                                   const int32_t *blk_count) {
+// FP64 sweeps difference the two fluxes as written; FP32 sweeps (S = float)
+// evaluate the flux change in the cancellation-free form euler_dflux.
+template <int D, typename S>
+__global__ __launch_bounds__(kBlock) void k_sweep(Dev d, const int32_t *blk_start, const int32_t *blk_count) {
     using T = Dim<D>;
     constexpr int nv = T::nv, SL = T::sl;
     const int b = xcd_block(blockIdx.x, gridDim.x);
@@ -1239,9 +1290,9 @@ template <int D> __global__ __launch_bounds__(kBlock) void k_sweep(Dev d, const 
     const int i = blk_start[b] + (ok ? lc : 0);
     const int NC = d.NC;
     const DevParams &P = d.prm[d.cell_case[i]];
-    double acc[nv];
+    S acc[nv];
 #pragma unroll
-    for (int v = 0; v < nv; ++v) acc[v] = 0.0;
+    for (int v = 0; v < nv; ++v) acc[v] = S(0);
 #pragma unroll
     for (int s = q; s < T::ns; s += SL) {
         const int2 sl = d.slot[s * NC + i];
@@ -1250,34 +1301,52 @@ template <int D> __global__ __launch_bounds__(kBlock) void k_sweep(Dev d, const 
             const int f = (sl.x > 0 ? sl.x : -sl.x) - 1;
             const double sg = sl.x > 0 ? 1.0 : -1.0;
             const double *w = d.swp + size_t(f) * 4;
-            double A[D], Um[nv], dUm[nv], Up[nv], Fa[nv], Fb[nv];
+            const double *Unb = LowRec<D, S>::U(d, nb);
+            const S *dUnb = LowRec<D, S>::dU(d, nb);
+            if constexpr (std::is_same<S, double>::value) {
+                double A[D], Um[nv], dUm[nv], Up[nv], Fa[nv], Fb[nv];
 #pragma unroll
-            for (int a = 0; a < D; ++a) A[a] = sg * w[a];
-            const double sl_lam = w[D];
+                for (int a = 0; a < D; ++a) A[a] = sg * w[a];
+                const double sl_lam = w[D];
 #pragma unroll
-            for (int v = 0; v < nv; ++v) {
-                Um[v] = d.U[size_t(nb) * T::us + v];
-                dUm[v] = d.dU[size_t(nb) * T::us + v];
-                Up[v] = Um[v] + dUm[v];
+                for (int v = 0; v < nv; ++v) {
+                    Um[v] = Unb[v];
+                    dUm[v] = dUnb[v];
+                    Up[v] = Um[v] + dUm[v];
+                }
+                euler_flux<D>(Up, A, P.gamma, Fa);
+                euler_flux<D>(Um, A, P.gamma, Fb);
+#pragma unroll
+                for (int v = 0; v < nv; ++v) acc[v] += 0.5 * (Fa[v] - Fb[v]) - 0.5 * sl_lam * dUm[v];
+            } else {
+                float A[D], Um[nv], dUm[nv], dF[nv];
+#pragma unroll
+                for (int a = 0; a < D; ++a) A[a] = float(sg * w[a]);
+                const float sl_lam = float(w[D]);
+#pragma unroll
+                for (int v = 0; v < nv; ++v) {
+                    Um[v] = float(Unb[v]);
+                    dUm[v] = dUnb[v];
+                }
+                euler_dflux<D, float>(Um, dUm, A, float(P.gamma), dF);
+#pragma unroll
+                for (int v = 0; v < nv; ++v) acc[v] += 0.5f * dF[v] - 0.5f * sl_lam * dUm[v];
             }
-            euler_flux<D>(Up, A, P.gamma, Fa);
-            euler_flux<D>(Um, A, P.gamma, Fb);
-#pragma unroll
-            for (int v = 0; v < nv; ++v) acc[v] += 0.5 * (Fa[v] - Fb[v]) - 0.5 * sl_lam * dUm[v];
         }
     }
 #pragma unroll
-    for (int v = 0; v < nv; ++v) acc[v] = group_sum<SL, double>(acc[v]);
+    for (int v = 0; v < nv; ++v) acc[v] = group_sum<SL, S>(acc[v]);
     if (!ok || !P.active) return;
     const double Di = d.D[i];
+    S *dUi = LowRec<D, S>::dU(d, i);
 #pragma unroll
     for (int v = 0; v < nv; ++v)
-        if (v % SL == q) d.dU[size_t(i) * T::us + v] = (d.RHS[v * NC + i] - acc[v]) / Di;
+        if (v % SL == q) dUi[v] = S((d.RHS[v * NC + i] - double(acc[v])) / Di);
 }
 
 // W += (U + dU) - W_p0 (W_p0 = W); partial sums of |rho - rho^n| and rho^n.
 // prolong = 0: sums only (explicit cycle).
-template <int D> __global__ __launch_bounds__(kBlock) void k_prolong_res(Dev d, int prolong) {
+template <int D, typename S> __global__ __launch_bounds__(kBlock) void k_prolong_res(Dev d, int prolong) {
     constexpr int nv = D + 2;
     __shared__ double sh[kBlock];
     const int b = blockIdx.x;
@@ -1291,7 +1360,7 @@ template <int D> __global__ __launch_bounds__(kBlock) void k_prolong_res(Dev d, 
         if (prolong && P.active) {
 #pragma unroll
             for (int v = 0; v < nv; ++v) {
-                const double u6 = d.U[size_t(i) * 2 * nv + v] + d.dU[size_t(i) * 2 * nv + v];
+                const double u6 = LowRec<D, S>::U(d, i)[v] + double(LowRec<D, S>::dU(d, i)[v]);
                 const double w = d.st[size_t(i) * Rec<D>::sr + v];
                 d.st[size_t(i) * Rec<D>::sr + v] = w + (u6 - w);
             }
