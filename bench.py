@@ -96,12 +96,13 @@ def sweep_sequence(n_colour, n_sweeps=2):
     return out
 
 
-def algorithmic_bytes(mesh, lm, rbytes):
+def algorithmic_bytes(mesh, lm, rbytes, sbytes=8):
     """Bytes per launch of each kernel kind, averaged over its launches in
     one S2O4 cycle: every distinct array element the kernel reads or writes
     by definition counted once per launch (no credit for cache re-reads, no
     charge for misses).  FP64 8 B, high-order arrays rbytes (8 FP64, 4
-    mixed), int32 4 B, int2 8 B.  Returns {kind: (bytes, launches)}."""
+    mixed), low-level increments dU sbytes (8 FP64, 4 mixed), int32 4 B,
+    int2 8 B.  Returns {kind: (bytes, launches)}."""
     d = mesh["dim"]
     z = layout_sizes(d)
     nv, ns, sr, gr, er, fs, nk = z["nv"], z["ns"], z["sr"], z["gr"], z["er"], z["fs"], z["nk"]
@@ -127,12 +128,12 @@ def algorithmic_bytes(mesh, lm, rbytes):
     lf_common = NF * (4 * 3 + 8 + 8 * d) + 8 * NF * (nv + d + 1)   # indices, S, avec; lowf, swp writes
     lf_force = lf_common + 8 * nv * (NF + nint)                   # W of both sides
     lf_first = lf_force
-    lf_step = lf_common + 16 * nv * (NF + nint)                   # U and dU of both sides
+    lf_step = lf_common + (8 + sbytes) * nv * (NF + nint)         # U and dU of both sides
     out["low_face"] = ((lf_force + lf_first + 5 * lf_step) / 7.0, 7)
     lc_common = NC * (8 * ns + 4) + NF * 8 * (nv + 1)
-    lc_force = lc_common + NC * 8 * (nv + nv + nv + nv + nv)      # R1, W; Sf, U, dU
-    lc_first = lc_common + NC * 8 * (nv + nv + nv + nv + nv + 2 + 1)   # U, Sf; U, RHS, dU; vol, h; D
-    lc_step = lc_first + NC * 8 * nv                              # + dU read
+    lc_force = lc_common + NC * (8 * 4 * nv + sbytes * nv)        # R1, W; Sf, U; dU
+    lc_first = lc_common + NC * (8 * (4 * nv + 2 + 1) + sbytes * nv)   # U, Sf; U, RHS; vol, h; D; dU
+    lc_step = lc_first + NC * sbytes * nv                         # + dU read
     out["low_cell"] = ((lc_force + lc_first + 5 * lc_step) / 7.0, 7)
     # sweeps, per colour class c: per cell of c its slots, case, RHS, D and
     # the dU write; the face record of every interior face of c (faces of an
@@ -146,10 +147,11 @@ def algorithmic_bytes(mesh, lm, rbytes):
     pairs = np.unique(np.concatenate([colour[a].astype(np.int64) * NC + b2, colour[b2].astype(np.int64) * NC + a]))
     n_nb_c = np.bincount(pairs // NC, minlength=lm.n_colour)
     n_cell_c = np.bincount(colour, minlength=lm.n_colour)
-    by_colour = n_cell_c * (8 * ns + 4 + 8 * nv + 8 + 8 * nv) + n_face_c * 8 * (d + 1) + n_nb_c * 16 * nv
+    by_colour = (n_cell_c * (8 * ns + 4 + 8 * nv + 8 + sbytes * nv) + n_face_c * 8 * (d + 1)
+                 + n_nb_c * (8 + sbytes) * nv)
     seq = sweep_sequence(lm.n_colour)
     out["sweep"] = (float(sum(by_colour[c] for c in seq)) / len(seq), 6 * len(seq))
-    out["prolong"] = (NC * 8 * (2 * nv + 2 * nv + 1), 1)
+    out["prolong"] = (NC * (8 * (nv + 2 * nv + 1) + sbytes * nv), 1)
     return out
 
 
@@ -252,7 +254,7 @@ def main():
     # dominant kernel by total time; every kernel's achieved bandwidth
     dom = max(kt, key=lambda k: kt[k][0])
     tot_ms = sum(v[0] for v in kt.values())
-    model = algorithmic_bytes(mesh, lm, 8 if prec == cg.FP64 else 4)
+    model = algorithmic_bytes(mesh, lm, 8 if prec == cg.FP64 else 4, 8 if prec == cg.FP64 else 4)
     per_kernel_gbs = {}
     for k, (ms, n) in kt.items():
         if n and k in model:
