@@ -178,12 +178,72 @@ def cpu_baseline(seconds_hint=30.0):
                        f"1 thread, {t:.1f} s")
 
 
+def run_batch(args):
+    """64 seeded cylinder cases of uneven size stepped together (one launch
+    per kernel covers every case), FP64 and MIXED32, as captured graphs of G
+    cycles; then the same cases one at a time in FP64, each with its own
+    graph.  value = batched FP64 cell-updates/s."""
+    import torch
+    import paper_2109_09965_amd as cg
+    import paper_2109_09965_amd.inputs as I
+    cases = I.batch_cases(64, 2109)
+    meshes = [I.batch_case_mesh(c) for c in cases]
+    winf = [I.free_stream(2, c["mach"], c["aoa"]) for c in cases]
+    lms = [cg.Mesh(m) for m in meshes]
+    params = [cg.Params(W_inf=w) for w in winf]
+    NC = sum(lm.n_cell for lm in lms)
+    G = max(g for g in (1, 2, 4, 5) if args.steps % g == 0)
+
+    def run(idx, prec):
+        b = cg.Batch([lms[i] for i in idx], [params[i] for i in idx], precision=prec)
+        for k, i in enumerate(idx):
+            W, dW = I.uniform_state(meshes[i], winf[i])
+            b.upload(k, W, dW)
+        for _ in range(args.warmup):
+            b.cycle()
+        b.graph_create(G)
+        hist = torch.zeros(G * len(idx), dtype=torch.float64, device="cuda")
+        b.graph_launch(hist)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps // G):
+            b.graph_launch(hist)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        res = hist.cpu().numpy()
+        del b
+        return t, bool(np.isfinite(res).all())
+
+    out = {}
+    for name, prec in (("fp64", cg.FP64), ("mixed32", cg.MIXED32)):
+        t, ok = run(list(range(len(cases))), prec)
+        out[name] = (NC * args.steps / t, ok)
+    t_one, ok_one = 0.0, True
+    for i in range(len(cases)):
+        t, ok = run([i], cg.FP64)
+        t_one += t
+        ok_one &= ok
+    one = NC * args.steps / t_one
+    sizes = sorted({lm.n_cell for lm in lms})
+    line = dict(metric="cell-updates/s per p-MG cycle", value=out["fp64"][0], unit="cell-updates/s", n_gpus=1,
+                steps=args.steps, warmup=args.warmup, ms_per_step=1e3 * NC / out["fp64"][0],
+                higher_is_better=True, scaling="weak", vs_baseline=None, dtype="f64",
+                data="synthetic (seeded cylinder meshes and free streams, uniform start)",
+                config=dict(workload="batch of 64 inviscid cylinders (n_theta in {32,64,128,256}, n_r = n_theta/2, "
+                            "Ma ~ U[0.1,0.4], AoA ~ U[-5,5] deg), one launch per kernel for all cases, "
+                            f"graphs of {G} cycles", cases=len(cases), cells=NC, case_sizes=sizes),
+                mixed32_value=out["mixed32"][0], one_at_a_time_fp64_value=one,
+                batched_speedup_fp64=out["fp64"][0] / one, batched_speedup_mixed32=out["mixed32"][0] / one,
+                finite=dict(fp64=out["fp64"][1], mixed32=out["mixed32"][1], one_at_a_time=ok_one))
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="sphere", choices=["sphere", "cylinder"])
+    ap.add_argument("--workload", default="sphere", choices=["sphere", "cylinder", "batch64"])
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed32", "mixed32_r64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
@@ -203,6 +263,10 @@ def main():
         print(f"bench.py: this build measures one GPU only; --gpus {args.gpus} is not supported "
               "(independent cases shard across GPUs without communication)", file=sys.stderr)
         sys.exit(2)
+
+    if args.workload == "batch64":
+        run_batch(args)
+        return
 
     import torch
     import paper_2109_09965_amd as cg

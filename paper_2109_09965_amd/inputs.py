@@ -618,13 +618,24 @@ def sphere_case_mesh():
     return cubed_sphere_mesh(28, 40, 20, 10, 0.5, 15.0, 1.08, first_spacing=0.05597)
 
 
-def batch_cases(n_cases=64, seed=2109):
-    """Seeded list of 2-D cylinder cases: n_theta in {32,64,128,256},
-    n_r = n_theta/2, Mach ~ U[0.1,0.6], AoA ~ U[-5,5] deg."""
+def batch_case_mesh(case):
+    """Cylinder O-mesh of one batch case, built like the 64 x 32 cylinder:
+    radius 0.5 to 20 with the same total radial stretch (ratio 1.1 per
+    layer at 32 layers, 1.1^(32/n_r) at n_r layers), split triangles."""
+    nr = case["n_r"]
+    return cylinder_mesh(case["n_theta"], nr, ratio=1.1 ** (32.0 / nr))
+
+
+def batch_cases(n_cases=64, seed=2109, mach=(0.1, 0.4)):
+    """Seeded list of 2-D inviscid cylinder cases: n_theta in {32,64,128,256},
+    n_r = n_theta/2, Mach ~ U[mach], AoA ~ U[-5,5] deg.  The default Mach
+    range stops at the cylinder's critical Mach number (about 0.4): beyond
+    it supersonic pockets and shocks form, which the smooth-flow scheme with
+    linear reconstruction weights does not capture."""
     rng = np.random.default_rng(seed)
     out = []
     for _ in range(n_cases):
         nt = int(rng.choice([32, 64, 128, 256]))
-        out.append(dict(n_theta=nt, n_r=nt // 2, mach=float(rng.uniform(0.1, 0.6)),
+        out.append(dict(n_theta=nt, n_r=nt // 2, mach=float(rng.uniform(*mach)),
                         aoa=float(rng.uniform(-5.0, 5.0))))
     return out
