@@ -151,6 +151,48 @@ cgks_status cgks_mesh_destroy(cgks_mesh *mesh);
    CGKS_ENOMEM. */
 cgks_status cgks_batch_create(const cgks_mesh *const *meshes, const cgks_params *params, int32_t n_case,
                               int32_t precision, cgks_batch **out);
+/* A pool: a batch with capacities instead of cases, for continuous
+   batching.  Up to max_cases cases live in it at once; each admitted case
+   holds one contiguous range of cells, faces, Gauss points and boundary
+   faces (the counts cgks_mesh_query reports) until it is released, so the
+   capacities are the pool's HBM footprint (cgks_batch_query gives the
+   bytes).  Every launch covers all admitted cases; entities of free ranges
+   are skipped.  A case gives bitwise the same results in a pool, alone or
+   among others admitted and released around it (no reduction or sweep
+   block spans two cases, and their shapes depend only on the case).  All
+   cases of a pool share dim, precision, n_implicit, n_sweeps, time_scheme
+   and explicit_only.  Arrays the library exposes in library cell order
+   ([nv][cells] residuals) use max_cells as the row length. */
+typedef struct {
+    int32_t dim, precision, max_cases;
+    int64_t max_cells, max_faces, max_gauss_points, max_boundary_faces;
+    int32_t n_implicit, n_sweeps, time_scheme, explicit_only;
+} cgks_pool_desc;
+cgks_status cgks_pool_create(const cgks_pool_desc *desc, cgks_batch **out);
+/* Admit a case into a free slot of a bound pool (the mesh must outlive its
+   stay): uploads its geometry into free ranges found first-fit, zeroes its
+   state and marks it active; *slot receives the case index to use with the
+   state, residual and report calls.  Upload an initial state next.
+   CGKS_ENOMEM when no slot or no free range of some entity type is large
+   enough (the caller keeps the request waiting; nothing changed),
+   CGKS_EINVAL on a dim or parameter mismatch, CGKS_EUNSUPPORTED for a mesh
+   with more than 16 colours.  Synchronous on stream; drops a captured
+   graph. */
+cgks_status cgks_batch_admit(cgks_batch *batch, const cgks_mesh *mesh, const cgks_params *params, int32_t *slot,
+                             void *stream);
+/* Stop and remove the case in slot; its ranges become free.  Download its
+   state first if needed.  Synchronous on stream; drops a captured graph.
+   CGKS_EINVAL for a free slot. */
+cgks_status cgks_batch_release(cgks_batch *batch, int32_t slot, void *stream);
+
+/* Slots and cell capacity of a batch or pool (the row length of the
+   [nv][cells] library-order arrays). */
+cgks_status cgks_batch_capacity(const cgks_batch *batch, int32_t *max_cases, int64_t *max_cells);
+/* Whether slot holds a case, the library index of its first cell (-1 when
+   free) and its cell count. */
+cgks_status cgks_batch_slot_info(const cgks_batch *batch, int32_t slot, int32_t *live, int64_t *cell_offset,
+                                 int64_t *n_cell);
+
 /* Device bytes the batch needs (geometry, state, work arrays). */
 cgks_status cgks_batch_query(const cgks_batch *batch, size_t *device_bytes);
 /* Bind a caller-owned device buffer of at least cgks_batch_query bytes

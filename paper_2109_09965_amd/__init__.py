@@ -27,7 +27,8 @@ EXPORTS = ["cgks_status_string", "cgks_mesh_create", "cgks_mesh_query", "cgks_me
            "cgks_mesh_geometry", "cgks_mesh_destroy", "cgks_batch_create", "cgks_batch_query", "cgks_batch_bind", "cgks_batch_destroy",
            "cgks_state_upload", "cgks_state_download", "cgks_state_device", "cgks_highorder_stage",
            "cgks_residual", "cgks_lowlevel_smooth", "cgks_cycle", "cgks_solve", "cgks_timing_enable",
-           "cgks_timing_read", "cgks_graph_create", "cgks_graph_launch", "cgks_graph_destroy", "cgks_wall_force"]
+           "cgks_timing_read", "cgks_graph_create", "cgks_graph_launch", "cgks_graph_destroy", "cgks_wall_force",
+           "cgks_pool_create", "cgks_batch_admit", "cgks_batch_release", "cgks_batch_capacity", "cgks_batch_slot_info"]
 KERNEL_KINDS = ["dt", "recon", "flux", "cell", "low_face", "low_cell", "sweep", "prolong"]
 
 
@@ -60,6 +61,13 @@ class _Params(C.Structure):
 class _SolveOpts(C.Structure):
     _fields_ = [("max_cycles", C.c_int32), ("tol", C.c_double), ("tol_abs", C.c_int32),
                 ("check_every", C.c_int32), ("res_history", C.c_void_p)]
+
+
+class _PoolDesc(C.Structure):
+    _fields_ = [("dim", C.c_int32), ("precision", C.c_int32), ("max_cases", C.c_int32),
+                ("max_cells", C.c_int64), ("max_faces", C.c_int64), ("max_gauss_points", C.c_int64),
+                ("max_boundary_faces", C.c_int64), ("n_implicit", C.c_int32), ("n_sweeps", C.c_int32),
+                ("time_scheme", C.c_int32), ("explicit_only", C.c_int32)]
 
 
 class _SolveReport(C.Structure):
@@ -109,6 +117,11 @@ def lib():
         L.cgks_graph_destroy.argtypes = [P]
         L.cgks_timing_read.argtypes = [P, P, P]
         L.cgks_wall_force.argtypes = [P, P, P]
+        L.cgks_pool_create.argtypes = [C.POINTER(_PoolDesc), C.POINTER(P)]
+        L.cgks_batch_admit.argtypes = [P, P, P, C.POINTER(C.c_int32), P]
+        L.cgks_batch_release.argtypes = [P, i32, P]
+        L.cgks_batch_capacity.argtypes = [P, C.POINTER(C.c_int32), C.POINTER(C.c_int64)]
+        L.cgks_batch_slot_info.argtypes = [P, i32, C.POINTER(C.c_int32), C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
         for name in EXPORTS:
             getattr(L, name).restype = C.c_int if name != "cgks_status_string" else C.c_char_p
         _lib = L
@@ -204,31 +217,83 @@ def _stream(stream):
 class Batch:
     """A batch of cases bound to one device arena (a torch uint8 tensor)."""
 
-    def __init__(self, meshes, params, precision=FP64, device="cuda", stream=None):
+    def __init__(self, meshes, params, precision=FP64, device="cuda", stream=None, _pool=None):
+        L = lib()
+        h = C.c_void_p()
+        if _pool is None:
+            self.meshes = list(meshes)
+            self.params = list(params)
+            n = len(self.meshes)
+            arr_m = (C.c_void_p * n)(*[m.h.value for m in self.meshes])
+            arr_p = (_Params * n)(*[p.c() for p in self.params])
+            self._keep = (arr_m, arr_p)
+            _check(L.cgks_batch_create(arr_m, arr_p, n, precision, C.byref(h)), "cgks_batch_create")
+            self.dim = self.meshes[0].dim
+        else:
+            _check(L.cgks_pool_create(C.byref(_pool), C.byref(h)), "cgks_pool_create")
+            self.meshes = [None] * _pool.max_cases
+            self.params = [None] * _pool.max_cases
+            self.dim = _pool.dim
+        self.h = h
+        self.precision = precision
+        self._bind(device, stream)
+
+    @classmethod
+    def pool(cls, dim, max_cases, max_cells, max_faces, max_gauss_points, max_boundary_faces, precision=FP64,
+             n_implicit=6, n_sweeps=2, time_scheme=S2O4, explicit_only=0, device="cuda", stream=None):
+        """An empty pool of fixed capacity; cases enter with admit() and
+        leave with release()."""
+        q = _PoolDesc(dim, precision, max_cases, max_cells, max_faces, max_gauss_points, max_boundary_faces,
+                      n_implicit, n_sweeps, time_scheme, explicit_only)
+        return cls(None, None, precision=precision, device=device, stream=stream, _pool=q)
+
+    def _bind(self, device, stream):
         import torch
         L = lib()
-        self.meshes = list(meshes)
-        self.params = list(params)
-        n = len(self.meshes)
-        arr_m = (C.c_void_p * n)(*[m.h.value for m in self.meshes])
-        arr_p = (_Params * n)(*[p.c() for p in self.params])
-        self._keep = (arr_m, arr_p)
-        h = C.c_void_p()
-        _check(L.cgks_batch_create(arr_m, arr_p, n, precision, C.byref(h)), "cgks_batch_create")
-        self.h = h
         nb = C.c_size_t()
-        _check(L.cgks_batch_query(h, C.byref(nb)), "cgks_batch_query")
+        _check(L.cgks_batch_query(self.h, C.byref(nb)), "cgks_batch_query")
         self.nbytes = nb.value
         self.arena = torch.empty(self.nbytes + 256, dtype=torch.uint8, device=device)
         base = self.arena.data_ptr()
         self._base = (base + 255) & ~255
         self.stream = stream
-        _check(L.cgks_batch_bind(h, C.c_void_p(self._base), self.nbytes, _stream(stream)), "cgks_batch_bind")
-        self.n_case = n
-        self.dim = self.meshes[0].dim
+        _check(L.cgks_batch_bind(self.h, C.c_void_p(self._base), self.nbytes, _stream(stream)), "cgks_batch_bind")
+        k, nc = C.c_int32(), C.c_int64()
+        _check(L.cgks_batch_capacity(self.h, C.byref(k), C.byref(nc)), "cgks_batch_capacity")
+        self.n_case = k.value
+        self.NC = nc.value
         self.nv = self.dim + 2
-        self.cell_off = np.concatenate([[0], np.cumsum([m.n_cell for m in self.meshes])]).astype(np.int64)
-        self.NC = int(self.cell_off[-1])
+        self._slots()
+
+    def _slots(self):
+        L = lib()
+        self.cell_off = np.full(self.n_case, -1, np.int64)
+        self.live = np.zeros(self.n_case, bool)
+        for c in range(self.n_case):
+            lv, off, n = C.c_int32(), C.c_int64(), C.c_int64()
+            _check(L.cgks_batch_slot_info(self.h, c, C.byref(lv), C.byref(off), C.byref(n)), "cgks_batch_slot_info")
+            self.live[c] = bool(lv.value)
+            self.cell_off[c] = off.value
+
+    def admit(self, mesh, params):
+        """Admit a case into a free slot; returns the slot, or None when the
+        pool has no room (CGKS_ENOMEM)."""
+        slot = C.c_int32()
+        st = lib().cgks_batch_admit(self.h, mesh.h, C.byref(params.c()), C.byref(slot), _stream(self.stream))
+        if st == ENOMEM:
+            return None
+        _check(st, "cgks_batch_admit")
+        c = slot.value
+        self.meshes[c] = mesh
+        self.params[c] = params
+        self._slots()
+        return c
+
+    def release(self, slot):
+        _check(lib().cgks_batch_release(self.h, slot, _stream(self.stream)), "cgks_batch_release")
+        self.meshes[slot] = None
+        self.params[slot] = None
+        self._slots()
 
     def __del__(self):
         if getattr(self, "h", None) and _lib is not None:
@@ -262,7 +327,7 @@ class Batch:
         """[k, NC] library-order array (numpy) -> [k, n_c] in case c's caller order."""
         m = self.meshes[c]
         out = np.empty((X.shape[0], m.n_cell))
-        out[:, m.lib2caller] = X[:, self.cell_off[c]:self.cell_off[c + 1]]
+        out[:, m.lib2caller] = X[:, self.cell_off[c]:self.cell_off[c] + m.n_cell]
         return out
 
     def lowlevel_smooth(self, R1):

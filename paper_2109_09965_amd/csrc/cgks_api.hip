@@ -18,6 +18,56 @@ namespace {
 
 constexpr int kRedChunk = 1024;   // cells per reduction block (never straddles cases)
 constexpr int kMaxGraphCycles = 64;   // cycles one captured graph may hold
+constexpr int kMaxColours = 16;   // colours a mesh may use
+constexpr int kSweepChunk = kBlock / 4;   // cells per sweep block (Dim<D>::sl lanes per cell)
+
+// First-fit allocator of index ranges in [0, cap): the arena positions of
+// one entity type (cells, faces, Gauss points, boundary slots).
+struct RangeAlloc {
+    int64_t cap = 0;
+    std::vector<std::pair<int64_t, int64_t>> free_r;   // (start, length), sorted, coalesced
+    std::vector<std::pair<int64_t, int64_t>> used;     // allocated ranges
+    void reset(int64_t c) {
+        cap = c;
+        free_r.clear();
+        used.clear();
+        if (c > 0) free_r.push_back({0, c});
+    }
+    int64_t take(int64_t n) {
+        if (n == 0) return 0;
+        for (size_t k = 0; k < free_r.size(); ++k)
+            if (free_r[k].second >= n) {
+                const int64_t st = free_r[k].first;
+                free_r[k].first += n;
+                free_r[k].second -= n;
+                if (free_r[k].second == 0) free_r.erase(free_r.begin() + k);
+                used.push_back({st, n});
+                return st;
+            }
+        return -1;
+    }
+    void give(int64_t st, int64_t n) {
+        if (n == 0) return;
+        for (size_t k = 0; k < used.size(); ++k)
+            if (used[k].first == st && used[k].second == n) {
+                used.erase(used.begin() + k);
+                break;
+            }
+        free_r.push_back({st, n});
+        std::sort(free_r.begin(), free_r.end());
+        std::vector<std::pair<int64_t, int64_t>> m;
+        for (auto &r : free_r) {
+            if (!m.empty() && m.back().first + m.back().second == r.first) m.back().second += r.second;
+            else m.push_back(r);
+        }
+        free_r.swap(m);
+    }
+    int64_t high_water() const {
+        int64_t h = 0;
+        for (auto &r : used) h = std::max(h, r.first + r.second);
+        return h;
+    }
+};
 
 struct Arena {
     size_t off = 0;
@@ -31,12 +81,23 @@ struct Arena {
 
 }  // namespace
 
+// A batch is a pool of n_case case slots over an arena with fixed
+// capacities NC, NF, NG, NB (cells, faces, Gauss points, boundary slots;
+// they are also the strides of the structure-of-arrays fields).  An
+// admitted case holds one contiguous range of each entity type for its
+// lifetime; kernels launch over the high-water marks and skip entities of
+// free slots (case id n_case, never active).
 struct cgks_batch {
     int n_case = 0, dim = 0, precision = 0;
-    std::vector<const cgks_mesh *> meshes;
+    std::vector<const cgks_mesh *> meshes;   // per slot, nullptr when free
     std::vector<cgks_params> params;
-    int64_t NC = 0, NF = 0, NG = 0, NB = 0;
+    std::vector<char> live;
+    int64_t NC = 0, NF = 0, NG = 0, NB = 0;          // capacities
+    int64_t hwC = 0, hwF = 0, hwG = 0, hwB = 0;      // launch extents
+    RangeAlloc ac, af, ag, ab;
     std::vector<int64_t> cell_off, face_off, gp_base, b_off;
+    std::vector<std::pair<const cgks_mesh *, cgks_params>> pending;   // admitted at bind
+    int64_t max_rb = 0, max_cb = 0;
     int max_colour = 0;
     // sweep blocks per colour
     std::vector<int32_t> cb_start, cb_count;
@@ -49,10 +110,10 @@ struct cgks_batch {
     char *base = nullptr;
     struct {
         size_t st, ev, Wn, L0, Lt0, G0, geo, vol, h, minv, slot, cell_case;
-        size_t fL, fR, fbc, fcase, gp_off, bslot, avec, S, shift, gavg, bface, gdat;
+        size_t fL, fR, fbc, fcase, gp_rng, bslot, avec, S, shift, gavg, bface, gdat;
         size_t gx, gn, gw, fsum, fsum32, ev32, minv32;
         size_t U, Sf, RHS, D, R1, lowf, swp;
-        size_t prm, dt, res, force, case_b_off, flag, rb_start, rb_count, rb_case, case_rb_off, part0, part1,
+        size_t prm, dt, res, force, case_b, flag, rb_start, rb_count, rb_case, case_rb_off, part0, part1,
             cb_start, cb_count;
         size_t res_hist;
     } o{};
@@ -114,7 +175,7 @@ void layout(cgks_batch *b) {
     o.fR = a.take<int32_t>(NF);
     o.fbc = a.take<int32_t>(NF);
     o.fcase = a.take<int32_t>(NF);
-    o.gp_off = a.take<int32_t>(NF + 1);
+    o.gp_rng = a.take<int2>(NF);
     o.bslot = a.take<int32_t>(NF);
     o.avec = a.take<double>(d * NF);
     o.S = a.take<double>(NF);
@@ -137,20 +198,25 @@ void layout(cgks_batch *b) {
     o.R1 = a.take<double>(nv * NC);
     o.lowf = a.take<double>(nv * NF);
     o.swp = a.take<double>(4 * NF);
-    o.prm = a.take<DevParams>(b->n_case);
-    o.dt = a.take<double>(b->n_case);
-    o.res = a.take<double>(b->n_case);
-    o.force = a.take<double>(3 * size_t(b->n_case));
-    o.case_b_off = a.take<int32_t>(b->n_case + 1);
-    o.flag = a.take<int32_t>(b->n_case);
-    o.rb_start = a.take<int32_t>(b->rb_start.size());
-    o.rb_count = a.take<int32_t>(b->rb_start.size());
-    o.rb_case = a.take<int32_t>(b->rb_start.size());
-    o.case_rb_off = a.take<int32_t>(b->n_case + 1);
-    o.part0 = a.take<double>(b->rb_start.size());
-    o.part1 = a.take<double>(b->rb_start.size());
-    o.cb_start = a.take<int32_t>(std::max<size_t>(b->cb_start.size(), 1));
-    o.cb_count = a.take<int32_t>(std::max<size_t>(b->cb_start.size(), 1));
+    // per slot, plus the never-active slot n_case that free entities point to
+    const size_t K1 = size_t(b->n_case) + 1;
+    o.prm = a.take<DevParams>(K1);
+    o.dt = a.take<double>(K1);
+    o.res = a.take<double>(K1);
+    o.force = a.take<double>(3 * K1);
+    o.case_b = a.take<int2>(K1);
+    o.flag = a.take<int32_t>(K1);
+    // table capacities: every case adds at most one partial chunk per block kind
+    b->max_rb = int64_t(NC) / kRedChunk + b->n_case + 1;
+    b->max_cb = int64_t(NC) / kSweepChunk + int64_t(b->n_case) * kMaxColours + 1;
+    o.rb_start = a.take<int32_t>(b->max_rb);
+    o.rb_count = a.take<int32_t>(b->max_rb);
+    o.rb_case = a.take<int32_t>(b->max_rb);
+    o.case_rb_off = a.take<int32_t>(K1 + 1);
+    o.part0 = a.take<double>(b->max_rb);
+    o.part1 = a.take<double>(b->max_rb);
+    o.cb_start = a.take<int32_t>(b->max_cb);
+    o.cb_count = a.take<int32_t>(b->max_cb);
     b->res_hist_len = size_t(kMaxGraphCycles) * b->n_case;
     o.res_hist = a.take<double>(b->res_hist_len);
     b->bytes = (a.off + 255) & ~size_t(255);
@@ -187,12 +253,12 @@ void fill_dev(cgks_batch *b) {
     d.slot = at<int2>(b, o.slot);
     d.cell_case = at<int32_t>(b, o.cell_case);
     d.fL = at<int32_t>(b, o.fL); d.fR = at<int32_t>(b, o.fR); d.fbc = at<int32_t>(b, o.fbc);
-    d.fcase = at<int32_t>(b, o.fcase); d.gp_off = at<int32_t>(b, o.gp_off); d.bslot = at<int32_t>(b, o.bslot);
+    d.fcase = at<int32_t>(b, o.fcase); d.gp_rng = at<int2>(b, o.gp_rng); d.bslot = at<int32_t>(b, o.bslot);
     d.avec = at<double>(b, o.avec); d.S = at<double>(b, o.S); d.shift = at<double>(b, o.shift);
     d.gavg = at<double>(b, o.gavg);
     d.bface = at<int32_t>(b, o.bface);
     d.gdat = at<double>(b, o.gdat);
-    d.NB_real = int32_t(b->NB);
+    d.NB_real = int32_t(b->hwB);
     d.gx = at<double>(b, o.gx); d.gn = at<double>(b, o.gn); d.gw = at<double>(b, o.gw);
     d.fsum = at<double>(b, o.fsum);
     d.fsum32 = at<float>(b, o.fsum32);
@@ -203,7 +269,7 @@ void fill_dev(cgks_batch *b) {
     d.lowf = at<double>(b, o.lowf); d.swp = at<double>(b, o.swp);
     d.prm = at<DevParams>(b, o.prm); d.dt = at<double>(b, o.dt); d.res = at<double>(b, o.res);
     d.flag = at<int32_t>(b, o.flag);
-    d.force = at<double>(b, o.force); d.case_b_off = at<int32_t>(b, o.case_b_off);
+    d.force = at<double>(b, o.force); d.case_b = at<int2>(b, o.case_b);
     d.rb_start = at<int32_t>(b, o.rb_start); d.rb_count = at<int32_t>(b, o.rb_count);
     d.rb_case = at<int32_t>(b, o.rb_case); d.case_rb_off = at<int32_t>(b, o.case_rb_off);
     d.part0 = at<double>(b, o.part0); d.part1 = at<double>(b, o.part1);
@@ -249,18 +315,18 @@ template <class F> void timed(cgks_batch *b, int kind, hipStream_t s, F &&launch
 template <int D, typename R> void launch_ho_kernels(cgks_batch *b, int mode, hipStream_t s) {
     const Dev &d = b->dev;
     timed(b, CGKS_K_RECON, s, [&] {
-        if (b->NB > 0) hipLaunchKernelGGL(k_ghost<D>, dim3(nblk(b->NB)), dim3(kBlock), 0, s, d);
-        hipLaunchKernelGGL((k_recon<D, R>), dim3(unsigned((b->NC + kReconBlock - 1) / kReconBlock)),
+        if (b->hwB > 0) hipLaunchKernelGGL(k_ghost<D>, dim3(nblk(b->hwB)), dim3(kBlock), 0, s, d);
+        hipLaunchKernelGGL((k_recon<D, R>), dim3(unsigned((b->hwC + kReconBlock - 1) / kReconBlock)),
                            dim3(kReconBlock), 0, s, d);
     });
     timed(b, CGKS_K_FLUX, s, [&] {
-        hipLaunchKernelGGL((k_flux<D, R>), dim3(nblk(b->NF * Dim<D>::lanes)), dim3(kBlock), 0, s, d,
+        hipLaunchKernelGGL((k_flux<D, R>), dim3(nblk(b->hwF * Dim<D>::lanes)), dim3(kBlock), 0, s, d,
                            (int)(mode != MODE_R1));
     });
-    if (mode == MODE_STAGE0 && b->NB > 0)
+    if (mode == MODE_STAGE0 && b->hwB > 0)
         hipLaunchKernelGGL((k_wall_force<D, R>), dim3(b->n_case), dim3(kBlock), 0, s, d);
     timed(b, CGKS_K_CELL, s, [&] {
-        hipLaunchKernelGGL((k_cell<D, R>), dim3(nblk(b->NC * Dim<D>::sl)), dim3(kBlock), 0, s, d, mode);
+        hipLaunchKernelGGL((k_cell<D, R>), dim3(nblk(b->hwC * Dim<D>::sl)), dim3(kBlock), 0, s, d, mode);
     });
 }
 
@@ -299,20 +365,20 @@ template <int D, typename S> cgks_status launch_lowlevel_s(cgks_batch *b, const 
     if (R1 != d.R1)
         HIP_TRY(hipMemcpyAsync(d.R1, R1, sizeof(double) * (D + 2) * b->NC, hipMemcpyDeviceToDevice, s));
     timed(b, CGKS_K_LOWFACE, s, [&] {
-        hipLaunchKernelGGL((k_low_face<D, S>), dim3(nblk(b->NF)), dim3(kBlock), 0, s, d, (int)LOW_SRC_W);
+        hipLaunchKernelGGL((k_low_face<D, S>), dim3(nblk(b->hwF)), dim3(kBlock), 0, s, d, (int)LOW_SRC_W);
     });
     timed(b, CGKS_K_LOWCELL, s, [&] {
-        hipLaunchKernelGGL((k_low_cell<D, S>), dim3(nblk(b->NC * Dim<D>::sl)), dim3(kBlock), 0, s, d,
+        hipLaunchKernelGGL((k_low_cell<D, S>), dim3(nblk(b->hwC * Dim<D>::sl)), dim3(kBlock), 0, s, d,
                            (int)LOW_FORCE, (double *)nullptr);
     });
     const std::vector<int> order = sweep_order(b->max_colour, b->n_sweeps);
     for (int k = 0; k < b->n_implicit; ++k) {
         timed(b, CGKS_K_LOWFACE, s, [&] {
-            hipLaunchKernelGGL((k_low_face<D, S>), dim3(nblk(b->NF)), dim3(kBlock), 0, s, d,
+            hipLaunchKernelGGL((k_low_face<D, S>), dim3(nblk(b->hwF)), dim3(kBlock), 0, s, d,
                                (int)(k ? LOW_SRC_U_DU : LOW_SRC_U));
         });
         timed(b, CGKS_K_LOWCELL, s, [&] {
-            hipLaunchKernelGGL((k_low_cell<D, S>), dim3(nblk(b->NC * Dim<D>::sl)), dim3(kBlock), 0, s, d,
+            hipLaunchKernelGGL((k_low_cell<D, S>), dim3(nblk(b->hwC * Dim<D>::sl)), dim3(kBlock), 0, s, d,
                                (int)(k ? LOW_STEP : LOW_STEP_FIRST), (double *)nullptr);
         });
         // the colour passes of one step run back to back: one timing span
@@ -442,80 +508,314 @@ cgks_status cgks_mesh_destroy(cgks_mesh *mesh) {
     return CGKS_OK;
 }
 
-cgks_status cgks_batch_create(const cgks_mesh *const *meshes, const cgks_params *params, int32_t n_case,
-                              int32_t precision, cgks_batch **out) {
-    if (!out || !meshes || !params || n_case <= 0) return CGKS_EINVAL;
+}  // extern "C"
+
+static bool params_ok(const cgks_batch *b, const cgks_params &p) {
+    return p.n_implicit == b->n_implicit && p.n_sweeps == b->n_sweeps && p.time_scheme == b->scheme &&
+           p.explicit_only == b->explicit_only && p.n_implicit >= 0 && p.n_sweeps >= 0 &&
+           (p.time_scheme == CGKS_S2O4 || p.time_scheme == CGKS_S1O2) && p.gamma > 1.0 && p.mu >= 0 && p.Pr > 0 &&
+           p.T_wall > 0 && p.cfl_high > 0 && p.cfl_low > 0;
+}
+
+static cgks_status new_pool(const cgks_pool_desc &q, cgks_batch **out) {
     *out = nullptr;
-    if (precision != CGKS_FP64 && precision != CGKS_MIXED32 && precision != CGKS_MIXED32_R64) return CGKS_EINVAL;
-    try {
-        cgks_batch *b = new cgks_batch;
-        b->n_case = n_case;
-        b->precision = precision;
-        b->dim = meshes[0] ? meshes[0]->hm.dim : 0;
-        b->n_implicit = params[0].n_implicit;
-        b->n_sweeps = params[0].n_sweeps;
-        b->scheme = params[0].time_scheme;
-        b->explicit_only = params[0].explicit_only;
-        for (int c = 0; c < n_case; ++c) {
-            const cgks_mesh *m = meshes[c];
-            const cgks_params &p = params[c];
-            if (!m || m->hm.dim != b->dim || p.n_implicit != b->n_implicit || p.n_sweeps != b->n_sweeps ||
-                p.time_scheme != b->scheme || p.explicit_only != b->explicit_only || p.n_implicit < 0 ||
-                p.n_sweeps < 0 || (p.time_scheme != CGKS_S2O4 && p.time_scheme != CGKS_S1O2) || !(p.gamma > 1.0) ||
-                p.mu < 0 || !(p.Pr > 0) || !(p.T_wall > 0) || !(p.cfl_high > 0) || !(p.cfl_low > 0)) {
-                delete b;
-                return CGKS_EINVAL;
+    if ((q.dim != 2 && q.dim != 3) || q.max_cases <= 0 || q.max_cells <= 0 || q.max_faces <= 0 ||
+        q.max_gauss_points <= 0 || q.max_boundary_faces < 0)
+        return CGKS_EINVAL;
+    if (q.precision != CGKS_FP64 && q.precision != CGKS_MIXED32 && q.precision != CGKS_MIXED32_R64) return CGKS_EINVAL;
+    // 32-bit indices: slot tables [8][cells], four lanes per face
+    if (q.max_cells > INT32_MAX / 8 || q.max_faces > INT32_MAX / 8 || q.max_gauss_points > INT32_MAX / 2 ||
+        q.max_boundary_faces > INT32_MAX / 2)
+        return CGKS_EINVAL;
+    cgks_batch *b = new cgks_batch;
+    b->n_case = q.max_cases;
+    b->dim = q.dim;
+    b->precision = q.precision;
+    b->NC = q.max_cells;
+    b->NF = q.max_faces;
+    b->NG = q.max_gauss_points;
+    b->NB = q.max_boundary_faces;
+    b->n_implicit = q.n_implicit;
+    b->n_sweeps = q.n_sweeps;
+    b->scheme = q.time_scheme;
+    b->explicit_only = q.explicit_only;
+    const size_t K = size_t(q.max_cases);
+    b->meshes.assign(K, nullptr);
+    b->params.assign(K, cgks_params{});
+    b->live.assign(K, 0);
+    b->cell_off.assign(K, 0);
+    b->face_off.assign(K, 0);
+    b->gp_base.assign(K, 0);
+    b->b_off.assign(K, 0);
+    b->ac.reset(b->NC);
+    b->af.reset(b->NF);
+    b->ag.reset(b->NG);
+    b->ab.reset(b->NB);
+    layout(b);
+    *out = b;
+    return CGKS_OK;
+}
+
+__global__ void k_fill_i32(int32_t *p, int64_t n, int32_t v) {
+    const int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+static hipError_t fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_i32, dim3(nblk(n)), dim3(kBlock), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
+// strided upload of a structure-of-arrays slice: ncomp rows of n elements
+// from host (row pitch n) to field base + off elements (row pitch stride)
+template <class T>
+static hipError_t put_soa(cgks_batch *b, size_t field, int64_t off, int64_t stride, const std::vector<T> &v,
+                          int64_t n, int ncomp, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    return hipMemcpy2DAsync(b->base + field + size_t(off) * sizeof(T), size_t(stride) * sizeof(T), v.data(),
+                            size_t(n) * sizeof(T), size_t(n) * sizeof(T), size_t(ncomp), hipMemcpyHostToDevice, s);
+}
+template <class T>
+static hipError_t put_at(cgks_batch *b, size_t field, int64_t off, const std::vector<T> &v, hipStream_t s) {
+    if (v.empty()) return hipSuccess;
+    return hipMemcpyAsync(b->base + field + size_t(off) * sizeof(T), v.data(), v.size() * sizeof(T),
+                          hipMemcpyHostToDevice, s);
+}
+
+// Geometry, slots and per-slot data of the case in slot c, written into its
+// ranges (host tables of that case only); synchronises the stream.
+static cgks_status upload_case(cgks_batch *b, int c, hipStream_t s) {
+    const HostMesh &m = b->meshes[c]->hm;
+    const int d = b->dim, nk = ncoef_of(d), nq = nquad_of(d), ns = d == 2 ? 4 : 8;
+    const int nsym = nk * (nk + 1) / 2, gr = d + nq + 1, nv = d + 2;
+    const int64_t n = m.n_cell, nf = m.n_face, ng = m.n_gp, nb = m.n_bface;
+    const int64_t co = b->cell_off[c], fo = b->face_off[c], go = b->gp_base[c], bo = b->b_off[c];
+    std::vector<double> vol(n), h(n), geo(gr * n), minv(nsym * n);
+    std::vector<int2> slot(ns * n, make_int2(0, -1));
+    std::vector<int32_t> cell_case(n, c);
+    std::vector<int32_t> fL(nf), fR(nf), fbc(nf), fcase(nf, c), bslot(nf, -1);
+    std::vector<int2> gp_rng(nf);
+    std::vector<double> avec(d * nf), S(nf), shift(d * nf), gavg(nk * nb), gx(d * ng), gn(d * ng), gw(ng);
+    std::vector<int32_t> bface(nb);
+    for (int64_t l = 0; l < n; ++l) {
+        const int64_t i = m.lib2caller[l];
+        vol[l] = m.vol[i];
+        h[l] = m.h[i];
+        for (int a = 0; a < d; ++a) geo[l * gr + a] = m.ctr[i * d + a];
+        for (int q = 0; q < nq; ++q) geo[l * gr + d + q] = m.sec[i * nq + q];
+        geo[l * gr + d + nq] = m.h[i];
+        int k = 0;
+        for (int r = 0; r < nk; ++r)
+            for (int t = r; t < nk; ++t) minv[(k++) * n + l] = m.minv[i * nk * nk + r * nk + t];
+        int sl = 0;
+        for (int64_t q = m.cf_ptr[i]; q < m.cf_ptr[i + 1]; ++q, ++sl) {
+            const int64_t f = m.cf_face[q];
+            const int side = m.cf_side[q];
+            const int64_t nbr = side ? m.owner[f] : m.neigh[f];
+            slot[sl * n + l] = make_int2(side ? -int32_t(fo + f + 1) : int32_t(fo + f + 1),
+                                         nbr >= 0 ? int32_t(co + m.caller2lib[nbr]) : -1);
+        }
+    }
+    int64_t bcount = 0;
+    for (int64_t f = 0; f < nf; ++f) {
+        fL[f] = int32_t(co + m.caller2lib[m.owner[f]]);
+        fR[f] = m.neigh[f] >= 0 ? int32_t(co + m.caller2lib[m.neigh[f]]) : -1;
+        fbc[f] = m.neigh[f] >= 0 ? 0 : m.bc[f];
+        gp_rng[f] = make_int2(int32_t(go + m.gp_off[f]), int32_t(go + m.gp_off[f + 1]));
+        for (int a = 0; a < d; ++a) {
+            avec[a * nf + f] = m.avec[f * d + a];
+            shift[a * nf + f] = m.shift[f * d + a];
+        }
+        S[f] = m.S[f];
+        if (m.neigh[f] < 0) {
+            const int64_t B = bcount++;
+            bslot[f] = int32_t(bo + B);
+            bface[B] = int32_t(fo + f);
+            for (int k = 0; k < nk; ++k) gavg[k * nb + B] = m.gavg[f * nk + k];
+        }
+    }
+    for (int64_t g = 0; g < ng; ++g) {
+        for (int a = 0; a < d; ++a) {
+            gx[a * ng + g] = m.gx[g * d + a];
+            gn[a * ng + g] = m.gn[g * d + a];
+        }
+        gw[g] = m.gw[g];
+    }
+    auto &o = b->o;
+    HIP_TRY(put_at(b, o.vol, co, vol, s)); HIP_TRY(put_at(b, o.h, co, h, s));
+    HIP_TRY(put_at(b, o.geo, co * gr, geo, s));
+    HIP_TRY(put_soa(b, o.minv, co, b->NC, minv, n, nsym, s));
+    if (b->precision != CGKS_FP64) {
+        std::vector<float> m32(minv.begin(), minv.end());
+        HIP_TRY(put_soa(b, o.minv32, co, b->NC, m32, n, nsym, s));
+        HIP_TRY(hipStreamSynchronize(s));
+    }
+    HIP_TRY(put_soa(b, o.slot, co, b->NC, slot, n, ns, s));
+    HIP_TRY(put_at(b, o.cell_case, co, cell_case, s));
+    HIP_TRY(put_at(b, o.fL, fo, fL, s)); HIP_TRY(put_at(b, o.fR, fo, fR, s)); HIP_TRY(put_at(b, o.fbc, fo, fbc, s));
+    HIP_TRY(put_at(b, o.fcase, fo, fcase, s)); HIP_TRY(put_at(b, o.gp_rng, fo, gp_rng, s));
+    HIP_TRY(put_at(b, o.bslot, fo, bslot, s));
+    HIP_TRY(put_soa(b, o.avec, fo, b->NF, avec, nf, d, s)); HIP_TRY(put_at(b, o.S, fo, S, s));
+    HIP_TRY(put_soa(b, o.shift, fo, b->NF, shift, nf, d, s));
+    HIP_TRY(put_soa(b, o.gavg, bo, std::max<int64_t>(b->NB, 1), gavg, nb, nk, s));
+    HIP_TRY(put_at(b, o.bface, bo, bface, s));
+    HIP_TRY(put_soa(b, o.gx, go, b->NG, gx, ng, d, s)); HIP_TRY(put_soa(b, o.gn, go, b->NG, gn, ng, d, s));
+    HIP_TRY(put_at(b, o.gw, go, gw, s));
+    // per slot; the state and low-level records of the range start at zero
+    std::vector<DevParams> prm{dev_params(b->params[c], d)};
+    std::vector<double> zero3(3, 0.0), zero1(1, 0.0);
+    std::vector<int32_t> zflag(1, 0);
+    std::vector<int2> cb{make_int2(int32_t(bo), int32_t(nb))};
+    HIP_TRY(put_at(b, o.prm, c, prm, s)); HIP_TRY(put_at(b, o.force, 3 * int64_t(c), zero3, s));
+    HIP_TRY(put_at(b, o.dt, c, zero1, s)); HIP_TRY(put_at(b, o.res, c, zero1, s));
+    HIP_TRY(put_at(b, o.flag, c, zflag, s)); HIP_TRY(put_at(b, o.case_b, c, cb, s));
+    const int sr = nv + d * nv;
+    HIP_TRY(hipMemsetAsync(b->base + o.st + size_t(co) * sr * sizeof(double), 0, size_t(n) * sr * sizeof(double), s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return CGKS_OK;
+}
+
+// Sweep chunks (per colour, every live case's cells of that colour), the
+// per-case reduction blocks and the launch extents, after the set of live
+// cases changed.  Drops a captured graph (its launches have the old shape).
+static cgks_status rebuild_tables(cgks_batch *b, hipStream_t s) {
+    b->drop_graph();
+    b->hwC = b->ac.high_water();
+    b->hwF = b->af.high_water();
+    b->hwG = b->ag.high_water();
+    b->hwB = b->ab.high_water();
+    b->dev.NB_real = int32_t(b->hwB);
+    b->max_colour = 0;
+    for (int c = 0; c < b->n_case; ++c)
+        if (b->live[c]) b->max_colour = std::max(b->max_colour, b->meshes[c]->hm.n_colour);
+    b->cb_start.clear();
+    b->cb_count.clear();
+    b->colour_blk_off.assign(b->max_colour + 1, 0);
+    for (int col = 0; col < b->max_colour; ++col) {
+        for (int c = 0; c < b->n_case; ++c) {
+            if (!b->live[c]) continue;
+            const HostMesh &m = b->meshes[c]->hm;
+            if (col >= m.n_colour) continue;
+            int64_t start = b->cell_off[c];
+            for (int k = 0; k < col; ++k) start += m.colour_count[k];
+            const int64_t n = m.colour_count[col];
+            for (int64_t q = 0; q < n; q += kSweepChunk) {
+                b->cb_start.push_back(int32_t(start + q));
+                b->cb_count.push_back(int32_t(std::min<int64_t>(kSweepChunk, n - q)));
             }
-            b->meshes.push_back(m);
-            b->params.push_back(p);
-            b->cell_off.push_back(b->NC);
-            b->face_off.push_back(b->NF);
-            b->gp_base.push_back(b->NG);
-            b->b_off.push_back(b->NB);
-            b->NC += m->hm.n_cell;
-            b->NF += m->hm.n_face;
-            b->NG += m->hm.n_gp;
-            b->NB += m->hm.n_bface;
-            b->max_colour = std::max(b->max_colour, m->hm.n_colour);
         }
-        if (b->NC >= INT32_MAX || b->NG >= INT32_MAX) {
-            delete b;
-            return CGKS_EINVAL;
-        }
-        // sweep blocks: for each colour, every case's cells of that colour in
-        // chunks of kBlock (library order is colour-major within a case)
-        b->colour_blk_off.assign(b->max_colour + 1, 0);
-        for (int col = 0; col < b->max_colour; ++col) {
-            for (int c = 0; c < n_case; ++c) {
-                const HostMesh &m = meshes[c]->hm;
-                if (col >= m.n_colour) continue;
-                int64_t start = b->cell_off[c];
-                for (int k = 0; k < col; ++k) start += m.colour_count[k];
-                const int64_t n = m.colour_count[col];
-                const int64_t chunk = kBlock / 4;   // Dim<D>::sl lanes per cell
-                for (int64_t q = 0; q < n; q += chunk) {
-                    b->cb_start.push_back(int32_t(start + q));
-                    b->cb_count.push_back(int32_t(std::min<int64_t>(chunk, n - q)));
-                }
-            }
-            b->colour_blk_off[col + 1] = b->cb_start.size();
-        }
-        // reduction blocks: per case, chunks of kRedChunk cells
-        b->case_rb_off.push_back(0);
-        for (int c = 0; c < n_case; ++c) {
-            const int64_t n = meshes[c]->hm.n_cell;
+        b->colour_blk_off[col + 1] = b->cb_start.size();
+    }
+    b->rb_start.clear();
+    b->rb_count.clear();
+    b->rb_case.clear();
+    b->case_rb_off.assign(1, 0);
+    for (int c = 0; c <= b->n_case; ++c) {
+        if (c < b->n_case && b->live[c]) {
+            const int64_t n = b->meshes[c]->hm.n_cell;
             for (int64_t q = 0; q < n; q += kRedChunk) {
                 b->rb_start.push_back(int32_t(b->cell_off[c] + q));
                 b->rb_count.push_back(int32_t(std::min<int64_t>(kRedChunk, n - q)));
                 b->rb_case.push_back(c);
             }
-            b->case_rb_off.push_back(int32_t(b->rb_start.size()));
         }
-        layout(b);
+        b->case_rb_off.push_back(int32_t(b->rb_start.size()));
+    }
+    if (int64_t(b->cb_start.size()) > b->max_cb || int64_t(b->rb_start.size()) > b->max_rb) return CGKS_EINVAL;
+    auto &o = b->o;
+    HIP_TRY(put_at(b, o.cb_start, 0, b->cb_start, s)); HIP_TRY(put_at(b, o.cb_count, 0, b->cb_count, s));
+    HIP_TRY(put_at(b, o.rb_start, 0, b->rb_start, s)); HIP_TRY(put_at(b, o.rb_count, 0, b->rb_count, s));
+    HIP_TRY(put_at(b, o.rb_case, 0, b->rb_case, s)); HIP_TRY(put_at(b, o.case_rb_off, 0, b->case_rb_off, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return CGKS_OK;
+}
+
+static cgks_status admit(cgks_batch *b, const cgks_mesh *mesh, const cgks_params &p, int c, hipStream_t s) {
+    const HostMesh &m = mesh->hm;
+    if (m.dim != b->dim || !params_ok(b, p)) return CGKS_EINVAL;
+    if (m.n_colour > kMaxColours) return CGKS_EUNSUPPORTED;
+    const int64_t co = b->ac.take(m.n_cell);
+    const int64_t fo = co < 0 ? -1 : b->af.take(m.n_face);
+    const int64_t go = fo < 0 ? -1 : b->ag.take(m.n_gp);
+    const int64_t bo = go < 0 ? -1 : b->ab.take(m.n_bface);
+    if (bo < 0) {
+        if (go >= 0) b->ag.give(go, m.n_gp);
+        if (fo >= 0) b->af.give(fo, m.n_face);
+        if (co >= 0) b->ac.give(co, m.n_cell);
+        return CGKS_ENOMEM;
+    }
+    b->meshes[c] = mesh;
+    b->params[c] = p;
+    b->live[c] = 1;
+    b->cell_off[c] = co;
+    b->face_off[c] = fo;
+    b->gp_base[c] = go;
+    b->b_off[c] = bo;
+    return upload_case(b, c, s);
+}
+
+extern "C" {
+
+cgks_status cgks_batch_create(const cgks_mesh *const *meshes, const cgks_params *params, int32_t n_case,
+                              int32_t precision, cgks_batch **out) {
+    if (!out || !meshes || !params || n_case <= 0) return CGKS_EINVAL;
+    *out = nullptr;
+    try {
+        cgks_pool_desc q{};
+        q.dim = meshes[0] ? meshes[0]->hm.dim : 0;
+        q.precision = precision;
+        q.max_cases = n_case;
+        q.n_implicit = params[0].n_implicit;
+        q.n_sweeps = params[0].n_sweeps;
+        q.time_scheme = params[0].time_scheme;
+        q.explicit_only = params[0].explicit_only;
+        for (int c = 0; c < n_case; ++c) {
+            if (!meshes[c] || meshes[c]->hm.dim != q.dim) return CGKS_EINVAL;
+            q.max_cells += meshes[c]->hm.n_cell;
+            q.max_faces += meshes[c]->hm.n_face;
+            q.max_gauss_points += meshes[c]->hm.n_gp;
+            q.max_boundary_faces += meshes[c]->hm.n_bface;
+        }
+        cgks_batch *b = nullptr;
+        cgks_status st = new_pool(q, &b);
+        if (st) return st;
+        for (int c = 0; c < n_case; ++c) {
+            if (!params_ok(b, params[c]) || meshes[c]->hm.n_colour > kMaxColours) {
+                delete b;
+                return meshes[c]->hm.n_colour > kMaxColours ? CGKS_EUNSUPPORTED : CGKS_EINVAL;
+            }
+            b->pending.push_back({meshes[c], params[c]});
+        }
         *out = b;
     } catch (const std::bad_alloc &) {
         return CGKS_ENOMEM;
     }
+    return CGKS_OK;
+}
+
+cgks_status cgks_pool_create(const cgks_pool_desc *desc, cgks_batch **out) {
+    if (!desc || !out) return CGKS_EINVAL;
+    try {
+        return new_pool(*desc, out);
+    } catch (const std::bad_alloc &) {
+        return CGKS_ENOMEM;
+    }
+}
+
+cgks_status cgks_batch_capacity(const cgks_batch *b, int32_t *max_cases, int64_t *max_cells) {
+    if (!b || !max_cases || !max_cells) return CGKS_EINVAL;
+    *max_cases = b->n_case;
+    *max_cells = b->NC;
+    return CGKS_OK;
+}
+
+cgks_status cgks_batch_slot_info(const cgks_batch *b, int32_t slot, int32_t *live, int64_t *cell_offset,
+                                 int64_t *n_cell) {
+    if (!b || slot < 0 || slot >= b->n_case || !live || !cell_offset || !n_cell) return CGKS_EINVAL;
+    *live = b->live[slot];
+    *cell_offset = b->live[slot] ? b->cell_off[slot] : -1;
+    *n_cell = b->live[slot] ? b->meshes[slot]->hm.n_cell : 0;
     return CGKS_OK;
 }
 
@@ -526,112 +826,69 @@ cgks_status cgks_batch_query(const cgks_batch *b, size_t *bytes) {
 }
 
 cgks_status cgks_batch_bind(cgks_batch *b, void *buf, size_t bytes, void *stream) {
-    if (!b || !buf || (reinterpret_cast<uintptr_t>(buf) & 255)) return CGKS_EINVAL;
+    if (!b || !buf || (reinterpret_cast<uintptr_t>(buf) & 255) || b->base) return CGKS_EINVAL;
     if (bytes < b->bytes) return CGKS_ENOMEM;
     hipStream_t s = static_cast<hipStream_t>(stream);
     b->base = static_cast<char *>(buf);
     fill_dev(b);
-    const int d = b->dim, nv = d + 2, nk = ncoef_of(d), nq = nquad_of(d), ns = d == 2 ? 4 : 8;
-    const int nsym = nk * (nk + 1) / 2;
-    const size_t NC = b->NC, NF = b->NF, NG = b->NG, NB = std::max<int64_t>(b->NB, 1);
     try {
-        const int gr = d + nq + 1;
-        std::vector<double> vol(NC), h(NC), geo(gr * NC), minv(nsym * NC);
-        std::vector<int2> slot(ns * NC, make_int2(0, -1));
-        std::vector<int32_t> cell_case(NC);
-        std::vector<int32_t> fL(NF), fR(NF), fbc(NF), fcase(NF), gp_off(NF + 1), bslot(NF, -1);
-        std::vector<double> avec(d * NF), S(NF), shift(d * NF), gavg(nk * NB, 0.0), gx(d * NG), gn(d * NG), gw(NG);
-        std::vector<int32_t> bface(NB, 0);
-        std::vector<DevParams> prm;
-        for (int c = 0; c < b->n_case; ++c) {
-            const HostMesh &m = b->meshes[c]->hm;
-            const int64_t co = b->cell_off[c], fo = b->face_off[c], go = b->gp_base[c], bo = b->b_off[c];
-            prm.push_back(dev_params(b->params[c], d));
-            for (int64_t l = 0; l < m.n_cell; ++l) {
-                const int64_t i = m.lib2caller[l];
-                const int64_t I = co + l;
-                vol[I] = m.vol[i];
-                h[I] = m.h[i];
-                cell_case[I] = c;
-                for (int a = 0; a < d; ++a) geo[I * gr + a] = m.ctr[i * d + a];
-                for (int q = 0; q < nq; ++q) geo[I * gr + d + q] = m.sec[i * nq + q];
-                geo[I * gr + d + nq] = m.h[i];
-                int k = 0;
-                for (int r = 0; r < nk; ++r)
-                    for (int t = r; t < nk; ++t) minv[(k++) * NC + I] = m.minv[i * nk * nk + r * nk + t];
-                int sl = 0;
-                for (int64_t q = m.cf_ptr[i]; q < m.cf_ptr[i + 1]; ++q, ++sl) {
-                    const int64_t f = m.cf_face[q];
-                    const int side = m.cf_side[q];
-                    const int64_t nb = side ? m.owner[f] : m.neigh[f];
-                    slot[sl * NC + I] = make_int2(side ? -int32_t(fo + f + 1) : int32_t(fo + f + 1),
-                                                  nb >= 0 ? int32_t(co + m.caller2lib[nb]) : -1);
-                }
-            }
-            int64_t bcount = 0;
-            for (int64_t f = 0; f < m.n_face; ++f) {
-                const int64_t F = fo + f;
-                fL[F] = int32_t(co + m.caller2lib[m.owner[f]]);
-                fR[F] = m.neigh[f] >= 0 ? int32_t(co + m.caller2lib[m.neigh[f]]) : -1;
-                fbc[F] = m.neigh[f] >= 0 ? 0 : m.bc[f];
-                fcase[F] = c;
-                gp_off[F] = int32_t(go + m.gp_off[f]);
-                for (int a = 0; a < d; ++a) {
-                    avec[a * NF + F] = m.avec[f * d + a];
-                    shift[a * NF + F] = m.shift[f * d + a];
-                }
-                S[F] = m.S[f];
-                if (m.neigh[f] < 0) {
-                    const int64_t B = bo + bcount++;
-                    bslot[F] = int32_t(B);
-                    bface[B] = int32_t(F);
-                    for (int k = 0; k < nk; ++k) gavg[k * NB + B] = m.gavg[f * nk + k];
-                }
-            }
-            for (int64_t g = 0; g < m.n_gp; ++g) {
-                for (int a = 0; a < d; ++a) {
-                    gx[a * NG + go + g] = m.gx[g * d + a];
-                    gn[a * NG + go + g] = m.gn[g * d + a];
-                }
-                gw[go + g] = m.gw[g];
-            }
-        }
-        gp_off[NF] = int32_t(NG);
-        std::vector<int32_t> zero_flag(b->n_case, 0);
-        std::vector<double> zero_case(b->n_case, 0.0);
-        auto &o = b->o;
-        HIP_TRY(put(b, o.vol, vol, s)); HIP_TRY(put(b, o.h, h, s)); HIP_TRY(put(b, o.geo, geo, s));
-        HIP_TRY(put(b, o.minv, minv, s));
-        if (b->precision != CGKS_FP64) {
-            std::vector<float> m32(minv.begin(), minv.end());
-            HIP_TRY(put(b, o.minv32, m32, s));
-        }
-        HIP_TRY(put(b, o.slot, slot, s));
-        HIP_TRY(put(b, o.cell_case, cell_case, s));
-        HIP_TRY(put(b, o.fL, fL, s)); HIP_TRY(put(b, o.fR, fR, s)); HIP_TRY(put(b, o.fbc, fbc, s));
-        HIP_TRY(put(b, o.fcase, fcase, s)); HIP_TRY(put(b, o.gp_off, gp_off, s)); HIP_TRY(put(b, o.bslot, bslot, s));
-        HIP_TRY(put(b, o.avec, avec, s)); HIP_TRY(put(b, o.S, S, s)); HIP_TRY(put(b, o.shift, shift, s));
-        HIP_TRY(put(b, o.gavg, gavg, s));
-        HIP_TRY(put(b, o.bface, bface, s));
-        HIP_TRY(put(b, o.gx, gx, s)); HIP_TRY(put(b, o.gn, gn, s)); HIP_TRY(put(b, o.gw, gw, s));
-        HIP_TRY(put(b, o.prm, prm, s)); HIP_TRY(put(b, o.flag, zero_flag, s));
-        std::vector<int32_t> case_b_off(b->b_off.begin(), b->b_off.end());
-        case_b_off.push_back(int32_t(b->NB));
-        HIP_TRY(put(b, o.case_b_off, case_b_off, s));
-        std::vector<double> zero_force(3 * size_t(b->n_case), 0.0);   // alive until the sync below
-        HIP_TRY(put(b, o.force, zero_force, s));
-        HIP_TRY(put(b, o.dt, zero_case, s)); HIP_TRY(put(b, o.res, zero_case, s));
-        HIP_TRY(put(b, o.rb_start, b->rb_start, s)); HIP_TRY(put(b, o.rb_count, b->rb_count, s));
-        HIP_TRY(put(b, o.rb_case, b->rb_case, s)); HIP_TRY(put(b, o.case_rb_off, b->case_rb_off, s));
-        HIP_TRY(put(b, o.cb_start, b->cb_start, s)); HIP_TRY(put(b, o.cb_count, b->cb_count, s));
-        // zero state and work arrays so that a cycle never reads garbage
-        HIP_TRY(hipMemsetAsync(b->base + o.st, 0, o.geo - o.st, s));
-        HIP_TRY(hipMemsetAsync(b->base + o.U, 0, o.prm - o.U, s));
+        // everything starts at zero (no slot active); free entities point to
+        // the never-active slot n_case, free boundary slots to no face
+        HIP_TRY(hipMemsetAsync(b->base, 0, b->bytes, s));
+        HIP_TRY(fill_i32(at<int32_t>(b, b->o.cell_case), b->NC, b->n_case, s));
+        HIP_TRY(fill_i32(at<int32_t>(b, b->o.fcase), b->NF, b->n_case, s));
+        HIP_TRY(fill_i32(at<int32_t>(b, b->o.bface), std::max<int64_t>(b->NB, 1), -1, s));
         HIP_TRY(hipStreamSynchronize(s));
+        for (size_t k = 0; k < b->pending.size(); ++k) {
+            cgks_status st = admit(b, b->pending[k].first, b->pending[k].second, int(k), s);
+            if (st) return st;
+        }
+        b->pending.clear();
+        return rebuild_tables(b, s);
     } catch (const std::bad_alloc &) {
         return CGKS_ENOMEM;
     }
-    return CGKS_OK;
+}
+
+cgks_status cgks_batch_admit(cgks_batch *b, const cgks_mesh *mesh, const cgks_params *params, int32_t *slot,
+                             void *stream) {
+    if (!b || !b->base || !mesh || !params || !slot) return CGKS_EINVAL;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    int c = 0;
+    while (c < b->n_case && b->live[c]) ++c;
+    if (c == b->n_case) return CGKS_ENOMEM;
+    try {
+        cgks_status st = admit(b, mesh, *params, c, s);
+        if (st) return st;
+        *slot = c;
+        return rebuild_tables(b, s);
+    } catch (const std::bad_alloc &) {
+        return CGKS_ENOMEM;
+    }
+}
+
+cgks_status cgks_batch_release(cgks_batch *b, int32_t c, void *stream) {
+    if (!b || !b->base || c < 0 || c >= b->n_case || !b->live[c]) return CGKS_EINVAL;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const HostMesh &m = b->meshes[c]->hm;
+    // the slot stops running first, then its entities are handed back
+    DevParams off{};
+    HIP_TRY(hipMemcpyAsync((void *)(b->dev.prm + c), &off, sizeof(DevParams), hipMemcpyHostToDevice, s));
+    HIP_TRY(fill_i32(at<int32_t>(b, b->o.cell_case) + b->cell_off[c], m.n_cell, b->n_case, s));
+    HIP_TRY(fill_i32(at<int32_t>(b, b->o.fcase) + b->face_off[c], m.n_face, b->n_case, s));
+    HIP_TRY(fill_i32(at<int32_t>(b, b->o.bface) + b->b_off[c], m.n_bface, -1, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    b->ac.give(b->cell_off[c], m.n_cell);
+    b->af.give(b->face_off[c], m.n_face);
+    b->ag.give(b->gp_base[c], m.n_gp);
+    b->ab.give(b->b_off[c], m.n_bface);
+    b->live[c] = 0;
+    b->meshes[c] = nullptr;
+    try {
+        return rebuild_tables(b, s);
+    } catch (const std::bad_alloc &) {
+        return CGKS_ENOMEM;
+    }
 }
 
 cgks_status cgks_batch_destroy(cgks_batch *b) {
@@ -640,7 +897,7 @@ cgks_status cgks_batch_destroy(cgks_batch *b) {
 }
 
 static cgks_status state_xfer(cgks_batch *b, int32_t c, double *W, double *dW, void *stream, bool up) {
-    if (!b || !b->base || c < 0 || c >= b->n_case || (up && !W)) return CGKS_EINVAL;
+    if (!b || !b->base || c < 0 || c >= b->n_case || !b->live[c] || (up && !W)) return CGKS_EINVAL;
     hipStream_t s = static_cast<hipStream_t>(stream);
     const HostMesh &m = b->meshes[c]->hm;
     const int d = b->dim, nv = d + 2, sr = nv + d * nv;
@@ -678,7 +935,7 @@ cgks_status cgks_state_download(cgks_batch *b, int32_t c, double *W, double *dW,
 }
 
 cgks_status cgks_state_device(cgks_batch *b, int32_t c, double **rec, int32_t *rec_len, int64_t *n_cell) {
-    if (!b || !b->base || c < 0 || c >= b->n_case) return CGKS_EINVAL;
+    if (!b || !b->base || c < 0 || c >= b->n_case || !b->live[c]) return CGKS_EINVAL;
     const int nv = b->dim + 2, sr = nv + b->dim * nv;
     if (rec) *rec = b->dev.st + size_t(b->cell_off[c]) * sr;
     if (rec_len) *rec_len = sr;
@@ -705,14 +962,14 @@ cgks_status cgks_residual(cgks_batch *b, int32_t kind, double *out, void *stream
     }
     if (kind == CGKS_RESIDUAL_LOW) {
         if (b->dim == 2) {
-            hipLaunchKernelGGL((k_low_face<2, double>), dim3(nblk(b->NF)), dim3(kBlock), 0, s, b->dev,
+            hipLaunchKernelGGL((k_low_face<2, double>), dim3(nblk(b->hwF)), dim3(kBlock), 0, s, b->dev,
                                (int)LOW_SRC_W);
-            hipLaunchKernelGGL((k_low_cell<2, double>), dim3(nblk(b->NC * Dim<2>::sl)), dim3(kBlock), 0, s, b->dev,
+            hipLaunchKernelGGL((k_low_cell<2, double>), dim3(nblk(b->hwC * Dim<2>::sl)), dim3(kBlock), 0, s, b->dev,
                                (int)LOW_R0_OUT, out);
         } else {
-            hipLaunchKernelGGL((k_low_face<3, double>), dim3(nblk(b->NF)), dim3(kBlock), 0, s, b->dev,
+            hipLaunchKernelGGL((k_low_face<3, double>), dim3(nblk(b->hwF)), dim3(kBlock), 0, s, b->dev,
                                (int)LOW_SRC_W);
-            hipLaunchKernelGGL((k_low_cell<3, double>), dim3(nblk(b->NC * Dim<3>::sl)), dim3(kBlock), 0, s, b->dev,
+            hipLaunchKernelGGL((k_low_cell<3, double>), dim3(nblk(b->hwC * Dim<3>::sl)), dim3(kBlock), 0, s, b->dev,
                                (int)LOW_R0_OUT, out);
         }
         HIP_TRY(hipGetLastError());
@@ -748,13 +1005,15 @@ cgks_status cgks_solve(cgks_batch *b, const cgks_solve_opts *opts, cgks_solve_re
     std::vector<double> res(n), first(n, 0.0), best(n, INFINITY);
     std::vector<int32_t> flag(n);
     std::vector<char> done(n, 0);
+    int remaining = 0;
     for (int c = 0; c < n; ++c) {
         rep[c] = cgks_solve_report{0, 0, 0.0, 0.0, CGKS_ENOTCONV, {0.0, 0.0, 0.0}};
+        if (b->live[c]) ++remaining;
+        else done[c] = 1;   // free slot: nothing to solve
     }
     std::vector<DevParams> prm(n);
     HIP_TRY(hipMemcpyAsync(prm.data(), b->dev.prm, sizeof(DevParams) * n, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
-    int remaining = n;
     // blocks of `every` cycles run as one captured graph (one host round trip
     // per block); a shorter final block runs eagerly
     const bool use_graph = every > 1 && every <= 8;
@@ -814,8 +1073,8 @@ cgks_status cgks_solve(cgks_batch *b, const cgks_solve_opts *opts, cgks_solve_re
     HIP_TRY(hipStreamSynchronize(s));
     for (int c = 0; c < n; ++c)
         for (int a = 0; a < 3; ++a) rep[c].force[a] = force[3 * size_t(c) + a];
-    // leave every case active again for later calls
-    for (int c = 0; c < n; ++c) prm[c].active = 1;
+    // leave every admitted case active again for later calls
+    for (int c = 0; c < n; ++c) prm[c].active = b->live[c] ? 1 : 0;
     HIP_TRY(hipMemcpyAsync((void *)b->dev.prm, prm.data(), sizeof(DevParams) * n, hipMemcpyHostToDevice, s));
     HIP_TRY(hipStreamSynchronize(s));
     return CGKS_OK;

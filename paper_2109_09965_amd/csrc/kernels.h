@@ -44,7 +44,8 @@ struct Dev {
     const int2 *slot;         // [ns][NC]: (x) face code +-(f + 1), 0 = none; (y) neighbour cell or -1
     const int32_t *cell_case;
     // faces
-    const int32_t *fL, *fR, *fbc, *fcase, *gp_off, *bslot;
+    const int32_t *fL, *fR, *fbc, *fcase, *bslot;
+    const int2 *gp_rng;       // [NF] Gauss points [x, y) of each face
     const double *avec, *S, *shift, *gavg;
     const int32_t *bface;     // [NB] face of each boundary slot
     double *gdat;             // [NB][nv + D nv] ghost cell average and gradient
@@ -62,7 +63,7 @@ struct Dev {
     const DevParams *prm;
     double *dt, *res;
     double *force;     // per case [3]: wall force of the latest stage-0 pass
-    const int32_t *case_b_off;   // [n_case + 1] boundary-slot range of each case
+    const int2 *case_b;          // per case: first boundary slot, count
     int32_t *flag;     // per case: bit 0 non-physical state met
     // reductions
     const int32_t *rb_start, *rb_count, *rb_case, *case_rb_off;
@@ -648,6 +649,7 @@ template <int D> __global__ __launch_bounds__(kBlock) void k_ghost(Dev d) {
     const int B = blockIdx.x * kBlock + threadIdx.x;
     if (B >= d.NB_real) return;
     const int f = d.bface[B];
+    if (f < 0 || !d.prm[d.fcase[f]].active) return;
     const int i = d.fL[f];
     const int NC = d.NC;
     const DevParams &P = d.prm[d.fcase[f]];
@@ -686,7 +688,7 @@ template <int D, typename R> __global__ __launch_bounds__(kReconBlock) void k_re
     const int i = i0 + threadIdx.x;
     const int NC = d.NC;
     const int ncell = min(kReconBlock, NC - i0);
-    if (i < NC) {
+    if (i < NC && d.prm[d.cell_case[i]].active) {
     using RC = Rec<D>;
     const double *gi = d.geo + size_t(i) * RC::gr;
     const double *si = d.st + size_t(i) * RC::sr;
@@ -895,7 +897,9 @@ template <int D, typename R> __global__ __launch_bounds__(kBlock) void k_flux(De
     const int fr_raw = t / G, q = t % G;
     const bool face_ok = fr_raw < d.NF;
     const int f = face_ok ? fr_raw : d.NF - 1;
-    const int g0 = d.gp_off[f], g1 = d.gp_off[f + 1];
+    if (!d.prm[d.fcase[f]].active) return;   // the face group leaves together
+    const int2 gr_ = d.gp_rng[f];
+    const int g0 = gr_.x, g1 = gr_.y;
     const bool gp_ok = face_ok && g0 + q < g1;
     const int g = gp_ok ? g0 + q : g0;
     const int cs = d.fcase[f];
@@ -1044,6 +1048,7 @@ template <int D, typename R> __global__ __launch_bounds__(kBlock) void k_cell(De
     const int NC = d.NC;
     const int cs = d.cell_case[i];
     const DevParams &P = d.prm[cs];
+    if (!P.active) return;   // the cell's lane group leaves together
     const bool want_g = mode != MODE_R1;
     double F0s[nv], Fts[nv], G0s[D][nv], Gts[D][nv];
 #pragma unroll
@@ -1225,6 +1230,7 @@ template <int D, typename S> __global__ __launch_bounds__(kBlock) void k_low_cel
     const int i = ok ? ir : d.NC - 1;
     const int NC = d.NC;
     const DevParams &P = d.prm[d.cell_case[i]];
+    if (!P.active) return;   // the cell's lane group leaves together
     double R0[nv], lS = 0.0;
 #pragma unroll
     for (int v = 0; v < nv; ++v) R0[v] = 0.0;
@@ -1393,7 +1399,8 @@ template <int D, typename R> __global__ __launch_bounds__(kBlock) void k_wall_fo
     double f[D];
 #pragma unroll
     for (int a = 0; a < D; ++a) f[a] = 0.0;
-    for (int B = d.case_b_off[c] + threadIdx.x; B < d.case_b_off[c + 1]; B += kBlock) {
+    const int2 cb = d.case_b[c];
+    for (int B = cb.x + threadIdx.x; B < cb.x + cb.y; B += kBlock) {
         const int F = d.bface[B];
         const int bc = d.fbc[F];
         if (bc != 1 && bc != 2) continue;
