@@ -238,12 +238,94 @@ def run_batch(args):
     print(json.dumps(line), flush=True)
 
 
+def _serve_mesh(spec):
+    import paper_2109_09965_amd.inputs as I
+    return I.serve_mesh(spec)
+
+
+def run_serve(args):
+    """Serving trace: seeded Poisson arrivals (20 requests/s) of steady-solve
+    requests, 70 % viscous cylinders and 30 % hybrid spheres, served by the
+    continuous-batching server (pools admitted by HBM footprint) and, for
+    comparison, strictly one case at a time in FP64 in arrival order.
+    value = the server's aggregate cell-updates/s."""
+    import concurrent.futures as cf
+    import multiprocessing as mp
+    import paper_2109_09965_amd.inputs as I
+    trace = I.serve_trace(args.requests, seed=9965, rate=20.0)
+    # the client prepares its meshes before the trace starts (worker
+    # processes forked before anything touches the GPU)
+    with cf.ProcessPoolExecutor(max_workers=min(16, os.cpu_count() or 1), mp_context=mp.get_context("fork")) as ex:
+        meshes = list(ex.map(_serve_mesh, trace, chunksize=1))
+    import paper_2109_09965_amd as cg
+    from paper_2109_09965_amd.serve import Request, Server, summarize
+    with cf.ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
+        lms = list(ex.map(cg.Mesh, meshes))
+    import torch
+    prec = {"fp64": cg.FP64, "mixed32": cg.MIXED32, "mixed32_r64": cg.MIXED32_R64}[args.precision]
+    tol = 1e-10 if prec == cg.FP64 else 1e-8
+
+    def requests():
+        out = []
+        for k, (spec, m, lm) in enumerate(zip(trace, meshes, lms)):
+            w = I.free_stream(spec["dim"], spec["mach"], spec["aoa"])
+            W, dW = I.uniform_state(m, w)
+            out.append(Request(rid=k, arrival=spec["arrival"], mesh=lm,
+                               params=cg.Params(W_inf=w, mu=spec["mach"] / spec["re"], Pr=0.72), W0=W, dW0=dW, tol=tol))
+        return out
+
+    free = torch.cuda.mem_get_info()[0]
+    budget = args.budget_gb * 1e9 if args.budget_gb else 0.9 * free
+    srv = Server(budget, precision=prec, max_cases=64, epoch_cycles=8, max_cycles=4000, stall_cycles=400,
+                 max_resident={2: args.resident_2d, 3: args.resident_3d})
+    reqs = requests()
+    served = srv.run(reqs)
+    del srv
+    torch.cuda.empty_cache()
+    # one case at a time, FP64, arrival order, the same tolerance rule
+    base = None
+    if not args.no_sequential:
+        seq = requests()
+        t0 = time.perf_counter()
+        work = 0
+        for r in seq:
+            while time.perf_counter() - t0 < r.arrival:
+                time.sleep(0.001)
+            b = cg.Batch([r.mesh], [r.params])
+            r.admitted = time.perf_counter() - t0
+            b.upload(0, r.W0, r.dW0)
+            rep, hist = b.solve(max_cycles=4000, tol=r.tol, tol_abs=True, check_every=8, history=True)
+            r.cycles = rep[0]["cycles"]
+            r.W, _ = b.download(0)
+            r.done = time.perf_counter() - t0
+            r.status = "converged" if rep[0]["converged"] else "not_converged"
+            work += r.mesh.n_cell * r.cycles
+            del b
+        base = summarize(seq, work, time.perf_counter() - t0)
+    n2 = sum(1 for t in trace if t["dim"] == 2)
+    line = dict(metric="aggregate cell-updates/s and p50/p99 time-to-steady (serving)", value=served["cell_updates_per_s"],
+                unit="cell-updates/s", n_gpus=1, steps=len(trace), warmup=0, ms_per_step=None,
+                higher_is_better=True, scaling="weak", vs_baseline=None,
+                dtype="f64" if prec == cg.FP64 else "f32+f64", data="synthetic (seeded request trace and meshes)",
+                config=dict(workload=f"serving trace: {len(trace)} requests at 20/s ({n2} viscous cylinders, "
+                                     f"{len(trace) - n2} hybrid cubed spheres), tol Res <= {tol:g}",
+                            precision=args.precision.upper(), budget_gb=budget / 1e9,
+                            resident_cells={"2d": args.resident_2d, "3d": args.resident_3d}),
+                served=served, one_at_a_time_fp64=base)
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="sphere", choices=["sphere", "cylinder", "batch64"])
+    ap.add_argument("--workload", default="sphere", choices=["sphere", "cylinder", "batch64", "serve"])
+    ap.add_argument("--requests", type=int, default=256, help="serving trace length")
+    ap.add_argument("--budget-gb", type=float, default=0.0, help="serving HBM budget (default 0.9 x free)")
+    ap.add_argument("--no-sequential", action="store_true", help="serving: skip the one-at-a-time baseline")
+    ap.add_argument("--resident-2d", type=int, default=200_000, help="serving: cells a 2-D pool runs at once")
+    ap.add_argument("--resident-3d", type=int, default=500_000, help="serving: cells a 3-D pool runs at once")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed32", "mixed32_r64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
@@ -266,6 +348,9 @@ def main():
 
     if args.workload == "batch64":
         run_batch(args)
+        return
+    if args.workload == "serve":
+        run_serve(args)
         return
 
     import torch

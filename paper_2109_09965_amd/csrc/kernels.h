@@ -664,7 +664,7 @@ template <int D> __global__ __launch_bounds__(kBlock) void k_ghost(Dev d) {
     (void)NC;
     const double iS = 1.0 / d.S[f];
 #pragma unroll
-    for (int a = 0; a < D; ++a) n[a] = d.avec[a * d.NF + f] * iS;
+    for (int a = 0; a < D; ++a) n[a] = d.avec[size_t(a) * d.NF + f] * iS;
     ghost_data<D>(d.fbc[f], n, Wi, Gi, P, Wg, Gg);
     double *o = d.gdat + size_t(B) * (nv + D * nv);
 #pragma unroll
@@ -710,7 +710,7 @@ template <int D, typename R> __global__ __launch_bounds__(kReconBlock) void k_re
     for (int q = 0; q < nq; ++q) own[q] = gi[D + sidx<D>(qa<D>(q), qb<D>(q))] * ih * ih;
 #pragma unroll 1
     for (int s = 0; s < T::ns; ++s) {
-        const int2 sl = d.slot[s * NC + i];
+        const int2 sl = d.slot[size_t(s) * NC + i];
         const int code = sl.x;
         if (code == 0) break;
         const int f = (code > 0 ? code : -code) - 1;
@@ -723,7 +723,7 @@ template <int D, typename R> __global__ __launch_bounds__(kReconBlock) void k_re
             double dx[D];
 #pragma unroll
             for (int a = 0; a < D; ++a) {
-                dx[a] = gm[a] + sg * d.shift[a * d.NF + f] - xc[a];
+                dx[a] = gm[a] + sg * d.shift[size_t(a) * d.NF + f] - xc[a];
                 avg[a] = R(dx[a] * ih);
             }
 #pragma unroll
@@ -735,7 +735,7 @@ template <int D, typename R> __global__ __launch_bounds__(kReconBlock) void k_re
         } else {
             const int bs = d.bslot[f];
 #pragma unroll
-            for (int k = 0; k < nk; ++k) avg[k] = R(d.gavg[k * d.NB + bs]);
+            for (int k = 0; k < nk; ++k) avg[k] = R(d.gavg[size_t(k) * d.NB + bs]);
             gd = d.gdat + size_t(bs) * (nv + D * nv);
         }
 #pragma unroll
@@ -777,7 +777,7 @@ template <int D, typename R> __global__ __launch_bounds__(kReconBlock) void k_re
         for (int v = 0; v < nv; ++v) c[v] = R(0.0);
 #pragma unroll
         for (int j = 0; j < nk; ++j) {
-            const R mkj = minv[midx<D>(k, j) * NC + i];
+            const R mkj = minv[size_t(midx<D>(k, j)) * NC + i];
 #pragma unroll
             for (int v = 0; v < nv; ++v) c[v] += mkj * rhs[j][v];
         }
@@ -908,8 +908,8 @@ template <int D, typename R> __global__ __launch_bounds__(kBlock) void k_flux(De
     R x[D], n[D];
 #pragma unroll
     for (int a = 0; a < D; ++a) {
-        x[a] = R(d.gx[a * d.NG + g]);
-        n[a] = R(d.gn[a * d.NG + g]);
+        x[a] = R(d.gx[size_t(a) * d.NG + g]);
+        n[a] = R(d.gn[size_t(a) * d.NG + g]);
     }
     const R wJ = gp_ok ? R(d.gw[g]) : R(0.0);
     Frame<D, R> fr;
@@ -927,7 +927,7 @@ template <int D, typename R> __global__ __launch_bounds__(kBlock) void k_flux(De
             if (cR >= 0) {
                 R xr[D], WRg[nv], GR[D][nv];
 #pragma unroll
-                for (int a = 0; a < D; ++a) xr[a] = x[a] - R(d.shift[a * d.NF + f]);
+                for (int a = 0; a < D; ++a) xr[a] = x[a] - R(d.shift[size_t(a) * d.NF + f]);
                 recon_eval<D, R>(d, cR, xr, WRg, GR);
                 fr.to_local(WRg, WR);
                 fr.grad_to_local(GR, GRl);
@@ -1059,7 +1059,7 @@ template <int D, typename R> __global__ __launch_bounds__(kBlock) void k_cell(De
     }
 #pragma unroll
     for (int s = q; s < T::ns; s += SL) {
-        const int code = d.slot[s * NC + i].x;
+        const int code = d.slot[size_t(s) * NC + i].x;
         if (code != 0) {
             const int f = (code > 0 ? code : -code) - 1;
             const double sg = code > 0 ? 1.0 : -1.0;
@@ -1101,23 +1101,23 @@ template <int D, typename R> __global__ __launch_bounds__(kBlock) void k_cell(De
     for (int v = 0; v < nv; ++v) {
         if (v % SL != q) continue;
         if (mode == MODE_R1) {
-            d.R1[v * NC + i] = -(F0s[v] + 0.5 * dt * Fts[v]);
+            d.R1[size_t(v) * NC + i] = -(F0s[v] + 0.5 * dt * Fts[v]);
             continue;
         }
         const double L = -F0s[v] / V, Lt = -Fts[v] / V;
         double *si = d.st + size_t(i) * Rec<D>::sr;
         if (mode == MODE_STAGE0) {
             const double w = si[v];
-            d.Wn[v * NC + i] = w;
-            d.L0[v * NC + i] = L;
-            d.Lt0[v * NC + i] = Lt;
+            d.Wn[size_t(v) * NC + i] = w;
+            d.L0[size_t(v) * NC + i] = L;
+            d.Lt0[size_t(v) * NC + i] = Lt;
             si[v] = P.scheme == 0 ? w + 0.5 * dt * L + 0.125 * dt * dt * Lt : w + dt * L + 0.5 * dt * dt * Lt;
         } else {
-            si[v] = d.Wn[v * NC + i] + dt * d.L0[v * NC + i] + dt * dt / 6.0 * (d.Lt0[v * NC + i] + 2.0 * Lt);
+            si[v] = d.Wn[size_t(v) * NC + i] + dt * d.L0[size_t(v) * NC + i] + dt * dt / 6.0 * (d.Lt0[size_t(v) * NC + i] + 2.0 * Lt);
         }
 #pragma unroll
         for (int a = 0; a < D; ++a) {
-            const int k = (a * nv + v) * NC + i;
+            const size_t k = size_t(a * nv + v) * NC + i;
             const double G = G0s[a][v] / V, Gt = Gts[a][v] / V;
             if (mode == MODE_STAGE0) {
                 d.G0[k] = G;
@@ -1176,7 +1176,7 @@ template <int D, typename S> __global__ __launch_bounds__(kBlock) void k_low_fac
     const double Sf = d.S[f], iS = 1.0 / Sf;
     double n[D];
 #pragma unroll
-    for (int a = 0; a < D; ++a) n[a] = d.avec[a * d.NF + f] * iS;
+    for (int a = 0; a < D; ++a) n[a] = d.avec[size_t(a) * d.NF + f] * iS;
     Frame<D, double> fr;
     fr.build(n);
     double UL[nv], Ul[nv], Ur[nv];
@@ -1215,7 +1215,7 @@ template <int D, typename S> __global__ __launch_bounds__(kBlock) void k_low_fac
     for (int v = 0; v < nv; ++v) d.lowf[size_t(f) * nv + v] = ok ? Sf * F[v] : 0.0;
     double *w = d.swp + size_t(f) * 4;
 #pragma unroll
-    for (int a = 0; a < D; ++a) w[a] = d.avec[a * d.NF + f];
+    for (int a = 0; a < D; ++a) w[a] = d.avec[size_t(a) * d.NF + f];
     w[D] = Sf * lam;
 }
 
@@ -1236,7 +1236,7 @@ template <int D, typename S> __global__ __launch_bounds__(kBlock) void k_low_cel
     for (int v = 0; v < nv; ++v) R0[v] = 0.0;
 #pragma unroll
     for (int s = q; s < T::ns; s += SL) {
-        const int code = d.slot[s * NC + i].x;
+        const int code = d.slot[size_t(s) * NC + i].x;
         if (code != 0) {
             const int f = (code > 0 ? code : -code) - 1;
             const double sg = code > 0 ? 1.0 : -1.0;
@@ -1255,14 +1255,14 @@ template <int D, typename S> __global__ __launch_bounds__(kBlock) void k_low_cel
     if (mode == LOW_R0_OUT) {
 #pragma unroll
         for (int v = 0; v < nv; ++v)
-            if (v % SL == q) out[v * NC + i] = R0[v];
+            if (v % SL == q) out[size_t(v) * NC + i] = R0[v];
         return;
     }
     if (mode == LOW_FORCE) {
 #pragma unroll
         for (int v = 0; v < nv; ++v)
             if (v % SL == q) {
-                d.Sf[v * NC + i] = d.R1[v * NC + i] - R0[v];
+                d.Sf[size_t(v) * NC + i] = d.R1[size_t(v) * NC + i] - R0[v];
                 Ui[v] = d.st[size_t(i) * Rec<D>::sr + v];
                 dUi[v] = S(0);
             }
@@ -1275,7 +1275,7 @@ template <int D, typename S> __global__ __launch_bounds__(kBlock) void k_low_cel
     for (int v = 0; v < nv; ++v)
         if (v % SL == q) {
             Ui[v] = u[v];
-            d.RHS[v * NC + i] = R0[v] + d.Sf[v * NC + i];
+            d.RHS[size_t(v) * NC + i] = R0[v] + d.Sf[size_t(v) * NC + i];
             dUi[v] = S(0);
         }
     if (q == 0) d.D[i] = d.vol[i] / state_dt<D>(u, d.h[i], P.cfl_low, P) + 0.5 * lS;
@@ -1301,7 +1301,7 @@ __global__ __launch_bounds__(kBlock) void k_sweep(Dev d, const int32_t *blk_star
     for (int v = 0; v < nv; ++v) acc[v] = S(0);
 #pragma unroll
     for (int s = q; s < T::ns; s += SL) {
-        const int2 sl = d.slot[s * NC + i];
+        const int2 sl = d.slot[size_t(s) * NC + i];
         if (sl.x != 0 && sl.y >= 0) {
             const int nb = sl.y;
             const int f = (sl.x > 0 ? sl.x : -sl.x) - 1;
@@ -1347,7 +1347,7 @@ __global__ __launch_bounds__(kBlock) void k_sweep(Dev d, const int32_t *blk_star
     S *dUi = LowRec<D, S>::dU(d, i);
 #pragma unroll
     for (int v = 0; v < nv; ++v)
-        if (v % SL == q) dUi[v] = S((d.RHS[v * NC + i] - double(acc[v])) / Di);
+        if (v % SL == q) dUi[v] = S((d.RHS[size_t(v) * NC + i] - double(acc[v])) / Di);
 }
 
 // W += (U + dU) - W_p0 (W_p0 = W); partial sums of |rho - rho^n| and rho^n.

@@ -618,6 +618,44 @@ def sphere_case_mesh():
     return cubed_sphere_mesh(28, 40, 20, 10, 0.5, 15.0, 1.08, first_spacing=0.05597)
 
 
+def serve_trace(n_requests=256, seed=9965, rate=20.0, frac_2d=0.7, mach=(0.1, 0.4), re_2d=(10.0, 40.0),
+                re_3d=(50.0, 200.0)):
+    """Seeded steady-solve request trace: exponential inter-arrival times at
+    `rate` per second; frac_2d of the requests are viscous cylinders built
+    like the batch cases with n_theta in {32, 64} (n_r = n_theta/2; on the
+    finer batch rings the two-level cycle diverges at the wall for Re <= 40),
+    the rest hybrid cubed-sphere O-grids with n in {14..28} quads per cube edge
+    (about the 24x48 .. 48x96 surface quads of latitude-longitude grids) and
+    L in {16..40} layers (L/2 hex, L/4 prism, the rest tet), stretched to
+    r = 15.  Mach ~ U[mach]; Re ~ U[re_2d] / U[re_3d] on the diameter, kept
+    in the steady regime of each body (cylinder below about 47, sphere below
+    about 210)."""
+    rng = np.random.default_rng(seed)
+    t = np.cumsum(rng.exponential(1.0 / rate, n_requests))
+    out = []
+    for k in range(n_requests):
+        if rng.uniform() < frac_2d:
+            nt = int(rng.choice([32, 64]))
+            spec = dict(dim=2, n_theta=nt, n_r=nt // 2, re=float(rng.uniform(*re_2d)))
+        else:
+            n = int(rng.integers(14, 29))
+            L = int(rng.integers(16, 41))
+            spec = dict(dim=3, n=n, layers=L, re=float(rng.uniform(*re_3d)))
+        spec.update(arrival=float(t[k]), mach=float(rng.uniform(*mach)), aoa=float(rng.uniform(-5.0, 5.0)))
+        out.append(spec)
+    return out
+
+
+def serve_mesh(spec):
+    """Mesh of one trace request: the cylinder with a no-slip isothermal
+    wall, or the cubed-sphere O-grid (radial ratio 1.08^(40/L) to r = 15)."""
+    if spec["dim"] == 2:
+        nr = spec["n_r"]
+        return cylinder_mesh(spec["n_theta"], nr, ratio=1.1 ** (32.0 / nr), wall=BC_NOSLIP_ISOTHERMAL)
+    L = spec["layers"]
+    return cubed_sphere_mesh(spec["n"], L, L // 2, L // 4, 0.5, 15.0, 1.08 ** (40.0 / L))
+
+
 def batch_case_mesh(case):
     """Cylinder O-mesh of one batch case, built like the 64 x 32 cylinder:
     radius 0.5 to 20 with the same total radial stretch (ratio 1.1 per

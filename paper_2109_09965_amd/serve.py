@@ -1,0 +1,240 @@
+"""Continuous-batching steady-solve server over the pool API.
+
+Requests (a prepared mesh, its free stream and gas parameters, a
+tolerance) arrive over time.  The server keeps one pool per dimension, each
+with a fixed capacity carved out of an HBM budget, and each on its own HIP
+stream so the two pools' work overlaps on the device.  In every epoch it
+admits waiting requests in arrival order while their mesh fits into free
+ranges (the pool's HBM footprint), replays a captured graph of
+``epoch_cycles`` cycles of every admitted case, reads the per-case Res
+history, and retires cases that converged (or stalled at their precision's
+floor, or hit the cycle cap): their state is downloaded to the host and
+their ranges are released for the next admissions.  A case gives bitwise the
+same state in the mix as alone after the same number of cycles.
+
+Time-to-steady runs from a request's arrival to its converged state on the
+host; queue wait (arrival to admission) and service (admission to done) are
+reported with it.
+"""
+import dataclasses
+import time
+
+import numpy as np
+
+from . import FP64, Batch, Params
+
+# Faces, Gauss points and boundary faces reserved per cell of capacity:
+# upper bounds over the trace's meshes (cylinder O-grids: 1.5 faces and 3
+# Gauss points per cell, boundary faces 1/n_r per cell; hybrid sphere
+# O-grids: 2 (tets) to 3 (hexes) faces and 6 to 12 Gauss points per cell,
+# boundary faces up to a fifth of the cells on coarse grids).  They cost
+# far less than a cell (see entity_bytes), so the margins are cheap.
+ENTITY_RATIOS = {2: (1.0, 1.6, 3.2, 0.25), 3: (1.0, 3.0, 12.0, 0.25)}
+
+
+@dataclasses.dataclass
+class Request:
+    rid: int
+    arrival: float            # seconds after the start of the trace
+    mesh: object              # paper_2109_09965_amd.Mesh (prepared by the client)
+    params: Params
+    W0: np.ndarray
+    dW0: np.ndarray
+    tol: float
+    # filled in by the server
+    admitted: float = None
+    done: float = None
+    cycles: int = 0
+    res_first: float = None
+    res_last: float = None
+    best: float = np.inf
+    best_at: int = 0
+    status: str = "waiting"
+    W: np.ndarray = None
+    slot: int = None
+
+
+def entity_bytes(dim, precision):
+    """Pool bytes per cell, face, Gauss point and boundary face."""
+    import ctypes as C
+    from . import _PoolDesc, _check, lib
+    L = lib()
+
+    def nbytes(*caps):
+        q = _PoolDesc(dim, precision, 1, *caps, 6, 2, 0, 0)
+        h = C.c_void_p()
+        _check(L.cgks_pool_create(C.byref(q), C.byref(h)), "cgks_pool_create")
+        nb = C.c_size_t()
+        _check(L.cgks_batch_query(h, C.byref(nb)), "cgks_batch_query")
+        L.cgks_batch_destroy(h)
+        return nb.value
+
+    one = 1 << 20
+    base = nbytes(one, one, one, one)
+    out = []
+    for k in range(4):
+        caps = [one] * 4
+        caps[k] = 2 * one
+        out.append((nbytes(*caps) - base) / one)
+    return out
+
+
+def caps_for_budget(dim, precision, budget_bytes):
+    """Entity capacities of a pool that fits budget_bytes, proportioned for
+    meshes of the given dimension."""
+    per = entity_bytes(dim, precision)
+    ratios = ENTITY_RATIOS[dim]
+    cells = int(budget_bytes / sum(p * r for p, r in zip(per, ratios)))
+    return [max(1, int(cells * r)) for r in ratios]
+
+
+class Server:
+    """max_resident[dim]: cells a pool may hold at once beyond its first
+    case.  A few hundred thousand cells already fill the GPU, so letting more
+    in only time-shares it (every case then advances more slowly); small
+    cases still batch up to the cap.  None = bounded by memory alone."""
+
+    def __init__(self, budget_bytes, precision=FP64, max_cases=64, epoch_cycles=8, max_cycles=4000,
+                 stall_cycles=400, share_3d=0.75, max_resident=None):
+        import torch
+        self.precision = precision
+        self.epoch = epoch_cycles
+        self.max_cycles = max_cycles
+        self.stall = stall_cycles
+        self.pools, self.streams = {}, {}
+        for dim, share in ((2, 1.0 - share_3d), (3, share_3d)):
+            caps = caps_for_budget(dim, precision, share * budget_bytes)
+            st = torch.cuda.Stream()
+            self.streams[dim] = st
+            self.pools[dim] = Batch.pool(dim, max_cases, *caps, precision=precision, stream=st)
+        self.max_resident = max_resident or {}
+        self.live = {2: {}, 3: {}}        # slot -> Request
+        self.dirty = {2: True, 3: True}   # membership changed: capture again
+
+    def try_admit(self, req, now):
+        dim = req.mesh.dim
+        cap = self.max_resident.get(dim)
+        resident = sum(r.mesh.n_cell for r in self.live[dim].values())
+        if cap is not None and self.live[dim] and resident + req.mesh.n_cell > cap:
+            return False
+        slot = self.pools[dim].admit(req.mesh, req.params)
+        if slot is None:
+            return False
+        self.pools[dim].upload(slot, req.W0, req.dW0)
+        req.slot, req.admitted, req.status = slot, now, "running"
+        self.live[dim][slot] = req
+        self.dirty[dim] = True
+        return True
+
+    def step(self):
+        """One epoch of every non-empty pool; returns cell-updates done."""
+        import torch
+        work = 0
+        hist = {}
+        for dim, pool in self.pools.items():
+            if not self.live[dim]:
+                continue
+            with torch.cuda.stream(self.streams[dim]):
+                if self.dirty[dim]:
+                    pool.graph_create(self.epoch)
+                    self.dirty[dim] = False
+                h = torch.zeros(self.epoch * pool.n_case, dtype=torch.float64, device="cuda")
+                pool.graph_launch(h)
+                hist[dim] = h
+            work += self.epoch * sum(r.mesh.n_cell for r in self.live[dim].values())
+        for dim, h in hist.items():
+            self.streams[dim].synchronize()
+            hist[dim] = h.cpu().numpy().reshape(self.epoch, -1)
+        return work, hist
+
+    def retire(self, hist, now_fn):
+        done = []
+        for dim, H in hist.items():
+            pool = self.pools[dim]
+            for slot, req in list(self.live[dim].items()):
+                finished = None
+                for j in range(self.epoch):
+                    r = float(H[j, slot])
+                    req.cycles += 1
+                    if req.res_first is None:
+                        req.res_first = r
+                    req.res_last = r
+                    if r < 0.99 * req.best:
+                        req.best, req.best_at = r, req.cycles
+                    if finished is not None:
+                        continue
+                    if not np.isfinite(r):
+                        finished = "nonphysical"
+                    elif r <= req.tol:
+                        finished = "converged"
+                    elif req.cycles - req.best_at >= self.stall:
+                        finished = "stalled"
+                    elif req.cycles >= self.max_cycles:
+                        finished = "max_cycles"
+                # the state after the epoch's last cycle (req.cycles counts
+                # every cycle the case ran)
+                if finished:
+                    req.W, _ = pool.download(slot)
+                    pool.release(slot)
+                    req.status, req.done = finished, now_fn()
+                    del self.live[dim][slot]
+                    self.dirty[dim] = True
+                    done.append(req)
+        return done
+
+    def run(self, requests, log=None):
+        """Serve a trace (requests sorted by arrival); returns a summary."""
+        reqs = sorted(requests, key=lambda r: r.arrival)
+        waiting, nxt, finished = [], 0, []
+        work = 0
+        t0 = time.perf_counter()
+        now = lambda: time.perf_counter() - t0
+        while len(finished) < len(reqs):
+            t = now()
+            while nxt < len(reqs) and reqs[nxt].arrival <= t:
+                waiting.append(reqs[nxt])
+                nxt += 1
+            # arrival order per dimension: a request that does not fit blocks
+            # later ones of its dimension (no starvation of large cases)
+            blocked = set()
+            for req in list(waiting):
+                d = req.mesh.dim
+                if d in blocked:
+                    continue
+                if self.try_admit(req, t):
+                    waiting.remove(req)
+                elif not self.live[d]:
+                    # does not fit even into the empty pool: never will
+                    req.status, req.admitted, req.done = "rejected", t, t
+                    waiting.remove(req)
+                    finished.append(req)
+                else:
+                    blocked.add(d)
+            if not (self.live[2] or self.live[3]):
+                if nxt < len(reqs):
+                    time.sleep(max(0.0, min(0.01, reqs[nxt].arrival - now())))
+                continue
+            w, hist = self.step()
+            work += w
+            done = self.retire(hist, now)
+            finished += done
+            if log:
+                for r in done:
+                    log(r)
+        makespan = now()
+        return summarize(finished, work, makespan)
+
+
+def summarize(finished, work, makespan):
+    tts = np.array([r.done - r.arrival for r in finished])
+    wait = np.array([r.admitted - r.arrival for r in finished])
+    svc = np.array([r.done - r.admitted for r in finished])
+    status = {}
+    for r in finished:
+        status[r.status] = status.get(r.status, 0) + 1
+    return dict(requests=len(finished), makespan_s=makespan, cell_updates=int(work),
+                cell_updates_per_s=work / makespan if makespan > 0 else 0.0,
+                p50_time_to_steady_s=float(np.percentile(tts, 50)), p99_time_to_steady_s=float(np.percentile(tts, 99)),
+                p50_queue_wait_s=float(np.percentile(wait, 50)), p99_queue_wait_s=float(np.percentile(wait, 99)),
+                p50_service_s=float(np.percentile(svc, 50)), p99_service_s=float(np.percentile(svc, 99)),
+                status=status)

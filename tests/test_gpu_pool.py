@@ -130,3 +130,25 @@ def test_pool_case_matches_oracle():
     Wg, dWg = pool.download(s)
     assert np.abs(Wg - Wo).max() <= 1e-11 * np.abs(Wo).max()
     assert np.abs(dWg - dWo).max() <= 1e-10 * np.abs(dWo).max()
+
+
+def test_large_capacity_pool_equals_alone():
+    """A 3-D pool whose cell capacity times the 45 packed operator entries
+    per cell passes 2^31 (structure-of-arrays offsets need 64 bits): a case
+    in it equals the same case alone, bitwise."""
+    m = I.cubed_sphere_mesh(4, 8, 3, 2)
+    w = I.free_stream(3, 0.3, 3.0)
+    p = cg.Params(W_inf=w, mu=0.003, Pr=0.72)
+    W, dW = I.smooth_state(m, w, seed=12, amp=0.02)
+    lm = cg.Mesh(m)
+    nc, nf, ng, nb = counts(lm)
+    cap_cells = 50_000_000
+    pool = cg.Batch.pool(3, 2, cap_cells, 2 * nf, 2 * ng, 2 * nb)
+    s = pool.admit(lm, p)
+    pool.upload(s, W, dW)
+    for _ in range(3):
+        pool.cycle()
+    Wp, dWp = pool.download(s)
+    Wa, dWa = alone(m, p, W, dW, 3)
+    assert np.array_equal(Wp, Wa) and np.array_equal(dWp, dWa)
+    del pool

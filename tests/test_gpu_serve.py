@@ -1,0 +1,62 @@
+"""The continuous-batching server on a small trace: requests of both
+dimensions arrive while others run, admission is bounded by a small HBM
+budget, every request converges, and each result is bitwise the state of the
+same case stepped alone for the same number of cycles."""
+import numpy as np
+import pytest
+
+import paper_2109_09965_amd as cg
+import paper_2109_09965_amd.inputs as I
+from paper_2109_09965_amd.serve import Request, Server
+
+pytestmark = pytest.mark.gpu
+
+
+def small_trace(n=10, seed=3):
+    rng = np.random.default_rng(seed)
+    t = np.cumsum(rng.exponential(0.02, n))
+    specs = []
+    for k in range(n):
+        mach = float(rng.uniform(0.15, 0.35))
+        if k % 3 == 2:
+            nn = int(rng.integers(3, 5))
+            m = I.cubed_sphere_mesh(nn, 6, 3, 1, r_far=6.0)
+            re = float(rng.uniform(50, 150))
+        else:
+            nt = int(rng.choice([16, 24, 32]))
+            m = I.cylinder_mesh(nt, nt // 2, r_far=10.0, wall=I.BC_NOSLIP_ISOTHERMAL)
+            re = float(rng.uniform(10, 40))
+        specs.append((float(t[k]), m, mach, re))
+    return specs
+
+
+def request(k, arrival, m, mach, re, tol):
+    d = m["dim"]
+    w = I.free_stream(d, mach, 2.0)
+    W, dW = I.uniform_state(m, w)
+    return Request(rid=k, arrival=arrival, mesh=cg.Mesh(m), params=cg.Params(W_inf=w, mu=mach / re, Pr=0.72),
+                   W0=W, dW0=dW, tol=tol)
+
+
+def test_server_converges_every_request_and_results_equal_alone():
+    specs = small_trace()
+    reqs = [request(k, *s, tol=1e-5) for k, s in enumerate(specs)]
+    # budget for about two meshes per dimension at a time: admission binds
+    big = max(r.mesh.n_cell for r in reqs)
+    from paper_2109_09965_amd.serve import ENTITY_RATIOS, entity_bytes
+    budget = 2.2 * big * sum(p * q for p, q in zip(entity_bytes(3, cg.FP64), ENTITY_RATIOS[3])) / 0.5
+    srv = Server(budget, precision=cg.FP64, max_cases=3, epoch_cycles=4, max_cycles=2000, stall_cycles=400,
+                 share_3d=0.5)
+    out = srv.run(reqs)
+    print(out, flush=True)
+    assert out["requests"] == len(reqs)
+    assert out["status"] == {"converged": len(reqs)}
+    # at most three cases per pool at once, ten requests: some waited
+    assert max(r.admitted - r.arrival for r in reqs) > 0.0
+    for r in reqs[:4] + reqs[-2:]:
+        b = cg.Batch([r.mesh], [r.params])
+        b.upload(0, r.W0, r.dW0)
+        for _ in range(r.cycles):
+            b.cycle()
+        Wa, _ = b.download(0)
+        assert np.array_equal(Wa, r.W), (r.rid, np.abs(Wa - r.W).max())
