@@ -199,6 +199,8 @@ def run_batch(args):
         for k, i in enumerate(idx):
             W, dW = I.uniform_state(meshes[i], winf[i])
             b.upload(k, W, dW)
+        if not args.no_autotune:
+            b.autotune()
         for _ in range(args.warmup):
             b.cycle()
         b.graph_create(G)
@@ -279,7 +281,12 @@ def run_serve(args):
     srv = Server(budget, precision=prec, max_cases=64, epoch_cycles=8, max_cycles=4000, stall_cycles=400,
                  max_resident={2: args.resident_2d, 3: args.resident_3d})
     reqs = requests()
-    served = srv.run(reqs)
+
+    def progress(r):
+        print(f"served {r.rid}: dim {r.mesh.dim} cells {r.mesh.n_cell} {r.status} after {r.cycles} cycles, "
+              f"time-to-steady {r.done - r.arrival:.2f} s", file=sys.stderr, flush=True)
+
+    served = srv.run(reqs, log=progress)
     del srv
     torch.cuda.empty_cache()
     # one case at a time, FP64, arrival order, the same tolerance rule
@@ -301,6 +308,8 @@ def run_serve(args):
             r.status = "converged" if rep[0]["converged"] else "not_converged"
             work += r.mesh.n_cell * r.cycles
             del b
+            print(f"one at a time {r.rid}: {r.status} after {r.cycles} cycles, time-to-steady "
+                  f"{r.done - r.arrival:.2f} s", file=sys.stderr, flush=True)
         base = summarize(seq, work, time.perf_counter() - t0)
     n2 = sum(1 for t in trace if t["dim"] == 2)
     line = dict(metric="aggregate cell-updates/s and p50/p99 time-to-steady (serving)", value=served["cell_updates_per_s"],
@@ -328,6 +337,7 @@ def main():
     ap.add_argument("--resident-3d", type=int, default=500_000, help="serving: cells a 3-D pool runs at once")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed32", "mixed32_r64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default launch shapes")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
                     help="only run 5 device-to-device copies of MIB MiB (counter calibration)")
     args = ap.parse_args()
@@ -363,6 +373,7 @@ def main():
     b = cg.Batch([lm], [cg.Params(**kw)], precision=prec)
     W, dW = I.uniform_state(mesh, kw["W_inf"])
     b.upload(0, W, dW)
+    picks = None if args.no_autotune else b.autotune()     # launch shapes, before the timed region
     res = torch.zeros(1, dtype=torch.float64, device="cuda")
     for _ in range(args.warmup):
         b.cycle(res)
@@ -430,7 +441,8 @@ def main():
                dtype="f64" if prec == cg.FP64 else "f32+f64",
                data="synthetic (seeded mesh generator, uniform free-stream start)",
                config=dict(workload=desc, cells=NC, faces=NF, gauss_points=NG, colours=lm.n_colour,
-                           precision=args.precision.upper(), time_scheme="S2O4", implicit_steps=6, sweeps=2),
+                           precision=args.precision.upper(), time_scheme="S2O4", implicit_steps=6, sweeps=2,
+                           launch_shapes=picks),
                roofline=rf, kernels=breakdown, res_last=float(res.cpu()[0]), res_after_graph=res_graph,
                eager_ms_per_step=1e3 * t_eager / args.steps, graph_ms_per_step=1e3 * t_graph / args.steps)
     if not args.no_cpu_baseline:

@@ -288,6 +288,20 @@ cgks_status cgks_solve(cgks_batch *batch, const cgks_solve_opts *opts, cgks_solv
    an unbound batch. */
 cgks_status cgks_wall_force(cgks_batch *batch, double *force, void *stream);
 
+/* Pick the launch shapes of this batch by measurement (the batching
+   autotuner): threads per block of the face Gauss-point flux, the cell
+   gather and update, the low-level face flux and the low-level cell setup
+   (64, 128 or 256 each), and cells per block of the relaxation sweep (16,
+   32 or 64), each the fastest of three timed launches on the batch's own
+   data and current state.  Results never depend on these shapes (no
+   reduction crosses a face's or cell's lane group), so a tuned batch steps
+   bitwise like an untuned one.  The timed launches write only work arrays
+   (reconstruction records, face sums, R1, the low-level arrays), never W or
+   grad W.  choice (host, may be NULL) receives the five picks in that
+   order.  Synchronous on stream; drops a captured graph.  CGKS_EINVAL for
+   an unbound batch or a pool without cases. */
+cgks_status cgks_batch_autotune(cgks_batch *batch, int32_t *choice, void *stream);
+
 /* Kernel timing.  enable = 1 brackets the kernel launches of the batch with
    pairs of HIP events recorded on the launch stream: one pair per launch,
    except that the back-to-back colour passes of one implicit step share

@@ -15,7 +15,8 @@ from dataclasses import dataclass
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libcgks.so")
+# CGKS_LIB_PATH selects another build of the same library (for A/B timing)
+LIB_PATH = os.environ.get("CGKS_LIB_PATH") or os.path.join(_HERE, "libcgks.so")
 _lib = None
 
 OK, EINVAL, ENOMEM, EDEVICE, EMESH, ENONPHYS, EDIVERGED, ENOTCONV, EUNSUPPORTED = range(9)
@@ -28,7 +29,8 @@ EXPORTS = ["cgks_status_string", "cgks_mesh_create", "cgks_mesh_query", "cgks_me
            "cgks_state_upload", "cgks_state_download", "cgks_state_device", "cgks_highorder_stage",
            "cgks_residual", "cgks_lowlevel_smooth", "cgks_cycle", "cgks_solve", "cgks_timing_enable",
            "cgks_timing_read", "cgks_graph_create", "cgks_graph_launch", "cgks_graph_destroy", "cgks_wall_force",
-           "cgks_pool_create", "cgks_batch_admit", "cgks_batch_release", "cgks_batch_capacity", "cgks_batch_slot_info"]
+           "cgks_pool_create", "cgks_batch_admit", "cgks_batch_release", "cgks_batch_capacity", "cgks_batch_slot_info",
+           "cgks_batch_autotune"]
 KERNEL_KINDS = ["dt", "recon", "flux", "cell", "low_face", "low_cell", "sweep", "prolong"]
 
 
@@ -122,6 +124,7 @@ def lib():
         L.cgks_batch_release.argtypes = [P, i32, P]
         L.cgks_batch_capacity.argtypes = [P, C.POINTER(C.c_int32), C.POINTER(C.c_int64)]
         L.cgks_batch_slot_info.argtypes = [P, i32, C.POINTER(C.c_int32), C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
+        L.cgks_batch_autotune.argtypes = [P, P, P]
         for name in EXPORTS:
             getattr(L, name).restype = C.c_int if name != "cgks_status_string" else C.c_char_p
         _lib = L
@@ -347,6 +350,13 @@ class Batch:
         """Replay the captured cycles; res_history: device float64 [n_cycles * n_case] or None."""
         ptr = C.c_void_p(res_history.data_ptr()) if res_history is not None else None
         _check(lib().cgks_graph_launch(self.h, ptr, _stream(self.stream)), "cgks_graph_launch")
+
+    def autotune(self):
+        """Measure and keep the fastest launch shapes; returns them."""
+        ch = np.zeros(5, np.int32)
+        _check(lib().cgks_batch_autotune(self.h, _ptr(ch), _stream(self.stream)), "cgks_batch_autotune")
+        return dict(flux_block=int(ch[0]), cell_block=int(ch[1]), low_face_block=int(ch[2]),
+                    low_cell_block=int(ch[3]), sweep_chunk=int(ch[4]))
 
     def wall_force(self):
         """[n_case, 3] force of the gas on the walls at the start of the latest cycle."""

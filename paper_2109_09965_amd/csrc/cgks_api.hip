@@ -19,7 +19,7 @@ namespace {
 constexpr int kRedChunk = 1024;   // cells per reduction block (never straddles cases)
 constexpr int kMaxGraphCycles = 64;   // cycles one captured graph may hold
 constexpr int kMaxColours = 16;   // colours a mesh may use
-constexpr int kSweepChunk = kBlock / 4;   // cells per sweep block (Dim<D>::sl lanes per cell)
+constexpr int kSweepChunkMin = 16;   // smallest tunable sweep chunk (cells per block)
 
 // First-fit allocator of index ranges in [0, cap): the arena positions of
 // one entity type (cells, faces, Gauss points, boundary slots).
@@ -99,6 +99,9 @@ struct cgks_batch {
     std::vector<std::pair<const cgks_mesh *, cgks_params>> pending;   // admitted at bind
     int64_t max_rb = 0, max_cb = 0;
     int max_colour = 0;
+    // launch shapes (threads per block; cells per sweep block), set by
+    // cgks_batch_autotune; results never depend on them
+    int blk_flux = kBlock, blk_cell = kBlock, blk_face = kBlock, blk_lcell = kBlock, sweep_chunk = kBlock / 4;
     // sweep blocks per colour
     std::vector<int32_t> cb_start, cb_count;
     std::vector<int64_t> colour_blk_off;   // [max_colour + 1]
@@ -208,7 +211,7 @@ void layout(cgks_batch *b) {
     o.flag = a.take<int32_t>(K1);
     // table capacities: every case adds at most one partial chunk per block kind
     b->max_rb = int64_t(NC) / kRedChunk + b->n_case + 1;
-    b->max_cb = int64_t(NC) / kSweepChunk + int64_t(b->n_case) * kMaxColours + 1;
+    b->max_cb = int64_t(NC) / kSweepChunkMin + int64_t(b->n_case) * kMaxColours + 1;
     o.rb_start = a.take<int32_t>(b->max_rb);
     o.rb_count = a.take<int32_t>(b->max_rb);
     o.rb_case = a.take<int32_t>(b->max_rb);
@@ -283,7 +286,7 @@ template <class T> hipError_t put(cgks_batch *b, size_t off, const std::vector<T
     return hipMemcpyAsync(b->base + off, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s);
 }
 
-inline unsigned nblk(int64_t n) { return unsigned((n + kBlock - 1) / kBlock); }
+inline unsigned nblk(int64_t n, int blk = kBlock) { return unsigned((n + blk - 1) / blk); }
 
 // Launch `launch()` (which issues `launches` kernels back to back)
 // bracketed by two events when timing is enabled.
@@ -320,13 +323,14 @@ template <int D, typename R> void launch_ho_kernels(cgks_batch *b, int mode, hip
                            dim3(kReconBlock), 0, s, d);
     });
     timed(b, CGKS_K_FLUX, s, [&] {
-        hipLaunchKernelGGL((k_flux<D, R>), dim3(nblk(b->hwF * Dim<D>::lanes)), dim3(kBlock), 0, s, d,
+        hipLaunchKernelGGL((k_flux<D, R>), dim3(nblk(b->hwF * Dim<D>::lanes, b->blk_flux)), dim3(b->blk_flux), 0, s, d,
                            (int)(mode != MODE_R1));
     });
     if (mode == MODE_STAGE0 && b->hwB > 0)
         hipLaunchKernelGGL((k_wall_force<D, R>), dim3(b->n_case), dim3(kBlock), 0, s, d);
     timed(b, CGKS_K_CELL, s, [&] {
-        hipLaunchKernelGGL((k_cell<D, R>), dim3(nblk(b->hwC * Dim<D>::sl)), dim3(kBlock), 0, s, d, mode);
+        hipLaunchKernelGGL((k_cell<D, R>), dim3(nblk(b->hwC * Dim<D>::sl, b->blk_cell)), dim3(b->blk_cell), 0, s, d,
+                           mode);
     });
 }
 
@@ -365,21 +369,22 @@ template <int D, typename S> cgks_status launch_lowlevel_s(cgks_batch *b, const 
     if (R1 != d.R1)
         HIP_TRY(hipMemcpyAsync(d.R1, R1, sizeof(double) * (D + 2) * b->NC, hipMemcpyDeviceToDevice, s));
     timed(b, CGKS_K_LOWFACE, s, [&] {
-        hipLaunchKernelGGL((k_low_face<D, S>), dim3(nblk(b->hwF)), dim3(kBlock), 0, s, d, (int)LOW_SRC_W);
+        hipLaunchKernelGGL((k_low_face<D, S>), dim3(nblk(b->hwF, b->blk_face)), dim3(b->blk_face), 0, s, d,
+                           (int)LOW_SRC_W);
     });
     timed(b, CGKS_K_LOWCELL, s, [&] {
-        hipLaunchKernelGGL((k_low_cell<D, S>), dim3(nblk(b->hwC * Dim<D>::sl)), dim3(kBlock), 0, s, d,
-                           (int)LOW_FORCE, (double *)nullptr);
+        hipLaunchKernelGGL((k_low_cell<D, S>), dim3(nblk(b->hwC * Dim<D>::sl, b->blk_lcell)), dim3(b->blk_lcell), 0,
+                           s, d, (int)LOW_FORCE, (double *)nullptr);
     });
     const std::vector<int> order = sweep_order(b->max_colour, b->n_sweeps);
     for (int k = 0; k < b->n_implicit; ++k) {
         timed(b, CGKS_K_LOWFACE, s, [&] {
-            hipLaunchKernelGGL((k_low_face<D, S>), dim3(nblk(b->hwF)), dim3(kBlock), 0, s, d,
+            hipLaunchKernelGGL((k_low_face<D, S>), dim3(nblk(b->hwF, b->blk_face)), dim3(b->blk_face), 0, s, d,
                                (int)(k ? LOW_SRC_U_DU : LOW_SRC_U));
         });
         timed(b, CGKS_K_LOWCELL, s, [&] {
-            hipLaunchKernelGGL((k_low_cell<D, S>), dim3(nblk(b->hwC * Dim<D>::sl)), dim3(kBlock), 0, s, d,
-                               (int)(k ? LOW_STEP : LOW_STEP_FIRST), (double *)nullptr);
+            hipLaunchKernelGGL((k_low_cell<D, S>), dim3(nblk(b->hwC * Dim<D>::sl, b->blk_lcell)), dim3(b->blk_lcell),
+                               0, s, d, (int)(k ? LOW_STEP : LOW_STEP_FIRST), (double *)nullptr);
         });
         // the colour passes of one step run back to back: one timing span
         int n_pass = 0;
@@ -390,7 +395,7 @@ template <int D, typename S> cgks_status launch_lowlevel_s(cgks_batch *b, const 
                 for (int c : order) {
                     const int64_t b0 = b->colour_blk_off[c], nb = b->colour_blk_off[c + 1] - b0;
                     if (nb == 0) continue;
-                    hipLaunchKernelGGL((k_sweep<D, S>), dim3(unsigned(nb)), dim3(kBlock), 0, s, d,
+                    hipLaunchKernelGGL((k_sweep<D, S>), dim3(unsigned(nb)), dim3(4 * b->sweep_chunk), 0, s, d,
                                        (const int32_t *)(b->d_cb_start + b0),
                                        (const int32_t *)(b->d_cb_count + b0));
                 }
@@ -700,9 +705,9 @@ static cgks_status rebuild_tables(cgks_batch *b, hipStream_t s) {
             int64_t start = b->cell_off[c];
             for (int k = 0; k < col; ++k) start += m.colour_count[k];
             const int64_t n = m.colour_count[col];
-            for (int64_t q = 0; q < n; q += kSweepChunk) {
+            for (int64_t q = 0; q < n; q += b->sweep_chunk) {
                 b->cb_start.push_back(int32_t(start + q));
-                b->cb_count.push_back(int32_t(std::min<int64_t>(kSweepChunk, n - q)));
+                b->cb_count.push_back(int32_t(std::min<int64_t>(b->sweep_chunk, n - q)));
             }
         }
         b->colour_blk_off[col + 1] = b->cb_start.size();
@@ -1085,6 +1090,116 @@ cgks_status cgks_wall_force(cgks_batch *b, double *force, void *stream) {
     hipStream_t s = static_cast<hipStream_t>(stream);
     HIP_TRY(hipMemcpyAsync(force, b->dev.force, sizeof(double) * 3 * b->n_case, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
+    return CGKS_OK;
+}
+
+}  // extern "C"
+
+// Times the candidate launch shapes of the face, cell and sweep kernels on
+// the batch's own data and keeps the fastest.  Only launches that leave the
+// state W, grad W untouched are timed: the reconstruction from the current
+// state, the flux with gradient sums, the residual pass of k_cell, the
+// low-level face flux and R0, and whole sequences of colour passes on the
+// low-level work arrays (set up from the current state first).
+template <int D, typename R, typename S> static cgks_status autotune_t(cgks_batch *b, hipStream_t s) {
+    const Dev &d = b->dev;
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    auto time_of = [&](auto &&launch) -> float {
+        launch();                     // warm-up
+        (void)hipEventRecord(e0, s);
+        for (int r = 0; r < 5; ++r) launch();
+        (void)hipEventRecord(e1, s);
+        (void)hipEventSynchronize(e1);
+        float ms = 0.0f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        return ms;
+    };
+    // cand[0] is the default shape; another one is taken only when it is
+    // at least 3 % faster (timing noise must not move the choice)
+    auto pick = [&](const int *cand, int n, auto &&launch_with) {
+        int best = cand[0];
+        const float t0 = time_of([&] { launch_with(cand[0]); });
+        float bt = t0;
+        for (int k = 1; k < n; ++k) {
+            const float t = time_of([&] { launch_with(cand[k]); });
+            if (t < bt && t < 0.97f * t0) bt = t, best = cand[k];
+        }
+        return best;
+    };
+    static const int blocks[3] = {256, 128, 64};
+    if (b->hwB > 0) hipLaunchKernelGGL(k_ghost<D>, dim3(nblk(b->hwB)), dim3(kBlock), 0, s, d);
+    hipLaunchKernelGGL((k_recon<D, R>), dim3(unsigned((b->hwC + kReconBlock - 1) / kReconBlock)), dim3(kReconBlock),
+                       0, s, d);
+    b->blk_flux = pick(blocks, 3, [&](int blk) {
+        hipLaunchKernelGGL((k_flux<D, R>), dim3(nblk(b->hwF * Dim<D>::lanes, blk)), dim3(blk), 0, s, d, 1);
+    });
+    b->blk_cell = pick(blocks, 3, [&](int blk) {
+        hipLaunchKernelGGL((k_cell<D, R>), dim3(nblk(b->hwC * Dim<D>::sl, blk)), dim3(blk), 0, s, d, (int)MODE_R1);
+    });
+    b->blk_face = pick(blocks, 3, [&](int blk) {
+        hipLaunchKernelGGL((k_low_face<D, S>), dim3(nblk(b->hwF, blk)), dim3(blk), 0, s, d, (int)LOW_SRC_W);
+    });
+    b->blk_lcell = pick(blocks, 3, [&](int blk) {
+        hipLaunchKernelGGL((k_low_cell<D, S>), dim3(nblk(b->hwC * Dim<D>::sl, blk)), dim3(blk), 0, s, d,
+                           (int)LOW_R0_OUT, d.Sf);
+    });
+    // low-level work arrays from the current state, then the sweep chunk
+    hipLaunchKernelGGL((k_low_cell<D, S>), dim3(nblk(b->hwC * Dim<D>::sl, b->blk_lcell)), dim3(b->blk_lcell), 0, s, d,
+                       (int)LOW_FORCE, (double *)nullptr);
+    hipLaunchKernelGGL((k_low_face<D, S>), dim3(nblk(b->hwF, b->blk_face)), dim3(b->blk_face), 0, s, d,
+                       (int)LOW_SRC_U);
+    hipLaunchKernelGGL((k_low_cell<D, S>), dim3(nblk(b->hwC * Dim<D>::sl, b->blk_lcell)), dim3(b->blk_lcell), 0, s, d,
+                       (int)LOW_STEP_FIRST, (double *)nullptr);
+    static const int chunks[3] = {64, 32, 16};
+    cgks_status st = CGKS_OK;
+    const std::vector<int> order = sweep_order(b->max_colour, b->n_sweeps);
+    const int chunk = pick(chunks, 3, [&](int ch) {
+        if (b->sweep_chunk != ch) {
+            b->sweep_chunk = ch;
+            if (rebuild_tables(b, s) != CGKS_OK) st = CGKS_EDEVICE;
+        }
+        for (int c : order) {   // the colour passes of one implicit step
+            const int64_t b0 = b->colour_blk_off[c], nb = b->colour_blk_off[c + 1] - b0;
+            if (nb == 0) continue;
+            hipLaunchKernelGGL((k_sweep<D, S>), dim3(unsigned(nb)), dim3(4 * ch), 0, s, d,
+                               (const int32_t *)(b->d_cb_start + b0), (const int32_t *)(b->d_cb_count + b0));
+        }
+    });
+    b->sweep_chunk = chunk;
+    if (st == CGKS_OK) st = rebuild_tables(b, s);
+    // nothing the timing did counts as a health event
+    std::vector<int32_t> zero(b->n_case + 1, 0);
+    HIP_TRY(hipMemcpyAsync(b->dev.flag, zero.data(), sizeof(int32_t) * zero.size(), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    HIP_TRY(hipGetLastError());
+    return st;
+}
+
+extern "C" {
+
+cgks_status cgks_batch_autotune(cgks_batch *b, int32_t *choice, void *stream) {
+    if (!b || !b->base) return CGKS_EINVAL;
+    bool any = false;
+    for (int c = 0; c < b->n_case; ++c) any |= b->live[c] != 0;
+    if (!any) return CGKS_EINVAL;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    b->drop_graph();
+    cgks_status st;
+    const bool f32 = b->precision != CGKS_FP64;
+    if (b->dim == 2) st = f32 ? autotune_t<2, float, float>(b, s) : autotune_t<2, double, double>(b, s);
+    else st = f32 ? autotune_t<3, float, float>(b, s) : autotune_t<3, double, double>(b, s);
+    if (st) return st;
+    if (choice) {
+        choice[0] = b->blk_flux;
+        choice[1] = b->blk_cell;
+        choice[2] = b->blk_face;
+        choice[3] = b->blk_lcell;
+        choice[4] = b->sweep_chunk;
+    }
     return CGKS_OK;
 }
 

@@ -51,7 +51,7 @@ struct Dev {
     double *gdat;             // [NB][nv + D nv] ghost cell average and gradient
     // gauss points
     const double *gx, *gn, *gw;
-    double *fsum;      // per face [NF][2 nv + 2 D nv]: sum_g wJ (F0, Ft, W_c n, W_t n)
+    double *fsum;      // per face [NF][2 nv + 2 D nv]: sum_g wJ of (F0, Ft), then per axis a (W_c n_a, W_t n_a)
     float *fsum32;     // the same in FP32 (mixed-precision batches)
     // low level: U and dU in one cell-major record per cell (LowRec: U in
     // FP64, then dU in the sweep precision; a neighbour gather reads one
@@ -219,8 +219,9 @@ template <int D, typename R> struct Moments {
 
 // micro-slope coefficients a = a0 + a_u u + a_v v (+ a_w w) + a_E (u^2 + .. + xi^2)/2
 // solving <a psi> = b in closed form (b per unit density)
-template <int D, typename R> __device__ __forceinline__ void micro_slope(const R *b, const R *U, R lam, R N,
-                                                             R *a) {
+// (il = 1/(2 lam), iN = 1/N passed in: no division here)
+template <int D, typename R> __device__ __forceinline__ void micro_slope(const R *b, const R *U, R lam, R il, R N,
+                                                             R iN, R *a) {
     constexpr int nv = D + 2;
     R U2 = 0, Ub = 0;
 #pragma unroll
@@ -228,7 +229,7 @@ template <int D, typename R> __device__ __forceinline__ void micro_slope(const R
         U2 += U[k] * U[k];
         Ub += U[k] * b[1 + k];
     }
-    const R aE = R(4.0) * lam * lam / N * (R(2.0) * b[nv - 1] - R(2.0) * Ub + (U2 - N / (R(2.0) * lam)) * b[0]);
+    const R aE = R(4.0) * lam * lam * iN * (R(2.0) * b[nv - 1] - R(2.0) * Ub + (U2 - N * il) * b[0]);
     R aU = 0;
 #pragma unroll
     for (int k = 0; k < D; ++k) {
@@ -236,7 +237,7 @@ template <int D, typename R> __device__ __forceinline__ void micro_slope(const R
         aU += a[1 + k] * U[k];
     }
     a[nv - 1] = aE;
-    a[0] = b[0] - aU - R(0.5) * aE * (U2 + N / (R(2.0) * lam));
+    a[0] = b[0] - aU - R(0.5) * aE * (U2 + N * il);
 }
 
 // E[a u^i v^j w^l xi^(2e)]
@@ -270,10 +271,11 @@ template <int D, typename R> struct Prim {
     R rho, U[D], p, lam;
     __device__ __forceinline__ void from(const R *W, R gamma) {
         rho = W[0];
+        const R ir = R(1.0) / rho;
         R ke = 0;
 #pragma unroll
         for (int a = 0; a < D; ++a) {
-            U[a] = W[1 + a] / rho;
+            U[a] = W[1 + a] * ir;
             ke += U[a] * U[a];
         }
         p = (gamma - R(1.0)) * (W[D + 1] - R(0.5) * rho * ke);
@@ -313,6 +315,7 @@ template <int D, typename R> __device__ bool gks_flux(const R *Wc, const R Gc[D]
     m.full(Uf, q.lam, R(P.K));
     const R tau = R(P.mu) / q.p;
     const R ir = R(1.0) / q.rho;
+    const R il = R(0.5) / q.lam, iN = R(1.0) / N;
     // one direction at a time: micro-slope a^(j), its share of the
     // compatibility sum b = -<(sum_j a^(j) u_j) psi> and of the collision term
     // tt = <u psi (sum_j a^(j) u_j)>
@@ -324,7 +327,7 @@ template <int D, typename R> __device__ bool gks_flux(const R *Wc, const R Gc[D]
         R g[nv], a[nv], t0[nv];
 #pragma unroll
         for (int v = 0; v < nv; ++v) g[v] = Gc[j][v] * ir;
-        micro_slope<D, R>(g, q.U, q.lam, N, a);
+        micro_slope<D, R>(g, q.U, q.lam, il, N, iN, a);
         Epsi<D, R>(m, a, j == 0 ? 1 : 0, j == 1 ? 1 : 0, j == 2 ? 1 : 0, t0);
 #pragma unroll
         for (int v = 0; v < nv; ++v) b[v] -= t0[v];
@@ -333,7 +336,7 @@ template <int D, typename R> __device__ bool gks_flux(const R *Wc, const R Gc[D]
         for (int v = 0; v < nv; ++v) tt[v] += t0[v];
     }
     R A[nv], eA[nv];
-    micro_slope<D, R>(b, q.U, q.lam, N, A);
+    micro_slope<D, R>(b, q.U, q.lam, il, N, iN, A);
     // E[u psi A] gives the time derivative of the flux
     Epsi<D, R>(m, A, 1, 0, 0, eA);
     // E[u psi]
@@ -359,10 +362,11 @@ template <int D, typename R> __device__ bool gks_flux(const R *Wc, const R Gc[D]
 
 // half-range moments <u^k>_{u >< 0}, k = 0..3
 template <typename R> __device__ __forceinline__ void half_moments(R U, R lam, R sgn, R *m) {
+    const R hl = R(0.5) / lam;   // 1/(2 lam)
     m[0] = R(0.5) * erfc(-sgn * sqrt(lam) * U);
     m[1] = U * m[0] + sgn * R(0.5) * exp(-lam * U * U) * rsqrt(R(M_PI) * lam);
-    m[2] = U * m[1] + R(0.5) / lam * m[0];
-    m[3] = U * m[2] + R(1.0) / lam * m[1];
+    m[2] = U * m[1] + hl * m[0];
+    m[3] = U * m[2] + R(2.0) * hl * m[1];
 }
 
 // accumulate rho <psi>_{half} (state) and rho <u psi>_{half} (flux) of one side
@@ -513,6 +517,10 @@ template <int D> __device__ __forceinline__ double state_dt(const double *U, dou
     return cfl * h / (sqrt(ke) + c + 2.0 * P.mu / rho / h);
 }
 
+// The face, cell and sweep kernels take their block size from the launch
+// (a multiple of 4 lanes, at most kBlock) so that it can be tuned per batch;
+// a thread's work never depends on it.
+//
 // Workgroups are handed to the 8 XCDs round-robin (block b runs on XCD
 // b mod 8), each XCD with its own L2.  xcd_block renumbers the launch so
 // that every XCD works through one contiguous range of logical blocks:
@@ -879,9 +887,28 @@ __device__ inline void flag_nonphysical(int32_t *flag, bool bad, int c) {
 }
 
 // sum of v over the G consecutive lanes of a face group (every lane gets it)
+// DPP quad permutation (lane l of each group of four takes lane l ^ m,
+// m = 1 or 2) of a 32- or 64-bit value, without the LDS crossbar
+template <int M> __device__ __forceinline__ int dpp_xor_i32(int x) {
+    constexpr int ctrl = M == 1 ? 0xB1 : 0x4E;   // quad_perm [1,0,3,2] / [2,3,0,1]
+    return __builtin_amdgcn_mov_dpp(x, ctrl, 0xF, 0xF, false);
+}
+template <int M> __device__ __forceinline__ double dpp_xor(double v) {
+    const long long u = __double_as_longlong(v);
+    const int lo = dpp_xor_i32<M>(int(u & 0xffffffffll)), hi = dpp_xor_i32<M>(int(u >> 32));
+    return __longlong_as_double((long long)(unsigned(lo)) | ((long long)hi << 32));
+}
+template <int M> __device__ __forceinline__ float dpp_xor(float v) {
+    return __int_as_float(dpp_xor_i32<M>(__float_as_int(v)));
+}
+
+// sum of v over the G (2 or 4) consecutive lanes of a group, every lane
+// of the group gets it: butterfly of quad permutations (all lanes of a
+// group active)
 template <int G, typename T> __device__ __forceinline__ T group_sum(T v) {
-#pragma unroll
-    for (int m = 1; m < G; m <<= 1) v += __shfl_xor(v, m, G);
+    static_assert(G == 2 || G == 4, "lane groups of 2 or 4");
+    v += dpp_xor<1>(v);
+    if constexpr (G == 4) v += dpp_xor<2>(v);
     return v;
 }
 
@@ -893,7 +920,7 @@ template <int G, typename T> __device__ __forceinline__ T group_sum(T v) {
 template <int D, typename R> __global__ __launch_bounds__(kBlock) void k_flux(Dev d, int want_grad) {
     using T = Dim<D>;
     constexpr int nv = T::nv, G = T::lanes, FS = T::fs;
-    const int t = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+    const int t = xcd_block(blockIdx.x, gridDim.x) * int(blockDim.x) + threadIdx.x;
     const int fr_raw = t / G, q = t % G;
     const bool face_ok = fr_raw < d.NF;
     const int f = face_ok ? fr_raw : d.NF - 1;
@@ -988,7 +1015,7 @@ template <int D, typename R> __global__ __launch_bounds__(kBlock) void k_flux(De
 #pragma unroll
             for (int a = 0; a < D; ++a) {
                 const R sum = group_sum<G, R>(w * n[a]);
-                if (writer) dst[2 * nv + a * nv + v] = sum;
+                if (writer) dst[2 * nv + a * 2 * nv + v] = sum;
             }
         }
     }
@@ -1025,7 +1052,7 @@ template <int D, typename R> __global__ __launch_bounds__(kBlock) void k_flux(De
 #pragma unroll
             for (int a = 0; a < D; ++a) {
                 const R sum = group_sum<G, R>(w * n[a]);
-                if (writer) dst[2 * nv + D * nv + a * nv + v] = sum;
+                if (writer) dst[2 * nv + a * 2 * nv + nv + v] = sum;
             }
         }
     }
@@ -1040,8 +1067,8 @@ enum { MODE_STAGE0 = 0, MODE_STAGE1 = 1, MODE_R1 = 2 };
 // are reduced across the group and lane q then owns variables q, q + sl.
 template <int D, typename R> __global__ __launch_bounds__(kBlock) void k_cell(Dev d, int mode) {
     using T = Dim<D>;
-    constexpr int nv = T::nv, SL = T::sl;
-    const int t = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+    constexpr int nv = T::nv, SL = T::sl, GW = 2 * nv;
+    const int t = xcd_block(blockIdx.x, gridDim.x) * int(blockDim.x) + threadIdx.x;
     const int ir = t / SL, q = t % SL;
     const bool ok = ir < d.NC;
     const int i = ok ? ir : d.NC - 1;
@@ -1050,81 +1077,61 @@ template <int D, typename R> __global__ __launch_bounds__(kBlock) void k_cell(De
     const DevParams &P = d.prm[cs];
     if (!P.active) return;   // the cell's lane group leaves together
     const bool want_g = mode != MODE_R1;
-    double F0s[nv], Fts[nv], G0s[D][nv], Gts[D][nv];
+    // lane 0 sums the flux group (F0, Ft) of the cell's face records, lane
+    // 1 + a the Gauss-Green group of axis a (W_c n_a, W_t n_a): each lane
+    // reads its own contiguous 2 nv values of every face and needs no other
+    // lane's sums
+    const bool mine = q == 0 || (want_g && q <= D);
+    double acc[GW];
 #pragma unroll
-    for (int v = 0; v < nv; ++v) {
-        F0s[v] = Fts[v] = 0.0;
-#pragma unroll
-        for (int a = 0; a < D; ++a) G0s[a][v] = Gts[a][v] = 0.0;
-    }
-#pragma unroll
-    for (int s = q; s < T::ns; s += SL) {
-        const int code = d.slot[size_t(s) * NC + i].x;
-        if (code != 0) {
+    for (int k = 0; k < GW; ++k) acc[k] = 0.0;
+    if (mine) {
+#pragma unroll 1
+        for (int s = 0; s < T::ns; ++s) {
+            const int code = d.slot[size_t(s) * NC + i].x;
+            if (code == 0) break;
             const int f = (code > 0 ? code : -code) - 1;
             const double sg = code > 0 ? 1.0 : -1.0;
-            const R *src = HoArrays<R>::fsum(d) + size_t(f) * T::fs;
+            const R *src = HoArrays<R>::fsum(d) + size_t(f) * T::fs + q * GW;
 #pragma unroll
-            for (int v = 0; v < nv; ++v) {
-                F0s[v] += sg * double(src[v]);
-                Fts[v] += sg * double(src[nv + v]);
-            }
-            if (want_g) {
-#pragma unroll
-                for (int a = 0; a < D; ++a)
-#pragma unroll
-                    for (int v = 0; v < nv; ++v) {
-                        G0s[a][v] += sg * double(src[2 * nv + a * nv + v]);
-                        Gts[a][v] += sg * double(src[2 * nv + D * nv + a * nv + v]);
-                    }
-            }
+            for (int k = 0; k < GW; ++k) acc[k] += sg * double(src[k]);
         }
     }
-#pragma unroll
-    for (int v = 0; v < nv; ++v) {
-        F0s[v] = group_sum<SL, double>(F0s[v]);
-        Fts[v] = group_sum<SL, double>(Fts[v]);
-    }
-    if (want_g) {
-#pragma unroll
-        for (int a = 0; a < D; ++a)
-#pragma unroll
-            for (int v = 0; v < nv; ++v) {
-                G0s[a][v] = group_sum<SL, double>(G0s[a][v]);
-                Gts[a][v] = group_sum<SL, double>(Gts[a][v]);
-            }
-    }
-    if (!ok || !P.active) return;
+    if (!ok || !mine) return;
     const double dt = d.dt[cs];
     const double V = d.vol[i];
+    double *si = d.st + size_t(i) * Rec<D>::sr;
+    if (q == 0) {
+#pragma unroll
+        for (int v = 0; v < nv; ++v) {
+            if (mode == MODE_R1) {
+                d.R1[size_t(v) * NC + i] = -(acc[v] + 0.5 * dt * acc[nv + v]);
+                continue;
+            }
+            const double L = -acc[v] / V, Lt = -acc[nv + v] / V;
+            if (mode == MODE_STAGE0) {
+                const double w = si[v];
+                d.Wn[size_t(v) * NC + i] = w;
+                d.L0[size_t(v) * NC + i] = L;
+                d.Lt0[size_t(v) * NC + i] = Lt;
+                si[v] = P.scheme == 0 ? w + 0.5 * dt * L + 0.125 * dt * dt * Lt : w + dt * L + 0.5 * dt * dt * Lt;
+            } else {
+                si[v] = d.Wn[size_t(v) * NC + i] + dt * d.L0[size_t(v) * NC + i] +
+                        dt * dt / 6.0 * (d.Lt0[size_t(v) * NC + i] + 2.0 * Lt);
+            }
+        }
+        return;
+    }
+    const int a = q - 1;
 #pragma unroll
     for (int v = 0; v < nv; ++v) {
-        if (v % SL != q) continue;
-        if (mode == MODE_R1) {
-            d.R1[size_t(v) * NC + i] = -(F0s[v] + 0.5 * dt * Fts[v]);
-            continue;
-        }
-        const double L = -F0s[v] / V, Lt = -Fts[v] / V;
-        double *si = d.st + size_t(i) * Rec<D>::sr;
+        const size_t k = size_t(a * nv + v) * NC + i;
+        const double G = acc[v] / V, Gt = acc[nv + v] / V;
         if (mode == MODE_STAGE0) {
-            const double w = si[v];
-            d.Wn[size_t(v) * NC + i] = w;
-            d.L0[size_t(v) * NC + i] = L;
-            d.Lt0[size_t(v) * NC + i] = Lt;
-            si[v] = P.scheme == 0 ? w + 0.5 * dt * L + 0.125 * dt * dt * Lt : w + dt * L + 0.5 * dt * dt * Lt;
+            d.G0[k] = G;
+            si[nv + a * nv + v] = P.scheme == 0 ? G + 0.5 * dt * Gt : G + dt * Gt;
         } else {
-            si[v] = d.Wn[size_t(v) * NC + i] + dt * d.L0[size_t(v) * NC + i] + dt * dt / 6.0 * (d.Lt0[size_t(v) * NC + i] + 2.0 * Lt);
-        }
-#pragma unroll
-        for (int a = 0; a < D; ++a) {
-            const size_t k = size_t(a * nv + v) * NC + i;
-            const double G = G0s[a][v] / V, Gt = Gts[a][v] / V;
-            if (mode == MODE_STAGE0) {
-                d.G0[k] = G;
-                si[nv + a * nv + v] = P.scheme == 0 ? G + 0.5 * dt * Gt : G + dt * Gt;
-            } else {
-                si[nv + a * nv + v] = d.G0[k] + dt * Gt;
-            }
+            si[nv + a * nv + v] = d.G0[k] + dt * Gt;
         }
     }
 }
@@ -1167,7 +1174,7 @@ template <int D, typename S> __device__ __forceinline__ void low_state(const Dev
 // lowf[f] = S_f F_kfvs(U_L, U_R; n_f); swp[f] = (S_f n_f, S_f lam_f).
 template <int D, typename S> __global__ __launch_bounds__(kBlock) void k_low_face(Dev d, int src) {
     constexpr int nv = D + 2;
-    const int f = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+    const int f = xcd_block(blockIdx.x, gridDim.x) * int(blockDim.x) + threadIdx.x;
     if (f >= d.NF) return;
     const int cs = d.fcase[f];
     const DevParams &P = d.prm[cs];
@@ -1224,7 +1231,7 @@ enum { LOW_FORCE = 0, LOW_STEP_FIRST = 1, LOW_STEP = 2, LOW_R0_OUT = 3 };
 template <int D, typename S> __global__ __launch_bounds__(kBlock) void k_low_cell(Dev d, int mode, double *out) {
     using T = Dim<D>;
     constexpr int nv = T::nv, SL = T::sl;
-    const int t = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
+    const int t = xcd_block(blockIdx.x, gridDim.x) * int(blockDim.x) + threadIdx.x;
     const int ir = t / SL, q = t % SL;
     const bool ok = ir < d.NC;
     const int i = ok ? ir : d.NC - 1;

@@ -135,3 +135,27 @@ def test_solve_freezes_converged_cases():
         batch.solve(max_cycles=1, tol=0.0, check_every=1)   # every case active again
         W2, _ = batch.download(first_done)
         assert not np.array_equal(W1, W2)
+
+
+@pytest.mark.parametrize("kinds,precision", [(["cyl", "cyl_small", "cyl"], cg.FP64), (["sphere", "sphere_b"], cg.FP64),
+                                             (["sphere", "sphere_b"], cg.MIXED32)])
+def test_autotuned_batch_steps_bitwise_like_untuned(kinds, precision):
+    """Tuning picks launch shapes only: the tuned batch's states equal the
+    untuned batch's bitwise, and the picks are among the candidates."""
+    cases = [case(k, i) for i, k in enumerate(kinds)]
+    tuned = cg.Batch([cg.Mesh(c[0]) for c in cases], [cg.Params(**c[1]) for c in cases], precision=precision)
+    plain = cg.Batch([cg.Mesh(c[0]) for c in cases], [cg.Params(**c[1]) for c in cases], precision=precision)
+    for i, c in enumerate(cases):
+        tuned.upload(i, c[2], c[3])
+        plain.upload(i, c[2], c[3])
+    picks = tuned.autotune()
+    print(picks, flush=True)
+    assert picks["sweep_chunk"] in (16, 32, 64)
+    assert all(picks[k] in (64, 128, 256) for k in ("flux_block", "cell_block", "low_face_block", "low_cell_block"))
+    for _ in range(3):
+        tuned.cycle()
+        plain.cycle()
+    for i in range(len(cases)):
+        Wt, dWt = tuned.download(i)
+        Wp, dWp = plain.download(i)
+        assert np.array_equal(Wt, Wp) and np.array_equal(dWt, dWp), i
