@@ -279,11 +279,12 @@ def run_serve(args):
     free = torch.cuda.mem_get_info()[0]
     budget = args.budget_gb * 1e9 if args.budget_gb else 0.9 * free
     srv = Server(budget, precision=prec, max_cases=64, epoch_cycles=8, max_cycles=4000, stall_cycles=400,
-                 max_resident={2: args.resident_2d, 3: args.resident_3d})
+                 max_resident={2: args.resident_2d, 3: args.resident_3d}, finish_fp64=not args.no_fp64_finish)
     reqs = requests()
 
     def progress(r):
-        print(f"served {r.rid}: dim {r.mesh.dim} cells {r.mesh.n_cell} {r.status} after {r.cycles} cycles, "
+        print(f"served {r.rid}: dim {r.mesh.dim} cells {r.mesh.n_cell} {r.status} after {r.cycles} cycles "
+              f"({r.cycles_fp64} in FP64), "
               f"time-to-steady {r.done - r.arrival:.2f} s", file=sys.stderr, flush=True)
 
     served = srv.run(reqs, log=progress)
@@ -333,6 +334,8 @@ def main():
     ap.add_argument("--requests", type=int, default=256, help="serving trace length")
     ap.add_argument("--budget-gb", type=float, default=0.0, help="serving HBM budget (default 0.9 x free)")
     ap.add_argument("--no-sequential", action="store_true", help="serving: skip the one-at-a-time baseline")
+    ap.add_argument("--no-fp64-finish", action="store_true",
+                    help="serving, mixed precisions: do not finish cases at the FP32 floor in FP64")
     ap.add_argument("--resident-2d", type=int, default=200_000, help="serving: cells a 2-D pool runs at once")
     ap.add_argument("--resident-3d", type=int, default=500_000, help="serving: cells a 3-D pool runs at once")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed32", "mixed32_r64"])

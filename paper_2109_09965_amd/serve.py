@@ -44,14 +44,17 @@ class Request:
     # filled in by the server
     admitted: float = None
     done: float = None
-    cycles: int = 0
+    cycles: int = 0           # all cycles the case ran
+    cycles_fp64: int = 0      # of them, cycles in an FP64 finishing pool
     res_first: float = None
     res_last: float = None
     best: float = np.inf
     best_at: int = 0
     status: str = "waiting"
     W: np.ndarray = None
+    dW: np.ndarray = None
     slot: int = None
+    key: tuple = None         # (pool kind, dim) the case runs in
 
 
 def entity_bytes(dim, precision):
@@ -92,38 +95,59 @@ class Server:
     """max_resident[dim]: cells a pool may hold at once beyond its first
     case.  A few hundred thousand cells already fill the GPU, so letting more
     in only time-shares it (every case then advances more slowly); small
-    cases still batch up to the cap.  None = bounded by memory alone."""
+    cases still batch up to the cap.  None = bounded by memory alone.
+
+    finish_fp64 (mixed precisions): a case whose Res stops improving (by 1 %
+    over promote_after cycles) before reaching its tolerance has met the FP32
+    floor; it moves, state and gradients, into an FP64 pool of its dimension
+    and finishes there (admitted ahead of new arrivals)."""
 
     def __init__(self, budget_bytes, precision=FP64, max_cases=64, epoch_cycles=8, max_cycles=4000,
-                 stall_cycles=400, share_3d=0.75, max_resident=None):
+                 stall_cycles=400, share_3d=0.75, max_resident=None, finish_fp64=False, fp64_share=0.3,
+                 promote_after=100):
         import torch
         self.precision = precision
         self.epoch = epoch_cycles
         self.max_cycles = max_cycles
         self.stall = stall_cycles
+        self.promote_after = promote_after
+        self.finish = finish_fp64 and precision != FP64
+        kinds = [("run", precision, 1.0 - fp64_share if self.finish else 1.0)]
+        if self.finish:
+            kinds.append(("fp64", FP64, fp64_share))
         self.pools, self.streams = {}, {}
-        for dim, share in ((2, 1.0 - share_3d), (3, share_3d)):
-            caps = caps_for_budget(dim, precision, share * budget_bytes)
-            st = torch.cuda.Stream()
-            self.streams[dim] = st
-            self.pools[dim] = Batch.pool(dim, max_cases, *caps, precision=precision, stream=st)
+        for kind, prec, share in kinds:
+            for dim, dshare in ((2, 1.0 - share_3d), (3, share_3d)):
+                key = (kind, dim)
+                caps = caps_for_budget(dim, prec, share * dshare * budget_bytes)
+                st = torch.cuda.Stream()
+                self.streams[key] = st
+                self.pools[key] = Batch.pool(dim, max_cases, *caps, precision=prec, stream=st)
         self.max_resident = max_resident or {}
-        self.live = {2: {}, 3: {}}        # slot -> Request
-        self.dirty = {2: True, 3: True}   # membership changed: capture again
+        self.live = {k: {} for k in self.pools}       # slot -> Request
+        self.dirty = {k: True for k in self.pools}    # membership changed: capture again
+        self.to_finish = []                           # promoted cases waiting for an FP64 slot
 
-    def try_admit(self, req, now):
-        dim = req.mesh.dim
+    def _admit(self, key, req, W, dW):
+        dim = key[1]
         cap = self.max_resident.get(dim)
-        resident = sum(r.mesh.n_cell for r in self.live[dim].values())
-        if cap is not None and self.live[dim] and resident + req.mesh.n_cell > cap:
+        resident = sum(r.mesh.n_cell for r in self.live[key].values())
+        if cap is not None and self.live[key] and resident + req.mesh.n_cell > cap:
             return False
-        slot = self.pools[dim].admit(req.mesh, req.params)
+        pool = self.pools[key]
+        slot = pool.admit(req.mesh, req.params)
         if slot is None:
             return False
-        self.pools[dim].upload(slot, req.W0, req.dW0)
-        req.slot, req.admitted, req.status = slot, now, "running"
-        self.live[dim][slot] = req
-        self.dirty[dim] = True
+        pool.upload(slot, W, dW)
+        req.slot, req.key = slot, key
+        self.live[key][slot] = req
+        self.dirty[key] = True
+        return True
+
+    def try_admit(self, req, now):
+        if not self._admit(("run", req.mesh.dim), req, req.W0, req.dW0):
+            return False
+        req.admitted, req.status = now, "running"
         return True
 
     def step(self):
@@ -131,31 +155,34 @@ class Server:
         import torch
         work = 0
         hist = {}
-        for dim, pool in self.pools.items():
-            if not self.live[dim]:
+        for key, pool in self.pools.items():
+            if not self.live[key]:
                 continue
-            with torch.cuda.stream(self.streams[dim]):
-                if self.dirty[dim]:
+            with torch.cuda.stream(self.streams[key]):
+                if self.dirty[key]:
                     pool.graph_create(self.epoch)
-                    self.dirty[dim] = False
+                    self.dirty[key] = False
                 h = torch.zeros(self.epoch * pool.n_case, dtype=torch.float64, device="cuda")
                 pool.graph_launch(h)
-                hist[dim] = h
-            work += self.epoch * sum(r.mesh.n_cell for r in self.live[dim].values())
-        for dim, h in hist.items():
-            self.streams[dim].synchronize()
-            hist[dim] = h.cpu().numpy().reshape(self.epoch, -1)
+                hist[key] = h
+            work += self.epoch * sum(r.mesh.n_cell for r in self.live[key].values())
+        for key, h in hist.items():
+            self.streams[key].synchronize()
+            hist[key] = h.cpu().numpy().reshape(self.epoch, -1)
         return work, hist
 
     def retire(self, hist, now_fn):
         done = []
-        for dim, H in hist.items():
-            pool = self.pools[dim]
-            for slot, req in list(self.live[dim].items()):
+        for key, H in hist.items():
+            pool = self.pools[key]
+            promote_ok = self.finish and key[0] == "run"
+            for slot, req in list(self.live[key].items()):
                 finished = None
                 for j in range(self.epoch):
                     r = float(H[j, slot])
                     req.cycles += 1
+                    if key[0] == "fp64":
+                        req.cycles_fp64 += 1
                     if req.res_first is None:
                         req.res_first = r
                     req.res_last = r
@@ -167,6 +194,8 @@ class Server:
                         finished = "nonphysical"
                     elif r <= req.tol:
                         finished = "converged"
+                    elif promote_ok and req.cycles - req.best_at >= self.promote_after:
+                        finished = "promote"
                     elif req.cycles - req.best_at >= self.stall:
                         finished = "stalled"
                     elif req.cycles >= self.max_cycles:
@@ -174,11 +203,15 @@ class Server:
                 # the state after the epoch's last cycle (req.cycles counts
                 # every cycle the case ran)
                 if finished:
-                    req.W, _ = pool.download(slot)
+                    req.W, req.dW = pool.download(slot)
                     pool.release(slot)
+                    del self.live[key][slot]
+                    self.dirty[key] = True
+                    if finished == "promote":
+                        req.status, req.best, req.best_at = "finishing", np.inf, req.cycles
+                        self.to_finish.append(req)
+                        continue
                     req.status, req.done = finished, now_fn()
-                    del self.live[dim][slot]
-                    self.dirty[dim] = True
                     done.append(req)
         return done
 
@@ -194,6 +227,16 @@ class Server:
             while nxt < len(reqs) and reqs[nxt].arrival <= t:
                 waiting.append(reqs[nxt])
                 nxt += 1
+            # promoted cases first (they hold no memory while they wait)
+            for req in list(self.to_finish):
+                key = ("fp64", req.mesh.dim)
+                if self._admit(key, req, req.W, req.dW):
+                    self.to_finish.remove(req)
+                elif not self.live[key]:
+                    # no room even in the empty FP64 pool: keep the FP32 result
+                    req.status, req.done = "stalled", now()
+                    self.to_finish.remove(req)
+                    finished.append(req)
             # arrival order per dimension: a request that does not fit blocks
             # later ones of its dimension (no starvation of large cases)
             blocked = set()
@@ -203,15 +246,15 @@ class Server:
                     continue
                 if self.try_admit(req, t):
                     waiting.remove(req)
-                elif not self.live[d]:
+                elif not self.live[("run", d)]:
                     # does not fit even into the empty pool: never will
                     req.status, req.admitted, req.done = "rejected", t, t
                     waiting.remove(req)
                     finished.append(req)
                 else:
                     blocked.add(d)
-            if not (self.live[2] or self.live[3]):
-                if nxt < len(reqs):
+            if not any(self.live.values()):
+                if nxt < len(reqs) and not self.to_finish:
                     time.sleep(max(0.0, min(0.01, reqs[nxt].arrival - now())))
                 continue
             w, hist = self.step()
@@ -233,6 +276,7 @@ def summarize(finished, work, makespan):
     for r in finished:
         status[r.status] = status.get(r.status, 0) + 1
     return dict(requests=len(finished), makespan_s=makespan, cell_updates=int(work),
+                fp64_finishing_cycles=int(sum(r.cycles_fp64 for r in finished)),
                 cell_updates_per_s=work / makespan if makespan > 0 else 0.0,
                 p50_time_to_steady_s=float(np.percentile(tts, 50)), p99_time_to_steady_s=float(np.percentile(tts, 99)),
                 p50_queue_wait_s=float(np.percentile(wait, 50)), p99_queue_wait_s=float(np.percentile(wait, 99)),
