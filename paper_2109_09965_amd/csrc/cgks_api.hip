@@ -116,7 +116,7 @@ struct cgks_batch {
         size_t fL, fR, fbc, fcase, gp_rng, bslot, avec, S, shift, gavg, bface, gdat;
         size_t gx, gn, gw, fsum, fsum32, ev32, minv32;
         size_t U, Sf, RHS, D, R1, lowf, swp;
-        size_t prm, dt, res, force, case_b, flag, rb_start, rb_count, rb_case, case_rb_off, part0, part1,
+        size_t prm, dt, res, force, wallf, case_b, flag, rb_start, rb_count, rb_case, case_rb_off, part0, part1,
             cb_start, cb_count;
         size_t res_hist;
     } o{};
@@ -207,6 +207,7 @@ void layout(cgks_batch *b) {
     o.dt = a.take<double>(K1);
     o.res = a.take<double>(K1);
     o.force = a.take<double>(3 * K1);
+    o.wallf = a.take<double>(3 * NB);
     o.case_b = a.take<int2>(K1);
     o.flag = a.take<int32_t>(K1);
     // table capacities: every case adds at most one partial chunk per block kind
@@ -272,7 +273,7 @@ void fill_dev(cgks_batch *b) {
     d.lowf = at<double>(b, o.lowf); d.swp = at<double>(b, o.swp);
     d.prm = at<DevParams>(b, o.prm); d.dt = at<double>(b, o.dt); d.res = at<double>(b, o.res);
     d.flag = at<int32_t>(b, o.flag);
-    d.force = at<double>(b, o.force); d.case_b = at<int2>(b, o.case_b);
+    d.force = at<double>(b, o.force); d.case_b = at<int2>(b, o.case_b); d.wallf = at<double>(b, o.wallf);
     d.rb_start = at<int32_t>(b, o.rb_start); d.rb_count = at<int32_t>(b, o.rb_count);
     d.rb_case = at<int32_t>(b, o.rb_case); d.case_rb_off = at<int32_t>(b, o.case_rb_off);
     d.part0 = at<double>(b, o.part0); d.part1 = at<double>(b, o.part1);
@@ -324,10 +325,8 @@ template <int D, typename R> void launch_ho_kernels(cgks_batch *b, int mode, hip
     });
     timed(b, CGKS_K_FLUX, s, [&] {
         hipLaunchKernelGGL((k_flux<D, R>), dim3(nblk(b->hwF * Dim<D>::lanes, b->blk_flux)), dim3(b->blk_flux), 0, s, d,
-                           (int)(mode != MODE_R1));
+                           (int)(mode == MODE_R1 ? 0 : mode == MODE_STAGE0 ? 2 : 1));
     });
-    if (mode == MODE_STAGE0 && b->hwB > 0)
-        hipLaunchKernelGGL((k_wall_force<D, R>), dim3(b->n_case), dim3(kBlock), 0, s, d);
     timed(b, CGKS_K_CELL, s, [&] {
         hipLaunchKernelGGL((k_cell<D, R>), dim3(nblk(b->hwC * Dim<D>::sl, b->blk_cell)), dim3(b->blk_cell), 0, s, d,
                            mode);
@@ -1072,22 +1071,29 @@ cgks_status cgks_solve(cgks_batch *b, const cgks_solve_opts *opts, cgks_solve_re
         }
         k += todo;
     }
-    // wall force of each case's last active stage-0 pass
-    std::vector<double> force(3 * size_t(n));
-    HIP_TRY(hipMemcpyAsync(force.data(), b->dev.force, sizeof(double) * 3 * n, hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
-    for (int c = 0; c < n; ++c)
-        for (int a = 0; a < 3; ++a) rep[c].force[a] = force[3 * size_t(c) + a];
     // leave every admitted case active again for later calls
     for (int c = 0; c < n; ++c) prm[c].active = b->live[c] ? 1 : 0;
     HIP_TRY(hipMemcpyAsync((void *)b->dev.prm, prm.data(), sizeof(DevParams) * n, hipMemcpyHostToDevice, s));
-    HIP_TRY(hipStreamSynchronize(s));
+    // wall force of each case's last stage-0 pass (a frozen case kept its
+    // wall sums from its last active cycle)
+    std::vector<double> force(3 * size_t(n));
+    {
+        cgks_status fst = cgks_wall_force(b, force.data(), stream);
+        if (fst) return fst;
+    }
+    for (int c = 0; c < n; ++c)
+        for (int a = 0; a < 3; ++a) rep[c].force[a] = force[3 * size_t(c) + a];
     return CGKS_OK;
 }
 
 cgks_status cgks_wall_force(cgks_batch *b, double *force, void *stream) {
     if (!b || !b->base || !force) return CGKS_EINVAL;
     hipStream_t s = static_cast<hipStream_t>(stream);
+    if (b->hwB > 0) {
+        if (b->dim == 2) hipLaunchKernelGGL(k_wall_force<2>, dim3(b->n_case), dim3(kBlock), 0, s, b->dev);
+        else hipLaunchKernelGGL(k_wall_force<3>, dim3(b->n_case), dim3(kBlock), 0, s, b->dev);
+        HIP_TRY(hipGetLastError());
+    }
     HIP_TRY(hipMemcpyAsync(force, b->dev.force, sizeof(double) * 3 * b->n_case, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     return CGKS_OK;

@@ -62,7 +62,8 @@ struct Dev {
     // per case
     const DevParams *prm;
     double *dt, *res;
-    double *force;     // per case [3]: wall force of the latest stage-0 pass
+    double *force;     // per case [3]: wall force (reduced from wallf on request)
+    double *wallf;     // per boundary slot [3]: sum_g wJ F0 momentum of the latest stage-0 pass (wall faces)
     const int2 *case_b;          // per case: first boundary slot, count
     int32_t *flag;     // per case: bit 0 non-physical state met
     // reductions
@@ -917,6 +918,9 @@ template <int G, typename T> __device__ __forceinline__ T group_sum(T v) {
 // with weight 0, so every lane runs the same code.  The face sums
 //   sum_g wJ (F0, Ft, W_c n, W_t n)   (global frame)
 // are reduced across the group and written face-major by its first lane.
+// want_grad: 0 = flux sums only (the residual pass), 1 = with the
+// Gauss-Green sums (stage passes), 2 = also keep the wall faces' momentum
+// sums in wallf (stage 0)
 template <int D, typename R> __global__ __launch_bounds__(kBlock) void k_flux(Dev d, int want_grad) {
     using T = Dim<D>;
     constexpr int nv = T::nv, G = T::lanes, FS = T::fs;
@@ -1033,10 +1037,12 @@ template <int D, typename R> __global__ __launch_bounds__(kBlock) void k_flux(De
         for (int v = 0; v < nv; ++v) Wt[v] = R(0.0);
     }
     fr.to_global(F0, o);
+    const bool wall_out = want_grad == 2 && writer && cR < 0 && (bc == 1 || bc == 2);
 #pragma unroll
     for (int v = 0; v < nv; ++v) {
         const R sum = group_sum<G, R>(wJ * o[v]);
         if (writer) dst[v] = sum;
+        if (v >= 1 && v <= D && wall_out) d.wallf[size_t(d.bslot[f]) * 3 + (v - 1)] = double(sum);
     }
     fr.to_global(Ft, o);
 #pragma unroll
@@ -1396,24 +1402,23 @@ __global__ void k_res_store(const double *res, double *hist, int n_case) {
 }
 
 // Force of the gas on the walls (slip and no-slip boundary faces) of each
-// case: the momentum components of the face sums sum_g wJ F0 of the latest
-// flux pass, one block per case over its boundary faces in slot order.
-template <int D, typename R> __global__ __launch_bounds__(kBlock) void k_wall_force(Dev d) {
+// case: the momentum sums sum_g wJ F0 the latest stage-0 flux pass kept per
+// boundary slot, one block per case over its boundary slots in order.
+// Reduced on request only (not part of the cycle).
+template <int D> __global__ __launch_bounds__(kBlock) void k_wall_force(Dev d) {
     __shared__ double sh[kBlock];
     const int c = blockIdx.x;
-    if (!d.prm[c].active) return;
-    constexpr int FS = Dim<D>::fs;
     double f[D];
 #pragma unroll
     for (int a = 0; a < D; ++a) f[a] = 0.0;
     const int2 cb = d.case_b[c];
     for (int B = cb.x + threadIdx.x; B < cb.x + cb.y; B += kBlock) {
         const int F = d.bface[B];
+        if (F < 0) continue;
         const int bc = d.fbc[F];
         if (bc != 1 && bc != 2) continue;
-        const R *src = HoArrays<R>::fsum(d) + size_t(F) * FS;
 #pragma unroll
-        for (int a = 0; a < D; ++a) f[a] += double(src[1 + a]);
+        for (int a = 0; a < D; ++a) f[a] += d.wallf[size_t(B) * 3 + a];
     }
 #pragma unroll
     for (int a = 0; a < D; ++a) {
