@@ -155,6 +155,69 @@ def algorithmic_bytes(mesh, lm, rbytes, sbytes=8):
     return out
 
 
+def converge_report(mesh, lm, kw, drop=1e-10, max_cycles=3000):
+    """The workload run to a residual drop from the uniform start: FP64, and
+    MIXED32_R64 until it levels off at its FP32 floor, then finished in
+    FP64 to the same drop.  Reports cycles, seconds, drag coefficient and
+    the mixed state's error against the FP64 converged state (L2 and max,
+    relative), before and after the FP64 finish."""
+    import torch
+    import paper_2109_09965_amd as cg
+    import paper_2109_09965_amd.inputs as I
+    W0, dW0 = I.uniform_state(mesh, kw["W_inf"])
+    area = np.pi * 0.25 if mesh["dim"] == 3 else 1.0
+
+    def solve(b, tol, tol_abs, cycles):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rep, hist = b.solve(max_cycles=cycles, tol=tol, tol_abs=tol_abs, check_every=8, history=True)
+        torch.cuda.synchronize()
+        return rep[0], hist[0][:rep[0]["cycles"]], time.perf_counter() - t0
+
+    b = cg.Batch([lm], [cg.Params(**kw)])
+    b.upload(0, W0, dW0)
+    b.autotune()
+    r64, h64, t64 = solve(b, drop, False, max_cycles)
+    W64, _ = b.download(0)
+    cd64 = cg.drag_coefficient(r64["force"], kw["W_inf"], area)
+    del b
+    out = dict(fp64=dict(cycles=r64["cycles"], seconds=t64, res_drop=float(h64[-1] / h64[0]), converged=r64["converged"],
+                         cd=cd64))
+    # mixed: run until Res stops improving by 1 % over 100 cycles (its floor)
+    bm = cg.Batch([lm], [cg.Params(**kw)], precision=cg.MIXED32_R64)
+    bm.upload(0, W0, dW0)
+    bm.autotune()
+    tm, hm, cyc = 0.0, [], 0
+    best, best_at = np.inf, 0
+    while cyc < max_cycles:
+        rm, h, t = solve(bm, drop, False, 50)
+        tm += t
+        hm += list(h)
+        cyc += rm["cycles"]
+        for k, r in enumerate(h):
+            if r < 0.99 * best:
+                best, best_at = r, cyc - len(h) + k + 1
+        if rm["converged"] or cyc - best_at >= 100:
+            break
+    Wm, dWm = bm.download(0)
+    cdm = cg.drag_coefficient(rm["force"], kw["W_inf"], area)
+    del bm
+    err = lambda A: (float(np.linalg.norm(A - W64) / np.linalg.norm(W64)), float(np.abs(A - W64).max() / np.abs(W64).max()))
+    e_floor = err(Wm)
+    bf = cg.Batch([lm], [cg.Params(**kw)])
+    bf.upload(0, Wm, dWm)
+    bf.autotune()
+    rf, hf, tf = solve(bf, drop * hm[0], True, max_cycles)
+    Wf, _ = bf.download(0)
+    del bf
+    out["mixed32_r64"] = dict(cycles_mixed=cyc, cycles_fp64_finish=rf["cycles"], seconds=tm + tf,
+                              floor_drop=float(min(hm) / hm[0]), cd_at_floor=cdm,
+                              cd=cg.drag_coefficient(rf["force"], kw["W_inf"], area), converged=rf["converged"],
+                              l2_rel_err_at_floor=e_floor[0], max_rel_err_at_floor=e_floor[1],
+                              l2_rel_err=err(Wf)[0], max_rel_err=err(Wf)[1])
+    return out
+
+
 def cpu_baseline(seconds_hint=30.0):
     """The oracle as it stands, on a reduced hybrid sphere built the same way
     (cubed sphere 6 x 14 x 14 surface quads x 20 layers), single thread."""
@@ -341,6 +404,7 @@ def main():
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed32", "mixed32_r64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default launch shapes")
+    ap.add_argument("--no-converge", action="store_true", help="skip the run to a 1e-10 residual drop")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
                     help="only run 5 device-to-device copies of MIB MiB (counter calibration)")
     args = ap.parse_args()
@@ -448,6 +512,8 @@ def main():
                            launch_shapes=picks),
                roofline=rf, kernels=breakdown, res_last=float(res.cpu()[0]), res_after_graph=res_graph,
                eager_ms_per_step=1e3 * t_eager / args.steps, graph_ms_per_step=1e3 * t_graph / args.steps)
+    if args.workload == "sphere" and not args.no_converge:
+        out["convergence"] = converge_report(mesh, lm, kw)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)
