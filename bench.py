@@ -405,6 +405,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default launch shapes")
     ap.add_argument("--no-converge", action="store_true", help="skip the run to a 1e-10 residual drop")
+    ap.add_argument("--order-tile", type=int, default=0,
+                    help="caller cells per tile of the library cell order (0 = library default)")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
                     help="only run 5 device-to-device copies of MIB MiB (counter calibration)")
     args = ap.parse_args()
@@ -435,7 +437,7 @@ def main():
     import paper_2109_09965_amd.inputs as I
 
     mesh, kw, desc = workload(args.workload)
-    lm = cg.Mesh(mesh)
+    lm = cg.Mesh(mesh, order_tile=args.order_tile)
     prec = {"fp64": cg.FP64, "mixed32": cg.MIXED32, "mixed32_r64": cg.MIXED32_R64}[args.precision]
     b = cg.Batch([lm], [cg.Params(**kw)], precision=prec)
     W, dW = I.uniform_state(mesh, kw["W_inf"])
@@ -509,7 +511,7 @@ def main():
                data="synthetic (seeded mesh generator, uniform free-stream start)",
                config=dict(workload=desc, cells=NC, faces=NF, gauss_points=NG, colours=lm.n_colour,
                            precision=args.precision.upper(), time_scheme="S2O4", implicit_steps=6, sweeps=2,
-                           launch_shapes=picks),
+                           launch_shapes=picks, order_tile=args.order_tile or cg.ORDER_TILE_DEFAULT),
                roofline=rf, kernels=breakdown, res_last=float(res.cpu()[0]), res_after_graph=res_graph,
                eager_ms_per_step=1e3 * t_eager / args.steps, graph_ms_per_step=1e3 * t_graph / args.steps)
     if args.workload == "sphere" and not args.no_converge:

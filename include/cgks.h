@@ -72,6 +72,12 @@ enum { CGKS_RESIDUAL_HIGH = 0, CGKS_RESIDUAL_LOW = 1, CGKS_RESIDUAL_NORM = 2 };
  * boundary face, whose face_bc is one of the CGKS_BC_* tags.  face_shift
  * (may be NULL) holds, per face, the translation [dim] that carries the
  * neighbour next to the owner across a periodic seam (zero elsewhere).
+ * order_tile sets the library cell order: consecutive tiles of order_tile
+ * caller cells, each tile colour-major inside (0 = the library default,
+ * CGKS_ORDER_TILE_DEFAULT; >= n_cell gives one tile, i.e. the whole mesh
+ * colour-major).  Cells of one colour are independent, so the order changes
+ * no result beyond the rounding of the residual norm's sum; tiles keep a
+ * cell's neighbours close in memory and on one XCD.
  * All arrays are host memory, read during cgks_mesh_create only.
  */
 typedef struct {
@@ -86,7 +92,10 @@ typedef struct {
     const int64_t *face_neigh;      /* [n_face] in [0, n_cell) or -1 */
     const int32_t *face_bc;         /* [n_face] */
     const double *face_shift;       /* [n_face][dim] or NULL */
+    int64_t order_tile;             /* cells per ordering tile; 0 = default; < 0 is CGKS_EINVAL */
 } cgks_mesh_desc;
+
+#define CGKS_ORDER_TILE_DEFAULT 4096
 
 typedef struct {
     int dim, n_colour;
@@ -123,7 +132,8 @@ typedef struct cgks_batch cgks_batch;
 /* Build faces' Gauss points (3 per triangle, 4 per quadrilateral with a
    normal at each point, 2 per 2-D edge), cell volumes, centroids and second
    moments, the reconstruction operators, the multicolour classes (greedy,
-   smallest free colour, in caller cell order) and the library cell order.
+   smallest free colour, in caller cell order) and the library cell order
+   (tiles of order_tile caller cells, colour-major inside each tile).
    Host work only.  *out receives a handle (free with cgks_mesh_destroy).
    Errors: CGKS_EINVAL (null/size), CGKS_EMESH, CGKS_ENOMEM. */
 cgks_status cgks_mesh_create(const cgks_mesh_desc *desc, cgks_mesh **out);

@@ -41,11 +41,14 @@ class CgksError(RuntimeError):
         super().__init__(f"{what}: {msg} ({status})")
 
 
+ORDER_TILE_DEFAULT = 4096   # CGKS_ORDER_TILE_DEFAULT of include/cgks.h
+
+
 class _Desc(C.Structure):
     _fields_ = [("dim", C.c_int), ("n_vert", C.c_int64), ("xyz", C.c_void_p), ("n_cell", C.c_int64),
                 ("n_face", C.c_int64), ("face_vert_ptr", C.c_void_p), ("face_vert", C.c_void_p),
                 ("face_owner", C.c_void_p), ("face_neigh", C.c_void_p), ("face_bc", C.c_void_p),
-                ("face_shift", C.c_void_p)]
+                ("face_shift", C.c_void_p), ("order_tile", C.c_int64)]
 
 
 class _Info(C.Structure):
@@ -171,7 +174,9 @@ class Params:
 class Mesh:
     """Host-side mesh handle (cgks_mesh_create) from a face-based mesh dict."""
 
-    def __init__(self, m: dict):
+    def __init__(self, m: dict, order_tile: int = 0):
+        """order_tile: caller cells per tile of the library cell order
+        (0 = library default)."""
         L = lib()
         self.dim = int(m["dim"])
         self.nv = self.dim + 2
@@ -184,7 +189,7 @@ class Mesh:
                     sh=np.ascontiguousarray(m["face_shift"], np.float64))
         d = _Desc(self.dim, len(keep["xyz"]), _ptr(keep["xyz"]), int(m["n_cell"]), len(keep["own"]),
                   _ptr(keep["ptr"]), _ptr(keep["fv"]), _ptr(keep["own"]), _ptr(keep["nb"]), _ptr(keep["bc"]),
-                  _ptr(keep["sh"]))
+                  _ptr(keep["sh"]), int(order_tile))
         h = C.c_void_p()
         _check(L.cgks_mesh_create(C.byref(d), C.byref(h)), "cgks_mesh_create")
         self.h = h

@@ -19,7 +19,6 @@ namespace {
 constexpr int kRedChunk = 1024;   // cells per reduction block (never straddles cases)
 constexpr int kMaxGraphCycles = 64;   // cycles one captured graph may hold
 constexpr int kMaxColours = 16;   // colours a mesh may use
-constexpr int kSweepChunkMin = 16;   // smallest tunable sweep chunk (cells per block)
 
 // First-fit allocator of index ranges in [0, cap): the arena positions of
 // one entity type (cells, faces, Gauss points, boundary slots).
@@ -212,7 +211,8 @@ void layout(cgks_batch *b) {
     o.flag = a.take<int32_t>(K1);
     // table capacities: every case adds at most one partial chunk per block kind
     b->max_rb = int64_t(NC) / kRedChunk + b->n_case + 1;
-    b->max_cb = int64_t(NC) / kSweepChunkMin + int64_t(b->n_case) * kMaxColours + 1;
+    // sweep chunks are disjoint and never empty: at most one per cell
+    b->max_cb = int64_t(NC) + 1;
     o.rb_start = a.take<int32_t>(b->max_rb);
     o.rb_count = a.take<int32_t>(b->max_rb);
     o.rb_case = a.take<int32_t>(b->max_rb);
@@ -680,7 +680,7 @@ static cgks_status upload_case(cgks_batch *b, int c, hipStream_t s) {
     return CGKS_OK;
 }
 
-// Sweep chunks (per colour, every live case's cells of that colour), the
+// Sweep chunks (per colour, every live case's runs of that colour), the
 // per-case reduction blocks and the launch extents, after the set of live
 // cases changed.  Drops a captured graph (its launches have the old shape).
 static cgks_status rebuild_tables(cgks_batch *b, hipStream_t s) {
@@ -701,12 +701,12 @@ static cgks_status rebuild_tables(cgks_batch *b, hipStream_t s) {
             if (!b->live[c]) continue;
             const HostMesh &m = b->meshes[c]->hm;
             if (col >= m.n_colour) continue;
-            int64_t start = b->cell_off[c];
-            for (int k = 0; k < col; ++k) start += m.colour_count[k];
-            const int64_t n = m.colour_count[col];
-            for (int64_t q = 0; q < n; q += b->sweep_chunk) {
-                b->cb_start.push_back(int32_t(start + q));
-                b->cb_count.push_back(int32_t(std::min<int64_t>(b->sweep_chunk, n - q)));
+            for (int64_t r = m.run_ptr[col]; r < m.run_ptr[col + 1]; ++r) {
+                const int64_t start = b->cell_off[c] + m.run_start[r], n = m.run_count[r];
+                for (int64_t q = 0; q < n; q += b->sweep_chunk) {
+                    b->cb_start.push_back(int32_t(start + q));
+                    b->cb_count.push_back(int32_t(std::min<int64_t>(b->sweep_chunk, n - q)));
+                }
             }
         }
         b->colour_blk_off[col + 1] = b->cb_start.size();

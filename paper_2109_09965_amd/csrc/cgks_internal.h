@@ -40,8 +40,13 @@ struct HostMesh {
     std::vector<uint8_t> linear;            // 1 = linear fallback
     std::vector<double> gavg;               // [face][nk] ghost basis averages (boundary faces)
     // library order
+    int64_t tile = 0;                       // caller cells per ordering tile
     std::vector<int64_t> lib2caller, caller2lib;
     std::vector<int64_t> colour_count;      // cells per colour
+    // runs of consecutive library cells of one colour (one per tile and
+    // colour present in it), grouped by colour: runs of colour c are
+    // [run_ptr[c], run_ptr[c + 1])
+    std::vector<int64_t> run_ptr, run_start, run_count;
 };
 
 cgks_status build_host_mesh(const cgks_mesh_desc *d, HostMesh &m);

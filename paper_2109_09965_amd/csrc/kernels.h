@@ -192,79 +192,45 @@ template <int D, typename R> struct Frame {
 };
 
 // ---------------------------------------------------------------------
-// Maxwellian moments (per unit density) in the local frame.
+// Moments of the Maxwellian in central form.  With c = u - U (local
+// frame) and s = (|c|^2 + xi^2) / 2 the moment vectors psi = (1, u, E-term)
+// and psi_c = (1, c, s) are related by psi = M psi_c:
+//   psi_0 = 1,  psi_k = U_k + c_k,  psi_E = |U|^2/2 + U.c + s.
+// Under the Maxwellian c is Gaussian with variance theta = 1/(2 lam) per
+// component, so odd central moments vanish and the even ones needed here
+// are closed forms in theta and N = K + D (Isserlis' theorem):
+//   E[c_j c_k] = theta d_jk,  E[s] = N theta/2,  E[c_j c_k s] = d_jk theta^2 (N+2)/2,
+//   E[s^2] = N (N+2) theta^2/4,  E[c_j c_k s^2] = d_jk theta^3 (N+2)(N+4)/4.
+// A micro-slope a.psi whose moments <a psi> = g are given is, in central
+// form, alpha_0 + alpha.c + a_E s with
+//   g_c = M^-1 g,  alpha_k theta = g_ck,
+//   a_E = 2 g_cs / (N theta^2) - g_c0 / theta,  alpha_0 = g_c0 - a_E N theta/2,
+// and every product moment the flux needs reduces to g_c (below), so the
+// slopes never have to be formed explicitly.
 // ---------------------------------------------------------------------
-template <int D, typename R> struct Moments {
-    R mu[7], mv[6], mw[6], xi[3];
-    __device__ __forceinline__ void full(const R *U, R lam, R K) {
-        const R il = R(0.5) / lam;
-        mu[0] = R(1.0); mu[1] = U[0];
-#pragma unroll
-        for (int k = 2; k < 7; ++k) mu[k] = U[0] * mu[k - 1] + (k - 1) * il * mu[k - 2];
-        mv[0] = R(1.0); mv[1] = U[1];
-#pragma unroll
-        for (int k = 2; k < 6; ++k) mv[k] = U[1] * mv[k - 1] + (k - 1) * il * mv[k - 2];
-        if (D == 3) {
-            mw[0] = R(1.0); mw[1] = U[D - 1];
-#pragma unroll
-            for (int k = 2; k < 6; ++k) mw[k] = U[D - 1] * mw[k - 1] + (k - 1) * il * mw[k - 2];
-        }
-        xi[0] = R(1.0);
-        xi[1] = K * il;
-        xi[2] = (K * K + R(2.0) * K) * il * il;
-    }
-    __device__ __forceinline__ R M(int i, int j, int l, int e) const {
-        return D == 3 ? mu[i] * mv[j] * mw[l] * xi[e] : mu[i] * mv[j] * xi[e];
-    }
-};
 
-// micro-slope coefficients a = a0 + a_u u + a_v v (+ a_w w) + a_E (u^2 + .. + xi^2)/2
-// solving <a psi> = b in closed form (b per unit density)
-// (il = 1/(2 lam), iN = 1/N passed in: no division here)
-template <int D, typename R> __device__ __forceinline__ void micro_slope(const R *b, const R *U, R lam, R il, R N,
-                                                             R iN, R *a) {
-    constexpr int nv = D + 2;
-    R U2 = 0, Ub = 0;
+// x_c = M^-1 x (u2h = |U|^2 / 2)
+template <int D, typename R> __device__ __forceinline__ void to_central(const R *x, const R *U, R u2h, R *xc) {
+    R ux = 0;
+    xc[0] = x[0];
 #pragma unroll
     for (int k = 0; k < D; ++k) {
-        U2 += U[k] * U[k];
-        Ub += U[k] * b[1 + k];
+        xc[1 + k] = x[1 + k] - U[k] * x[0];
+        ux += U[k] * x[1 + k];
     }
-    const R aE = R(4.0) * lam * lam * iN * (R(2.0) * b[nv - 1] - R(2.0) * Ub + (U2 - N * il) * b[0]);
-    R aU = 0;
+    xc[D + 1] = x[D + 1] - ux + u2h * x[0];
+}
+
+// x = M x_c, scaled by rho
+template <int D, typename R> __device__ __forceinline__ void from_central(const R *xc, const R *U, R u2h, R rho, R *x) {
+    R ux = 0;
+    x[0] = rho * xc[0];
 #pragma unroll
     for (int k = 0; k < D; ++k) {
-        a[1 + k] = R(2.0) * lam * (b[1 + k] - U[k] * b[0]) - aE * U[k];
-        aU += a[1 + k] * U[k];
+        x[1 + k] = rho * (xc[1 + k] + U[k] * xc[0]);
+        ux += U[k] * xc[1 + k];
     }
-    a[nv - 1] = aE;
-    a[0] = b[0] - aU - R(0.5) * aE * (U2 + N * il);
-}
-
-// E[a u^i v^j w^l xi^(2e)]
-template <int D, typename R> __device__ __forceinline__ R Ea(const Moments<D, R> &m, const R *a, int i, int j, int l, int e) {
-    R s = a[0] * m.M(i, j, l, e) + a[1] * m.M(i + 1, j, l, e) + a[2] * m.M(i, j + 1, l, e);
-    R q = m.M(i + 2, j, l, e) + m.M(i, j + 2, l, e) + m.M(i, j, l, e + 1);
-    if constexpr (D == 3) {
-        s += a[3] * m.M(i, j, l + 1, e);
-        q += m.M(i, j, l + 2, e);
-    }
-    return s + R(0.5) * a[D + 1] * q;
-}
-
-// out[p] = E[psi_p a u^i v^j w^l]
-template <int D, typename R> __device__ __forceinline__ void Epsi(const Moments<D, R> &m, const R *a, int i, int j, int l,
-                                                      R *out) {
-    constexpr int nv = D + 2;
-    out[0] = Ea<D, R>(m, a, i, j, l, 0);
-    out[1] = Ea<D, R>(m, a, i + 1, j, l, 0);
-    out[2] = Ea<D, R>(m, a, i, j + 1, l, 0);
-    R q = Ea<D, R>(m, a, i + 2, j, l, 0) + Ea<D, R>(m, a, i, j + 2, l, 0) + Ea<D, R>(m, a, i, j, l, 1);
-    if constexpr (D == 3) {
-        out[3] = Ea<D, R>(m, a, i, j, l + 1, 0);
-        q += Ea<D, R>(m, a, i, j, l + 2, 0);
-    }
-    out[nv - 1] = R(0.5) * q;
+    x[D + 1] = rho * (xc[D + 1] + ux + u2h * xc[0]);
 }
 
 // primitive variables of a local-frame state
@@ -287,17 +253,24 @@ template <int D, typename R> struct Prim {
 // Smooth-flow gas-kinetic flux (local frame, axis 0 = normal):
 //   f = g^c [1 - tau (a.u + A) + A t]
 // F0 = flux at t = 0, Ft = its time derivative, Wt = rho <A psi>.
+// With the micro-slope a^(j) of direction j (its central moments
+// g^(j)_c = M^-1 (grad_j W / rho)) and n = 0 the normal axis:
+//   <A psi_c> = b_c = -sum_j E[u_j a^(j) psi_c]
+//   sum_j E[u_n u_j a^(j) psi_c] = sum_j (U_n U_j g_c + U_n E[c_j a psi_c]
+//                                  + U_j E[c_n a psi_c] + E[c_n c_j a psi_c])
+//   E[c_n c_j a psi_c] = (d_nj c1 g_cs,
+//                         theta (d_nj g_ck + d_nk g_cj + d_jk g_cn),
+//                         d_nj c2 (2 c1 g_cs - theta g_c0))
+// F0 = rho M (E[u_n psi_c] - tau (sum_j E[u_n u_j a psi_c] + E[u_n A psi_c])),
+// Ft = rho M E[u_n A psi_c], Wt = rho M b_c.
 // Returns false for a non-physical interface state.
 template <int D, typename R> __device__ bool gks_flux(const R *Wc, const R Gc[D][D + 2], const DevParams &P, R *F0,
                                           R *Ft, R *Wt) {
-    constexpr int nv = D + 2;
+    constexpr int nv = D + 2, S = D + 1;
     Prim<D, R> q;
     q.from(Wc, R(P.gamma));
     if (!(q.rho > R(0.0)) || !(q.p > R(0.0))) return false;
     const R N = R(P.K) + D;
-    R Uf[3] = {0, 0, 0};
-#pragma unroll
-    for (int a = 0; a < D; ++a) Uf[a] = q.U[a];
     // Fourier heat flux of the interface state along the normal (R = 1,
     // T = p / rho), used for the Prandtl-number correction
     R qcorr = R(0.0);
@@ -312,51 +285,73 @@ template <int D, typename R> __device__ bool gks_flux(const R *Wc, const R Gc[D]
         const R Tn = (pn * q.rho - q.p * Gc[0][0]) / (q.rho * q.rho);
         qcorr = (R(1.0) / R(P.Pr) - R(1.0)) * (-R(P.mu) * R(P.gamma) / (R(P.gamma) - R(1.0)) * Tn);
     }
-    Moments<D, R> m;
-    m.full(Uf, q.lam, R(P.K));
-    const R tau = R(P.mu) / q.p;
     const R ir = R(1.0) / q.rho;
-    const R il = R(0.5) / q.lam, iN = R(1.0) / N;
-    // one direction at a time: micro-slope a^(j), its share of the
-    // compatibility sum b = -<(sum_j a^(j) u_j) psi> and of the collision term
-    // tt = <u psi (sum_j a^(j) u_j)>
-    R b[nv], tt[nv];
+    const R th = q.p * ir;                      // theta = 1 / (2 lam)
+    const R tau = R(P.mu) / q.p;
+    const R c1 = R(2.0) / N, c2 = R(0.5) * th * (N + R(2.0));
+    R u2h = 0;
 #pragma unroll
-    for (int v = 0; v < nv; ++v) b[v] = tt[v] = R(0.0);
+    for (int k = 0; k < D; ++k) u2h += q.U[k] * q.U[k];
+    u2h *= R(0.5);
+    const R Un = q.U[0];
+    R bc[nv], tc[nv];
+#pragma unroll
+    for (int v = 0; v < nv; ++v) bc[v] = tc[v] = R(0.0);
 #pragma unroll
     for (int j = 0; j < D; ++j) {
-        R g[nv], a[nv], t0[nv];
+        R g[nv], gc[nv];
 #pragma unroll
         for (int v = 0; v < nv; ++v) g[v] = Gc[j][v] * ir;
-        micro_slope<D, R>(g, q.U, q.lam, il, N, iN, a);
-        Epsi<D, R>(m, a, j == 0 ? 1 : 0, j == 1 ? 1 : 0, j == 2 ? 1 : 0, t0);
+        to_central<D, R>(g, q.U, u2h, gc);
+        const R Uj = q.U[j];
+        // E[c_j a psi_c] = (g_cj, d_jk c1 g_cs, c2 g_cj), c1 = 2/N,
+        // c2 = theta (N+2)/2; the same with j = n; E[u_j a psi_c] = U_j g_c + rj
+        R rj[nv], rn[nv];
 #pragma unroll
-        for (int v = 0; v < nv; ++v) b[v] -= t0[v];
-        Epsi<D, R>(m, a, j == 0 ? 2 : 1, j == 1 ? 1 : 0, j == 2 ? 1 : 0, t0);
+        for (int v = 0; v < nv; ++v) rj[v] = rn[v] = R(0.0);
+        rj[0] = gc[1 + j];
+        rj[1 + j] = c1 * gc[S];
+        rj[S] = c2 * gc[1 + j];
+        rn[0] = gc[1];
+        rn[1] = c1 * gc[S];
+        rn[S] = c2 * gc[1];
+        // E[c_n c_j a psi_c]
+        R sj[nv];
 #pragma unroll
-        for (int v = 0; v < nv; ++v) tt[v] += t0[v];
-    }
-    R A[nv], eA[nv];
-    micro_slope<D, R>(b, q.U, q.lam, il, N, iN, A);
-    // E[u psi A] gives the time derivative of the flux
-    Epsi<D, R>(m, A, 1, 0, 0, eA);
-    // E[u psi]
-    R eu[nv];
-    eu[0] = m.mu[1];
-    eu[1] = m.mu[2];
-    eu[2] = m.mu[1] * m.mv[1];
-    R ep = m.mu[3] + m.mu[1] * (m.mv[2] + m.xi[1]);
-    if constexpr (D == 3) {
-        eu[3] = m.mu[1] * m.mw[1];
-        ep += m.mu[1] * m.mw[2];
-    }
-    eu[nv - 1] = R(0.5) * ep;
+        for (int v = 0; v < nv; ++v) sj[v] = R(0.0);
+        if (j == 0) {
+            sj[0] = c1 * gc[S];
+            sj[S] = c2 * (R(2.0) * c1 * gc[S] - th * gc[0]);
 #pragma unroll
-    for (int v = 0; v < nv; ++v) {
-        F0[v] = q.rho * (eu[v] - tau * (tt[v] + eA[v]));
-        Ft[v] = q.rho * eA[v];
-        Wt[v] = q.rho * b[v];
+            for (int k = 0; k < D; ++k) sj[1 + k] = th * gc[1 + k];
+            sj[1] += th * R(2.0) * gc[1];
+        } else {
+            sj[1] = th * gc[1 + j];
+            sj[1 + j] = th * gc[1];
+        }
+        const R UnUj = Un * Uj;
+#pragma unroll
+        for (int v = 0; v < nv; ++v) {
+            bc[v] -= Uj * gc[v] + rj[v];
+            tc[v] += UnUj * gc[v] + Un * rj[v] + Uj * rn[v] + sj[v];
+        }
     }
+    // E[u_n A psi_c] for the slope A with central moments b_c
+    R ea[nv], fc[nv];
+#pragma unroll
+    for (int v = 0; v < nv; ++v) ea[v] = Un * bc[v];
+    ea[0] += bc[1];
+    ea[1] += c1 * bc[S];
+    ea[S] += c2 * bc[1];
+    // E[u_n psi_c] = (U_n, theta d_nk, U_n N theta / 2)
+#pragma unroll
+    for (int v = 0; v < nv; ++v) fc[v] = -tau * (tc[v] + ea[v]);
+    fc[0] += Un;
+    fc[1] += th;
+    fc[S] += R(0.5) * Un * N * th;
+    from_central<D, R>(fc, q.U, u2h, q.rho, F0);
+    from_central<D, R>(ea, q.U, u2h, q.rho, Ft);
+    from_central<D, R>(bc, q.U, u2h, q.rho, Wt);
     F0[nv - 1] += qcorr;
     return true;
 }
@@ -817,12 +812,17 @@ template <> struct Vec16<float> {
     static __device__ __forceinline__ void unpack(const T &t, float *o) { o[0] = t.x; o[1] = t.y; o[2] = t.z; o[3] = t.w; }
 };
 
+// Reconstruction of cell i evaluated at x: W(x) into Wx, and its gradient
+// added into G (global frame).  The coefficients are consumed in groups of
+// KG basis functions with a scheduling barrier between groups, so at most
+// one group's loads are in flight: the flux kernel's register peak (and so
+// its occupancy) is set here.
 template <int D, typename R> __device__ __forceinline__ void recon_eval(const Dev &d, int i, const R *x, R *Wx,
                                                                         R G[D][D + 2]) {
     using T = Dim<D>;
     using RC = Rec<D>;
     using V = Vec16<R>;
-    constexpr int nv = T::nv, nq = T::nq;
+    constexpr int nv = T::nv, nq = T::nq, KG = 3;
     const R *base = HoArrays<R>::ev(d) + size_t(i) * RC::er;
     const typename V::T *rv = reinterpret_cast<const typename V::T *>(base);
     constexpr int NV = RC::OC / V::n;
@@ -832,40 +832,37 @@ template <int D, typename R> __device__ __forceinline__ void recon_eval(const De
 #pragma unroll
     for (int k = NV * V::n; k < RC::OC; ++k) r[k] = base[k];
     const R ih = r[D];
-    R y[D];
+    R y[D], yh[D];
 #pragma unroll
-    for (int a = 0; a < D; ++a) y[a] = (x[a] - r[a]) * ih;
-#pragma unroll
-    for (int v = 0; v < nv; ++v) {
-        Wx[v] = r[RC::OW + v];
-#pragma unroll
-        for (int a = 0; a < D; ++a) G[a][v] = R(0.0);
+    for (int a = 0; a < D; ++a) {
+        y[a] = (x[a] - r[a]) * ih;
+        yh[a] = y[a] * ih;
     }
+#pragma unroll
+    for (int v = 0; v < nv; ++v) Wx[v] = r[RC::OW + v];
     const R *c = base + RC::OC;
 #pragma unroll
-    for (int a = 0; a < D; ++a)
+    for (int k = 0; k < D + nq; ++k) {
+        if (k % KG == 0 && k > 0) __builtin_amdgcn_sched_barrier(0);
+        if (k < D) {
 #pragma unroll
-        for (int v = 0; v < nv; ++v) {
-            const R ck = c[a * nv + v];
-            Wx[v] += ck * y[a];
-            G[a][v] += ck;
-        }
+            for (int v = 0; v < nv; ++v) {
+                const R ck = c[k * nv + v];
+                Wx[v] += ck * y[k];
+                G[k][v] += ck * ih;
+            }
+        } else {
+            const int q = k - D, a = qa<D>(q), b = qb<D>(q);
+            const R phi = y[a] * y[b] - r[D + 1 + q];
 #pragma unroll
-    for (int q = 0; q < nq; ++q) {
-        const int a = qa<D>(q), b = qb<D>(q);
-        const R phi = y[a] * y[b] - r[D + 1 + q];
-#pragma unroll
-        for (int v = 0; v < nv; ++v) {
-            const R ck = c[(D + q) * nv + v];
-            Wx[v] += ck * phi;
-            G[a][v] += ck * y[b];
-            G[b][v] += ck * y[a];
+            for (int v = 0; v < nv; ++v) {
+                const R ck = c[k * nv + v];
+                Wx[v] += ck * phi;
+                G[a][v] += ck * yh[b];
+                G[b][v] += ck * yh[a];
+            }
         }
     }
-#pragma unroll
-    for (int a = 0; a < D; ++a)
-#pragma unroll
-        for (int v = 0; v < nv; ++v) G[a][v] *= ih;
 }
 
 // ---------------------------------------------------------------------
@@ -949,50 +946,64 @@ template <int D, typename R> __global__ __launch_bounds__(kBlock) void k_flux(De
     bool ok = true;
     const int bc = d.fbc[f];
     {
-        R Wg[nv], GL[D][nv], WL[nv], GLl[D][nv];
-        recon_eval<D, R>(d, cL, x, Wg, GL);
-        fr.to_local(Wg, WL);
-        fr.grad_to_local(GL, GLl);
+        // gradients summed in the global frame, rotated once
+        R Gs[D][nv], WL[nv];
+#pragma unroll
+        for (int a = 0; a < D; ++a)
+#pragma unroll
+            for (int v = 0; v < nv; ++v) Gs[a][v] = R(0.0);
+        {
+            R Wg[nv];
+            recon_eval<D, R>(d, cL, x, Wg, Gs);
+            fr.to_local(Wg, WL);
+        }
         if (cR >= 0 || bc != 2) {
-            R WR[nv], GRl[D][nv];
+            R WR[nv];
             if (cR >= 0) {
-                R xr[D], WRg[nv], GR[D][nv];
+                R xr[D], WRg[nv];
 #pragma unroll
                 for (int a = 0; a < D; ++a) xr[a] = x[a] - R(d.shift[size_t(a) * d.NF + f]);
-                recon_eval<D, R>(d, cR, xr, WRg, GR);
+                recon_eval<D, R>(d, cR, xr, WRg, Gs);
                 fr.to_local(WRg, WR);
-                fr.grad_to_local(GR, GRl);
             } else if (bc == 1) {
-                // mirror: normal momentum reversed; normal derivatives change sign
-                // except that of the normal momentum
+                // mirror: normal momentum reversed
 #pragma unroll
                 for (int v = 0; v < nv; ++v) WR[v] = WL[v];
                 WR[1] = -WL[1];
-#pragma unroll
-                for (int a = 0; a < D; ++a)
-#pragma unroll
-                    for (int v = 0; v < nv; ++v) {
-                        const R sa = (a == 0) ? -R(1.0) : R(1.0);
-                        GRl[a][v] = (v == 1 ? -sa : sa) * GLl[a][v];
-                    }
             } else {
                 R Wo_g[nv], Wo[nv];
 #pragma unroll
                 for (int v = 0; v < nv; ++v) Wo_g[v] = R(P.W_inf[v]);
                 fr.to_local(Wo_g, Wo);
                 farfield_state<D, R>(WL, Wo, R(P.gamma), WR);
-#pragma unroll
-                for (int a = 0; a < D; ++a)
-#pragma unroll
-                    for (int v = 0; v < nv; ++v) GRl[a][v] = R(0.0);
             }
 #pragma unroll
             for (int v = 0; v < nv; ++v) Wc[v] = R(0.0);
-            ok = half_side<D, R>(WL, P, R(1.0), Wc, nullptr) && half_side<D, R>(WR, P, -R(1.0), Wc, nullptr);
+            // one side at a time (the erfc and exp of both sides interleaved
+            // would set the register peak of the kernel)
+            __builtin_amdgcn_sched_barrier(0);
+            ok = half_side<D, R>(WL, P, R(1.0), Wc, nullptr);
+            __builtin_amdgcn_sched_barrier(0);
+            ok = half_side<D, R>(WR, P, -R(1.0), Wc, nullptr) && ok;
+            __builtin_amdgcn_sched_barrier(0);
+            fr.grad_to_local(Gs, Gc);
+            if (cR < 0 && bc == 1) {
+                // mirror ghost: a derivative flips sign when exactly one of
+                // (normal direction, normal momentum) applies to it; flipped
+                // ones cancel in the average, the others are kept whole
 #pragma unroll
-            for (int a = 0; a < D; ++a)
+                for (int a = 0; a < D; ++a)
 #pragma unroll
-                for (int v = 0; v < nv; ++v) Gc[a][v] = R(0.5) * (GLl[a][v] + GRl[a][v]);
+                    for (int v = 0; v < nv; ++v)
+                        if ((a == 0) != (v == 1)) Gc[a][v] = R(0.0);
+            } else {
+                // interior: average of both sides; far field: the exterior
+                // state has zero gradient
+#pragma unroll
+                for (int a = 0; a < D; ++a)
+#pragma unroll
+                    for (int v = 0; v < nv; ++v) Gc[a][v] *= R(0.5);
+            }
         } else {
             // no-slip isothermal wall: (p_L / T_w, 0, p_L), interior gradient
             Prim<D, R> pq;
@@ -1001,10 +1012,7 @@ template <int D, typename R> __global__ __launch_bounds__(kBlock) void k_flux(De
             for (int v = 0; v < nv; ++v) Wc[v] = R(0.0);
             Wc[0] = pq.p / R(P.T_wall);
             Wc[nv - 1] = pq.p / (R(P.gamma) - R(1.0));
-#pragma unroll
-            for (int a = 0; a < D; ++a)
-#pragma unroll
-                for (int v = 0; v < nv; ++v) Gc[a][v] = GLl[a][v];
+            fr.grad_to_local(Gs, Gc);
         }
     }
     R *dst = HoArrays<R>::fsum(d) + size_t(f) * FS;

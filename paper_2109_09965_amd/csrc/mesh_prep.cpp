@@ -438,14 +438,33 @@ void colour_and_order(HostMesh &m) {
     m.n_colour = ncol;
     m.colour_count.assign(ncol, 0);
     for (int64_t i = 0; i < m.n_cell; ++i) m.colour_count[m.colour[i]]++;
-    std::vector<int64_t> start(ncol + 1, 0);
-    for (int c = 0; c < ncol; ++c) start[c + 1] = start[c] + m.colour_count[c];
+    // library order: tiles of m.tile consecutive caller cells, colour-major
+    // inside each tile (increasing caller id within a colour)
     m.lib2caller.assign(m.n_cell, 0);
     m.caller2lib.assign(m.n_cell, 0);
-    for (int64_t i = 0; i < m.n_cell; ++i) {
-        const int64_t l = start[m.colour[i]]++;
-        m.lib2caller[l] = i;
-        m.caller2lib[i] = l;
+    std::vector<std::vector<std::pair<int64_t, int64_t>>> runs(ncol);
+    int64_t l = 0;
+    for (int64_t t0 = 0; t0 < m.n_cell; t0 += m.tile) {
+        const int64_t t1 = std::min(m.n_cell, t0 + m.tile);
+        for (int c = 0; c < ncol; ++c) {
+            const int64_t first = l;
+            for (int64_t i = t0; i < t1; ++i)
+                if (m.colour[i] == c) {
+                    m.lib2caller[l] = i;
+                    m.caller2lib[i] = l++;
+                }
+            if (l > first) runs[c].push_back({first, l - first});
+        }
+    }
+    m.run_ptr.assign(ncol + 1, 0);
+    m.run_start.clear();
+    m.run_count.clear();
+    for (int c = 0; c < ncol; ++c) {
+        for (const auto &r : runs[c]) {
+            m.run_start.push_back(r.first);
+            m.run_count.push_back(r.second);
+        }
+        m.run_ptr[c + 1] = int64_t(m.run_start.size());
     }
 }
 
@@ -455,8 +474,10 @@ cgks_status build_host_mesh(const cgks_mesh_desc *ds, HostMesh &m) {
     if (!ds || (ds->dim != 2 && ds->dim != 3) || ds->n_cell <= 0 || ds->n_face <= 0 || ds->n_vert <= 0 ||
         !ds->xyz || !ds->face_vert_ptr || !ds->face_vert || !ds->face_owner || !ds->face_neigh || !ds->face_bc)
         return CGKS_EINVAL;
+    if (ds->order_tile < 0) return CGKS_EINVAL;
     const int d = ds->dim;
     m.dim = d;
+    m.tile = ds->order_tile > 0 ? ds->order_tile : CGKS_ORDER_TILE_DEFAULT;
     m.nv = d + 2;
     m.nk = ncoef_of(d);
     m.nq = nquad_of(d);

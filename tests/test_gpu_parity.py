@@ -60,14 +60,14 @@ CASES = ["cyl2d_slip", "cyl2d_visc", "box2d_per", "box3d_per", "box3d_slip", "sp
 class Pair:
     """Oracle solver and a one-case GPU batch on the same mesh and params."""
 
-    def __init__(self, name, **over):
+    def __init__(self, name, order_tile=0, **over):
         m, kw, W, dW = make_case(name)
         kw.update(over)
         self.mesh = m
         self.W0, self.dW0 = W, dW
         self.om = oracle.Mesh(m)
         self.os = oracle.Solver(self.om, oracle.Params(**kw))
-        self.lm = cg.Mesh(m)
+        self.lm = cg.Mesh(m, order_tile=order_tile)
         self.b = cg.Batch([self.lm], [cg.Params(**kw)])
         self.b.upload(0, W, dW)
 
@@ -144,6 +144,38 @@ def test_cycles(name, scheme):
         check_state(p, W, dW, f"{name} s{scheme} cycle{k}")
         r_g = float(res.cpu()[0])
         assert abs(r_g - r_or) <= 1e-9 * r_or, (r_g, r_or)
+
+
+@pytest.mark.parametrize("name", ["cyl2d_visc", "cubed_sphere"])
+def test_cycles_tiled_order(name):
+    """A library order of many ragged tiles (37 cells, colour-major inside
+    each) against the oracle."""
+    import torch
+    p = Pair(name, order_tile=37)
+    W, dW = p.W0.copy(), p.dW0.copy()
+    res = torch.zeros(1, dtype=torch.float64, device="cuda")
+    for k in range(3):
+        r_or = p.os.cycle(W, dW)
+        p.b.cycle(res)
+        check_state(p, W, dW, f"{name} tiles of 37, cycle{k}")
+        assert abs(float(res.cpu()[0]) - r_or) <= 1e-9 * r_or
+
+
+@pytest.mark.parametrize("precision", [cg.FP64, cg.MIXED32])
+def test_state_does_not_depend_on_the_tile_size(precision):
+    """Cells of one colour are independent and every per-cell sum runs in
+    slot order, so the state after whole cycles is bitwise the same for any
+    tiling of the library order (only the residual norm's sum order moves)."""
+    m, kw, W, dW = make_case("cubed_sphere")
+    out = []
+    for tile in (37, 256, 10**9):
+        b = cg.Batch([cg.Mesh(m, order_tile=tile)], [cg.Params(**kw)], precision=precision)
+        b.upload(0, W, dW)
+        for _ in range(3):
+            b.cycle()
+        out.append(b.download(0))
+    for Wt, dWt in out[1:]:
+        assert np.array_equal(Wt, out[0][0]) and np.array_equal(dWt, out[0][1])
 
 
 def test_explicit_only_cycles():

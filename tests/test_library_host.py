@@ -44,9 +44,39 @@ def test_host_geometry_and_colouring_match_oracle(mk):
     assert np.array_equal(lm.colour, ce["colour"])
     assert lm.n_colour == om.n_colour
     assert np.array_equal(lin, om.linear_cells())
-    # library order is colour-major and a permutation
+    # library order is a permutation, colour-major when the mesh is one tile
     assert np.array_equal(np.sort(lm.lib2caller), np.arange(mesh["n_cell"]))
     assert np.all(np.diff(lm.colour[lm.lib2caller]) >= 0)
+
+
+@pytest.mark.parametrize("tile", [1, 7, 64, 1000, 10**9])
+def test_library_order_is_tiled_colour_major(tile):
+    """Tiles of `tile` consecutive caller cells, colour-major inside each
+    tile, increasing caller id within a colour of a tile."""
+    mesh = I.cubed_sphere_mesh(4, 10, 4, 3)
+    n = mesh["n_cell"]
+    lm = cg.Mesh(mesh, order_tile=tile)
+    l2c = lm.lib2caller
+    assert np.array_equal(np.sort(l2c), np.arange(n))
+    t = l2c // tile
+    assert np.all(np.diff(t) >= 0)                      # tiles in order
+    key = t * (lm.n_colour + 1) + lm.colour[l2c]
+    assert np.all(np.diff(key) >= 0)                    # colour-major inside a tile
+    same = np.diff(key) == 0
+    assert np.all(np.diff(l2c)[same] > 0)               # caller order inside a run
+    # the colouring does not depend on the order
+    assert np.array_equal(lm.colour, cg.Mesh(mesh, order_tile=10**9).colour)
+
+
+def test_order_tile_default_matches_header():
+    src = open(os.path.join(ROOT, "include", "cgks.h")).read()
+    assert int(re.search(r"#define CGKS_ORDER_TILE_DEFAULT (\d+)", src).group(1)) == cg.ORDER_TILE_DEFAULT
+
+
+def test_negative_order_tile_is_rejected():
+    with pytest.raises(cg.CgksError) as e:
+        cg.Mesh(I.cylinder_mesh(16, 8), order_tile=-1)
+    assert e.value.status == cg.EINVAL
 
 
 def test_mesh_errors_are_reported():
