@@ -259,23 +259,60 @@ static void cell_geometry(om_mesh *m) {
     }
 }
 
-/* greedy colouring in cell order: smallest colour unused by any face
-   neighbour (the multicolour ordering of the smoother) */
+/* Multicolour ordering of the smoother (a reading: the paper sweeps by
+   element index).  Welsh-Powell greedy colouring: cells are visited by
+   decreasing number of faces shared with another cell (ties: increasing cell
+   id) and each takes the smallest colour no already coloured face neighbour
+   has.  The classes are then renumbered for the sweep, which visits the first
+   colour three times per implicit step, the last twice and the others four
+   times: the largest class becomes the last colour, the second largest the
+   first, the remaining ones the colours between in decreasing size (equal
+   sizes: smaller greedy colour first). */
 static void colour_cells(om_mesh *m) {
-    int maxc = 0;
-    for (long i = 0; i < m->n_cell; i++) {
-        int used[64] = {0};
+    long n = m->n_cell;
+    int *deg = (int *)calloc(n, sizeof(int));
+    int maxdeg = 0;
+    for (long i = 0; i < n; i++) {
+        m->colour[i] = -1;
         for (long q = m->cf_ptr[i]; q < m->cf_ptr[i + 1]; q++) {
             long f = m->cf_face[q];
             long o = m->cf_sign[q] > 0 ? m->neigh[f] : m->owner[f];
-            if (o >= 0 && o < i) used[m->colour[o]] = 1;
+            if (o >= 0) deg[i]++;
         }
-        int c = 0;
-        while (used[c]) c++;
-        m->colour[i] = c;
-        if (c + 1 > maxc) maxc = c + 1;
+        if (deg[i] > maxdeg) maxdeg = deg[i];
     }
-    m->n_colour = maxc;
+    int ncol = 0;
+    for (int dg = maxdeg; dg >= 0; dg--)
+        for (long i = 0; i < n; i++) {
+            if (deg[i] != dg) continue;
+            int used[64] = {0};
+            for (long q = m->cf_ptr[i]; q < m->cf_ptr[i + 1]; q++) {
+                long f = m->cf_face[q];
+                long o = m->cf_sign[q] > 0 ? m->neigh[f] : m->owner[f];
+                if (o >= 0 && m->colour[o] >= 0) used[m->colour[o]] = 1;
+            }
+            int c = 0;
+            while (used[c]) c++;
+            m->colour[i] = c;
+            if (c + 1 > ncol) ncol = c + 1;
+        }
+    free(deg);
+    /* classes by decreasing size, then the new colour of each */
+    long size[64] = {0};
+    int rank[64], newc[64];
+    for (long i = 0; i < n; i++) size[m->colour[i]]++;
+    for (int c = 0; c < ncol; c++) rank[c] = c;
+    for (int a = 1; a < ncol; a++)        /* insertion sort: stable, so ties keep the greedy order */
+        for (int b = a; b > 0 && size[rank[b]] > size[rank[b - 1]]; b--) {
+            int t = rank[b]; rank[b] = rank[b - 1]; rank[b - 1] = t;
+        }
+    for (int k = 0; k < ncol; k++) {
+        if (k == 0) newc[rank[k]] = ncol - 1;
+        else if (k == 1) newc[rank[k]] = 0;
+        else newc[rank[k]] = k - 1;
+    }
+    for (long i = 0; i < n; i++) m->colour[i] = newc[m->colour[i]];
+    m->n_colour = ncol;
 }
 
 /* ------------------------------------------------------------------ */

@@ -419,15 +419,30 @@ cgks_status recon_setup(HostMesh &m) {
     return CGKS_OK;
 }
 
+// Multicolour classes of the relaxation sweeps (Algorithm 1 in a
+// deterministic parallel order).  Largest-degree-first greedy colouring
+// (Welsh-Powell): cells in order of decreasing count of faces with a
+// neighbour cell, ties by caller id, each given the smallest colour absent
+// from its coloured neighbours.  Class ids are then assigned by size: a step's
+// passes visit colour 0 three times, colour C-1 twice and the others four
+// times, so the largest class takes C-1, the next largest 0 and the rest
+// 1..C-2 by decreasing size (stable on the greedy id).
 void colour_and_order(HostMesh &m) {
-    m.colour.assign(m.n_cell, -1);
+    const int64_t n = m.n_cell;
+    auto neighbour = [&](int64_t q) { return m.cf_side[q] ? m.owner[m.cf_face[q]] : m.neigh[m.cf_face[q]]; };
+    std::vector<int> deg(n, 0);
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t q = m.cf_ptr[i]; q < m.cf_ptr[i + 1]; ++q) deg[i] += neighbour(q) >= 0;
+    std::vector<int64_t> visit(n);
+    for (int64_t i = 0; i < n; ++i) visit[i] = i;
+    std::stable_sort(visit.begin(), visit.end(), [&](int64_t x, int64_t y) { return deg[x] > deg[y]; });
+    m.colour.assign(n, -1);
     int ncol = 0;
     std::vector<char> used;
-    for (int64_t i = 0; i < m.n_cell; ++i) {
+    for (int64_t i : visit) {
         used.assign(ncol + 1, 0);
         for (int64_t q = m.cf_ptr[i]; q < m.cf_ptr[i + 1]; ++q) {
-            const int64_t f = m.cf_face[q];
-            const int64_t nb = m.cf_side[q] ? m.owner[f] : m.neigh[f];
+            const int64_t nb = neighbour(q);
             if (nb >= 0 && m.colour[nb] >= 0) used[m.colour[nb]] = 1;
         }
         int c = 0;
@@ -435,6 +450,14 @@ void colour_and_order(HostMesh &m) {
         m.colour[i] = c;
         ncol = std::max(ncol, c + 1);
     }
+    std::vector<int64_t> size(ncol, 0);
+    for (int64_t i = 0; i < n; ++i) size[m.colour[i]]++;
+    std::vector<int> by_size(ncol);
+    for (int c = 0; c < ncol; ++c) by_size[c] = c;
+    std::stable_sort(by_size.begin(), by_size.end(), [&](int x, int y) { return size[x] > size[y]; });
+    std::vector<int> relabel(ncol);
+    for (int k = 0; k < ncol; ++k) relabel[by_size[k]] = k == 0 ? ncol - 1 : k - 1;
+    for (int64_t i = 0; i < n; ++i) m.colour[i] = relabel[m.colour[i]];
     m.n_colour = ncol;
     m.colour_count.assign(ncol, 0);
     for (int64_t i = 0; i < m.n_cell; ++i) m.colour_count[m.colour[i]]++;

@@ -254,6 +254,37 @@ def test_colouring_is_an_independent_set(mk):
     assert om.n_colour == col.max() + 1
 
 
+@pytest.mark.parametrize("mk", [I.cylinder_case_mesh, lambda: I.sphere_mesh(8, 16, 8, 3, 2),
+                                lambda: I.cubed_sphere_mesh(4, 8, 3, 2),
+                                lambda: I.box3d_mesh((3, 3, 5), perturb=0.2, seed=4)])
+def test_colouring_is_largest_first_and_numbered_by_class_size(mk):
+    """Largest-degree-first greedy colouring meets the Welsh-Powell bound
+    n_colour <= max_i min(d_i + 1, i) (degrees sorted decreasing, i from 1);
+    the largest class is the last colour, the next largest the first, the
+    others in between by decreasing size."""
+    mesh = mk()
+    om = oracle.Mesh(mesh)
+    col = om.cells()["colour"]
+    n = mesh["n_cell"]
+    ok = mesh["face_neigh"] >= 0
+    deg = np.bincount(mesh["face_owner"][ok], minlength=n) + np.bincount(mesh["face_neigh"][ok], minlength=n)
+    d = np.sort(deg)[::-1]
+    assert om.n_colour <= np.max(np.minimum(d + 1, np.arange(1, n + 1)))
+    size = np.bincount(col)
+    C = om.n_colour
+    if C >= 2:
+        assert size[C - 1] >= size[0]
+        assert np.all(size[0] >= size[1:C - 1])
+        assert np.all(np.diff(size[1:C - 1]) <= 0)
+
+
+def test_sphere_workload_needs_four_colours():
+    """The hybrid sphere of the benchmark takes four colours (greedy in
+    caller order needs a fifth, for a single cell)."""
+    om = oracle.Mesh(I.sphere_case_mesh())
+    assert om.n_colour == 4
+
+
 @pytest.mark.parametrize("n,layers", [(3, (6, 2, 2)), (5, (8, 3, 2))])
 def test_cubed_sphere_is_a_valid_conforming_mesh(n, layers):
     """The cubed-sphere O-grid: every interior face joins exactly two cells
