@@ -601,6 +601,7 @@ static cgks_status upload_case(cgks_batch *b, int c, hipStream_t s) {
     std::vector<int32_t> fL(nf), fR(nf), fbc(nf), fcase(nf, c), bslot(nf, -1);
     std::vector<int2> gp_rng(nf);
     std::vector<double> avec(d * nf), S(nf), shift(d * nf), gavg(nk * nb), gx(d * ng), gn(d * ng), gw(ng);
+    std::vector<double> swp(4 * nf, 0.0);   // sweep records: area vector now, S lam by each low-level step
     std::vector<int32_t> bface(nb);
     for (int64_t l = 0; l < n; ++l) {
         const int64_t i = m.lib2caller[l];
@@ -630,6 +631,7 @@ static cgks_status upload_case(cgks_batch *b, int c, hipStream_t s) {
         for (int a = 0; a < d; ++a) {
             avec[a * nf + f] = m.avec[f * d + a];
             shift[a * nf + f] = m.shift[f * d + a];
+            swp[4 * f + a] = m.avec[f * d + a];
         }
         S[f] = m.S[f];
         if (m.neigh[f] < 0) {
@@ -661,6 +663,7 @@ static cgks_status upload_case(cgks_batch *b, int c, hipStream_t s) {
     HIP_TRY(put_at(b, o.fcase, fo, fcase, s)); HIP_TRY(put_at(b, o.gp_rng, fo, gp_rng, s));
     HIP_TRY(put_at(b, o.bslot, fo, bslot, s));
     HIP_TRY(put_soa(b, o.avec, fo, b->NF, avec, nf, d, s)); HIP_TRY(put_at(b, o.S, fo, S, s));
+    HIP_TRY(put_at(b, o.swp, 4 * fo, swp, s));
     HIP_TRY(put_soa(b, o.shift, fo, b->NF, shift, nf, d, s));
     HIP_TRY(put_soa(b, o.gavg, bo, std::max<int64_t>(b->NB, 1), gavg, nb, nk, s));
     HIP_TRY(put_at(b, o.bface, bo, bface, s));

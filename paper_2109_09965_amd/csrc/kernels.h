@@ -58,7 +58,7 @@ struct Dev {
     // record), Sf, RHS, R1 [nv][NC]
     double *U, *Sf, *RHS, *D, *R1;
     double *lowf;      // [NF][nv]: S_f F_kfvs
-    double *swp;       // [NF][4]: area vector S_f n_f (D values), S_f lam_f
+    double *swp;       // [NF][4]: area vector S_f n_f (D values, set at upload), S_f lam_f (each low-level step)
     // per case
     const DevParams *prm;
     double *dt, *res;
@@ -72,6 +72,13 @@ struct Dev {
 };
 
 template <int D> struct Dim;
+
+// Single-use streams (a cell's own operator and stage arrays, whole-line
+// record writes): non-temporal loads and stores, which leave L2 to the
+// records that neighbours read again.  Not for scattered partial-line
+// writes (the face sums), where they cost far more than they save.
+template <typename T> __device__ __forceinline__ T ld_nt(const T *p) { return __builtin_nontemporal_load(p); }
+template <typename T> __device__ __forceinline__ void st_nt(T v, T *p) { __builtin_nontemporal_store(v, p); }
 
 // precision-dependent arrays of the high-order pass
 template <typename R> struct HoArrays;
@@ -781,7 +788,7 @@ template <int D, typename R> __global__ __launch_bounds__(kReconBlock) void k_re
         for (int v = 0; v < nv; ++v) c[v] = R(0.0);
 #pragma unroll
         for (int j = 0; j < nk; ++j) {
-            const R mkj = minv[size_t(midx<D>(k, j)) * NC + i];
+            const R mkj = ld_nt(minv + size_t(midx<D>(k, j)) * NC + i);
 #pragma unroll
             for (int v = 0; v < nv; ++v) c[v] += mkj * rhs[j][v];
         }
@@ -794,7 +801,7 @@ template <int D, typename R> __global__ __launch_bounds__(kReconBlock) void k_re
     const int total = ncell * Rec<D>::er;
     for (int k = threadIdx.x; k < total; k += kReconBlock) {
         const int c = k / Rec<D>::er, j = k - c * Rec<D>::er;
-        dst[k] = rec_lds[c * ERP + j];
+        st_nt(rec_lds[c * ERP + j], dst + k);
     }
 }
 
@@ -812,25 +819,47 @@ template <> struct Vec16<float> {
     static __device__ __forceinline__ void unpack(const T &t, float *o) { o[0] = t.x; o[1] = t.y; o[2] = t.z; o[3] = t.w; }
 };
 
+// lane p of each group of G lanes (G = 2 or 4, all active) to the whole group
+template <int G, int P> __device__ __forceinline__ int bcast_i32(int x) {
+    constexpr int ctrl = G == 4 ? (P | P << 2 | P << 4 | P << 6) : (P | P << 2 | (P + 2) << 4 | (P + 2) << 6);
+    return __builtin_amdgcn_mov_dpp(x, ctrl, 0xF, 0xF, false);
+}
+template <int G, int P> __device__ __forceinline__ double bcast(double v) {
+    const long long u = __double_as_longlong(v);
+    const int lo = bcast_i32<G, P>(int(u & 0xffffffffll)), hi = bcast_i32<G, P>(int(u >> 32));
+    return __longlong_as_double((long long)(unsigned(lo)) | ((long long)hi << 32));
+}
+template <int G, int P> __device__ __forceinline__ float bcast(float v) {
+    return __int_as_float(bcast_i32<G, P>(__float_as_int(v)));
+}
+template <int G, typename R> __device__ __forceinline__ R bcast_from(R v, int p) {
+    switch (p) {
+        case 0: return bcast<G, 0>(v);
+        case 1: return bcast<G, 1>(v);
+        case 2: return G == 4 ? bcast<G, 2>(v) : v;
+        default: return G == 4 ? bcast<G, 3>(v) : v;
+    }
+}
+
 // Reconstruction of cell i evaluated at x: W(x) into Wx, and its gradient
-// added into G (global frame).  The coefficients are consumed in groups of
-// KG basis functions with a scheduling barrier between groups, so at most
-// one group's loads are in flight: the flux kernel's register peak (and so
-// its occupancy) is set here.
-template <int D, typename R> __device__ __forceinline__ void recon_eval(const Dev &d, int i, const R *x, R *Wx,
+// added into G (global frame).  The G lanes of a face group share the
+// record: lane q loads values [q er/G, (q+1) er/G) and every value reaches
+// the group by a quad-permute broadcast, so the record crosses the memory
+// pipeline once per face instead of once per Gauss point.
+template <int D, typename R> __device__ __forceinline__ void recon_eval(const Dev &d, int i, int q, const R *x, R *Wx,
                                                                         R G[D][D + 2]) {
     using T = Dim<D>;
     using RC = Rec<D>;
-    using V = Vec16<R>;
-    constexpr int nv = T::nv, nq = T::nq, KG = 3;
-    const R *base = HoArrays<R>::ev(d) + size_t(i) * RC::er;
-    const typename V::T *rv = reinterpret_cast<const typename V::T *>(base);
-    constexpr int NV = RC::OC / V::n;
+    constexpr int nv = T::nv, nq = T::nq, KG = 3, GL = T::lanes, PL = RC::er / GL;
+    static_assert(RC::er % GL == 0, "record splits evenly over the face lanes");
+    const R *base = HoArrays<R>::ev(d) + size_t(i) * RC::er + q * PL;
+    R mine[PL];
+#pragma unroll
+    for (int m = 0; m < PL; ++m) mine[m] = base[m];
+#define CGKS_REC(j) bcast_from<GL, R>(mine[(j) % PL], (j) / PL)
     R r[RC::OC];
 #pragma unroll
-    for (int k = 0; k < NV; ++k) V::unpack(rv[k], r + V::n * k);
-#pragma unroll
-    for (int k = NV * V::n; k < RC::OC; ++k) r[k] = base[k];
+    for (int k = 0; k < RC::OC; ++k) r[k] = CGKS_REC(k);
     const R ih = r[D];
     R y[D], yh[D];
 #pragma unroll
@@ -840,29 +869,29 @@ template <int D, typename R> __device__ __forceinline__ void recon_eval(const De
     }
 #pragma unroll
     for (int v = 0; v < nv; ++v) Wx[v] = r[RC::OW + v];
-    const R *c = base + RC::OC;
 #pragma unroll
     for (int k = 0; k < D + nq; ++k) {
         if (k % KG == 0 && k > 0) __builtin_amdgcn_sched_barrier(0);
         if (k < D) {
 #pragma unroll
             for (int v = 0; v < nv; ++v) {
-                const R ck = c[k * nv + v];
+                const R ck = CGKS_REC(RC::OC + k * nv + v);
                 Wx[v] += ck * y[k];
                 G[k][v] += ck * ih;
             }
         } else {
-            const int q = k - D, a = qa<D>(q), b = qb<D>(q);
-            const R phi = y[a] * y[b] - r[D + 1 + q];
+            const int qq = k - D, a = qa<D>(qq), b = qb<D>(qq);
+            const R phi = y[a] * y[b] - r[D + 1 + qq];
 #pragma unroll
             for (int v = 0; v < nv; ++v) {
-                const R ck = c[k * nv + v];
+                const R ck = CGKS_REC(RC::OC + k * nv + v);
                 Wx[v] += ck * phi;
                 G[a][v] += ck * yh[b];
                 G[b][v] += ck * yh[a];
             }
         }
     }
+#undef CGKS_REC
 }
 
 // ---------------------------------------------------------------------
@@ -954,7 +983,7 @@ template <int D, typename R> __global__ __launch_bounds__(kBlock) void k_flux(De
             for (int v = 0; v < nv; ++v) Gs[a][v] = R(0.0);
         {
             R Wg[nv];
-            recon_eval<D, R>(d, cL, x, Wg, Gs);
+            recon_eval<D, R>(d, cL, q, x, Wg, Gs);
             fr.to_local(Wg, WL);
         }
         if (cR >= 0 || bc != 2) {
@@ -963,7 +992,7 @@ template <int D, typename R> __global__ __launch_bounds__(kBlock) void k_flux(De
                 R xr[D], WRg[nv];
 #pragma unroll
                 for (int a = 0; a < D; ++a) xr[a] = x[a] - R(d.shift[size_t(a) * d.NF + f]);
-                recon_eval<D, R>(d, cR, xr, WRg, Gs);
+                recon_eval<D, R>(d, cR, q, xr, WRg, Gs);
                 fr.to_local(WRg, WR);
             } else if (bc == 1) {
                 // mirror: normal momentum reversed
@@ -1119,19 +1148,19 @@ template <int D, typename R> __global__ __launch_bounds__(kBlock) void k_cell(De
 #pragma unroll
         for (int v = 0; v < nv; ++v) {
             if (mode == MODE_R1) {
-                d.R1[size_t(v) * NC + i] = -(acc[v] + 0.5 * dt * acc[nv + v]);
+                st_nt(-(acc[v] + 0.5 * dt * acc[nv + v]), d.R1 + size_t(v) * NC + i);
                 continue;
             }
             const double L = -acc[v] / V, Lt = -acc[nv + v] / V;
             if (mode == MODE_STAGE0) {
                 const double w = si[v];
-                d.Wn[size_t(v) * NC + i] = w;
-                d.L0[size_t(v) * NC + i] = L;
-                d.Lt0[size_t(v) * NC + i] = Lt;
+                st_nt(w, d.Wn + size_t(v) * NC + i);
+                st_nt(L, d.L0 + size_t(v) * NC + i);
+                st_nt(Lt, d.Lt0 + size_t(v) * NC + i);
                 si[v] = P.scheme == 0 ? w + 0.5 * dt * L + 0.125 * dt * dt * Lt : w + dt * L + 0.5 * dt * dt * Lt;
             } else {
-                si[v] = d.Wn[size_t(v) * NC + i] + dt * d.L0[size_t(v) * NC + i] +
-                        dt * dt / 6.0 * (d.Lt0[size_t(v) * NC + i] + 2.0 * Lt);
+                si[v] = ld_nt(d.Wn + size_t(v) * NC + i) + dt * ld_nt(d.L0 + size_t(v) * NC + i) +
+                        dt * dt / 6.0 * (ld_nt(d.Lt0 + size_t(v) * NC + i) + 2.0 * Lt);
             }
         }
         return;
@@ -1142,10 +1171,10 @@ template <int D, typename R> __global__ __launch_bounds__(kBlock) void k_cell(De
         const size_t k = size_t(a * nv + v) * NC + i;
         const double G = acc[v] / V, Gt = acc[nv + v] / V;
         if (mode == MODE_STAGE0) {
-            d.G0[k] = G;
+            st_nt(G, d.G0 + k);
             si[nv + a * nv + v] = P.scheme == 0 ? G + 0.5 * dt * Gt : G + dt * Gt;
         } else {
-            si[nv + a * nv + v] = d.G0[k] + dt * Gt;
+            si[nv + a * nv + v] = ld_nt(d.G0 + k) + dt * Gt;
         }
     }
 }
@@ -1185,7 +1214,7 @@ template <int D, typename S> __device__ __forceinline__ void low_state(const Dev
     }
 }
 
-// lowf[f] = S_f F_kfvs(U_L, U_R; n_f); swp[f] = (S_f n_f, S_f lam_f).
+// lowf[f] = S_f F_kfvs(U_L, U_R; n_f); swp[f][D] = S_f lam_f.
 template <int D, typename S> __global__ __launch_bounds__(kBlock) void k_low_face(Dev d, int src) {
     constexpr int nv = D + 2;
     const int f = xcd_block(blockIdx.x, gridDim.x) * int(blockDim.x) + threadIdx.x;
@@ -1234,10 +1263,7 @@ template <int D, typename S> __global__ __launch_bounds__(kBlock) void k_low_fac
     fr.to_global(Fl, F);
 #pragma unroll
     for (int v = 0; v < nv; ++v) d.lowf[size_t(f) * nv + v] = ok ? Sf * F[v] : 0.0;
-    double *w = d.swp + size_t(f) * 4;
-#pragma unroll
-    for (int a = 0; a < D; ++a) w[a] = d.avec[size_t(a) * d.NF + f];
-    w[D] = Sf * lam;
+    d.swp[size_t(f) * 4 + D] = Sf * lam;   // the area vector part is written at upload
 }
 
 enum { LOW_FORCE = 0, LOW_STEP_FIRST = 1, LOW_STEP = 2, LOW_R0_OUT = 3 };
