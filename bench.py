@@ -125,16 +125,14 @@ def algorithmic_bytes(mesh, lm, rbytes, sbytes=8):
     out["cell"] = ((st0 + st1 + r1) / 3.0, 3)
     own, nb = mesh["face_owner"], mesh["face_neigh"]
     nint = NF - NB
-    lf_common = NF * (4 * 3 + 8 + 8 * d) + 8 * NF * (nv + d + 1)   # indices, S, avec; lowf, swp writes
+    lf_common = NF * (4 * 3 + 8 + 8 * d) + 8 * NF * (nv + 1)      # indices, S, avec; lowf, S lam writes
     lf_force = lf_common + 8 * nv * (NF + nint)                   # W of both sides
-    lf_first = lf_force
     lf_step = lf_common + (8 + sbytes) * nv * (NF + nint)         # U and dU of both sides
-    out["low_face"] = ((lf_force + lf_first + 5 * lf_step) / 7.0, 7)
+    out["low_face"] = ((lf_force + 5 * lf_step) / 6.0, 6)         # the first step reuses the forcing's
     lc_common = NC * (8 * ns + 4) + NF * 8 * (nv + 1)
-    lc_force = lc_common + NC * (8 * 4 * nv + sbytes * nv)        # R1, W; Sf, U; dU
-    lc_first = lc_common + NC * (8 * (4 * nv + 2 + 1) + sbytes * nv)   # U, Sf; U, RHS; vol, h; D; dU
-    lc_step = lc_first + NC * sbytes * nv                         # + dU read
-    out["low_cell"] = ((lc_force + lc_first + 5 * lc_step) / 7.0, 7)
+    lc_force = lc_common + NC * (8 * (5 * nv + 2 + 1) + sbytes * nv)   # R1, W; Sf, U, RHS; vol, h; D; dU
+    lc_step = lc_common + NC * (8 * (4 * nv + 2 + 1) + 2 * sbytes * nv)  # U, Sf; U, RHS; vol, h; D; dU r/w
+    out["low_cell"] = ((lc_force + 5 * lc_step) / 6.0, 6)
     # sweeps, per colour class c: per cell of c its slots, case, RHS, D and
     # the dU write; the face record of every interior face of c (faces of an
     # independent set are distinct); the U, dU record of every distinct

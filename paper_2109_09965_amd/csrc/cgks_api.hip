@@ -377,14 +377,17 @@ template <int D, typename S> cgks_status launch_lowlevel_s(cgks_batch *b, const 
     });
     const std::vector<int> order = sweep_order(b->max_colour, b->n_sweeps);
     for (int k = 0; k < b->n_implicit; ++k) {
-        timed(b, CGKS_K_LOWFACE, s, [&] {
-            hipLaunchKernelGGL((k_low_face<D, S>), dim3(nblk(b->hwF, b->blk_face)), dim3(b->blk_face), 0, s, d,
-                               (int)(k ? LOW_SRC_U_DU : LOW_SRC_U));
-        });
-        timed(b, CGKS_K_LOWCELL, s, [&] {
-            hipLaunchKernelGGL((k_low_cell<D, S>), dim3(nblk(b->hwC * Dim<D>::sl, b->blk_lcell)), dim3(b->blk_lcell),
-                               0, s, d, (int)(k ? LOW_STEP : LOW_STEP_FIRST), (double *)nullptr);
-        });
+        // the first step starts at U = W: its set-up came with the forcing
+        if (k > 0) {
+            timed(b, CGKS_K_LOWFACE, s, [&] {
+                hipLaunchKernelGGL((k_low_face<D, S>), dim3(nblk(b->hwF, b->blk_face)), dim3(b->blk_face), 0, s, d,
+                                   (int)LOW_SRC_U_DU);
+            });
+            timed(b, CGKS_K_LOWCELL, s, [&] {
+                hipLaunchKernelGGL((k_low_cell<D, S>), dim3(nblk(b->hwC * Dim<D>::sl, b->blk_lcell)),
+                                   dim3(b->blk_lcell), 0, s, d, (int)LOW_STEP, (double *)nullptr);
+            });
+        }
         // the colour passes of one step run back to back: one timing span
         int n_pass = 0;
         for (int c : order) n_pass += b->colour_blk_off[c + 1] > b->colour_blk_off[c];
@@ -1155,12 +1158,10 @@ template <int D, typename R, typename S> static cgks_status autotune_t(cgks_batc
                            (int)LOW_R0_OUT, d.Sf);
     });
     // low-level work arrays from the current state, then the sweep chunk
+    hipLaunchKernelGGL((k_low_face<D, S>), dim3(nblk(b->hwF, b->blk_face)), dim3(b->blk_face), 0, s, d,
+                       (int)LOW_SRC_W);
     hipLaunchKernelGGL((k_low_cell<D, S>), dim3(nblk(b->hwC * Dim<D>::sl, b->blk_lcell)), dim3(b->blk_lcell), 0, s, d,
                        (int)LOW_FORCE, (double *)nullptr);
-    hipLaunchKernelGGL((k_low_face<D, S>), dim3(nblk(b->hwF, b->blk_face)), dim3(b->blk_face), 0, s, d,
-                       (int)LOW_SRC_U);
-    hipLaunchKernelGGL((k_low_cell<D, S>), dim3(nblk(b->hwC * Dim<D>::sl, b->blk_lcell)), dim3(b->blk_lcell), 0, s, d,
-                       (int)LOW_STEP_FIRST, (double *)nullptr);
     static const int chunks[3] = {64, 32, 16};
     cgks_status st = CGKS_OK;
     const std::vector<int> order = sweep_order(b->max_colour, b->n_sweeps);

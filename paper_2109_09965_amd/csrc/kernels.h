@@ -1198,9 +1198,9 @@ template <int D> __device__ __forceinline__ double side_radius(const double *U, 
     return fabs(un) + sqrt(P.gamma * p / rho) + 2.0 * P.mu / rho * Sf / V;
 }
 
-enum { LOW_SRC_W = 0, LOW_SRC_U = 1, LOW_SRC_U_DU = 2 };
+enum { LOW_SRC_W = 0, LOW_SRC_U_DU = 2 };
 
-// state of cell i: W from the state records, the low-level U, or U + dU
+// state of cell i: W from the state records, or the low-level U + dU
 template <int D, typename S> __device__ __forceinline__ void low_state(const Dev &d, int src, int i, double *out) {
     constexpr int nv = D + 2;
     if (src == LOW_SRC_W) {
@@ -1266,7 +1266,10 @@ template <int D, typename S> __global__ __launch_bounds__(kBlock) void k_low_fac
     d.swp[size_t(f) * 4 + D] = Sf * lam;   // the area vector part is written at upload
 }
 
-enum { LOW_FORCE = 0, LOW_STEP_FIRST = 1, LOW_STEP = 2, LOW_R0_OUT = 3 };
+// LOW_FORCE: forcing S = R1 - R0(W), U = W, and the first implicit step's
+// set-up at U = W (its KFVS fluxes are the ones R0(W) was gathered from);
+// LOW_STEP: U += dU and the next step's set-up; LOW_R0_OUT: R0 only.
+enum { LOW_FORCE = 0, LOW_STEP = 2, LOW_R0_OUT = 3 };
 
 template <int D, typename S> __global__ __launch_bounds__(kBlock) void k_low_cell(Dev d, int mode, double *out) {
     using T = Dim<D>;
@@ -1305,26 +1308,30 @@ template <int D, typename S> __global__ __launch_bounds__(kBlock) void k_low_cel
             if (v % SL == q) out[size_t(v) * NC + i] = R0[v];
         return;
     }
+    double u[nv];
     if (mode == LOW_FORCE) {
+#pragma unroll
+        for (int v = 0; v < nv; ++v) u[v] = d.st[size_t(i) * Rec<D>::sr + v];
 #pragma unroll
         for (int v = 0; v < nv; ++v)
             if (v % SL == q) {
-                d.Sf[size_t(v) * NC + i] = d.R1[size_t(v) * NC + i] - R0[v];
-                Ui[v] = d.st[size_t(i) * Rec<D>::sr + v];
+                const double sf = d.R1[size_t(v) * NC + i] - R0[v];
+                d.Sf[size_t(v) * NC + i] = sf;
+                Ui[v] = u[v];
+                d.RHS[size_t(v) * NC + i] = R0[v] + sf;
                 dUi[v] = S(0);
             }
-        return;
+    } else {
+#pragma unroll
+        for (int v = 0; v < nv; ++v) u[v] = Ui[v] + double(dUi[v]);
+#pragma unroll
+        for (int v = 0; v < nv; ++v)
+            if (v % SL == q) {
+                Ui[v] = u[v];
+                d.RHS[size_t(v) * NC + i] = R0[v] + d.Sf[size_t(v) * NC + i];
+                dUi[v] = S(0);
+            }
     }
-    double u[nv];
-#pragma unroll
-    for (int v = 0; v < nv; ++v) u[v] = mode == LOW_STEP ? Ui[v] + double(dUi[v]) : Ui[v];
-#pragma unroll
-    for (int v = 0; v < nv; ++v)
-        if (v % SL == q) {
-            Ui[v] = u[v];
-            d.RHS[size_t(v) * NC + i] = R0[v] + d.Sf[size_t(v) * NC + i];
-            dUi[v] = S(0);
-        }
     if (q == 0) d.D[i] = d.vol[i] / state_dt<D>(u, d.h[i], P.cfl_low, P) + 0.5 * lS;
 }
 
