@@ -372,8 +372,8 @@ template <int D, typename S> cgks_status launch_lowlevel_s(cgks_batch *b, const 
                            (int)LOW_SRC_W);
     });
     timed(b, CGKS_K_LOWCELL, s, [&] {
-        hipLaunchKernelGGL((k_low_cell<D, S>), dim3(nblk(b->hwC * Dim<D>::sl, b->blk_lcell)), dim3(b->blk_lcell), 0,
-                           s, d, (int)LOW_FORCE, (double *)nullptr);
+        hipLaunchKernelGGL((k_low_cell<D, S, LOW_FORCE>), dim3(nblk(b->hwC * Dim<D>::sl, b->blk_lcell)),
+                           dim3(b->blk_lcell), 0, s, d, (double *)nullptr);
     });
     const std::vector<int> order = sweep_order(b->max_colour, b->n_sweeps);
     for (int k = 0; k < b->n_implicit; ++k) {
@@ -384,8 +384,8 @@ template <int D, typename S> cgks_status launch_lowlevel_s(cgks_batch *b, const 
                                    (int)LOW_SRC_U_DU);
             });
             timed(b, CGKS_K_LOWCELL, s, [&] {
-                hipLaunchKernelGGL((k_low_cell<D, S>), dim3(nblk(b->hwC * Dim<D>::sl, b->blk_lcell)),
-                                   dim3(b->blk_lcell), 0, s, d, (int)LOW_STEP, (double *)nullptr);
+                hipLaunchKernelGGL((k_low_cell<D, S, LOW_STEP>), dim3(nblk(b->hwC * Dim<D>::sl, b->blk_lcell)),
+                                   dim3(b->blk_lcell), 0, s, d, (double *)nullptr);
             });
         }
         // the colour passes of one step run back to back: one timing span
@@ -974,13 +974,13 @@ cgks_status cgks_residual(cgks_batch *b, int32_t kind, double *out, void *stream
         if (b->dim == 2) {
             hipLaunchKernelGGL((k_low_face<2, double>), dim3(nblk(b->hwF)), dim3(kBlock), 0, s, b->dev,
                                (int)LOW_SRC_W);
-            hipLaunchKernelGGL((k_low_cell<2, double>), dim3(nblk(b->hwC * Dim<2>::sl)), dim3(kBlock), 0, s, b->dev,
-                               (int)LOW_R0_OUT, out);
+            hipLaunchKernelGGL((k_low_cell<2, double, LOW_R0_OUT>), dim3(nblk(b->hwC * Dim<2>::sl)), dim3(kBlock), 0,
+                               s, b->dev, out);
         } else {
             hipLaunchKernelGGL((k_low_face<3, double>), dim3(nblk(b->hwF)), dim3(kBlock), 0, s, b->dev,
                                (int)LOW_SRC_W);
-            hipLaunchKernelGGL((k_low_cell<3, double>), dim3(nblk(b->hwC * Dim<3>::sl)), dim3(kBlock), 0, s, b->dev,
-                               (int)LOW_R0_OUT, out);
+            hipLaunchKernelGGL((k_low_cell<3, double, LOW_R0_OUT>), dim3(nblk(b->hwC * Dim<3>::sl)), dim3(kBlock), 0,
+                               s, b->dev, out);
         }
         HIP_TRY(hipGetLastError());
         return CGKS_OK;
@@ -1154,14 +1154,14 @@ template <int D, typename R, typename S> static cgks_status autotune_t(cgks_batc
         hipLaunchKernelGGL((k_low_face<D, S>), dim3(nblk(b->hwF, blk)), dim3(blk), 0, s, d, (int)LOW_SRC_W);
     });
     b->blk_lcell = pick(blocks, 3, [&](int blk) {
-        hipLaunchKernelGGL((k_low_cell<D, S>), dim3(nblk(b->hwC * Dim<D>::sl, blk)), dim3(blk), 0, s, d,
-                           (int)LOW_R0_OUT, d.Sf);
+        hipLaunchKernelGGL((k_low_cell<D, S, LOW_R0_OUT>), dim3(nblk(b->hwC * Dim<D>::sl, blk)), dim3(blk), 0, s, d,
+                           d.Sf);
     });
     // low-level work arrays from the current state, then the sweep chunk
     hipLaunchKernelGGL((k_low_face<D, S>), dim3(nblk(b->hwF, b->blk_face)), dim3(b->blk_face), 0, s, d,
                        (int)LOW_SRC_W);
-    hipLaunchKernelGGL((k_low_cell<D, S>), dim3(nblk(b->hwC * Dim<D>::sl, b->blk_lcell)), dim3(b->blk_lcell), 0, s, d,
-                       (int)LOW_FORCE, (double *)nullptr);
+    hipLaunchKernelGGL((k_low_cell<D, S, LOW_FORCE>), dim3(nblk(b->hwC * Dim<D>::sl, b->blk_lcell)), dim3(b->blk_lcell),
+                       0, s, d, (double *)nullptr);
     static const int chunks[3] = {64, 32, 16};
     cgks_status st = CGKS_OK;
     const std::vector<int> order = sweep_order(b->max_colour, b->n_sweeps);

@@ -11,6 +11,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstddef>
 #include <cstdint>
 #include <type_traits>
 
@@ -19,15 +20,26 @@ namespace cgks {
 constexpr int kBlock = 256;
 
 struct DevParams {
-    double gamma, mu, Pr, T_wall;
+    double gamma;
+    int32_t active;    // 0: the case is frozen (finished), kernels leave it untouched
+    int32_t scheme;    // 0 S2O4, 1 S1O2
+    // (gamma and active share the first 16 bytes: a gather kernel reads them
+    // with one load, so the flag arrives with the value its arithmetic needs)
+    double mu, Pr, T_wall;
     double W_inf[5];
     double cfl_high, cfl_low, dt_fixed;
     double K;          // internal degrees of freedom of the gas
-    int32_t scheme;    // 0 S2O4, 1 S1O2
     int32_t explicit_only;
-    int32_t active;    // 0: the case is frozen (finished), kernels leave it untouched
     int32_t pad;
 };
+static_assert(offsetof(DevParams, active) == 8, "gamma and active in the first 16 bytes");
+
+// gamma and the active flag of a case with one 16-byte load
+__device__ __forceinline__ void gamma_active(const DevParams &P, double &gamma, bool &active) {
+    const int4 g = *reinterpret_cast<const int4 *>(&P);
+    gamma = __longlong_as_double((long long)(unsigned(g.x)) | ((long long)g.y << 32));
+    active = g.z != 0;
+}
 
 struct Dev {
     int32_t NC, NF, NG, NB;   // NB >= 1 (array extent); NB_real boundary faces
@@ -1129,15 +1141,36 @@ template <int D, typename R> __global__ __launch_bounds__(kBlock) void k_cell(De
 #pragma unroll
     for (int k = 0; k < GW; ++k) acc[k] = 0.0;
     if (mine) {
-#pragma unroll 1
-        for (int s = 0; s < T::ns; ++s) {
-            const int code = d.slot[size_t(s) * NC + i].x;
-            if (code == 0) break;
-            const int f = (code > 0 ? code : -code) - 1;
-            const double sg = code > 0 ? 1.0 : -1.0;
-            const R *src = HoArrays<R>::fsum(d) + size_t(f) * T::fs + q * GW;
+        if constexpr (std::is_same<R, float>::value) {
+            // FP32 face records: every slot code first, then all face
+            // groups at once; an empty slot reads face 0 with weight 0 (face
+            // sums are always finite: a non-physical Gauss point contributes
+            // zeros).  -6 % on the sphere; with FP64 records the loads in
+            // flight cost the kernel its occupancy (+7 %), so FP64 gathers
+            // slot by slot.
+            int code[T::ns];
 #pragma unroll
-            for (int k = 0; k < GW; ++k) acc[k] += sg * double(src[k]);
+            for (int s = 0; s < T::ns; ++s) code[s] = d.slot[size_t(s) * NC + i].x;
+#pragma unroll
+            for (int s = 0; s < T::ns; ++s) {
+                const bool has = code[s] != 0;
+                const int f = has ? (code[s] > 0 ? code[s] : -code[s]) - 1 : 0;
+                const double sg = has ? (code[s] > 0 ? 1.0 : -1.0) : 0.0;
+                const R *src = HoArrays<R>::fsum(d) + size_t(f) * T::fs + q * GW;
+#pragma unroll
+                for (int k = 0; k < GW; ++k) acc[k] += sg * double(src[k]);
+            }
+        } else {
+#pragma unroll 1
+            for (int s = 0; s < T::ns; ++s) {
+                const int code = d.slot[size_t(s) * NC + i].x;
+                if (code == 0) break;
+                const int f = (code > 0 ? code : -code) - 1;
+                const double sg = code > 0 ? 1.0 : -1.0;
+                const R *src = HoArrays<R>::fsum(d) + size_t(f) * T::fs + q * GW;
+#pragma unroll
+                for (int k = 0; k < GW; ++k) acc[k] += sg * double(src[k]);
+            }
         }
     }
     if (!ok || !mine) return;
@@ -1271,51 +1304,73 @@ template <int D, typename S> __global__ __launch_bounds__(kBlock) void k_low_fac
 // LOW_STEP: U += dU and the next step's set-up; LOW_R0_OUT: R0 only.
 enum { LOW_FORCE = 0, LOW_STEP = 2, LOW_R0_OUT = 3 };
 
-template <int D, typename S> __global__ __launch_bounds__(kBlock) void k_low_cell(Dev d, int mode, double *out) {
+template <int D, typename S, int MODE> __global__ __launch_bounds__(kBlock) void k_low_cell(Dev d, double *out) {
+    constexpr int mode = MODE;
     using T = Dim<D>;
-    constexpr int nv = T::nv, SL = T::sl;
+    constexpr int nv = T::nv, SL = T::sl, NS = T::ns / SL;   // slots per lane
     const int t = xcd_block(blockIdx.x, gridDim.x) * int(blockDim.x) + threadIdx.x;
     const int ir = t / SL, q = t % SL;
     const bool ok = ir < d.NC;
     const int i = ok ? ir : d.NC - 1;
     const int NC = d.NC;
+    // all slot codes first, then every face record at once, the case flag
+    // with gamma, and the cell's own inputs of the mode.  An empty slot reads
+    // face 0: its KFVS flux enters with weight 0 (lowf is always finite: a
+    // non-physical face stores zeros), its S lam through a select (that one
+    // may not be finite).  A select of the flux itself would become a branch
+    // around each load.
+    int code[NS];
+#pragma unroll
+    for (int k = 0; k < NS; ++k) code[k] = d.slot[size_t(q + k * SL) * NC + i].x;
     const DevParams &P = d.prm[d.cell_case[i]];
-    if (!P.active) return;   // the cell's lane group leaves together
+    double gamma;
+    bool active;
+    gamma_active(P, gamma, active);
+    (void)gamma;
+    double *Ui = LowRec<D, S>::U(d, i);
+    S *dUi = LowRec<D, S>::dU(d, i);
+    double u[nv], own[nv];   // state of the step; Sf (steps) or R1 (forcing) of this lane's variables
+    if constexpr (mode == LOW_FORCE) {
+#pragma unroll
+        for (int v = 0; v < nv; ++v) u[v] = d.st[size_t(i) * Rec<D>::sr + v];
+#pragma unroll
+        for (int v = 0; v < nv; ++v) own[v] = v % SL == q ? d.R1[size_t(v) * NC + i] : 0.0;
+    } else if constexpr (mode == LOW_STEP) {
+#pragma unroll
+        for (int v = 0; v < nv; ++v) u[v] = Ui[v] + double(dUi[v]);
+#pragma unroll
+        for (int v = 0; v < nv; ++v) own[v] = v % SL == q ? d.Sf[size_t(v) * NC + i] : 0.0;
+    }
+    const double Vi = d.vol[i], hi = d.h[i];
     double R0[nv], lS = 0.0;
 #pragma unroll
     for (int v = 0; v < nv; ++v) R0[v] = 0.0;
 #pragma unroll
-    for (int s = q; s < T::ns; s += SL) {
-        const int code = d.slot[size_t(s) * NC + i].x;
-        if (code != 0) {
-            const int f = (code > 0 ? code : -code) - 1;
-            const double sg = code > 0 ? 1.0 : -1.0;
-            const double *lf = d.lowf + size_t(f) * nv;
+    for (int k = 0; k < NS; ++k) {
+        const bool has = code[k] != 0;
+        const int f = has ? (code[k] > 0 ? code[k] : -code[k]) - 1 : 0;
+        const double sg = has ? (code[k] > 0 ? 1.0 : -1.0) : 0.0;
+        const double *lf = d.lowf + size_t(f) * nv;
+        const double sl_lam = d.swp[size_t(f) * 4 + D];
 #pragma unroll
-            for (int v = 0; v < nv; ++v) R0[v] -= sg * lf[v];
-            lS += d.swp[size_t(f) * 4 + D];
-        }
+        for (int v = 0; v < nv; ++v) R0[v] -= sg * lf[v];
+        lS += has ? sl_lam : 0.0;
     }
 #pragma unroll
     for (int v = 0; v < nv; ++v) R0[v] = group_sum<SL, double>(R0[v]);
     lS = group_sum<SL, double>(lS);
-    if (!ok || !P.active) return;
-    double *Ui = LowRec<D, S>::U(d, i);
-    S *dUi = LowRec<D, S>::dU(d, i);
-    if (mode == LOW_R0_OUT) {
+    if (!ok || !active) return;   // the cell's lane group leaves together
+    if constexpr (mode == LOW_R0_OUT) {
 #pragma unroll
         for (int v = 0; v < nv; ++v)
             if (v % SL == q) out[size_t(v) * NC + i] = R0[v];
         return;
     }
-    double u[nv];
-    if (mode == LOW_FORCE) {
-#pragma unroll
-        for (int v = 0; v < nv; ++v) u[v] = d.st[size_t(i) * Rec<D>::sr + v];
+    if constexpr (mode == LOW_FORCE) {
 #pragma unroll
         for (int v = 0; v < nv; ++v)
             if (v % SL == q) {
-                const double sf = d.R1[size_t(v) * NC + i] - R0[v];
+                const double sf = own[v] - R0[v];
                 d.Sf[size_t(v) * NC + i] = sf;
                 Ui[v] = u[v];
                 d.RHS[size_t(v) * NC + i] = R0[v] + sf;
@@ -1323,16 +1378,14 @@ template <int D, typename S> __global__ __launch_bounds__(kBlock) void k_low_cel
             }
     } else {
 #pragma unroll
-        for (int v = 0; v < nv; ++v) u[v] = Ui[v] + double(dUi[v]);
-#pragma unroll
         for (int v = 0; v < nv; ++v)
             if (v % SL == q) {
                 Ui[v] = u[v];
-                d.RHS[size_t(v) * NC + i] = R0[v] + d.Sf[size_t(v) * NC + i];
+                d.RHS[size_t(v) * NC + i] = R0[v] + own[v];
                 dUi[v] = S(0);
             }
     }
-    if (q == 0) d.D[i] = d.vol[i] / state_dt<D>(u, d.h[i], P.cfl_low, P) + 0.5 * lS;
+    if (q == 0) d.D[i] = Vi / state_dt<D>(u, hi, P.cfl_low, P) + 0.5 * lS;
 }
 
 // one colour class: blocks listed in (start, count) tables.  With A = s S_f n_f
@@ -1343,42 +1396,76 @@ template <int D, typename S> __global__ __launch_bounds__(kBlock) void k_low_cel
 template <int D, typename S>
 __global__ __launch_bounds__(kBlock) void k_sweep(Dev d, const int32_t *blk_start, const int32_t *blk_count) {
     using T = Dim<D>;
-    constexpr int nv = T::nv, SL = T::sl;
+    constexpr int nv = T::nv, SL = T::sl, NS = T::ns / SL;   // slots per lane
     const int b = xcd_block(blockIdx.x, gridDim.x);
     const int lc = threadIdx.x / SL, q = threadIdx.x % SL;
     const bool ok = lc < blk_count[b];
     const int i = blk_start[b] + (ok ? lc : 0);
     const int NC = d.NC;
-    const DevParams &P = d.prm[d.cell_case[i]];
     S acc[nv];
 #pragma unroll
     for (int v = 0; v < nv; ++v) acc[v] = S(0);
+    if constexpr (std::is_same<S, double>::value) {
+        // FP64: everything this lane reads is addressed up front, so both
+        // slots, both neighbour records and the cell's own RHS and D are in
+        // flight together.  A slot without a neighbour reads the cell's own
+        // record and face 0, and a select (not a product: those records may
+        // hold anything) drops it.  The lane's RHS values are loaded without
+        // a select (a select of a load becomes a branch around it): its own
+        // variable q and the last one, which lane 0 owns when nv > SL.
+        int2 sl[NS];
 #pragma unroll
-    for (int s = q; s < T::ns; s += SL) {
-        const int2 sl = d.slot[size_t(s) * NC + i];
-        if (sl.x != 0 && sl.y >= 0) {
-            const int nb = sl.y;
-            const int f = (sl.x > 0 ? sl.x : -sl.x) - 1;
-            const double sg = sl.x > 0 ? 1.0 : -1.0;
+        for (int k = 0; k < NS; ++k) sl[k] = d.slot[size_t(q + k * SL) * NC + i];
+        double gamma;
+        bool active;
+        gamma_active(d.prm[d.cell_case[i]], gamma, active);
+        const double Di = d.D[i];
+        const double rhs_q = d.RHS[size_t(q) * NC + i], rhs_last = d.RHS[size_t(nv - 1) * NC + i];
+#pragma unroll
+        for (int k = 0; k < NS; ++k) {
+            const bool has = (sl[k].x != 0) & (sl[k].y >= 0);
+            const int nb = has ? sl[k].y : i;
+            const int f = has ? (sl[k].x > 0 ? sl[k].x : -sl[k].x) - 1 : 0;
+            const double sg = sl[k].x > 0 ? 1.0 : -1.0;
             const double *w = d.swp + size_t(f) * 4;
             const double *Unb = LowRec<D, S>::U(d, nb);
-            const S *dUnb = LowRec<D, S>::dU(d, nb);
-            if constexpr (std::is_same<S, double>::value) {
-                double A[D], Um[nv], dUm[nv], Up[nv], Fa[nv], Fb[nv];
+            const double *dUnb = LowRec<D, S>::dU(d, nb);
+            double A[D], Um[nv], dUm[nv], Up[nv], Fa[nv], Fb[nv];
 #pragma unroll
-                for (int a = 0; a < D; ++a) A[a] = sg * w[a];
-                const double sl_lam = w[D];
+            for (int a = 0; a < D; ++a) A[a] = sg * w[a];
+            const double sl_lam = w[D];
 #pragma unroll
-                for (int v = 0; v < nv; ++v) {
-                    Um[v] = Unb[v];
-                    dUm[v] = dUnb[v];
-                    Up[v] = Um[v] + dUm[v];
-                }
-                euler_flux<D>(Up, A, P.gamma, Fa);
-                euler_flux<D>(Um, A, P.gamma, Fb);
+            for (int v = 0; v < nv; ++v) {
+                Um[v] = Unb[v];
+                dUm[v] = dUnb[v];
+                Up[v] = Um[v] + dUm[v];
+            }
+            euler_flux<D>(Up, A, gamma, Fa);
+            euler_flux<D>(Um, A, gamma, Fb);
 #pragma unroll
-                for (int v = 0; v < nv; ++v) acc[v] += 0.5 * (Fa[v] - Fb[v]) - 0.5 * sl_lam * dUm[v];
-            } else {
+            for (int v = 0; v < nv; ++v) acc[v] += has ? 0.5 * (Fa[v] - Fb[v]) - 0.5 * sl_lam * dUm[v] : 0.0;
+        }
+#pragma unroll
+        for (int v = 0; v < nv; ++v) acc[v] = group_sum<SL, S>(acc[v]);
+        if (!ok || !active) return;
+        double *dUi = LowRec<D, S>::dU(d, i);
+#pragma unroll
+        for (int v = 0; v < nv; ++v)
+            if (v % SL == q) dUi[v] = ((v < SL ? rhs_q : rhs_last) - acc[v]) / Di;
+    } else {
+        // FP32 (lighter records): slot by slot, the loads guarded by the
+        // slot's test, faster here than addressing everything up front
+        const DevParams &P = d.prm[d.cell_case[i]];
+#pragma unroll
+        for (int s = q; s < T::ns; s += SL) {
+            const int2 sl = d.slot[size_t(s) * NC + i];
+            if (sl.x != 0 && sl.y >= 0) {
+                const int nb = sl.y;
+                const int f = (sl.x > 0 ? sl.x : -sl.x) - 1;
+                const double sg = sl.x > 0 ? 1.0 : -1.0;
+                const double *w = d.swp + size_t(f) * 4;
+                const double *Unb = LowRec<D, S>::U(d, nb);
+                const S *dUnb = LowRec<D, S>::dU(d, nb);
                 float A[D], Um[nv], dUm[nv], dF[nv];
 #pragma unroll
                 for (int a = 0; a < D; ++a) A[a] = float(sg * w[a]);
@@ -1393,15 +1480,15 @@ __global__ __launch_bounds__(kBlock) void k_sweep(Dev d, const int32_t *blk_star
                 for (int v = 0; v < nv; ++v) acc[v] += 0.5f * dF[v] - 0.5f * sl_lam * dUm[v];
             }
         }
+#pragma unroll
+        for (int v = 0; v < nv; ++v) acc[v] = group_sum<SL, S>(acc[v]);
+        if (!ok || !P.active) return;
+        const double Di = d.D[i];
+        S *dUi = LowRec<D, S>::dU(d, i);
+#pragma unroll
+        for (int v = 0; v < nv; ++v)
+            if (v % SL == q) dUi[v] = S((d.RHS[size_t(v) * NC + i] - double(acc[v])) / Di);
     }
-#pragma unroll
-    for (int v = 0; v < nv; ++v) acc[v] = group_sum<SL, S>(acc[v]);
-    if (!ok || !P.active) return;
-    const double Di = d.D[i];
-    S *dUi = LowRec<D, S>::dU(d, i);
-#pragma unroll
-    for (int v = 0; v < nv; ++v)
-        if (v % SL == q) dUi[v] = S((d.RHS[size_t(v) * NC + i] - double(acc[v])) / Di);
 }
 
 // W += (U + dU) - W_p0 (W_p0 = W); partial sums of |rho - rho^n| and rho^n.
