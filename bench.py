@@ -404,7 +404,7 @@ def main():
     ap.add_argument("--no-autotune", action="store_true", help="keep the default launch shapes")
     ap.add_argument("--no-converge", action="store_true", help="skip the run to a 1e-10 residual drop")
     ap.add_argument("--order-tile", type=int, default=0,
-                    help="caller cells per tile of the library cell order (0 = library default)")
+                    help="cells per tile of the library cell order (0 = library default)")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
                     help="only run 5 device-to-device copies of MIB MiB (counter calibration)")
     args = ap.parse_args()

@@ -72,10 +72,11 @@ enum { CGKS_RESIDUAL_HIGH = 0, CGKS_RESIDUAL_LOW = 1, CGKS_RESIDUAL_NORM = 2 };
  * boundary face, whose face_bc is one of the CGKS_BC_* tags.  face_shift
  * (may be NULL) holds, per face, the translation [dim] that carries the
  * neighbour next to the owner across a periodic seam (zero elsewhere).
- * order_tile sets the library cell order: consecutive tiles of order_tile
- * caller cells, each tile colour-major inside (0 = the library default,
- * CGKS_ORDER_TILE_DEFAULT; >= n_cell gives one tile, i.e. the whole mesh
- * colour-major).  Cells of one colour are independent, so the order changes
+ * order_tile sets the library cell order: the cells are put on a Morton
+ * (Z-order) curve of their centroids and cut into tiles of order_tile
+ * consecutive cells, each tile colour-major inside (0 = the library
+ * default, CGKS_ORDER_TILE_DEFAULT; >= n_cell gives one tile, i.e. the
+ * whole mesh colour-major).  Cells of one colour are independent, so the order changes
  * no result beyond the rounding of the residual norm's sum; tiles keep a
  * cell's neighbours close in memory and on one XCD.
  * All arrays are host memory, read during cgks_mesh_create only.
@@ -133,7 +134,8 @@ typedef struct cgks_batch cgks_batch;
    normal at each point, 2 per 2-D edge), cell volumes, centroids and second
    moments, the reconstruction operators, the multicolour classes (greedy,
    smallest free colour, in caller cell order) and the library cell order
-   (tiles of order_tile caller cells, colour-major inside each tile).
+   (tiles of order_tile cells along a Morton curve of the centroids,
+   colour-major inside each tile).
    Host work only.  *out receives a handle (free with cgks_mesh_destroy).
    Errors: CGKS_EINVAL (null/size), CGKS_EMESH, CGKS_ENOMEM. */
 cgks_status cgks_mesh_create(const cgks_mesh_desc *desc, cgks_mesh **out);

@@ -175,8 +175,8 @@ class Mesh:
     """Host-side mesh handle (cgks_mesh_create) from a face-based mesh dict."""
 
     def __init__(self, m: dict, order_tile: int = 0):
-        """order_tile: caller cells per tile of the library cell order
-        (0 = library default)."""
+        """order_tile: cells per tile of the library cell order (tiles cut
+        from a Morton curve of the cell centroids; 0 = library default)."""
         L = lib()
         self.dim = int(m["dim"])
         self.nv = self.dim + 2

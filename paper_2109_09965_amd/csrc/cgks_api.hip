@@ -621,35 +621,38 @@ static cgks_status upload_case(cgks_batch *b, int c, hipStream_t s) {
             const int64_t f = m.cf_face[q];
             const int side = m.cf_side[q];
             const int64_t nbr = side ? m.owner[f] : m.neigh[f];
-            slot[sl * n + l] = make_int2(side ? -int32_t(fo + f + 1) : int32_t(fo + f + 1),
-                                         nbr >= 0 ? int32_t(co + m.caller2lib[nbr]) : -1);
+            const int32_t code = int32_t(fo + m.caller2libf[f] + 1);   // slot order: caller face order
+            slot[sl * n + l] = make_int2(side ? -code : code, nbr >= 0 ? int32_t(co + m.caller2lib[nbr]) : -1);
         }
     }
-    int64_t bcount = 0;
-    for (int64_t f = 0; f < nf; ++f) {
-        fL[f] = int32_t(co + m.caller2lib[m.owner[f]]);
-        fR[f] = m.neigh[f] >= 0 ? int32_t(co + m.caller2lib[m.neigh[f]]) : -1;
-        fbc[f] = m.neigh[f] >= 0 ? 0 : m.bc[f];
-        gp_rng[f] = make_int2(int32_t(go + m.gp_off[f]), int32_t(go + m.gp_off[f + 1]));
-        for (int a = 0; a < d; ++a) {
-            avec[a * nf + f] = m.avec[f * d + a];
-            shift[a * nf + f] = m.shift[f * d + a];
-            swp[4 * f + a] = m.avec[f * d + a];
+    // faces, their Gauss points and boundary slots in the library face order
+    int64_t bcount = 0, gl = 0;
+    for (int64_t lf = 0; lf < nf; ++lf) {
+        const int64_t f = m.libf2caller[lf];
+        fL[lf] = int32_t(co + m.caller2lib[m.owner[f]]);
+        fR[lf] = m.neigh[f] >= 0 ? int32_t(co + m.caller2lib[m.neigh[f]]) : -1;
+        fbc[lf] = m.neigh[f] >= 0 ? 0 : m.bc[f];
+        const int64_t g0 = gl;
+        for (int64_t g = m.gp_off[f]; g < m.gp_off[f + 1]; ++g, ++gl) {
+            for (int a = 0; a < d; ++a) {
+                gx[a * ng + gl] = m.gx[g * d + a];
+                gn[a * ng + gl] = m.gn[g * d + a];
+            }
+            gw[gl] = m.gw[g];
         }
-        S[f] = m.S[f];
+        gp_rng[lf] = make_int2(int32_t(go + g0), int32_t(go + gl));
+        for (int a = 0; a < d; ++a) {
+            avec[a * nf + lf] = m.avec[f * d + a];
+            shift[a * nf + lf] = m.shift[f * d + a];
+            swp[4 * lf + a] = m.avec[f * d + a];
+        }
+        S[lf] = m.S[f];
         if (m.neigh[f] < 0) {
             const int64_t B = bcount++;
-            bslot[f] = int32_t(bo + B);
-            bface[B] = int32_t(fo + f);
+            bslot[lf] = int32_t(bo + B);
+            bface[B] = int32_t(fo + lf);
             for (int k = 0; k < nk; ++k) gavg[k * nb + B] = m.gavg[f * nk + k];
         }
-    }
-    for (int64_t g = 0; g < ng; ++g) {
-        for (int a = 0; a < d; ++a) {
-            gx[a * ng + g] = m.gx[g * d + a];
-            gn[a * ng + g] = m.gn[g * d + a];
-        }
-        gw[g] = m.gw[g];
     }
     auto &o = b->o;
     HIP_TRY(put_at(b, o.vol, co, vol, s)); HIP_TRY(put_at(b, o.h, co, h, s));

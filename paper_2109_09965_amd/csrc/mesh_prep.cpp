@@ -419,6 +419,56 @@ cgks_status recon_setup(HostMesh &m) {
     return CGKS_OK;
 }
 
+// Morton (Z-order) key: the bits of 21-bit (3-D) or 32-bit (2-D) grid
+// coordinates interleaved
+static uint64_t spread3(uint64_t x) {
+    x &= 0x1fffffull;
+    x = (x | x << 32) & 0x1f00000000ffffull;
+    x = (x | x << 16) & 0x1f0000ff0000ffull;
+    x = (x | x << 8) & 0x100f00f00f00f00full;
+    x = (x | x << 4) & 0x10c30c30c30c30c3ull;
+    x = (x | x << 2) & 0x1249249249249249ull;
+    return x;
+}
+static uint64_t spread2(uint64_t x) {
+    x &= 0xffffffffull;
+    x = (x | x << 16) & 0x0000ffff0000ffffull;
+    x = (x | x << 8) & 0x00ff00ff00ff00ffull;
+    x = (x | x << 4) & 0x0f0f0f0f0f0f0f0full;
+    x = (x | x << 2) & 0x3333333333333333ull;
+    x = (x | x << 1) & 0x5555555555555555ull;
+    return x;
+}
+
+// Cells along a Morton curve of their centroids (the bounding box mapped
+// onto the grid; ties by caller id): consecutive cells are close in space.
+static std::vector<int64_t> morton_order(const HostMesh &m) {
+    const int d = m.dim;
+    const int64_t n = m.n_cell;
+    double lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+    for (int a = 0; a < d; ++a) lo[a] = hi[a] = m.ctr[a];
+    for (int64_t i = 0; i < n; ++i)
+        for (int a = 0; a < d; ++a) {
+            lo[a] = std::min(lo[a], m.ctr[i * d + a]);
+            hi[a] = std::max(hi[a], m.ctr[i * d + a]);
+        }
+    const double cells = d == 3 ? double(1 << 21) : 4294967296.0;
+    std::vector<uint64_t> key(n);
+    for (int64_t i = 0; i < n; ++i) {
+        uint64_t k = 0;
+        for (int a = 0; a < d; ++a) {
+            const double w = hi[a] > lo[a] ? (m.ctr[i * d + a] - lo[a]) / (hi[a] - lo[a]) : 0.0;
+            const uint64_t g = uint64_t(std::min(cells - 1.0, std::max(0.0, std::floor(w * cells))));
+            k |= (d == 3 ? spread3(g) : spread2(g)) << a;
+        }
+        key[i] = k;
+    }
+    std::vector<int64_t> order(n);
+    for (int64_t i = 0; i < n; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int64_t x, int64_t y) { return key[x] < key[y]; });
+    return order;
+}
+
 // Multicolour classes of the relaxation sweeps (Algorithm 1 in a
 // deterministic parallel order).  Largest-degree-first greedy colouring
 // (Welsh-Powell): cells in order of decreasing count of faces with a
@@ -461,8 +511,9 @@ void colour_and_order(HostMesh &m) {
     m.n_colour = ncol;
     m.colour_count.assign(ncol, 0);
     for (int64_t i = 0; i < m.n_cell; ++i) m.colour_count[m.colour[i]]++;
-    // library order: tiles of m.tile consecutive caller cells, colour-major
-    // inside each tile (increasing caller id within a colour)
+    // library order: tiles of m.tile consecutive cells of the Morton curve,
+    // colour-major inside each tile (curve order within a colour)
+    const std::vector<int64_t> curve = morton_order(m);
     m.lib2caller.assign(m.n_cell, 0);
     m.caller2lib.assign(m.n_cell, 0);
     std::vector<std::vector<std::pair<int64_t, int64_t>>> runs(ncol);
@@ -471,11 +522,13 @@ void colour_and_order(HostMesh &m) {
         const int64_t t1 = std::min(m.n_cell, t0 + m.tile);
         for (int c = 0; c < ncol; ++c) {
             const int64_t first = l;
-            for (int64_t i = t0; i < t1; ++i)
+            for (int64_t r = t0; r < t1; ++r) {
+                const int64_t i = curve[r];
                 if (m.colour[i] == c) {
                     m.lib2caller[l] = i;
                     m.caller2lib[i] = l++;
                 }
+            }
             if (l > first) runs[c].push_back({first, l - first});
         }
     }
@@ -489,6 +542,18 @@ void colour_and_order(HostMesh &m) {
         }
         m.run_ptr[c + 1] = int64_t(m.run_start.size());
     }
+    // faces follow their cells
+    std::vector<int64_t> fkey(m.n_face);
+    for (int64_t f = 0; f < m.n_face; ++f) {
+        const int64_t a = m.caller2lib[m.owner[f]];
+        fkey[f] = m.neigh[f] >= 0 ? std::min(a, m.caller2lib[m.neigh[f]]) : a;
+    }
+    m.libf2caller.resize(m.n_face);
+    for (int64_t f = 0; f < m.n_face; ++f) m.libf2caller[f] = f;
+    std::stable_sort(m.libf2caller.begin(), m.libf2caller.end(),
+                     [&](int64_t x, int64_t y) { return fkey[x] < fkey[y]; });
+    m.caller2libf.assign(m.n_face, 0);
+    for (int64_t lf = 0; lf < m.n_face; ++lf) m.caller2libf[m.libf2caller[lf]] = lf;
 }
 
 }  // namespace

@@ -49,21 +49,42 @@ def test_host_geometry_and_colouring_match_oracle(mk):
     assert np.all(np.diff(lm.colour[lm.lib2caller]) >= 0)
 
 
+def morton_keys(ctr):
+    """Z-order keys of points: the bounding box mapped onto a grid of 2^21
+    (3-D) or 2^32 (2-D) cells per axis, the grid coordinates' bits
+    interleaved (axis 0 lowest)."""
+    n, d = ctr.shape
+    bits = 21 if d == 3 else 32
+    lo, hi = ctr.min(axis=0), ctr.max(axis=0)
+    w = np.where(hi > lo, (ctr - lo) / np.where(hi > lo, hi - lo, 1.0), 0.0)
+    g = np.clip(np.floor(w * 2.0**bits), 0, 2**bits - 1).astype(np.uint64)
+    key = np.zeros(n, dtype=np.uint64)
+    for b in range(bits):
+        for a in range(d):
+            key |= ((g[:, a] >> np.uint64(b)) & np.uint64(1)) << np.uint64(b * d + a)
+    return key
+
+
 @pytest.mark.parametrize("tile", [1, 7, 64, 1000, 10**9])
 def test_library_order_is_tiled_colour_major(tile):
-    """Tiles of `tile` consecutive caller cells, colour-major inside each
-    tile, increasing caller id within a colour of a tile."""
+    """Tiles of `tile` consecutive cells along the Morton curve of the cell
+    centroids (ties by caller id), colour-major inside each tile, curve
+    order within a colour of a tile."""
     mesh = I.cubed_sphere_mesh(4, 10, 4, 3)
     n = mesh["n_cell"]
     lm = cg.Mesh(mesh, order_tile=tile)
     l2c = lm.lib2caller
     assert np.array_equal(np.sort(l2c), np.arange(n))
-    t = l2c // tile
-    assert np.all(np.diff(t) >= 0)                      # tiles in order
+    _, ctr, _, _ = lm.geometry()
+    curve = np.lexsort((np.arange(n), morton_keys(ctr)))   # stable by key, ties by caller id
+    rank = np.empty(n, np.int64)
+    rank[curve] = np.arange(n)
+    t = rank[l2c] // tile
+    assert np.all(np.diff(t) >= 0)                      # tiles in curve order
     key = t * (lm.n_colour + 1) + lm.colour[l2c]
     assert np.all(np.diff(key) >= 0)                    # colour-major inside a tile
     same = np.diff(key) == 0
-    assert np.all(np.diff(l2c)[same] > 0)               # caller order inside a run
+    assert np.all(np.diff(rank[l2c])[same] > 0)         # curve order inside a run
     # the colouring does not depend on the order
     assert np.array_equal(lm.colour, cg.Mesh(mesh, order_tile=10**9).colour)
 
