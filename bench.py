@@ -28,22 +28,22 @@ VALU_PEAK_TFLOPS = {"fp64": 78.6, "mixed32": 157.3, "mixed32_r64": 78.6}
 # (FMA = 2), from the VALU instruction counters of one launch on the
 # sphere workload (SQ_INSTS_VALU_{FMA,MUL,ADD,TRANS}_F64 resp. _F32, x 64
 # lanes), charged to the lanes that carry a Gauss point.
-FLUX_FLOP_PER_GP = {"fp64": 1918.0, "mixed32": 1713.0, "mixed32_r64": (2 * 1713.0 + 1918.0) / 3.0}
+FLUX_FLOP_PER_GP = {"fp64": 1941.0, "mixed32": 1733.0, "mixed32_r64": (2 * 1733.0 + 1941.0) / 3.0}
 
 # HBM bytes per launch from rocprofv3 FETCH_SIZE (x 2.0) and WRITE_SIZE
 # (x 1.0) on the sphere workload, each factor from a plain device copy of
 # known size.  Valid only for the kernel source they were taken on (its
 # SHA-256); any other source reports null.
-PROFILED_KERNELS_SHA256 = "c1bb49a433e89f6f017b1718de05b03fa224dcaa15e9570a85b78c00678161e2"
+PROFILED_KERNELS_SHA256 = "7e7354177b08e3288b546a39ec90a7f2e7e640e9bbff3ddc69cd7c4fc42e1723"
 PROFILED_TRAFFIC = {           # (kernel kind, precision) -> bytes per launch
-    ("dt", "fp64"): 79185791.0, ("dt", "mixed32"): 79185637.1,
-    ("recon", "fp64"): 880728509.8, ("recon", "mixed32"): 720899039.6,   # with the boundary ghost pre-pass
-    ("flux", "fp64"): 1149799715.6, ("flux", "mixed32"): 689265221.8,
-    ("cell", "fp64"): 831707646.4, ("cell", "mixed32"): 556612247.2,
-    ("low_face", "fp64"): 187498535.0, ("low_face", "mixed32"): 178656781.0,
-    ("low_cell", "fp64"): 306745060.2, ("low_cell", "mixed32"): 285773638.9,
-    ("sweep", "fp64"): 54722904.6, ("sweep", "mixed32"): 46842770.0,          # average over colour classes
-    ("prolong", "fp64"): 174290864.0, ("prolong", "mixed32"): 163236896.3,
+    ("dt", "fp64"): 79185890.0, ("dt", "mixed32"): 79185777.3,
+    ("recon", "fp64"): 682891803.6, ("recon", "mixed32"): 640162959.4,   # with the boundary ghost pre-pass
+    ("flux", "fp64"): 819104785.0, ("flux", "mixed32"): 535155743.3,
+    ("cell", "fp64"): 789203080.1, ("cell", "mixed32"): 399834015.3,
+    ("low_face", "fp64"): 182236893.4, ("low_face", "mixed32"): 174542538.0,
+    ("low_cell", "fp64"): 256554314.4, ("low_cell", "mixed32"): 242209048.9,  # 1 forcing + 5 step launches
+    ("sweep", "fp64"): 57028147.7, ("sweep", "mixed32"): 42903669.2,          # average over colour classes
+    ("prolong", "fp64"): 174291700.8, ("prolong", "mixed32"): 161205242.6,
 }
 
 

@@ -65,6 +65,40 @@ def test_case_in_a_changing_pool_equals_alone(precision):
         assert np.array_equal(Wp, Wa) and np.array_equal(dWp, dWa), name
 
 
+@pytest.mark.parametrize("precision", [cg.FP64, cg.MIXED32])
+def test_tiled_cases_in_a_changing_pool_equal_alone(precision):
+    """Meshes cut into many ragged tiles (sweep runs per tile and colour,
+    faces in their cells' order) admitted and released around each other:
+    each case still equals itself alone in one whole-mesh tile, bitwise."""
+    A = cyl(32, 0.2, 2.0, 7)
+    m3 = I.cubed_sphere_mesh(4, 8, 3, 2)
+    w3 = I.free_stream(3, 0.3, 3.0)
+    W3, dW3 = I.smooth_state(m3, w3, seed=8, amp=0.02)
+    S3 = (m3, cg.Params(W_inf=w3, mu=0.003, Pr=0.72), W3, dW3)
+    B = cyl(16, 0.3, -1.0, 9)
+    la, lb = cg.Mesh(A[0], order_tile=53), cg.Mesh(B[0], order_tile=29)
+    tot = np.array(counts(la)) + np.array(counts(lb))
+    pool = cg.Batch.pool(2, 3, *[int(x) for x in tot], precision=precision)
+    sb = pool.admit(lb, B[1])
+    pool.upload(sb, B[2], B[3])
+    sa = pool.admit(la, A[1])
+    pool.upload(sa, A[2], A[3])
+    pool.cycle()
+    pool.release(sb)
+    pool.cycle()
+    Wp, dWp = pool.download(sa)
+    Wa, dWa = alone(A[0], A[1], A[2], A[3], 2, precision)
+    assert np.array_equal(Wp, Wa) and np.array_equal(dWp, dWa)
+    # 3-D: a batch of one tiled case against the same case in one tile
+    bt = cg.Batch([cg.Mesh(m3, order_tile=41)], [S3[1]], precision=precision)
+    b1 = cg.Batch([cg.Mesh(m3, order_tile=10**9)], [S3[1]], precision=precision)
+    for b in (bt, b1):
+        b.upload(0, W3, dW3)
+        for _ in range(2):
+            b.cycle()
+    assert all(np.array_equal(x, y) for x, y in zip(bt.download(0), b1.download(0)))
+
+
 def test_admission_is_bounded_by_capacity_and_reuses_ranges():
     cases = [cyl(32, 0.2 + 0.02 * k, 0.0, k) for k in range(4)]
     lm = [cg.Mesh(c[0]) for c in cases]
