@@ -47,8 +47,9 @@ struct HostMesh {
     // colour present in it), grouped by colour: runs of colour c are
     // [run_ptr[c], run_ptr[c + 1])
     std::vector<int64_t> run_ptr, run_start, run_count;
-    // library face order: faces by the smaller library index of their cells
-    // (ties by caller id), so a tile's faces are close together too
+    // library face order: interior faces by the smaller library index of
+    // their cells, then boundary faces by their cell's (ties by caller id),
+    // so a tile's faces are close together too
     std::vector<int64_t> libf2caller, caller2libf;
 };
 

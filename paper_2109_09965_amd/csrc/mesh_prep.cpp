@@ -542,11 +542,12 @@ void colour_and_order(HostMesh &m) {
         }
         m.run_ptr[c + 1] = int64_t(m.run_start.size());
     }
-    // faces follow their cells
+    // faces follow their cells; boundary faces after the interior ones, so
+    // that a face kernel's waves do not mix the two paths
     std::vector<int64_t> fkey(m.n_face);
     for (int64_t f = 0; f < m.n_face; ++f) {
         const int64_t a = m.caller2lib[m.owner[f]];
-        fkey[f] = m.neigh[f] >= 0 ? std::min(a, m.caller2lib[m.neigh[f]]) : a;
+        fkey[f] = m.neigh[f] >= 0 ? std::min(a, m.caller2lib[m.neigh[f]]) : m.n_cell + a;
     }
     m.libf2caller.resize(m.n_face);
     for (int64_t f = 0; f < m.n_face; ++f) m.libf2caller[f] = f;
