@@ -817,20 +817,6 @@ template <int D, typename R> __global__ __launch_bounds__(kReconBlock) void k_re
     }
 }
 
-// value and gradient of P_i at x (x in cell i's frame), from the cell's
-// evaluation record (read with 16-byte loads)
-template <typename R> struct Vec16;
-template <> struct Vec16<double> {
-    using T = double2;
-    static constexpr int n = 2;
-    static __device__ __forceinline__ void unpack(const T &t, double *o) { o[0] = t.x; o[1] = t.y; }
-};
-template <> struct Vec16<float> {
-    using T = float4;
-    static constexpr int n = 4;
-    static __device__ __forceinline__ void unpack(const T &t, float *o) { o[0] = t.x; o[1] = t.y; o[2] = t.z; o[3] = t.w; }
-};
-
 // lane p of each group of G lanes (G = 2 or 4, all active) to the whole group
 template <int G, int P> __device__ __forceinline__ int bcast_i32(int x) {
     constexpr int ctrl = G == 4 ? (P | P << 2 | P << 4 | P << 6) : (P | P << 2 | (P + 2) << 4 | (P + 2) << 6);
@@ -1323,10 +1309,7 @@ template <int D, typename S, int MODE> __global__ __launch_bounds__(kBlock) void
 #pragma unroll
     for (int k = 0; k < NS; ++k) code[k] = d.slot[size_t(q + k * SL) * NC + i].x;
     const DevParams &P = d.prm[d.cell_case[i]];
-    double gamma;
-    bool active;
-    gamma_active(P, gamma, active);
-    (void)gamma;
+    const bool active = P.active;
     double *Ui = LowRec<D, S>::U(d, i);
     S *dUi = LowRec<D, S>::dU(d, i);
     double u[nv], own[nv];   // state of the step; Sf (steps) or R1 (forcing) of this lane's variables
