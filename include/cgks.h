@@ -47,15 +47,20 @@ typedef enum {
     CGKS_ENONPHYS = 5,    /* density or pressure <= 0 met during a cycle */
     CGKS_EDIVERGED = 6,   /* residual grew by 1e3 over its running minimum */
     CGKS_ENOTCONV = 7,    /* cgks_solve hit max_cycles before the tolerance */
-    CGKS_EUNSUPPORTED = 8 /* valid but not implemented (e.g. adiabatic wall tag) */
+    CGKS_EUNSUPPORTED = 8 /* valid but not implemented (e.g. more colours than the sweep supports) */
 } cgks_status;
 
 /* boundary tags of boundary faces (interior faces carry 0) */
 enum {
     CGKS_BC_INTERIOR = 0,
-    CGKS_BC_SLIP_WALL = 1,          /* inviscid reflecting wall */
-    CGKS_BC_NOSLIP_ISOTHERMAL = 2,  /* no-slip wall at temperature T_wall */
-    CGKS_BC_NOSLIP_ADIABATIC = 3,   /* reserved: returns CGKS_EUNSUPPORTED */
+    CGKS_BC_SLIP_WALL = 1,          /* inviscid reflecting wall: mirror state, normal velocity reversed */
+    CGKS_BC_NOSLIP_ISOTHERMAL = 2,  /* no-slip wall at temperature T_wall: wall state (p_L / T_wall, 0,
+                                       p_L), interior gradient, no mass flux.  Not a wall of the
+                                       paper's cases; stable only on near-wall cells of about
+                                       0.1 D at Re 40; went non-physical on 0.05 D ones */
+    CGKS_BC_NOSLIP_ADIABATIC = 3,   /* no-slip adiabatic wall (Sec. 4 viscous cases): mirror state
+                                       with every velocity component reversed; zero velocity and
+                                       zero heat flux at the wall */
     CGKS_BC_FARFIELD = 4            /* characteristic (Riemann invariant) far field */
 };
 
@@ -273,8 +278,10 @@ typedef struct {
 } cgks_solve_opts;
 
 typedef struct {
-    int32_t cycles;
-    int32_t converged;
+    int32_t cycles;        /* cycles applied to the case's state: the stop is
+                              taken at a check, so this is a multiple of
+                              check_every (or max_cycles) */
+    int32_t converged;     /* the tolerance was met at some cycle of the last block */
     double res_first, res_last;
     cgks_status status;    /* CGKS_OK, CGKS_ENOTCONV, CGKS_ENONPHYS, CGKS_EDIVERGED */
     double force[3];       /* wall force at the start of the case's last cycle (see cgks_wall_force) */
@@ -284,7 +291,9 @@ typedef struct {
    (host).  Res is checked on the host every check_every cycles; with
    2 <= check_every <= 8 those cycles run as one captured graph (this
    replaces a graph made by cgks_graph_create).  A case that meets its tolerance, or is
-   found non-physical or diverging, stops being updated at that check. */
+   found non-physical or diverging, at any cycle of a block stops being
+   updated at the check that ends the block; res_history holds every cycle
+   it ran. */
 cgks_status cgks_solve(cgks_batch *batch, const cgks_solve_opts *opts, cgks_solve_report *report, void *stream);
 
 /* Force of the gas on the walls of each case (Sec. 4, sphere and cylinder

@@ -564,7 +564,7 @@ static int ghost_cell(const om_mesh *m, const om_params *P, long i, long f, cons
         for (int k = 0; k < d * nv; k++) dWg[k] = 0.0;
         return 0;
     }
-    if (bc != BC_SLIP && bc != BC_ISOTHERMAL) return -3;
+    if (bc != BC_SLIP && bc != BC_ISOTHERMAL && bc != BC_ADIABATIC) return -3;
     /* M acting on (rho, m, E): identity on scalars, R (slip) or -I (no slip) on m */
     double Mm[3][3];
     for (int a = 0; a < 3; a++)
@@ -1165,6 +1165,22 @@ static int ho_pass(const om_mesh *m, const om_params *P, const double *W, const 
                 state_to_local(d, e, P->W_inf, Winf_l);
                 farfield_state(d, P->gamma, WL, Winf_l, WR);
                 memset(dWR, 0, sizeof(double) * d * nv);
+            } else if (m->bc[f] == BC_ADIABATIC) {
+                /* no-slip adiabatic wall (Sec. 4 viscous cases): the mirror
+                   ghost with every velocity component reversed.  A derivative
+                   of the ghost field changes sign when exactly one of (normal
+                   direction, momentum component) applies to it, so in the
+                   average the normal derivatives of rho and E and the
+                   tangential derivatives of the momentum vanish: zero velocity
+                   and zero heat flux at the wall. */
+                vcopy(WR, WL, nv);
+                for (int a = 0; a < d; a++) WR[1 + a] = -WL[1 + a];
+                for (int a = 0; a < d; a++)
+                    for (int v = 0; v < nv; v++) {
+                        double sgn = (a == 0) ? -1.0 : 1.0;
+                        if (v >= 1 && v <= d) sgn = -sgn;
+                        dWR[a * nv + v] = sgn * dWL[a * nv + v];
+                    }
             } else if (m->bc[f] == BC_ISOTHERMAL) {
                 wall = 1;
             } else {
@@ -1196,7 +1212,7 @@ static int ho_pass(const om_mesh *m, const om_params *P, const double *W, const 
             vec_to_global(d, e, Ftl, Ft);
             vec_to_global(d, e, Wc, Wg);
             vec_to_global(d, e, Wtl, Wt);
-            if (R < 0 && (m->bc[f] == BC_SLIP || m->bc[f] == BC_ISOTHERMAL))
+            if (R < 0 && (m->bc[f] == BC_SLIP || m->bc[f] == BC_ISOTHERMAL || m->bc[f] == BC_ADIABATIC))
                 for (int a = 0; a < d; a++) o->force[a] += wJ * F0[1 + a];
             for (int side = 0; side < 2; side++) {
                 long c = side ? R : L;
@@ -1395,7 +1411,7 @@ static int ghost_state(const om_mesh *m, const om_params *P, int bc, double e[3]
         double Winf_l[NVMAX];
         state_to_local(d, e, P->W_inf, Winf_l);
         farfield_state(d, P->gamma, Ul, Winf_l, Ug);
-    } else if (bc == BC_ISOTHERMAL) {
+    } else if (bc == BC_ISOTHERMAL || bc == BC_ADIABATIC) {
         /* no slip: every velocity component reversed */
         vcopy(Ug, Ul, nv);
         for (int a = 0; a < d; a++) Ug[1 + a] = -Ul[1 + a];

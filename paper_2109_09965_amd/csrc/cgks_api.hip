@@ -1049,29 +1049,35 @@ cgks_status cgks_solve(cgks_batch *b, const cgks_solve_opts *opts, cgks_solve_re
             }
         }        HIP_TRY(hipMemcpyAsync(flag.data(), b->dev.flag, sizeof(int32_t) * n, hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
+        // every live case ran all `todo` cycles of the block; a stop seen at
+        // any of them (or the non-physical flag, known per block only) takes
+        // effect at this check, and the report counts the cycles the state ran
         bool changed = false;
-        for (int j = 0; j < todo; ++j) {
-            for (int c = 0; c < n; ++c) {
-                if (done[c]) continue;
+        for (int c = 0; c < n; ++c) {
+            if (done[c]) continue;
+            cgks_status cst = CGKS_OK;
+            bool conv = false;
+            for (int j = 0; j < todo; ++j) {
                 const double r = hist[size_t(j) * n + c];
                 const int cyc = k + j + 1;
-                rep[c].cycles = cyc;
-                rep[c].res_last = r;
                 if (cyc == 1) rep[c].res_first = first[c] = r;
                 if (opts->res_history) opts->res_history[size_t(c) * opts->max_cycles + cyc - 1] = r;
                 best[c] = std::min(best[c], r);
-                cgks_status cst = CGKS_OK;
-                if (flag[c] & 1 || !std::isfinite(r)) cst = CGKS_ENONPHYS;
+                if (cst != CGKS_OK || conv) continue;
+                if (!std::isfinite(r)) cst = CGKS_ENONPHYS;
                 else if (r > 1e3 * best[c]) cst = CGKS_EDIVERGED;
-                const bool conv = opts->tol_abs ? r <= opts->tol : (first[c] > 0 && r / first[c] <= opts->tol);
-                if (cst != CGKS_OK || conv) {
-                    done[c] = 1;
-                    --remaining;
-                    rep[c].converged = conv && cst == CGKS_OK;
-                    rep[c].status = cst == CGKS_OK ? CGKS_OK : cst;
-                    prm[c].active = 0;
-                    changed = true;
-                }
+                else conv = opts->tol_abs ? r <= opts->tol : (first[c] > 0 && r / first[c] <= opts->tol);
+            }
+            if (cst == CGKS_OK && (flag[c] & 1)) cst = CGKS_ENONPHYS;
+            rep[c].cycles = k + todo;
+            rep[c].res_last = hist[size_t(todo - 1) * n + c];
+            if (cst != CGKS_OK || conv) {
+                done[c] = 1;
+                --remaining;
+                rep[c].converged = conv && cst == CGKS_OK;
+                rep[c].status = cst;
+                prm[c].active = 0;
+                changed = true;
             }
         }
         if (changed) {

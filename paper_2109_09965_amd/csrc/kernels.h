@@ -992,11 +992,16 @@ template <int D, typename R> __global__ __launch_bounds__(kBlock) void k_flux(De
                 for (int a = 0; a < D; ++a) xr[a] = x[a] - R(d.shift[size_t(a) * d.NF + f]);
                 recon_eval<D, R>(d, cR, q, xr, WRg, Gs);
                 fr.to_local(WRg, WR);
-            } else if (bc == 1) {
-                // mirror: normal momentum reversed
+            } else if (bc == 1 || bc == 3) {
+                // mirror: normal momentum reversed (slip), every momentum
+                // component reversed (no-slip adiabatic)
 #pragma unroll
                 for (int v = 0; v < nv; ++v) WR[v] = WL[v];
                 WR[1] = -WL[1];
+                if (bc == 3) {
+#pragma unroll
+                    for (int a = 1; a < D; ++a) WR[1 + a] = -WL[1 + a];
+                }
             } else {
                 R Wo_g[nv], Wo[nv];
 #pragma unroll
@@ -1014,15 +1019,20 @@ template <int D, typename R> __global__ __launch_bounds__(kBlock) void k_flux(De
             ok = half_side<D, R>(WR, P, -R(1.0), Wc, nullptr) && ok;
             __builtin_amdgcn_sched_barrier(0);
             fr.grad_to_local(Gs, Gc);
-            if (cR < 0 && bc == 1) {
+            if (cR < 0 && (bc == 1 || bc == 3)) {
                 // mirror ghost: a derivative flips sign when exactly one of
-                // (normal direction, normal momentum) applies to it; flipped
-                // ones cancel in the average, the others are kept whole
+                // (normal direction, reversed momentum component) applies to
+                // it; flipped ones cancel in the average, the others are kept
+                // whole.  No-slip adiabatic: zero normal derivative of rho and
+                // E at zero velocity, hence no heat flux.
+                const bool all_mom = bc == 3;
 #pragma unroll
                 for (int a = 0; a < D; ++a)
 #pragma unroll
-                    for (int v = 0; v < nv; ++v)
-                        if ((a == 0) != (v == 1)) Gc[a][v] = R(0.0);
+                    for (int v = 0; v < nv; ++v) {
+                        const bool rev = all_mom ? (v >= 1 && v <= D) : (v == 1);
+                        if ((a == 0) != rev) Gc[a][v] = R(0.0);
+                    }
             } else {
                 // interior: average of both sides; far field: the exterior
                 // state has zero gradient
@@ -1072,7 +1082,7 @@ template <int D, typename R> __global__ __launch_bounds__(kBlock) void k_flux(De
         for (int v = 0; v < nv; ++v) Wt[v] = R(0.0);
     }
     fr.to_global(F0, o);
-    const bool wall_out = want_grad == 2 && writer && cR < 0 && (bc == 1 || bc == 2);
+    const bool wall_out = want_grad == 2 && writer && cR < 0 && (bc == 1 || bc == 2 || bc == 3);
 #pragma unroll
     for (int v = 0; v < nv; ++v) {
         const R sum = group_sum<G, R>(wJ * o[v]);
@@ -1263,7 +1273,7 @@ template <int D, typename S> __global__ __launch_bounds__(kBlock) void k_low_fac
         for (int v = 0; v < nv; ++v) Ur[v] = Ul[v];
         if (bc == 1) {
             Ur[1] = -Ul[1];
-        } else if (bc == 2) {
+        } else if (bc == 2 || bc == 3) {
 #pragma unroll
             for (int a = 0; a < D; ++a) Ur[1 + a] = -Ul[1 + a];
         } else {
@@ -1527,7 +1537,7 @@ template <int D> __global__ __launch_bounds__(kBlock) void k_wall_force(Dev d) {
         const int F = d.bface[B];
         if (F < 0) continue;
         const int bc = d.fbc[F];
-        if (bc != 1 && bc != 2) continue;
+        if (bc != 1 && bc != 2 && bc != 3) continue;
 #pragma unroll
         for (int a = 0; a < D; ++a) f[a] += d.wallf[size_t(B) * 3 + a];
     }

@@ -589,8 +589,8 @@ cgks_status build_host_mesh(const cgks_mesh_desc *ds, HostMesh &m) {
             return CGKS_EMESH;
         if (m.neigh[f] < 0) {
             ++m.n_bface;
-            if (m.bc[f] == CGKS_BC_NOSLIP_ADIABATIC) return CGKS_EUNSUPPORTED;
-            if (m.bc[f] != CGKS_BC_SLIP_WALL && m.bc[f] != CGKS_BC_NOSLIP_ISOTHERMAL && m.bc[f] != CGKS_BC_FARFIELD)
+            if (m.bc[f] != CGKS_BC_SLIP_WALL && m.bc[f] != CGKS_BC_NOSLIP_ISOTHERMAL &&
+                m.bc[f] != CGKS_BC_NOSLIP_ADIABATIC && m.bc[f] != CGKS_BC_FARFIELD)
                 return CGKS_EMESH;
         }
     }

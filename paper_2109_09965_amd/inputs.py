@@ -368,7 +368,7 @@ def sphere_layer_types(n_layers=40, n_hex=20, n_prism=10):
 
 
 def sphere_mesh(n_theta=48, n_phi=96, n_layers=40, n_hex=20, n_prism=10, r_wall=0.5, r_far=15.0,
-                ratio=1.08, first_spacing=None, wall=BC_NOSLIP_ISOTHERMAL):
+                ratio=1.08, first_spacing=None, wall=BC_NOSLIP_ADIABATIC):
     """3-D hybrid O-grid around a sphere on a latitude-longitude surface grid
     (n_theta x n_phi quads; the polar rows collapse to triangles), n_layers
     radial layers: hexahedra, prisms, tetrahedra (see sphere_layer_types)."""
@@ -409,7 +409,7 @@ def sphere_mesh(n_theta=48, n_phi=96, n_layers=40, n_hex=20, n_prism=10, r_wall=
 
 
 def cubed_sphere_mesh(n=28, n_layers=40, n_hex=20, n_prism=10, r_wall=0.5, r_far=15.0, ratio=1.08,
-                      first_spacing=None, wall=BC_NOSLIP_ISOTHERMAL):
+                      first_spacing=None, wall=BC_NOSLIP_ADIABATIC):
     """3-D hybrid O-grid around a sphere on a cubed-sphere surface grid: the
     six faces of a cube, each n x n quads (equiangular gnomonic map), pushed
     onto the sphere, then extruded through n_layers radial layers of
@@ -622,9 +622,8 @@ def serve_trace(n_requests=256, seed=9965, rate=20.0, frac_2d=0.7, mach=(0.1, 0.
                 re_3d=(50.0, 200.0)):
     """Seeded steady-solve request trace: exponential inter-arrival times at
     `rate` per second; frac_2d of the requests are viscous cylinders built
-    like the batch cases with n_theta in {32, 64} (n_r = n_theta/2; on the
-    finer batch rings the two-level cycle diverges at the wall for Re <= 40),
-    the rest hybrid cubed-sphere O-grids with n in {14..28} quads per cube edge
+    like the batch cases with n_theta in {32, 64} (n_r = n_theta/2) and a
+    no-slip adiabatic wall, the rest hybrid cubed-sphere O-grids with n in {14..28} quads per cube edge
     (about the 24x48 .. 48x96 surface quads of latitude-longitude grids) and
     L in {16..40} layers (L/2 hex, L/4 prism, the rest tet), stretched to
     r = 15.  Mach ~ U[mach]; Re ~ U[re_2d] / U[re_3d] on the diameter, kept
@@ -647,11 +646,11 @@ def serve_trace(n_requests=256, seed=9965, rate=20.0, frac_2d=0.7, mach=(0.1, 0.
 
 
 def serve_mesh(spec):
-    """Mesh of one trace request: the cylinder with a no-slip isothermal
+    """Mesh of one trace request: the cylinder with a no-slip adiabatic
     wall, or the cubed-sphere O-grid (radial ratio 1.08^(40/L) to r = 15)."""
     if spec["dim"] == 2:
         nr = spec["n_r"]
-        return cylinder_mesh(spec["n_theta"], nr, ratio=1.1 ** (32.0 / nr), wall=BC_NOSLIP_ISOTHERMAL)
+        return cylinder_mesh(spec["n_theta"], nr, ratio=1.1 ** (32.0 / nr), wall=BC_NOSLIP_ADIABATIC)
     L = spec["layers"]
     return cubed_sphere_mesh(spec["n"], L, L // 2, L // 4, 0.5, 15.0, 1.08 ** (40.0 / L))
 

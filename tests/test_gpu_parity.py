@@ -28,6 +28,10 @@ def make_case(name):
         m = I.cylinder_mesh(32, 16, wall=I.BC_NOSLIP_ISOTHERMAL)
         Winf = I.free_stream(2, 0.15)
         kw = dict(W_inf=Winf, mu=0.15 / 40, Pr=0.72)
+    elif name == "cyl2d_adiab":
+        m = I.cylinder_mesh(32, 16, wall=I.BC_NOSLIP_ADIABATIC)
+        Winf = I.free_stream(2, 0.15)
+        kw = dict(W_inf=Winf, mu=0.15 / 40, Pr=0.72)
     elif name == "box2d_per":
         m = I.box2d_mesh(10, perturb=0.3, seed=2)
         Winf = I.free_stream(2, 0.4, 30.0)
@@ -41,11 +45,15 @@ def make_case(name):
         Winf = I.free_stream(3, 0.3, 15.0)
         kw = dict(W_inf=Winf)
     elif name == "sphere":
-        m = I.sphere_mesh(8, 16, 8, 3, 2)
+        m = I.sphere_mesh(8, 16, 8, 3, 2, wall=I.BC_NOSLIP_ISOTHERMAL)
         Winf = I.free_stream(3, 0.25)
         kw = dict(W_inf=Winf, mu=0.25 / 100, Pr=0.72)
     elif name == "cubed_sphere":
-        m = I.cubed_sphere_mesh(4, 8, 3, 2)
+        m = I.cubed_sphere_mesh(4, 8, 3, 2, wall=I.BC_NOSLIP_ISOTHERMAL)
+        Winf = I.free_stream(3, 0.3, 4.0)
+        kw = dict(W_inf=Winf, mu=0.3 / 100, Pr=0.72)
+    elif name == "cubed_sphere_adiab":
+        m = I.cubed_sphere_mesh(4, 8, 3, 2, wall=I.BC_NOSLIP_ADIABATIC)
         Winf = I.free_stream(3, 0.3, 4.0)
         kw = dict(W_inf=Winf, mu=0.3 / 100, Pr=0.72)
     else:
@@ -54,7 +62,8 @@ def make_case(name):
     return m, kw, W, dW
 
 
-CASES = ["cyl2d_slip", "cyl2d_visc", "box2d_per", "box3d_per", "box3d_slip", "sphere", "cubed_sphere"]
+CASES = ["cyl2d_slip", "cyl2d_visc", "cyl2d_adiab", "box2d_per", "box3d_per", "box3d_slip", "sphere", "cubed_sphere",
+         "cubed_sphere_adiab"]
 
 
 class Pair:
@@ -227,10 +236,11 @@ def test_wall_force(name):
         assert np.abs(fg - fo).max() <= 1e-11 * scale, (k, fg, fo)
 
 
-def test_wall_force_open_box_on_device():
+@pytest.mark.parametrize("wall", [I.BC_NOSLIP_ISOTHERMAL, I.BC_NOSLIP_ADIABATIC])
+def test_wall_force_open_box_on_device(wall):
     """Gas at rest in a box with a far-field top: the force on the walls is
     -p0 * (top area) * e_z (the oracle's pin, here through the C ABI)."""
-    m = I.box3d_mesh((3, 3, 5), perturb=0.2, seed=6, bc=I.BC_NOSLIP_ISOTHERMAL)
+    m = I.box3d_mesh((3, 3, 5), perturb=0.2, seed=6, bc=wall)
     bc = m["face_bc"].copy()
     ptr, fv, xyz = m["face_vert_ptr"], m["face_vert"], m["xyz"]
     for f in np.nonzero(m["face_neigh"] < 0)[0]:

@@ -1,0 +1,56 @@
+"""Converged drag against the values the paper prints (Sec. 4), through the
+C ABI, with the no-slip adiabatic wall of the paper's viscous cases.
+
+These are behavioural checks of the whole method, not parity: the paper's
+numbers come from finer meshes than the ones run here, so the tolerance is
+the spread of the values printed beside them (the cylinder's experimental
+range 1.46-1.56 is about +-3 % around 1.525; the sphere's schemes give
+1.002-1.016 and the experiment 1.0).  The cylinder drag of the paper's
+conditions must also come out the same on two meshes a factor two apart, to
+1 %: a wall treatment that is not consistent shows up as a strong mesh and
+Mach dependence of the pressure drag."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import paper_2109_09965_amd as cg
+import paper_2109_09965_amd.inputs as I
+
+pytestmark = pytest.mark.gpu
+
+GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "drag_paper.json")))
+
+
+def converged_cd(m, Ma, Re, area, max_cycles):
+    w = I.free_stream(m["dim"], Ma)
+    b = cg.Batch([cg.Mesh(m)], [cg.Params(W_inf=w, mu=Ma / Re, Pr=0.72)])
+    W, dW = I.uniform_state(m, w)
+    b.upload(0, W, dW)
+    rep, _ = b.solve(max_cycles=max_cycles, tol=1e-9, check_every=8)
+    r = rep[0]
+    cd = cg.drag_coefficient(r["force"], w, area)
+    print(f"{m['name'] if 'name' in m else m['dim']}: {r['cycles']} cycles, converged {r['converged']}, "
+          f"Cd {cd:.4f}", flush=True)
+    assert r["converged"], r
+    return cd
+
+
+def test_cylinder_re40_drag_matches_paper():
+    g = GOLD["cylinder_re40"]
+    cds = []
+    for nt, nr, ratio, h in ((64, 32, 1.1, 0.09695), (128, 64, 1.06, 0.05)):
+        m = I.cylinder_mesh(nt, nr, 0.5, ratio=ratio, first_spacing=h, wall=I.BC_NOSLIP_ADIABATIC)
+        cds.append(converged_cd(m, g["Ma"], g["Re"], 1.0, 6000))
+    lo, hi = g["Cd_experiment_range"]
+    for cd in cds:
+        assert lo <= cd <= hi
+        assert abs(cd - g["Cd"]) <= 0.03 * g["Cd"]
+    assert abs(cds[0] - cds[1]) <= 0.01 * g["Cd"]
+
+
+def test_sphere_re118_drag_matches_paper():
+    g = GOLD["sphere_re118"]
+    cd = converged_cd(I.sphere_case_mesh(), g["Ma"], g["Re"], np.pi * 0.25, 3000)
+    assert abs(cd - g["Cd"]) <= 0.03 * g["Cd"]

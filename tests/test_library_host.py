@@ -110,6 +110,9 @@ def test_mesh_errors_are_reported():
     assert e.value.status == cg.EMESH
     adi = dict(mesh)
     adi["face_bc"] = np.where(mesh["face_bc"] == I.BC_SLIP_WALL, I.BC_NOSLIP_ADIABATIC, mesh["face_bc"]).astype(np.int32)
+    cg.Mesh(adi)
+    unknown = dict(mesh)
+    unknown["face_bc"] = np.where(mesh["face_bc"] == I.BC_SLIP_WALL, 7, mesh["face_bc"]).astype(np.int32)
     with pytest.raises(cg.CgksError) as e:
-        cg.Mesh(adi)
-    assert e.value.status == cg.EUNSUPPORTED
+        cg.Mesh(unknown)
+    assert e.value.status == cg.EMESH

@@ -297,7 +297,7 @@ def test_cubed_sphere_is_a_valid_conforming_mesh(n, layers):
     own, nb, bc = mesh["face_owner"], mesh["face_neigh"], mesh["face_bc"]
     assert np.all(own >= 0)
     # boundary faces: 6n^2 wall quads, 12n^2 far-field triangles (tet layer)
-    assert (bc == I.BC_NOSLIP_ISOTHERMAL).sum() == 6 * n * n
+    assert (bc == I.BC_NOSLIP_ADIABATIC).sum() == 6 * n * n
     assert (bc == I.BC_FARFIELD).sum() == 12 * n * n
     assert np.all((nb < 0) == (bc > 0))
     cnt = np.bincount(np.concatenate([own, nb[nb >= 0]]), minlength=mesh["n_cell"])

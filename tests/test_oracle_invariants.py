@@ -61,11 +61,18 @@ def test_periodic_conservation(mk, scheme):
     (lambda bc: I.box2d_mesh(8, periodic=False, perturb=0.3, seed=2, bc=bc), I.BC_SLIP_WALL),
     (lambda bc: I.box3d_mesh((3, 3, 5), perturb=0.2, seed=4, bc=bc), I.BC_SLIP_WALL),
     (lambda bc: I.box3d_mesh((3, 3, 5), perturb=0.2, seed=4, bc=bc), I.BC_NOSLIP_ISOTHERMAL),
+    (lambda bc: I.box2d_mesh(8, periodic=False, perturb=0.3, seed=2, bc=bc), I.BC_NOSLIP_ADIABATIC),
+    (lambda bc: I.box3d_mesh((3, 3, 5), perturb=0.2, seed=4, bc=bc), I.BC_NOSLIP_ADIABATIC),
 ])
 def test_walls_carry_no_mass(mk, bc):
     """A closed box with slip walls conserves mass and energy in the
     high-order stages (the mirrored interface state has no normal mass or
-    energy flux); with no-slip isothermal walls mass is conserved."""
+    energy flux); with no-slip isothermal walls mass is conserved.  With
+    no-slip adiabatic walls mass and energy are conserved: the wall state
+    has zero velocity, so the viscous stress does no work, and the mirrored
+    gradients give zero normal temperature derivative, so no heat crosses;
+    a wrong sign in the mirrored gradients leaves a heat flux and fails
+    this."""
     mesh = mk(bc)
     d = mesh["dim"]
     Winf = I.free_stream(d, 0.3, 15.0)
@@ -78,7 +85,7 @@ def test_walls_carry_no_mass(mk, bc):
     s.stage(1, W, dW)
     tot = W @ vol
     assert tot[0] == pytest.approx(tot0[0], rel=1e-14)
-    if bc == I.BC_SLIP_WALL:
+    if bc in (I.BC_SLIP_WALL, I.BC_NOSLIP_ADIABATIC):
         assert tot[-1] == pytest.approx(tot0[-1], rel=1e-14)
     R1 = s.residual_high(W, dW)
     assert abs(R1[0].sum()) <= 1e-13 * np.abs(R1[0]).sum()
@@ -101,7 +108,7 @@ def open_top_box(mesh, top):
     (lambda bc: I.box2d_mesh(6, periodic=False, perturb=0.3, seed=3, bc=bc), 2.0, 2.0),
     (lambda bc: I.box3d_mesh((3, 3, 5), perturb=0.2, seed=6, bc=bc), 1.0, 1.0),
 ])
-@pytest.mark.parametrize("bc", [I.BC_SLIP_WALL, I.BC_NOSLIP_ISOTHERMAL])
+@pytest.mark.parametrize("bc", [I.BC_SLIP_WALL, I.BC_NOSLIP_ISOTHERMAL, I.BC_NOSLIP_ADIABATIC])
 def test_wall_force_of_gas_at_rest_in_an_open_box(mk, top, area, bc):
     """Gas at rest at the free-stream pressure in a box whose top side is
     far field and whose other sides are walls: the wall momentum flux is
