@@ -5,7 +5,7 @@ gradient update, high-order residual, KFVS forcing, 6 implicit steps of 2
 multicolour point-relaxation sweeps, prolongation, Res) on every cell of the
 workload.  Default workload: 3-D hybrid sphere O-grid on a cubed-sphere
 surface (6 x 28 x 28 quads, 40 layers: 20 hex, 10 prism, 10 tet; 470,400
-cells), Ma 0.25, Re 100, Pr 0.72, no-slip isothermal wall, FP64.  Inputs are resident on the device
+cells), Ma 0.25, Re 100, Pr 0.72, no-slip adiabatic wall, FP64.  Inputs are resident on the device
 before the timed region.  Prints one JSON line.
 """
 import argparse
@@ -28,22 +28,22 @@ VALU_PEAK_TFLOPS = {"fp64": 78.6, "mixed32": 157.3, "mixed32_r64": 78.6}
 # (FMA = 2), from the VALU instruction counters of one launch on the
 # sphere workload (SQ_INSTS_VALU_{FMA,MUL,ADD,TRANS}_F64 resp. _F32, x 64
 # lanes), charged to the lanes that carry a Gauss point.
-FLUX_FLOP_PER_GP = {"fp64": 1941.0, "mixed32": 1733.0, "mixed32_r64": (2 * 1733.0 + 1941.0) / 3.0}
+FLUX_FLOP_PER_GP = {"fp64": 1909.0, "mixed32": 1705.0, "mixed32_r64": (2 * 1705.0 + 1909.0) / 3.0}
 
 # HBM bytes per launch from rocprofv3 FETCH_SIZE (x 2.0) and WRITE_SIZE
 # (x 1.0) on the sphere workload, each factor from a plain device copy of
 # known size.  Valid only for the kernel source they were taken on (its
 # SHA-256); any other source reports null.
-PROFILED_KERNELS_SHA256 = "7e7354177b08e3288b546a39ec90a7f2e7e640e9bbff3ddc69cd7c4fc42e1723"
+PROFILED_KERNELS_SHA256 = "9d30f73579b07af89bb455977099131565f94a2d4fa0043a8bfc3230484780c2"
 PROFILED_TRAFFIC = {           # (kernel kind, precision) -> bytes per launch
-    ("dt", "fp64"): 79185890.0, ("dt", "mixed32"): 79185777.3,
-    ("recon", "fp64"): 682891803.6, ("recon", "mixed32"): 640162959.4,   # with the boundary ghost pre-pass
-    ("flux", "fp64"): 819104785.0, ("flux", "mixed32"): 535155743.3,
-    ("cell", "fp64"): 789203080.1, ("cell", "mixed32"): 399834015.3,
-    ("low_face", "fp64"): 182236893.4, ("low_face", "mixed32"): 174542538.0,
-    ("low_cell", "fp64"): 256554314.4, ("low_cell", "mixed32"): 242209048.9,  # 1 forcing + 5 step launches
-    ("sweep", "fp64"): 57028147.7, ("sweep", "mixed32"): 42903669.2,          # average over colour classes
-    ("prolong", "fp64"): 174291700.8, ("prolong", "mixed32"): 161205242.6,
+    ("dt", "fp64"): 79177578.1, ("dt", "mixed32"): 79177468.4,
+    ("recon", "fp64"): 678968786.3, ("recon", "mixed32"): 635464737.1,   # with the boundary ghost pre-pass
+    ("flux", "fp64"): 825385461.3, ("flux", "mixed32"): 538532734.0,
+    ("cell", "fp64"): 785571397.8, ("cell", "mixed32"): 399836821.4,
+    ("low_face", "fp64"): 183769066.5, ("low_face", "mixed32"): 175811667.1,
+    ("low_cell", "fp64"): 256209261.0, ("low_cell", "mixed32"): 242059802.9,  # 1 forcing + 5 step launches
+    ("sweep", "fp64"): 56913584.5, ("sweep", "mixed32"): 42842009.4,          # average over colour classes
+    ("prolong", "fp64"): 173976724.0, ("prolong", "mixed32"): 163417429.1,
 }
 
 
@@ -53,10 +53,10 @@ def workload(name):
         mesh = I.sphere_case_mesh()
         Ma, Re = 0.25, 100.0
         Winf = I.free_stream(3, Ma)
-        kw = dict(W_inf=Winf, mu=Ma * 1.0 / Re, Pr=0.72, T_wall=1.0 / 1.4)
+        kw = dict(W_inf=Winf, mu=Ma * 1.0 / Re, Pr=0.72)
         desc = ("3-D laminar sphere, hybrid O-grid on a cubed sphere 6x28x28 surface quads x 40 layers "
                 "(20 hex, 10 prism, 10 tet), "
-                "Ma 0.25, Re 100, Pr 0.72, isothermal no-slip wall, S2O4 + 6 implicit steps x 2 sweeps")
+                "Ma 0.25, Re 100, Pr 0.72, adiabatic no-slip wall, S2O4 + 6 implicit steps x 2 sweeps")
     elif name == "cylinder":
         mesh = I.cylinder_case_mesh()
         Winf = I.free_stream(2, 0.2)
@@ -224,7 +224,7 @@ def cpu_baseline(seconds_hint=30.0):
     mesh = I.cubed_sphere_mesh(14, 20, 10, 5, r_far=15.0, ratio=1.08)
     Ma, Re = 0.25, 100.0
     Winf = I.free_stream(3, Ma)
-    s = oracle.Solver(oracle.Mesh(mesh), oracle.Params(W_inf=Winf, mu=Ma / Re, Pr=0.72, T_wall=1 / 1.4))
+    s = oracle.Solver(oracle.Mesh(mesh), oracle.Params(W_inf=Winf, mu=Ma / Re, Pr=0.72))
     W, dW = I.uniform_state(mesh, Winf)
     n = 0
     t0 = time.perf_counter()

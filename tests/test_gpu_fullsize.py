@@ -33,7 +33,7 @@ def full():
     m = I.sphere_case_mesh()
     Ma, Re = 0.25, 100.0
     w = I.free_stream(3, Ma)
-    kw = dict(W_inf=w, mu=Ma / Re, Pr=0.72, T_wall=1.0 / 1.4)
+    kw = dict(W_inf=w, mu=Ma / Re, Pr=0.72)
     W, dW = I.smooth_state(m, w, seed=21, amp=0.03)
     print(f"full-size sphere: {m['n_cell']} cells", flush=True)
     return dict(mesh=m, kw=kw, W=W, dW=dW, lm=cg.Mesh(m), om=oracle.Mesh(m), cache={})
