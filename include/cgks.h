@@ -45,7 +45,8 @@ typedef enum {
     CGKS_EMESH = 4,       /* invalid mesh: non-positive volume, face shared by > 2 cells,
                              unsupported face shape, stencil that fixes no linear fit */
     CGKS_ENONPHYS = 5,    /* density or pressure <= 0 met during a cycle */
-    CGKS_EDIVERGED = 6,   /* residual grew by 1e3 over its running minimum */
+    CGKS_EDIVERGED = 6,   /* residual grew to 1e3 times its first value (the start-up rise of an
+                             impulsive start stays well below that) */
     CGKS_ENOTCONV = 7,    /* cgks_solve hit max_cycles before the tolerance */
     CGKS_EUNSUPPORTED = 8 /* valid but not implemented (e.g. more colours than the sweep supports) */
 } cgks_status;

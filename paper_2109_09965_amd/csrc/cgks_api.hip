@@ -1015,7 +1015,7 @@ cgks_status cgks_solve(cgks_batch *b, const cgks_solve_opts *opts, cgks_solve_re
     hipStream_t s = static_cast<hipStream_t>(stream);
     const int n = b->n_case;
     const int every = std::max(1, opts->check_every);
-    std::vector<double> res(n), first(n, 0.0), best(n, INFINITY);
+    std::vector<double> first(n, 0.0);
     std::vector<int32_t> flag(n);
     std::vector<char> done(n, 0);
     int remaining = 0;
@@ -1047,7 +1047,8 @@ cgks_status cgks_solve(cgks_batch *b, const cgks_solve_opts *opts, cgks_solve_re
                 HIP_TRY(hipMemcpyAsync(hist.data() + size_t(j) * n, b->dev.res, sizeof(double) * n,
                                        hipMemcpyDeviceToHost, s));
             }
-        }        HIP_TRY(hipMemcpyAsync(flag.data(), b->dev.flag, sizeof(int32_t) * n, hipMemcpyDeviceToHost, s));
+        }
+        HIP_TRY(hipMemcpyAsync(flag.data(), b->dev.flag, sizeof(int32_t) * n, hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
         // every live case ran all `todo` cycles of the block; a stop seen at
         // any of them (or the non-physical flag, known per block only) takes
@@ -1062,10 +1063,9 @@ cgks_status cgks_solve(cgks_batch *b, const cgks_solve_opts *opts, cgks_solve_re
                 const int cyc = k + j + 1;
                 if (cyc == 1) rep[c].res_first = first[c] = r;
                 if (opts->res_history) opts->res_history[size_t(c) * opts->max_cycles + cyc - 1] = r;
-                best[c] = std::min(best[c], r);
                 if (cst != CGKS_OK || conv) continue;
                 if (!std::isfinite(r)) cst = CGKS_ENONPHYS;
-                else if (r > 1e3 * best[c]) cst = CGKS_EDIVERGED;
+                else if (r > 1e3 * first[c]) cst = CGKS_EDIVERGED;
                 else conv = opts->tol_abs ? r <= opts->tol : (first[c] > 0 && r / first[c] <= opts->tol);
             }
             if (cst == CGKS_OK && (flag[c] & 1)) cst = CGKS_ENONPHYS;
