@@ -137,6 +137,35 @@ def test_solve_freezes_converged_cases():
         assert not np.array_equal(W1, W2)
 
 
+def test_solve_reports_the_cycles_the_state_ran():
+    """With checks every 8 cycles (run as captured graphs) a case that meets
+    its tolerance inside a block stops at the check that ends the block: the
+    report counts those cycles, the history holds each of them, and the state
+    equals the case stepped eagerly for that many cycles, bitwise."""
+    m, kw, W, dW = case("cyl", 0)
+    lm = cg.Mesh(m)
+    b = cg.Batch([lm], [cg.Params(**kw)])
+    b.upload(0, W, dW)
+    _, href = b.solve(max_cycles=64, tol=0.0, check_every=1, history=True)
+    ratio = href[0] / href[0][0]
+    # a new running minimum of Res reached strictly inside a block of 8
+    met = next(c for c in range(9, 60) if c % 8 and ratio[c - 1] < ratio[:c - 1].min())
+    tol = ratio[met - 1]
+    b.upload(0, W, dW)
+    rep, hist = b.solve(max_cycles=64, tol=tol, check_every=8, history=True)
+    r = rep[0]
+    assert r["converged"] and r["cycles"] == 8 * (met // 8 + 1), (met, r)
+    np.testing.assert_array_equal(hist[0][:r["cycles"]], href[0][:r["cycles"]])
+    assert r["res_last"] == href[0][r["cycles"] - 1]
+    Ws, dWs = b.download(0)
+    e = cg.Batch([lm], [cg.Params(**kw)])
+    e.upload(0, W, dW)
+    for _ in range(r["cycles"]):
+        e.cycle()
+    We, dWe = e.download(0)
+    assert np.array_equal(Ws, We) and np.array_equal(dWs, dWe)
+
+
 @pytest.mark.parametrize("kinds,precision", [(["cyl", "cyl_small", "cyl"], cg.FP64), (["sphere", "sphere_b"], cg.FP64),
                                              (["sphere", "sphere_b"], cg.MIXED32)])
 def test_autotuned_batch_steps_bitwise_like_untuned(kinds, precision):
