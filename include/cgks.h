@@ -66,6 +66,7 @@ enum {
 };
 
 enum { CGKS_S2O4 = 0, CGKS_S1O2 = 1 };
+enum { CGKS_LOW_KFVS = 0, CGKS_LOW_LF = 1 };
 enum { CGKS_FP64 = 0, CGKS_MIXED32 = 1, CGKS_MIXED32_R64 = 2 };
 enum { CGKS_RESIDUAL_HIGH = 0, CGKS_RESIDUAL_LOW = 1, CGKS_RESIDUAL_NORM = 2 };
 
@@ -131,6 +132,10 @@ typedef struct {
     int32_t time_scheme;            /* CGKS_S2O4 or CGKS_S1O2 */
     int32_t explicit_only;
     double dt_fixed;
+    int32_t low_flux;               /* first-order flux of the low-order level (Sec. 3; Sec. 4 compares
+                                       the two): CGKS_LOW_KFVS (0, the paper's default) or CGKS_LOW_LF,
+                                       1/2 (F_n(U_L) + F_n(U_R)) - 1/2 lam_f (U_R - U_L) with the face's
+                                       spectral radius lam_f of the implicit operator; per case */
 } cgks_params;
 
 typedef struct cgks_mesh cgks_mesh;
@@ -138,8 +143,9 @@ typedef struct cgks_batch cgks_batch;
 
 /* Build faces' Gauss points (3 per triangle, 4 per quadrilateral with a
    normal at each point, 2 per 2-D edge), cell volumes, centroids and second
-   moments, the reconstruction operators, the multicolour classes (greedy,
-   smallest free colour, in caller cell order) and the library cell order
+   moments, the reconstruction operators, the multicolour classes
+   (largest-degree-first greedy colouring, classes numbered by size) and the
+   library cell order
    (tiles of order_tile cells along a Morton curve of the centroids,
    colour-major inside each tile).
    Host work only.  *out receives a handle (free with cgks_mesh_destroy).

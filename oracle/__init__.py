@@ -21,6 +21,7 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
 S2O4, S1O2 = 0, 1
+LOW_KFVS, LOW_LF = 0, 1
 
 
 def build(force: bool = True) -> str:
@@ -83,7 +84,7 @@ class _CParams(C.Structure):
     _fields_ = [("gamma", C.c_double), ("mu", C.c_double), ("Pr", C.c_double), ("T_wall", C.c_double),
                 ("W_inf", C.c_double * 5), ("cfl_high", C.c_double), ("cfl_low", C.c_double),
                 ("n_implicit", C.c_int), ("n_sweeps", C.c_int), ("time_scheme", C.c_int),
-                ("explicit_only", C.c_int), ("dt_fixed", C.c_double)]
+                ("explicit_only", C.c_int), ("dt_fixed", C.c_double), ("low_flux", C.c_int)]
 
 
 @dataclass
@@ -101,6 +102,7 @@ class Params:
     time_scheme: int = S2O4
     explicit_only: int = 0
     dt_fixed: float = 0.0
+    low_flux: int = LOW_KFVS
 
     def c(self):
         p = _CParams()
@@ -112,6 +114,7 @@ class Params:
         p.n_implicit, p.n_sweeps = self.n_implicit, self.n_sweeps
         p.time_scheme, p.explicit_only = self.time_scheme, self.explicit_only
         p.dt_fixed = self.dt_fixed
+        p.low_flux = self.low_flux
         return p
 
 

@@ -33,6 +33,7 @@ typedef struct {
     int time_scheme;   /* 0 = two-stage fourth order (S2O4), 1 = one-step second order (S1O2) */
     int explicit_only; /* 1: high-order step only, no low-order level */
     double dt_fixed;   /* > 0: use this global time step instead of the CFL rule */
+    int low_flux;      /* first-order flux of the low-order level: 0 KFVS, 1 Lax-Friedrichs */
 } om_params;
 
 typedef struct {
@@ -1421,7 +1422,29 @@ static int ghost_state(const om_mesh *m, const om_params *P, int bc, double e[3]
     return 0;
 }
 
-/* R0_i = -sum_f s S_f F_kfvs(U_L, U_R; n_f), first order, one flux per face */
+static void euler_flux(int dim, double gamma, const double *U, const double *n, double *F);
+static double side_radius(const om_mesh *m, const om_params *P, const double *U, long i, long f);
+
+/* First-order Lax-Friedrichs flux in the face frame (the low-order flux the
+   paper compares with KFVS in Sec. 4):
+     F = 1/2 (F_n(U_l) + F_n(U_r)) - 1/2 lam (U_r - U_l),
+   lam the spectral radius the implicit operator uses on this face, so that
+   the operator's splitting A+- = 1/2 (A +- lam I) is the flux's own
+   Jacobian at frozen lam. */
+static int lf_flux(int dim, double gamma, const double *Ul, const double *Ur, double lam, double *F) {
+    int nv = dim + 2;
+    prim a = to_prim(Ul, dim, gamma), b = to_prim(Ur, dim, gamma);
+    if (!(a.rho > 0) || !(a.p > 0) || !(b.rho > 0) || !(b.p > 0)) return -1;
+    const double e0[3] = {1.0, 0.0, 0.0};
+    double Fa[NVMAX], Fb[NVMAX];
+    euler_flux(dim, gamma, Ul, e0, Fa);
+    euler_flux(dim, gamma, Ur, e0, Fb);
+    for (int v = 0; v < nv; v++) F[v] = 0.5 * (Fa[v] + Fb[v]) - 0.5 * lam * (Ur[v] - Ul[v]);
+    return 0;
+}
+
+/* R0_i = -sum_f s S_f F(U_L, U_R; n_f), first order, one flux per face; F is
+   KFVS, or Lax-Friedrichs with the face's spectral radius (low_flux = 1) */
 int om_residual_low(const om_mesh *m, const om_params *P, const double *U, double *R0) {
     int d = m->dim, nv = m->nv;
     long N = m->n_cell;
@@ -1443,7 +1466,16 @@ int om_residual_low(const om_mesh *m, const om_params *P, const double *U, doubl
         }
         (void)UL;
         double Fl[NVMAX], F[NVMAX];
-        if (om_kfvs(d, P->gamma, Ul, Ur, Fl)) return -1;
+        if (P->low_flux == 1) {
+            double lam = side_radius(m, P, U, L, f);
+            if (R >= 0) {
+                double r = side_radius(m, P, U, R, f);
+                if (r > lam) lam = r;
+            }
+            if (lf_flux(d, P->gamma, Ul, Ur, lam, Fl)) return -1;
+        } else if (om_kfvs(d, P->gamma, Ul, Ur, Fl)) {
+            return -1;
+        }
         vec_to_global(d, e, Fl, F);
         for (int v = 0; v < nv; v++) {
             R0[v * N + L] -= m->S[f] * F[v];

@@ -21,6 +21,7 @@ _lib = None
 
 OK, EINVAL, ENOMEM, EDEVICE, EMESH, ENONPHYS, EDIVERGED, ENOTCONV, EUNSUPPORTED = range(9)
 S2O4, S1O2 = 0, 1
+LOW_KFVS, LOW_LF = 0, 1
 FP64, MIXED32, MIXED32_R64 = 0, 1, 2
 RESIDUAL_HIGH, RESIDUAL_LOW, RESIDUAL_NORM = 0, 1, 2
 
@@ -60,7 +61,7 @@ class _Params(C.Structure):
     _fields_ = [("gamma", C.c_double), ("mu", C.c_double), ("Pr", C.c_double), ("T_wall", C.c_double),
                 ("W_inf", C.c_double * 5), ("cfl_high", C.c_double), ("cfl_low", C.c_double),
                 ("n_implicit", C.c_int32), ("n_sweeps", C.c_int32), ("time_scheme", C.c_int32),
-                ("explicit_only", C.c_int32), ("dt_fixed", C.c_double)]
+                ("explicit_only", C.c_int32), ("dt_fixed", C.c_double), ("low_flux", C.c_int32)]
 
 
 class _SolveOpts(C.Structure):
@@ -158,6 +159,7 @@ class Params:
     time_scheme: int = S2O4
     explicit_only: int = 0
     dt_fixed: float = 0.0
+    low_flux: int = LOW_KFVS
 
     def c(self):
         p = _Params()
@@ -168,6 +170,7 @@ class Params:
         p.cfl_high, p.cfl_low = self.cfl_high, self.cfl_low
         p.n_implicit, p.n_sweeps = self.n_implicit, self.n_sweeps
         p.time_scheme, p.explicit_only, p.dt_fixed = self.time_scheme, self.explicit_only, self.dt_fixed
+        p.low_flux = self.low_flux
         return p
 
 

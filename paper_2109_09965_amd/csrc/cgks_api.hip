@@ -239,6 +239,7 @@ DevParams dev_params(const cgks_params &p, int dim) {
     q.K = dim == 3 ? (5.0 - 3.0 * p.gamma) / (p.gamma - 1.0) : (4.0 - 2.0 * p.gamma) / (p.gamma - 1.0);
     q.scheme = p.time_scheme;
     q.explicit_only = p.explicit_only;
+    q.low_flux = p.low_flux;
     q.active = 1;
     return q;
 }
@@ -521,7 +522,7 @@ static bool params_ok(const cgks_batch *b, const cgks_params &p) {
     return p.n_implicit == b->n_implicit && p.n_sweeps == b->n_sweeps && p.time_scheme == b->scheme &&
            p.explicit_only == b->explicit_only && p.n_implicit >= 0 && p.n_sweeps >= 0 &&
            (p.time_scheme == CGKS_S2O4 || p.time_scheme == CGKS_S1O2) && p.gamma > 1.0 && p.mu >= 0 && p.Pr > 0 &&
-           p.T_wall > 0 && p.cfl_high > 0 && p.cfl_low > 0;
+           p.T_wall > 0 && p.cfl_high > 0 && p.cfl_low > 0 && (p.low_flux == CGKS_LOW_KFVS || p.low_flux == CGKS_LOW_LF);
 }
 
 static cgks_status new_pool(const cgks_pool_desc &q, cgks_batch **out) {

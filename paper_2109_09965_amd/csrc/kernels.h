@@ -30,7 +30,7 @@ struct DevParams {
     double cfl_high, cfl_low, dt_fixed;
     double K;          // internal degrees of freedom of the gas
     int32_t explicit_only;
-    int32_t pad;
+    int32_t low_flux;  // 0 KFVS, 1 Lax-Friedrichs (low-order level)
 };
 static_assert(offsetof(DevParams, active) == 8, "gamma and active in the first 16 bytes");
 
@@ -1243,7 +1243,8 @@ template <int D, typename S> __device__ __forceinline__ void low_state(const Dev
     }
 }
 
-// lowf[f] = S_f F_kfvs(U_L, U_R; n_f); swp[f][D] = S_f lam_f.
+// lowf[f] = S_f F(U_L, U_R; n_f), F the case's first-order flux (KFVS or
+// Lax-Friedrichs); swp[f][D] = S_f lam_f.
 template <int D, typename S> __global__ __launch_bounds__(kBlock) void k_low_face(Dev d, int src) {
     constexpr int nv = D + 2;
     const int f = xcd_block(blockIdx.x, gridDim.x) * int(blockDim.x) + threadIdx.x;
@@ -1285,9 +1286,24 @@ template <int D, typename S> __global__ __launch_bounds__(kBlock) void k_low_fac
         }
     }
     double Fl[nv], F[nv];
+    bool ok;
+    if (P.low_flux == 1) {
+        // Lax-Friedrichs with the face's spectral radius
+        Prim<D, double> a, c;
+        a.from(Ul, P.gamma);
+        c.from(Ur, P.gamma);
+        ok = a.rho > 0.0 && a.p > 0.0 && c.rho > 0.0 && c.p > 0.0;
+        const double e0[D] = {1.0};
+        double Fa[nv], Fb[nv];
+        euler_flux<D>(Ul, e0, P.gamma, Fa);
+        euler_flux<D>(Ur, e0, P.gamma, Fb);
 #pragma unroll
-    for (int v = 0; v < nv; ++v) Fl[v] = 0.0;
-    const bool ok = half_side<D, double>(Ul, P, 1.0, nullptr, Fl) && half_side<D, double>(Ur, P, -1.0, nullptr, Fl);
+        for (int v = 0; v < nv; ++v) Fl[v] = 0.5 * (Fa[v] + Fb[v]) - 0.5 * lam * (Ur[v] - Ul[v]);
+    } else {
+#pragma unroll
+        for (int v = 0; v < nv; ++v) Fl[v] = 0.0;
+        ok = half_side<D, double>(Ul, P, 1.0, nullptr, Fl) && half_side<D, double>(Ur, P, -1.0, nullptr, Fl);
+    }
     flag_nonphysical(d.flag, !ok, cs);
     fr.to_global(Fl, F);
 #pragma unroll

@@ -187,6 +187,26 @@ def test_state_does_not_depend_on_the_tile_size(precision):
         assert np.array_equal(Wt, out[0][0]) and np.array_equal(dWt, out[0][1])
 
 
+@pytest.mark.parametrize("name", ["cyl2d_adiab", "box3d_per", "cubed_sphere_adiab"])
+def test_lax_friedrichs_low_level(name):
+    """The Lax-Friedrichs low-level flux: R0 and three whole cycles against
+    the oracle."""
+    import torch
+    p = Pair(name, low_flux=cg.LOW_LF)
+    W, dW = p.W0.copy(), p.dW0.copy()
+    R0 = p.os.residual_low(W)
+    R0g = p.b.to_caller(0, p.b.residual(cg.RESIDUAL_LOW).cpu().numpy())
+    e0 = rel(R0g, R0)
+    print(f"{name} LF: R0 rel err {e0:.2e}", flush=True)
+    assert e0 <= TOL_W
+    res = torch.zeros(1, dtype=torch.float64, device="cuda")
+    for k in range(3):
+        r_or = p.os.cycle(W, dW)
+        p.b.cycle(res)
+        check_state(p, W, dW, f"{name} LF cycle{k}")
+        assert abs(float(res.cpu()[0]) - r_or) <= 1e-9 * r_or
+
+
 def test_explicit_only_cycles():
     p = Pair("cyl2d_visc", explicit_only=1)
     W, dW = p.W0.copy(), p.dW0.copy()

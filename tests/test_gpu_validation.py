@@ -78,3 +78,37 @@ def test_two_level_cycle_accelerates_steady_convergence():
         print(f"explicit_only={expl}: {r['cycles']} cycles, residual drop {hh[-1] / hh[0]:.2e}", flush=True)
     assert drops[0][1] <= 1e-10
     assert drops[1][1] > 1e-8, drops
+
+
+@pytest.mark.parametrize("scheme", [cg.S1O2, cg.S2O4])
+def test_low_level_flux_choice(scheme):
+    """Sec. 4 (cylinder): KFVS and Lax-Friedrichs on the low level converge
+    alike.  Under S1O2 the transferred residual R1 is exactly the explicit
+    step's increment over dt, so the cycle can only stand still where R1 = 0:
+    the converged state is the same for both low-level fluxes (to the residual
+    level reached).  Under S2O4 the step's increment and R1 vanish at states
+    that differ at O(dt^2); the cycle stands still where the correction
+    cancels the increment, which depends slightly on the low-level operator."""
+    g = GOLD["cylinder_re40"]
+    m = I.cylinder_mesh(64, 32, 0.5, ratio=1.1, first_spacing=0.09695, wall=I.BC_NOSLIP_ADIABATIC)
+    w = I.free_stream(2, g["Ma"])
+    lm = cg.Mesh(m)
+    out = {}
+    for lf in (cg.LOW_KFVS, cg.LOW_LF):
+        b = cg.Batch([lm], [cg.Params(W_inf=w, mu=g["Ma"] / g["Re"], Pr=0.72, low_flux=lf, time_scheme=scheme)])
+        W, dW = I.uniform_state(m, w)
+        b.upload(0, W, dW)
+        rep, _ = b.solve(max_cycles=6000, tol=1e-12, check_every=8)
+        r = rep[0]
+        out[lf] = (r["cycles"], b.download(0)[0], cg.drag_coefficient(r["force"], w, 1.0))
+        print(f"scheme {scheme} low flux {lf}: {r['cycles']} cycles, converged {r['converged']}, "
+              f"Cd {out[lf][2]:.8f}", flush=True)
+        assert r["converged"], r
+    (ck, Wk, cdk), (cl, Wl, cdl) = out[cg.LOW_KFVS], out[cg.LOW_LF]
+    dw = np.abs(Wk - Wl).max() / np.abs(Wk).max()
+    print(f"state difference {dw:.2e}, Cd difference {abs(cdk - cdl):.2e}", flush=True)
+    if scheme == cg.S1O2:
+        assert dw <= 1e-9 and abs(cdk - cdl) <= 1e-8
+    else:
+        assert dw <= 1e-4 and abs(cdk - cdl) <= 1e-4 * cdk
+    assert 0.5 <= cl / ck <= 2.0

@@ -21,12 +21,13 @@ def run_cycles(mesh, params, W, dW, n):
     (lambda: I.box2d_mesh(8, perturb=0.3, seed=2), 0.5, 30.0, 0.02, 0.72),
     (lambda: I.box3d_mesh((3, 3, 5), periodic=True, perturb=0.2, seed=4), 0.4, 20.0, 0.01, 0.72),
 ])
-def test_free_stream_is_preserved(mk, mach, aoa, mu, Pr):
+@pytest.mark.parametrize("low_flux", [oracle.LOW_KFVS, oracle.LOW_LF])
+def test_free_stream_is_preserved(mk, mach, aoa, mu, Pr, low_flux):
     mesh = mk()
     d = mesh["dim"]
     Winf = I.free_stream(d, mach, aoa)
     W, dW = I.uniform_state(mesh, Winf)
-    _, res = run_cycles(mesh, oracle.Params(W_inf=Winf, mu=mu, Pr=Pr), W, dW, 20)
+    _, res = run_cycles(mesh, oracle.Params(W_inf=Winf, mu=mu, Pr=Pr, low_flux=low_flux), W, dW, 20)
     assert np.abs(W - Winf[:, None]).max() <= 1e-13
     assert np.abs(dW).max() <= 1e-12
     assert max(res) <= 1e-14
@@ -34,17 +35,19 @@ def test_free_stream_is_preserved(mk, mach, aoa, mu, Pr):
 
 @pytest.mark.parametrize("mk", [lambda: I.box2d_mesh(8, perturb=0.3, seed=2),
                                 lambda: I.box3d_mesh((3, 3, 5), periodic=True, perturb=0.2, seed=4)])
-@pytest.mark.parametrize("scheme", [oracle.S2O4, oracle.S1O2])
-def test_periodic_conservation(mk, scheme):
+@pytest.mark.parametrize("scheme,low_flux", [(oracle.S2O4, oracle.LOW_KFVS), (oracle.S1O2, oracle.LOW_KFVS),
+                                             (oracle.S2O4, oracle.LOW_LF)])
+def test_periodic_conservation(mk, scheme, low_flux):
     """Each face flux enters its two cells with opposite signs: the high-order
-    stages conserve sum |V| W and the residuals of both levels sum to zero."""
+    stages conserve sum |V| W and the residuals of both levels (KFVS or
+    Lax-Friedrichs on the low one) sum to zero."""
     mesh = mk()
     d = mesh["dim"]
     Winf = I.free_stream(d, 0.3, 15.0)
     W, dW = I.smooth_state(mesh, Winf, seed=3, amp=0.05)
     om = oracle.Mesh(mesh)
     vol = om.cells()["vol"]
-    s = oracle.Solver(om, oracle.Params(W_inf=Winf, mu=0.01, Pr=0.72, time_scheme=scheme))
+    s = oracle.Solver(om, oracle.Params(W_inf=Winf, mu=0.01, Pr=0.72, time_scheme=scheme, low_flux=low_flux))
     tot0 = W @ vol
     s.stage(0, W, dW)
     np.testing.assert_allclose(W @ vol, tot0, rtol=1e-14, atol=1e-14)
@@ -141,7 +144,8 @@ def test_time_marching_closed_forms(z):
 
 
 @pytest.mark.parametrize("mk", [lambda: I.cylinder_mesh(32, 16), lambda: I.sphere_mesh(6, 12, 6, 2, 2)])
-def test_s1o2_residual_is_the_step_increment(mk):
+@pytest.mark.parametrize("low_flux", [oracle.LOW_KFVS, oracle.LOW_LF])
+def test_s1o2_residual_is_the_step_increment(mk, low_flux):
     """R1 is the time-averaged net flux over one step, so with one time step
     |V|^-1 dt R1 is exactly the S1O2 increment from the same state.  Hence a
     state the explicit S1O2 scheme leaves unchanged has R1 = 0, the forcing
@@ -153,7 +157,8 @@ def test_s1o2_residual_is_the_step_increment(mk):
     W, dW = I.smooth_state(mesh, Winf, seed=7, amp=0.03)
     om = oracle.Mesh(mesh)
     vol = om.cells()["vol"]
-    P = oracle.Params(W_inf=Winf, mu=0.01 if d == 3 else 0.0, Pr=0.72, time_scheme=oracle.S1O2, dt_fixed=2e-3)
+    P = oracle.Params(W_inf=Winf, mu=0.01 if d == 3 else 0.0, Pr=0.72, time_scheme=oracle.S1O2, dt_fixed=2e-3,
+                      low_flux=low_flux)
     s = oracle.Solver(om, P)
     W1, dW1 = W.copy(), dW.copy()
     s.stage(0, W1, dW1)
@@ -164,6 +169,34 @@ def test_s1o2_residual_is_the_step_increment(mk):
     Wl = W.copy()
     s.lowlevel(Wl, np.zeros_like(W))
     np.testing.assert_allclose(Wl, W, rtol=0, atol=1e-14)
+
+
+@pytest.mark.parametrize("low_flux", [oracle.LOW_KFVS, oracle.LOW_LF])
+def test_low_level_residual_diffuses_a_density_bump_at_rest(low_flux):
+    """Gas at rest at uniform pressure with a density bump: the Euler flux
+    carries no mass, so the first-order mass residual is the flux's
+    numerical dissipation alone.  Both low-level fluxes must move mass from
+    the densest cell to its neighbours and into the least dense cell (a wrong
+    sign of the dissipation term turns this around), and Lax-Friedrichs
+    (dissipation lam_f >= c, the sound speed) more strongly than KFVS
+    (whose mass dissipation at rest is sqrt(theta / 2 pi) < c per side)."""
+    mesh = I.box2d_mesh(10, perturb=0.2, seed=5)
+    om = oracle.Mesh(mesh)
+    x = om.cells()["ctr"]
+    n = mesh["n_cell"]
+    rho = 1.0 + 0.2 * np.exp(-((x[:, 0] - 1.0) ** 2 + (x[:, 1] - 1.0) ** 2) / 0.1)
+    W = np.zeros((4, n))
+    W[0] = rho
+    W[3] = (1.0 / 1.4) / 0.4
+    out = {}
+    for lf in (oracle.LOW_KFVS, oracle.LOW_LF):
+        s = oracle.Solver(om, oracle.Params(W_inf=I.free_stream(2, 0.0), low_flux=lf))
+        out[lf] = s.residual_low(W)
+    R = out[low_flux]
+    imax, imin = int(np.argmax(rho)), int(np.argmin(rho))
+    assert R[0, imax] < 0 < R[0, imin]
+    assert abs(R[0].sum()) <= 1e-14 * np.abs(R[0]).sum()
+    assert np.abs(out[oracle.LOW_LF][0, imax]) > np.abs(out[oracle.LOW_KFVS][0, imax])
 
 
 def tri_cell_vertices(mesh):
