@@ -266,12 +266,18 @@ def _tet_faces(t):
     return [(p, q, r), (p, q, s), (p, r, s), (q, r, s)]
 
 
+# six pyramids per hex: each hex face (corner ids i + 2j + 4k) is the base of
+# one pyramid whose apex is the hex's centre, local vertex 8
+_HEX_FACES = [(0, 2, 6, 4), (1, 3, 7, 5), (0, 1, 5, 4), (2, 3, 7, 6), (0, 1, 3, 2), (4, 5, 7, 6)]
+_PYRAMIDS = [[base] + [(base[e], base[(e + 1) % 4], 8) for e in range(4)] for base in _HEX_FACES]
+
 LAYER_TEMPLATES = {
     "hex": [_HEX],
     "hex7": [_HEX7],
     "hex7b": [_HEX7B],
     "prism": [_PRISM_A, _PRISM_B],
     "tet": [_tet_faces(t) for t in _KUHN],
+    "pyr": _PYRAMIDS,   # conforming with hex layers (quad faces) only
 }
 
 
@@ -300,9 +306,17 @@ def _hybrid_grid(ni, nj, layer_types, gid, tid, coords, classify, cells=None):
         I, J = (np.asarray(c, np.int64) for c in cells)
     faces, cof, cell_vs = [], [], []
     ncell = 0
+    corners = [np.stack([gid(I + (l & 1), J + ((l >> 1) & 1), np.full_like(I, k) + ((l >> 2) & 1))
+                         for l in range(8)], 1) for k in range(len(layer_types))]
+    # hex centres (apexes of pyramid layers) get ids after every corner id
+    base_id = int(max(G.max() for G in corners)) + 1
+    centre_of = []                      # [n_centre, 8] corner ids of each centre
     for k, lt in enumerate(layer_types):
-        K = np.full_like(I, k)
-        G = np.stack([gid(I + (l & 1), J + ((l >> 1) & 1), K + ((l >> 2) & 1)) for l in range(8)], 1)
+        G = corners[k]
+        if lt == "pyr":
+            first = base_id + sum(len(c) for c in centre_of)
+            G = np.concatenate([G, (first + np.arange(len(I)))[:, None]], 1)
+            centre_of.append(corners[k])
         for tmpl in LAYER_TEMPLATES[lt]:
             fl = []
             for f in tmpl:
@@ -326,9 +340,13 @@ def _hybrid_grid(ni, nj, layer_types, gid, tid, coords, classify, cells=None):
     all_ids = np.unique(F[F >= 0])
     n_vert = int(all_ids.max() + 1)
     xyz = np.zeros((n_vert, 3))
-    xyz[all_ids] = coords(all_ids)
+    cid = all_ids[all_ids < base_id]
+    xyz[cid] = coords(cid)
     topo = np.arange(n_vert, dtype=np.int64)
-    topo[all_ids] = tid(all_ids)
+    topo[cid] = tid(cid)
+    if centre_of:
+        C = np.concatenate(centre_of)
+        xyz[base_id:base_id + len(C)] = coords(C.ravel()).reshape(len(C), 8, 3).mean(1)
     ctr = _fast_ctr(ncell, cell_vs, xyz)
     F = _orient_fast(F, cnt, cof, xyz, ctr)
     return _assemble(3, xyz, topo, F, cnt, cof, ncell, classify)

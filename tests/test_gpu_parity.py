@@ -40,6 +40,10 @@ def make_case(name):
         m = I.box3d_mesh((3, 3, 5), periodic=True, perturb=0.2, seed=4)
         Winf = I.free_stream(3, 0.4, 20.0)
         kw = dict(W_inf=Winf, mu=0.01, Pr=0.72)
+    elif name == "box3d_pyr":
+        m = I.box3d_mesh((3, 3, 4), layer_types=["hex", "pyr", "hex", "pyr"], periodic=True, perturb=0.2, seed=3)
+        Winf = I.free_stream(3, 0.35, 25.0)
+        kw = dict(W_inf=Winf, mu=0.01, Pr=0.72)
     elif name == "box3d_slip":
         m = I.box3d_mesh((4, 3, 5), perturb=0.2, seed=6, bc=I.BC_SLIP_WALL)
         Winf = I.free_stream(3, 0.3, 15.0)
@@ -62,8 +66,8 @@ def make_case(name):
     return m, kw, W, dW
 
 
-CASES = ["cyl2d_slip", "cyl2d_visc", "cyl2d_adiab", "box2d_per", "box3d_per", "box3d_slip", "sphere", "cubed_sphere",
-         "cubed_sphere_adiab"]
+CASES = ["cyl2d_slip", "cyl2d_visc", "cyl2d_adiab", "box2d_per", "box3d_per", "box3d_pyr", "box3d_slip", "sphere",
+         "cubed_sphere", "cubed_sphere_adiab"]
 
 
 class Pair:

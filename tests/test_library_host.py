@@ -31,7 +31,7 @@ def test_library_exports_every_declared_symbol():
 @pytest.mark.parametrize("mk", [I.cylinder_case_mesh, lambda: I.sphere_mesh(8, 16, 10, 4, 3),
                                 lambda: I.cubed_sphere_mesh(4, 10, 4, 3),
                                 lambda: I.box3d_mesh((3, 3, 5), periodic=True, perturb=0.2, seed=4),
-                                lambda: I.box2d_mesh(6, perturb=0.3, seed=2)])
+                                lambda: I.box2d_mesh(6, perturb=0.3, seed=2), lambda: I.box3d_mesh((3, 3, 4), layer_types=["hex", "pyr", "hex", "pyr"], periodic=True, perturb=0.2, seed=3)])
 def test_host_geometry_and_colouring_match_oracle(mk):
     mesh = mk()
     lm = cg.Mesh(mesh)

@@ -40,11 +40,14 @@ def test_single_cells_volume_centroid_moments():
     np.testing.assert_allclose(tr["vol"], [2.0, 2.0], atol=1e-14)
 
 
-@pytest.mark.parametrize("L,n,pert", [((1.0, 1.0, 1.0), (2, 2, 5), 0.0), ((1.0, 2.0, 0.5), (3, 2, 5), 0.3)])
-def test_cells_tile_the_box(L, n, pert):
+@pytest.mark.parametrize("L,n,pert,layers", [((1.0, 1.0, 1.0), (2, 2, 5), 0.0, None),
+                                              ((1.0, 2.0, 0.5), (3, 2, 5), 0.3, None),
+                                              ((1.0, 2.0, 0.5), (3, 2, 4), 0.3, ["pyr", "hex", "pyr", "hex"])])
+def test_cells_tile_the_box(L, n, pert, layers):
     """Sum over cells of the raw moments equals the box integrals, for every
-    cell type (hex, 7-face hex, prisms, Kuhn tets) and non-planar faces."""
-    m = oracle.Mesh(I.box3d_mesh(n, L=L, perturb=pert, seed=1)).cells()
+    cell type (hex, 7-face hex, prisms, Kuhn tets, pyramids) and non-planar
+    faces."""
+    m = oracle.Mesh(I.box3d_mesh(n, L=L, perturb=pert, seed=1, layer_types=layers)).cells()
     V = np.prod(L)
     assert m["vol"].min() > 0
     assert m["vol"].sum() == pytest.approx(V, rel=1e-13)
@@ -151,7 +154,7 @@ def cell_face_sums(mesh, fa, fn):
                                 lambda: I.sphere_mesh(6, 12, 6, 2, 2),
                                 lambda: I.cubed_sphere_mesh(4, 6, 2, 2),
                                 lambda: I.box2d_mesh(5, perturb=0.3, seed=1),
-                                lambda: I.cylinder_mesh(12, 6)])
+                                lambda: I.cylinder_mesh(12, 6), lambda: I.box3d_mesh((3, 3, 4), layer_types=["pyr", "hex", "pyr", "hex"], perturb=0.3, seed=5)])
 def test_closure_and_gauss_green_on_linear_field(mk):
     mesh = mk()
     om = oracle.Mesh(mesh)
@@ -168,7 +171,7 @@ def test_closure_and_gauss_green_on_linear_field(mk):
                                 lambda: I.sphere_mesh(6, 12, 8, 3, 2),
                                 lambda: I.cubed_sphere_mesh(3, 8, 3, 2),
                                 lambda: I.box2d_mesh(6, periodic=False, perturb=0.3, seed=1),
-                                lambda: I.cylinder_mesh(12, 6)])
+                                lambda: I.cylinder_mesh(12, 6), lambda: I.box3d_mesh((3, 3, 4), layer_types=["pyr", "hex", "pyr", "hex"], perturb=0.3, seed=5)])
 def test_reconstruction_exact_for_quadratics(mk):
     """Cell averages and averaged gradients of a global quadratic give back
     that quadratic and its gradient at every face Gauss point."""
@@ -244,7 +247,7 @@ def test_workload_stencils_are_full_rank(mk):
 
 @pytest.mark.parametrize("mk", [I.cylinder_case_mesh, lambda: I.sphere_mesh(8, 16, 8, 3, 2),
                                 lambda: I.cubed_sphere_mesh(4, 8, 3, 2),
-                                lambda: I.box3d_mesh((3, 3, 5), periodic=True)])
+                                lambda: I.box3d_mesh((3, 3, 5), periodic=True), lambda: I.box3d_mesh((3, 3, 4), layer_types=["hex", "pyr", "hex", "pyr"], periodic=True, perturb=0.2, seed=3)])
 def test_colouring_is_an_independent_set(mk):
     mesh = mk()
     om = oracle.Mesh(mesh)
