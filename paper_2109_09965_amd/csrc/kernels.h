@@ -375,10 +375,33 @@ template <int D, typename R> __device__ bool gks_flux(const R *Wc, const R Gc[D]
     return true;
 }
 
+// Maclaurin coefficients of erf, (-1)^n / (n! (2n + 1)) (Abramowitz and
+// Stegun 7.1.5), folded to constants at compile time
+__host__ __device__ constexpr double erf_series_coef(int n) {
+    double f = 1.0;
+    for (int k = 2; k <= n; ++k) f *= k;
+    return (n % 2 ? -1.0 : 1.0) / (f * (2 * n + 1));
+}
+
+// 1 + erf(y) = erfc(-y).  For |y| <= 1/2 the first term left out of twelve
+// is below 1e-17 of the leading one (double rounding), the first left out
+// of seven below 1e-9 (single); larger |y| take the library erfc.
+template <typename R> __device__ __forceinline__ R one_plus_erf(R y) {
+    constexpr int nt = sizeof(R) == 8 ? 12 : 7;
+    if (fabs(y) <= R(0.5)) {
+        const R y2 = y * y;
+        R s = R(erf_series_coef(nt - 1));
+#pragma unroll
+        for (int n = nt - 2; n >= 0; --n) s = s * y2 + R(erf_series_coef(n));
+        return R(1.0) + R(1.1283791670955126) * y * s;   // 2 / sqrt(pi)
+    }
+    return erfc(-y);
+}
+
 // half-range moments <u^k>_{u >< 0}, k = 0..3
 template <typename R> __device__ __forceinline__ void half_moments(R U, R lam, R sgn, R *m) {
     const R hl = R(0.5) / lam;   // 1/(2 lam)
-    m[0] = R(0.5) * erfc(-sgn * sqrt(lam) * U);
+    m[0] = R(0.5) * one_plus_erf<R>(sgn * sqrt(lam) * U);
     m[1] = U * m[0] + sgn * R(0.5) * exp(-lam * U * U) * rsqrt(R(M_PI) * lam);
     m[2] = U * m[1] + hl * m[0];
     m[3] = U * m[2] + R(2.0) * hl * m[1];
