@@ -28,22 +28,22 @@ VALU_PEAK_TFLOPS = {"fp64": 78.6, "mixed32": 157.3, "mixed32_r64": 78.6}
 # (FMA = 2), from the VALU instruction counters of one launch on the
 # sphere workload (SQ_INSTS_VALU_{FMA,MUL,ADD,TRANS}_F64 resp. _F32, x 64
 # lanes), charged to the lanes that carry a Gauss point.
-FLUX_FLOP_PER_GP = {"fp64": 1909.0, "mixed32": 1705.0, "mixed32_r64": (2 * 1705.0 + 1909.0) / 3.0}
+FLUX_FLOP_PER_GP = {"fp64": 1733.0, "mixed32": 1627.0, "mixed32_r64": (2 * 1627.0 + 1733.0) / 3.0}
 
 # HBM bytes per launch from rocprofv3 FETCH_SIZE (x 2.0) and WRITE_SIZE
 # (x 1.0) on the sphere workload, each factor from a plain device copy of
 # known size.  Valid only for the kernel source they were taken on (its
 # SHA-256); any other source reports null.
-PROFILED_KERNELS_SHA256 = "9d30f73579b07af89bb455977099131565f94a2d4fa0043a8bfc3230484780c2"
+PROFILED_KERNELS_SHA256 = "a25d7205f9b4cafe248b1dd9decf1b252d0c5b40a2f90e2c63d3aa4cf0593399"
 PROFILED_TRAFFIC = {           # (kernel kind, precision) -> bytes per launch
-    ("dt", "fp64"): 79177578.1, ("dt", "mixed32"): 79177468.4,
-    ("recon", "fp64"): 678968786.3, ("recon", "mixed32"): 635464737.1,   # with the boundary ghost pre-pass
-    ("flux", "fp64"): 825385461.3, ("flux", "mixed32"): 538532734.0,
-    ("cell", "fp64"): 785571397.8, ("cell", "mixed32"): 399836821.4,
-    ("low_face", "fp64"): 183769066.5, ("low_face", "mixed32"): 175811667.1,
-    ("low_cell", "fp64"): 256209261.0, ("low_cell", "mixed32"): 242059802.9,  # 1 forcing + 5 step launches
-    ("sweep", "fp64"): 56913584.5, ("sweep", "mixed32"): 42842009.4,          # average over colour classes
-    ("prolong", "fp64"): 173976724.0, ("prolong", "mixed32"): 163417429.1,
+    ("dt", "fp64"): 79171468.3, ("dt", "mixed32"): 79171322.0,
+    ("recon", "fp64"): 678861672.4, ("recon", "mixed32"): 634255387.9,   # with the boundary ghost pre-pass
+    ("flux", "fp64"): 826632834.2, ("flux", "mixed32"): 538591387.8,
+    ("cell", "fp64"): 785694505.2, ("cell", "mixed32"): 399790245.8,
+    ("low_face", "fp64"): 183670243.1, ("low_face", "mixed32"): 175698820.5,
+    ("low_cell", "fp64"): 256193060.3, ("low_cell", "mixed32"): 242040724.6,  # 1 forcing + 5 step launches
+    ("sweep", "fp64"): 56908783.7, ("sweep", "mixed32"): 42832334.9,          # average over colour classes
+    ("prolong", "fp64"): 174301912.4, ("prolong", "mixed32"): 160882068.9,
 }
 
 
