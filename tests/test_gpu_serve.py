@@ -24,7 +24,7 @@ def small_trace(n=10, seed=3):
             re = float(rng.uniform(50, 150))
         else:
             nt = int(rng.choice([16, 24, 32]))
-            m = I.cylinder_mesh(nt, nt // 2, r_far=10.0, wall=I.BC_NOSLIP_ISOTHERMAL)
+            m = I.cylinder_mesh(nt, nt // 2, r_far=10.0, wall=I.BC_NOSLIP_ADIABATIC)
             re = float(rng.uniform(10, 40))
         specs.append((float(t[k]), m, mach, re))
     return specs
