@@ -12,6 +12,13 @@
  * Where the paper defers a detail to other work the reading taken here is
  * named in the comment of the function that implements it.
  *
+ * Parity unpinned (no check independent of this file beyond agreement with
+ * the HIP path and behavioural tests): the weights of the reconstruction's
+ * least-squares rows (recon_cell; its exactness on quadratic data is
+ * pinned), the high-order time-step rule (cell_dt, om_dt), the spectral
+ * radius of the implicit operator (side_radius) and the low level's local
+ * time step (cell_dt with cfl_low).
+ *
  * Build: gcc -O2 -fno-fast-math -ffp-contract=off -fPIC -shared.
  */
 #include <math.h>
