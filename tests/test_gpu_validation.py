@@ -1,5 +1,6 @@
-"""Converged drag against the values the paper prints (Sec. 4), through the
-C ABI, with the no-slip adiabatic wall of the paper's viscous cases.
+"""Converged drag, wake length and separation angle against the values the
+paper prints (Sec. 4), through the C ABI, with the no-slip adiabatic wall
+of the paper's viscous cases.
 
 These are behavioural checks of the whole method, not parity: the paper's
 numbers come from finer meshes than the ones run here, so the tolerance is
@@ -23,7 +24,33 @@ pytestmark = pytest.mark.gpu
 GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "drag_paper.json")))
 
 
-def converged_cd(m, Ma, Re, area, max_cycles):
+def wake_and_separation(m, W, n_theta):
+    """Wake length (rear of the cylinder to where the centreline velocity
+    turns positive, in diameters) and separation angle (from the rear
+    stagnation point, where the first wall layer's tangential velocity
+    changes sign), from the converged cell averages of the O-mesh."""
+    vol, cen, h, lin = cg.Mesh(m).geometry()
+    cen = np.asarray(cen)
+    cen = cen if cen.shape[0] == m["n_cell"] else cen.T
+    x, y = cen[:, 0], cen[:, 1]
+    r, th = np.hypot(x, y), np.arctan2(y, x)
+    u, v = W[1] / W[0], W[2] / W[0]
+    sel = (np.abs(th) < 2 * np.pi / n_theta) & (x > 0)
+    o = np.argsort(r[sel])
+    rs, us = r[sel][o], u[sel][o]
+    j = np.nonzero((us[:-1] < 0) & (us[1:] >= 0))[0][0]
+    wake = rs[j] - us[j] * (rs[j + 1] - rs[j]) / (us[j + 1] - us[j]) - 0.5
+    radii = np.unique(np.round(r, 6))
+    wall = (r < radii[0] + 0.6 * (radii[2] - radii[0])) & (y > 0)
+    tw, uw = th[wall], (-u * np.sin(th) + v * np.cos(th))[wall]
+    o = np.argsort(tw)
+    tw, uw = tw[o], uw[o]
+    j = np.nonzero(np.sign(uw[:-1]) != np.sign(uw[1:]))[0][0]
+    sep = np.degrees(tw[j] - uw[j] * (tw[j + 1] - tw[j]) / (uw[j + 1] - uw[j]))
+    return wake, sep
+
+
+def converged_cd(m, Ma, Re, area, max_cycles, state=None):
     w = I.free_stream(m["dim"], Ma)
     b = cg.Batch([cg.Mesh(m)], [cg.Params(W_inf=w, mu=Ma / Re, Pr=0.72)])
     W, dW = I.uniform_state(m, w)
@@ -34,15 +61,24 @@ def converged_cd(m, Ma, Re, area, max_cycles):
     print(f"{m['name'] if 'name' in m else m['dim']}: {r['cycles']} cycles, converged {r['converged']}, "
           f"Cd {cd:.4f}", flush=True)
     assert r["converged"], r
+    if state is not None:
+        state.append(b.download(0)[0])
     return cd
 
 
-def test_cylinder_re40_drag_matches_paper():
+def test_cylinder_re40_matches_paper():
     g = GOLD["cylinder_re40"]
-    cds = []
+    cds, states = [], []
     for nt, nr, ratio, h in ((64, 32, 1.1, 0.09695), (128, 64, 1.06, 0.05)):
         m = I.cylinder_mesh(nt, nr, 0.5, ratio=ratio, first_spacing=h, wall=I.BC_NOSLIP_ADIABATIC)
-        cds.append(converged_cd(m, g["Ma"], g["Re"], 1.0, 6000))
+        cds.append(converged_cd(m, g["Ma"], g["Re"], 1.0, 6000, states))
+    # the finer mesh (Mesh I's near-wall size): wake length and separation
+    # angle within the spread of the values printed beside the paper's
+    wake, sep = wake_and_separation(m, states[-1], 128)
+    print(f"wake length {wake:.3f} (paper {g['wake_length']}), separation angle {sep:.2f} deg "
+          f"(paper {g['separation_angle_deg']})", flush=True)
+    assert abs(wake - g["wake_length"]) <= 0.05 * g["wake_length"]
+    assert abs(sep - g["separation_angle_deg"]) <= 1.5
     lo, hi = g["Cd_experiment_range"]
     for cd in cds:
         assert lo <= cd <= hi
