@@ -86,10 +86,49 @@ def test_cylinder_re40_matches_paper():
     assert abs(cds[0] - cds[1]) <= 0.01 * g["Cd"]
 
 
-def test_sphere_re118_drag_matches_paper():
+def sphere_wake_and_separation(m, W):
+    """Closed-wake length along the rear axis (diameters, from the rear of the
+    sphere) and separation angle from the front stagnation point, where the
+    azimuthal mean of the first wall layer's meridional velocity changes
+    sign (2-degree bins)."""
+    vol, cen, h, lin = cg.Mesh(m).geometry()
+    cen = np.asarray(cen)
+    cen = cen if cen.shape[0] == m["n_cell"] else cen.T
+    x, rp, r = cen[:, 0], np.hypot(cen[:, 1], cen[:, 2]), np.linalg.norm(cen, axis=1)
+    phi = np.arctan2(rp, x)
+    u = W[1:4] / W[0]
+    sel = (phi < 0.08) & (x > 0.5)
+    o = np.argsort(x[sel])
+    xs, us = x[sel][o], u[0][sel][o]
+    j = np.nonzero((us[:-1] < 0) & (us[1:] >= 0))[0][0]
+    wake = xs[j] - us[j] * (xs[j + 1] - xs[j]) / (us[j + 1] - us[j]) - 0.5
+    wall = r < r.min() + 0.02
+    rq = np.maximum(rp, 1e-30)
+    uphi = -np.sin(phi) * u[0] + np.cos(phi) * (u[1] * cen[:, 1] + u[2] * cen[:, 2]) / rq
+    bins = np.linspace(0, np.pi, 91)
+    idx = np.digitize(phi[wall], bins) - 1
+    c, mean = [], []
+    for k in range(90):
+        if np.any(idx == k):
+            c.append(0.5 * (bins[k] + bins[k + 1]))
+            mean.append(uphi[wall][idx == k].mean())
+    c, mean = np.array(c), np.array(mean)
+    j = np.nonzero(np.sign(mean[:-1]) != np.sign(mean[1:]))[0][0]
+    sep_rear = c[j] - mean[j] * (c[j + 1] - c[j]) / (mean[j + 1] - mean[j])
+    return wake, 180.0 - np.degrees(sep_rear)
+
+
+def test_sphere_re118_matches_paper():
     g = GOLD["sphere_re118"]
-    cd = converged_cd(I.sphere_case_mesh(), g["Ma"], g["Re"], np.pi * 0.25, 3000)
+    m = I.sphere_case_mesh()
+    states = []
+    cd = converged_cd(m, g["Ma"], g["Re"], np.pi * 0.25, 3000, states)
     assert abs(cd - g["Cd"]) <= 0.03 * g["Cd"]
+    wake, sep = sphere_wake_and_separation(m, states[0])
+    print(f"wake length {wake:.3f} (paper {g['wake_length']}), separation angle {sep:.2f} deg "
+          f"(paper {g['separation_angle_deg']})", flush=True)
+    assert abs(wake - g["wake_length"]) <= 0.05
+    assert abs(sep - g["separation_angle_deg"]) <= 2.5
 
 
 def test_two_level_cycle_accelerates_steady_convergence():
