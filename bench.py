@@ -80,7 +80,7 @@ def layout_sizes(d):
     nk = 5 if d == 2 else 9
     nq = 3 if d == 2 else 6
     return dict(nv=nv, nk=nk, nq=nq, ns=4 if d == 2 else 8, nsym=nk * (nk + 1) // 2, sr=nv + d * nv,
-                gr=d + nq + 1, er=d + 1 + nq + nv + nk * nv, fs=2 * nv + 2 * d * nv)
+                gr=d + nq + 1, er=d + 1 + nq + nv + nk * nv, fs=2 * nv + 2 * d * nv, fs_planar=4 * nv + d)
 
 
 def sweep_sequence(n_colour, n_sweeps=2):
@@ -115,12 +115,16 @@ def algorithmic_bytes(mesh, lm, rbytes, sbytes=8):
     out["recon"] = (recon + ghost, 3)          # ghost pre-pass timed with the reconstruction
     face_idx = NF * (5 * 4 + 8 * d) + 4
     gp = NG * 8 * (2 * d + 1)
-    flux_grad = NC * R * er + gp + face_idx + NF * R * fs
+    # face records: F0, Ft, header and one Gauss-Green group for a planar face,
+    # one group per axis otherwise
+    NP = lm.info.n_planar_faces
+    frec = R * (NP * z["fs_planar"] + (NF - NP) * fs)
+    flux_grad = NC * R * er + gp + face_idx + frec
     flux_r1 = NC * R * er + gp + face_idx + NF * R * 2 * nv
     out["flux"] = ((2 * flux_grad + flux_r1) / 3.0, 3)
     cell_common = NC * (8 * ns + 4 + 8)
-    st0 = cell_common + NF * R * fs + NC * 8 * (nv + 3 * nv + sr + d * nv)
-    st1 = cell_common + NF * R * fs + NC * 8 * (3 * nv + d * nv + sr)
+    st0 = cell_common + frec + NC * 8 * (nv + 3 * nv + sr + d * nv)
+    st1 = cell_common + frec + NC * 8 * (3 * nv + d * nv + sr)
     r1 = cell_common + NF * R * 2 * nv + NC * 8 * nv
     out["cell"] = ((st0 + st1 + r1) / 3.0, 3)
     own, nb = mesh["face_owner"], mesh["face_neigh"]

@@ -109,6 +109,8 @@ typedef struct {
     int dim, n_colour;
     int64_t n_cell, n_face, n_gp, n_boundary_face;
     int64_t n_linear_cells;         /* cells whose stencil only fixes a linear fit */
+    int64_t n_planar_faces;         /* faces whose Gauss points share one normal (all 2-D edges and
+                                       triangles; flat quads): their face records are shorter */
 } cgks_mesh_info;
 
 /*

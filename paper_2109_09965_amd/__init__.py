@@ -54,7 +54,8 @@ class _Desc(C.Structure):
 
 class _Info(C.Structure):
     _fields_ = [("dim", C.c_int), ("n_colour", C.c_int), ("n_cell", C.c_int64), ("n_face", C.c_int64),
-                ("n_gp", C.c_int64), ("n_boundary_face", C.c_int64), ("n_linear_cells", C.c_int64)]
+                ("n_gp", C.c_int64), ("n_boundary_face", C.c_int64), ("n_linear_cells", C.c_int64),
+                ("n_planar_faces", C.c_int64)]
 
 
 class _Params(C.Structure):

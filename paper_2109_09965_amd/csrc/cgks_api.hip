@@ -188,8 +188,11 @@ void layout(cgks_batch *b) {
     o.gx = a.take<double>(d * NG);
     o.gn = a.take<double>(d * NG);
     o.gw = a.take<double>(NG);
-    o.fsum = a.take<double>(ho64 ? (2 * nv + 2 * d * nv) * NF : 0);
-    o.fsum32 = a.take<float>(mixed ? (2 * nv + 2 * d * nv) * NF : 0);
+    const int64_t face_rec = 2 * nv + 2 * d * nv;   // Dim<D>::fs
+    static_assert(Dim<2>::fs == 2 * 4 + 2 * 2 * 4 && Dim<3>::fs == 2 * 5 + 2 * 3 * 5, "face record size");
+    static_assert(Dim<2>::fh + 2 <= Dim<2>::fs && Dim<3>::fh + 3 <= Dim<3>::fs, "planar normal inside the record");
+    o.fsum = a.take<double>(ho64 ? face_rec * NF : 0);
+    o.fsum32 = a.take<float>(mixed ? face_rec * NF : 0);
     o.ev32 = a.take<float>(mixed ? er * NC : 0);
     o.minv32 = a.take<float>(mixed ? nk * (nk + 1) / 2 * NC : 0);
     // low-level records: U (FP64) + dU (FP64, or FP32 padded to 16 bytes)
@@ -477,6 +480,18 @@ cgks_status cgks_mesh_create(const cgks_mesh_desc *desc, cgks_mesh **out) {
     return CGKS_OK;
 }
 
+// planar face: the unit normals of its Gauss points agree with the first
+// one's to 1e-12, so its Gauss-Green sums are that normal times one plain
+// sum (a change below 1e-12 relative; flat quads whose per-point normals
+// differ only by rounding count as planar)
+static bool face_planar(const HostMesh &m, int64_t f) {
+    const int d = m.dim;
+    for (int64_t g = m.gp_off[f] + 1; g < m.gp_off[f + 1]; ++g)
+        for (int a = 0; a < d; ++a)
+            if (std::fabs(m.gn[g * d + a] - m.gn[m.gp_off[f] * d + a]) > 1e-12) return false;
+    return true;
+}
+
 cgks_status cgks_mesh_query(const cgks_mesh *mesh, cgks_mesh_info *info) {
     if (!mesh || !info) return CGKS_EINVAL;
     const HostMesh &m = mesh->hm;
@@ -489,6 +504,9 @@ cgks_status cgks_mesh_query(const cgks_mesh *mesh, cgks_mesh_info *info) {
     int64_t nl = 0;
     for (auto v : m.linear) nl += v;
     info->n_linear_cells = nl;
+    int64_t np = 0;
+    for (int64_t f = 0; f < m.n_face; ++f) np += face_planar(m, f) ? 1 : 0;
+    info->n_planar_faces = np;
     return CGKS_OK;
 }
 
@@ -622,7 +640,8 @@ static cgks_status upload_case(cgks_batch *b, int c, hipStream_t s) {
             const int64_t f = m.cf_face[q];
             const int side = m.cf_side[q];
             const int64_t nbr = side ? m.owner[f] : m.neigh[f];
-            const int32_t code = int32_t(fo + m.caller2libf[f] + 1);   // slot order: caller face order
+            int32_t code = int32_t(fo + m.caller2libf[f] + 1);   // slot order: caller face order
+            if (face_planar(m, f)) code |= kSlotPlanar;
             slot[sl * n + l] = make_int2(side ? -code : code, nbr >= 0 ? int32_t(co + m.caller2lib[nbr]) : -1);
         }
     }
@@ -633,6 +652,7 @@ static cgks_status upload_case(cgks_batch *b, int c, hipStream_t s) {
         fL[lf] = int32_t(co + m.caller2lib[m.owner[f]]);
         fR[lf] = m.neigh[f] >= 0 ? int32_t(co + m.caller2lib[m.neigh[f]]) : -1;
         fbc[lf] = m.neigh[f] >= 0 ? 0 : m.bc[f];
+        if (face_planar(m, f)) fbc[lf] |= kFacePlanar;
         const int64_t g0 = gl;
         for (int64_t g = m.gp_off[f]; g < m.gp_off[f + 1]; ++g, ++gl) {
             for (int a = 0; a < d; ++a) {

@@ -63,7 +63,7 @@ struct Dev {
     double *gdat;             // [NB][nv + D nv] ghost cell average and gradient
     // gauss points
     const double *gx, *gn, *gw;
-    double *fsum;      // per face [NF][2 nv + 2 D nv]: sum_g wJ of (F0, Ft), then per axis a (W_c n_a, W_t n_a)
+    double *fsum;      // per face [NF][Dim<D>::fs]: sum_g wJ of (F0, Ft), header, Gauss-Green groups (Dim<D>)
     float *fsum32;     // the same in FP32 (mixed-precision batches)
     // low level: U and dU in one cell-major record per cell (LowRec: U in
     // FP64, then dU in the sweep precision; a neighbour gather reads one
@@ -123,8 +123,22 @@ template <int D> struct Dim {
     static constexpr int nsym = nk * (nk + 1) / 2;
     static constexpr int lanes = D == 2 ? 2 : 4;   // threads per face (one per Gauss point)
     static constexpr int sl = 4;                   // threads per cell in the slot gathers
-    static constexpr int fs = 2 * nv + 2 * D * nv; // face sums per face
+    // face record: F0, Ft (2 nv), then the Gauss-Green sums.  Any face: one
+    // group per axis (sum w W n_a, sum w W_t n_a).  A planar face (every
+    // Gauss point has the same normal): one plain group (sum w W, sum w W_t)
+    // in the first group's place and the face normal after it, where the
+    // second group would be; the cell kernel multiplies by the normal
+    static constexpr int fg = 2 * nv;                // Gauss-Green groups offset
+    static constexpr int fh = 4 * nv;                // normal offset (planar faces)
+    static constexpr int fs = fg + 2 * D * nv;       // record size (a planar face uses 4 nv + D)
 };
+// planar faces are marked on the host in the face tag (the boundary tag is
+// in the low three bits) and in the slot codes (bit 30 of |code|, below the
+// sign that gives the face's orientation seen from the cell)
+constexpr int kFacePlanar = 8;
+constexpr int kSlotPlanar = 1 << 30;
+__device__ __forceinline__ int slot_face(int code) { return ((code > 0 ? code : -code) & (kSlotPlanar - 1)) - 1; }
+__device__ __forceinline__ bool slot_planar(int code) { return ((code > 0 ? code : -code) & kSlotPlanar) != 0; }
 
 // quadratic basis (a, b) pairs: 2-D (00, 01, 11); 3-D (00, 11, 22, 01, 02, 12)
 template <int D> __device__ __forceinline__ int qa(int q) {
@@ -711,7 +725,7 @@ template <int D> __global__ __launch_bounds__(kBlock) void k_ghost(Dev d) {
     const double iS = 1.0 / d.S[f];
 #pragma unroll
     for (int a = 0; a < D; ++a) n[a] = d.avec[size_t(a) * d.NF + f] * iS;
-    ghost_data<D>(d.fbc[f], n, Wi, Gi, P, Wg, Gg);
+    ghost_data<D>(d.fbc[f] & 7, n, Wi, Gi, P, Wg, Gg);
     double *o = d.gdat + size_t(B) * (nv + D * nv);
 #pragma unroll
     for (int v = 0; v < nv; ++v) o[v] = Wg[v];
@@ -759,7 +773,7 @@ template <int D, typename R> __global__ __launch_bounds__(kReconBlock) void k_re
         const int2 sl = d.slot[size_t(s) * NC + i];
         const int code = sl.x;
         if (code == 0) break;
-        const int f = (code > 0 ? code : -code) - 1;
+        const int f = slot_face(code);
         const int nb = sl.y;
         R avg[nk];
         const double *gd;
@@ -994,7 +1008,8 @@ template <int D, typename R> __global__ __launch_bounds__(kBlock) void k_flux(De
     fr.build(n);
     R Wc[nv], Gc[D][nv];
     bool ok = true;
-    const int bc = d.fbc[f];
+    const int bc = d.fbc[f] & 7;
+    const bool planar = (d.fbc[f] & kFacePlanar) != 0;
     {
         // gradients summed in the global frame, rotated once
         R Gs[D][nv], WL[nv];
@@ -1078,16 +1093,22 @@ template <int D, typename R> __global__ __launch_bounds__(kBlock) void k_flux(De
     R *dst = HoArrays<R>::fsum(d) + size_t(f) * FS;
     const bool writer = face_ok && q == 0;
     R o[nv];
-    // Gauss-Green sums of the interface state at t = 0
+    // Gauss-Green sums of the interface state at t = 0 (a planar face: the
+    // plain sum, in the first group; the reductions run for every face, the
+    // lane group of a face takes one branch)
     if (want_grad) {
+        if (writer && planar) {
+#pragma unroll
+            for (int a = 0; a < D; ++a) dst[T::fh + a] = n[a];
+        }
         fr.to_global(Wc, o);
 #pragma unroll
         for (int v = 0; v < nv; ++v) {
             const R w = ok ? wJ * o[v] : R(0.0);
 #pragma unroll
             for (int a = 0; a < D; ++a) {
-                const R sum = group_sum<G, R>(w * n[a]);
-                if (writer) dst[2 * nv + a * 2 * nv + v] = sum;
+                const R sum = group_sum<G, R>(planar ? (a == 0 ? w : R(0.0)) : w * n[a]);
+                if (writer && (!planar || a == 0)) dst[T::fg + a * 2 * nv + v] = sum;
             }
         }
     }
@@ -1125,8 +1146,8 @@ template <int D, typename R> __global__ __launch_bounds__(kBlock) void k_flux(De
             const R w = wJ * o[v];
 #pragma unroll
             for (int a = 0; a < D; ++a) {
-                const R sum = group_sum<G, R>(w * n[a]);
-                if (writer) dst[2 * nv + a * 2 * nv + nv + v] = sum;
+                const R sum = group_sum<G, R>(planar ? (a == 0 ? w : R(0.0)) : w * n[a]);
+                if (writer && (!planar || a == 0)) dst[T::fg + a * 2 * nv + nv + v] = sum;
             }
         }
     }
@@ -1153,9 +1174,11 @@ template <int D, typename R> __global__ __launch_bounds__(kBlock) void k_cell(De
     const bool want_g = mode != MODE_R1;
     // lane 0 sums the flux group (F0, Ft) of the cell's face records, lane
     // 1 + a the Gauss-Green group of axis a (W_c n_a, W_t n_a): each lane
-    // reads its own contiguous 2 nv values of every face and needs no other
-    // lane's sums
+    // reads 2 nv values of every face and needs no other lane's sums.  For a
+    // planar face (marked in its slot code) lane 1 + a reads the one plain
+    // group and scales it by n_a.
     const bool mine = q == 0 || (want_g && q <= D);
+    const int ax = q - 1;
     double acc[GW];
 #pragma unroll
     for (int k = 0; k < GW; ++k) acc[k] = 0.0;
@@ -1173,22 +1196,40 @@ template <int D, typename R> __global__ __launch_bounds__(kBlock) void k_cell(De
 #pragma unroll
             for (int s = 0; s < T::ns; ++s) {
                 const bool has = code[s] != 0;
-                const int f = has ? (code[s] > 0 ? code[s] : -code[s]) - 1 : 0;
+                const int f = has ? slot_face(code[s]) : 0;
                 const double sg = has ? (code[s] > 0 ? 1.0 : -1.0) : 0.0;
-                const R *src = HoArrays<R>::fsum(d) + size_t(f) * T::fs + q * GW;
+                const R *rec = HoArrays<R>::fsum(d) + size_t(f) * T::fs;
+                if (q == 0) {
 #pragma unroll
-                for (int k = 0; k < GW; ++k) acc[k] += sg * double(src[k]);
+                    for (int k = 0; k < GW; ++k) acc[k] += sg * double(rec[k]);
+                } else {
+                    const bool pl = slot_planar(code[s]);
+                    const R na = rec[T::fh + ax];
+                    const R *g = rec + T::fg + (pl ? 0 : ax * GW);
+                    const double wg = pl ? double(na) : 1.0;
+#pragma unroll
+                    for (int k = 0; k < GW; ++k) acc[k] += sg * wg * double(g[k]);
+                }
             }
         } else {
 #pragma unroll 1
             for (int s = 0; s < T::ns; ++s) {
                 const int code = d.slot[size_t(s) * NC + i].x;
                 if (code == 0) break;
-                const int f = (code > 0 ? code : -code) - 1;
+                const int f = slot_face(code);
                 const double sg = code > 0 ? 1.0 : -1.0;
-                const R *src = HoArrays<R>::fsum(d) + size_t(f) * T::fs + q * GW;
+                const R *rec = HoArrays<R>::fsum(d) + size_t(f) * T::fs;
+                if (q == 0) {
 #pragma unroll
-                for (int k = 0; k < GW; ++k) acc[k] += sg * double(src[k]);
+                    for (int k = 0; k < GW; ++k) acc[k] += sg * double(rec[k]);
+                } else {
+                    const bool pl = slot_planar(code);
+                    const R na = rec[T::fh + ax];
+                    const R *g = rec + T::fg + (pl ? 0 : ax * GW);
+                    const double wg = pl ? double(na) : 1.0;
+#pragma unroll
+                    for (int k = 0; k < GW; ++k) acc[k] += sg * wg * double(g[k]);
+                }
             }
         }
     }
@@ -1292,7 +1333,7 @@ template <int D, typename S> __global__ __launch_bounds__(kBlock) void k_low_fac
         fr.to_local(UR, Ur);
         lam = fmax(lam, side_radius<D>(UR, n, Sf, d.vol[R], P));
     } else {
-        const int bc = d.fbc[f];
+        const int bc = d.fbc[f] & 7;
 #pragma unroll
         for (int v = 0; v < nv; ++v) Ur[v] = Ul[v];
         if (bc == 1) {
@@ -1380,7 +1421,7 @@ template <int D, typename S, int MODE> __global__ __launch_bounds__(kBlock) void
 #pragma unroll
     for (int k = 0; k < NS; ++k) {
         const bool has = code[k] != 0;
-        const int f = has ? (code[k] > 0 ? code[k] : -code[k]) - 1 : 0;
+        const int f = has ? slot_face(code[k]) : 0;
         const double sg = has ? (code[k] > 0 ? 1.0 : -1.0) : 0.0;
         const double *lf = d.lowf + size_t(f) * nv;
         const double sl_lam = d.swp[size_t(f) * 4 + D];
@@ -1457,7 +1498,7 @@ __global__ __launch_bounds__(kBlock) void k_sweep(Dev d, const int32_t *blk_star
         for (int k = 0; k < NS; ++k) {
             const bool has = (sl[k].x != 0) & (sl[k].y >= 0);
             const int nb = has ? sl[k].y : i;
-            const int f = has ? (sl[k].x > 0 ? sl[k].x : -sl[k].x) - 1 : 0;
+            const int f = has ? slot_face(sl[k].x) : 0;
             const double sg = sl[k].x > 0 ? 1.0 : -1.0;
             const double *w = d.swp + size_t(f) * 4;
             const double *Unb = LowRec<D, S>::U(d, nb);
@@ -1493,7 +1534,7 @@ __global__ __launch_bounds__(kBlock) void k_sweep(Dev d, const int32_t *blk_star
             const int2 sl = d.slot[size_t(s) * NC + i];
             if (sl.x != 0 && sl.y >= 0) {
                 const int nb = sl.y;
-                const int f = (sl.x > 0 ? sl.x : -sl.x) - 1;
+                const int f = slot_face(sl.x);
                 const double sg = sl.x > 0 ? 1.0 : -1.0;
                 const double *w = d.swp + size_t(f) * 4;
                 const double *Unb = LowRec<D, S>::U(d, nb);
@@ -1575,7 +1616,7 @@ template <int D> __global__ __launch_bounds__(kBlock) void k_wall_force(Dev d) {
     for (int B = cb.x + threadIdx.x; B < cb.x + cb.y; B += kBlock) {
         const int F = d.bface[B];
         if (F < 0) continue;
-        const int bc = d.fbc[F];
+        const int bc = d.fbc[F] & 7;
         if (bc != 1 && bc != 2 && bc != 3) continue;
 #pragma unroll
         for (int a = 0; a < D; ++a) f[a] += d.wallf[size_t(B) * 3 + a];
