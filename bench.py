@@ -28,22 +28,22 @@ VALU_PEAK_TFLOPS = {"fp64": 78.6, "mixed32": 157.3, "mixed32_r64": 78.6}
 # (FMA = 2), from the VALU instruction counters of one launch on the
 # sphere workload (SQ_INSTS_VALU_{FMA,MUL,ADD,TRANS}_F64 resp. _F32, x 64
 # lanes), charged to the lanes that carry a Gauss point.
-FLUX_FLOP_PER_GP = {"fp64": 1733.0, "mixed32": 1627.0, "mixed32_r64": (2 * 1627.0 + 1733.0) / 3.0}
+FLUX_FLOP_PER_GP = {"fp64": 1703.0, "mixed32": 1597.0, "mixed32_r64": (2 * 1597.0 + 1703.0) / 3.0}
 
 # HBM bytes per launch from rocprofv3 FETCH_SIZE (x 2.0) and WRITE_SIZE
 # (x 1.0) on the sphere workload, each factor from a plain device copy of
 # known size.  Valid only for the kernel source they were taken on (its
 # SHA-256); any other source reports null.
-PROFILED_KERNELS_SHA256 = "a25d7205f9b4cafe248b1dd9decf1b252d0c5b40a2f90e2c63d3aa4cf0593399"
+PROFILED_KERNELS_SHA256 = "a67d4b35e561a12fd05dc9af9ab3a182963af9a8bc2800442ea874c447bf0772"
 PROFILED_TRAFFIC = {           # (kernel kind, precision) -> bytes per launch
-    ("dt", "fp64"): 79171468.3, ("dt", "mixed32"): 79171322.0,
-    ("recon", "fp64"): 678861672.4, ("recon", "mixed32"): 634255387.9,   # with the boundary ghost pre-pass
-    ("flux", "fp64"): 826632834.2, ("flux", "mixed32"): 538591387.8,
-    ("cell", "fp64"): 785694505.2, ("cell", "mixed32"): 399790245.8,
-    ("low_face", "fp64"): 183670243.1, ("low_face", "mixed32"): 175698820.5,
-    ("low_cell", "fp64"): 256193060.3, ("low_cell", "mixed32"): 242040724.6,  # 1 forcing + 5 step launches
-    ("sweep", "fp64"): 56908783.7, ("sweep", "mixed32"): 42832334.9,          # average over colour classes
-    ("prolong", "fp64"): 174301912.4, ("prolong", "mixed32"): 160882068.9,
+    ("dt", "fp64"): 79177531.7, ("dt", "mixed32"): 79177374.7,
+    ("recon", "fp64"): 679255456.3, ("recon", "mixed32"): 633554708.2,   # with the boundary ghost pre-pass
+    ("flux", "fp64"): 733025348.4, ("flux", "mixed32"): 495858768.0,
+    ("cell", "fp64"): 721311471.3, ("cell", "mixed32"): 393949429.7,
+    ("low_face", "fp64"): 183696964.2, ("low_face", "mixed32"): 175756009.3,
+    ("low_cell", "fp64"): 256195522.1, ("low_cell", "mixed32"): 242107724.8,  # 1 forcing + 5 step launches
+    ("sweep", "fp64"): 56935212.6, ("sweep", "mixed32"): 42794519.4,          # average over colour classes
+    ("prolong", "fp64"): 174333353.0, ("prolong", "mixed32"): 161268825.5,
 }
 
 
