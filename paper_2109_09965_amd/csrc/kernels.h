@@ -1199,17 +1199,14 @@ template <int D, typename R> __global__ __launch_bounds__(kBlock) void k_cell(De
                 const int f = has ? slot_face(code[s]) : 0;
                 const double sg = has ? (code[s] > 0 ? 1.0 : -1.0) : 0.0;
                 const R *rec = HoArrays<R>::fsum(d) + size_t(f) * T::fs;
-                if (q == 0) {
+                // one instruction stream for the whole lane group: lane 0
+                // takes (F0, Ft) with weight 1, the others their group
+                const bool pl = q > 0 && slot_planar(code[s]);
+                const R na = rec[T::fh + (q > 0 ? ax : 0)];
+                const R *g = rec + (q == 0 ? 0 : T::fg + (pl ? 0 : ax * GW));
+                const double w = sg * (pl ? double(na) : 1.0);
 #pragma unroll
-                    for (int k = 0; k < GW; ++k) acc[k] += sg * double(rec[k]);
-                } else {
-                    const bool pl = slot_planar(code[s]);
-                    const R na = rec[T::fh + ax];
-                    const R *g = rec + T::fg + (pl ? 0 : ax * GW);
-                    const double wg = pl ? double(na) : 1.0;
-#pragma unroll
-                    for (int k = 0; k < GW; ++k) acc[k] += sg * wg * double(g[k]);
-                }
+                for (int k = 0; k < GW; ++k) acc[k] += w * double(g[k]);
             }
         } else {
 #pragma unroll 1
@@ -1219,17 +1216,12 @@ template <int D, typename R> __global__ __launch_bounds__(kBlock) void k_cell(De
                 const int f = slot_face(code);
                 const double sg = code > 0 ? 1.0 : -1.0;
                 const R *rec = HoArrays<R>::fsum(d) + size_t(f) * T::fs;
-                if (q == 0) {
+                const bool pl = q > 0 && slot_planar(code);
+                const R na = rec[T::fh + (q > 0 ? ax : 0)];
+                const R *g = rec + (q == 0 ? 0 : T::fg + (pl ? 0 : ax * GW));
+                const double w = sg * (pl ? double(na) : 1.0);
 #pragma unroll
-                    for (int k = 0; k < GW; ++k) acc[k] += sg * double(rec[k]);
-                } else {
-                    const bool pl = slot_planar(code);
-                    const R na = rec[T::fh + ax];
-                    const R *g = rec + T::fg + (pl ? 0 : ax * GW);
-                    const double wg = pl ? double(na) : 1.0;
-#pragma unroll
-                    for (int k = 0; k < GW; ++k) acc[k] += sg * wg * double(g[k]);
-                }
+                for (int k = 0; k < GW; ++k) acc[k] += w * double(g[k]);
             }
         }
     }
