@@ -34,16 +34,16 @@ FLUX_FLOP_PER_GP = {"fp64": 1703.0, "mixed32": 1597.0, "mixed32_r64": (2 * 1597.
 # (x 1.0) on the sphere workload, each factor from a plain device copy of
 # known size.  Valid only for the kernel source they were taken on (its
 # SHA-256); any other source reports null.
-PROFILED_KERNELS_SHA256 = "a67d4b35e561a12fd05dc9af9ab3a182963af9a8bc2800442ea874c447bf0772"
+PROFILED_KERNELS_SHA256 = "db8a84437a6c6de57b54718710bcc7276b77cbfb8344ab04a5a83d68c8a94d7b"
 PROFILED_TRAFFIC = {           # (kernel kind, precision) -> bytes per launch
-    ("dt", "fp64"): 79177531.7, ("dt", "mixed32"): 79177374.7,
-    ("recon", "fp64"): 679255456.3, ("recon", "mixed32"): 633554708.2,   # with the boundary ghost pre-pass
-    ("flux", "fp64"): 733025348.4, ("flux", "mixed32"): 495858768.0,
-    ("cell", "fp64"): 721311471.3, ("cell", "mixed32"): 393949429.7,
-    ("low_face", "fp64"): 183696964.2, ("low_face", "mixed32"): 175756009.3,
-    ("low_cell", "fp64"): 256195522.1, ("low_cell", "mixed32"): 242107724.8,  # 1 forcing + 5 step launches
-    ("sweep", "fp64"): 56935212.6, ("sweep", "mixed32"): 42794519.4,          # average over colour classes
-    ("prolong", "fp64"): 174333353.0, ("prolong", "mixed32"): 161268825.5,
+    ("dt", "fp64"): 79177625.2, ("dt", "mixed32"): 79177457.6,
+    ("recon", "fp64"): 679239381.7, ("recon", "mixed32"): 633410233.7,   # with the boundary ghost pre-pass
+    ("flux", "fp64"): 732863033.1, ("flux", "mixed32"): 495873789.4,
+    ("cell", "fp64"): 708539775.6, ("cell", "mixed32"): 397115198.0,
+    ("low_face", "fp64"): 183695890.9, ("low_face", "mixed32"): 175766193.2,
+    ("low_cell", "fp64"): 256368229.1, ("low_cell", "mixed32"): 242041112.0,  # 1 forcing + 5 step launches
+    ("sweep", "fp64"): 56982947.4, ("sweep", "mixed32"): 42808721.3,          # average over colour classes
+    ("prolong", "fp64"): 173888783.6, ("prolong", "mixed32"): 162011321.5,
 }
 
 
