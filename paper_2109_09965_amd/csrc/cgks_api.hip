@@ -549,9 +549,8 @@ static cgks_status new_pool(const cgks_pool_desc &q, cgks_batch **out) {
         q.max_gauss_points <= 0 || q.max_boundary_faces < 0)
         return CGKS_EINVAL;
     if (q.precision != CGKS_FP64 && q.precision != CGKS_MIXED32 && q.precision != CGKS_MIXED32_R64) return CGKS_EINVAL;
-    // 32-bit indices: slot tables [8][cells], four lanes per face
-    // int32 indices throughout; face ids + 1 also stay below kSlotPlanar, the
-    // planar-face bit of the slot codes
+    // 32-bit indices: slot tables [8][cells], four lanes per face; face ids
+    // + 1 also stay below kSlotPlanar, the planar-face bit of the slot codes
     static_assert(INT32_MAX / 8 + 1 < kSlotPlanar, "face ids must not reach the planar bit");
     if (q.max_cells > INT32_MAX / 8 || q.max_faces > INT32_MAX / 8 || q.max_gauss_points > INT32_MAX / 2 ||
         q.max_boundary_faces > INT32_MAX / 2)
