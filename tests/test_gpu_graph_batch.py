@@ -188,3 +188,29 @@ def test_autotuned_batch_steps_bitwise_like_untuned(kinds, precision):
         Wt, dWt = tuned.download(i)
         Wp, dWp = plain.download(i)
         assert np.array_equal(Wt, Wp) and np.array_equal(dWt, dWp), i
+
+
+def test_nonphysical_case_is_flagged_and_leaves_the_batch_alone():
+    """A case whose state has a cell of negative pressure is reported
+    non-physical after its first cycle and frozen, while the other case of
+    the batch runs on and ends bitwise equal to the same case run alone: a
+    bad case never fails a batch (per-case flags, time steps and norms)."""
+    good, bad = case("cyl", 0), case("cyl_small", 1)
+    Wb = bad[2].copy()
+    rho, mom = Wb[0, 7], Wb[1:3, 7]
+    Wb[-1, 7] = 0.25 * 0.5 * float(mom @ mom) / rho      # E below the kinetic energy: p < 0
+    assert 0.4 * (Wb[-1, 7] - 0.5 * float(mom @ mom) / rho) < 0
+    b = cg.Batch([cg.Mesh(good[0]), cg.Mesh(bad[0])], [cg.Params(**good[1]), cg.Params(**bad[1])])
+    b.upload(0, good[2], good[3])
+    b.upload(1, Wb, bad[3])
+    rep, _ = b.solve(max_cycles=6, tol=0.0, check_every=1)
+    print(rep, flush=True)
+    assert rep[1]["status"] == cg.ENONPHYS and rep[1]["cycles"] == 1 and not rep[1]["converged"]
+    assert rep[0]["status"] == cg.ENOTCONV and rep[0]["cycles"] == 6
+    Wg, dWg = b.download(0)
+    a = cg.Batch([cg.Mesh(good[0])], [cg.Params(**good[1])])
+    a.upload(0, good[2], good[3])
+    for _ in range(6):
+        a.cycle()
+    Wa, dWa = a.download(0)
+    assert np.array_equal(Wg, Wa) and np.array_equal(dWg, dWa)
