@@ -34,7 +34,7 @@ FLUX_FLOP_PER_GP = {"fp64": 1703.0, "mixed32": 1597.0, "mixed32_r64": (2 * 1597.
 # (x 1.0) on the sphere workload, each factor from a plain device copy of
 # known size.  Valid only for the kernel source they were taken on (its
 # SHA-256); any other source reports null.
-PROFILED_KERNELS_SHA256 = "db8a84437a6c6de57b54718710bcc7276b77cbfb8344ab04a5a83d68c8a94d7b"
+PROFILED_KERNELS_SHA256 = "0e1cf00d40d686405480acd3b2ae92c7458880b7596f8ce29bceb7cfa6f9220f"
 PROFILED_TRAFFIC = {           # (kernel kind, precision) -> bytes per launch
     ("dt", "fp64"): 79177625.2, ("dt", "mixed32"): 79177457.6,
     ("recon", "fp64"): 679239381.7, ("recon", "mixed32"): 633410233.7,   # with the boundary ghost pre-pass

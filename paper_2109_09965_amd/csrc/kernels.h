@@ -63,7 +63,7 @@ struct Dev {
     double *gdat;             // [NB][nv + D nv] ghost cell average and gradient
     // gauss points
     const double *gx, *gn, *gw;
-    double *fsum;      // per face [NF][Dim<D>::fs]: sum_g wJ of (F0, Ft), header, Gauss-Green groups (Dim<D>)
+    double *fsum;      // per face [NF][Dim<D>::fs]: sum_g wJ of (F0, Ft), then the Gauss-Green groups (Dim<D>)
     float *fsum32;     // the same in FP32 (mixed-precision batches)
     // low level: U and dU in one cell-major record per cell (LowRec: U in
     // FP64, then dU in the sweep precision; a neighbour gather reads one
@@ -1094,8 +1094,8 @@ template <int D, typename R> __global__ __launch_bounds__(kBlock) void k_flux(De
     const bool writer = face_ok && q == 0;
     R o[nv];
     // Gauss-Green sums of the interface state at t = 0 (a planar face: the
-    // plain sum, in the first group; the reductions run for every face, the
-    // lane group of a face takes one branch)
+    // plain sum in the first group and the normal after it; every face runs
+    // the same D reductions, a planar one with weights (1, 0, 0))
     if (want_grad) {
         if (writer && planar) {
 #pragma unroll
