@@ -116,3 +116,22 @@ def test_mesh_errors_are_reported():
     with pytest.raises(cg.CgksError) as e:
         cg.Mesh(unknown)
     assert e.value.status == cg.EMESH
+
+
+@pytest.mark.parametrize("over,expect", [({}, 0), ({"low_flux": 1}, 0), ({"low_flux": 2}, 1), ({"time_scheme": 5}, 1),
+                                         ({"mu": -1e-3}, 1), ({"gamma": 1.0}, 1), ({"cfl_high": 0.0}, 1),
+                                         ({"cfl_low": -1.0}, 1), ({"Pr": 0.0}, 1)])
+def test_batch_parameters_are_validated(over, expect):
+    """cgks_batch_create checks every case's parameters on the host before
+    any device work: CGKS_EINVAL for an unknown low-level flux or time
+    scheme, negative viscosity, gamma <= 1, non-positive CFL numbers or
+    Prandtl number."""
+    import ctypes as C
+    L = cg.lib()
+    lm = cg.Mesh(I.cylinder_mesh(16, 8))
+    p = cg.Params(W_inf=I.free_stream(2, 0.2), **over).c()
+    h = C.c_void_p()
+    st = L.cgks_batch_create((C.c_void_p * 1)(lm.h), C.byref(p), 1, cg.FP64, C.byref(h))
+    assert st == expect
+    if st == 0:
+        L.cgks_batch_destroy(h)
