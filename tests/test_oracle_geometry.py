@@ -282,8 +282,9 @@ def test_colouring_is_largest_first_and_numbered_by_class_size(mk):
 
 
 def test_sphere_workload_needs_four_colours():
-    """The hybrid sphere of the benchmark takes four colours (greedy in
-    caller order needs a fifth, for a single cell)."""
+    """The hybrid sphere of the benchmark takes four colours under the
+    largest-degree-first greedy colouring (greedy in caller order needs a
+    fifth, for a single cell)."""
     om = oracle.Mesh(I.sphere_case_mesh())
     assert om.n_colour == 4
 
