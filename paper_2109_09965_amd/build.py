@@ -18,10 +18,10 @@ def build(verbose: bool = False) -> str:
     obj_prep = os.path.join(CSRC, "mesh_prep.o")
     obj_api = os.path.join(CSRC, "cgks_api.o")
     cmds = [
-        ["g++", "-O2", "-std=c++17", "-fPIC", "-I", os.path.join(ROOT, "include"), "-c",
+        ["g++", "-O2", "-std=c++17", "-fPIC", "-pthread", "-I", os.path.join(ROOT, "include"), "-c",
          os.path.join(CSRC, "mesh_prep.cpp"), "-o", obj_prep],
         ["hipcc"] + HIP_FLAGS + ["-c", os.path.join(CSRC, "cgks_api.hip"), "-o", obj_api],
-        ["hipcc", "-shared", "-fPIC", "--offload-arch=gfx950", obj_api, obj_prep, "-o", LIB + ".tmp"],
+        ["hipcc", "-shared", "-fPIC", "-pthread", "--offload-arch=gfx950", obj_api, obj_prep, "-o", LIB + ".tmp"],
     ]
     for c in cmds:
         if verbose:

@@ -3,14 +3,36 @@
 // library cell order.  Runs once per mesh on the host (FP64, long double for
 // the small dense factorisations).
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
 #include <new>
+#include <thread>
+#include <vector>
 
 #include "cgks_internal.h"
 
 namespace cgks {
 namespace {
+
+// fn(begin, end) over [0, n) in contiguous chunks on up to 16 host threads.
+// Used only for loops whose iterations write their own entries, so the
+// results do not depend on the split.
+template <class F> void parallel_for(int64_t n, F &&fn) {
+    const unsigned hw = std::thread::hardware_concurrency();
+    const int64_t nt = std::min<int64_t>(std::max(1u, std::min(hw, 16u)), std::max<int64_t>(1, n / 4096));
+    if (nt <= 1) {
+        fn(int64_t(0), n);
+        return;
+    }
+    std::vector<std::thread> pool;
+    const int64_t chunk = (n + nt - 1) / nt;
+    for (int64_t t = 0; t < nt; ++t) {
+        const int64_t a = t * chunk, b = std::min(n, a + chunk);
+        if (a < b) pool.emplace_back([&fn, a, b] { fn(a, b); });
+    }
+    for (auto &th : pool) th.join();
+}
 
 struct V3 {
     double x[3] = {0, 0, 0};
@@ -167,74 +189,80 @@ cgks_status cell_geometry(HostMesh &m) {
     m.ctr.assign(m.n_cell * d, 0.0);
     m.sec.assign(m.n_cell * m.nq, 0.0);
     m.h.assign(m.n_cell, 0.0);
-    for (int64_t i = 0; i < m.n_cell; ++i) {
-        double ref[3] = {0, 0, 0};
-        {
-            const int64_t f = m.cf_face[m.cf_ptr[i]];
-            face_pt(m, f, 0, m.cf_side[m.cf_ptr[i]], ref);
-        }
-        Moments mo;
-        double sumS = 0;
-        for (int64_t q = m.cf_ptr[i]; q < m.cf_ptr[i + 1]; ++q) {
-            const int64_t f = m.cf_face[q];
-            const int side = m.cf_side[q];
-            const double sg = side ? -1.0 : 1.0;
-            const int nfv = int(m.fptr[f + 1] - m.fptr[f]);
-            double P[4][3] = {};
-            for (int k = 0; k < nfv; ++k) {
-                face_pt(m, f, k, side, P[k]);
-                for (int a = 0; a < d; ++a) P[k][a] -= ref[a];
+    std::atomic<bool> bad{false};
+    parallel_for(m.n_cell, [&](int64_t i0, int64_t i1) {
+        for (int64_t i = i0; i < i1; ++i) {
+            double ref[3] = {0, 0, 0};
+            {
+                const int64_t f = m.cf_face[m.cf_ptr[i]];
+                face_pt(m, f, 0, m.cf_side[m.cf_ptr[i]], ref);
             }
-            sumS += m.S[f];
-            if (d == 2) {
-                const double n[2] = {sg * (P[1][1] - P[0][1]), -sg * (P[1][0] - P[0][0])};  // |n| = length
-                const double sw[3] = {1.0 / 6.0, 4.0 / 6.0, 1.0 / 6.0};
-                for (int k = 0; k < 3; ++k) {
-                    const double t = 0.5 * k;
-                    const double y[2] = {P[0][0] + t * (P[1][0] - P[0][0]), P[0][1] + t * (P[1][1] - P[0][1])};
-                    const double nw[2] = {n[0] * sw[k], n[1] * sw[k]};
-                    mo.add(2, y, nw);
+            Moments mo;
+            double sumS = 0;
+            for (int64_t q = m.cf_ptr[i]; q < m.cf_ptr[i + 1]; ++q) {
+                const int64_t f = m.cf_face[q];
+                const int side = m.cf_side[q];
+                const double sg = side ? -1.0 : 1.0;
+                const int nfv = int(m.fptr[f + 1] - m.fptr[f]);
+                double P[4][3] = {};
+                for (int k = 0; k < nfv; ++k) {
+                    face_pt(m, f, k, side, P[k]);
+                    for (int a = 0; a < d; ++a) P[k][a] -= ref[a];
                 }
-            } else if (nfv == 3) {
-                double e1[3], e2[3], N[3];
-                sub(P[1], P[0], e1, 3);
-                sub(P[2], P[0], e2, 3);
-                cross(e1, e2, N);  // |N| = 2A
-                for (int js = 0; js < 3; ++js)
-                    for (int jt = 0; jt < 3; ++jt) {
-                        const double s = q3x[js], t = q3x[jt];
-                        const double a = s, b = t * (1.0 - s);
-                        const double w = q3w[js] * q3w[jt] * (1.0 - s);
-                        double y[3], nw[3];
-                        for (int c = 0; c < 3; ++c) {
-                            y[c] = P[0][c] + a * e1[c] + b * e2[c];
-                            nw[c] = sg * N[c] * w;
+                sumS += m.S[f];
+                if (d == 2) {
+                    const double n[2] = {sg * (P[1][1] - P[0][1]), -sg * (P[1][0] - P[0][0])};  // |n| = length
+                    const double sw[3] = {1.0 / 6.0, 4.0 / 6.0, 1.0 / 6.0};
+                    for (int k = 0; k < 3; ++k) {
+                        const double t = 0.5 * k;
+                        const double y[2] = {P[0][0] + t * (P[1][0] - P[0][0]), P[0][1] + t * (P[1][1] - P[0][1])};
+                        const double nw[2] = {n[0] * sw[k], n[1] * sw[k]};
+                        mo.add(2, y, nw);
+                    }
+                } else if (nfv == 3) {
+                    double e1[3], e2[3], N[3];
+                    sub(P[1], P[0], e1, 3);
+                    sub(P[2], P[0], e2, 3);
+                    cross(e1, e2, N);  // |N| = 2A
+                    for (int js = 0; js < 3; ++js)
+                        for (int jt = 0; jt < 3; ++jt) {
+                            const double s = q3x[js], t = q3x[jt];
+                            const double a = s, b = t * (1.0 - s);
+                            const double w = q3w[js] * q3w[jt] * (1.0 - s);
+                            double y[3], nw[3];
+                            for (int c = 0; c < 3; ++c) {
+                                y[c] = P[0][c] + a * e1[c] + b * e2[c];
+                                nw[c] = sg * N[c] * w;
+                            }
+                            mo.add(3, y, nw);
                         }
-                        mo.add(3, y, nw);
-                    }
-            } else {
-                for (int js = 0; js < 4; ++js)
-                    for (int jt = 0; jt < 4; ++jt) {
-                        double y[3], N[3], nw[3];
-                        quad_map(P, q4x[js], q4x[jt], y, N);
-                        for (int c = 0; c < 3; ++c) nw[c] = sg * N[c] * q4w[js] * q4w[jt];
-                        mo.add(3, y, nw);
-                    }
+                } else {
+                    for (int js = 0; js < 4; ++js)
+                        for (int jt = 0; jt < 4; ++jt) {
+                            double y[3], N[3], nw[3];
+                            quad_map(P, q4x[js], q4x[jt], y, N);
+                            for (int c = 0; c < 3; ++c) nw[c] = sg * N[c] * q4w[js] * q4w[jt];
+                            mo.add(3, y, nw);
+                        }
+                }
             }
+            if (!(mo.V > 0)) {
+                bad = true;
+                continue;
+            }
+            m.vol[i] = mo.V;
+            double yc[3];
+            for (int a = 0; a < d; ++a) {
+                yc[a] = mo.M1[a] / mo.V;
+                m.ctr[i * d + a] = ref[a] + yc[a];
+            }
+            int q = 0;
+            for (int a = 0; a < d; ++a)
+                for (int b = a; b < d; ++b) m.sec[i * m.nq + q++] = mo.M2[a][b] / mo.V - yc[a] * yc[b];
+            m.h[i] = 2.0 * d * mo.V / sumS;
         }
-        if (!(mo.V > 0)) return CGKS_EMESH;
-        m.vol[i] = mo.V;
-        double yc[3];
-        for (int a = 0; a < d; ++a) {
-            yc[a] = mo.M1[a] / mo.V;
-            m.ctr[i * d + a] = ref[a] + yc[a];
-        }
-        int q = 0;
-        for (int a = 0; a < d; ++a)
-            for (int b = a; b < d; ++b) m.sec[i * m.nq + q++] = mo.M2[a][b] / mo.V - yc[a] * yc[b];
-        m.h[i] = 2.0 * d * mo.V / sumS;
-    }
-    return CGKS_OK;
+    });
+    return bad ? CGKS_EMESH : CGKS_OK;
 }
 
 // index of (a, b), a <= b, in the packed second-moment arrays
@@ -399,24 +427,30 @@ cgks_status recon_setup(HostMesh &m) {
         if (m.neigh[f] < 0) ghost_avg(m, f, m.gavg.data() + f * nk);
     m.minv.assign(m.n_cell * nk * nk, 0.0);
     m.linear.assign(m.n_cell, 0);
-    std::vector<long double> A;
-    for (int64_t i = 0; i < m.n_cell; ++i) {
-        int nr = 0;
-        recon_rows(m, i, A, nr);
-        std::vector<long double> Q(A);
-        if (nr >= nk && qr_ratio(nr, nk, Q) > kRankTol) {
-            inverse_normal(nk, Q, nk, m.minv.data() + i * nk * nk);
-            continue;
+    std::atomic<bool> bad{false};
+    parallel_for(m.n_cell, [&](int64_t i0, int64_t i1) {
+        std::vector<long double> A;
+        for (int64_t i = i0; i < i1; ++i) {
+            int nr = 0;
+            recon_rows(m, i, A, nr);
+            std::vector<long double> Q(A);
+            if (nr >= nk && qr_ratio(nr, nk, Q) > kRankTol) {
+                inverse_normal(nk, Q, nk, m.minv.data() + i * nk * nk);
+                continue;
+            }
+            // linear fallback: the same rows restricted to the linear columns
+            std::vector<long double> L(nr * d);
+            for (int r = 0; r < nr; ++r)
+                for (int a = 0; a < d; ++a) L[r * d + a] = A[r * nk + a];
+            if (!(qr_ratio(nr, d, L) > kRankTol)) {
+                bad = true;
+                continue;
+            }
+            inverse_normal(d, L, nk, m.minv.data() + i * nk * nk);
+            m.linear[i] = 1;
         }
-        // linear fallback: the same rows restricted to the linear columns
-        std::vector<long double> L(nr * d);
-        for (int r = 0; r < nr; ++r)
-            for (int a = 0; a < d; ++a) L[r * d + a] = A[r * nk + a];
-        if (!(qr_ratio(nr, d, L) > kRankTol)) return CGKS_EMESH;
-        inverse_normal(d, L, nk, m.minv.data() + i * nk * nk);
-        m.linear[i] = 1;
-    }
-    return CGKS_OK;
+    });
+    return bad ? CGKS_EMESH : CGKS_OK;
 }
 
 // Morton (Z-order) key: the bits of 21-bit (3-D) or 32-bit (2-D) grid
