@@ -135,3 +135,26 @@ def test_batch_parameters_are_validated(over, expect):
     assert st == expect
     if st == 0:
         L.cgks_batch_destroy(h)
+
+
+def test_invalid_batch_arguments_are_rejected_on_the_host():
+    """Empty and inconsistent inputs return CGKS_EINVAL before any device
+    work: no cases, NULL arrays or output handle, an unknown precision, cases
+    of different dimensions in one batch, a NULL mesh among the cases, and
+    NULL handles for the query and solve calls."""
+    import ctypes as C
+    L = cg.lib()
+    m2, m3 = cg.Mesh(I.cylinder_mesh(16, 8)), cg.Mesh(I.box3d_mesh((3, 3, 5), periodic=True))
+    p = cg.Params(W_inf=I.free_stream(2, 0.2)).c()
+    pp = (cg._Params * 2)(p, p)
+    h = C.c_void_p()
+    one = (C.c_void_p * 1)(m2.h)
+    assert L.cgks_batch_create(one, C.byref(p), 0, cg.FP64, C.byref(h)) == cg.EINVAL
+    assert L.cgks_batch_create(None, C.byref(p), 1, cg.FP64, C.byref(h)) == cg.EINVAL
+    assert L.cgks_batch_create(one, C.byref(p), 1, cg.FP64, None) == cg.EINVAL
+    assert L.cgks_batch_create(one, C.byref(p), 1, 7, C.byref(h)) == cg.EINVAL
+    assert L.cgks_batch_create((C.c_void_p * 2)(m2.h, m3.h), pp, 2, cg.FP64, C.byref(h)) == cg.EINVAL
+    assert L.cgks_batch_create((C.c_void_p * 2)(m2.h, None), pp, 2, cg.FP64, C.byref(h)) == cg.EINVAL
+    assert L.cgks_mesh_query(None, C.byref(cg._Info())) == cg.EINVAL
+    assert L.cgks_solve(None, None, None, None) == cg.EINVAL
+    assert L.cgks_status_string(cg.EINVAL) == b"invalid argument"
