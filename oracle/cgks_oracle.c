@@ -15,9 +15,11 @@
  * Parity unpinned (no check independent of this file beyond agreement with
  * the HIP path and behavioural tests): the weights of the reconstruction's
  * least-squares rows (recon_cell; its exactness on quadratic data is
- * pinned), the high-order time-step rule (cell_dt, om_dt), the spectral
- * radius of the implicit operator (side_radius) and the low level's local
- * time step (cell_dt with cfl_low).
+ * pinned), the high-order time-step rule (cell_dt, om_dt), the viscous term
+ * of the implicit operator's spectral radius (side_radius: its inviscid part
+ * |U.n| + c and the larger-of-two-sides rule are pinned through the
+ * Lax-Friedrichs mass flux at rest) and the low level's local time step
+ * (cell_dt with cfl_low).
  *
  * Build: gcc -O2 -fno-fast-math -ffp-contract=off -fPIC -shared.
  */

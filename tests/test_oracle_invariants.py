@@ -283,3 +283,46 @@ def test_multigrid_accelerates_viscous_cylinder():
         drops[expl] = res[-1] / res[0]
     assert drops[0] < 1e-4
     assert drops[0] < 1e-2 * drops[1], drops
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_low_level_mass_fluxes_at_rest_match_closed_forms(dim):
+    """Gas at rest at uniform pressure p, inviscid, with the density of one
+    cell i raised: across a face of i only the numerical dissipation moves
+    mass, so each neighbour j's first-order mass residual (the face sum, not
+    divided by the volume) is S_f times the mass flux from i to j, and i's is
+    minus the sum over its faces.
+    Closed forms, independent of the oracle's code:
+      KFVS: the one-sided mass flux of a Maxwellian at rest is
+            rho sqrt(theta / 2 pi) = sqrt(rho p / 2 pi) (kinetic theory), so
+            the flux is sqrt(p / 2 pi) (sqrt(rho_i) - sqrt(rho_j));
+      Lax-Friedrichs: 1/2 lam_f (rho_i - rho_j) with lam_f the larger of the
+            two sides' spectral radii of the Euler flux Jacobian, |U.n| + c
+            = c = sqrt(gamma p / rho) at rest (the lighter side here).
+    This pins the inviscid part of the implicit operator's spectral radius
+    and the max-of-sides rule."""
+    if dim == 2:
+        mesh = I.box2d_mesh(6, perturb=0.0, seed=1)
+    else:
+        mesh = I.box3d_mesh((4, 4, 4), periodic=True)
+    om = oracle.Mesh(mesh)
+    S = om.faces()["S"]
+    own, nb = np.asarray(mesh["face_owner"]), np.asarray(mesh["face_neigh"])
+    n, g, p = mesh["n_cell"], 1.4, 0.7
+    i = n // 2
+    fi = np.flatnonzero((own == i) | (nb == i))
+    assert len(fi) >= dim + 1 and (nb[fi] >= 0).all()
+    rho_i, rho_0 = 1.3, 1.0
+    W = np.zeros((dim + 2, n))
+    W[0] = rho_0
+    W[0, i] = rho_i
+    W[dim + 1] = p / (g - 1.0)
+    flux = {oracle.LOW_KFVS: np.sqrt(p / (2 * np.pi)) * (np.sqrt(rho_i) - np.sqrt(rho_0)),
+            oracle.LOW_LF: 0.5 * np.sqrt(g * p / rho_0) * (rho_i - rho_0)}
+    for lf, F in flux.items():
+        s = oracle.Solver(om, oracle.Params(W_inf=I.free_stream(dim, 0.0), mu=0.0, gamma=g, low_flux=lf))
+        R = s.residual_low(W)
+        for f in fi:
+            j = nb[f] if own[f] == i else own[f]
+            assert R[0, j] == pytest.approx(S[f] * F, rel=1e-12), (lf, f)
+        assert R[0, i] == pytest.approx(-S[fi].sum() * F, rel=1e-12), lf
