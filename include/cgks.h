@@ -228,7 +228,10 @@ cgks_status cgks_batch_destroy(cgks_batch *batch);
 
 /* Set / read the state of case c from host arrays in caller cell order:
    W_host [dim+2][n_cell], dW_host [dim][dim+2][n_cell] (NULL = zero on
-   upload, skipped on download).  Synchronous on stream. */
+   upload, skipped on download).  Synchronous on stream.  The copy goes
+   through a pinned host buffer that the batch keeps, grown to the largest
+   case transferred and freed with the batch (CGKS_EDEVICE if it cannot be
+   allocated). */
 cgks_status cgks_state_upload(cgks_batch *batch, int32_t c, const double *W_host, const double *dW_host,
                               void *stream);
 cgks_status cgks_state_download(cgks_batch *batch, int32_t c, double *W_host, double *dW_host, void *stream);

@@ -143,9 +143,13 @@ struct cgks_batch {
         graph = nullptr;
         graph_cycles = 0;
     }
+    // pinned host staging of state transfers, grown to the largest case
+    double *xfer = nullptr;
+    size_t xfer_cap = 0;
     ~cgks_batch() {
         drop_graph();
         for (hipEvent_t e : events) (void)hipEventDestroy(e);
+        if (xfer) (void)hipHostFree(xfer);
     }
 };
 
@@ -938,27 +942,41 @@ static cgks_status state_xfer(cgks_batch *b, int32_t c, double *W, double *dW, v
     const HostMesh &m = b->meshes[c]->hm;
     const int d = b->dim, nv = d + 2, sr = nv + d * nv;
     const int64_t n = m.n_cell, co = b->cell_off[c];
-    std::vector<double> buf(size_t(n) * sr);
+    const size_t len = size_t(n) * sr;
+    if (len > b->xfer_cap) {
+        if (b->xfer) (void)hipHostFree(b->xfer);
+        b->xfer = nullptr;
+        b->xfer_cap = 0;
+        HIP_TRY(hipHostMalloc(reinterpret_cast<void **>(&b->xfer), len * sizeof(double), hipHostMallocDefault));
+        b->xfer_cap = len;
+    }
+    double *buf = b->xfer;
     double *dev = b->dev.st + size_t(co) * sr;
+    // the permutation between caller and library order runs on host threads,
+    // each writing its own cells
     if (up) {
-        for (int64_t l = 0; l < n; ++l) {
-            const int64_t i = m.lib2caller[l];
-            for (int r = 0; r < nv; ++r) buf[l * sr + r] = W[r * n + i];
-            for (int r = 0; r < d * nv; ++r) buf[l * sr + nv + r] = dW ? dW[r * n + i] : 0.0;
-        }
-        HIP_TRY(hipMemcpyAsync(dev, buf.data(), buf.size() * sizeof(double), hipMemcpyHostToDevice, s));
+        parallel_for(n, [&](int64_t l0, int64_t l1) {
+            for (int64_t l = l0; l < l1; ++l) {
+                const int64_t i = m.lib2caller[l];
+                for (int r = 0; r < nv; ++r) buf[l * sr + r] = W[r * n + i];
+                for (int r = 0; r < d * nv; ++r) buf[l * sr + nv + r] = dW ? dW[r * n + i] : 0.0;
+            }
+        });
+        HIP_TRY(hipMemcpyAsync(dev, buf, len * sizeof(double), hipMemcpyHostToDevice, s));
         HIP_TRY(hipStreamSynchronize(s));
         return CGKS_OK;
     }
-    HIP_TRY(hipMemcpyAsync(buf.data(), dev, buf.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(buf, dev, len * sizeof(double), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
-    for (int64_t l = 0; l < n; ++l) {
-        const int64_t i = m.lib2caller[l];
-        if (W)
-            for (int r = 0; r < nv; ++r) W[r * n + i] = buf[l * sr + r];
-        if (dW)
-            for (int r = 0; r < d * nv; ++r) dW[r * n + i] = buf[l * sr + nv + r];
-    }
+    parallel_for(n, [&](int64_t l0, int64_t l1) {
+        for (int64_t l = l0; l < l1; ++l) {
+            const int64_t i = m.lib2caller[l];
+            if (W)
+                for (int r = 0; r < nv; ++r) W[r * n + i] = buf[l * sr + r];
+            if (dW)
+                for (int r = 0; r < d * nv; ++r) dW[r * n + i] = buf[l * sr + nv + r];
+        }
+    });
     return CGKS_OK;
 }
 

@@ -15,25 +15,6 @@
 namespace cgks {
 namespace {
 
-// fn(begin, end) over [0, n) in contiguous chunks on up to 16 host threads.
-// Used only for loops whose iterations write their own entries, so the
-// results do not depend on the split.
-template <class F> void parallel_for(int64_t n, F &&fn) {
-    const unsigned hw = std::thread::hardware_concurrency();
-    const int64_t nt = std::min<int64_t>(std::max(1u, std::min(hw, 16u)), std::max<int64_t>(1, n / 4096));
-    if (nt <= 1) {
-        fn(int64_t(0), n);
-        return;
-    }
-    std::vector<std::thread> pool;
-    const int64_t chunk = (n + nt - 1) / nt;
-    for (int64_t t = 0; t < nt; ++t) {
-        const int64_t a = t * chunk, b = std::min(n, a + chunk);
-        if (a < b) pool.emplace_back([&fn, a, b] { fn(a, b); });
-    }
-    for (auto &th : pool) th.join();
-}
-
 struct V3 {
     double x[3] = {0, 0, 0};
 };
