@@ -59,6 +59,7 @@ def lib():
         L.om_moment.restype = d
         L.om_moment.argtypes = [i, d, dp, i, i, i, i, i]
         L.om_micro_slope.argtypes = [i, d, dp, dp, dp]
+        L.om_farfield_state.argtypes = [i, d, dp, dp, dp]
         L.om_ctx_create.restype = P
         L.om_ctx_create.argtypes = [P, P]
         L.om_ctx_destroy.argtypes = [P]
@@ -285,6 +286,15 @@ def kfvs(UL, UR, gamma=1.4):
     out = np.zeros_like(UL)
     if lib().om_kfvs(len(UL) - 2, gamma, UL, _c64(UR), out):
         raise RuntimeError("non-physical state")
+    return out
+
+
+def farfield_state(W_in, W_inf, gamma=1.4):
+    """Far-field boundary state from the interior state and the free stream,
+    both in the face frame (axis 0 = outward normal)."""
+    W_in = _c64(W_in)
+    out = np.zeros_like(W_in)
+    lib().om_farfield_state(len(W_in) - 2, gamma, W_in, _c64(W_inf), out)
     return out
 
 

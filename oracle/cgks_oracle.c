@@ -14,12 +14,16 @@
  *
  * Parity unpinned (no check independent of this file beyond agreement with
  * the HIP path and behavioural tests): the weights of the reconstruction's
- * least-squares rows (recon_cell; its exactness on quadratic data is
- * pinned), the high-order time-step rule (cell_dt, om_dt), the viscous term
- * of the implicit operator's spectral radius (side_radius: its inviscid part
- * |U.n| + c and the larger-of-two-sides rule are pinned through the
- * Lax-Friedrichs mass flux at rest) and the low level's local time step
- * (cell_dt with cfl_low).
+ * least-squares rows (recon_cell; its exactness on quadratic data, with
+ * and without the mirror ghost rows of walls, is pinned), the high-order
+ * time-step rule (cell_dt, om_dt), the viscous term of the implicit
+ * operator's spectral radius (side_radius: its inviscid part |U.n| + c and
+ * the larger-of-two-sides rule are pinned through the Lax-Friedrichs mass
+ * flux at rest) and the low level's local time step (cell_dt with
+ * cfl_low).  The relaxation update of om_lowlevel is pinned through the
+ * backward-Euler equation its converged sweeps solve, ghost_cell through
+ * mirror-symmetric quadratics and farfield_state through the Riemann
+ * invariants, entropy and tangential velocity it must carry.
  *
  * Build: gcc -O2 -fno-fast-math -ffp-contract=off -fPIC -shared.
  */
@@ -435,7 +439,8 @@ void om_mesh_faces(const om_mesh *m, int *ngp, double *gx, double *gn, double *g
 /* the cell average exactly; the c_k solve, in the least-squares sense,  */
 /*   <P_i>_m = W_m and h_i <grad P_i>_m = h_i gradW_m  for every face     */
 /*   neighbour m, and h_i <grad P_i>_i = h_i gradW_i,                     */
-/* unweighted rows, by Householder QR.  Boundary faces add no rows.      */
+/* unweighted rows, by Householder QR.  A boundary face brings the rows  */
+/* of its ghost cell (ghost_cell below) when boundary data are given.    */
 /* ------------------------------------------------------------------ */
 /* a stencil whose rows do not fix every quadratic coefficient (an R
    diagonal below RANK_TOL of the largest) falls back to the linear
@@ -1091,7 +1096,11 @@ static void grad_to_local(int dim, double e[3][3], const double *dW, double *dWl
 }
 
 /* non-reflecting far field from the normal Riemann invariants of the
-   interior state and the free stream (local frame, axis 0 outward) */
+   interior state and the free stream (local frame, axis 0 outward):
+   the outgoing invariant U_n + 2c/(gamma-1) comes from the interior, the
+   incoming U_n - 2c/(gamma-1) from the free stream; entropy p/rho^gamma and
+   the tangential velocity from the side the flow comes from; supersonic
+   inflow takes the free stream, supersonic outflow the interior */
 static void farfield_state(int dim, double gamma, const double *Wl, const double *Winf_l, double *Wb) {
     int nv = dim + 2;
     prim I = to_prim(Wl, dim, gamma), O = to_prim(Winf_l, dim, gamma);
@@ -1111,6 +1120,11 @@ static void farfield_state(int dim, double gamma, const double *Wl, const double
     double ke = 0;
     for (int a = 0; a < dim; a++) { Wb[1 + a] = rho * U[a]; ke += U[a] * U[a]; }
     Wb[nv - 1] = p / (gamma - 1.0) + 0.5 * rho * ke;
+}
+
+/* exported for the far-field pins (local frame, axis 0 outward) */
+void om_farfield_state(int dim, double gamma, const double *Wl, const double *Winf_l, double *Wb) {
+    farfield_state(dim, gamma, Wl, Winf_l, Wb);
 }
 
 /* ------------------------------------------------------------------ */
