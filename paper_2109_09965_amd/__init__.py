@@ -145,6 +145,31 @@ def _ptr(a):
     return a.ctypes.data_as(C.c_void_p) if a is not None else None
 
 
+def _check_tensor(t, min_numel, what):
+    """A device buffer handed to the library must be a contiguous float64
+    CUDA tensor with at least min_numel elements (the library writes or
+    reads that many): anything else raises ValueError before the call."""
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise ValueError(f"{what}: expected a torch tensor, got {type(t).__name__}")
+    if t.dtype != torch.float64:
+        raise ValueError(f"{what}: expected float64, got {t.dtype}")
+    if not t.is_cuda:
+        raise ValueError(f"{what}: expected a device (cuda) tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{what}: expected a contiguous tensor")
+    if t.numel() < min_numel:
+        raise ValueError(f"{what}: {t.numel()} elements, the library needs {min_numel}")
+
+
+def _host_array(a, shape, what):
+    """Host state array as contiguous float64 of exactly `shape`."""
+    a = np.ascontiguousarray(a, np.float64)
+    if a.shape != tuple(shape):
+        raise ValueError(f"{what}: shape {a.shape}, expected {tuple(shape)}")
+    return a
+
+
 @dataclass
 class Params:
     """Per-case parameters (cgks_params); W_inf holds dim+2 conservative values."""
@@ -296,6 +321,7 @@ class Batch:
             return None
         _check(st, "cgks_batch_admit")
         c = slot.value
+        self.graph_cycles = 0      # admission drops a captured graph
         self.meshes[c] = mesh
         self.params[c] = params
         self._slots()
@@ -303,6 +329,7 @@ class Batch:
 
     def release(self, slot):
         _check(lib().cgks_batch_release(self.h, slot, _stream(self.stream)), "cgks_batch_release")
+        self.graph_cycles = 0      # release drops a captured graph
         self.meshes[slot] = None
         self.params[slot] = None
         self._slots()
@@ -312,13 +339,19 @@ class Batch:
             _lib.cgks_batch_destroy(self.h)
             self.h = None
 
+    def _case_mesh(self, c):
+        if not (0 <= c < self.n_case) or self.meshes[c] is None:
+            raise ValueError(f"case {c}: no case in this slot")
+        return self.meshes[c]
+
     def upload(self, c, W, dW=None):
-        W = np.ascontiguousarray(W, np.float64)
-        dW = None if dW is None else np.ascontiguousarray(dW, np.float64)
+        n = self._case_mesh(c).n_cell
+        W = _host_array(W, (self.nv, n), "W")
+        dW = None if dW is None else _host_array(dW, (self.dim, self.nv, n), "dW")
         _check(lib().cgks_state_upload(self.h, c, _ptr(W), _ptr(dW), _stream(self.stream)), "cgks_state_upload")
 
     def download(self, c):
-        m = self.meshes[c]
+        m = self._case_mesh(c)
         W = np.zeros((self.nv, m.n_cell))
         dW = np.zeros((self.dim, self.nv, m.n_cell))
         _check(lib().cgks_state_download(self.h, c, _ptr(W), _ptr(dW), _stream(self.stream)), "cgks_state_download")
@@ -343,10 +376,13 @@ class Batch:
         return out
 
     def lowlevel_smooth(self, R1):
+        _check_tensor(R1, self.nv * self.NC, "R1")
         _check(lib().cgks_lowlevel_smooth(self.h, C.c_void_p(R1.data_ptr()), _stream(self.stream)),
                "cgks_lowlevel_smooth")
 
     def cycle(self, res=None):
+        if res is not None:
+            _check_tensor(res, self.n_case, "res")
         ptr = C.c_void_p(res.data_ptr()) if res is not None else None
         _check(lib().cgks_cycle(self.h, ptr, _stream(self.stream)), "cgks_cycle")
 
@@ -357,6 +393,10 @@ class Batch:
 
     def graph_launch(self, res_history=None):
         """Replay the captured cycles; res_history: device float64 [n_cycles * n_case] or None."""
+        if res_history is not None:
+            if getattr(self, "graph_cycles", 0) <= 0:
+                raise ValueError("graph_launch: no graph captured")
+            _check_tensor(res_history, self.graph_cycles * self.n_case, "res_history")
         ptr = C.c_void_p(res_history.data_ptr()) if res_history is not None else None
         _check(lib().cgks_graph_launch(self.h, ptr, _stream(self.stream)), "cgks_graph_launch")
 
@@ -364,6 +404,7 @@ class Batch:
         """Measure and keep the fastest launch shapes; returns them."""
         ch = np.zeros(5, np.int32)
         _check(lib().cgks_batch_autotune(self.h, _ptr(ch), _stream(self.stream)), "cgks_batch_autotune")
+        self.graph_cycles = 0      # tuning drops a captured graph
         return dict(flux_block=int(ch[0]), cell_block=int(ch[1]), low_face_block=int(ch[2]),
                     low_cell_block=int(ch[3]), sweep_chunk=int(ch[4]))
 
@@ -391,6 +432,10 @@ class Batch:
             opts.res_history = hist.ctypes.data_as(C.c_void_p)
         rep = (_SolveReport * self.n_case)()
         _check(lib().cgks_solve(self.h, C.byref(opts), rep, _stream(self.stream)), "cgks_solve")
+        # with 2 <= check_every <= 8 the library replaced any captured graph by
+        # one of check_every cycles; otherwise the previous graph is kept
+        if 2 <= check_every <= 8:
+            self.graph_cycles = check_every
         out = [dict(cycles=r.cycles, converged=bool(r.converged), res_first=r.res_first, res_last=r.res_last,
                     status=r.status, force=np.array(r.force[:])) for r in rep]
         return out, hist
