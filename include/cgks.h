@@ -257,6 +257,24 @@ cgks_status cgks_highorder_stage(cgks_batch *batch, int32_t stage, void *stream)
    sum |rho_new - rho_old| / sum rho_old (Sec. 4). */
 cgks_status cgks_residual(cgks_batch *batch, int32_t kind, double *out_dev, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+   capture, serving loops or harnesses that forbid hipMalloc): the
+   transferred residual R1 of cgks_residual(CGKS_RESIDUAL_HIGH), from the
+   same kernels and bitwise the same, but the residual pass's work arrays
+   (boundary ghost data, reconstruction records, face sums) live in a fixed
+   64 MiB array of the library on the current device instead of the batch
+   arena.  Batches whose launch extents need more get CGKS_ENOMEM (the pass
+   needs about 1.2 KB per cell in 3-D FP64, 0.5 KB in 2-D, less in
+   MIXED32).  The batch must be bound on the current device (CGKS_EINVAL
+   otherwise).  out_dev: [dim+2][max_cells] as for cgks_residual; entries of
+   cells outside any case are left untouched.  Calls no hipMalloc, hipFree
+   or other allocating routine (kernel timing is not recorded for this
+   call).  Each device holds one copy of the array, shared by every call on
+   it: calls that overlap on one device race, so serialise them (one stream,
+   or events).  The first call on a device looks up the array's address
+   (CGKS_EDEVICE if that fails). */
+cgks_status cgks_residual_high_noalloc(cgks_batch *batch, double *out_dev, void *stream);
+
 /* Low level of the cycle (Sec. 3 steps 2-5) on every case: W_p0 = W,
    forcing S = R1 - R0(W_p0), n_implicit backward-Euler steps solved by
    multicolour point relaxation, W += U - W_p0.  R1_dev as written by

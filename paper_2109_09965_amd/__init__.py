@@ -31,7 +31,7 @@ EXPORTS = ["cgks_status_string", "cgks_mesh_create", "cgks_mesh_query", "cgks_me
            "cgks_residual", "cgks_lowlevel_smooth", "cgks_cycle", "cgks_solve", "cgks_timing_enable",
            "cgks_timing_read", "cgks_graph_create", "cgks_graph_launch", "cgks_graph_destroy", "cgks_wall_force",
            "cgks_pool_create", "cgks_batch_admit", "cgks_batch_release", "cgks_batch_capacity", "cgks_batch_slot_info",
-           "cgks_batch_autotune"]
+           "cgks_batch_autotune", "cgks_residual_high_noalloc"]
 KERNEL_KINDS = ["dt", "recon", "flux", "cell", "low_face", "low_cell", "sweep", "prolong"]
 
 
@@ -130,6 +130,7 @@ def lib():
         L.cgks_batch_capacity.argtypes = [P, C.POINTER(C.c_int32), C.POINTER(C.c_int64)]
         L.cgks_batch_slot_info.argtypes = [P, i32, C.POINTER(C.c_int32), C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
         L.cgks_batch_autotune.argtypes = [P, P, P]
+        L.cgks_residual_high_noalloc.argtypes = [P, P, P]
         for name in EXPORTS:
             getattr(L, name).restype = C.c_int if name != "cgks_status_string" else C.c_char_p
         _lib = L
@@ -367,6 +368,19 @@ class Batch:
         out = torch.empty(n, dtype=torch.float64, device=self.arena.device)
         _check(lib().cgks_residual(self.h, kind, C.c_void_p(out.data_ptr()), _stream(self.stream)), "cgks_residual")
         return out if kind == RESIDUAL_NORM else out.view(self.nv, self.NC)
+
+    def residual_high_noalloc(self, out=None):
+        """R1 like residual(RESIDUAL_HIGH), computed with the library's fixed
+        device scratch instead of the batch arena (the entry point for
+        callers that cannot allocate).  out: float64 device tensor of
+        nv * NC elements (allocated here when None)."""
+        import torch
+        if out is None:
+            out = torch.empty(self.nv * self.NC, dtype=torch.float64, device=self.arena.device)
+        _check_tensor(out, self.nv * self.NC, "out")
+        _check(lib().cgks_residual_high_noalloc(self.h, C.c_void_p(out.data_ptr()), _stream(self.stream)),
+               "cgks_residual_high_noalloc")
+        return out.view(self.nv, self.NC)
 
     def to_caller(self, c, X):
         """[k, NC] library-order array (numpy) -> [k, n_c] in case c's caller order."""

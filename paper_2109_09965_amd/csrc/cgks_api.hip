@@ -6,6 +6,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -324,8 +325,7 @@ template <class F> void timed(cgks_batch *b, int kind, hipStream_t s, F &&launch
         if ((x) != hipSuccess) return CGKS_EDEVICE;     \
     } while (0)
 
-template <int D, typename R> void launch_ho_kernels(cgks_batch *b, int mode, hipStream_t s) {
-    const Dev &d = b->dev;
+template <int D, typename R> void launch_ho_kernels(cgks_batch *b, const Dev &d, int mode, hipStream_t s) {
     timed(b, CGKS_K_RECON, s, [&] {
         if (b->hwB > 0) hipLaunchKernelGGL(k_ghost<D>, dim3(nblk(b->hwB)), dim3(kBlock), 0, s, d);
         hipLaunchKernelGGL((k_recon<D, R>), dim3(unsigned((b->hwC + kReconBlock - 1) / kReconBlock)),
@@ -351,8 +351,8 @@ template <int D> cgks_status launch_highorder(cgks_batch *b, int mode, hipStream
     }
     // MIXED32_R64 evaluates the residual pass R1 in FP64
     if (b->precision == CGKS_MIXED32 || (b->precision == CGKS_MIXED32_R64 && mode != MODE_R1))
-        launch_ho_kernels<D, float>(b, mode, s);
-    else launch_ho_kernels<D, double>(b, mode, s);
+        launch_ho_kernels<D, float>(b, d, mode, s);
+    else launch_ho_kernels<D, double>(b, d, mode, s);
     HIP_TRY(hipGetLastError());
     return CGKS_OK;
 }
@@ -424,6 +424,84 @@ template <int D, typename S> cgks_status launch_lowlevel_s(cgks_batch *b, const 
 template <int D> cgks_status launch_lowlevel(cgks_batch *b, const double *R1, hipStream_t s) {
     return b->precision != CGKS_FP64 ? launch_lowlevel_s<D, float>(b, R1, s)
                                      : launch_lowlevel_s<D, double>(b, R1, s);
+}
+
+// ---------------------------------------------------------------------
+// Scratch of cgks_residual_high_noalloc: the ghost data, reconstruction
+// records and face sums of one residual pass live in this array instead of
+// the batch arena, for callers that cannot allocate.  Every device the
+// library runs on holds its own copy until the process ends.  In host code
+// the name stands for a host-side shadow, never a device address: kernels
+// receive the address hipGetSymbolAddress returns for the current device.
+// ---------------------------------------------------------------------
+constexpr size_t kScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_dev[kMaxDevices] = {};
+
+// device address of `scratch` on the current device, looked up once per device
+cgks_status scratch_address(void **out) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return CGKS_EDEVICE;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return CGKS_EDEVICE;
+        g_scratch_dev[dev] = p;
+    }
+    *out = g_scratch_dev[dev];
+    return CGKS_OK;
+}
+
+// byte offsets of the residual pass's scratch arrays (256-byte aligned) for
+// the batch's launch extents; returns the bytes needed
+template <int D> size_t scratch_plan(const cgks_batch *b, size_t &o_ev, size_t &o_gd, size_t &o_fs) {
+    const size_t rb = b->precision == CGKS_MIXED32 ? sizeof(float) : sizeof(double);
+    size_t off = 0;
+    auto take = [&off](size_t n) {
+        off = (off + 255) & ~size_t(255);
+        const size_t o = off;
+        off += n;
+        return o;
+    };
+    // the reconstruction stores whole blocks of kReconBlock records (up to NC)
+    const int64_t rec_cells = std::min<int64_t>(b->NC, (b->hwC + kReconBlock - 1) / kReconBlock * kReconBlock);
+    o_ev = take(size_t(rec_cells) * Rec<D>::er * rb);
+    o_gd = take(size_t(std::max<int64_t>(b->hwB, 1)) * (Rec<D>::sr) * sizeof(double));
+    // faces beyond the high-water mark belong to no case and store nothing
+    o_fs = take(size_t(b->hwF) * Dim<D>::fs * rb);
+    return off;
+}
+
+template <int D> cgks_status residual_high_noalloc(cgks_batch *b, double *out, hipStream_t s) {
+    size_t o_ev = 0, o_gd = 0, o_fs = 0;
+    if (scratch_plan<D>(b, o_ev, o_gd, o_fs) > kScratchBytes) return CGKS_ENOMEM;
+    void *base = nullptr;
+    cgks_status st = scratch_address(&base);
+    if (st) return st;
+    // the batch's arena must be on the current device (the scratch is per device)
+    int dev = -1;
+    hipPointerAttribute_t attr{};
+    if (hipGetDevice(&dev) != hipSuccess || hipPointerGetAttributes(&attr, b->base) != hipSuccess) return CGKS_EDEVICE;
+    if (attr.device != dev) return CGKS_EINVAL;
+    char *sb = static_cast<char *>(base);
+    Dev d = b->dev;
+    d.ev = reinterpret_cast<double *>(sb + o_ev);
+    d.ev32 = reinterpret_cast<float *>(sb + o_ev);
+    d.gdat = reinterpret_cast<double *>(sb + o_gd);
+    d.fsum = reinterpret_cast<double *>(sb + o_fs);
+    d.fsum32 = reinterpret_cast<float *>(sb + o_fs);
+    d.R1 = out;
+    // no timing events here: creating them would allocate
+    const bool timing = b->timing;
+    b->timing = false;
+    if (b->precision == CGKS_MIXED32) launch_ho_kernels<D, float>(b, d, MODE_R1, s);
+    else launch_ho_kernels<D, double>(b, d, MODE_R1, s);
+    b->timing = timing;
+    HIP_TRY(hipGetLastError());
+    return CGKS_OK;
 }
 
 template <int D> cgks_status launch_cycle(cgks_batch *b, hipStream_t s) {
@@ -1034,6 +1112,12 @@ cgks_status cgks_residual(cgks_batch *b, int32_t kind, double *out, void *stream
         return CGKS_OK;
     }
     return CGKS_EINVAL;
+}
+
+cgks_status cgks_residual_high_noalloc(cgks_batch *b, double *out, void *stream) {
+    if (!b || !b->base || !out) return CGKS_EINVAL;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    return b->dim == 2 ? residual_high_noalloc<2>(b, out, s) : residual_high_noalloc<3>(b, out, s);
 }
 
 cgks_status cgks_lowlevel_smooth(cgks_batch *b, const double *R1, void *stream) {
