@@ -22,6 +22,7 @@ _lib = None
 
 S2O4, S1O2 = 0, 1
 LOW_KFVS, LOW_LF = 0, 1
+FLUX_SMOOTH, FLUX_FULL = 0, 1
 
 
 def build(force: bool = True) -> str:
@@ -55,6 +56,7 @@ def lib():
         L.om_recon_linear_cells.argtypes = [P, P, ip]
         L.om_gks_flux.argtypes = [i, d, d, d, dp, dp, dp, dp, dp]
         L.om_halfspace_state.argtypes = [i, d, dp, dp, dp]
+        L.om_gks_flux_full.argtypes = [i, d, d, d, d, dp, dp, dp, dp, dp, dp, dp, dp]
         L.om_kfvs.argtypes = [i, d, dp, dp, dp]
         L.om_moment.restype = d
         L.om_moment.argtypes = [i, d, dp, i, i, i, i, i]
@@ -85,7 +87,8 @@ class _CParams(C.Structure):
     _fields_ = [("gamma", C.c_double), ("mu", C.c_double), ("Pr", C.c_double), ("T_wall", C.c_double),
                 ("W_inf", C.c_double * 5), ("cfl_high", C.c_double), ("cfl_low", C.c_double),
                 ("n_implicit", C.c_int), ("n_sweeps", C.c_int), ("time_scheme", C.c_int),
-                ("explicit_only", C.c_int), ("dt_fixed", C.c_double), ("low_flux", C.c_int)]
+                ("explicit_only", C.c_int), ("dt_fixed", C.c_double), ("low_flux", C.c_int),
+                ("flux_kind", C.c_int), ("weno_eps", C.c_double)]
 
 
 @dataclass
@@ -104,6 +107,8 @@ class Params:
     explicit_only: int = 0
     dt_fixed: float = 0.0
     low_flux: int = LOW_KFVS
+    flux_kind: int = FLUX_SMOOTH
+    weno_eps: float = 0.0
 
     def c(self):
         p = _CParams()
@@ -116,6 +121,8 @@ class Params:
         p.time_scheme, p.explicit_only = self.time_scheme, self.explicit_only
         p.dt_fixed = self.dt_fixed
         p.low_flux = self.low_flux
+        p.flux_kind = self.flux_kind
+        p.weno_eps = self.weno_eps
         return p
 
 
@@ -271,6 +278,17 @@ def gks_flux(W, dW, gamma=1.4, mu=0.0, Pr=1.0):
     if st:
         raise RuntimeError("non-physical state")
     return F0, Ft, Wt
+
+
+def gks_flux_full(WL, dWL, WR, dWR, dt, gamma=1.4, mu=0.0, Pr=1.0):
+    """Full time-dependent solution in the face frame: (F0, Ft, W0, Wt)."""
+    WL = _c64(WL)
+    dim = len(WL) - 2
+    out = [np.zeros(dim + 2) for _ in range(4)]
+    st = lib().om_gks_flux_full(dim, gamma, mu, Pr, dt, WL, _c64(dWL).ravel(), _c64(WR), _c64(dWR).ravel(), *out)
+    if st:
+        raise RuntimeError("non-physical state")
+    return tuple(out)
 
 
 def halfspace_state(WL, WR, gamma=1.4):

@@ -47,6 +47,8 @@ typedef struct {
     int explicit_only; /* 1: high-order step only, no low-order level */
     double dt_fixed;   /* > 0: use this global time step instead of the CFL rule */
     int low_flux;      /* first-order flux of the low-order level: 0 KFVS, 1 Lax-Friedrichs */
+    int flux_kind;     /* high-order flux: 0 smooth solution, 1 full time-dependent solution */
+    double weno_eps;   /* > 0: nonlinear reconstruction weights with this epsilon; 0: linear weights */
 } om_params;
 
 typedef struct {
@@ -609,13 +611,96 @@ static int ghost_cell(const om_mesh *m, const om_params *P, long i, long f, cons
     return 0;
 }
 
+/* Nonlinear weights of the compact reconstruction, for flows with
+   discontinuities (Sec. 4 uses WENO-type weights there with a small
+   positive epsilon; their form is taken from other work).  Reading: the
+   candidates are the quadratic P0 of the least-squares fit and, for every
+   face neighbour or ghost m of the stencil, the linear polynomial P_m that
+   fits m's average and h-scaled averaged gradient alone in the least-squares
+   sense; linear weights gamma_0 = 0.95 for P0 and (1 - gamma_0)/M for each
+   of the M linear candidates; smoothness indicators in the cell's scaled
+   coordinates xi = (x - x_i)/h_i,
+     beta = sum_a <(dP/dxi_a)^2>_i + sum_{a<=b} (d2P/dxi_a dxi_b)^2
+   (<.>_i the cell average); weights omega_k proportional to
+   gamma_k / (eps + beta_k)^2, normalised per variable; and the result
+     P = omega_0/gamma_0 (P0 - sum_m gamma_m P_m) + sum_m omega_m P_m,
+   which is P0 when the indicators agree (linear data) and tends to P0 as
+   eps grows. */
+#define WENO_GAMMA0 0.95
+static void weno_combine(const om_mesh *m, long i, int nb_count, const double *nb_xi, const double *nb_dW,
+                         const double *nb_dU, double eps, double *coef) {
+    int d = m->dim, nv = m->nv, nq = d == 2 ? 3 : 6;
+    double h = m->h[i];
+    /* linear candidates: rows xi_m . c = W_m - W_i and c = h grad W_m */
+    double cand[8][DMAX * NVMAX];
+    for (int k = 0; k < nb_count; k++) {
+        double A[(DMAX + 1) * DMAX], B[(DMAX + 1) * NVMAX];
+        for (int a = 0; a < d; a++) A[a] = nb_xi[k * d + a];
+        for (int v = 0; v < nv; v++) B[v] = nb_dU[k * nv + v];
+        for (int r = 0; r < d; r++) {
+            for (int a = 0; a < d; a++) A[(1 + r) * d + a] = r == a ? 1.0 : 0.0;
+            for (int v = 0; v < nv; v++) B[(1 + r) * nv + v] = h * nb_dW[(k * d + r) * nv + v];
+        }
+        lsq_qr(d + 1, d, A, nv, B);
+        for (int a = 0; a < d; a++)
+            for (int v = 0; v < nv; v++) cand[k][a * nv + v] = B[a * nv + v];
+    }
+    /* second moments of the cell in xi */
+    double Mxx[3][3];
+    for (int a = 0; a < d; a++)
+        for (int b = 0; b < d; b++) Mxx[a][b] = m->sec[i * 6 + sec_index(d, a, b)] / (h * h);
+    double g0 = WENO_GAMMA0, gk = (1.0 - WENO_GAMMA0) / nb_count;
+    for (int v = 0; v < nv; v++) {
+        /* Hessian of P0 in xi */
+        double D[3][3] = {{0}};
+        for (int q = 0; q < nq; q++) {
+            int p = QA[d - 2][q], r = QB[d - 2][q];
+            double c = coef[(d + q) * nv + v];
+            if (p == r) D[p][p] += 2.0 * c;
+            else { D[p][r] += c; D[r][p] += c; }
+        }
+        double beta0 = 0;
+        for (int a = 0; a < d; a++) {
+            double ca = coef[a * nv + v];
+            double quad = 0;
+            for (int b = 0; b < d; b++)
+                for (int b2 = 0; b2 < d; b2++) quad += D[a][b] * D[a][b2] * Mxx[b][b2];
+            beta0 += ca * ca + quad;
+            for (int b = a; b < d; b++) beta0 += D[a][b] * D[a][b];
+        }
+        double w0 = g0 / ((eps + beta0) * (eps + beta0));
+        double wk[8], wsum = w0;
+        for (int k = 0; k < nb_count; k++) {
+            double beta = 0;
+            for (int a = 0; a < d; a++) beta += cand[k][a * nv + v] * cand[k][a * nv + v];
+            wk[k] = gk / ((eps + beta) * (eps + beta));
+            wsum += wk[k];
+        }
+        double om0 = w0 / wsum;
+        for (int a = 0; a < d; a++) {
+            double lin = coef[a * nv + v], mix = 0;
+            for (int k = 0; k < nb_count; k++) {
+                lin -= gk * cand[k][a * nv + v];
+                mix += wk[k] / wsum * cand[k][a * nv + v];
+            }
+            coef[a * nv + v] = om0 / g0 * lin + mix;
+        }
+        for (int q = 0; q < nq; q++) coef[(d + q) * nv + v] *= om0 / g0;
+    }
+}
+
 /* coefficients c[k][v] of cell i; returns 0 (quadratic), 1 (linear
-   fallback), -1 if even the linear fit fails, -3 on an unsupported tag */
+   fallback, only without boundary data), -1 if the stencil fixes no
+   quadratic (with boundary data) or not even a linear fit, -3 on an
+   unsupported tag.  With boundary data and weno_eps > 0 the nonlinear
+   weights above are applied. */
 static int recon_cell(const om_mesh *m, const om_params *P, long i, const double *W, const double *dW,
                       double *coef) {
     int d = m->dim, nv = m->nv, nc = m->ncoef;
     long N = m->n_cell;
     double A[64 * NCMAX], B[64 * NVMAX];
+    double nb_xi[8 * DMAX], nb_dW[8 * DMAX * NVMAX], nb_dU[8 * NVMAX];
+    int nb_count = 0;
     int nr = 0;
     const double *xc = m->ctr + i * d;
     double h = m->h[i];
@@ -638,6 +723,12 @@ static int recon_cell(const om_mesh *m, const om_params *P, long i, const double
             if (st) return st;
         }
         basis_average(m, c, sec, xc, h, avg);
+        for (int a = 0; a < d; a++) nb_xi[nb_count * d + a] = avg[a];
+        for (int v = 0; v < nv; v++) {
+            nb_dU[nb_count * nv + v] = Wnb[v] - W[v * N + i];
+            for (int a = 0; a < d; a++) nb_dW[(nb_count * d + a) * nv + v] = dWnb[a * nv + v];
+        }
+        nb_count++;
         /* average row */
         for (int k = 0; k < nc; k++) A[nr * nc + k] = avg[k] - own[k];
         for (int v = 0; v < nv; v++) B[nr * nv + v] = Wnb[v] - W[v * N + i];
@@ -673,8 +764,12 @@ static int recon_cell(const om_mesh *m, const om_params *P, long i, const double
     if (nr >= nc && lsq_qr(nr, nc, A, nv, B) > 0) {
         for (int k = 0; k < nc; k++)
             for (int v = 0; v < nv; v++) coef[k * nv + v] = B[k * nv + v];
+        if (P && P->weno_eps > 0) weno_combine(m, i, nb_count, nb_xi, nb_dW, nb_dU, P->weno_eps, coef);
         return 0;
     }
+    /* with the boundary rows every stencil of a valid mesh fixes the
+       quadratic; the linear fit serves the pins without boundary rows */
+    if (P) return -1;
     if (lsq_qr(nr, d, A1, nv, B1) <= 0) return -1;
     for (int k = 0; k < nc; k++)
         for (int v = 0; v < nv; v++) coef[k * nv + v] = k < d ? B1[k * nv + v] : 0.0;
@@ -998,6 +1093,177 @@ int om_halfspace_state(int dim, double gamma, const double *WL, const double *WR
     return 0;
 }
 
+/* ------------------------------------------------------------------ */
+/* Full time-dependent gas-kinetic solution at a Gauss point (Sec. 2.2, */
+/* the 2nd-flux equation), for flows with discontinuities (Sec. 4):     */
+/*  f(t) = (1 - e) g^c + [(t + tau) e - tau] (a^c.u) g^c               */
+/*       + (t - tau + tau e) A^c g^c                                   */
+/*       + e g^l [1 - (tau + t) a^l.u - tau A^l] H(u)                  */
+/*       + e g^r [1 - (tau + t) a^r.u - tau A^r] (1 - H(u)),           */
+/* e = exp(-t / tau_n), u the normal velocity.  g^l, g^r are the        */
+/* Maxwellians of the left and right interface states, a^l, a^r their  */
+/* micro-slopes from the left and right gradients, A^l, A^r from their  */
+/* own compatibility conditions; g^c is the half-space combination W^c  */
+/* with the slopes of 1/2 (grad W^l + grad W^r), as on the smooth path. */
+/* tau = mu / p^c.  Reading of the numerical collision time, which the  */
+/* paper takes from other work: tau_n = tau + |p^l - p^r|/(p^l + p^r) dt.*/
+/* The time marching takes the flux as F0 + t Ft, the linear function   */
+/* with the same integrals over [0, dt/2] and [0, dt], and the          */
+/* interface state as W0 + t Wt through its values at dt/2 and dt.  For  */
+/* equal left and right states and gradients the solution is the smooth */
+/* one (Eq. 2nd-smooth-flux) exactly, whatever tau_n.                   */
+/* ------------------------------------------------------------------ */
+typedef struct {
+    double g[NVMAX], a[NVMAX], A[NVMAX]; /* rho <w psi>, rho <w psi a.u>, rho <w psi A> */
+} kin_terms;
+
+/* micro-slopes a^(j) (axis j of the local frame) of the Maxwellian with
+   moments M and density rho from the gradient dW [dim][nv], and A from the
+   compatibility condition <(a.u + A) psi> = 0, both over the whole
+   velocity space */
+static void slopes_and_A(const moments *M, int dim, double rho, const double *dW, double a[3][NVMAX], double *A) {
+    int nv = dim + 2;
+    double b[NVMAX];
+    for (int j = 0; j < dim; j++) {
+        for (int v = 0; v < nv; v++) b[v] = dW[j * nv + v] / rho;
+        micro_slope(M, dim, b, a[j]);
+    }
+    poly au, tmp, t2;
+    p_zero(&au);
+    for (int j = 0; j < dim; j++) {
+        p_combo(&tmp, a[j], dim);
+        p_mulvar(&tmp, j, &t2);
+        p_add(&au, &t2);
+    }
+    for (int p = 0; p < nv; p++) {
+        poly ps, z;
+        p_psi(&ps, p, dim);
+        p_mul(&ps, &au, &z);
+        b[p] = -p_expect(&z, M);
+    }
+    micro_slope(M, dim, b, A);
+}
+
+/* rho <w psi>, rho <w psi (a.u)>, rho <w psi A> under the moments M, with
+   the weight w = 1 (ku = 0) or the normal velocity u (ku = 1) */
+static void kinetic_terms(const moments *M, int dim, double rho, double a[3][NVMAX], const double *A, int ku,
+                          kin_terms *t) {
+    int nv = dim + 2;
+    poly au, tmp, t2, PA;
+    p_zero(&au);
+    for (int j = 0; j < dim; j++) {
+        p_combo(&tmp, a[j], dim);
+        p_mulvar(&tmp, j, &t2);
+        p_add(&au, &t2);
+    }
+    p_combo(&PA, A, dim);
+    for (int p = 0; p < nv; p++) {
+        poly ps, w, z;
+        p_psi(&ps, p, dim);
+        if (ku) p_mulvar(&ps, 0, &w);
+        else w = ps;
+        t->g[p] = rho * p_expect(&w, M);
+        p_mul(&w, &au, &z);
+        t->a[p] = rho * p_expect(&z, M);
+        p_mul(&w, &PA, &z);
+        t->A[p] = rho * p_expect(&z, M);
+    }
+}
+
+/* the five time functions of the full solution -- 1 - e, (t + tau) e - tau,
+   t - tau + tau e, e, (tau + t) e -- at t = T (integral = 0) or integrated
+   over [0, T] (integral = 1) */
+static void full_time_weights(double T, double tau, double taun, int integral, double w[5]) {
+    double E = taun > 0 ? exp(-T / taun) : 0.0;
+    if (!integral) {
+        w[0] = 1.0 - E;
+        w[1] = (T + tau) * E - tau;
+        w[2] = T - tau + tau * E;
+        w[3] = E;
+        w[4] = (tau + T) * E;
+        return;
+    }
+    double omE = 1.0 - E;
+    w[0] = T - taun * omE;
+    w[1] = taun * taun * omE - taun * T * E + tau * taun * omE - tau * T;
+    w[2] = 0.5 * T * T - tau * T + tau * taun * omE;
+    w[3] = taun * omE;
+    w[4] = tau * taun * omE + taun * taun * omE - taun * T * E;
+}
+
+static void full_combine(const double w[5], double tau, int nv, const kin_terms *c, const kin_terms *l,
+                         const kin_terms *r, double *out) {
+    for (int p = 0; p < nv; p++)
+        out[p] = w[0] * c->g[p] + w[1] * c->a[p] + w[2] * c->A[p] +
+                 w[3] * (l->g[p] + r->g[p] - tau * (l->A[p] + r->A[p])) - w[4] * (l->a[p] + r->a[p]);
+}
+
+/* Local frame (axis 0 = face normal, from left to right).  In: left and
+   right states and gradients [dim][nv] (local axes), the time step dt.
+   Out: F0, Ft (flux and its time slope of the linear fit), W0, Wt
+   (interface state and its time slope).  Returns -1 for a non-physical
+   state. */
+int om_gks_flux_full(int dim, double gamma, double mu, double Pr, double dt, const double *WL, const double *dWL,
+                     const double *WR, const double *dWR, double *F0, double *Ft, double *W0, double *Wt) {
+    int nv = dim + 2;
+    double K = internal_dof(dim, gamma);
+    double Wc[NVMAX], dWc[DMAX * NVMAX];
+    if (om_halfspace_state(dim, gamma, WL, WR, Wc)) return -1;
+    for (int k = 0; k < dim * nv; k++) dWc[k] = 0.5 * (dWL[k] + dWR[k]);
+    prim qc = to_prim(Wc, dim, gamma), ql = to_prim(WL, dim, gamma), qr = to_prim(WR, dim, gamma);
+    if (!(qc.rho > 0) || !(qc.p > 0)) return -1;
+    moments Mc, Ml, Mr, Hl, Hr;
+    make_moments(&qc, K, &Mc);
+    make_moments(&ql, K, &Ml);
+    make_moments(&qr, K, &Mr);
+    Hl = Ml;
+    half_moments(ql.U[0], ql.lam, +1, Hl.u);
+    Hr = Mr;
+    half_moments(qr.U[0], qr.lam, -1, Hr.u);
+    double ac[3][NVMAX], al[3][NVMAX], ar[3][NVMAX], Ac[NVMAX], Al[NVMAX], Ar[NVMAX];
+    slopes_and_A(&Mc, dim, qc.rho, dWc, ac, Ac);
+    slopes_and_A(&Ml, dim, ql.rho, dWL, al, Al);
+    slopes_and_A(&Mr, dim, qr.rho, dWR, ar, Ar);
+    double tau = mu / qc.p;
+    double taun = tau + fabs(ql.p - qr.p) / (ql.p + qr.p) * dt;
+    kin_terms fc, fl, fr, wc, wl, wr;
+    kinetic_terms(&Mc, dim, qc.rho, ac, Ac, 1, &fc);
+    kinetic_terms(&Hl, dim, ql.rho, al, Al, 1, &fl);
+    kinetic_terms(&Hr, dim, qr.rho, ar, Ar, 1, &fr);
+    kinetic_terms(&Mc, dim, qc.rho, ac, Ac, 0, &wc);
+    kinetic_terms(&Hl, dim, ql.rho, al, Al, 0, &wl);
+    kinetic_terms(&Hr, dim, qr.rho, ar, Ar, 0, &wr);
+    double w[5], I1[NVMAX], I2[NVMAX], V1[NVMAX], V2[NVMAX];
+    full_time_weights(dt, tau, taun, 1, w);
+    full_combine(w, tau, nv, &fc, &fl, &fr, I1);
+    full_time_weights(0.5 * dt, tau, taun, 1, w);
+    full_combine(w, tau, nv, &fc, &fl, &fr, I2);
+    full_time_weights(dt, tau, taun, 0, w);
+    full_combine(w, tau, nv, &wc, &wl, &wr, V1);
+    full_time_weights(0.5 * dt, tau, taun, 0, w);
+    full_combine(w, tau, nv, &wc, &wl, &wr, V2);
+    for (int p = 0; p < nv; p++) {
+        F0[p] = (4.0 * I2[p] - I1[p]) / dt;
+        Ft[p] = 4.0 * (I1[p] - 2.0 * I2[p]) / (dt * dt);
+        W0[p] = 2.0 * V2[p] - V1[p];
+        Wt[p] = 2.0 * (V1[p] - V2[p]) / dt;
+    }
+    if (Pr != 1.0 && mu != 0.0) {
+        /* as on the smooth path: q_n = -mu cp dT/dn from W^c, grad W^c */
+        const double *dn = dWc;
+        double ke_d = 0, ke = 0;
+        for (int a2 = 0; a2 < dim; a2++) {
+            ke_d += qc.U[a2] * dn[1 + a2];
+            ke += qc.U[a2] * qc.U[a2];
+        }
+        double pn = (gamma - 1.0) * (dn[nv - 1] - ke_d + 0.5 * ke * dn[0]);
+        double Tn = (pn * qc.rho - qc.p * dn[0]) / (qc.rho * qc.rho);
+        double qn = -mu * gamma / (gamma - 1.0) * Tn;
+        F0[nv - 1] += (1.0 / Pr - 1.0) * qn;
+    }
+    return 0;
+}
+
 /* First-order kinetic flux vector splitting flux in the local frame:
    F = rho_L <u psi>_{u>0,L} + rho_R <u psi>_{u<0,R}. */
 int om_kfvs(int dim, double gamma, const double *UL, const double *UR, double *F) {
@@ -1141,7 +1407,7 @@ typedef struct {
     int status;
 } ho_sums;
 
-static int ho_pass(const om_mesh *m, const om_params *P, const double *W, const double *dW, ho_sums *o) {
+static int ho_pass(const om_mesh *m, const om_params *P, const double *W, const double *dW, double dt, ho_sums *o) {
     int d = m->dim, nv = m->nv, nc = m->ncoef;
     long N = m->n_cell;
     memset(o->F0s, 0, sizeof(double) * nv * N);
@@ -1225,7 +1491,15 @@ static int ho_pass(const om_mesh *m, const om_params *P, const double *W, const 
                 for (int k = 0; k < d * nv; k++) dWc[k] = 0.5 * (dWL[k] + dWR[k]);
             }
             double F0l[NVMAX], Ftl[NVMAX], Wtl[NVMAX];
-            if (om_gks_flux(d, P->gamma, P->mu, P->Pr, Wc, dWc, F0l, Ftl, Wtl)) { o->status = -1; free(coef); return -1; }
+            if (P->flux_kind == 1 && !wall) {
+                /* full solution: the interface state of the Gauss-Green sums is
+                   its time fit W0 in place of W^c */
+                if (om_gks_flux_full(d, P->gamma, P->mu, P->Pr, dt, WL, dWL, WR, dWR, F0l, Ftl, Wc, Wtl)) {
+                    o->status = -1; free(coef); return -1;
+                }
+            } else if (om_gks_flux(d, P->gamma, P->mu, P->Pr, Wc, dWc, F0l, Ftl, Wtl)) {
+                o->status = -1; free(coef); return -1;
+            }
             if (wall) {
                 F0l[0] = 0.0;
                 Ftl[0] = 0.0;
@@ -1349,7 +1623,7 @@ int om_stage(om_ctx *c, int stage, double *W, double *dW) {
         vcopy(c->Wn, W, (int)(nv * N));
     }
     double dt = c->dt;
-    int st = ho_pass(m, P, W, dW, &c->hs);
+    int st = ho_pass(m, P, W, dW, dt, &c->hs);
     if (st) return st;
     if (stage == 0) for (int a = 0; a < 3; a++) c->force[a] = c->hs.force[a];
     for (long i = 0; i < N; i++) {
@@ -1401,7 +1675,7 @@ int om_residual_high(om_ctx *c, const double *W, const double *dW, double *R1) {
     const om_mesh *m = c->m;
     long N = m->n_cell;
     int nv = m->nv;
-    int st = ho_pass(m, &c->P, W, dW, &c->hs);
+    int st = ho_pass(m, &c->P, W, dW, c->dt, &c->hs);
     if (st) return st;
     for (long i = 0; i < N; i++)
         for (int v = 0; v < nv; v++) R1[v * N + i] = -(c->hs.F0s[v * N + i] + 0.5 * c->dt * c->hs.Fts[v * N + i]);
@@ -1413,7 +1687,7 @@ int om_ho_sums(om_ctx *c, const double *W, const double *dW, double *F0s, double
     const om_mesh *m = c->m;
     long N = m->n_cell;
     int nv = m->nv, d = m->dim;
-    int st = ho_pass(m, &c->P, W, dW, &c->hs);
+    int st = ho_pass(m, &c->P, W, dW, c->dt, &c->hs);
     if (st) return st;
     vcopy(F0s, c->hs.F0s, (int)(nv * N));
     vcopy(Fts, c->hs.Fts, (int)(nv * N));
