@@ -67,6 +67,7 @@ enum {
 
 enum { CGKS_S2O4 = 0, CGKS_S1O2 = 1 };
 enum { CGKS_LOW_KFVS = 0, CGKS_LOW_LF = 1 };
+enum { CGKS_FLUX_SMOOTH = 0, CGKS_FLUX_FULL = 1 };
 enum { CGKS_FP64 = 0, CGKS_MIXED32 = 1, CGKS_MIXED32_R64 = 2 };
 enum { CGKS_RESIDUAL_HIGH = 0, CGKS_RESIDUAL_LOW = 1, CGKS_RESIDUAL_NORM = 2 };
 
@@ -138,6 +139,21 @@ typedef struct {
                                        the two): CGKS_LOW_KFVS (0, the paper's default) or CGKS_LOW_LF,
                                        1/2 (F_n(U_L) + F_n(U_R)) - 1/2 lam_f (U_R - U_L) with the face's
                                        spectral radius lam_f of the implicit operator; per case */
+    int32_t flux_kind;              /* high-order flux (Sec. 2.2): CGKS_FLUX_SMOOTH (0), the simplified
+                                       solution for smooth flow (Eq. 2nd-smooth-flux), or CGKS_FLUX_FULL,
+                                       the full time-dependent solution (Eq. 2nd-flux) that Sec. 4 uses for
+                                       transonic and supersonic flow: an exp(-t/tau_n) blend of the
+                                       equilibrium part and the left/right free-transport parts with
+                                       tau_n = tau + |p_l - p_r| / (p_l + p_r) dt; the time marching takes
+                                       its flux and interface state as linear fits in t over [0, dt/2] and
+                                       [0, dt].  Equal left and right data give the smooth solution. */
+    double weno_eps;                /* 0: linear reconstruction weights (smooth flow, Sec. 4); > 0:
+                                       nonlinear WENO-type weights with this epsilon (the paper uses 1e-2
+                                       and 1e-6): candidates are the quadratic fit and one linear fit per
+                                       face neighbour (its average and gradient), weights proportional to
+                                       gamma_k / (eps + beta_k)^2 with gamma_0 = 0.95 */
+    double area_ref;                /* reference area of the drag coefficient (Sec. 4: the sphere's
+                                       pi D^2 / 4, the cylinder's D per unit span); 0: none */
 } cgks_params;
 
 typedef struct cgks_mesh cgks_mesh;

@@ -22,6 +22,7 @@ _lib = None
 OK, EINVAL, ENOMEM, EDEVICE, EMESH, ENONPHYS, EDIVERGED, ENOTCONV, EUNSUPPORTED = range(9)
 S2O4, S1O2 = 0, 1
 LOW_KFVS, LOW_LF = 0, 1
+FLUX_SMOOTH, FLUX_FULL = 0, 1
 FP64, MIXED32, MIXED32_R64 = 0, 1, 2
 RESIDUAL_HIGH, RESIDUAL_LOW, RESIDUAL_NORM = 0, 1, 2
 
@@ -62,7 +63,8 @@ class _Params(C.Structure):
     _fields_ = [("gamma", C.c_double), ("mu", C.c_double), ("Pr", C.c_double), ("T_wall", C.c_double),
                 ("W_inf", C.c_double * 5), ("cfl_high", C.c_double), ("cfl_low", C.c_double),
                 ("n_implicit", C.c_int32), ("n_sweeps", C.c_int32), ("time_scheme", C.c_int32),
-                ("explicit_only", C.c_int32), ("dt_fixed", C.c_double), ("low_flux", C.c_int32)]
+                ("explicit_only", C.c_int32), ("dt_fixed", C.c_double), ("low_flux", C.c_int32),
+                ("flux_kind", C.c_int32), ("weno_eps", C.c_double), ("area_ref", C.c_double)]
 
 
 class _SolveOpts(C.Structure):
@@ -187,6 +189,9 @@ class Params:
     explicit_only: int = 0
     dt_fixed: float = 0.0
     low_flux: int = LOW_KFVS
+    flux_kind: int = FLUX_SMOOTH
+    weno_eps: float = 0.0
+    area_ref: float = 0.0
 
     def c(self):
         p = _Params()
@@ -198,6 +203,7 @@ class Params:
         p.n_implicit, p.n_sweeps = self.n_implicit, self.n_sweeps
         p.time_scheme, p.explicit_only, p.dt_fixed = self.time_scheme, self.explicit_only, self.dt_fixed
         p.low_flux = self.low_flux
+        p.flux_kind, p.weno_eps, p.area_ref = self.flux_kind, self.weno_eps, self.area_ref
         return p
 
 

@@ -108,6 +108,7 @@ struct cgks_batch {
     // reduction blocks
     std::vector<int32_t> rb_start, rb_count, rb_case, case_rb_off;
     int n_implicit = 6, n_sweeps = 2, scheme = 0, explicit_only = 0;
+    bool any_full = false, any_weno = false;   // some live case uses the full solution / nonlinear weights
     // arena
     size_t bytes = 0;
     char *base = nullptr;
@@ -248,6 +249,8 @@ DevParams dev_params(const cgks_params &p, int dim) {
     q.scheme = p.time_scheme;
     q.explicit_only = p.explicit_only;
     q.low_flux = p.low_flux;
+    q.flux_full = p.flux_kind == CGKS_FLUX_FULL;
+    q.weno_eps = p.weno_eps;
     q.active = 1;
     return q;
 }
@@ -325,15 +328,27 @@ template <class F> void timed(cgks_batch *b, int kind, hipStream_t s, F &&launch
         if ((x) != hipSuccess) return CGKS_EDEVICE;     \
     } while (0)
 
+// the reconstruction and flux kernels in the variant the batch's cases
+// need: nonlinear weights and the full gas-kinetic solution are compiled
+// into separate instances, so batches without them run the plain kernels
+template <int D, typename R> void launch_recon(const cgks_batch *b, const Dev &d, hipStream_t s) {
+    const dim3 grid(unsigned((b->hwC + kReconBlock - 1) / kReconBlock));
+    if (b->any_weno) hipLaunchKernelGGL((k_recon<D, R, true>), grid, dim3(kReconBlock), 0, s, d);
+    else hipLaunchKernelGGL((k_recon<D, R, false>), grid, dim3(kReconBlock), 0, s, d);
+}
+template <int D, typename R> void launch_flux(const cgks_batch *b, const Dev &d, int blk, int want_grad, hipStream_t s) {
+    const dim3 grid(nblk(b->hwF * Dim<D>::lanes, blk));
+    if (b->any_full) hipLaunchKernelGGL((k_flux<D, R, true>), grid, dim3(blk), 0, s, d, want_grad);
+    else hipLaunchKernelGGL((k_flux<D, R, false>), grid, dim3(blk), 0, s, d, want_grad);
+}
+
 template <int D, typename R> void launch_ho_kernels(cgks_batch *b, const Dev &d, int mode, hipStream_t s) {
     timed(b, CGKS_K_RECON, s, [&] {
         if (b->hwB > 0) hipLaunchKernelGGL(k_ghost<D>, dim3(nblk(b->hwB)), dim3(kBlock), 0, s, d);
-        hipLaunchKernelGGL((k_recon<D, R>), dim3(unsigned((b->hwC + kReconBlock - 1) / kReconBlock)),
-                           dim3(kReconBlock), 0, s, d);
+        launch_recon<D, R>(b, d, s);
     });
     timed(b, CGKS_K_FLUX, s, [&] {
-        hipLaunchKernelGGL((k_flux<D, R>), dim3(nblk(b->hwF * Dim<D>::lanes, b->blk_flux)), dim3(b->blk_flux), 0, s, d,
-                           (int)(mode == MODE_R1 ? 0 : mode == MODE_STAGE0 ? 2 : 1));
+        launch_flux<D, R>(b, d, b->blk_flux, (int)(mode == MODE_R1 ? 0 : mode == MODE_STAGE0 ? 2 : 1), s);
     });
     timed(b, CGKS_K_CELL, s, [&] {
         hipLaunchKernelGGL((k_cell<D, R>), dim3(nblk(b->hwC * Dim<D>::sl, b->blk_cell)), dim3(b->blk_cell), 0, s, d,
@@ -622,7 +637,8 @@ static bool params_ok(const cgks_batch *b, const cgks_params &p) {
     return p.n_implicit == b->n_implicit && p.n_sweeps == b->n_sweeps && p.time_scheme == b->scheme &&
            p.explicit_only == b->explicit_only && p.n_implicit >= 0 && p.n_sweeps >= 0 &&
            (p.time_scheme == CGKS_S2O4 || p.time_scheme == CGKS_S1O2) && p.gamma > 1.0 && p.mu >= 0 && p.Pr > 0 &&
-           p.T_wall > 0 && p.cfl_high > 0 && p.cfl_low > 0 && (p.low_flux == CGKS_LOW_KFVS || p.low_flux == CGKS_LOW_LF);
+           p.T_wall > 0 && p.cfl_high > 0 && p.cfl_low > 0 && (p.low_flux == CGKS_LOW_KFVS || p.low_flux == CGKS_LOW_LF) &&
+           (p.flux_kind == CGKS_FLUX_SMOOTH || p.flux_kind == CGKS_FLUX_FULL) && p.weno_eps >= 0 && p.area_ref >= 0;
 }
 
 static cgks_status new_pool(const cgks_pool_desc &q, cgks_batch **out) {
@@ -805,8 +821,13 @@ static cgks_status rebuild_tables(cgks_batch *b, hipStream_t s) {
     b->hwB = b->ab.high_water();
     b->dev.NB_real = int32_t(b->hwB);
     b->max_colour = 0;
+    b->any_full = b->any_weno = false;
     for (int c = 0; c < b->n_case; ++c)
-        if (b->live[c]) b->max_colour = std::max(b->max_colour, b->meshes[c]->hm.n_colour);
+        if (b->live[c]) {
+            b->max_colour = std::max(b->max_colour, b->meshes[c]->hm.n_colour);
+            b->any_full = b->any_full || b->params[c].flux_kind == CGKS_FLUX_FULL;
+            b->any_weno = b->any_weno || b->params[c].weno_eps > 0;
+        }
     b->cb_start.clear();
     b->cb_count.clear();
     b->colour_blk_off.assign(b->max_colour + 1, 0);
@@ -1276,11 +1297,8 @@ template <int D, typename R, typename S> static cgks_status autotune_t(cgks_batc
     };
     static const int blocks[3] = {256, 128, 64};
     if (b->hwB > 0) hipLaunchKernelGGL(k_ghost<D>, dim3(nblk(b->hwB)), dim3(kBlock), 0, s, d);
-    hipLaunchKernelGGL((k_recon<D, R>), dim3(unsigned((b->hwC + kReconBlock - 1) / kReconBlock)), dim3(kReconBlock),
-                       0, s, d);
-    b->blk_flux = pick(blocks, 3, [&](int blk) {
-        hipLaunchKernelGGL((k_flux<D, R>), dim3(nblk(b->hwF * Dim<D>::lanes, blk)), dim3(blk), 0, s, d, 1);
-    });
+    launch_recon<D, R>(b, d, s);
+    b->blk_flux = pick(blocks, 3, [&](int blk) { launch_flux<D, R>(b, d, blk, 1, s); });
     b->blk_cell = pick(blocks, 3, [&](int blk) {
         hipLaunchKernelGGL((k_cell<D, R>), dim3(nblk(b->hwC * Dim<D>::sl, blk)), dim3(blk), 0, s, d, (int)MODE_R1);
     });

@@ -31,6 +31,9 @@ struct DevParams {
     double K;          // internal degrees of freedom of the gas
     int32_t explicit_only;
     int32_t low_flux;  // 0 KFVS, 1 Lax-Friedrichs (low-order level)
+    int32_t flux_full; // 1: full time-dependent gas-kinetic solution (discontinuities)
+    int32_t pad_;
+    double weno_eps;   // > 0: nonlinear reconstruction weights with this epsilon
 };
 static_assert(offsetof(DevParams, active) == 8, "gamma and active in the first 16 bytes");
 
@@ -451,6 +454,317 @@ template <int D, typename R> __device__ __forceinline__ bool half_side(const R *
     return true;
 }
 
+// ---------------------------------------------------------------------
+// Full time-dependent gas-kinetic solution (the 2nd-flux equation of
+// Sec. 2.2, for flows with discontinuities):
+//   f(t) = (1 - e) g^c + [(t + tau) e - tau] (a^c.u) g^c + (t - tau + tau e) A^c g^c
+//        + e g^l [1 - (tau + t) a^l.u - tau A^l] H(u) + e g^r [...] (1 - H(u)),
+// e = exp(-t / tau_n), tau_n = tau + |p_l - p_r| / (p_l + p_r) dt.  The
+// equilibrium part reuses the central-moment algebra of gks_flux.  The
+// left and right parts need half-range moments in the normal velocity u,
+// where odd central moments no longer vanish, so their micro-slopes are
+// formed explicitly in the raw basis psi = (1, u, v, w, (|u|^2 + Z)/2)
+// (Z = xi^2) and every expectation is expanded over monomials
+// u^a v^b w^c Z^e: the normal part uses the half-range moments of u, the
+// tangential velocities and Z their full Gaussian moments.
+// ---------------------------------------------------------------------
+
+// monomials u^a v^b w^c Z^e of psi_p, with their coefficients
+template <int D> struct PsiTerms;
+template <> struct PsiTerms<3> {
+    static constexpr int n[5] = {1, 1, 1, 1, 4};
+    static constexpr int m[5][4][4] = {{{0, 0, 0, 0}}, {{1, 0, 0, 0}}, {{0, 1, 0, 0}}, {{0, 0, 1, 0}},
+                                       {{2, 0, 0, 0}, {0, 2, 0, 0}, {0, 0, 2, 0}, {0, 0, 0, 1}}};
+    static constexpr double k[5][4] = {{1.0}, {1.0}, {1.0}, {1.0}, {0.5, 0.5, 0.5, 0.5}};
+};
+template <> struct PsiTerms<2> {
+    static constexpr int n[4] = {1, 1, 1, 3};
+    static constexpr int m[4][4][4] = {{{0, 0, 0, 0}}, {{1, 0, 0, 0}}, {{0, 1, 0, 0}},
+                                       {{2, 0, 0, 0}, {0, 2, 0, 0}, {0, 0, 0, 1}}};
+    static constexpr double k[4][4] = {{1.0}, {1.0}, {1.0}, {0.5, 0.5, 0.5}};
+};
+
+// the central-moment coefficients (alpha_0, alpha, a_E) of a slope whose
+// central moments are gc, turned into raw psi coefficients
+template <int D, typename R>
+__device__ __forceinline__ void central_to_raw(const R *gc, const R *U, R u2h, R th, R N, R *raw) {
+    constexpr int S = D + 1;
+    const R it = R(1.0) / th;
+    const R aE = R(2.0) * gc[S] * it * it / N - gc[0] * it;
+    R a0 = gc[0] - aE * N * th * R(0.5), aU = 0;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        const R al = gc[1 + k] * it;
+        aU += al * U[k];
+        raw[1 + k] = al - aE * U[k];
+    }
+    raw[0] = a0 - aU + aE * u2h;
+    raw[S] = aE;
+}
+
+// One side (sgn = +1: u > 0, left; -1: u < 0, right) of the full
+// solution's free-transport part: accumulates rho <w psi>, rho <w psi a.u>
+// and rho <w psi A> over the half space for w = u (flux: Fg, Fa, FA) and
+// w = 1 (state: Wg, Wa, WA).  W, G: state and gradient [axis][v] in the
+// face frame.  Returns false for a non-physical state.
+template <int D, typename R>
+__device__ bool half_side_full(const R *W, const R G[D][D + 2], const DevParams &P, R sgn, R *Fg, R *Fa, R *FA,
+                               R *Wg, R *Wa, R *WA) {
+    constexpr int nv = D + 2, S = D + 1;
+    using PT = PsiTerms<D>;
+    Prim<D, R> q;
+    q.from(W, R(P.gamma));
+    if (!(q.rho > R(0.0)) || !(q.p > R(0.0))) return false;
+    const R N = R(P.K) + D, ir = R(1.0) / q.rho, th = q.p * ir;
+    const R c1 = R(2.0) / N, c2 = R(0.5) * th * (N + R(2.0));
+    R u2h = 0;
+#pragma unroll
+    for (int k = 0; k < D; ++k) u2h += q.U[k] * q.U[k];
+    u2h *= R(0.5);
+    // raw micro-slopes a^(j) of the three axes and A (compatibility over
+    // the whole velocity space, as on the smooth path)
+    R a[D][nv], bc[nv], A[nv];
+#pragma unroll
+    for (int v = 0; v < nv; ++v) bc[v] = R(0.0);
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+        R g[nv], gc[nv];
+#pragma unroll
+        for (int v = 0; v < nv; ++v) g[v] = G[j][v] * ir;
+        to_central<D, R>(g, q.U, u2h, gc);
+        central_to_raw<D, R>(gc, q.U, u2h, th, N, a[j]);
+        R rj[nv];
+#pragma unroll
+        for (int v = 0; v < nv; ++v) rj[v] = R(0.0);
+        rj[0] = gc[1 + j];
+        rj[1 + j] = c1 * gc[S];
+        rj[S] = c2 * gc[1 + j];
+#pragma unroll
+        for (int v = 0; v < nv; ++v) bc[v] -= q.U[j] * gc[v] + rj[v];
+    }
+    central_to_raw<D, R>(bc, q.U, u2h, th, N, A);
+    // moments: u over the half space, v, w over the whole line, Z
+    R Hu[7], Mv[6], Mw[6], MZ[3];
+    const R var = R(0.5) / q.lam;   // variance of each velocity component: 1 / (2 lam)
+    Hu[0] = R(0.5) * one_plus_erf<R>(sgn * sqrt(q.lam) * q.U[0]);
+    Hu[1] = q.U[0] * Hu[0] + sgn * R(0.5) * exp(-q.lam * q.U[0] * q.U[0]) * rsqrt(R(M_PI) * q.lam);
+#pragma unroll
+    for (int k = 0; k + 2 < 7; ++k) Hu[k + 2] = q.U[0] * Hu[k + 1] + R(k + 1) * var * Hu[k];
+    Mv[0] = R(1.0);
+    Mv[1] = D > 1 ? q.U[1] : R(0.0);
+#pragma unroll
+    for (int k = 0; k + 2 < 6; ++k) Mv[k + 2] = Mv[1] * Mv[k + 1] + R(k + 1) * var * Mv[k];
+    Mw[0] = R(1.0);
+    Mw[1] = D > 2 ? q.U[D - 1] : R(0.0);
+#pragma unroll
+    for (int k = 0; k + 2 < 6; ++k) Mw[k + 2] = Mw[1] * Mw[k + 1] + R(k + 1) * var * Mw[k];
+    MZ[0] = R(1.0);
+    MZ[1] = R(P.K) * var;
+    MZ[2] = R(P.K) * (R(P.K) + R(2.0)) * var * var;
+#define CGKS_EXP(ua, vb, wc, ze) (Hu[ua] * Mv[vb] * Mw[wc] * MZ[ze])
+#pragma unroll
+    for (int p = 0; p < nv; ++p) {
+        R eg[2] = {0, 0}, ea[2] = {0, 0}, eA[2] = {0, 0};   // [w = 1, w = u]
+#pragma unroll
+        for (int i1 = 0; i1 < PT::n[p]; ++i1) {
+            const int pa = PT::m[p][i1][0], pb = PT::m[p][i1][1], pc = PT::m[p][i1][2], pe = PT::m[p][i1][3];
+            const R k1 = R(PT::k[p][i1]);
+            eg[0] += k1 * CGKS_EXP(pa, pb, pc, pe);
+            eg[1] += k1 * CGKS_EXP(pa + 1, pb, pc, pe);
+#pragma unroll
+            for (int qq = 0; qq < nv; ++qq)
+#pragma unroll
+                for (int i2 = 0; i2 < PT::n[qq]; ++i2) {
+                    const int ua = pa + PT::m[qq][i2][0], vb = pb + PT::m[qq][i2][1];
+                    const int wc = pc + PT::m[qq][i2][2], ze = pe + PT::m[qq][i2][3];
+                    const R kk = k1 * R(PT::k[qq][i2]);
+                    // A psi_q
+                    eA[0] += A[qq] * kk * CGKS_EXP(ua, vb, wc, ze);
+                    eA[1] += A[qq] * kk * CGKS_EXP(ua + 1, vb, wc, ze);
+                    // sum_j a^(j)_q psi_q u_j
+                    R s0 = a[0][qq] * CGKS_EXP(ua + 1, vb, wc, ze);
+                    R s1 = a[0][qq] * CGKS_EXP(ua + 2, vb, wc, ze);
+                    if (D > 1) {
+                        s0 += a[1][qq] * CGKS_EXP(ua, vb + 1, wc, ze);
+                        s1 += a[1][qq] * CGKS_EXP(ua + 1, vb + 1, wc, ze);
+                    }
+                    if (D > 2) {
+                        s0 += a[D - 1][qq] * CGKS_EXP(ua, vb, wc + 1, ze);
+                        s1 += a[D - 1][qq] * CGKS_EXP(ua + 1, vb, wc + 1, ze);
+                    }
+                    ea[0] += kk * s0;
+                    ea[1] += kk * s1;
+                }
+        }
+        Wg[p] += q.rho * eg[0];
+        Fg[p] += q.rho * eg[1];
+        Wa[p] += q.rho * ea[0];
+        Fa[p] += q.rho * ea[1];
+        WA[p] += q.rho * eA[0];
+        FA[p] += q.rho * eA[1];
+    }
+#undef CGKS_EXP
+    return true;
+}
+
+// Equilibrium part of the full solution: rho <w psi>, rho <w psi a.u>,
+// rho <w psi A> of g^c for w = u (Fcg, Fca, FcA) and the state slope
+// rho <psi A> (WcA; rho <psi a.u> = -WcA by compatibility), from the same
+// central-moment algebra as gks_flux.  Returns false for a non-physical
+// interface state.
+template <int D, typename R>
+__device__ bool equilibrium_terms(const R *Wc, const R Gc[D][D + 2], const DevParams &P, R *Fcg, R *Fca, R *FcA,
+                                  R *WcA) {
+    constexpr int nv = D + 2, S = D + 1;
+    Prim<D, R> q;
+    q.from(Wc, R(P.gamma));
+    if (!(q.rho > R(0.0)) || !(q.p > R(0.0))) return false;
+    const R N = R(P.K) + D, ir = R(1.0) / q.rho, th = q.p * ir;
+    const R c1 = R(2.0) / N, c2 = R(0.5) * th * (N + R(2.0));
+    R u2h = 0;
+#pragma unroll
+    for (int k = 0; k < D; ++k) u2h += q.U[k] * q.U[k];
+    u2h *= R(0.5);
+    const R Un = q.U[0];
+    R bc[nv], tc[nv];
+#pragma unroll
+    for (int v = 0; v < nv; ++v) bc[v] = tc[v] = R(0.0);
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+        R g[nv], gc[nv];
+#pragma unroll
+        for (int v = 0; v < nv; ++v) g[v] = Gc[j][v] * ir;
+        to_central<D, R>(g, q.U, u2h, gc);
+        const R Uj = q.U[j];
+        R rj[nv], rn[nv], sj[nv];
+#pragma unroll
+        for (int v = 0; v < nv; ++v) rj[v] = rn[v] = sj[v] = R(0.0);
+        rj[0] = gc[1 + j];
+        rj[1 + j] = c1 * gc[S];
+        rj[S] = c2 * gc[1 + j];
+        rn[0] = gc[1];
+        rn[1] = c1 * gc[S];
+        rn[S] = c2 * gc[1];
+        if (j == 0) {
+            sj[0] = c1 * gc[S];
+            sj[S] = c2 * (R(2.0) * c1 * gc[S] - th * gc[0]);
+#pragma unroll
+            for (int k = 0; k < D; ++k) sj[1 + k] = th * gc[1 + k];
+            sj[1] += th * R(2.0) * gc[1];
+        } else {
+            sj[1] = th * gc[1 + j];
+            sj[1 + j] = th * gc[1];
+        }
+#pragma unroll
+        for (int v = 0; v < nv; ++v) {
+            bc[v] -= Uj * gc[v] + rj[v];
+            tc[v] += Un * Uj * gc[v] + Un * rj[v] + Uj * rn[v] + sj[v];
+        }
+    }
+    R ea[nv], eu[nv];
+#pragma unroll
+    for (int v = 0; v < nv; ++v) {
+        ea[v] = Un * bc[v];
+        eu[v] = R(0.0);
+    }
+    ea[0] += bc[1];
+    ea[1] += c1 * bc[S];
+    ea[S] += c2 * bc[1];
+    eu[0] = Un;
+    eu[1] = th;
+    eu[S] = R(0.5) * Un * N * th;
+    from_central<D, R>(eu, q.U, u2h, q.rho, Fcg);
+    from_central<D, R>(tc, q.U, u2h, q.rho, Fca);
+    from_central<D, R>(ea, q.U, u2h, q.rho, FcA);
+    from_central<D, R>(bc, q.U, u2h, q.rho, WcA);
+    return true;
+}
+
+// the five time functions of the full solution -- 1 - e, (t + tau) e - tau,
+// t - tau + tau e, e, (tau + t) e -- at t = T, or integrated over [0, T]
+template <typename R> __device__ __forceinline__ void full_time_weights(R T, R tau, R taun, bool integral, R *w) {
+    const R E = taun > R(0.0) ? exp(-T / taun) : R(0.0);
+    if (!integral) {
+        w[0] = R(1.0) - E;
+        w[1] = (T + tau) * E - tau;
+        w[2] = T - tau + tau * E;
+        w[3] = E;
+        w[4] = (tau + T) * E;
+        return;
+    }
+    const R omE = R(1.0) - E;
+    w[0] = T - taun * omE;
+    w[1] = taun * taun * omE - taun * T * E + tau * taun * omE - tau * T;
+    w[2] = R(0.5) * T * T - tau * T + tau * taun * omE;
+    w[3] = taun * omE;
+    w[4] = tau * taun * omE + taun * taun * omE - taun * T * E;
+}
+
+// Full solution at a Gauss point (face frame): flux F0 + t Ft with the
+// solution's integrals over [0, dt/2] and [0, dt], interface state W0 + t
+// Wt through its values at dt/2 and dt.  WL, GL, WR, GR: left and right
+// states and gradients; Wc, Gc: the half-space equilibrium state and the
+// mean gradient.  Returns false for a non-physical state.
+template <int D, typename R>
+__device__ bool gks_flux_full(const R *WL, const R GL[D][D + 2], const R *WR, const R GR[D][D + 2], const R *Wc,
+                              const R Gc[D][D + 2], const DevParams &P, R dt, R *F0, R *Ft, R *W0, R *Wt) {
+    constexpr int nv = D + 2;
+    R Fcg[nv], Fca[nv], FcA[nv], WcA[nv];
+    if (!equilibrium_terms<D, R>(Wc, Gc, P, Fcg, Fca, FcA, WcA)) return false;
+    R SFg[nv], SFa[nv], SFA[nv], SWg[nv], SWa[nv], SWA[nv];
+#pragma unroll
+    for (int v = 0; v < nv; ++v) SFg[v] = SFa[v] = SFA[v] = SWg[v] = SWa[v] = SWA[v] = R(0.0);
+    __builtin_amdgcn_sched_barrier(0);
+    bool ok = half_side_full<D, R>(WL, GL, P, R(1.0), SFg, SFa, SFA, SWg, SWa, SWA);
+    __builtin_amdgcn_sched_barrier(0);
+    ok = half_side_full<D, R>(WR, GR, P, -R(1.0), SFg, SFa, SFA, SWg, SWa, SWA) && ok;
+    if (!ok) return false;
+    Prim<D, R> qc, ql, qr;
+    qc.from(Wc, R(P.gamma));
+    ql.from(WL, R(P.gamma));
+    qr.from(WR, R(P.gamma));
+    const R tau = R(P.mu) / qc.p;
+    const R taun = tau + fabs(ql.p - qr.p) / (ql.p + qr.p) * dt;
+    R w[5];
+    R I1[nv], I2[nv], V1[nv], V2[nv];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const R T = (k & 1) ? R(0.5) * dt : dt;
+        const bool integral = k < 2;
+        full_time_weights<R>(T, tau, taun, integral, w);
+#pragma unroll
+        for (int v = 0; v < nv; ++v) {
+            const R out = integral
+                ? w[0] * Fcg[v] + w[1] * Fca[v] + w[2] * FcA[v] + w[3] * (SFg[v] - tau * SFA[v]) - w[4] * SFa[v]
+                : w[0] * Wc[v] - w[1] * WcA[v] + w[2] * WcA[v] + w[3] * (SWg[v] - tau * SWA[v]) - w[4] * SWa[v];
+            if (k == 0) I1[v] = out;
+            else if (k == 1) I2[v] = out;
+            else if (k == 2) V1[v] = out;
+            else V2[v] = out;
+        }
+    }
+    const R idt = R(1.0) / dt;
+#pragma unroll
+    for (int v = 0; v < nv; ++v) {
+        F0[v] = (R(4.0) * I2[v] - I1[v]) * idt;
+        Ft[v] = R(4.0) * (I1[v] - R(2.0) * I2[v]) * idt * idt;
+        W0[v] = R(2.0) * V2[v] - V1[v];
+        Wt[v] = R(2.0) * (V1[v] - V2[v]) * idt;
+    }
+    if (R(P.Pr) != R(1.0) && R(P.mu) != R(0.0)) {
+        R ke = 0, ked = 0;
+#pragma unroll
+        for (int k = 0; k < D; ++k) {
+            ke += qc.U[k] * qc.U[k];
+            ked += qc.U[k] * Gc[0][1 + k];
+        }
+        const R pn = (R(P.gamma) - R(1.0)) * (Gc[0][nv - 1] - ked + R(0.5) * ke * Gc[0][0]);
+        const R Tn = (pn * qc.rho - qc.p * Gc[0][0]) / (qc.rho * qc.rho);
+        F0[nv - 1] += (R(1.0) / R(P.Pr) - R(1.0)) * (-R(P.mu) * R(P.gamma) / (R(P.gamma) - R(1.0)) * Tn);
+    }
+    return true;
+}
+
 // characteristic far-field state (local frame, axis 0 outward)
 template <int D, typename R> __device__ void farfield_state(const R *Wl, const R *Wo, R gamma, R *Wb) {
     constexpr int nv = D + 2;
@@ -735,11 +1049,140 @@ template <int D> __global__ __launch_bounds__(kBlock) void k_ghost(Dev d) {
         for (int v = 0; v < nv; ++v) o[nv + a * nv + v] = Gg[a][v];
 }
 
+// Nonlinear (WENO-type) weights of the compact reconstruction, for flows
+// with discontinuities (Sec. 4 applies them with a small epsilon; their
+// form is taken from other work).  Candidates: the quadratic P0 just
+// fitted (coefficients c, [k][v]) and, for each face neighbour or ghost m,
+// the linear polynomial fitting m's average and h-scaled averaged gradient
+// in the least-squares sense, in closed form c_m = g + r (dW - r.g) /
+// (1 + |r|^2) with r the scaled centroid offset and g = h grad W_m.  Linear
+// weights 0.95 and 0.05 / M; indicators in xi = (x - x_i)/h:
+// beta = sum_a <(dP/dxi_a)^2> + sum_{a<=b} (d2P/dxi_a dxi_b)^2; weights
+// proportional to gamma / (eps + beta)^2; the result
+// omega_0/gamma_0 (P0 - sum gamma_m P_m) + sum omega_m P_m replaces c.
+constexpr double kWenoGamma0 = 0.95;
+template <int D, typename R>
+__device__ void weno_weights(const Dev &d, int i, int NC, const double *xc, double ih, double h, const double *own,
+                             const double *Wi, R eps, R *c) {
+    using T = Dim<D>;
+    using RC = Rec<D>;
+    constexpr int nv = T::nv, nq = T::nq;
+    // cell second moments in xi and the indicator of P0
+    R M[D][D];
+#pragma unroll
+    for (int q = 0; q < nq; ++q) M[qa<D>(q)][qb<D>(q)] = M[qb<D>(q)][qa<D>(q)] = R(own[q]);
+    R beta0[nv];
+#pragma unroll
+    for (int v = 0; v < nv; ++v) {
+        R H[D][D];
+#pragma unroll
+        for (int a = 0; a < D; ++a)
+#pragma unroll
+            for (int b = 0; b < D; ++b) H[a][b] = R(0.0);
+#pragma unroll
+        for (int q = 0; q < nq; ++q) {
+            const int a = qa<D>(q), b = qb<D>(q);
+            const R cq = c[(D + q) * nv + v];
+            if (a == b) H[a][a] += R(2.0) * cq;
+            else {
+                H[a][b] += cq;
+                H[b][a] += cq;
+            }
+        }
+        R bt = R(0.0);
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            const R ca = c[a * nv + v];
+            R quad = R(0.0);
+#pragma unroll
+            for (int b = 0; b < D; ++b)
+#pragma unroll
+                for (int b2 = 0; b2 < D; ++b2) quad += H[a][b] * H[a][b2] * M[b][b2];
+            bt += ca * ca + quad;
+#pragma unroll
+            for (int b = a; b < D; ++b) bt += H[a][b] * H[a][b];
+        }
+        beta0[v] = bt;
+    }
+    // the linear candidates, one per slot
+    R Sw[nv], Sc[D][nv], Sg[D][nv];
+#pragma unroll
+    for (int v = 0; v < nv; ++v) {
+        Sw[v] = R(0.0);
+#pragma unroll
+        for (int a = 0; a < D; ++a) Sc[a][v] = Sg[a][v] = R(0.0);
+    }
+    int M_cand = 0;
+#pragma unroll 1
+    for (int s = 0; s < T::ns; ++s) {
+        const int2 sl = d.slot[size_t(s) * NC + i];
+        const int code = sl.x;
+        if (code == 0) break;
+        const int f = slot_face(code);
+        const int nb = sl.y;
+        R r[D];
+        const double *gd;
+        if (nb >= 0) {
+            const double sg = code > 0 ? 1.0 : -1.0;
+            const double *gm = d.geo + size_t(nb) * RC::gr;
+#pragma unroll
+            for (int a = 0; a < D; ++a) r[a] = R((gm[a] + sg * d.shift[size_t(a) * d.NF + f] - xc[a]) * ih);
+            gd = d.st + size_t(nb) * RC::sr;
+        } else {
+            const int bs = d.bslot[f];
+#pragma unroll
+            for (int a = 0; a < D; ++a) r[a] = R(d.gavg[size_t(a) * d.NB + bs]);
+            gd = d.gdat + size_t(bs) * (nv + D * nv);
+        }
+        ++M_cand;
+        R rr = R(1.0);
+#pragma unroll
+        for (int a = 0; a < D; ++a) rr += r[a] * r[a];
+        const R irr = R(1.0) / rr;
+#pragma unroll
+        for (int v = 0; v < nv; ++v) {
+            R g[D], rg = R(0.0);
+#pragma unroll
+            for (int a = 0; a < D; ++a) {
+                g[a] = R(h * gd[nv + a * nv + v]);
+                rg += r[a] * g[a];
+            }
+            const R t = (R(gd[v] - Wi[v]) - rg) * irr;
+            R beta = R(0.0), cm[D];
+#pragma unroll
+            for (int a = 0; a < D; ++a) {
+                cm[a] = g[a] + r[a] * t;
+                beta += cm[a] * cm[a];
+            }
+            const R wk = R(1.0) / ((eps + beta) * (eps + beta));
+            Sw[v] += wk;
+#pragma unroll
+            for (int a = 0; a < D; ++a) {
+                Sc[a][v] += wk * cm[a];
+                Sg[a][v] += cm[a];
+            }
+        }
+    }
+    const R g0 = R(kWenoGamma0), gk = (R(1.0) - R(kWenoGamma0)) / R(M_cand);
+#pragma unroll
+    for (int v = 0; v < nv; ++v) {
+        const R w0 = g0 / ((eps + beta0[v]) * (eps + beta0[v]));
+        const R itot = R(1.0) / (w0 + gk * Sw[v]);
+        const R s0 = w0 * itot / g0;   // omega_0 / gamma_0
+#pragma unroll
+        for (int a = 0; a < D; ++a) c[a * nv + v] = s0 * (c[a * nv + v] - gk * Sg[a][v]) + gk * Sc[a][v] * itot;
+#pragma unroll
+        for (int q = 0; q < nq; ++q) c[(D + q) * nv + v] *= s0;
+    }
+}
+
 // One thread per cell, all conservative variables: c = Minv M^T b.  The
 // evaluation records of the block's cells are assembled in LDS and written
 // out as one contiguous, coalesced range.
 constexpr int kReconBlock = 64;
-template <int D, typename R> __global__ __launch_bounds__(kReconBlock) void k_recon(Dev d) {
+// WENO: the launch also serves cases with nonlinear weights (weno_eps > 0),
+// applied after the linear-weight fit; other cases are untouched by it.
+template <int D, typename R, bool WENO> __global__ __launch_bounds__(kReconBlock) void k_recon(Dev d) {
     using T = Dim<D>;
     constexpr int nv = T::nv, nk = T::nk, nq = T::nq;
     constexpr int ERP = Rec<D>::er + 1;   // padded LDS row
@@ -843,6 +1286,10 @@ template <int D, typename R> __global__ __launch_bounds__(kReconBlock) void k_re
         }
 #pragma unroll
         for (int v = 0; v < nv; ++v) e[RC::OC + k * nv + v] = c[v];
+    }
+    if constexpr (WENO) {
+        const double eps_d = d.prm[d.cell_case[i]].weno_eps;
+        if (eps_d > 0.0) weno_weights<D, R>(d, i, NC, xc, ih, h, own, Wi, R(eps_d), e + RC::OC);
     }
     }
     __syncthreads();
@@ -982,7 +1429,9 @@ template <int G, typename T> __device__ __forceinline__ T group_sum(T v) {
 // want_grad: 0 = flux sums only (the residual pass), 1 = with the
 // Gauss-Green sums (stage passes), 2 = also keep the wall faces' momentum
 // sums in wallf (stage 0)
-template <int D, typename R> __global__ __launch_bounds__(kBlock) void k_flux(Dev d, int want_grad) {
+// FULL: the launch also serves cases with the full time-dependent solution
+// (flux_full); smooth cases of such a launch take exactly the smooth path.
+template <int D, typename R, bool FULL> __global__ __launch_bounds__(kBlock) void k_flux(Dev d, int want_grad) {
     using T = Dim<D>;
     constexpr int nv = T::nv, G = T::lanes, FS = T::fs;
     const int t = xcd_block(blockIdx.x, gridDim.x) * int(blockDim.x) + threadIdx.x;
@@ -1010,6 +1459,9 @@ template <int D, typename R> __global__ __launch_bounds__(kBlock) void k_flux(De
     bool ok = true;
     const int bc = d.fbc[f] & 7;
     const bool planar = (d.fbc[f] & kFacePlanar) != 0;
+    const bool full = FULL && P.flux_full != 0;
+    bool did_full = false;
+    R F0f[nv], Ftf[nv], Wtf[nv];
     {
         // gradients summed in the global frame, rotated once
         R Gs[D][nv], WL[nv];
@@ -1021,6 +1473,14 @@ template <int D, typename R> __global__ __launch_bounds__(kBlock) void k_flux(De
             R Wg[nv];
             recon_eval<D, R>(d, cL, q, x, Wg, Gs);
             fr.to_local(Wg, WL);
+        }
+        // the left gradient alone, for the full solution
+        R GLg[FULL ? D : 1][nv];
+        if constexpr (FULL) {
+#pragma unroll
+            for (int a = 0; a < D; ++a)
+#pragma unroll
+                for (int v = 0; v < nv; ++v) GLg[a][v] = Gs[a][v];
         }
         if (cR >= 0 || bc != 2) {
             R WR[nv];
@@ -1079,6 +1539,46 @@ template <int D, typename R> __global__ __launch_bounds__(kBlock) void k_flux(De
 #pragma unroll
                     for (int v = 0; v < nv; ++v) Gc[a][v] *= R(0.5);
             }
+            if constexpr (FULL) {
+                if (full && ok) {
+                    // the two one-sided gradients in the face frame: the right
+                    // cell's reconstruction once more, the mirror of the left
+                    // one at a slip or adiabatic wall, zero at the far field
+                    R GL[D][nv], GR[D][nv];
+                    fr.grad_to_local(GLg, GL);
+                    if (cR >= 0) {
+                        R GRg[D][nv], xr[D], WRg[nv];
+#pragma unroll
+                        for (int a = 0; a < D; ++a)
+#pragma unroll
+                            for (int v = 0; v < nv; ++v) GRg[a][v] = R(0.0);
+#pragma unroll
+                        for (int a = 0; a < D; ++a) xr[a] = x[a] - R(d.shift[size_t(a) * d.NF + f]);
+                        recon_eval<D, R>(d, cR, q, xr, WRg, GRg);
+                        fr.grad_to_local(GRg, GR);
+                    } else if (bc == 1 || bc == 3) {
+                        const bool all_mom = bc == 3;
+#pragma unroll
+                        for (int a = 0; a < D; ++a)
+#pragma unroll
+                            for (int v = 0; v < nv; ++v) {
+                                const bool rev = all_mom ? (v >= 1 && v <= D) : (v == 1);
+                                GR[a][v] = (a == 0) != rev ? -GL[a][v] : GL[a][v];
+                            }
+                    } else {
+#pragma unroll
+                        for (int a = 0; a < D; ++a)
+#pragma unroll
+                            for (int v = 0; v < nv; ++v) GR[a][v] = R(0.0);
+                    }
+                    R W0[nv];
+                    ok = gks_flux_full<D, R>(WL, GL, WR, GR, Wc, Gc, P, R(d.dt[cs]), F0f, Ftf, W0, Wtf);
+                    did_full = true;
+                    // the Gauss-Green sums take the interface state's time fit
+#pragma unroll
+                    for (int v = 0; v < nv; ++v) Wc[v] = W0[v];
+                }
+            }
         } else {
             // no-slip isothermal wall: (p_L / T_w, 0, p_L), interior gradient
             Prim<D, R> pq;
@@ -1113,7 +1613,16 @@ template <int D, typename R> __global__ __launch_bounds__(kBlock) void k_flux(De
         }
     }
     R F0[nv], Ft[nv], Wt[nv];
-    if (ok) ok = gks_flux<D, R>(Wc, Gc, P, F0, Ft, Wt);
+    if (FULL && did_full) {
+#pragma unroll
+        for (int v = 0; v < nv; ++v) {
+            F0[v] = F0f[v];
+            Ft[v] = Ftf[v];
+            Wt[v] = Wtf[v];
+        }
+    } else if (ok) {
+        ok = gks_flux<D, R>(Wc, Gc, P, F0, Ft, Wt);
+    }
     flag_nonphysical(d.flag, !ok && gp_ok, cs);
     if (!ok) {
 #pragma unroll
