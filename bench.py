@@ -20,9 +20,13 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
-# MI355X vector FP64 / FP32 (published); MIXED32_R64 runs two FP32 flux
-# launches and one FP64 launch per cycle and is priced at the FP64 peak
-VALU_PEAK_TFLOPS = {"fp64": 78.6, "mixed32": 157.3, "mixed32_r64": 78.6}
+# MI355X vector peaks: FP64 78.6 TFLOP/s (256 CUs x 2.4 GHz x 64 FMA per
+# clock).  The published FP32 figure, 157.3, counts packed FP32 (two
+# operations per lane per instruction); this build compiles with packed
+# FP32 off, so an FP32 lane operation issues at the FP64 rate and the FP32
+# kernels are priced at 78.6 as well.
+VALU_PEAK_TFLOPS = {"fp64": 78.6, "mixed32": 78.6, "mixed32_r64": 78.6}
+FP32_PACKED_PEAK_TFLOPS = 157.3
 
 # Floating-point operations of the high-order flux kernel per Gauss point
 # (FMA = 2), from the VALU instruction counters of one launch on the
@@ -220,27 +224,22 @@ def converge_report(mesh, lm, kw, drop=1e-10, max_cycles=3000):
     return out
 
 
-def cpu_baseline(seconds_hint=30.0):
-    """The oracle as it stands, on a reduced hybrid sphere built the same way
-    (cubed sphere 6 x 14 x 14 surface quads x 20 layers), single thread."""
+def cpu_baseline(mesh, kw):
+    """The oracle as it stands (plain FP64 C, one host thread) timed on one
+    whole cycle of the benchmark mesh from the same uniform start."""
     import oracle
     import paper_2109_09965_amd.inputs as I
-    mesh = I.cubed_sphere_mesh(14, 20, 10, 5, r_far=15.0, ratio=1.08)
-    Ma, Re = 0.25, 100.0
-    Winf = I.free_stream(3, Ma)
-    s = oracle.Solver(oracle.Mesh(mesh), oracle.Params(W_inf=Winf, mu=Ma / Re, Pr=0.72))
-    W, dW = I.uniform_state(mesh, Winf)
-    n = 0
     t0 = time.perf_counter()
-    while True:
-        s.cycle(W, dW)
-        n += 1
-        if time.perf_counter() - t0 > seconds_hint / 3 or n >= 3:
-            break
+    om = oracle.Mesh(mesh)
+    t_prep = time.perf_counter() - t0
+    s = oracle.Solver(om, oracle.Params(**{k: v for k, v in kw.items() if k != "area_ref"}))
+    W, dW = I.uniform_state(mesh, kw["W_inf"])
+    t0 = time.perf_counter()
+    s.cycle(W, dW)
     t = time.perf_counter() - t0
-    return dict(value=mesh["n_cell"] * n / t, unit="cell-updates/s", cores=1, kind="oracle",
-                sample=f"{n} cycle(s) of the 6x14x14x20 cubed-sphere hybrid sphere ({mesh['n_cell']} cells), FP64, "
-                       f"1 thread, {t:.1f} s")
+    return dict(value=mesh["n_cell"] / t, unit="cell-updates/s", cores=1, kind="oracle",
+                sample=f"1 cycle of the benchmark mesh ({mesh['n_cell']} cells), FP64, 1 thread, {t:.1f} s "
+                       f"(oracle geometry and colouring {t_prep:.1f} s, not timed)")
 
 
 def run_batch(args):
@@ -255,7 +254,10 @@ def run_batch(args):
     meshes = [I.batch_case_mesh(c) for c in cases]
     winf = [I.free_stream(2, c["mach"], c["aoa"]) for c in cases]
     lms = [cg.Mesh(m) for m in meshes]
-    params = [cg.Params(W_inf=w) for w in winf]
+    # transonic cases (Ma > 0.4) with the full gas-kinetic solution and
+    # nonlinear weights, as the paper runs its transonic flows
+    params = [cg.Params(W_inf=w, flux_kind=cg.FLUX_FULL if c["transonic"] else cg.FLUX_SMOOTH,
+                        weno_eps=args.weno_eps if c["transonic"] else 0.0) for c, w in zip(cases, winf)]
     NC = sum(lm.n_cell for lm in lms)
     G = max(g for g in (1, 2, 4, 5) if args.steps % g == 0)
 
@@ -277,19 +279,19 @@ def run_batch(args):
             b.graph_launch(hist)
         torch.cuda.synchronize()
         t = time.perf_counter() - t0
-        res = hist.cpu().numpy()
+        res = hist.cpu().numpy().reshape(G, len(idx))
         del b
-        return t, bool(np.isfinite(res).all())
+        return t, int(np.isfinite(res[-1]).sum())
 
     out = {}
     for name, prec in (("fp64", cg.FP64), ("mixed32", cg.MIXED32)):
         t, ok = run(list(range(len(cases))), prec)
         out[name] = (NC * args.steps / t, ok)
-    t_one, ok_one = 0.0, True
+    t_one, ok_one = 0.0, 0
     for i in range(len(cases)):
         t, ok = run([i], cg.FP64)
         t_one += t
-        ok_one &= ok
+        ok_one += ok
     one = NC * args.steps / t_one
     sizes = sorted({lm.n_cell for lm in lms})
     line = dict(metric="cell-updates/s per p-MG cycle", value=out["fp64"][0], unit="cell-updates/s", n_gpus=1,
@@ -297,11 +299,14 @@ def run_batch(args):
                 higher_is_better=True, scaling="weak", vs_baseline=None, dtype="f64",
                 data="synthetic (seeded cylinder meshes and free streams, uniform start)",
                 config=dict(workload="batch of 64 inviscid cylinders (n_theta in {32,64,128,256}, n_r = n_theta/2, "
-                            "Ma ~ U[0.1,0.4], AoA ~ U[-5,5] deg), one launch per kernel for all cases, "
-                            f"graphs of {G} cycles", cases=len(cases), cells=NC, case_sizes=sizes),
+                            "Ma ~ U[0.1,0.6], AoA ~ U[-5,5] deg; Ma > 0.4 with the full gas-kinetic solution "
+                            f"and nonlinear weights, eps {args.weno_eps:g}), one launch per kernel for all cases, "
+                            f"graphs of {G} cycles", cases=len(cases), cells=NC, case_sizes=sizes,
+                            transonic_cases=sum(c["transonic"] for c in cases)),
                 mixed32_value=out["mixed32"][0], one_at_a_time_fp64_value=one,
                 batched_speedup_fp64=out["fp64"][0] / one, batched_speedup_mixed32=out["mixed32"][0] / one,
-                finite=dict(fp64=out["fp64"][1], mixed32=out["mixed32"][1], one_at_a_time=ok_one))
+                cases_finite_after_all_steps=dict(fp64=out["fp64"][1], mixed32=out["mixed32"][1],
+                                                  one_at_a_time=ok_one))
     print(json.dumps(line), flush=True)
 
 
@@ -337,8 +342,11 @@ def run_serve(args):
         for k, (spec, m, lm) in enumerate(zip(trace, meshes, lms)):
             w = I.free_stream(spec["dim"], spec["mach"], spec["aoa"])
             W, dW = I.uniform_state(m, w)
-            out.append(Request(rid=k, arrival=spec["arrival"], mesh=lm,
-                               params=cg.Params(W_inf=w, mu=spec["mach"] / spec["re"], Pr=0.72), W0=W, dW0=dW, tol=tol))
+            # transonic requests (Ma > 0.4) with the full gas-kinetic solution and nonlinear weights
+            tr = spec["mach"] > 0.4
+            p = cg.Params(W_inf=w, mu=spec["mach"] / spec["re"], Pr=0.72,
+                          flux_kind=cg.FLUX_FULL if tr else cg.FLUX_SMOOTH, weno_eps=1e-2 if tr else 0.0)
+            out.append(Request(rid=k, arrival=spec["arrival"], mesh=lm, params=p, W0=W, dW0=dW, tol=tol))
         return out
 
     free = torch.cuda.mem_get_info()[0]
@@ -382,8 +390,9 @@ def run_serve(args):
                 unit="cell-updates/s", n_gpus=1, steps=len(trace), warmup=0, ms_per_step=None,
                 higher_is_better=True, scaling="weak", vs_baseline=None,
                 dtype="f64" if prec == cg.FP64 else "f32+f64", data="synthetic (seeded request trace and meshes)",
-                config=dict(workload=f"serving trace: {len(trace)} requests at 20/s ({n2} viscous cylinders, "
-                                     f"{len(trace) - n2} hybrid cubed spheres), tol Res <= {tol:g}",
+                config=dict(workload=f"serving trace: {len(trace)} requests at 20/s ({n2} viscous cylinders "
+                                     f"n_theta 32..256, {len(trace) - n2} hybrid cubed spheres; Ma ~ U[0.1,0.5], "
+                                     f"Re ~ U[50,300]), tol Res <= {tol:g}, at most 4000 cycles",
                             precision=args.precision.upper(), budget_gb=budget / 1e9,
                             resident_cells={"2d": args.resident_2d, "3d": args.resident_3d}),
                 served=served, one_at_a_time_fp64=base)
@@ -405,6 +414,8 @@ def main():
     ap.add_argument("--resident-3d", type=int, default=500_000, help="serving: cells a 3-D pool runs at once")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed32", "mixed32_r64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true", help="FP64 only: skip the MIXED32 and MIXED32_R64 legs")
+    ap.add_argument("--weno-eps", type=float, default=1e-2, help="batch64: epsilon of the transonic cases' weights")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default launch shapes")
     ap.add_argument("--no-converge", action="store_true", help="skip the run to a 1e-10 residual drop")
     ap.add_argument("--order-tile", type=int, default=0,
@@ -440,7 +451,43 @@ def main():
 
     mesh, kw, desc = workload(args.workload)
     lm = cg.Mesh(mesh, order_tile=args.order_tile)
-    prec = {"fp64": cg.FP64, "mixed32": cg.MIXED32, "mixed32_r64": cg.MIXED32_R64}[args.precision]
+    main_prec = args.precision
+    out = measure(mesh, lm, kw, main_prec, args)
+    value = out.pop("value")
+    line = dict(metric="cell-updates/s per p-MG cycle", value=value, unit="cell-updates/s", n_gpus=1,
+                steps=args.steps, warmup=args.warmup, ms_per_step=out.pop("ms_per_step"),
+                higher_is_better=True, scaling="weak", vs_baseline=None,
+                dtype="f64" if main_prec == "fp64" else "f32+f64",
+                data="synthetic (seeded mesh generator, uniform free-stream start)",
+                config=dict(workload=desc, cells=lm.n_cell, faces=lm.n_face, gauss_points=lm.n_gp,
+                            colours=lm.n_colour, precision=main_prec.upper(), time_scheme="S2O4", implicit_steps=6,
+                            sweeps=2, launch_shapes=out.pop("launch_shapes"),
+                            order_tile=args.order_tile or cg.ORDER_TILE_DEFAULT))
+    line["roofline"] = out.pop("roofline")
+    line.update(out)
+    if main_prec == "fp64" and not args.no_mixed:
+        # the FP32 half of the metric on the same mesh, same launch procedure
+        for name in ("mixed32", "mixed32_r64"):
+            o = measure(mesh, lm, kw, name, args)
+            line[name] = dict(value=o["value"], unit="cell-updates/s", ms_per_step=o["ms_per_step"], dtype="f32+f64",
+                              roofline=o["roofline"], kernels=o["kernels"])
+    if args.workload == "sphere" and not args.no_converge:
+        line["convergence"] = converge_report(mesh, lm, kw)
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(mesh, kw)
+    print(json.dumps(line), flush=True)
+
+
+def measure(mesh, lm, kw, prec_name, args):
+    """Tune the launch shapes, run the warm-up cycles, time args.steps cycles
+    with HIP-event kernel timing on the launch stream, then time them again
+    without events, eagerly and as captured graphs; value from the faster of
+    the last two.  Returns the value, the kernel breakdown and the dominant
+    kernel's roofline."""
+    import torch
+    import paper_2109_09965_amd as cg
+    import paper_2109_09965_amd.inputs as I
+    prec = {"fp64": cg.FP64, "mixed32": cg.MIXED32, "mixed32_r64": cg.MIXED32_R64}[prec_name]
     b = cg.Batch([lm], [cg.Params(**kw)], precision=prec)
     W, dW = I.uniform_state(mesh, kw["W_inf"])
     b.upload(0, W, dW)
@@ -451,11 +498,9 @@ def main():
     torch.cuda.synchronize()
     b.timing(True)
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
     for _ in range(args.steps):
         b.cycle(res)
     torch.cuda.synchronize()
-    t = time.perf_counter() - t0
     kt = b.timing_read()
     b.timing(False)
     # the timed region above carries event records; time once more without
@@ -479,8 +524,7 @@ def main():
     t_graph = time.perf_counter() - t0
     res_graph = float(hist.cpu()[-1])
     t_clean = min(t_eager, t_graph)
-    NC, NF, NG, NB = lm.n_cell, lm.n_face, lm.n_gp, lm.info.n_boundary_face
-    d = mesh["dim"]
+    NC, NG = lm.n_cell, lm.n_gp
     value = NC * args.steps / t_clean
     # dominant kernel by total time; every kernel's achieved bandwidth
     dom = max(kt, key=lambda k: kt[k][0])
@@ -491,13 +535,15 @@ def main():
         if n and k in model:
             per_kernel_gbs[k] = model[k][0] / (ms / n * 1e-3) / 1e9
     avg_ms = kt[dom][0] / kt[dom][1]
-    traffic = PROFILED_TRAFFIC.get((dom, args.precision)) if kernels_sha256() == PROFILED_KERNELS_SHA256 else None
+    traffic = PROFILED_TRAFFIC.get((dom, prec_name)) if kernels_sha256() == PROFILED_KERNELS_SHA256 else None
     if dom == "flux":
-        flop = FLUX_FLOP_PER_GP[args.precision] * NG
+        flop = FLUX_FLOP_PER_GP[prec_name] * NG
         ach = flop / (avg_ms * 1e-3) / 1e12
-        peak = VALU_PEAK_TFLOPS[args.precision]
+        peak = VALU_PEAK_TFLOPS[prec_name]
         rf = dict(bound="alu", kernel=dom, achieved=ach, peak=peak, unit="TFLOP/s", frac=ach / peak,
                   traffic=traffic, flop_per_launch=flop, alg_bytes_per_launch=model[dom][0], avg_launch_ms=avg_ms)
+        if prec_name != "fp64":
+            rf["peak_packed_fp32"] = FP32_PACKED_PEAK_TFLOPS
     else:
         byt = model[dom][0]
         ach = byt / (avg_ms * 1e-3) / 1e9
@@ -506,21 +552,10 @@ def main():
     breakdown = {k: dict(ms_per_step=v[0] / args.steps, launches_per_step=v[1] / args.steps,
                          share=v[0] / tot_ms if tot_ms else 0.0, alg_gbs=per_kernel_gbs.get(k))
                  for k, v in kt.items()}
-    out = dict(metric="cell-updates/s per p-MG cycle", value=value, unit="cell-updates/s", n_gpus=1,
-               steps=args.steps, warmup=args.warmup, ms_per_step=1e3 * t_clean / args.steps,
-               higher_is_better=True, scaling="weak", vs_baseline=None,
-               dtype="f64" if prec == cg.FP64 else "f32+f64",
-               data="synthetic (seeded mesh generator, uniform free-stream start)",
-               config=dict(workload=desc, cells=NC, faces=NF, gauss_points=NG, colours=lm.n_colour,
-                           precision=args.precision.upper(), time_scheme="S2O4", implicit_steps=6, sweeps=2,
-                           launch_shapes=picks, order_tile=args.order_tile or cg.ORDER_TILE_DEFAULT),
-               roofline=rf, kernels=breakdown, res_last=float(res.cpu()[0]), res_after_graph=res_graph,
-               eager_ms_per_step=1e3 * t_eager / args.steps, graph_ms_per_step=1e3 * t_graph / args.steps)
-    if args.workload == "sphere" and not args.no_converge:
-        out["convergence"] = converge_report(mesh, lm, kw)
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline()
-    print(json.dumps(out), flush=True)
+    del b
+    return dict(value=value, ms_per_step=1e3 * t_clean / args.steps, launch_shapes=picks, roofline=rf,
+                kernels=breakdown, res_last=float(res.cpu()[0]), res_after_graph=res_graph,
+                eager_ms_per_step=1e3 * t_eager / args.steps, graph_ms_per_step=1e3 * t_graph / args.steps)
 
 
 if __name__ == "__main__":

@@ -636,23 +636,24 @@ def sphere_case_mesh():
     return cubed_sphere_mesh(28, 40, 20, 10, 0.5, 15.0, 1.08, first_spacing=0.05597)
 
 
-def serve_trace(n_requests=256, seed=9965, rate=20.0, frac_2d=0.7, mach=(0.1, 0.4), re_2d=(10.0, 40.0),
-                re_3d=(50.0, 200.0)):
+def serve_trace(n_requests=256, seed=9965, rate=20.0, frac_2d=0.7, mach=(0.1, 0.5), re_2d=(50.0, 300.0),
+                re_3d=(50.0, 300.0), n_theta_2d=(32, 64, 128, 256)):
     """Seeded steady-solve request trace: exponential inter-arrival times at
     `rate` per second; frac_2d of the requests are viscous cylinders built
-    like the batch cases with n_theta in {32, 64} (n_r = n_theta/2) and a
-    no-slip adiabatic wall, the rest hybrid cubed-sphere O-grids with n in {14..28} quads per cube edge
-    (about the 24x48 .. 48x96 surface quads of latitude-longitude grids) and
-    L in {16..40} layers (L/2 hex, L/4 prism, the rest tet), stretched to
-    r = 15.  Mach ~ U[mach]; Re ~ U[re_2d] / U[re_3d] on the diameter, kept
-    in the steady regime of each body (cylinder below about 47, sphere below
-    about 210)."""
+    like the batch cases (n_theta from n_theta_2d, n_r = n_theta/2) with a
+    no-slip adiabatic wall, the rest hybrid cubed-sphere O-grids with n in
+    {14..28} quads per cube edge (about the 24x48 .. 48x96 surface quads of
+    latitude-longitude grids) and L in {16..40} layers (L/2 hex, L/4 prism,
+    the rest tet), stretched to r = 15.  Mach ~ U[mach]; Re ~ U[re_2d] /
+    U[re_3d] on the diameter.  Above Re of about 47 (cylinder) and 210
+    (sphere) the physical flow sheds vortices, so some requests have no
+    steady state: a server caps their cycles and reports them apart."""
     rng = np.random.default_rng(seed)
     t = np.cumsum(rng.exponential(1.0 / rate, n_requests))
     out = []
     for k in range(n_requests):
         if rng.uniform() < frac_2d:
-            nt = int(rng.choice([32, 64]))
+            nt = int(rng.choice(list(n_theta_2d)))
             spec = dict(dim=2, n_theta=nt, n_r=nt // 2, re=float(rng.uniform(*re_2d)))
         else:
             n = int(rng.integers(14, 29))
@@ -681,16 +682,16 @@ def batch_case_mesh(case):
     return cylinder_mesh(case["n_theta"], nr, ratio=1.1 ** (32.0 / nr))
 
 
-def batch_cases(n_cases=64, seed=2109, mach=(0.1, 0.4)):
+def batch_cases(n_cases=64, seed=2109, mach=(0.1, 0.6)):
     """Seeded list of 2-D inviscid cylinder cases: n_theta in {32,64,128,256},
-    n_r = n_theta/2, Mach ~ U[mach], AoA ~ U[-5,5] deg.  The default Mach
-    range stops at the cylinder's critical Mach number (about 0.4): beyond
-    it supersonic pockets and shocks form, which the smooth-flow scheme with
-    linear reconstruction weights does not capture."""
+    n_r = n_theta/2, Mach ~ U[mach], AoA ~ U[-5,5] deg.  Above the
+    cylinder's critical Mach number (about 0.4) supersonic pockets and
+    shocks form: such cases are marked transonic (the paper runs them with
+    the full gas-kinetic solution and nonlinear reconstruction weights)."""
     rng = np.random.default_rng(seed)
     out = []
     for _ in range(n_cases):
         nt = int(rng.choice([32, 64, 128, 256]))
-        out.append(dict(n_theta=nt, n_r=nt // 2, mach=float(rng.uniform(*mach)),
-                        aoa=float(rng.uniform(-5.0, 5.0))))
+        m = float(rng.uniform(*mach))
+        out.append(dict(n_theta=nt, n_r=nt // 2, mach=m, aoa=float(rng.uniform(-5.0, 5.0)), transonic=m > 0.4))
     return out

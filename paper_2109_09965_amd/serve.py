@@ -269,16 +269,25 @@ class Server:
 
 
 def summarize(finished, work, makespan):
-    tts = np.array([r.done - r.arrival for r in finished])
-    wait = np.array([r.admitted - r.arrival for r in finished])
-    svc = np.array([r.done - r.admitted for r in finished])
+    """Aggregate throughput over all requests; p50/p99 time-to-steady,
+    queue wait and service time over the converged requests only (a
+    request that stalled, diverged, went non-physical or hit the cycle cap
+    has no time-to-steady); the other outcomes are counted beside them."""
+    conv = [r for r in finished if r.status == "converged"]
     status = {}
     for r in finished:
         status[r.status] = status.get(r.status, 0) + 1
-    return dict(requests=len(finished), makespan_s=makespan, cell_updates=int(work),
+
+    def pct(vals, q):
+        return float(np.percentile(vals, q)) if len(vals) else None
+    tts = np.array([r.done - r.arrival for r in conv])
+    wait = np.array([r.admitted - r.arrival for r in conv])
+    svc = np.array([r.done - r.admitted for r in conv])
+    return dict(requests=len(finished), converged=len(conv), not_converged=len(finished) - len(conv),
+                makespan_s=makespan, cell_updates=int(work),
                 fp64_finishing_cycles=int(sum(r.cycles_fp64 for r in finished)),
                 cell_updates_per_s=work / makespan if makespan > 0 else 0.0,
-                p50_time_to_steady_s=float(np.percentile(tts, 50)), p99_time_to_steady_s=float(np.percentile(tts, 99)),
-                p50_queue_wait_s=float(np.percentile(wait, 50)), p99_queue_wait_s=float(np.percentile(wait, 99)),
-                p50_service_s=float(np.percentile(svc, 50)), p99_service_s=float(np.percentile(svc, 99)),
+                p50_time_to_steady_s=pct(tts, 50), p99_time_to_steady_s=pct(tts, 99),
+                p50_queue_wait_s=pct(wait, 50), p99_queue_wait_s=pct(wait, 99),
+                p50_service_s=pct(svc, 50), p99_service_s=pct(svc, 99),
                 status=status)
