@@ -43,7 +43,8 @@ typedef enum {
     CGKS_ENOMEM = 2,      /* host allocation failed or device buffer too small */
     CGKS_EDEVICE = 3,     /* a HIP call failed */
     CGKS_EMESH = 4,       /* invalid mesh: non-positive volume, face shared by > 2 cells,
-                             unsupported face shape, stencil that fixes no linear fit */
+                             unmatched face, unsupported face shape, stencil that cannot fix the
+                             quadratic reconstruction, invalid colouring */
     CGKS_ENONPHYS = 5,    /* density or pressure <= 0 met during a cycle */
     CGKS_EDIVERGED = 6,   /* residual grew to 1e3 times its first value (the start-up rise of an
                              impulsive start stays well below that) */
@@ -62,7 +63,8 @@ enum {
     CGKS_BC_NOSLIP_ADIABATIC = 3,   /* no-slip adiabatic wall (Sec. 4 viscous cases): mirror state
                                        with every velocity component reversed; zero velocity and
                                        zero heat flux at the wall */
-    CGKS_BC_FARFIELD = 4            /* characteristic (Riemann invariant) far field */
+    CGKS_BC_FARFIELD = 4,           /* characteristic (Riemann invariant) far field */
+    CGKS_BC_PERIODIC = 5            /* cell-based meshes only: joined to its partner face (bface_pair) */
 };
 
 enum { CGKS_S2O4 = 0, CGKS_S1O2 = 1 };
@@ -72,22 +74,81 @@ enum { CGKS_FP64 = 0, CGKS_MIXED32 = 1, CGKS_MIXED32_R64 = 2 };
 enum { CGKS_RESIDUAL_HIGH = 0, CGKS_RESIDUAL_LOW = 1, CGKS_RESIDUAL_NORM = 2 };
 
 /*
- * Face-based mesh (Sec. 2.1: the boundary of a cell is a union of faces).
- * Linear elements: 2-D faces are straight edges (2 vertex ids), 3-D faces are
- * planar triangles (3 ids) or bilinear quadrilaterals (4 ids, cyclic).  The
- * vertex order makes the normal point out of face_owner (counter-clockwise
- * owner boundary in 2-D, right-hand rule in 3-D).  face_neigh = -1 marks a
- * boundary face, whose face_bc is one of the CGKS_BC_* tags.  face_shift
- * (may be NULL) holds, per face, the translation [dim] that carries the
- * neighbour next to the owner across a periodic seam (zero elsewhere).
- * order_tile sets the library cell order: the cells are put on a Morton
- * (Z-order) curve of their centroids and cut into tiles of order_tile
- * consecutive cells, each tile colour-major inside (0 = the library
- * default, CGKS_ORDER_TILE_DEFAULT; >= n_cell gives one tile, i.e. the
- * whole mesh colour-major).  Cells of one colour are independent, so the order changes
- * no result beyond the rounding of the residual norm's sum; tiles keep a
- * cell's neighbours close in memory and on one XCD.
- * All arrays are host memory, read during cgks_mesh_create only.
+ * Hybrid mesh, cell based (Sec. 2.1: linear elements; a cell's boundary is a
+ * union of N_f triangle or quadrilateral faces, edges in 2-D).  Cells are
+ * given by type and a CSR list of vertex ids in the local order below; the
+ * library builds the faces (shared faces matched by their vertex sets),
+ * orients each face outward from its owner, and tags the faces that no two
+ * cells share from the boundary-face list.  POLY cells (split-face cells,
+ * cells with collapsed vertices) list their faces explicitly: cell_vert
+ * holds the face count, then per face its vertex count (2 in 2-D, 3 or 4 in
+ * 3-D) and ids.
+ */
+enum {
+    CGKS_CELL_TRI = 1,    /* 2-D, vertices 0 1 2: edges 01 12 20 */
+    CGKS_CELL_QUAD = 2,   /* 2-D, vertices 0 1 2 3 in cyclic order: edges 01 12 23 30 */
+    CGKS_CELL_TET = 3,    /* faces 012 013 123 023 */
+    CGKS_CELL_PYR = 4,    /* base 0123 (cyclic), apex 4: faces 0123 014 124 234 304 */
+    CGKS_CELL_PRISM = 5,  /* triangles 012 and 345, edges 03 14 25: faces 012 345 0143 1254 2035 */
+    CGKS_CELL_HEX = 6,    /* quads 0123 and 4567 (cyclic), edges 04 15 26 37: faces 0123 4567 0154 1265
+                             2376 3047 */
+    CGKS_CELL_POLY = 7    /* explicit faces (see above) */
+};
+
+/*
+ * dim 2 or 3; xyz [n_vert][dim]; cell_type [n_cell], cell_vert_ptr
+ * [n_cell + 1], cell_vert: the cells.  n_bface boundary faces:
+ * bface_vert_ptr [n_bface + 1], bface_vert (vertex ids in any order),
+ * bface_tag [n_bface] (CGKS_BC_*).  A CGKS_BC_PERIODIC face b is joined to
+ * the face bface_pair[b] (which must be periodic and pair back to b) as one
+ * interior face; their centroid offset is the period.  bface_pair may be
+ * NULL without periodic faces.  colour [n_cell] (NULL: the library's
+ * largest-degree-first greedy colouring) sets the classes of the
+ * multicolour relaxation: ids 0..15, no two face neighbours alike
+ * (CGKS_EMESH otherwise); the sweeps visit them in id order.  order_tile:
+ * as in cgks_face_mesh_desc.  Every cell face must be shared by exactly
+ * one other cell or listed once as a boundary face (CGKS_EMESH otherwise).
+ * All arrays are host memory, read during the call only.
+ */
+typedef struct {
+    int dim;
+    int64_t n_vert;
+    const double *xyz;
+    int64_t n_cell;
+    const int32_t *cell_type;
+    const int64_t *cell_vert_ptr;
+    const int64_t *cell_vert;
+    int64_t n_bface;
+    const int64_t *bface_vert_ptr;
+    const int64_t *bface_vert;
+    const int32_t *bface_tag;
+    const int64_t *bface_pair;      /* [n_bface] or NULL */
+    const int32_t *colour;          /* [n_cell] or NULL */
+    int64_t order_tile;
+} cgks_mesh_desc;
+
+/*
+ * Face-based mesh (the second way in; the same mesh gives the same results
+ * bitwise either way).  2-D faces are straight edges (2 vertex ids), 3-D
+ * faces are planar triangles (3 ids) or bilinear quadrilaterals (4 ids,
+ * cyclic).  The vertex order makes the normal point out of face_owner
+ * (counter-clockwise owner boundary in 2-D, right-hand rule in 3-D).
+ * face_neigh = -1 marks a boundary face, whose face_bc is one of the
+ * CGKS_BC_* wall or far-field tags.  face_shift (may be NULL) holds, per
+ * face, the translation [dim] that carries the neighbour next to the owner
+ * across a periodic seam (zero elsewhere).  The library puts faces into a
+ * canonical form first (owner the smaller cell id, vertex cycle starting
+ * at its smallest id, faces sorted by owner, neighbour and vertices), so
+ * results depend on the mesh only, not on the order the faces are listed
+ * in.  colour: as in cgks_mesh_desc.  order_tile sets the library cell
+ * order: the cells are put on a Morton (Z-order) curve of their centroids
+ * and cut into tiles of order_tile consecutive cells, each tile
+ * colour-major inside (0 = the library default, CGKS_ORDER_TILE_DEFAULT;
+ * >= n_cell gives one tile, i.e. the whole mesh colour-major).  Cells of
+ * one colour are independent, so the order changes no result beyond the
+ * rounding of the residual norm's sum; tiles keep a cell's neighbours close
+ * in memory and on one XCD.  All arrays are host memory, read during the
+ * call only.
  */
 typedef struct {
     int dim;                        /* 2 or 3 */
@@ -101,15 +162,15 @@ typedef struct {
     const int64_t *face_neigh;      /* [n_face] in [0, n_cell) or -1 */
     const int32_t *face_bc;         /* [n_face] */
     const double *face_shift;       /* [n_face][dim] or NULL */
+    const int32_t *colour;          /* [n_cell] or NULL */
     int64_t order_tile;             /* cells per ordering tile; 0 = default; < 0 is CGKS_EINVAL */
-} cgks_mesh_desc;
+} cgks_face_mesh_desc;
 
 #define CGKS_ORDER_TILE_DEFAULT 4096
 
 typedef struct {
     int dim, n_colour;
     int64_t n_cell, n_face, n_gp, n_boundary_face;
-    int64_t n_linear_cells;         /* cells whose stencil only fixes a linear fit */
     int64_t n_planar_faces;         /* faces whose Gauss points share one normal (all 2-D edges and
                                        triangles; flat quads): their face records are shorter */
 } cgks_mesh_info;
@@ -159,24 +220,28 @@ typedef struct {
 typedef struct cgks_mesh cgks_mesh;
 typedef struct cgks_batch cgks_batch;
 
-/* Build faces' Gauss points (3 per triangle, 4 per quadrilateral with a
-   normal at each point, 2 per 2-D edge), cell volumes, centroids and second
-   moments, the reconstruction operators, the multicolour classes
-   (largest-degree-first greedy colouring, classes numbered by size) and the
-   library cell order
-   (tiles of order_tile cells along a Morton curve of the centroids,
-   colour-major inside each tile).
-   Host work only.  *out receives a handle (free with cgks_mesh_destroy).
-   Errors: CGKS_EINVAL (null/size), CGKS_EMESH, CGKS_ENOMEM. */
+/* Build the faces (cell-based form) and their Gauss points (3 per
+   triangle, 4 per quadrilateral with a normal at each point, 2 per 2-D
+   edge), cell volumes, centroids and second moments, the reconstruction
+   operators, the multicolour classes (the caller's, or largest-degree-first
+   greedy colouring with classes numbered by size) and the library cell
+   order (tiles of order_tile cells along a Morton curve of the centroids,
+   colour-major inside each tile).  Host work only.  *out receives a handle
+   (free with cgks_mesh_destroy).  Errors: CGKS_EINVAL (null/size/type),
+   CGKS_EMESH (face shared by more than two cells, cell face neither shared
+   nor listed as boundary, boundary face matching no cell face, bad
+   periodic pairing, non-positive volume, a reconstruction stencil that
+   cannot fix the quadratic, an invalid caller colouring), CGKS_ENOMEM. */
 cgks_status cgks_mesh_create(const cgks_mesh_desc *desc, cgks_mesh **out);
+/* The same from a face-based description. */
+cgks_status cgks_mesh_create_faces(const cgks_face_mesh_desc *desc, cgks_mesh **out);
 cgks_status cgks_mesh_query(const cgks_mesh *mesh, cgks_mesh_info *info);
 /* lib_to_caller[n_cell]: caller cell id of each library cell; colour[n_cell]
    (may be NULL): colour of each caller cell. Host arrays. */
 cgks_status cgks_mesh_permutation(const cgks_mesh *mesh, int64_t *lib_to_caller, int32_t *colour);
 /* Cell geometry in caller order (host arrays, any may be NULL): vol[n_cell],
-   centroid[n_cell][dim], h[n_cell] = 2 dim |V| / sum_f S_f, linear[n_cell]
-   (1 where the reconstruction stencil only fixes a linear fit). */
-cgks_status cgks_mesh_geometry(const cgks_mesh *mesh, double *vol, double *centroid, double *h, int32_t *linear);
+   centroid[n_cell][dim], h[n_cell] = 2 dim |V| / sum_f S_f. */
+cgks_status cgks_mesh_geometry(const cgks_mesh *mesh, double *vol, double *centroid, double *h);
 cgks_status cgks_mesh_destroy(cgks_mesh *mesh);
 
 /* A batch is n_case (mesh, params) pairs stepped together: every kernel
@@ -331,6 +396,7 @@ typedef struct {
     double res_first, res_last;
     cgks_status status;    /* CGKS_OK, CGKS_ENOTCONV, CGKS_ENONPHYS, CGKS_EDIVERGED */
     double force[3];       /* wall force at the start of the case's last cycle (see cgks_wall_force) */
+    double cd;             /* drag coefficient of that force (see cgks_wall_force; NaN without area_ref) */
 } cgks_solve_report;
 
 /* Cycle until every case meets its tolerance or max_cycles; report[n_case]
@@ -344,16 +410,18 @@ cgks_status cgks_solve(cgks_batch *batch, const cgks_solve_opts *opts, cgks_solv
 
 /* Force of the gas on the walls of each case (Sec. 4, sphere and cylinder
    drag): the sum over slip and no-slip boundary faces of the face-quadrature
-   sum of the momentum components of the smooth flux F0, that is pressure
+   sum of the momentum components of the flux at t = 0 (F0), that is pressure
    plus viscous stress, with the face normal pointing out of the fluid.  It
    is taken in the first high-order pass (stage 0) of every cycle, at the
    state the cycle starts from; a case frozen by cgks_solve keeps the force
-   of its last cycle.  force: host [n_case][3] (the z entry is 0 in 2-D),
-   written after the work queued on stream has finished.  The drag
-   coefficient is force . e_inf / (1/2 rho_inf |U_inf|^2 A_ref).  MIXED32
-   batches sum FP32 face sums (in FP64).  CGKS_EINVAL on a NULL argument or
-   an unbound batch. */
-cgks_status cgks_wall_force(cgks_batch *batch, double *force, void *stream);
+   of its last cycle.  force: host [n_case][3] (the z entry is 0 in 2-D);
+   cd (may be NULL): host [n_case], the drag coefficient
+   force . e_inf / (1/2 rho_inf |U_inf|^2 area_ref) with e_inf the
+   free-stream direction (Sec. 4 tables), NaN where area_ref is 0 or the
+   free stream is at rest.  Written after the work queued on stream has
+   finished.  MIXED32 batches sum FP32 face sums (in FP64).  CGKS_EINVAL on
+   a NULL force or an unbound batch. */
+cgks_status cgks_wall_force(cgks_batch *batch, double *force, double *cd, void *stream);
 
 /* Pick the launch shapes of this batch by measurement (the batching
    autotuner): threads per block of the face Gauss-point flux, the cell

@@ -50,6 +50,7 @@ def lib():
         L.om_mesh_create.argtypes = [i, l, dp, l, l, lp, lp, lp, lp, ip, dp]
         L.om_mesh_destroy.argtypes = [P]
         L.om_mesh_n_colour.argtypes = [P]
+        L.om_mesh_set_colour.argtypes = [P, ip]
         L.om_mesh_cells.argtypes = [P, dp, dp, dp, dp, ip]
         L.om_mesh_faces.argtypes = [P, ip, dp, dp, dp, dp, dp]
         L.om_recon_eval.argtypes = [P, P, dp, dp, l, lp, dp, dp, dp]
@@ -137,7 +138,9 @@ def _i64(a):
 class Mesh:
     """Oracle mesh: computes its own geometry, quadrature and colouring."""
 
-    def __init__(self, m: dict):
+    def __init__(self, m: dict, colour=None):
+        """colour: optional caller colouring of the relaxation sweeps
+        (replaces the oracle's own greedy colouring)."""
         L = lib()
         self.dim = int(m["dim"])
         self.nv = self.dim + 2
@@ -149,6 +152,10 @@ class Mesh:
         k = self._keep
         self.h = L.om_mesh_create(self.dim, len(k["xyz"]), k["xyz"], self.n_cell, self.n_face, k["ptr"], k["fv"],
                                   k["own"], k["nb"], k["bc"], k["sh"])
+        if colour is not None:
+            self._colour = np.ascontiguousarray(colour, np.int32)
+            if L.om_mesh_set_colour(self.h, self._colour):
+                raise ValueError("colouring: neighbours share a colour or an id is out of range")
         self.n_colour = L.om_mesh_n_colour(self.h)
 
     def __del__(self):

@@ -408,6 +408,22 @@ void om_mesh_destroy(om_mesh *m) {
 
 /* geometry export for the tests */
 int om_mesh_n_colour(const om_mesh *m) { return m->n_colour; }
+
+/* replace the colouring by a caller's (class ids 0..63; the classes must be
+   independent sets, which the relaxation's order relies on).  Returns -1
+   if two face neighbours share a colour or an id is out of range. */
+int om_mesh_set_colour(om_mesh *m, const int *colour) {
+    int ncol = 0;
+    for (long i = 0; i < m->n_cell; i++) {
+        if (colour[i] < 0 || colour[i] >= 64) return -1;
+        if (colour[i] + 1 > ncol) ncol = colour[i] + 1;
+    }
+    for (long f = 0; f < m->n_face; f++)
+        if (m->neigh[f] >= 0 && colour[m->owner[f]] == colour[m->neigh[f]]) return -1;
+    for (long i = 0; i < m->n_cell; i++) m->colour[i] = colour[i];
+    m->n_colour = ncol;
+    return 0;
+}
 void om_mesh_cells(const om_mesh *m, double *vol, double *ctr, double *sec, double *h, int *colour) {
     for (long i = 0; i < m->n_cell; i++) {
         vol[i] = m->vol[i];

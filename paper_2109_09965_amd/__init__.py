@@ -26,7 +26,7 @@ FLUX_SMOOTH, FLUX_FULL = 0, 1
 FP64, MIXED32, MIXED32_R64 = 0, 1, 2
 RESIDUAL_HIGH, RESIDUAL_LOW, RESIDUAL_NORM = 0, 1, 2
 
-EXPORTS = ["cgks_status_string", "cgks_mesh_create", "cgks_mesh_query", "cgks_mesh_permutation",
+EXPORTS = ["cgks_status_string", "cgks_mesh_create", "cgks_mesh_create_faces", "cgks_mesh_query", "cgks_mesh_permutation",
            "cgks_mesh_geometry", "cgks_mesh_destroy", "cgks_batch_create", "cgks_batch_query", "cgks_batch_bind", "cgks_batch_destroy",
            "cgks_state_upload", "cgks_state_download", "cgks_state_device", "cgks_highorder_stage",
            "cgks_residual", "cgks_lowlevel_smooth", "cgks_cycle", "cgks_solve", "cgks_timing_enable",
@@ -47,16 +47,25 @@ ORDER_TILE_DEFAULT = 4096   # CGKS_ORDER_TILE_DEFAULT of include/cgks.h
 
 
 class _Desc(C.Structure):
+    """cgks_mesh_desc: cell based."""
+    _fields_ = [("dim", C.c_int), ("n_vert", C.c_int64), ("xyz", C.c_void_p), ("n_cell", C.c_int64),
+                ("cell_type", C.c_void_p), ("cell_vert_ptr", C.c_void_p), ("cell_vert", C.c_void_p),
+                ("n_bface", C.c_int64), ("bface_vert_ptr", C.c_void_p), ("bface_vert", C.c_void_p),
+                ("bface_tag", C.c_void_p), ("bface_pair", C.c_void_p), ("colour", C.c_void_p),
+                ("order_tile", C.c_int64)]
+
+
+class _FaceDesc(C.Structure):
+    """cgks_face_mesh_desc: face based."""
     _fields_ = [("dim", C.c_int), ("n_vert", C.c_int64), ("xyz", C.c_void_p), ("n_cell", C.c_int64),
                 ("n_face", C.c_int64), ("face_vert_ptr", C.c_void_p), ("face_vert", C.c_void_p),
                 ("face_owner", C.c_void_p), ("face_neigh", C.c_void_p), ("face_bc", C.c_void_p),
-                ("face_shift", C.c_void_p), ("order_tile", C.c_int64)]
+                ("face_shift", C.c_void_p), ("colour", C.c_void_p), ("order_tile", C.c_int64)]
 
 
 class _Info(C.Structure):
     _fields_ = [("dim", C.c_int), ("n_colour", C.c_int), ("n_cell", C.c_int64), ("n_face", C.c_int64),
-                ("n_gp", C.c_int64), ("n_boundary_face", C.c_int64), ("n_linear_cells", C.c_int64),
-                ("n_planar_faces", C.c_int64)]
+                ("n_gp", C.c_int64), ("n_boundary_face", C.c_int64), ("n_planar_faces", C.c_int64)]
 
 
 class _Params(C.Structure):
@@ -81,7 +90,7 @@ class _PoolDesc(C.Structure):
 
 class _SolveReport(C.Structure):
     _fields_ = [("cycles", C.c_int32), ("converged", C.c_int32), ("res_first", C.c_double),
-                ("res_last", C.c_double), ("status", C.c_int), ("force", C.c_double * 3)]
+                ("res_last", C.c_double), ("status", C.c_int), ("force", C.c_double * 3), ("cd", C.c_double)]
 
 
 def lib():
@@ -104,9 +113,10 @@ def lib():
         L.cgks_status_string.restype = C.c_char_p
         L.cgks_status_string.argtypes = [C.c_int]
         L.cgks_mesh_create.argtypes = [C.POINTER(_Desc), C.POINTER(P)]
+        L.cgks_mesh_create_faces.argtypes = [C.POINTER(_FaceDesc), C.POINTER(P)]
         L.cgks_mesh_query.argtypes = [P, C.POINTER(_Info)]
         L.cgks_mesh_permutation.argtypes = [P, P, P]
-        L.cgks_mesh_geometry.argtypes = [P, P, P, P, P]
+        L.cgks_mesh_geometry.argtypes = [P, P, P, P]
         L.cgks_mesh_destroy.argtypes = [P]
         L.cgks_batch_create.argtypes = [P, P, i32, i32, C.POINTER(P)]
         L.cgks_batch_query.argtypes = [P, C.POINTER(C.c_size_t)]
@@ -125,7 +135,7 @@ def lib():
         L.cgks_graph_launch.argtypes = [P, P, P]
         L.cgks_graph_destroy.argtypes = [P]
         L.cgks_timing_read.argtypes = [P, P, P]
-        L.cgks_wall_force.argtypes = [P, P, P]
+        L.cgks_wall_force.argtypes = [P, P, P, P]
         L.cgks_pool_create.argtypes = [C.POINTER(_PoolDesc), C.POINTER(P)]
         L.cgks_batch_admit.argtypes = [P, P, P, C.POINTER(C.c_int32), P]
         L.cgks_batch_release.argtypes = [P, i32, P]
@@ -208,26 +218,47 @@ class Params:
 
 
 class Mesh:
-    """Host-side mesh handle (cgks_mesh_create) from a face-based mesh dict."""
+    """Host-side mesh handle.  A mesh dict with the cell-based keys
+    (cell_type, cell_vert_ptr, cell_vert, bface_*) goes through
+    cgks_mesh_create, which builds the faces in the library; faces=True, or
+    a dict with only the face-based keys, through cgks_mesh_create_faces."""
 
-    def __init__(self, m: dict, order_tile: int = 0):
+    def __init__(self, m: dict, order_tile: int = 0, colour=None, faces: bool = False):
         """order_tile: cells per tile of the library cell order (tiles cut
-        from a Morton curve of the cell centroids; 0 = library default)."""
+        from a Morton curve of the cell centroids; 0 = library default).
+        colour: optional caller colouring [n_cell] of the relaxation sweeps."""
         L = lib()
         self.dim = int(m["dim"])
         self.nv = self.dim + 2
-        keep = dict(xyz=np.ascontiguousarray(m["xyz"], np.float64),
-                    ptr=np.ascontiguousarray(m["face_vert_ptr"], np.int64),
-                    fv=np.ascontiguousarray(m["face_vert"], np.int64),
-                    own=np.ascontiguousarray(m["face_owner"], np.int64),
-                    nb=np.ascontiguousarray(m["face_neigh"], np.int64),
-                    bc=np.ascontiguousarray(m["face_bc"], np.int32),
-                    sh=np.ascontiguousarray(m["face_shift"], np.float64))
-        d = _Desc(self.dim, len(keep["xyz"]), _ptr(keep["xyz"]), int(m["n_cell"]), len(keep["own"]),
-                  _ptr(keep["ptr"]), _ptr(keep["fv"]), _ptr(keep["own"]), _ptr(keep["nb"]), _ptr(keep["bc"]),
-                  _ptr(keep["sh"]), int(order_tile))
+        n_cell = int(m["n_cell"])
+        col = None if colour is None else np.ascontiguousarray(colour, np.int32)
+        if col is not None and col.shape != (n_cell,):
+            raise ValueError(f"colour: shape {col.shape}, expected ({n_cell},)")
+        xyz = np.ascontiguousarray(m["xyz"], np.float64)
         h = C.c_void_p()
-        _check(L.cgks_mesh_create(C.byref(d), C.byref(h)), "cgks_mesh_create")
+        if "cell_type" in m and not faces:
+            keep = dict(xyz=xyz, ct=np.ascontiguousarray(m["cell_type"], np.int32),
+                        cp=np.ascontiguousarray(m["cell_vert_ptr"], np.int64),
+                        cv=np.ascontiguousarray(m["cell_vert"], np.int64),
+                        bp=np.ascontiguousarray(m["bface_vert_ptr"], np.int64),
+                        bv=np.ascontiguousarray(m["bface_vert"], np.int64),
+                        bt=np.ascontiguousarray(m["bface_tag"], np.int32),
+                        bpair=np.ascontiguousarray(m["bface_pair"], np.int64), col=col)
+            d = _Desc(self.dim, len(xyz), _ptr(xyz), n_cell, _ptr(keep["ct"]), _ptr(keep["cp"]), _ptr(keep["cv"]),
+                      len(keep["bt"]), _ptr(keep["bp"]), _ptr(keep["bv"]), _ptr(keep["bt"]), _ptr(keep["bpair"]),
+                      _ptr(col), int(order_tile))
+            _check(L.cgks_mesh_create(C.byref(d), C.byref(h)), "cgks_mesh_create")
+        else:
+            keep = dict(xyz=xyz, ptr=np.ascontiguousarray(m["face_vert_ptr"], np.int64),
+                        fv=np.ascontiguousarray(m["face_vert"], np.int64),
+                        own=np.ascontiguousarray(m["face_owner"], np.int64),
+                        nb=np.ascontiguousarray(m["face_neigh"], np.int64),
+                        bc=np.ascontiguousarray(m["face_bc"], np.int32),
+                        sh=np.ascontiguousarray(m["face_shift"], np.float64), col=col)
+            d = _FaceDesc(self.dim, len(xyz), _ptr(xyz), n_cell, len(keep["own"]), _ptr(keep["ptr"]),
+                          _ptr(keep["fv"]), _ptr(keep["own"]), _ptr(keep["nb"]), _ptr(keep["bc"]), _ptr(keep["sh"]),
+                          _ptr(col), int(order_tile))
+            _check(L.cgks_mesh_create_faces(C.byref(d), C.byref(h)), "cgks_mesh_create_faces")
         self.h = h
         info = _Info()
         _check(L.cgks_mesh_query(h, C.byref(info)), "cgks_mesh_query")
@@ -239,12 +270,11 @@ class Mesh:
         _check(L.cgks_mesh_permutation(h, _ptr(self.lib2caller), _ptr(self.colour)), "cgks_mesh_permutation")
 
     def geometry(self):
-        """Caller-order (vol, centroid, h, linear) computed by the library."""
+        """Caller-order (vol, centroid, h) computed by the library."""
         n = self.n_cell
         vol, ctr, h = np.zeros(n), np.zeros((n, self.dim)), np.zeros(n)
-        lin = np.zeros(n, np.int32)
-        _check(lib().cgks_mesh_geometry(self.h, _ptr(vol), _ptr(ctr), _ptr(h), _ptr(lin)), "cgks_mesh_geometry")
-        return vol, ctr, h, lin
+        _check(lib().cgks_mesh_geometry(self.h, _ptr(vol), _ptr(ctr), _ptr(h)), "cgks_mesh_geometry")
+        return vol, ctr, h
 
     def __del__(self):
         if getattr(self, "h", None) and _lib is not None:
@@ -431,8 +461,16 @@ class Batch:
     def wall_force(self):
         """[n_case, 3] force of the gas on the walls at the start of the latest cycle."""
         f = np.zeros((self.n_case, 3))
-        _check(lib().cgks_wall_force(self.h, _ptr(f), _stream(self.stream)), "cgks_wall_force")
+        _check(lib().cgks_wall_force(self.h, _ptr(f), None, _stream(self.stream)), "cgks_wall_force")
         return f
+
+    def drag_coefficients(self):
+        """[n_case] drag coefficients of the latest wall forces, computed by
+        the library from each case's free stream and area_ref (NaN without)."""
+        f = np.zeros((self.n_case, 3))
+        cd = np.zeros(self.n_case)
+        _check(lib().cgks_wall_force(self.h, _ptr(f), _ptr(cd), _stream(self.stream)), "cgks_wall_force")
+        return cd
 
     def timing(self, enable=True):
         _check(lib().cgks_timing_enable(self.h, int(enable)), "cgks_timing_enable")
@@ -457,15 +495,5 @@ class Batch:
         if 2 <= check_every <= 8:
             self.graph_cycles = check_every
         out = [dict(cycles=r.cycles, converged=bool(r.converged), res_first=r.res_first, res_last=r.res_last,
-                    status=r.status, force=np.array(r.force[:])) for r in rep]
+                    status=r.status, force=np.array(r.force[:]), cd=r.cd) for r in rep]
         return out, hist
-
-
-def drag_coefficient(force, W_inf, area):
-    """Cd = F . e_inf / (1/2 rho_inf |U_inf|^2 A_ref) from a wall force."""
-    W_inf = np.asarray(W_inf, float)
-    d = len(W_inf) - 2
-    rho = W_inf[0]
-    U = W_inf[1:1 + d] / rho
-    q = 0.5 * rho * float(U @ U)
-    return float(np.asarray(force)[:d] @ (U / np.sqrt(U @ U))) / (q * area)

@@ -558,14 +558,16 @@ const char *cgks_status_string(cgks_status s) {
     return "unknown status";
 }
 
-cgks_status cgks_mesh_create(const cgks_mesh_desc *desc, cgks_mesh **out) {
+}  // extern "C"
+
+template <class Build> static cgks_status make_mesh(Build &&build, cgks_mesh **out) {
     if (!out) return CGKS_EINVAL;
     *out = nullptr;
     cgks_mesh *m = new (std::nothrow) cgks_mesh;
     if (!m) return CGKS_ENOMEM;
     cgks_status st;
     try {
-        st = build_host_mesh(desc, m->hm);
+        st = build(m->hm);
     } catch (const std::bad_alloc &) {
         st = CGKS_ENOMEM;
     }
@@ -575,6 +577,16 @@ cgks_status cgks_mesh_create(const cgks_mesh_desc *desc, cgks_mesh **out) {
     }
     *out = m;
     return CGKS_OK;
+}
+
+extern "C" {
+
+cgks_status cgks_mesh_create(const cgks_mesh_desc *desc, cgks_mesh **out) {
+    return make_mesh([desc](HostMesh &hm) { return build_host_mesh_cells(desc, hm); }, out);
+}
+
+cgks_status cgks_mesh_create_faces(const cgks_face_mesh_desc *desc, cgks_mesh **out) {
+    return make_mesh([desc](HostMesh &hm) { return build_host_mesh(desc, hm); }, out);
 }
 
 // planar face: the unit normals of its Gauss points agree with the first
@@ -598,9 +610,6 @@ cgks_status cgks_mesh_query(const cgks_mesh *mesh, cgks_mesh_info *info) {
     info->n_face = m.n_face;
     info->n_gp = m.n_gp;
     info->n_boundary_face = m.n_bface;
-    int64_t nl = 0;
-    for (auto v : m.linear) nl += v;
-    info->n_linear_cells = nl;
     int64_t np = 0;
     for (int64_t f = 0; f < m.n_face; ++f) np += face_planar(m, f) ? 1 : 0;
     info->n_planar_faces = np;
@@ -615,14 +624,12 @@ cgks_status cgks_mesh_permutation(const cgks_mesh *mesh, int64_t *lib_to_caller,
     return CGKS_OK;
 }
 
-cgks_status cgks_mesh_geometry(const cgks_mesh *mesh, double *vol, double *centroid, double *h, int32_t *linear) {
+cgks_status cgks_mesh_geometry(const cgks_mesh *mesh, double *vol, double *centroid, double *h) {
     if (!mesh) return CGKS_EINVAL;
     const HostMesh &m = mesh->hm;
     if (vol) std::copy(m.vol.begin(), m.vol.end(), vol);
     if (centroid) std::copy(m.ctr.begin(), m.ctr.end(), centroid);
     if (h) std::copy(m.h.begin(), m.h.end(), h);
-    if (linear)
-        for (int64_t i = 0; i < m.n_cell; ++i) linear[i] = m.linear[i];
     return CGKS_OK;
 }
 
@@ -1166,7 +1173,7 @@ cgks_status cgks_solve(cgks_batch *b, const cgks_solve_opts *opts, cgks_solve_re
     std::vector<char> done(n, 0);
     int remaining = 0;
     for (int c = 0; c < n; ++c) {
-        rep[c] = cgks_solve_report{0, 0, 0.0, 0.0, CGKS_ENOTCONV, {0.0, 0.0, 0.0}};
+        rep[c] = cgks_solve_report{0, 0, 0.0, 0.0, CGKS_ENOTCONV, {0.0, 0.0, 0.0}, std::nan("")};
         if (b->live[c]) ++remaining;
         else done[c] = 1;   // free slot: nothing to solve
     }
@@ -1237,17 +1244,19 @@ cgks_status cgks_solve(cgks_batch *b, const cgks_solve_opts *opts, cgks_solve_re
     HIP_TRY(hipMemcpyAsync((void *)b->dev.prm, prm.data(), sizeof(DevParams) * n, hipMemcpyHostToDevice, s));
     // wall force of each case's last stage-0 pass (a frozen case kept its
     // wall sums from its last active cycle)
-    std::vector<double> force(3 * size_t(n));
+    std::vector<double> force(3 * size_t(n)), cd(n);
     {
-        cgks_status fst = cgks_wall_force(b, force.data(), stream);
+        cgks_status fst = cgks_wall_force(b, force.data(), cd.data(), stream);
         if (fst) return fst;
     }
-    for (int c = 0; c < n; ++c)
+    for (int c = 0; c < n; ++c) {
         for (int a = 0; a < 3; ++a) rep[c].force[a] = force[3 * size_t(c) + a];
+        rep[c].cd = cd[c];
+    }
     return CGKS_OK;
 }
 
-cgks_status cgks_wall_force(cgks_batch *b, double *force, void *stream) {
+cgks_status cgks_wall_force(cgks_batch *b, double *force, double *cd, void *stream) {
     if (!b || !b->base || !force) return CGKS_EINVAL;
     hipStream_t s = static_cast<hipStream_t>(stream);
     if (b->hwB > 0) {
@@ -1257,6 +1266,22 @@ cgks_status cgks_wall_force(cgks_batch *b, double *force, void *stream) {
     }
     HIP_TRY(hipMemcpyAsync(force, b->dev.force, sizeof(double) * 3 * b->n_case, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
+    if (cd) {
+        // Cd = F . e_inf / (1/2 rho_inf |U_inf|^2 A_ref), e_inf = U_inf / |U_inf|
+        for (int c = 0; c < b->n_case; ++c) {
+            cd[c] = std::nan("");
+            if (!b->live[c]) continue;
+            const cgks_params &p = b->params[c];
+            const double rho = p.W_inf[0];
+            double u2 = 0, fu = 0;
+            for (int a = 0; a < b->dim; ++a) {
+                const double u = p.W_inf[1 + a] / rho;
+                u2 += u * u;
+                fu += force[3 * size_t(c) + a] * u;
+            }
+            if (p.area_ref > 0 && u2 > 0) cd[c] = fu / std::sqrt(u2) / (0.5 * rho * u2 * p.area_ref);
+        }
+    }
     return CGKS_OK;
 }
 

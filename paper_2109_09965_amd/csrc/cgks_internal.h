@@ -30,6 +30,7 @@ template <class F> inline void parallel_for(int64_t n, F &&fn) {
 }
 
 constexpr int kMaxGP = 4;     // Gauss points per face (3-D quad)
+constexpr int kMaxColoursMesh = 16;   // colour classes a caller colouring may use
 constexpr int kMaxSlots = 8;  // faces per cell kept in the padded slot table
 constexpr double kRankTol = 1e-8;
 
@@ -57,8 +58,7 @@ struct HostMesh {
     std::vector<int32_t> colour;
     int n_colour = 0;
     // reconstruction
-    std::vector<double> minv;               // [cell][nk*nk] (M^T M)^-1, linear block only on fallback
-    std::vector<uint8_t> linear;            // 1 = linear fallback
+    std::vector<double> minv;               // [cell][nk*nk] (M^T M)^-1
     std::vector<double> gavg;               // [face][nk] ghost basis averages (boundary faces)
     // library order
     int64_t tile = 0;                       // caller cells per ordering tile
@@ -74,7 +74,10 @@ struct HostMesh {
     std::vector<int64_t> libf2caller, caller2libf;
 };
 
-cgks_status build_host_mesh(const cgks_mesh_desc *d, HostMesh &m);
+// face-based and cell-based descriptions (the latter builds the faces and
+// then takes the face-based path)
+cgks_status build_host_mesh(const cgks_face_mesh_desc *d, HostMesh &m);
+cgks_status build_host_mesh_cells(const cgks_mesh_desc *d, HostMesh &m);
 
 }  // namespace cgks
 

@@ -1328,16 +1328,30 @@ template <int G, typename R> __device__ __forceinline__ R bcast_from(R v, int p)
 // record: lane q loads values [q er/G, (q+1) er/G) and every value reaches
 // the group by a quad-permute broadcast, so the record crosses the memory
 // pipeline once per face instead of once per Gauss point.
+template <int D> constexpr int rec_share() {
+    static_assert(Rec<D>::er % Dim<D>::lanes == 0, "record splits evenly over the face lanes");
+    return Rec<D>::er / Dim<D>::lanes;
+}
+
+template <int D, typename R> __device__ __forceinline__ void recon_eval_share(const R *mine, const R *x, R *Wx,
+                                                                              R G[D][D + 2]);
+
 template <int D, typename R> __device__ __forceinline__ void recon_eval(const Dev &d, int i, int q, const R *x, R *Wx,
                                                                         R G[D][D + 2]) {
-    using T = Dim<D>;
-    using RC = Rec<D>;
-    constexpr int nv = T::nv, nq = T::nq, KG = 3, GL = T::lanes, PL = RC::er / GL;
-    static_assert(RC::er % GL == 0, "record splits evenly over the face lanes");
-    const R *base = HoArrays<R>::ev(d) + size_t(i) * RC::er + q * PL;
+    constexpr int PL = rec_share<D>();
+    const R *base = HoArrays<R>::ev(d) + size_t(i) * Rec<D>::er + q * PL;
     R mine[PL];
 #pragma unroll
     for (int m = 0; m < PL; ++m) mine[m] = base[m];
+    recon_eval_share<D, R>(mine, x, Wx, G);
+}
+
+// the same from a share already in registers
+template <int D, typename R> __device__ __forceinline__ void recon_eval_share(const R *mine, const R *x, R *Wx,
+                                                                              R G[D][D + 2]) {
+    using T = Dim<D>;
+    using RC = Rec<D>;
+    constexpr int nv = T::nv, nq = T::nq, KG = 3, GL = T::lanes, PL = RC::er / GL;
 #define CGKS_REC(j) bcast_from<GL, R>(mine[(j) % PL], (j) / PL)
     R r[RC::OC];
 #pragma unroll

@@ -3,6 +3,7 @@
 // library cell order.  Runs once per mesh on the host (FP64, long double for
 // the small dense factorisations).
 #include <algorithm>
+#include <array>
 #include <atomic>
 #include <cmath>
 #include <cstring>
@@ -401,13 +402,15 @@ void recon_rows(const HostMesh &m, int64_t i, std::vector<long double> &A, int &
     }
 }
 
+// The reconstruction operators (M^T M)^-1 of every cell.  With the ghost
+// rows of boundary faces every stencil of a valid mesh fixes the whole
+// quadratic (each face brings d + 1 rows); one that does not is rejected.
 cgks_status recon_setup(HostMesh &m) {
-    const int nk = m.nk, d = m.dim;
+    const int nk = m.nk;
     m.gavg.assign(m.n_face * nk, 0.0);
     for (int64_t f = 0; f < m.n_face; ++f)
         if (m.neigh[f] < 0) ghost_avg(m, f, m.gavg.data() + f * nk);
     m.minv.assign(m.n_cell * nk * nk, 0.0);
-    m.linear.assign(m.n_cell, 0);
     std::atomic<bool> bad{false};
     parallel_for(m.n_cell, [&](int64_t i0, int64_t i1) {
         std::vector<long double> A;
@@ -415,20 +418,8 @@ cgks_status recon_setup(HostMesh &m) {
             int nr = 0;
             recon_rows(m, i, A, nr);
             std::vector<long double> Q(A);
-            if (nr >= nk && qr_ratio(nr, nk, Q) > kRankTol) {
-                inverse_normal(nk, Q, nk, m.minv.data() + i * nk * nk);
-                continue;
-            }
-            // linear fallback: the same rows restricted to the linear columns
-            std::vector<long double> L(nr * d);
-            for (int r = 0; r < nr; ++r)
-                for (int a = 0; a < d; ++a) L[r * d + a] = A[r * nk + a];
-            if (!(qr_ratio(nr, d, L) > kRankTol)) {
-                bad = true;
-                continue;
-            }
-            inverse_normal(d, L, nk, m.minv.data() + i * nk * nk);
-            m.linear[i] = 1;
+            if (nr >= nk && qr_ratio(nr, nk, Q) > kRankTol) inverse_normal(nk, Q, nk, m.minv.data() + i * nk * nk);
+            else bad = true;
         }
     });
     return bad ? CGKS_EMESH : CGKS_OK;
@@ -492,9 +483,26 @@ static std::vector<int64_t> morton_order(const HostMesh &m) {
 // passes visit colour 0 three times, colour C-1 twice and the others four
 // times, so the largest class takes C-1, the next largest 0 and the rest
 // 1..C-2 by decreasing size (stable on the greedy id).
-void colour_and_order(HostMesh &m) {
+void order_cells(HostMesh &m);
+
+// Multicolour classes and the library cell order.  colour (may be NULL):
+// the caller's classes, checked to be independent sets.
+cgks_status colour_and_order(HostMesh &m, const int32_t *caller_colour) {
     const int64_t n = m.n_cell;
     auto neighbour = [&](int64_t q) { return m.cf_side[q] ? m.owner[m.cf_face[q]] : m.neigh[m.cf_face[q]]; };
+    if (caller_colour) {
+        int ncol = 0;
+        for (int64_t i = 0; i < n; ++i) {
+            if (caller_colour[i] < 0 || caller_colour[i] >= kMaxColoursMesh) return CGKS_EMESH;
+            ncol = std::max(ncol, caller_colour[i] + 1);
+        }
+        for (int64_t f = 0; f < m.n_face; ++f)
+            if (m.neigh[f] >= 0 && caller_colour[m.owner[f]] == caller_colour[m.neigh[f]]) return CGKS_EMESH;
+        m.colour.assign(caller_colour, caller_colour + n);
+        m.n_colour = ncol;
+        order_cells(m);
+        return CGKS_OK;
+    }
     std::vector<int> deg(n, 0);
     for (int64_t i = 0; i < n; ++i)
         for (int64_t q = m.cf_ptr[i]; q < m.cf_ptr[i + 1]; ++q) deg[i] += neighbour(q) >= 0;
@@ -524,6 +532,14 @@ void colour_and_order(HostMesh &m) {
     for (int k = 0; k < ncol; ++k) relabel[by_size[k]] = k == 0 ? ncol - 1 : k - 1;
     for (int64_t i = 0; i < n; ++i) m.colour[i] = relabel[m.colour[i]];
     m.n_colour = ncol;
+    order_cells(m);
+    return CGKS_OK;
+}
+
+// library order from the colour classes: tiles of m.tile consecutive cells
+// of the Morton curve, colour-major inside each tile; faces follow
+void order_cells(HostMesh &m) {
+    const int ncol = m.n_colour;
     m.colour_count.assign(ncol, 0);
     for (int64_t i = 0; i < m.n_cell; ++i) m.colour_count[m.colour[i]]++;
     // library order: tiles of m.tile consecutive cells of the Morton curve,
@@ -572,9 +588,60 @@ void colour_and_order(HostMesh &m) {
     for (int64_t lf = 0; lf < m.n_face; ++lf) m.caller2libf[m.libf2caller[lf]] = lf;
 }
 
+
+// Canonical face form: the owner is the smaller cell id (a swap reverses
+// the vertex cycle and the periodic shift), a 3-D face's vertex cycle
+// starts at its smallest id, and faces are sorted by owner, neighbour
+// (boundary faces last) and vertex list.  Results then depend on the mesh
+// alone, not on how its faces were listed.
+void canonical_faces(HostMesh &m) {
+    const int d = m.dim;
+    const int64_t nf = m.n_face;
+    std::vector<std::vector<int64_t>> fv(nf);
+    for (int64_t f = 0; f < nf; ++f) {
+        fv[f].assign(m.fvert.begin() + m.fptr[f], m.fvert.begin() + m.fptr[f + 1]);
+        if (m.neigh[f] >= 0 && m.owner[f] > m.neigh[f]) {
+            std::swap(m.owner[f], m.neigh[f]);
+            std::reverse(fv[f].begin(), fv[f].end());
+            for (int a = 0; a < d; ++a) m.shift[f * d + a] = -m.shift[f * d + a];
+        }
+        if (d == 3) {
+            auto it = std::min_element(fv[f].begin(), fv[f].end());
+            std::rotate(fv[f].begin(), it, fv[f].end());
+        }
+    }
+    std::vector<int64_t> ord(nf);
+    for (int64_t f = 0; f < nf; ++f) ord[f] = f;
+    const int64_t big = m.n_cell;
+    std::sort(ord.begin(), ord.end(), [&](int64_t x, int64_t y) {
+        if (m.owner[x] != m.owner[y]) return m.owner[x] < m.owner[y];
+        const int64_t nx = m.neigh[x] < 0 ? big : m.neigh[x], ny = m.neigh[y] < 0 ? big : m.neigh[y];
+        if (nx != ny) return nx < ny;
+        return fv[x] < fv[y];
+    });
+    std::vector<int64_t> ptr(nf + 1, 0), vert, own(nf), nb(nf);
+    std::vector<int32_t> bc(nf);
+    std::vector<double> sh(nf * d);
+    for (int64_t k = 0; k < nf; ++k) {
+        const int64_t f = ord[k];
+        vert.insert(vert.end(), fv[f].begin(), fv[f].end());
+        ptr[k + 1] = int64_t(vert.size());
+        own[k] = m.owner[f];
+        nb[k] = m.neigh[f];
+        bc[k] = m.bc[f];
+        for (int a = 0; a < d; ++a) sh[k * d + a] = m.shift[f * d + a];
+    }
+    m.fptr.swap(ptr);
+    m.fvert.swap(vert);
+    m.owner.swap(own);
+    m.neigh.swap(nb);
+    m.bc.swap(bc);
+    m.shift.swap(sh);
+}
+
 }  // namespace
 
-cgks_status build_host_mesh(const cgks_mesh_desc *ds, HostMesh &m) {
+cgks_status build_host_mesh(const cgks_face_mesh_desc *ds, HostMesh &m) {
     if (!ds || (ds->dim != 2 && ds->dim != 3) || ds->n_cell <= 0 || ds->n_face <= 0 || ds->n_vert <= 0 ||
         !ds->xyz || !ds->face_vert_ptr || !ds->face_vert || !ds->face_owner || !ds->face_neigh || !ds->face_bc)
         return CGKS_EINVAL;
@@ -590,6 +657,8 @@ cgks_status build_host_mesh(const cgks_mesh_desc *ds, HostMesh &m) {
     m.xyz.assign(ds->xyz, ds->xyz + ds->n_vert * d);
     m.fptr.assign(ds->face_vert_ptr, ds->face_vert_ptr + ds->n_face + 1);
     if (m.fptr[0] != 0) return CGKS_EINVAL;
+    for (int64_t f = 0; f < m.n_face; ++f)
+        if (m.fptr[f + 1] < m.fptr[f]) return CGKS_EINVAL;
     m.fvert.assign(ds->face_vert, ds->face_vert + m.fptr[m.n_face]);
     m.owner.assign(ds->face_owner, ds->face_owner + m.n_face);
     m.neigh.assign(ds->face_neigh, ds->face_neigh + m.n_face);
@@ -609,6 +678,7 @@ cgks_status build_host_mesh(const cgks_mesh_desc *ds, HostMesh &m) {
                 return CGKS_EMESH;
         }
     }
+    canonical_faces(m);
     // faces of each cell in increasing face index
     m.cf_ptr.assign(m.n_cell + 1, 0);
     for (int64_t f = 0; f < m.n_face; ++f) {
@@ -638,8 +708,243 @@ cgks_status build_host_mesh(const cgks_mesh_desc *ds, HostMesh &m) {
     if (st != CGKS_OK) return st;
     st = cell_geometry(m);
     if (st != CGKS_OK) return st;
-    colour_and_order(m);
+    st = colour_and_order(m, ds->colour);
+    if (st != CGKS_OK) return st;
     return recon_setup(m);
+}
+
+// ---------------------------------------------------------------------
+// Faces from cells.
+// ---------------------------------------------------------------------
+namespace {
+
+// local faces of the standard cell types (vertex positions in the cell's
+// list; -1 ends a face)
+struct TypeFaces {
+    int dim, nvert, nface;
+    int face[6][4];
+};
+const TypeFaces *type_faces(int t) {
+    static const TypeFaces tri{2, 3, 3, {{0, 1, -1}, {1, 2, -1}, {2, 0, -1}}};
+    static const TypeFaces quad{2, 4, 4, {{0, 1, -1}, {1, 2, -1}, {2, 3, -1}, {3, 0, -1}}};
+    static const TypeFaces tet{3, 4, 4, {{0, 1, 2, -1}, {0, 1, 3, -1}, {1, 2, 3, -1}, {0, 2, 3, -1}}};
+    static const TypeFaces pyr{3, 5, 5, {{0, 1, 2, 3}, {0, 1, 4, -1}, {1, 2, 4, -1}, {2, 3, 4, -1}, {3, 0, 4, -1}}};
+    static const TypeFaces prism{3, 6, 5, {{0, 1, 2, -1}, {3, 4, 5, -1}, {0, 1, 4, 3}, {1, 2, 5, 4}, {2, 0, 3, 5}}};
+    static const TypeFaces hex{3, 8, 6,
+                               {{0, 1, 2, 3}, {4, 5, 6, 7}, {0, 1, 5, 4}, {1, 2, 6, 5}, {2, 3, 7, 6}, {3, 0, 4, 7}}};
+    switch (t) {
+        case CGKS_CELL_TRI: return &tri;
+        case CGKS_CELL_QUAD: return &quad;
+        case CGKS_CELL_TET: return &tet;
+        case CGKS_CELL_PYR: return &pyr;
+        case CGKS_CELL_PRISM: return &prism;
+        case CGKS_CELL_HEX: return &hex;
+        default: return nullptr;
+    }
+}
+
+struct CellFace {
+    std::array<int64_t, 4> key;   // sorted vertex ids, padded with -1
+    int64_t cell;
+    int64_t v[4];
+    int nv;
+};
+
+std::array<int64_t, 4> face_key(const int64_t *v, int nv) {
+    std::array<int64_t, 4> k{-1, -1, -1, -1};
+    for (int a = 0; a < nv; ++a) k[a] = v[a];
+    std::sort(k.begin(), k.begin() + nv);
+    return k;
+}
+
+}  // namespace
+
+cgks_status build_host_mesh_cells(const cgks_mesh_desc *ds, HostMesh &m) {
+    if (!ds || (ds->dim != 2 && ds->dim != 3) || ds->n_cell <= 0 || ds->n_vert <= 0 || !ds->xyz || !ds->cell_type ||
+        !ds->cell_vert_ptr || !ds->cell_vert || ds->n_bface < 0 || ds->order_tile < 0)
+        return CGKS_EINVAL;
+    if (ds->n_bface > 0 && (!ds->bface_vert_ptr || !ds->bface_vert || !ds->bface_tag)) return CGKS_EINVAL;
+    const int d = ds->dim;
+    const int64_t nc = ds->n_cell, nvx = ds->n_vert, nb = ds->n_bface;
+    const int64_t *cp = ds->cell_vert_ptr, *cv = ds->cell_vert;
+    if (cp[0] != 0) return CGKS_EINVAL;
+    auto vert_ok = [&](int64_t v) { return v >= 0 && v < nvx; };
+    // 1. every cell's faces, and the cell's vertex centroid
+    std::vector<CellFace> faces;
+    faces.reserve(size_t(nc) * (d == 2 ? 3 : 5));
+    std::vector<double> vctr(nc * d, 0.0);
+    for (int64_t i = 0; i < nc; ++i) {
+        const int64_t b = cp[i], e = cp[i + 1];
+        if (e <= b) return CGKS_EINVAL;
+        const int t = ds->cell_type[i];
+        std::vector<std::vector<int64_t>> fl;
+        if (t == CGKS_CELL_POLY) {
+            int64_t k = b;
+            const int64_t n_f = cv[k++];
+            if (n_f < d + 1 || n_f > (d == 2 ? 4 : kMaxSlots)) return CGKS_EMESH;
+            for (int64_t q = 0; q < n_f; ++q) {
+                if (k >= e) return CGKS_EINVAL;
+                const int64_t nfv = cv[k++];
+                if ((d == 2 && nfv != 2) || (d == 3 && nfv != 3 && nfv != 4) || k + nfv > e) return CGKS_EMESH;
+                fl.emplace_back(cv + k, cv + k + nfv);
+                k += nfv;
+            }
+            if (k != e) return CGKS_EINVAL;
+        } else {
+            const TypeFaces *tf = type_faces(t);
+            if (!tf || tf->dim != d || e - b != tf->nvert) return CGKS_EINVAL;
+            for (int q = 0; q < tf->nface; ++q) {
+                std::vector<int64_t> f;
+                for (int a = 0; a < 4 && tf->face[q][a] >= 0; ++a) f.push_back(cv[b + tf->face[q][a]]);
+                fl.push_back(f);
+            }
+        }
+        // vertex centroid over the cell's distinct vertices
+        std::vector<int64_t> vs;
+        for (auto &f : fl)
+            for (int64_t v : f) {
+                if (!vert_ok(v)) return CGKS_EMESH;
+                vs.push_back(v);
+            }
+        std::sort(vs.begin(), vs.end());
+        vs.erase(std::unique(vs.begin(), vs.end()), vs.end());
+        for (int64_t v : vs)
+            for (int a = 0; a < d; ++a) vctr[i * d + a] += ds->xyz[v * d + a] / double(vs.size());
+        for (auto &f : fl) {
+            CellFace c{};
+            c.nv = int(f.size());
+            for (int a = 0; a < c.nv; ++a) c.v[a] = f[a];
+            c.key = face_key(c.v, c.nv);
+            for (int a = 1; a < c.nv; ++a)
+                if (c.key[a] == c.key[a - 1]) return CGKS_EMESH;   // repeated vertex in a face
+            c.cell = i;
+            faces.push_back(c);
+        }
+    }
+    // 2. shared faces: equal vertex sets
+    std::vector<int64_t> ord(faces.size());
+    for (size_t k = 0; k < faces.size(); ++k) ord[k] = int64_t(k);
+    std::sort(ord.begin(), ord.end(), [&](int64_t x, int64_t y) {
+        if (faces[x].key != faces[y].key) return faces[x].key < faces[y].key;
+        return faces[x].cell < faces[y].cell;
+    });
+    // 3. the boundary list, by vertex set
+    std::vector<std::array<int64_t, 4>> bkey(nb);
+    for (int64_t q = 0; q < nb; ++q) {
+        const int64_t b = ds->bface_vert_ptr[q], e = ds->bface_vert_ptr[q + 1];
+        const int64_t nfv = e - b;
+        if ((d == 2 && nfv != 2) || (d == 3 && nfv != 3 && nfv != 4)) return CGKS_EMESH;
+        for (int64_t k = b; k < e; ++k)
+            if (!vert_ok(ds->bface_vert[k])) return CGKS_EMESH;
+        bkey[q] = face_key(ds->bface_vert + b, int(nfv));
+        const int32_t tag = ds->bface_tag[q];
+        if (tag != CGKS_BC_SLIP_WALL && tag != CGKS_BC_NOSLIP_ISOTHERMAL && tag != CGKS_BC_NOSLIP_ADIABATIC &&
+            tag != CGKS_BC_FARFIELD && tag != CGKS_BC_PERIODIC)
+            return CGKS_EMESH;
+        if (tag == CGKS_BC_PERIODIC) {
+            if (!ds->bface_pair) return CGKS_EINVAL;
+            const int64_t p = ds->bface_pair[q];
+            if (p < 0 || p >= nb || p == q || ds->bface_tag[p] != CGKS_BC_PERIODIC || ds->bface_pair[p] != q)
+                return CGKS_EMESH;
+        }
+    }
+    std::vector<int64_t> bord(nb);
+    for (int64_t q = 0; q < nb; ++q) bord[q] = q;
+    std::sort(bord.begin(), bord.end(), [&](int64_t x, int64_t y) { return bkey[x] < bkey[y]; });
+    for (int64_t q = 1; q < nb; ++q)
+        if (bkey[bord[q]] == bkey[bord[q - 1]]) return CGKS_EMESH;   // a boundary face listed twice
+    std::vector<int64_t> bface_of(nb, -1);     // boundary face -> cell face
+    // output arrays of the face-based form
+    std::vector<int64_t> fptr{0}, fvert, own, nbr;
+    std::vector<int32_t> fbc;
+    std::vector<double> shift;
+    // vertex average of a face, summed in increasing vertex id
+    auto face_centre = [&](const CellFace &c, double *x) {
+        for (int a = 0; a < d; ++a) {
+            double s = ds->xyz[c.key[0] * d + a];
+            for (int k = 1; k < c.nv; ++k) s += ds->xyz[c.key[k] * d + a];
+            x[a] = s / c.nv;
+        }
+    };
+    // the face's vertex cycle oriented outward from cell `owner`
+    auto emit = [&](const CellFace &c, int64_t owner, int64_t neigh, int32_t tag, const double *sh) {
+        const double *P[4];
+        for (int k = 0; k < c.nv; ++k) P[k] = ds->xyz + c.v[k] * d;
+        double nrm[3] = {0, 0, 0}, fc[3];
+        face_centre(c, fc);
+        if (d == 2) {
+            nrm[0] = P[1][1] - P[0][1];
+            nrm[1] = -(P[1][0] - P[0][0]);
+        } else {
+            double a[3], b[3];
+            for (int k = 0; k < 3; ++k) {
+                a[k] = c.nv == 4 ? P[2][k] - P[0][k] : P[1][k] - P[0][k];
+                b[k] = c.nv == 4 ? P[3][k] - P[1][k] : P[2][k] - P[0][k];
+            }
+            cross(a, b, nrm);
+        }
+        double dot = 0;
+        for (int k = 0; k < d; ++k) dot += nrm[k] * (fc[k] - vctr[owner * d + k]);
+        for (int k = 0; k < c.nv; ++k) fvert.push_back(dot < 0 ? c.v[c.nv - 1 - k] : c.v[k]);
+        fptr.push_back(int64_t(fvert.size()));
+        own.push_back(owner);
+        nbr.push_back(neigh);
+        fbc.push_back(tag);
+        for (int k = 0; k < d; ++k) shift.push_back(sh ? sh[k] : 0.0);
+    };
+    for (size_t k = 0; k < ord.size();) {
+        size_t r = k + 1;
+        while (r < ord.size() && faces[ord[r]].key == faces[ord[k]].key) ++r;
+        if (r - k > 2) return CGKS_EMESH;                        // shared by more than two cells
+        const CellFace &a = faces[ord[k]];
+        if (r - k == 2) {
+            const CellFace &b = faces[ord[k + 1]];
+            if (a.cell == b.cell) return CGKS_EMESH;
+            emit(a, a.cell, b.cell, CGKS_BC_INTERIOR, nullptr);   // a.cell < b.cell (sorted)
+        } else {
+            // a boundary face: find it in the list
+            auto it = std::lower_bound(bord.begin(), bord.end(), a.key,
+                                       [&](int64_t q, const std::array<int64_t, 4> &key) { return bkey[q] < key; });
+            if (it == bord.end() || bkey[*it] != a.key) return CGKS_EMESH;
+            bface_of[*it] = int64_t(ord[k]);
+            if (ds->bface_tag[*it] != CGKS_BC_PERIODIC) emit(a, a.cell, -1, ds->bface_tag[*it], nullptr);
+        }
+        k = r;
+    }
+    for (int64_t q = 0; q < nb; ++q)
+        if (bface_of[q] < 0) return CGKS_EMESH;                  // listed but matching no cell face
+    // periodic pairs: one interior face, owner the smaller cell
+    for (int64_t q = 0; q < nb; ++q) {
+        if (ds->bface_tag[q] != CGKS_BC_PERIODIC || ds->bface_pair[q] < q) continue;
+        const CellFace &a = faces[bface_of[q]], &b = faces[bface_of[ds->bface_pair[q]]];
+        if (a.cell == b.cell) return CGKS_EMESH;
+        const CellFace &o = a.cell < b.cell ? a : b, &n = a.cell < b.cell ? b : a;
+        double co[3], cn[3], sh[3];
+        face_centre(o, co);
+        face_centre(n, cn);
+        // the period: the offset of the two face centroids; components at
+        // round-off level of the coordinates are zero
+        for (int k = 0; k < d; ++k) {
+            sh[k] = co[k] - cn[k];
+            if (std::fabs(sh[k]) < 1e-12 * std::max({1.0, std::fabs(co[k]), std::fabs(cn[k])})) sh[k] = 0.0;
+        }
+        emit(o, o.cell, n.cell, CGKS_BC_INTERIOR, sh);
+    }
+    cgks_face_mesh_desc fd{};
+    fd.dim = d;
+    fd.n_vert = nvx;
+    fd.xyz = ds->xyz;
+    fd.n_cell = nc;
+    fd.n_face = int64_t(own.size());
+    fd.face_vert_ptr = fptr.data();
+    fd.face_vert = fvert.data();
+    fd.face_owner = own.data();
+    fd.face_neigh = nbr.data();
+    fd.face_bc = fbc.data();
+    fd.face_shift = shift.data();
+    fd.colour = ds->colour;
+    fd.order_tile = ds->order_tile;
+    return build_host_mesh(&fd, m);
 }
 
 }  // namespace cgks

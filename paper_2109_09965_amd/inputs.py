@@ -24,6 +24,20 @@ needs (paper, Sec. 2.1: the boundary of a cell is a union of N_f faces):
                                         neighbour next to the owner (nonzero
                                         only across periodic faces)
 
+The same meshes also carry the cell-based description the library's
+cgks_mesh_create takes (cells by type and vertex list, boundary faces by
+vertex list and tag; periodic seams as pairs of boundary faces):
+
+    cell_type      int32 [n_cell]       CELL_* (POLY: explicit faces)
+    cell_vert_ptr  int64 [n_cell + 1]   CSR into cell_vert
+    cell_vert      int64                vertex ids in the type's order, or for
+                                        POLY: face count, then per face its
+                                        vertex count and ids
+    bface_vert_ptr int64 [n_bface + 1]  CSR into bface_vert
+    bface_vert     int64
+    bface_tag      int32 [n_bface]      BC_* (BC_PERIODIC for seams)
+    bface_pair     int64 [n_bface]      partner of a periodic face, else -1
+
 Cell ids follow generation order (layer by layer for the O-grids).
 """
 from __future__ import annotations
@@ -116,9 +130,14 @@ def _assemble(dim, xyz, topo_of, F, cnt, cell_of_face, n_cell, classify):
     neigh_i = cell_of_face[nb_face]
 
     def centre(rows):
-        P = xyz[np.where(F[rows] >= 0, F[rows], 0)]
-        w = (F[rows] >= 0).astype(float)
-        return (P * w[:, :, None]).sum(1) / cnt[rows][:, None]
+        # vertex average, summed in increasing vertex id (padding last)
+        ids = np.sort(np.where(F[rows] >= 0, F[rows], _BIG), axis=1)
+        ok = ids < _BIG
+        P = xyz[np.where(ok, ids, 0)]
+        s = P[:, 0].copy()
+        for k in range(1, F.shape[1]):
+            s = s + np.where(ok[:, k:k + 1], P[:, k], 0.0)
+        return s / cnt[rows][:, None]
 
     shift_i = centre(own_face) - centre(nb_face)
     shift_i[np.abs(shift_i) < 1e-12] = 0.0
@@ -128,6 +147,21 @@ def _assemble(dim, xyz, topo_of, F, cnt, cell_of_face, n_cell, classify):
     bc_b = np.asarray(classify(centre(bnd)), dtype=np.int32) if len(bnd) else np.zeros(0, np.int32)
     if np.any(bc_b <= 0):
         raise ValueError("mesh: unclassified boundary face")
+
+    # boundary faces of the cell-based description: the unpaired faces, and
+    # both sides of every periodic pair (tagged periodic, each naming the other)
+    per = np.nonzero(np.any(shift_i != 0.0, axis=1))[0]
+    brows = np.concatenate([bnd, own_face[per], nb_face[per]])
+    btag = np.concatenate([bc_b, np.full(2 * len(per), BC_PERIODIC, np.int32)])
+    bpair = np.full(len(brows), -1, np.int64)
+    n0, npr = len(bnd), len(per)
+    bpair[n0:n0 + npr] = n0 + npr + np.arange(npr)
+    bpair[n0 + npr:] = n0 + np.arange(npr)
+    bcnt = cnt[brows]
+    bptr = np.zeros(len(brows) + 1, np.int64)
+    bptr[1:] = np.cumsum(bcnt)
+    bfv = F[brows]
+    bfv = bfv[bfv >= 0].astype(np.int64)
 
     rows = np.concatenate([own_face, bnd])
     owner = np.concatenate([owner_i, owner_b]).astype(np.int64)
@@ -145,7 +179,8 @@ def _assemble(dim, xyz, topo_of, F, cnt, cell_of_face, n_cell, classify):
     fv = fv[fv >= 0].astype(np.int64)
     return dict(dim=dim, xyz=np.ascontiguousarray(xyz, dtype=np.float64), n_cell=int(n_cell),
                 face_vert_ptr=ptr, face_vert=fv, face_owner=owner, face_neigh=neigh,
-                face_bc=bc, face_shift=np.ascontiguousarray(shift))
+                face_bc=bc, face_shift=np.ascontiguousarray(shift),
+                bface_vert_ptr=bptr, bface_vert=bfv, bface_tag=btag.astype(np.int32), bface_pair=bpair)
 
 
 # --------------------------------------------------------------------------
@@ -176,7 +211,11 @@ def _tri_grid(X, Y, gid, tid, classify):
     cnt = np.full(len(F), 2)
     ctr = xyz[tri].mean(1)
     F = _orient(F, cnt, cof, xyz, ctr)
-    return _assemble(2, xyz, topo, F, cnt, cof, n_cell, classify)
+    m = _assemble(2, xyz, topo, F, cnt, cof, n_cell, classify)
+    m["cell_type"] = np.full(n_cell, CELL_TRI, np.int32)
+    m["cell_vert_ptr"] = 3 * np.arange(n_cell + 1, dtype=np.int64)
+    m["cell_vert"] = tri.ravel().astype(np.int64)
+    return m
 
 
 def radial_stations(r0, r1, n, ratio):
@@ -271,6 +310,41 @@ def _tet_faces(t):
 _HEX_FACES = [(0, 2, 6, 4), (1, 3, 7, 5), (0, 1, 5, 4), (2, 3, 7, 6), (0, 1, 3, 2), (4, 5, 7, 6)]
 _PYRAMIDS = [[base] + [(base[e], base[(e + 1) % 4], 8) for e in range(4)] for base in _HEX_FACES]
 
+# cell types of the cell-based description (the library's CGKS_CELL_*)
+CELL_TRI, CELL_QUAD, CELL_TET, CELL_PYR, CELL_PRISM, CELL_HEX, CELL_POLY = 1, 2, 3, 4, 5, 6, 7
+BC_PERIODIC = 5
+
+
+def _template_key(tmpl):
+    return tuple(tuple(f) for f in tmpl)
+
+
+# standard cell types of the templates: (type, local corner ids in the
+# type's vertex order); other templates are written as POLY cells
+_CANON = {_template_key(_HEX): (CELL_HEX, [0, 1, 3, 2, 4, 5, 7, 6]),
+          _template_key(_PRISM_A): (CELL_PRISM, [0, 1, 3, 4, 5, 7]),
+          _template_key(_PRISM_B): (CELL_PRISM, [0, 3, 2, 4, 7, 6])}
+for _t in _KUHN:
+    _CANON[_template_key(_tet_faces(_t))] = (CELL_TET, list(_t))
+for _p in _PYRAMIDS:
+    _CANON[_template_key(_p)] = (CELL_PYR, list(_p[0]) + [8])
+
+
+def _cells_csr(blocks, n_cell):
+    """blocks: list of (cell ids, type, [n, k] vertex rows or list of
+    per-cell POLY encodings) -> cell_type, cell_vert_ptr, cell_vert in cell
+    id order."""
+    ctype = np.zeros(n_cell, np.int32)
+    rows = [None] * n_cell
+    for ids, t, verts in blocks:
+        ctype[ids] = t
+        for i, v in zip(ids, verts):
+            rows[i] = v
+    ptr = np.zeros(n_cell + 1, np.int64)
+    ptr[1:] = np.cumsum([len(r) for r in rows])
+    return ctype, ptr, np.concatenate([np.asarray(r, np.int64) for r in rows])
+
+
 LAYER_TEMPLATES = {
     "hex": [_HEX],
     "hex7": [_HEX7],
@@ -304,7 +378,7 @@ def _hybrid_grid(ni, nj, layer_types, gid, tid, coords, classify, cells=None):
         I, J = I.ravel(), J.ravel()
     else:
         I, J = (np.asarray(c, np.int64) for c in cells)
-    faces, cof, cell_vs = [], [], []
+    faces, cof, cell_vs, cell_blocks = [], [], [], []
     ncell = 0
     corners = [np.stack([gid(I + (l & 1), J + ((l >> 1) & 1), np.full_like(I, k) + ((l >> 2) & 1))
                          for l in range(8)], 1) for k in range(len(layer_types))]
@@ -334,6 +408,22 @@ def _hybrid_grid(ni, nj, layer_types, gid, tid, coords, classify, cells=None):
                 sel = ok & (c >= 3)
                 faces.append(Fd[sel])
                 cof.append(ids[sel])
+            # cell-based description: the standard type where no vertex
+            # collapsed, else the cell's remaining faces as a POLY cell
+            collapsed = np.zeros(len(I), bool)
+            for f, (_, c) in zip(tmpl, fl):
+                collapsed |= c != len(f)
+            canon = _CANON.get(_template_key(tmpl))
+            std = ok & ~collapsed if canon else np.zeros(len(I), bool)
+            if std.any():
+                cell_blocks.append((ids[std], canon[0], G[std][:, canon[1]]))
+            poly = ok & ~std
+            if poly.any():
+                enc = []
+                for r in np.nonzero(poly)[0]:
+                    fs = [Fd[r][:c[r]] for Fd, c in fl if c[r] >= 3]
+                    enc.append([len(fs)] + [x for f in fs for x in [len(f)] + list(f)])
+                cell_blocks.append((ids[poly], CELL_POLY, enc))
     F = np.concatenate(faces)
     cof = np.concatenate(cof)
     cnt = (F >= 0).sum(1)
@@ -349,7 +439,9 @@ def _hybrid_grid(ni, nj, layer_types, gid, tid, coords, classify, cells=None):
         xyz[base_id:base_id + len(C)] = coords(C.ravel()).reshape(len(C), 8, 3).mean(1)
     ctr = _fast_ctr(ncell, cell_vs, xyz)
     F = _orient_fast(F, cnt, cof, xyz, ctr)
-    return _assemble(3, xyz, topo, F, cnt, cof, ncell, classify)
+    m = _assemble(3, xyz, topo, F, cnt, cof, ncell, classify)
+    m["cell_type"], m["cell_vert_ptr"], m["cell_vert"] = _cells_csr(cell_blocks, ncell)
+    return m
 
 
 def _orient_fast(F, cnt, cof, xyz, ctr):

@@ -265,12 +265,14 @@ def test_wall_force_open_box_on_device(wall):
     """Gas at rest in a box with a far-field top: the force on the walls is
     -p0 * (top area) * e_z (the oracle's pin, here through the C ABI)."""
     m = I.box3d_mesh((3, 3, 5), perturb=0.2, seed=6, bc=wall)
-    bc = m["face_bc"].copy()
-    ptr, fv, xyz = m["face_vert_ptr"], m["face_vert"], m["xyz"]
-    for f in np.nonzero(m["face_neigh"] < 0)[0]:
-        if np.allclose(xyz[fv[ptr[f]:ptr[f + 1]], 2], 1.0):
-            bc[f] = I.BC_FARFIELD
-    m = dict(m, face_bc=bc)
+    # the top side becomes far field in the cell-based boundary list
+    tag = m["bface_tag"].copy()
+    ptr, fv, xyz = m["bface_vert_ptr"], m["bface_vert"], m["xyz"]
+    for q in range(len(tag)):
+        if np.allclose(xyz[fv[ptr[q]:ptr[q + 1]], 2], 1.0):
+            tag[q] = I.BC_FARFIELD
+    assert (tag == I.BC_FARFIELD).sum() == 18      # the top layer is tetrahedra: 2 triangles per quad
+    m = dict(m, bface_tag=tag)
     Winf = I.free_stream(3, 0.0)
     W, dW = I.uniform_state(m, Winf)
     b = cg.Batch([cg.Mesh(m)], [cg.Params(W_inf=Winf, mu=0.01, Pr=0.72)])
@@ -287,5 +289,58 @@ def test_solve_reports_wall_force():
         p.os.cycle(W, dW)
     fo = p.os.force()
     assert np.abs(rep[0]["force"] - fo).max() <= 1e-11 * np.abs(fo).max()
-    cd = cg.drag_coefficient(rep[0]["force"], I.free_stream(2, 0.15), 1.0)
-    assert np.isfinite(cd)
+    # without a reference area the report's drag coefficient is NaN; with
+    # one it is F . e_inf / (1/2 rho |U|^2 A) (free stream along x here)
+    assert np.isnan(rep[0]["cd"])
+    q = cg.Batch([p.lm], [cg.Params(W_inf=I.free_stream(2, 0.15), mu=0.15 / 40, Pr=0.72, area_ref=2.0)])
+    q.upload(0, p.W0, p.dW0)
+    rq, _ = q.solve(max_cycles=3, tol=0.0, check_every=1)
+    assert rq[0]["cd"] == pytest.approx(fo[0] / (0.5 * 0.15 ** 2 * 2.0), rel=1e-11)
+
+
+@pytest.mark.parametrize("name", ["cubed_sphere_adiab", "box3d_pyr", "cyl2d_adiab", "box2d_per"])
+def test_cell_and_face_descriptions_step_alike(name):
+    """The mesh built by the library's face builder from cells (the C ABI's
+    cgks_mesh_create) and the one built from the face list
+    (cgks_mesh_create_faces) give bitwise the same state after three
+    cycles."""
+    import torch
+    m, kw, W, dW = make_case(name)
+    out = []
+    for faces in (False, True):
+        b = cg.Batch([cg.Mesh(m, faces=faces)], [cg.Params(**kw)])
+        b.upload(0, W, dW)
+        for _ in range(3):
+            b.cycle()
+        torch.cuda.synchronize()
+        out.append(b.download(0))
+    assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
+
+
+@pytest.mark.parametrize("name", ["cubed_sphere_adiab", "cyl2d_adiab"])
+def test_caller_colouring_parity(name):
+    """A caller colouring (here the library's own classes relabelled in
+    reverse, a different sweep order) drives the relaxation of both the
+    HIP path and the oracle: three cycles agree to the parity tolerance,
+    and differ from the default colouring's cycles (the order is really
+    used)."""
+    m, kw, W, dW = make_case(name)
+    base = cg.Mesh(m)
+    col = (base.n_colour - 1 - base.colour).astype(np.int32)
+    lm = cg.Mesh(m, colour=col)
+    assert np.array_equal(lm.colour, col)
+    om = oracle.Mesh(m, colour=col)
+    os_ = oracle.Solver(om, oracle.Params(**kw))
+    b = cg.Batch([lm], [cg.Params(**kw)])
+    b.upload(0, W, dW)
+    Wo, dWo = W.copy(), dW.copy()
+    for _ in range(3):
+        os_.cycle(Wo, dWo)
+        b.cycle()
+    Wg, dWg = b.download(0)
+    assert rel(Wg, Wo) <= TOL_W and rel(dWg, dWo) <= TOL_G
+    bd = cg.Batch([base], [cg.Params(**kw)])
+    bd.upload(0, W, dW)
+    for _ in range(3):
+        bd.cycle()
+    assert not np.array_equal(bd.download(0)[0], Wg)

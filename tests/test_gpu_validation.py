@@ -29,7 +29,7 @@ def wake_and_separation(m, W, n_theta):
     turns positive, in diameters) and separation angle (from the rear
     stagnation point, where the first wall layer's tangential velocity
     changes sign), from the converged cell averages of the O-mesh."""
-    vol, cen, h, lin = cg.Mesh(m).geometry()
+    vol, cen, h = cg.Mesh(m).geometry()
     cen = np.asarray(cen)
     cen = cen if cen.shape[0] == m["n_cell"] else cen.T
     x, y = cen[:, 0], cen[:, 1]
@@ -52,12 +52,12 @@ def wake_and_separation(m, W, n_theta):
 
 def converged_cd(m, Ma, Re, area, max_cycles, state=None):
     w = I.free_stream(m["dim"], Ma)
-    b = cg.Batch([cg.Mesh(m)], [cg.Params(W_inf=w, mu=Ma / Re, Pr=0.72)])
+    b = cg.Batch([cg.Mesh(m)], [cg.Params(W_inf=w, mu=Ma / Re, Pr=0.72, area_ref=area)])
     W, dW = I.uniform_state(m, w)
     b.upload(0, W, dW)
     rep, _ = b.solve(max_cycles=max_cycles, tol=1e-9, check_every=8)
     r = rep[0]
-    cd = cg.drag_coefficient(r["force"], w, area)
+    cd = r["cd"]
     print(f"{m['name'] if 'name' in m else m['dim']}: {r['cycles']} cycles, converged {r['converged']}, "
           f"Cd {cd:.4f}", flush=True)
     assert r["converged"], r
@@ -91,7 +91,7 @@ def sphere_wake_and_separation(m, W):
     sphere) and separation angle from the front stagnation point, where the
     azimuthal mean of the first wall layer's meridional velocity changes
     sign (2-degree bins)."""
-    vol, cen, h, lin = cg.Mesh(m).geometry()
+    vol, cen, h = cg.Mesh(m).geometry()
     cen = np.asarray(cen)
     cen = cen if cen.shape[0] == m["n_cell"] else cen.T
     x, rp, r = cen[:, 0], np.hypot(cen[:, 1], cen[:, 2]), np.linalg.norm(cen, axis=1)
@@ -170,12 +170,13 @@ def test_low_level_flux_choice(scheme):
     lm = cg.Mesh(m)
     out = {}
     for lf in (cg.LOW_KFVS, cg.LOW_LF):
-        b = cg.Batch([lm], [cg.Params(W_inf=w, mu=g["Ma"] / g["Re"], Pr=0.72, low_flux=lf, time_scheme=scheme)])
+        b = cg.Batch([lm], [cg.Params(W_inf=w, mu=g["Ma"] / g["Re"], Pr=0.72, low_flux=lf, time_scheme=scheme,
+                                      area_ref=1.0)])
         W, dW = I.uniform_state(m, w)
         b.upload(0, W, dW)
         rep, _ = b.solve(max_cycles=6000, tol=1e-12, check_every=8)
         r = rep[0]
-        out[lf] = (r["cycles"], b.download(0)[0], cg.drag_coefficient(r["force"], w, 1.0))
+        out[lf] = (r["cycles"], b.download(0)[0], r["cd"])
         print(f"scheme {scheme} low flux {lf}: {r['cycles']} cycles, converged {r['converged']}, "
               f"Cd {out[lf][2]:.8f}", flush=True)
         assert r["converged"], r

@@ -37,13 +37,15 @@ def test_host_geometry_and_colouring_match_oracle(mk):
     lm = cg.Mesh(mesh)
     om = oracle.Mesh(mesh)
     ce = om.cells()
-    vol, ctr, h, lin = lm.geometry()
+    vol, ctr, h = lm.geometry()
     np.testing.assert_allclose(vol, ce["vol"], rtol=1e-12)
     np.testing.assert_allclose(ctr, ce["ctr"], rtol=0, atol=1e-12 * np.abs(ctr).max())
     np.testing.assert_allclose(h, ce["h"], rtol=1e-12)
     assert np.array_equal(lm.colour, ce["colour"])
     assert lm.n_colour == om.n_colour
-    assert np.array_equal(lin, om.linear_cells())
+    # with the boundary rows every stencil fixes the quadratic (the library
+    # accepted the mesh, and the oracle finds no rank-deficient stencil)
+    assert om.linear_cells().sum() == 0
     # library order is a permutation, colour-major when the mesh is one tile
     assert np.array_equal(np.sort(lm.lib2caller), np.arange(mesh["n_cell"]))
     assert np.all(np.diff(lm.colour[lm.lib2caller]) >= 0)
@@ -75,7 +77,7 @@ def test_library_order_is_tiled_colour_major(tile):
     lm = cg.Mesh(mesh, order_tile=tile)
     l2c = lm.lib2caller
     assert np.array_equal(np.sort(l2c), np.arange(n))
-    _, ctr, _, _ = lm.geometry()
+    _, ctr, _ = lm.geometry()
     curve = np.lexsort((np.arange(n), morton_keys(ctr)))   # stable by key, ties by caller id
     rank = np.empty(n, np.int64)
     rank[curve] = np.arange(n)
@@ -106,16 +108,119 @@ def test_mesh_errors_are_reported():
     bad["face_owner"] = mesh["face_owner"].copy()
     bad["face_owner"][0] = mesh["n_cell"] + 5
     with pytest.raises(cg.CgksError) as e:
-        cg.Mesh(bad)
+        cg.Mesh(bad, faces=True)
     assert e.value.status == cg.EMESH
     adi = dict(mesh)
     adi["face_bc"] = np.where(mesh["face_bc"] == I.BC_SLIP_WALL, I.BC_NOSLIP_ADIABATIC, mesh["face_bc"]).astype(np.int32)
-    cg.Mesh(adi)
+    cg.Mesh(adi, faces=True)
     unknown = dict(mesh)
     unknown["face_bc"] = np.where(mesh["face_bc"] == I.BC_SLIP_WALL, 7, mesh["face_bc"]).astype(np.int32)
     with pytest.raises(cg.CgksError) as e:
-        cg.Mesh(unknown)
+        cg.Mesh(unknown, faces=True)
     assert e.value.status == cg.EMESH
+
+
+def _expect(status, m, **kw):
+    with pytest.raises(cg.CgksError) as e:
+        cg.Mesh(m, **kw)
+    assert e.value.status == status, e.value
+
+
+def test_cell_mesh_errors_are_reported():
+    """The library's face builder rejects: a boundary face missing from the
+    list (a cell face neither shared nor listed), a listed face that matches
+    no cell face, a face listed twice, an unknown tag, a periodic face whose
+    partner does not pair back, a cell of a type foreign to the dimension
+    and a vertex id out of range."""
+    mesh = I.cylinder_mesh(16, 8)
+    nb = len(mesh["bface_tag"])
+    drop = dict(mesh)
+    drop["bface_vert_ptr"] = mesh["bface_vert_ptr"][:-1]
+    drop["bface_tag"] = mesh["bface_tag"][:-1]
+    drop["bface_pair"] = mesh["bface_pair"][:-1]
+    drop["bface_vert"] = mesh["bface_vert"][:mesh["bface_vert_ptr"][nb - 1]]
+    _expect(cg.EMESH, drop)
+    extra = dict(mesh)
+    extra["bface_vert_ptr"] = np.append(mesh["bface_vert_ptr"], mesh["bface_vert_ptr"][-1] + 2)
+    extra["bface_vert"] = np.append(mesh["bface_vert"], [0, 5])
+    extra["bface_tag"] = np.append(mesh["bface_tag"], I.BC_FARFIELD).astype(np.int32)
+    extra["bface_pair"] = np.append(mesh["bface_pair"], -1)
+    _expect(cg.EMESH, extra)
+    twice = dict(extra)
+    twice["bface_vert"] = np.append(mesh["bface_vert"], mesh["bface_vert"][:2])
+    _expect(cg.EMESH, twice)
+    tag = dict(mesh)
+    tag["bface_tag"] = np.where(mesh["bface_tag"] == I.BC_SLIP_WALL, 9, mesh["bface_tag"]).astype(np.int32)
+    _expect(cg.EMESH, tag)
+    per = I.box2d_mesh(4, periodic=True)
+    assert (per["bface_tag"] == I.BC_PERIODIC).all()
+    broken = dict(per)
+    broken["bface_pair"] = per["bface_pair"].copy()
+    broken["bface_pair"][0] = broken["bface_pair"][1]
+    _expect(cg.EMESH, broken)
+    wrong_type = dict(mesh)
+    wrong_type["cell_type"] = mesh["cell_type"].copy()
+    wrong_type["cell_type"][3] = I.CELL_TET
+    _expect(cg.EINVAL, wrong_type)
+    far = dict(mesh)
+    far["cell_vert"] = mesh["cell_vert"].copy()
+    far["cell_vert"][7] = len(mesh["xyz"]) + 3
+    _expect(cg.EMESH, far)
+
+
+@pytest.mark.parametrize("mk", [I.cylinder_case_mesh, lambda: I.box2d_mesh(6, periodic=True, perturb=0.3, seed=2),
+                                lambda: I.sphere_mesh(8, 16, 10, 4, 3), lambda: I.cubed_sphere_mesh(4, 10, 4, 3),
+                                lambda: I.box3d_mesh((3, 3, 5), periodic=True, perturb=0.2, seed=4),
+                                lambda: I.box3d_mesh((3, 3, 4), layer_types=["hex", "pyr", "hex", "pyr"],
+                                                     periodic=True, perturb=0.2, seed=3)])
+def test_cell_and_face_descriptions_build_the_same_mesh(mk):
+    """The library's face builder (cells by type and vertex list, boundary
+    faces by vertex list and tag, periodic seams as face pairs) and the
+    face-based description give bitwise the same host mesh: geometry,
+    colouring, library order and face counts; so does the face-based
+    description with its faces listed in a shuffled order and with
+    owner/neighbour swapped on some faces."""
+    mesh = mk()
+    a, b = cg.Mesh(mesh), cg.Mesh(mesh, faces=True)
+    rng = np.random.default_rng(4)
+    nf = len(mesh["face_owner"])
+    perm = rng.permutation(nf)
+    ptr, fv = mesh["face_vert_ptr"], mesh["face_vert"]
+    own, nb, sh = mesh["face_owner"][perm].copy(), mesh["face_neigh"][perm].copy(), mesh["face_shift"][perm].copy()
+    rows = [list(fv[ptr[f]:ptr[f + 1]]) for f in perm]
+    swap = (rng.uniform(size=nf) < 0.3) & (nb >= 0)
+    for k in np.nonzero(swap)[0]:
+        own[k], nb[k] = nb[k], own[k]
+        rows[k] = rows[k][::-1]
+        sh[k] = -sh[k]
+    shuffled = dict(mesh, face_owner=own, face_neigh=nb, face_shift=sh, face_bc=mesh["face_bc"][perm],
+                    face_vert=np.concatenate(rows).astype(np.int64),
+                    face_vert_ptr=np.concatenate([[0], np.cumsum([len(r) for r in rows])]).astype(np.int64))
+    c = cg.Mesh(shuffled, faces=True)
+    ga = a.geometry()
+    for other in (b, c):
+        for x, y in zip(ga, other.geometry()):
+            assert np.array_equal(x, y)
+        assert np.array_equal(a.colour, other.colour) and np.array_equal(a.lib2caller, other.lib2caller)
+        assert (a.n_face, a.n_gp, a.info.n_boundary_face, a.info.n_planar_faces) == \
+            (other.n_face, other.n_gp, other.info.n_boundary_face, other.info.n_planar_faces)
+
+
+def test_caller_colouring_is_used_and_checked():
+    """A caller colouring replaces the library's: an independent-set
+    colouring is taken as given (class ids and all); one that gives two face
+    neighbours the same colour, or ids outside 0..15, is rejected."""
+    mesh = I.cubed_sphere_mesh(4, 10, 4, 3)
+    base = cg.Mesh(mesh).colour
+    mine = (base + 2) % 6                 # a relabelled proper colouring, ids 0..5
+    lm = cg.Mesh(mesh, colour=mine)
+    assert np.array_equal(lm.colour, mine) and lm.n_colour == mine.max() + 1
+    clash = mine.copy()
+    own, nb = mesh["face_owner"], mesh["face_neigh"]
+    f = np.flatnonzero(nb >= 0)[0]
+    clash[nb[f]] = clash[own[f]]
+    _expect(cg.EMESH, mesh, colour=clash)
+    _expect(cg.EMESH, mesh, colour=np.full(mesh["n_cell"], 16, np.int32))
 
 
 @pytest.mark.parametrize("over,expect", [({}, 0), ({"low_flux": 1}, 0), ({"low_flux": 2}, 1), ({"time_scheme": 5}, 1),
