@@ -629,6 +629,110 @@ def box3d_mesh(n=(4, 4, 4), L=(1.0, 1.0, 1.0), layer_types=None, periodic=False,
     return m
 
 
+
+def extrude_two_layers(mesh2d, dz=None):
+    """The paper's way of running a 2-D case on a 3-D code (Sec. 4): the
+    triangle mesh extruded through two layers of prisms in z, each of
+    thickness dz (default: the smallest edge length of the 2-D mesh).  The
+    2-D boundary edges become quads with the same tags; the two layers are
+    periodic in z (the top of layer 1 is joined to the bottom of layer 0),
+    so each prism meets the other layer through both of its triangles and
+    a sweep that updates one layer before the other exerts no net z force
+    on it.  Cell k of layer l has id k + l n; vertex v of plane z = l dz
+    has id v + l n_vert."""
+    assert mesh2d["dim"] == 2 and (mesh2d["cell_type"] == CELL_TRI).all()
+    xy = mesh2d["xyz"]
+    nv2, n2 = len(xy), mesh2d["n_cell"]
+    tri = mesh2d["cell_vert"].reshape(n2, 3).copy()
+    ptr, fv = mesh2d["face_vert_ptr"], mesh2d["face_vert"]
+    own2, nb2, bc2 = mesh2d["face_owner"], mesh2d["face_neigh"], mesh2d["face_bc"]
+    e = xy[fv[ptr[1:] - 1]] - xy[fv[ptr[:-1]]]
+    if dz is None:
+        dz = float(np.sqrt((e * e).sum(1)).min())
+    xyz = np.concatenate([np.column_stack([xy, np.full(nv2, l * dz)]) for l in range(3)])
+    # counter-clockwise triangles: their (a, b, c) normal is +z
+    P = xy[tri]
+    ccw = ((P[:, 1, 0] - P[:, 0, 0]) * (P[:, 2, 1] - P[:, 0, 1])
+           - (P[:, 1, 1] - P[:, 0, 1]) * (P[:, 2, 0] - P[:, 0, 0])) > 0
+    tri[~ccw] = tri[~ccw][:, ::-1]
+    fvs, own, nb, bc, sh = [], [], [], [], []
+    ed = np.stack([fv[ptr[:-1]], fv[ptr[:-1] + 1]], 1)     # 2-D edges, normal out of their owner
+    for l in range(2):
+        for f in range(len(own2)):
+            p_, q_ = ed[f]
+            fvs.append([p_ + l * nv2, q_ + l * nv2, q_ + (l + 1) * nv2, p_ + (l + 1) * nv2])
+            own.append(own2[f] + l * n2)
+            nb.append(nb2[f] + l * n2 if nb2[f] >= 0 else -1)
+            bc.append(bc2[f])
+            sh.append([0.0, 0.0, 0.0])
+    for k in range(n2):
+        a, b, c = tri[k]
+        fvs.append([a + nv2, b + nv2, c + nv2])                 # mid plane, +z out of layer 0
+        own.append(k)
+        nb.append(k + n2)
+        bc.append(BC_INTERIOR)
+        sh.append([0.0, 0.0, 0.0])
+    # periodic seam: layer 0's bottom (owner) and layer 1's top
+    top0 = np.array([[c, b, a] for a, b, c in tri])             # -z out of layer 0
+    top2 = tri + 2 * nv2
+
+    def centre(ids):
+        ids = np.sort(ids)
+        s = xyz[ids[0]].copy()
+        for v in ids[1:]:
+            s = s + xyz[v]
+        return s / len(ids)
+    for k in range(n2):
+        fvs.append(list(top0[k]))
+        own.append(k)
+        nb.append(k + n2)
+        bc.append(BC_INTERIOR)
+        d = centre(top0[k]) - centre(top2[k])
+        d[np.abs(d) < 1e-12] = 0.0
+        sh.append(list(d))
+    cnt = np.array([len(x) for x in fvs])
+    m = dict(dim=3, xyz=xyz, n_cell=2 * n2,
+             face_vert_ptr=np.concatenate([[0], np.cumsum(cnt)]).astype(np.int64),
+             face_vert=np.concatenate(fvs).astype(np.int64), face_owner=np.array(own, np.int64),
+             face_neigh=np.array(nb, np.int64), face_bc=np.array(bc, np.int32), face_shift=np.array(sh))
+    # cell-based description
+    cells = np.concatenate([np.concatenate([tri + l * nv2, tri + (l + 1) * nv2], 1) for l in range(2)])
+    m["cell_type"] = np.full(2 * n2, CELL_PRISM, np.int32)
+    m["cell_vert_ptr"] = 6 * np.arange(2 * n2 + 1, dtype=np.int64)
+    m["cell_vert"] = cells.ravel().astype(np.int64)
+    bnd = np.flatnonzero(nb2 < 0)
+    bf = [[ed[f][0] + l * nv2, ed[f][1] + l * nv2, ed[f][1] + (l + 1) * nv2, ed[f][0] + (l + 1) * nv2]
+          for l in range(2) for f in bnd]
+    btag = [bc2[f] for l in range(2) for f in bnd]
+    nbd = len(bf)
+    bf += [list(top0[k]) for k in range(n2)] + [list(top2[k]) for k in range(n2)]
+    btag += [BC_PERIODIC] * (2 * n2)
+    pair = np.full(len(bf), -1, np.int64)
+    pair[nbd:nbd + n2] = nbd + n2 + np.arange(n2)
+    pair[nbd + n2:] = nbd + np.arange(n2)
+    bcnt = np.array([len(x) for x in bf])
+    m["bface_vert_ptr"] = np.concatenate([[0], np.cumsum(bcnt)]).astype(np.int64)
+    m["bface_vert"] = np.concatenate(bf).astype(np.int64)
+    m["bface_tag"] = np.array(btag, np.int32)
+    m["bface_pair"] = pair
+    m["name"] = f"two_layer_{mesh2d.get('name', '2d')}"
+    m["dz"] = dz
+    m["period"] = np.array([0.0, 0.0, 2 * dz])
+    return m
+
+
+def lift_state(W2, dW2, n_layers=2):
+    """A 2-D state [4][n], [2][4][n] as the z-uniform 3-D state of an
+    extruded mesh: w momentum and every z derivative zero."""
+    n = W2.shape[1]
+    W = np.zeros((5, n_layers * n))
+    dW = np.zeros((3, 5, n_layers * n))
+    for l in range(n_layers):
+        s = slice(l * n, (l + 1) * n)
+        W[[0, 1, 2, 4], s] = W2
+        dW[:2, [0, 1, 2, 4], s] = dW2
+    return W, dW
+
 # --------------------------------------------------------------------------
 # flow conditions and states
 # --------------------------------------------------------------------------
