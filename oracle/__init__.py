@@ -73,6 +73,7 @@ def lib():
         L.om_dt.argtypes = [P, P, dp]
         L.om_stage.argtypes = [P, i, dp, dp]
         L.om_stage_combine.argtypes = [i, i, d, d, d, d, d, C.POINTER(d)]
+        L.om_grad_combine.argtypes = [i, i, d, d, d, d, C.POINTER(d)]
         L.om_residual_high.argtypes = [P, dp, dp, dp]
         L.om_ho_sums.argtypes = [P, dp, dp, dp, dp, dp, dp]
         L.om_residual_low.argtypes = [P, P, dp, dp]
@@ -336,8 +337,17 @@ def micro_slope(W, dWdx, gamma=1.4):
 
 
 def stage_combine(scheme, stage, dt, Wn, L0, Lt0, Lt1=0.0):
+    """The cell-average update of one stage (the code every cell takes)."""
     out = C.c_double(0.0)
     lib().om_stage_combine(scheme, stage, dt, Wn, L0, Lt0, Lt1, C.byref(out))
+    return out.value
+
+
+def grad_combine(scheme, stage, dt, G0, G, Gt):
+    """The gradient update of one stage from Gauss-Green sums (the code every
+    cell takes); G0 is the first stage's G, used at stage 1."""
+    out = C.c_double(0.0)
+    lib().om_grad_combine(scheme, stage, dt, G0, G, Gt, C.byref(out))
     return out.value
 
 

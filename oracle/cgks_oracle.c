@@ -1629,6 +1629,21 @@ void om_ctx_force(const om_ctx *c, double *f) { f[0] = c->force[0]; f[1] = c->fo
 /* Gauss-Green: |V| grad W = sum_f sum_g wJ W_g n (Sec. 2.3).            */
 /* stage 0 computes dt and the first stage; stage 1 finishes S2O4.       */
 /* ------------------------------------------------------------------ */
+/* The stage formulas on one value, used by om_stage for every cell and
+   exported for the closed-form time-marching pins.  Cell averages: from
+   W^n, L^n, L_t^n (and L_t^* at stage 1).  Gradients: from the Gauss-Green
+   sums G = GG(W_g), Gt = GG(W_t) of the current pass (and G0 = GG(W_g^n)
+   at stage 1). */
+void om_stage_combine(int scheme, int stage, double dt, double Wn, double L0, double Lt0, double Lt1, double *out) {
+    if (stage == 0) *out = scheme == 0 ? Wn + 0.5 * dt * L0 + 0.125 * dt * dt * Lt0 : Wn + dt * L0 + 0.5 * dt * dt * Lt0;
+    else *out = Wn + dt * L0 + dt * dt / 6.0 * (Lt0 + 2.0 * Lt1);
+}
+
+void om_grad_combine(int scheme, int stage, double dt, double G0, double G, double Gt, double *out) {
+    if (stage == 0) *out = scheme == 0 ? G + 0.5 * dt * Gt : G + dt * Gt;
+    else *out = G0 + dt * Gt;
+}
+
 int om_stage(om_ctx *c, int stage, double *W, double *dW) {
     const om_mesh *m = c->m;
     const om_params *P = &c->P;
@@ -1650,13 +1665,10 @@ int om_stage(om_ctx *c, int stage, double *W, double *dW) {
             if (stage == 0) {
                 c->L0[v * N + i] = L;
                 c->Lt0[v * N + i] = Lt;
-                if (P->time_scheme == 0)
-                    W[v * N + i] = c->Wn[v * N + i] + 0.5 * dt * L + 0.125 * dt * dt * Lt;
-                else
-                    W[v * N + i] = c->Wn[v * N + i] + dt * L + 0.5 * dt * dt * Lt;
+                om_stage_combine(P->time_scheme, 0, dt, c->Wn[v * N + i], L, Lt, 0.0, &W[v * N + i]);
             } else {
-                W[v * N + i] = c->Wn[v * N + i] + dt * c->L0[v * N + i] +
-                               dt * dt / 6.0 * (c->Lt0[v * N + i] + 2.0 * Lt);
+                om_stage_combine(P->time_scheme, 1, dt, c->Wn[v * N + i], c->L0[v * N + i], c->Lt0[v * N + i], Lt,
+                                 &W[v * N + i]);
             }
             for (int a = 0; a < d; a++) {
                 long k = (a * nv + v) * N + i;
@@ -1664,21 +1676,12 @@ int om_stage(om_ctx *c, int stage, double *W, double *dW) {
                 if (stage == 0) {
                     c->G0[k] = G;
                     c->Gt0[k] = Gt;
-                    dW[k] = P->time_scheme == 0 ? G + 0.5 * dt * Gt : G + dt * Gt;
-                } else {
-                    dW[k] = c->G0[k] + dt * Gt;
                 }
+                om_grad_combine(P->time_scheme, stage, dt, c->G0[k], G, Gt, &dW[k]);
             }
         }
     }
     return 0;
-}
-
-/* exported for the closed-form time-marching pin: one S2O4 (or S1O2)
-   step of the stage formulas fed with given L and L_t operators */
-void om_stage_combine(int scheme, int stage, double dt, double Wn, double L0, double Lt0, double Lt1, double *out) {
-    if (stage == 0) *out = scheme == 0 ? Wn + 0.5 * dt * L0 + 0.125 * dt * dt * Lt0 : Wn + dt * L0 + 0.5 * dt * dt * Lt0;
-    else *out = Wn + dt * L0 + dt * dt / 6.0 * (Lt0 + 2.0 * Lt1);
 }
 
 /* ------------------------------------------------------------------ */

@@ -143,6 +143,21 @@ def test_time_marching_closed_forms(z):
     assert y2 == pytest.approx(y * (1 + z + z * z / 2), rel=1e-14)
 
 
+@pytest.mark.parametrize("z", [-0.9, -0.3, 0.05, 0.5, 1.2])
+def test_gradient_time_update_closed_forms(z):
+    """Gradients advance with the interface values they are summed from: for
+    an interface value y' = lam y (G = y, Gt = lam y at the start, Gt* = lam
+    times the mid-stage value), S2O4's midpoint rule gives the second-order
+    Taylor polynomial and S1O2's step the first-order one."""
+    lam, y, dt = 1.7, 1.3, z / 1.7
+    ys = oracle.grad_combine(oracle.S2O4, 0, dt, 0.0, y, lam * y)
+    assert ys == pytest.approx(y * (1 + z / 2), rel=1e-14)
+    y1 = oracle.grad_combine(oracle.S2O4, 1, dt, y, ys, lam * ys)
+    assert y1 == pytest.approx(y * (1 + z + z * z / 2), rel=1e-14)
+    y2 = oracle.grad_combine(oracle.S1O2, 0, dt, 0.0, y, lam * y)
+    assert y2 == pytest.approx(y * (1 + z), rel=1e-14)
+
+
 @pytest.mark.parametrize("mk", [lambda: I.cylinder_mesh(32, 16), lambda: I.sphere_mesh(6, 12, 6, 2, 2)])
 @pytest.mark.parametrize("low_flux", [oracle.LOW_KFVS, oracle.LOW_LF])
 def test_s1o2_residual_is_the_step_increment(mk, low_flux):
