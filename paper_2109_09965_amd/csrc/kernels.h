@@ -1448,18 +1448,26 @@ template <int G, typename T> __device__ __forceinline__ T group_sum(T v) {
 template <int D, typename R, bool FULL> __global__ __launch_bounds__(kBlock) void k_flux(Dev d, int want_grad) {
     using T = Dim<D>;
     constexpr int nv = T::nv, G = T::lanes, FS = T::fs;
+    constexpr int PL = rec_share<D>();
     const int t = xcd_block(blockIdx.x, gridDim.x) * int(blockDim.x) + threadIdx.x;
     const int fr_raw = t / G, q = t % G;
     const bool face_ok = fr_raw < d.NF;
     const int f = face_ok ? fr_raw : d.NF - 1;
-    if (!d.prm[d.fcase[f]].active) return;   // the face group leaves together
+    // Two rounds to memory before any arithmetic: everything indexed by the
+    // face, then everything indexed by what that holds (the Gauss points,
+    // both cells' record shares, the case), and only then the case's active
+    // flag, so no load waits on a branch.  A boundary face reads its own
+    // cell's share twice and drops the second.
+    const int cs = d.fcase[f];
     const int2 gr_ = d.gp_rng[f];
+    const int cL = d.fL[f], cR = d.fR[f];
+    const int fcode = d.fbc[f];
+    R sft[D];
+#pragma unroll
+    for (int a = 0; a < D; ++a) sft[a] = R(d.shift[size_t(a) * d.NF + f]);
     const int g0 = gr_.x, g1 = gr_.y;
     const bool gp_ok = face_ok && g0 + q < g1;
     const int g = gp_ok ? g0 + q : g0;
-    const int cs = d.fcase[f];
-    const DevParams &P = d.prm[cs];
-    const int cL = d.fL[f], cR = d.fR[f];
     R x[D], n[D];
 #pragma unroll
     for (int a = 0; a < D; ++a) {
@@ -1467,12 +1475,31 @@ template <int D, typename R, bool FULL> __global__ __launch_bounds__(kBlock) voi
         n[a] = R(d.gn[size_t(a) * d.NG + g]);
     }
     const R wJ = gp_ok ? R(d.gw[g]) : R(0.0);
+    const int case_on = d.prm[cs].active;
+    R shareL[PL], shareR[PL];
+    {
+        const R *ev = HoArrays<R>::ev(d);
+        const R *bl = ev + size_t(cL) * Rec<D>::er + q * PL;
+        const R *br = ev + size_t(cR >= 0 ? cR : cL) * Rec<D>::er + q * PL;
+#pragma unroll
+        for (int m = 0; m < PL; ++m) {
+            shareL[m] = bl[m];
+            shareR[m] = br[m];
+        }
+        // the shares and the flag are taken here, so the compiler cannot
+        // sink the shares' loads below the branch on the flag
+        asm volatile("" ::"v"(case_on));
+#pragma unroll
+        for (int m = 0; m < PL; ++m) asm volatile("" ::"v"(shareL[m]), "v"(shareR[m]));
+    }
+    if (!case_on) return;   // the face group leaves together
+    const DevParams &P = d.prm[cs];
     Frame<D, R> fr;
     fr.build(n);
     R Wc[nv], Gc[D][nv];
     bool ok = true;
-    const int bc = d.fbc[f] & 7;
-    const bool planar = (d.fbc[f] & kFacePlanar) != 0;
+    const int bc = fcode & 7;
+    const bool planar = (fcode & kFacePlanar) != 0;
     const bool full = FULL && P.flux_full != 0;
     bool did_full = false;
     R F0f[nv], Ftf[nv], Wtf[nv];
@@ -1485,7 +1512,7 @@ template <int D, typename R, bool FULL> __global__ __launch_bounds__(kBlock) voi
             for (int v = 0; v < nv; ++v) Gs[a][v] = R(0.0);
         {
             R Wg[nv];
-            recon_eval<D, R>(d, cL, q, x, Wg, Gs);
+            recon_eval_share<D, R>(shareL, x, Wg, Gs);
             fr.to_local(Wg, WL);
         }
         // the left gradient alone, for the full solution
@@ -1501,8 +1528,8 @@ template <int D, typename R, bool FULL> __global__ __launch_bounds__(kBlock) voi
             if (cR >= 0) {
                 R xr[D], WRg[nv];
 #pragma unroll
-                for (int a = 0; a < D; ++a) xr[a] = x[a] - R(d.shift[size_t(a) * d.NF + f]);
-                recon_eval<D, R>(d, cR, q, xr, WRg, Gs);
+                for (int a = 0; a < D; ++a) xr[a] = x[a] - sft[a];
+                recon_eval_share<D, R>(shareR, xr, WRg, Gs);
                 fr.to_local(WRg, WR);
             } else if (bc == 1 || bc == 3) {
                 // mirror: normal momentum reversed (slip), every momentum
@@ -1567,7 +1594,7 @@ template <int D, typename R, bool FULL> __global__ __launch_bounds__(kBlock) voi
 #pragma unroll
                             for (int v = 0; v < nv; ++v) GRg[a][v] = R(0.0);
 #pragma unroll
-                        for (int a = 0; a < D; ++a) xr[a] = x[a] - R(d.shift[size_t(a) * d.NF + f]);
+                        for (int a = 0; a < D; ++a) xr[a] = x[a] - sft[a];
                         recon_eval<D, R>(d, cR, q, xr, WRg, GRg);
                         fr.grad_to_local(GRg, GR);
                     } else if (bc == 1 || bc == 3) {
