@@ -251,6 +251,8 @@ DevParams dev_params(const cgks_params &p, int dim) {
     q.low_flux = p.low_flux;
     q.flux_full = p.flux_kind == CGKS_FLUX_FULL;
     q.weno_eps = p.weno_eps;
+    q.invN = 1.0 / (q.K + dim);
+    q.qcoef = (p.Pr != 1.0 && p.mu != 0.0) ? (1.0 / p.Pr - 1.0) * (-p.mu * p.gamma / (p.gamma - 1.0)) : 0.0;
     q.active = 1;
     return q;
 }
@@ -391,8 +393,7 @@ template <int D, typename S> cgks_status launch_lowlevel_s(cgks_batch *b, const 
     if (R1 != d.R1)
         HIP_TRY(hipMemcpyAsync(d.R1, R1, sizeof(double) * (D + 2) * b->NC, hipMemcpyDeviceToDevice, s));
     timed(b, CGKS_K_LOWFACE, s, [&] {
-        hipLaunchKernelGGL((k_low_face<D, S>), dim3(nblk(b->hwF, b->blk_face)), dim3(b->blk_face), 0, s, d,
-                           (int)LOW_SRC_W);
+        hipLaunchKernelGGL((k_low_face<D, S, LOW_SRC_W>), dim3(nblk(b->hwF, b->blk_face)), dim3(b->blk_face), 0, s, d);
     });
     timed(b, CGKS_K_LOWCELL, s, [&] {
         hipLaunchKernelGGL((k_low_cell<D, S, LOW_FORCE>), dim3(nblk(b->hwC * Dim<D>::sl, b->blk_lcell)),
@@ -403,8 +404,7 @@ template <int D, typename S> cgks_status launch_lowlevel_s(cgks_batch *b, const 
         // the first step starts at U = W: its set-up came with the forcing
         if (k > 0) {
             timed(b, CGKS_K_LOWFACE, s, [&] {
-                hipLaunchKernelGGL((k_low_face<D, S>), dim3(nblk(b->hwF, b->blk_face)), dim3(b->blk_face), 0, s, d,
-                                   (int)LOW_SRC_U_DU);
+                hipLaunchKernelGGL((k_low_face<D, S, LOW_SRC_U_DU>), dim3(nblk(b->hwF, b->blk_face)), dim3(b->blk_face), 0, s, d);
             });
             timed(b, CGKS_K_LOWCELL, s, [&] {
                 hipLaunchKernelGGL((k_low_cell<D, S, LOW_STEP>), dim3(nblk(b->hwC * Dim<D>::sl, b->blk_lcell)),
@@ -1122,13 +1122,11 @@ cgks_status cgks_residual(cgks_batch *b, int32_t kind, double *out, void *stream
     }
     if (kind == CGKS_RESIDUAL_LOW) {
         if (b->dim == 2) {
-            hipLaunchKernelGGL((k_low_face<2, double>), dim3(nblk(b->hwF)), dim3(kBlock), 0, s, b->dev,
-                               (int)LOW_SRC_W);
+            hipLaunchKernelGGL((k_low_face<2, double, LOW_SRC_W>), dim3(nblk(b->hwF)), dim3(kBlock), 0, s, b->dev);
             hipLaunchKernelGGL((k_low_cell<2, double, LOW_R0_OUT>), dim3(nblk(b->hwC * Dim<2>::sl)), dim3(kBlock), 0,
                                s, b->dev, out);
         } else {
-            hipLaunchKernelGGL((k_low_face<3, double>), dim3(nblk(b->hwF)), dim3(kBlock), 0, s, b->dev,
-                               (int)LOW_SRC_W);
+            hipLaunchKernelGGL((k_low_face<3, double, LOW_SRC_W>), dim3(nblk(b->hwF)), dim3(kBlock), 0, s, b->dev);
             hipLaunchKernelGGL((k_low_cell<3, double, LOW_R0_OUT>), dim3(nblk(b->hwC * Dim<3>::sl)), dim3(kBlock), 0,
                                s, b->dev, out);
         }
@@ -1328,15 +1326,14 @@ template <int D, typename R, typename S> static cgks_status autotune_t(cgks_batc
         hipLaunchKernelGGL((k_cell<D, R>), dim3(nblk(b->hwC * Dim<D>::sl, blk)), dim3(blk), 0, s, d, (int)MODE_R1);
     });
     b->blk_face = pick(blocks, 3, [&](int blk) {
-        hipLaunchKernelGGL((k_low_face<D, S>), dim3(nblk(b->hwF, blk)), dim3(blk), 0, s, d, (int)LOW_SRC_W);
+        hipLaunchKernelGGL((k_low_face<D, S, LOW_SRC_W>), dim3(nblk(b->hwF, blk)), dim3(blk), 0, s, d);
     });
     b->blk_lcell = pick(blocks, 3, [&](int blk) {
         hipLaunchKernelGGL((k_low_cell<D, S, LOW_R0_OUT>), dim3(nblk(b->hwC * Dim<D>::sl, blk)), dim3(blk), 0, s, d,
                            d.Sf);
     });
     // low-level work arrays from the current state, then the sweep chunk
-    hipLaunchKernelGGL((k_low_face<D, S>), dim3(nblk(b->hwF, b->blk_face)), dim3(b->blk_face), 0, s, d,
-                       (int)LOW_SRC_W);
+    hipLaunchKernelGGL((k_low_face<D, S, LOW_SRC_W>), dim3(nblk(b->hwF, b->blk_face)), dim3(b->blk_face), 0, s, d);
     hipLaunchKernelGGL((k_low_cell<D, S, LOW_FORCE>), dim3(nblk(b->hwC * Dim<D>::sl, b->blk_lcell)), dim3(b->blk_lcell),
                        0, s, d, (double *)nullptr);
     static const int chunks[3] = {64, 32, 16};

@@ -34,6 +34,10 @@ struct DevParams {
     int32_t flux_full; // 1: full time-dependent gas-kinetic solution (discontinuities)
     int32_t pad_;
     double weno_eps;   // > 0: nonlinear reconstruction weights with this epsilon
+    // per-case constants of the flux, set on the host: 1 / (K + D) and the
+    // Prandtl correction's factor (1/Pr - 1) (-mu gamma / (gamma - 1)) of the
+    // normal temperature derivative (0 when Pr = 1 or mu = 0)
+    double invN, qcoef;
 };
 static_assert(offsetof(DevParams, active) == 8, "gamma and active in the first 16 bytes");
 
@@ -270,11 +274,29 @@ template <int D, typename R> __device__ __forceinline__ void from_central(const 
 }
 
 // primitive variables of a local-frame state
+// 1/x from the hardware reciprocal estimate refined by Newton's iteration
+// for the reciprocal, r <- r + r (1 - x r) with a fused multiply-add (each
+// step doubles the correct bits; two steps in double, one in single).  For
+// the positive normal-range quantities of a state (density, pressure,
+// temperature); a non-physical state is discarded by its caller anyway.
+template <typename R> __device__ __forceinline__ R recip(R x);
+template <> __device__ __forceinline__ double recip<double>(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
+template <> __device__ __forceinline__ float recip<float>(float x) {
+    const float r = __builtin_amdgcn_rcpf(x);
+    return fmaf(r, fmaf(-x, r, 1.0f), r);
+}
+
 template <int D, typename R> struct Prim {
-    R rho, U[D], p, lam;
+    R rho, U[D], p, lam, ir, th;   // ir = 1 / rho, th = p / rho = 1 / (2 lam)
     __device__ __forceinline__ void from(const R *W, R gamma) {
         rho = W[0];
-        const R ir = R(1.0) / rho;
+        ir = recip<R>(rho);
         R ke = 0;
 #pragma unroll
         for (int a = 0; a < D; ++a) {
@@ -282,7 +304,8 @@ template <int D, typename R> struct Prim {
             ke += U[a] * U[a];
         }
         p = (gamma - R(1.0)) * (W[D + 1] - R(0.5) * rho * ke);
-        lam = rho / (R(2.0) * p);
+        th = p * ir;
+        lam = R(0.5) * recip<R>(th);
     }
 };
 
@@ -310,7 +333,7 @@ template <int D, typename R> __device__ bool gks_flux(const R *Wc, const R Gc[D]
     // Fourier heat flux of the interface state along the normal (R = 1,
     // T = p / rho), used for the Prandtl-number correction
     R qcorr = R(0.0);
-    if (R(P.Pr) != R(1.0) && R(P.mu) != R(0.0)) {
+    if (P.qcoef != 0.0) {
         R ke = 0, ked = 0;
 #pragma unroll
         for (int k = 0; k < D; ++k) {
@@ -318,13 +341,13 @@ template <int D, typename R> __device__ bool gks_flux(const R *Wc, const R Gc[D]
             ked += q.U[k] * Gc[0][1 + k];
         }
         const R pn = (R(P.gamma) - R(1.0)) * (Gc[0][nv - 1] - ked + R(0.5) * ke * Gc[0][0]);
-        const R Tn = (pn * q.rho - q.p * Gc[0][0]) / (q.rho * q.rho);
-        qcorr = (R(1.0) / R(P.Pr) - R(1.0)) * (-R(P.mu) * R(P.gamma) / (R(P.gamma) - R(1.0)) * Tn);
+        const R Tn = (pn * q.rho - q.p * Gc[0][0]) * (q.ir * q.ir);
+        qcorr = R(P.qcoef) * Tn;
     }
-    const R ir = R(1.0) / q.rho;
-    const R th = q.p * ir;                      // theta = 1 / (2 lam)
-    const R tau = R(P.mu) / q.p;
-    const R c1 = R(2.0) / N, c2 = R(0.5) * th * (N + R(2.0));
+    const R ir = q.ir;
+    const R th = q.th;                          // theta = 1 / (2 lam)
+    const R tau = R(P.mu) * (R(2.0) * q.lam * ir);   // mu / p
+    const R c1 = R(2.0) * R(P.invN), c2 = R(0.5) * th * (N + R(2.0));
     R u2h = 0;
 #pragma unroll
     for (int k = 0; k < D; ++k) u2h += q.U[k] * q.U[k];
@@ -416,8 +439,8 @@ template <typename R> __device__ __forceinline__ R one_plus_erf(R y) {
 }
 
 // half-range moments <u^k>_{u >< 0}, k = 0..3
-template <typename R> __device__ __forceinline__ void half_moments(R U, R lam, R sgn, R *m) {
-    const R hl = R(0.5) / lam;   // 1/(2 lam)
+template <typename R> __device__ __forceinline__ void half_moments(R U, R lam, R th, R sgn, R *m) {
+    const R hl = th;   // 1/(2 lam)
     m[0] = R(0.5) * one_plus_erf<R>(sgn * sqrt(lam) * U);
     m[1] = U * m[0] + sgn * R(0.5) * exp(-lam * U * U) * rsqrt(R(M_PI) * lam);
     m[2] = U * m[1] + hl * m[0];
@@ -432,11 +455,11 @@ template <int D, typename R> __device__ __forceinline__ bool half_side(const R *
     q.from(W, R(P.gamma));
     if (!(q.rho > R(0.0)) || !(q.p > R(0.0))) return false;
     R m[4];
-    half_moments<R>(q.U[0], q.lam, sgn, m);
+    half_moments<R>(q.U[0], q.lam, q.th, sgn, m);
     R ut2 = 0;
 #pragma unroll
     for (int a = 1; a < D; ++a) ut2 += q.U[a] * q.U[a];
-    const R rest = ut2 + (R(P.K) + D - 1) * R(0.5) / q.lam;   // <v^2> + <w^2> + <xi^2>
+    const R rest = ut2 + (R(P.K) + D - 1) * q.th;   // <v^2> + <w^2> + <xi^2>
     if (Wacc) {
         Wacc[0] += q.rho * m[0];
         Wacc[1] += q.rho * m[1];
@@ -515,8 +538,8 @@ __device__ bool half_side_full(const R *W, const R G[D][D + 2], const DevParams 
     Prim<D, R> q;
     q.from(W, R(P.gamma));
     if (!(q.rho > R(0.0)) || !(q.p > R(0.0))) return false;
-    const R N = R(P.K) + D, ir = R(1.0) / q.rho, th = q.p * ir;
-    const R c1 = R(2.0) / N, c2 = R(0.5) * th * (N + R(2.0));
+    const R N = R(P.K) + D, ir = q.ir, th = q.th;
+    const R c1 = R(2.0) * R(P.invN), c2 = R(0.5) * th * (N + R(2.0));
     R u2h = 0;
 #pragma unroll
     for (int k = 0; k < D; ++k) u2h += q.U[k] * q.U[k];
@@ -545,7 +568,7 @@ __device__ bool half_side_full(const R *W, const R G[D][D + 2], const DevParams 
     central_to_raw<D, R>(bc, q.U, u2h, th, N, A);
     // moments: u over the half space, v, w over the whole line, Z
     R Hu[7], Mv[6], Mw[6], MZ[3];
-    const R var = R(0.5) / q.lam;   // variance of each velocity component: 1 / (2 lam)
+    const R var = q.th;   // variance of each velocity component: 1 / (2 lam)
     Hu[0] = R(0.5) * one_plus_erf<R>(sgn * sqrt(q.lam) * q.U[0]);
     Hu[1] = q.U[0] * Hu[0] + sgn * R(0.5) * exp(-q.lam * q.U[0] * q.U[0]) * rsqrt(R(M_PI) * q.lam);
 #pragma unroll
@@ -619,8 +642,8 @@ __device__ bool equilibrium_terms(const R *Wc, const R Gc[D][D + 2], const DevPa
     Prim<D, R> q;
     q.from(Wc, R(P.gamma));
     if (!(q.rho > R(0.0)) || !(q.p > R(0.0))) return false;
-    const R N = R(P.K) + D, ir = R(1.0) / q.rho, th = q.p * ir;
-    const R c1 = R(2.0) / N, c2 = R(0.5) * th * (N + R(2.0));
+    const R N = R(P.K) + D, ir = q.ir, th = q.th;
+    const R c1 = R(2.0) * R(P.invN), c2 = R(0.5) * th * (N + R(2.0));
     R u2h = 0;
 #pragma unroll
     for (int k = 0; k < D; ++k) u2h += q.U[k] * q.U[k];
@@ -811,8 +834,9 @@ template <int D> __device__ __forceinline__ void euler_flux(const double *U, con
         ke += U[1 + a] * U[1 + a];
         un += U[1 + a] * n[a];
     }
-    un /= rho;
-    const double p = (gamma - 1.0) * (U[nv - 1] - 0.5 * ke / rho);
+    const double ir = recip<double>(rho);
+    un *= ir;
+    const double p = (gamma - 1.0) * (U[nv - 1] - 0.5 * ke * ir);
     F[0] = rho * un;
 #pragma unroll
     for (int a = 0; a < D; ++a) F[1 + a] = U[1 + a] * un + p * n[a];
@@ -828,12 +852,12 @@ template <int D> __device__ __forceinline__ void euler_flux(const double *U, con
 template <int D, typename S>
 __device__ __forceinline__ void euler_dflux(const S *U, const S *dU, const S *A, S gamma, S *dF) {
     constexpr int nv = D + 2;
-    const S rho = U[0], rho1 = U[0] + dU[0];
+    const S ir = recip<S>(U[0]), ir1 = recip<S>(U[0] + dU[0]);
     S u[D], du[D], un1 = S(0), dun = S(0), mu = S(0), dmu = S(0), dmA = S(0);
 #pragma unroll
     for (int a = 0; a < D; ++a) {
-        u[a] = U[1 + a] / rho;
-        du[a] = (dU[1 + a] - u[a] * dU[0]) / rho1;
+        u[a] = U[1 + a] * ir;
+        du[a] = (dU[1 + a] - u[a] * dU[0]) * ir1;
         un1 += (u[a] + du[a]) * A[a];
         dun += du[a] * A[a];
         mu += U[1 + a] * u[a];
@@ -871,16 +895,16 @@ template <int D> struct LowRec<D, float> {
 // ---------------------------------------------------------------------
 template <int D> __device__ __forceinline__ double state_dt(const double *U, double h, double cfl, const DevParams &P) {
     constexpr int nv = D + 2;
-    const double rho = U[0];
+    const double rho = U[0], ir = recip<double>(rho);
     double ke = 0;
 #pragma unroll
     for (int a = 0; a < D; ++a) {
-        const double u = U[1 + a] / rho;
+        const double u = U[1 + a] * ir;
         ke += u * u;
     }
     const double p = (P.gamma - 1.0) * (U[nv - 1] - 0.5 * rho * ke);
-    const double c = sqrt(P.gamma * p / rho);
-    return cfl * h / (sqrt(ke) + c + 2.0 * P.mu / rho / h);
+    const double c = sqrt(P.gamma * p * ir);
+    return cfl * h * recip<double>(sqrt(ke) + c + 2.0 * P.mu * ir * recip<double>(h));
 }
 
 // The face, cell and sweep kernels take their block size from the launch
@@ -1633,10 +1657,14 @@ template <int D, typename R, bool FULL> __global__ __launch_bounds__(kBlock) voi
     }
     R *dst = HoArrays<R>::fsum(d) + size_t(f) * FS;
     const bool writer = face_ok && q == 0;
+    // a wave whose faces are all planar reduces one Gauss-Green group per
+    // quantity instead of D (uniform branch)
+    const bool wave_planar = __all(planar);
     R o[nv];
     // Gauss-Green sums of the interface state at t = 0 (a planar face: the
-    // plain sum in the first group and the normal after it; every face runs
-    // the same D reductions, a planar one with weights (1, 0, 0))
+    // plain sum in the first group and the normal after it; in a wave with
+    // any warped face every face runs the same D reductions, a planar one
+    // with weights (1, 0, 0))
     if (want_grad) {
         if (writer && planar) {
 #pragma unroll
@@ -1646,10 +1674,15 @@ template <int D, typename R, bool FULL> __global__ __launch_bounds__(kBlock) voi
 #pragma unroll
         for (int v = 0; v < nv; ++v) {
             const R w = ok ? wJ * o[v] : R(0.0);
+            if (wave_planar) {
+                const R sum = group_sum<G, R>(w);
+                if (writer) dst[T::fg + v] = sum;
+            } else {
 #pragma unroll
-            for (int a = 0; a < D; ++a) {
-                const R sum = group_sum<G, R>(planar ? (a == 0 ? w : R(0.0)) : w * n[a]);
-                if (writer && (!planar || a == 0)) dst[T::fg + a * 2 * nv + v] = sum;
+                for (int a = 0; a < D; ++a) {
+                    const R sum = group_sum<G, R>(planar ? (a == 0 ? w : R(0.0)) : w * n[a]);
+                    if (writer && (!planar || a == 0)) dst[T::fg + a * 2 * nv + v] = sum;
+                }
             }
         }
     }
@@ -1694,10 +1727,15 @@ template <int D, typename R, bool FULL> __global__ __launch_bounds__(kBlock) voi
 #pragma unroll
         for (int v = 0; v < nv; ++v) {
             const R w = wJ * o[v];
+            if (wave_planar) {
+                const R sum = group_sum<G, R>(w);
+                if (writer) dst[T::fg + nv + v] = sum;
+            } else {
 #pragma unroll
-            for (int a = 0; a < D; ++a) {
-                const R sum = group_sum<G, R>(planar ? (a == 0 ? w : R(0.0)) : w * n[a]);
-                if (writer && (!planar || a == 0)) dst[T::fg + a * 2 * nv + nv + v] = sum;
+                for (int a = 0; a < D; ++a) {
+                    const R sum = group_sum<G, R>(planar ? (a == 0 ? w : R(0.0)) : w * n[a]);
+                    if (writer && (!planar || a == 0)) dst[T::fg + a * 2 * nv + nv + v] = sum;
+                }
             }
         }
     }
@@ -1777,7 +1815,7 @@ template <int D, typename R> __global__ __launch_bounds__(kBlock) void k_cell(De
     }
     if (!ok || !mine) return;
     const double dt = d.dt[cs];
-    const double V = d.vol[i];
+    const double iV = recip<double>(d.vol[i]);
     double *si = d.st + size_t(i) * Rec<D>::sr;
     if (q == 0) {
 #pragma unroll
@@ -1786,7 +1824,7 @@ template <int D, typename R> __global__ __launch_bounds__(kBlock) void k_cell(De
                 st_nt(-(acc[v] + 0.5 * dt * acc[nv + v]), d.R1 + size_t(v) * NC + i);
                 continue;
             }
-            const double L = -acc[v] / V, Lt = -acc[nv + v] / V;
+            const double L = -acc[v] * iV, Lt = -acc[nv + v] * iV;
             if (mode == MODE_STAGE0) {
                 const double w = si[v];
                 st_nt(w, d.Wn + size_t(v) * NC + i);
@@ -1804,7 +1842,7 @@ template <int D, typename R> __global__ __launch_bounds__(kBlock) void k_cell(De
 #pragma unroll
     for (int v = 0; v < nv; ++v) {
         const size_t k = size_t(a * nv + v) * NC + i;
-        const double G = acc[v] / V, Gt = acc[nv + v] / V;
+        const double G = acc[v] * iV, Gt = acc[nv + v] * iV;
         if (mode == MODE_STAGE0) {
             st_nt(G, d.G0 + k);
             si[nv + a * nv + v] = P.scheme == 0 ? G + 0.5 * dt * Gt : G + dt * Gt;
@@ -1821,24 +1859,24 @@ template <int D, typename R> __global__ __launch_bounds__(kBlock) void k_cell(De
 template <int D> __device__ __forceinline__ double side_radius(const double *U, const double *n, double Sf, double V,
                                                                const DevParams &P) {
     constexpr int nv = D + 2;
-    const double rho = U[0];
+    const double rho = U[0], ir = recip<double>(rho);
     double un = 0, ke = 0;
 #pragma unroll
     for (int a = 0; a < D; ++a) {
-        const double u = U[1 + a] / rho;
+        const double u = U[1 + a] * ir;
         un += u * n[a];
         ke += u * u;
     }
     const double p = (P.gamma - 1.0) * (U[nv - 1] - 0.5 * rho * ke);
-    return fabs(un) + sqrt(P.gamma * p / rho) + 2.0 * P.mu / rho * Sf / V;
+    return fabs(un) + sqrt(P.gamma * p * ir) + 2.0 * P.mu * ir * Sf * recip<double>(V);
 }
 
 enum { LOW_SRC_W = 0, LOW_SRC_U_DU = 2 };
 
 // state of cell i: W from the state records, or the low-level U + dU
-template <int D, typename S> __device__ __forceinline__ void low_state(const Dev &d, int src, int i, double *out) {
+template <int D, typename S, int src> __device__ __forceinline__ void low_state(const Dev &d, int i, double *out) {
     constexpr int nv = D + 2;
-    if (src == LOW_SRC_W) {
+    if constexpr (src == LOW_SRC_W) {
 #pragma unroll
         for (int v = 0; v < nv; ++v) out[v] = d.st[size_t(i) * Rec<D>::sr + v];
     } else {
@@ -1851,29 +1889,42 @@ template <int D, typename S> __device__ __forceinline__ void low_state(const Dev
 
 // lowf[f] = S_f F(U_L, U_R; n_f), F the case's first-order flux (KFVS or
 // Lax-Friedrichs); swp[f][D] = S_f lam_f.
-template <int D, typename S> __global__ __launch_bounds__(kBlock) void k_low_face(Dev d, int src) {
-    constexpr int nv = D + 2;
+template <int D, typename S, int SRC> __global__ __launch_bounds__(kBlock) void k_low_face(Dev d) {
+    constexpr int nv = D + 2, src = SRC;
     const int f = xcd_block(blockIdx.x, gridDim.x) * int(blockDim.x) + threadIdx.x;
     if (f >= d.NF) return;
+    // Two rounds to memory before any arithmetic (as in the flux): the
+    // face's own data, then both cells' states and volumes with the case's
+    // active flag, and only then the branch on the flag.  A boundary face
+    // reads its own cell twice and drops the second.
     const int cs = d.fcase[f];
-    const DevParams &P = d.prm[cs];
-    if (!P.active) return;
     const int L = d.fL[f], R = d.fR[f];
-    const double Sf = d.S[f], iS = 1.0 / Sf;
+    const double Sf = d.S[f];
+    double av[D];
+#pragma unroll
+    for (int a = 0; a < D; ++a) av[a] = d.avec[size_t(a) * d.NF + f];
+    const int case_on = d.prm[cs].active;
+    double UL[nv], UR[nv];
+    low_state<D, S, src>(d, L, UL);
+    low_state<D, S, src>(d, R >= 0 ? R : L, UR);
+    const double VL = d.vol[L], VR = d.vol[R >= 0 ? R : L];
+    asm volatile("" ::"v"(case_on), "v"(VL), "v"(VR));
+#pragma unroll
+    for (int v = 0; v < nv; ++v) asm volatile("" ::"v"(UL[v]), "v"(UR[v]));
+    if (!case_on) return;
+    const DevParams &P = d.prm[cs];
+    const double iS = recip<double>(Sf);
     double n[D];
 #pragma unroll
-    for (int a = 0; a < D; ++a) n[a] = d.avec[size_t(a) * d.NF + f] * iS;
+    for (int a = 0; a < D; ++a) n[a] = av[a] * iS;
     Frame<D, double> fr;
     fr.build(n);
-    double UL[nv], Ul[nv], Ur[nv];
-    low_state<D, S>(d, src, L, UL);
+    double Ul[nv], Ur[nv];
     fr.to_local(UL, Ul);
-    double lam = side_radius<D>(UL, n, Sf, d.vol[L], P);
+    double lam = side_radius<D>(UL, n, Sf, VL, P);
     if (R >= 0) {
-        double UR[nv];
-        low_state<D, S>(d, src, R, UR);
         fr.to_local(UR, Ur);
-        lam = fmax(lam, side_radius<D>(UR, n, Sf, d.vol[R], P));
+        lam = fmax(lam, side_radius<D>(UR, n, Sf, VR, P));
     } else {
         const int bc = d.fbc[f] & 7;
 #pragma unroll
@@ -2000,7 +2051,7 @@ template <int D, typename S, int MODE> __global__ __launch_bounds__(kBlock) void
                 dUi[v] = S(0);
             }
     }
-    if (q == 0) d.D[i] = Vi / state_dt<D>(u, hi, P.cfl_low, P) + 0.5 * lS;
+    if (q == 0) d.D[i] = Vi * recip<double>(state_dt<D>(u, hi, P.cfl_low, P)) + 0.5 * lS;
 }
 
 // one colour class: blocks listed in (start, count) tables.  With A = s S_f n_f
@@ -2064,9 +2115,10 @@ __global__ __launch_bounds__(kBlock) void k_sweep(Dev d, const int32_t *blk_star
         for (int v = 0; v < nv; ++v) acc[v] = group_sum<SL, S>(acc[v]);
         if (!ok || !active) return;
         double *dUi = LowRec<D, S>::dU(d, i);
+        const double iD = recip<double>(Di);
 #pragma unroll
         for (int v = 0; v < nv; ++v)
-            if (v % SL == q) dUi[v] = ((v < SL ? rhs_q : rhs_last) - acc[v]) / Di;
+            if (v % SL == q) dUi[v] = ((v < SL ? rhs_q : rhs_last) - acc[v]) * iD;
     } else {
         // FP32 (lighter records): slot by slot, the loads guarded by the
         // slot's test, faster here than addressing everything up front
@@ -2098,11 +2150,11 @@ __global__ __launch_bounds__(kBlock) void k_sweep(Dev d, const int32_t *blk_star
 #pragma unroll
         for (int v = 0; v < nv; ++v) acc[v] = group_sum<SL, S>(acc[v]);
         if (!ok || !P.active) return;
-        const double Di = d.D[i];
+        const double iD = recip<double>(d.D[i]);
         S *dUi = LowRec<D, S>::dU(d, i);
 #pragma unroll
         for (int v = 0; v < nv; ++v)
-            if (v % SL == q) dUi[v] = S((d.RHS[size_t(v) * NC + i] - double(acc[v])) / Di);
+            if (v % SL == q) dUi[v] = S((d.RHS[size_t(v) * NC + i] - double(acc[v])) * iD);
     }
 }
 
