@@ -32,22 +32,22 @@ FP32_PACKED_PEAK_TFLOPS = 157.3
 # (FMA = 2), from the VALU instruction counters of one launch on the
 # sphere workload (SQ_INSTS_VALU_{FMA,MUL,ADD,TRANS}_F64 resp. _F32, x 64
 # lanes), charged to the lanes that carry a Gauss point.
-FLUX_FLOP_PER_GP = {"fp64": 1703.0, "mixed32": 1597.0, "mixed32_r64": (2 * 1597.0 + 1703.0) / 3.0}
+FLUX_FLOP_PER_GP = {"fp64": 1541.7, "mixed32": 1412.7, "mixed32_r64": (2 * 1412.7 + 1541.7) / 3.0}
 
 # HBM bytes per launch from rocprofv3 FETCH_SIZE (x 2.0) and WRITE_SIZE
 # (x 1.0) on the sphere workload, each factor from a plain device copy of
 # known size.  Valid only for the kernel source they were taken on (its
 # SHA-256); any other source reports null.
-PROFILED_KERNELS_SHA256 = "0e1cf00d40d686405480acd3b2ae92c7458880b7596f8ce29bceb7cfa6f9220f"
+PROFILED_KERNELS_SHA256 = "169ec5ea73cd5d94d909d6823bc44c01648de16b55c5de90afcf6612f89ef428"
 PROFILED_TRAFFIC = {           # (kernel kind, precision) -> bytes per launch
-    ("dt", "fp64"): 79177625.2, ("dt", "mixed32"): 79177457.6,
-    ("recon", "fp64"): 679239381.7, ("recon", "mixed32"): 633410233.7,   # with the boundary ghost pre-pass
-    ("flux", "fp64"): 732863033.1, ("flux", "mixed32"): 495873789.4,
-    ("cell", "fp64"): 708539775.6, ("cell", "mixed32"): 397115198.0,
-    ("low_face", "fp64"): 183695890.9, ("low_face", "mixed32"): 175766193.2,
-    ("low_cell", "fp64"): 256368229.1, ("low_cell", "mixed32"): 242041112.0,  # 1 forcing + 5 step launches
-    ("sweep", "fp64"): 56982947.4, ("sweep", "mixed32"): 42808721.3,          # average over colour classes
-    ("prolong", "fp64"): 173888783.6, ("prolong", "mixed32"): 162011321.5,
+    ("dt", "fp64"): 79170784.0, ("dt", "mixed32"): 79170726.1,
+    ("recon", "fp64"): 679440658.3, ("recon", "mixed32"): 632559045.1,   # with the boundary ghost pre-pass
+    ("flux", "fp64"): 744805949.5, ("flux", "mixed32"): 500148120.9,
+    ("cell", "fp64"): 690207294.0, ("cell", "mixed32"): 393243260.4,
+    ("low_face", "fp64"): 183513339.9, ("low_face", "mixed32"): 175464507.9,
+    ("low_cell", "fp64"): 256217591.4, ("low_cell", "mixed32"): 242113086.5,  # 1 forcing + 5 step launches
+    ("sweep", "fp64"): 56982903.8, ("sweep", "mixed32"): 42801343.9,          # average over colour classes
+    ("prolong", "fp64"): 173073635.0, ("prolong", "mixed32"): 162951544.4,
 }
 
 
@@ -132,10 +132,12 @@ def algorithmic_bytes(mesh, lm, rbytes, sbytes=8):
     r1 = cell_common + NF * R * 2 * nv + NC * 8 * nv
     out["cell"] = ((st0 + st1 + r1) / 3.0, 3)
     own, nb = mesh["face_owner"], mesh["face_neigh"]
-    nint = NF - NB
-    lf_common = NF * (4 * 3 + 8 + 8 * d) + 8 * NF * (nv + 1)      # indices, S, avec; lowf, S lam writes
-    lf_force = lf_common + 8 * nv * (NF + nint)                   # W of both sides
-    lf_step = lf_common + (8 + sbytes) * nv * (NF + nint)         # U and dU of both sides
+    # indices, S, avec; lowf, S lam writes; the cells' volumes; each cell's
+    # state once (a face reads both of its cells, every cell is read by all
+    # its faces: counted once by definition)
+    lf_common = NF * (4 * 3 + 8 + 8 * d) + 8 * NF * (nv + 1) + 8 * NC
+    lf_force = lf_common + 8 * nv * NC                            # W
+    lf_step = lf_common + (8 + sbytes) * nv * NC                  # U and dU
     out["low_face"] = ((lf_force + 5 * lf_step) / 6.0, 6)         # the first step reuses the forcing's
     lc_common = NC * (8 * ns + 4) + NF * 8 * (nv + 1)
     lc_force = lc_common + NC * (8 * (5 * nv + 2 + 1) + sbytes * nv)   # R1, W; Sf, U, RHS; vol, h; D; dU

@@ -3,14 +3,17 @@
 Requests (a prepared mesh, its free stream and gas parameters, a
 tolerance) arrive over time.  The server keeps one pool per dimension, each
 with a fixed capacity carved out of an HBM budget, and each on its own HIP
-stream so the two pools' work overlaps on the device.  In every epoch it
-admits waiting requests in arrival order while their mesh fits into free
-ranges (the pool's HBM footprint), replays a captured graph of
-``epoch_cycles`` cycles of every admitted case, reads the per-case Res
-history, and retires cases that converged (or stalled at their precision's
-floor, or hit the cycle cap): their state is downloaded to the host and
-their ranges are released for the next admissions.  A case gives bitwise the
-same state in the mix as alone after the same number of cycles.
+stream so the two pools' work overlaps on the device.  Each pool runs its
+own sequence of epochs: whenever its previous epoch has finished (an event
+on its stream), the server reads that epoch's per-case Res history, retires
+cases that converged (or stalled at their precision's floor, or hit the
+cycle cap: their state is downloaded to the host and their ranges
+released), admits waiting requests of its dimension in arrival order while
+their mesh fits into free ranges (the pool's HBM footprint), and replays a
+captured graph of ``epoch_cycles`` cycles of every admitted case.  No pool
+waits for another's epoch, so host work for one pool overlaps the other's
+cycles.  A case gives bitwise the same state in the mix as alone after the
+same number of cycles.
 
 Time-to-steady runs from a request's arrival to its converged state on the
 host; queue wait (arrival to admission) and service (admission to done) are
@@ -127,6 +130,7 @@ class Server:
         self.live = {k: {} for k in self.pools}       # slot -> Request
         self.dirty = {k: True for k in self.pools}    # membership changed: capture again
         self.to_finish = []                           # promoted cases waiting for an FP64 slot
+        self.inflight = {}                            # pool -> (event, Res history, cell-updates) of its epoch
 
     def _admit(self, key, req, W, dW):
         dim = key[1]
@@ -150,26 +154,29 @@ class Server:
         req.admitted, req.status = now, "running"
         return True
 
-    def step(self):
-        """One epoch of every non-empty pool; returns cell-updates done."""
+    def launch(self, key):
+        """Start one epoch of the pool on its stream (capturing its graph
+        again if its membership changed)."""
         import torch
-        work = 0
-        hist = {}
-        for key, pool in self.pools.items():
-            if not self.live[key]:
-                continue
-            with torch.cuda.stream(self.streams[key]):
-                if self.dirty[key]:
-                    pool.graph_create(self.epoch)
-                    self.dirty[key] = False
-                h = torch.zeros(self.epoch * pool.n_case, dtype=torch.float64, device="cuda")
-                pool.graph_launch(h)
-                hist[key] = h
-            work += self.epoch * sum(r.mesh.n_cell for r in self.live[key].values())
-        for key, h in hist.items():
-            self.streams[key].synchronize()
-            hist[key] = h.cpu().numpy().reshape(self.epoch, -1)
-        return work, hist
+        pool, st = self.pools[key], self.streams[key]
+        with torch.cuda.stream(st):
+            if self.dirty[key]:
+                pool.graph_create(self.epoch)
+                self.dirty[key] = False
+            h = torch.zeros(self.epoch * pool.n_case, dtype=torch.float64, device="cuda")
+            pool.graph_launch(h)
+            ev = torch.cuda.Event()
+            ev.record(st)
+        work = self.epoch * sum(r.mesh.n_cell for r in self.live[key].values())
+        self.inflight[key] = (ev, h, work)
+
+    def collect(self, key, now_fn):
+        """Wait for the pool's epoch, retire its finished cases; returns
+        (cell-updates of the epoch, requests finished)."""
+        ev, h, work = self.inflight.pop(key)
+        ev.synchronize()
+        H = h.cpu().numpy().reshape(self.epoch, -1)
+        return work, self.retire({key: H}, now_fn)
 
     def retire(self, hist, now_fn):
         done = []
@@ -227,9 +234,23 @@ class Server:
             while nxt < len(reqs) and reqs[nxt].arrival <= t:
                 waiting.append(reqs[nxt])
                 nxt += 1
-            # promoted cases first (they hold no memory while they wait)
+            # pools whose epoch has finished: retire
+            progressed = False
+            for key in list(self.inflight):
+                if self.inflight[key][0].query():
+                    w, done = self.collect(key, now)
+                    work += w
+                    finished += done
+                    progressed = True
+                    if log:
+                        for r in done:
+                            log(r)
+            # admissions go into pools between their epochs only; promoted
+            # cases first (they hold no memory while they wait)
             for req in list(self.to_finish):
                 key = ("fp64", req.mesh.dim)
+                if key in self.inflight:
+                    continue
                 if self._admit(key, req, req.W, req.dW):
                     self.to_finish.remove(req)
                 elif not self.live[key]:
@@ -244,6 +265,9 @@ class Server:
                 d = req.mesh.dim
                 if d in blocked:
                     continue
+                if ("run", d) in self.inflight:
+                    blocked.add(d)
+                    continue
                 if self.try_admit(req, t):
                     waiting.remove(req)
                 elif not self.live[("run", d)]:
@@ -253,17 +277,17 @@ class Server:
                     finished.append(req)
                 else:
                     blocked.add(d)
-            if not any(self.live.values()):
+            # every idle pool with cases starts its next epoch
+            for key in self.pools:
+                if key not in self.inflight and self.live[key]:
+                    self.launch(key)
+                    progressed = True
+            if not self.inflight:
                 if nxt < len(reqs) and not self.to_finish:
                     time.sleep(max(0.0, min(0.01, reqs[nxt].arrival - now())))
                 continue
-            w, hist = self.step()
-            work += w
-            done = self.retire(hist, now)
-            finished += done
-            if log:
-                for r in done:
-                    log(r)
+            if not progressed:
+                time.sleep(2e-4)   # poll the running epochs
         makespan = now()
         return summarize(finished, work, makespan)
 
