@@ -48,6 +48,10 @@ PROFILED_TRAFFIC = {           # (kernel kind, precision) -> bytes per launch
     ("low_cell", "fp64"): 256217591.4, ("low_cell", "mixed32"): 242113086.5,  # 1 forcing + 5 step launches
     ("sweep", "fp64"): 56982903.8, ("sweep", "mixed32"): 42801343.9,          # average over colour classes
     ("prolong", "fp64"): 173073635.0, ("prolong", "mixed32"): 162951544.4,
+    ("dt", "mixed32_r64"): 79170727.6, ("recon", "mixed32_r64"): 647752913.3,
+    ("flux", "mixed32_r64"): 560686092.2, ("cell", "mixed32_r64"): 475542537.1,
+    ("low_face", "mixed32_r64"): 175485393.3, ("low_cell", "mixed32_r64"): 242069125.1,
+    ("sweep", "mixed32_r64"): 42752422.0, ("prolong", "mixed32_r64"): 162176804.6,
 }
 
 
