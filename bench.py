@@ -427,7 +427,23 @@ def main():
                     help="cells per tile of the library cell order (0 = library default)")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
                     help="only run 5 device-to-device copies of MIB MiB (counter calibration)")
+    ap.add_argument("--gather-calib", type=int, default=0, metavar="MIB",
+                    help="only run 5 gathers of MIB MiB in whole 128-byte rows, random row order (counter calibration)")
     args = ap.parse_args()
+    if args.gather_calib:
+        # every 128-byte row of the source read once, in a seeded random
+        # order, plus the 8-byte row indices; the output written in order
+        import torch
+        rows = args.gather_calib * (1 << 20) // 128
+        g = torch.Generator(device="cpu").manual_seed(2109)
+        perm = torch.randperm(rows, generator=g).cuda()
+        src = torch.ones(rows, 16, dtype=torch.float64, device="cuda")
+        out = torch.empty_like(src)
+        for _ in range(5):
+            torch.index_select(src, 0, perm, out=out)
+        torch.cuda.synchronize()
+        print(json.dumps(dict(gather_bytes_each=rows * 128, index_bytes_each=rows * 8, gathers=5)))
+        return
     if args.copy_calib:
         import torch
         n = args.copy_calib * (1 << 20) // 8
