@@ -1467,6 +1467,27 @@ template <int G, typename T> __device__ __forceinline__ T group_sum(T v) {
     return v;
 }
 
+// N consecutive values of a face record that every lane of the face's
+// group holds (after group_sum), spread over the group: lane q stores the
+// values q, q + G, ..., so one store instruction writes G adjacent values
+// of each face instead of one value from one lane
+// (val(j) gives value j; it is called for a row of G values at a time so
+// that only one row of sums is live)
+template <int G, int N, typename R, typename Val>
+__device__ __forceinline__ void group_store(R *dst, int q, bool on, Val val) {
+#pragma unroll
+    for (int r = 0; r < N; r += G) {
+        R v = val(r);
+#pragma unroll
+        for (int k = 1; k < G; ++k)
+            if (r + k < N) {
+                const R u = val(r + k);
+                v = q == k ? u : v;
+            }
+        if (on && r + q < N) dst[r + q] = v;
+    }
+}
+
 // One group of Dim<D>::lanes threads per face, one thread per Gauss point;
 // a lane without a Gauss point (triangles in 3-D) repeats the first point
 // with weight 0, so every lane runs the same code.  The face sums
@@ -1671,30 +1692,31 @@ template <int D, typename R, bool FULL> __global__ __launch_bounds__(kBlock) voi
     // quantity instead of D (uniform branch)
     const bool wave_planar = __all(planar);
     R o[nv];
-    // Gauss-Green sums of the interface state at t = 0 (a planar face: the
-    // plain sum in the first group and the normal after it; in a wave with
-    // any warped face every face runs the same D reductions, a planar one
-    // with weights (1, 0, 0))
+    // Gauss-Green sums of the interface state (at t = 0, then its time
+    // derivative): a planar face has the plain sum in the first group and
+    // the normal after it; in a wave with any warped face every face runs
+    // the same D reductions, a planar one with weights (1, 0, 0)
+    auto gauss_green = [&](const R *Wl, int off) {
+        fr.to_global(Wl, o);
+        R w[nv];
+#pragma unroll
+        for (int v = 0; v < nv; ++v) w[v] = wJ * o[v];
+        if (wave_planar) {
+            group_store<G, nv>(dst + T::fg + off, q, face_ok, [&](int v) { return group_sum<G, R>(w[v]); });
+        } else {
+#pragma unroll
+            for (int a = 0; a < D; ++a)
+                group_store<G, nv>(dst + T::fg + a * 2 * nv + off, q, face_ok && (!planar || a == 0), [&](int v) {
+                    return group_sum<G, R>(planar ? (a == 0 ? w[v] : R(0.0)) : w[v] * n[a]);
+                });
+        }
+    };
     if (want_grad) {
-        if (writer && planar) {
+        group_store<G, D>(dst + T::fh, q, face_ok && planar, [&](int a) { return n[a]; });
+        R Wz[nv];
 #pragma unroll
-            for (int a = 0; a < D; ++a) dst[T::fh + a] = n[a];
-        }
-        fr.to_global(Wc, o);
-#pragma unroll
-        for (int v = 0; v < nv; ++v) {
-            const R w = ok ? wJ * o[v] : R(0.0);
-            if (wave_planar) {
-                const R sum = group_sum<G, R>(w);
-                if (writer) dst[T::fg + v] = sum;
-            } else {
-#pragma unroll
-                for (int a = 0; a < D; ++a) {
-                    const R sum = group_sum<G, R>(planar ? (a == 0 ? w : R(0.0)) : w * n[a]);
-                    if (writer && (!planar || a == 0)) dst[T::fg + a * 2 * nv + v] = sum;
-                }
-            }
-        }
+        for (int v = 0; v < nv; ++v) Wz[v] = ok ? Wc[v] : R(0.0);
+        gauss_green(Wz, 0);
     }
     R F0[nv], Ft[nv], Wt[nv];
     if (FULL && did_full) {
@@ -1718,37 +1740,18 @@ template <int D, typename R, bool FULL> __global__ __launch_bounds__(kBlock) voi
 #pragma unroll
         for (int v = 0; v < nv; ++v) Wt[v] = R(0.0);
     }
-    fr.to_global(F0, o);
-    const bool wall_out = want_grad == 2 && writer && cR < 0 && (bc == 1 || bc == 2 || bc == 3);
-#pragma unroll
-    for (int v = 0; v < nv; ++v) {
-        const R sum = group_sum<G, R>(wJ * o[v]);
-        if (writer) dst[v] = sum;
-        if (v >= 1 && v <= D && wall_out) d.wallf[size_t(d.bslot[f]) * 3 + (v - 1)] = double(sum);
+    {
+        R of[2 * nv];
+        fr.to_global(F0, of);
+        fr.to_global(Ft, of + nv);
+        const bool wall_out = want_grad == 2 && writer && cR < 0 && (bc == 1 || bc == 2 || bc == 3);
+        group_store<G, 2 * nv>(dst, q, face_ok, [&](int v) {
+            const R sum = group_sum<G, R>(wJ * of[v]);
+            if (v >= 1 && v <= D && wall_out) d.wallf[size_t(d.bslot[f]) * 3 + (v - 1)] = double(sum);
+            return sum;
+        });
     }
-    fr.to_global(Ft, o);
-#pragma unroll
-    for (int v = 0; v < nv; ++v) {
-        const R sum = group_sum<G, R>(wJ * o[v]);
-        if (writer) dst[nv + v] = sum;
-    }
-    if (want_grad) {
-        fr.to_global(Wt, o);
-#pragma unroll
-        for (int v = 0; v < nv; ++v) {
-            const R w = wJ * o[v];
-            if (wave_planar) {
-                const R sum = group_sum<G, R>(w);
-                if (writer) dst[T::fg + nv + v] = sum;
-            } else {
-#pragma unroll
-                for (int a = 0; a < D; ++a) {
-                    const R sum = group_sum<G, R>(planar ? (a == 0 ? w : R(0.0)) : w * n[a]);
-                    if (writer && (!planar || a == 0)) dst[T::fg + a * 2 * nv + nv + v] = sum;
-                }
-            }
-        }
-    }
+    if (want_grad) gauss_green(Wt, nv);
 }
 
 // ---------------------------------------------------------------------
