@@ -890,6 +890,23 @@ template <int D> struct LowRec<D, float> {
     }
 };
 
+// cell i's low-level record set to U = u, dU = 0 by the cell's SL lanes:
+// the record's 16-byte pieces go to lane k % SL (U below nv doubles; dU and
+// the padding after it are zero bits in either precision)
+template <int D, typename S, int SL>
+__device__ __forceinline__ void low_rec_reset(const Dev &d, int i, const double *u, int q) {
+    constexpr int nv = D + 2, np = LowRec<D, S>::stride / 2;
+    double2 *rec = reinterpret_cast<double2 *>(LowRec<D, S>::U(d, i));
+#pragma unroll
+    for (int r = 0; r < np; r += SL) {
+        double2 v = make_double2(0.0, 0.0);
+#pragma unroll
+        for (int j = r; j < r + SL && j < np; ++j)
+            if (q == j - r) v = make_double2(2 * j < nv ? u[2 * j] : 0.0, 2 * j + 1 < nv ? u[2 * j + 1] : 0.0);
+        if (r + q < np) rec[r + q] = v;
+    }
+}
+
 // ---------------------------------------------------------------------
 // Global time step: per-block minimum over a case's cells, then per case.
 // ---------------------------------------------------------------------
@@ -1763,15 +1780,22 @@ enum { MODE_STAGE0 = 0, MODE_STAGE1 = 1, MODE_R1 = 2 };
 // are reduced across the group and lane q then owns variables q, q + sl.
 template <int D, typename R> __global__ __launch_bounds__(kBlock) void k_cell(Dev d, int mode) {
     using T = Dim<D>;
-    constexpr int nv = T::nv, SL = T::sl, GW = 2 * nv;
-    const int t = xcd_block(blockIdx.x, gridDim.x) * int(blockDim.x) + threadIdx.x;
-    const int ir = t / SL, q = t % SL;
+    constexpr int nv = T::nv, SL = T::sl, GW = 2 * nv, SR = Rec<D>::sr;
+    // stage passes: the block's new state records pass through LDS so that
+    // its stores are consecutive (the lanes of a cell would store 5 doubles
+    // apart, 16 cells at once)
+    __shared__ __align__(16) double stage[kBlock / SL * SR];
+    __shared__ int live_s[kBlock / SL];
+    const int nbc = int(blockDim.x) / SL;
+    const int c0 = xcd_block(blockIdx.x, gridDim.x) * nbc;
+    if (c0 >= d.NC) return;   // the whole block
+    const int ir = c0 + int(threadIdx.x) / SL, q = int(threadIdx.x) % SL, lc = ir - c0;
     const bool ok = ir < d.NC;
     const int i = ok ? ir : d.NC - 1;
     const int NC = d.NC;
     const int cs = d.cell_case[i];
     const DevParams &P = d.prm[cs];
-    if (!P.active) return;   // the cell's lane group leaves together
+    const bool act = P.active;
     const bool want_g = mode != MODE_R1;
     // lane 0 sums the flux group (F0, Ft) of the cell's face records, lane
     // 1 + a the Gauss-Green group of axis a (W_c n_a, W_t n_a): each lane
@@ -1783,7 +1807,7 @@ template <int D, typename R> __global__ __launch_bounds__(kBlock) void k_cell(De
     double acc[GW];
 #pragma unroll
     for (int k = 0; k < GW; ++k) acc[k] = 0.0;
-    if (mine) {
+    if (act && mine) {
         if constexpr (std::is_same<R, float>::value) {
             // FP32 face records: every slot code first, then all face
             // groups at once; an empty slot reads face 0 with weight 0 (face
@@ -1826,43 +1850,58 @@ template <int D, typename R> __global__ __launch_bounds__(kBlock) void k_cell(De
             }
         }
     }
-    if (!ok || !mine) return;
+    const bool live = ok && act;
     const double dt = d.dt[cs];
-    const double iV = recip<double>(d.vol[i]);
-    double *si = d.st + size_t(i) * Rec<D>::sr;
-    if (q == 0) {
-#pragma unroll
-        for (int v = 0; v < nv; ++v) {
-            if (mode == MODE_R1) {
-                st_nt(-(acc[v] + 0.5 * dt * acc[nv + v]), d.R1 + size_t(v) * NC + i);
-                continue;
-            }
-            const double L = -acc[v] * iV, Lt = -acc[nv + v] * iV;
-            if (mode == MODE_STAGE0) {
-                const double w = si[v];
-                st_nt(w, d.Wn + size_t(v) * NC + i);
-                st_nt(L, d.L0 + size_t(v) * NC + i);
-                st_nt(Lt, d.Lt0 + size_t(v) * NC + i);
-                si[v] = P.scheme == 0 ? w + 0.5 * dt * L + 0.125 * dt * dt * Lt : w + dt * L + 0.5 * dt * dt * Lt;
-            } else {
-                si[v] = ld_nt(d.Wn + size_t(v) * NC + i) + dt * ld_nt(d.L0 + size_t(v) * NC + i) +
-                        dt * dt / 6.0 * (ld_nt(d.Lt0 + size_t(v) * NC + i) + 2.0 * Lt);
-            }
-        }
+    if (mode == MODE_R1) {
+        if (!live || q != 0) return;
+        for (int v = 0; v < nv; ++v) st_nt(-(acc[v] + 0.5 * dt * acc[nv + v]), d.R1 + size_t(v) * NC + i);
         return;
     }
-    const int a = q - 1;
+    // lane 0: the new W (record positions 0 .. nv-1); lane 1 + a: the new
+    // gradient along axis a (positions nv (1 + a) ...)
+    double *o = stage + lc * SR + q * nv;
+    if (live && mine) {
+        const double iV = recip<double>(d.vol[i]);
+        const double *si = d.st + size_t(i) * SR;
+        if (q == 0) {
 #pragma unroll
-    for (int v = 0; v < nv; ++v) {
-        const size_t k = size_t(a * nv + v) * NC + i;
-        const double G = acc[v] * iV, Gt = acc[nv + v] * iV;
-        if (mode == MODE_STAGE0) {
-            st_nt(G, d.G0 + k);
-            si[nv + a * nv + v] = P.scheme == 0 ? G + 0.5 * dt * Gt : G + dt * Gt;
+            for (int v = 0; v < nv; ++v) {
+                const double L = -acc[v] * iV, Lt = -acc[nv + v] * iV;
+                if (mode == MODE_STAGE0) {
+                    const double w = si[v];
+                    st_nt(w, d.Wn + size_t(v) * NC + i);
+                    st_nt(L, d.L0 + size_t(v) * NC + i);
+                    st_nt(Lt, d.Lt0 + size_t(v) * NC + i);
+                    o[v] = P.scheme == 0 ? w + 0.5 * dt * L + 0.125 * dt * dt * Lt : w + dt * L + 0.5 * dt * dt * Lt;
+                } else {
+                    o[v] = ld_nt(d.Wn + size_t(v) * NC + i) + dt * ld_nt(d.L0 + size_t(v) * NC + i) +
+                           dt * dt / 6.0 * (ld_nt(d.Lt0 + size_t(v) * NC + i) + 2.0 * Lt);
+                }
+            }
         } else {
-            si[nv + a * nv + v] = ld_nt(d.G0 + k) + dt * Gt;
+            const int a = q - 1;
+#pragma unroll
+            for (int v = 0; v < nv; ++v) {
+                const size_t k = size_t(a * nv + v) * NC + i;
+                const double G = acc[v] * iV, Gt = acc[nv + v] * iV;
+                if (mode == MODE_STAGE0) {
+                    st_nt(G, d.G0 + k);
+                    o[v] = P.scheme == 0 ? G + 0.5 * dt * Gt : G + dt * Gt;
+                } else {
+                    o[v] = ld_nt(d.G0 + k) + dt * Gt;
+                }
+            }
         }
     }
+    if (q == 0) live_s[lc] = live;
+    __syncthreads();
+    // the block's records are consecutive: 16-byte stores, a cell's only
+    // where it is live
+    const int ncell = min(nbc, NC - c0);
+    double2 *dst = reinterpret_cast<double2 *>(d.st + size_t(c0) * SR);
+    const double2 *src = reinterpret_cast<const double2 *>(stage);
+    for (int e = int(threadIdx.x); e < ncell * (SR / 2); e += int(blockDim.x))
+        if (live_s[e / (SR / 2)]) dst[e] = src[e];
 }
 
 // ---------------------------------------------------------------------
@@ -1901,11 +1940,19 @@ template <int D, typename S, int src> __device__ __forceinline__ void low_state(
 }
 
 // lowf[f] = S_f F(U_L, U_R; n_f), F the case's first-order flux (KFVS or
-// Lax-Friedrichs); swp[f][D] = S_f lam_f.
+// Lax-Friedrichs); swp[f] = (S_f n_f, S_f lam_f).
 template <int D, typename S, int SRC> __global__ __launch_bounds__(kBlock) void k_low_face(Dev d) {
     constexpr int nv = D + 2, src = SRC;
-    const int f = xcd_block(blockIdx.x, gridDim.x) * int(blockDim.x) + threadIdx.x;
-    if (f >= d.NF) return;
+    // the block's flux records pass through LDS so that its stores to lowf
+    // are consecutive (one face per thread would store 2 nv doubles apart)
+    __shared__ double stage[kBlock * nv];
+    __shared__ int live_s[kBlock];
+    const int nb = int(blockDim.x);
+    const int f0 = xcd_block(blockIdx.x, gridDim.x) * nb;
+    if (f0 >= d.NF) return;   // the whole block
+    const int fr_raw = f0 + int(threadIdx.x);
+    const bool in = fr_raw < d.NF;
+    const int f = in ? fr_raw : d.NF - 1;
     // Two rounds to memory before any arithmetic (as in the flux): the
     // face's own data, then both cells' states and volumes with the case's
     // active flag, and only then the branch on the flag.  A boundary face
@@ -1924,61 +1971,69 @@ template <int D, typename S, int SRC> __global__ __launch_bounds__(kBlock) void 
     asm volatile("" ::"v"(case_on), "v"(VL), "v"(VR));
 #pragma unroll
     for (int v = 0; v < nv; ++v) asm volatile("" ::"v"(UL[v]), "v"(UR[v]));
-    if (!case_on) return;
-    const DevParams &P = d.prm[cs];
-    const double iS = recip<double>(Sf);
-    double n[D];
+    const bool live = in && case_on;
+    if (live) {
+        const DevParams &P = d.prm[cs];
+        const double iS = recip<double>(Sf);
+        double n[D];
 #pragma unroll
-    for (int a = 0; a < D; ++a) n[a] = av[a] * iS;
-    Frame<D, double> fr;
-    fr.build(n);
-    double Ul[nv], Ur[nv];
-    fr.to_local(UL, Ul);
-    double lam = side_radius<D>(UL, n, Sf, VL, P);
-    if (R >= 0) {
-        fr.to_local(UR, Ur);
-        lam = fmax(lam, side_radius<D>(UR, n, Sf, VR, P));
-    } else {
-        const int bc = d.fbc[f] & 7;
-#pragma unroll
-        for (int v = 0; v < nv; ++v) Ur[v] = Ul[v];
-        if (bc == 1) {
-            Ur[1] = -Ul[1];
-        } else if (bc == 2 || bc == 3) {
-#pragma unroll
-            for (int a = 0; a < D; ++a) Ur[1 + a] = -Ul[1 + a];
+        for (int a = 0; a < D; ++a) n[a] = av[a] * iS;
+        Frame<D, double> fr;
+        fr.build(n);
+        double Ul[nv], Ur[nv];
+        fr.to_local(UL, Ul);
+        double lam = side_radius<D>(UL, n, Sf, VL, P);
+        if (R >= 0) {
+            fr.to_local(UR, Ur);
+            lam = fmax(lam, side_radius<D>(UR, n, Sf, VR, P));
         } else {
-            double Wo_g[nv], Wo[nv];
+            const int bc = d.fbc[f] & 7;
 #pragma unroll
-            for (int v = 0; v < nv; ++v) Wo_g[v] = P.W_inf[v];
-            fr.to_local(Wo_g, Wo);
-            farfield_state<D, double>(Ul, Wo, P.gamma, Ur);
+            for (int v = 0; v < nv; ++v) Ur[v] = Ul[v];
+            if (bc == 1) {
+                Ur[1] = -Ul[1];
+            } else if (bc == 2 || bc == 3) {
+#pragma unroll
+                for (int a = 0; a < D; ++a) Ur[1 + a] = -Ul[1 + a];
+            } else {
+                double Wo_g[nv], Wo[nv];
+#pragma unroll
+                for (int v = 0; v < nv; ++v) Wo_g[v] = P.W_inf[v];
+                fr.to_local(Wo_g, Wo);
+                farfield_state<D, double>(Ul, Wo, P.gamma, Ur);
+            }
         }
+        double Fl[nv], F[nv];
+        bool ok;
+        if (P.low_flux == 1) {
+            // Lax-Friedrichs with the face's spectral radius
+            Prim<D, double> a, c;
+            a.from(Ul, P.gamma);
+            c.from(Ur, P.gamma);
+            ok = a.rho > 0.0 && a.p > 0.0 && c.rho > 0.0 && c.p > 0.0;
+            const double e0[D] = {1.0};
+            double Fa[nv], Fb[nv];
+            euler_flux<D>(Ul, e0, P.gamma, Fa);
+            euler_flux<D>(Ur, e0, P.gamma, Fb);
+#pragma unroll
+            for (int v = 0; v < nv; ++v) Fl[v] = 0.5 * (Fa[v] + Fb[v]) - 0.5 * lam * (Ur[v] - Ul[v]);
+        } else {
+#pragma unroll
+            for (int v = 0; v < nv; ++v) Fl[v] = 0.0;
+            ok = half_side<D, double>(Ul, P, 1.0, nullptr, Fl) && half_side<D, double>(Ur, P, -1.0, nullptr, Fl);
+        }
+        flag_nonphysical(d.flag, !ok, cs);
+        fr.to_global(Fl, F);
+#pragma unroll
+        for (int v = 0; v < nv; ++v) stage[threadIdx.x * nv + v] = ok ? Sf * F[v] : 0.0;
+        d.swp[size_t(f) * 4 + D] = Sf * lam;   // the area vector part is written at upload
     }
-    double Fl[nv], F[nv];
-    bool ok;
-    if (P.low_flux == 1) {
-        // Lax-Friedrichs with the face's spectral radius
-        Prim<D, double> a, c;
-        a.from(Ul, P.gamma);
-        c.from(Ur, P.gamma);
-        ok = a.rho > 0.0 && a.p > 0.0 && c.rho > 0.0 && c.p > 0.0;
-        const double e0[D] = {1.0};
-        double Fa[nv], Fb[nv];
-        euler_flux<D>(Ul, e0, P.gamma, Fa);
-        euler_flux<D>(Ur, e0, P.gamma, Fb);
-#pragma unroll
-        for (int v = 0; v < nv; ++v) Fl[v] = 0.5 * (Fa[v] + Fb[v]) - 0.5 * lam * (Ur[v] - Ul[v]);
-    } else {
-#pragma unroll
-        for (int v = 0; v < nv; ++v) Fl[v] = 0.0;
-        ok = half_side<D, double>(Ul, P, 1.0, nullptr, Fl) && half_side<D, double>(Ur, P, -1.0, nullptr, Fl);
-    }
-    flag_nonphysical(d.flag, !ok, cs);
-    fr.to_global(Fl, F);
-#pragma unroll
-    for (int v = 0; v < nv; ++v) d.lowf[size_t(f) * nv + v] = ok ? Sf * F[v] : 0.0;
-    d.swp[size_t(f) * 4 + D] = Sf * lam;   // the area vector part is written at upload
+    live_s[threadIdx.x] = live;
+    __syncthreads();
+    const int nrow = min(nb, d.NF - f0);
+    double *dst = d.lowf + size_t(f0) * nv;
+    for (int e = int(threadIdx.x); e < nrow * nv; e += nb)
+        if (live_s[e / nv]) dst[e] = stage[e];
 }
 
 // LOW_FORCE: forcing S = R1 - R0(W), U = W, and the first implicit step's
@@ -2051,19 +2106,14 @@ template <int D, typename S, int MODE> __global__ __launch_bounds__(kBlock) void
             if (v % SL == q) {
                 const double sf = own[v] - R0[v];
                 d.Sf[size_t(v) * NC + i] = sf;
-                Ui[v] = u[v];
                 d.RHS[size_t(v) * NC + i] = R0[v] + sf;
-                dUi[v] = S(0);
             }
     } else {
 #pragma unroll
         for (int v = 0; v < nv; ++v)
-            if (v % SL == q) {
-                Ui[v] = u[v];
-                d.RHS[size_t(v) * NC + i] = R0[v] + own[v];
-                dUi[v] = S(0);
-            }
+            if (v % SL == q) d.RHS[size_t(v) * NC + i] = R0[v] + own[v];
     }
+    low_rec_reset<D, S, SL>(d, i, u, q);
     if (q == 0) d.D[i] = Vi * recip<double>(state_dt<D>(u, hi, P.cfl_low, P)) + 0.5 * lS;
 }
 
@@ -2181,19 +2231,45 @@ template <int D, typename S> __global__ __launch_bounds__(kBlock) void k_prolong
     const DevParams &P = d.prm[cs];
     const int n = d.rb_count[b];
     const int NC = d.NC;
+    const int i0 = d.rb_start[b];
+    const bool pro = prolong && P.active;
+    // NB cells per thread at a time: every load of the batch first, then the
+    // updates and sums in the cells' order (the stores would otherwise keep
+    // each cell's loads behind the previous cell's stores)
+    constexpr int NB = 4;
     double s0 = 0, s1 = 0;
-    for (int k = threadIdx.x; k < n; k += kBlock) {
-        const int i = d.rb_start[b] + k;
-        if (prolong && P.active) {
+    for (int k0 = int(threadIdx.x); k0 < n; k0 += NB * kBlock) {
+        double up[NB][nv], w[NB][nv], wn[NB];
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+            const int k = k0 + j * kBlock;
+            const int i = i0 + (k < n ? k : 0);
+            const double *U = LowRec<D, S>::U(d, i);
+            const S *dU = LowRec<D, S>::dU(d, i);
 #pragma unroll
             for (int v = 0; v < nv; ++v) {
-                const double u6 = LowRec<D, S>::U(d, i)[v] + double(LowRec<D, S>::dU(d, i)[v]);
-                const double w = d.st[size_t(i) * Rec<D>::sr + v];
-                d.st[size_t(i) * Rec<D>::sr + v] = w + (u6 - w);
+                up[j][v] = U[v] + double(dU[v]);
+                w[j][v] = d.st[size_t(i) * Rec<D>::sr + v];
             }
+            wn[j] = d.Wn[i];
         }
-        s0 += fabs(d.st[size_t(i) * Rec<D>::sr] - d.Wn[i]);
-        s1 += d.Wn[i];
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+            const int k = k0 + j * kBlock;
+            if (k >= n) break;
+            const int i = i0 + k;
+            double r0 = w[j][0];
+            if (pro) {
+#pragma unroll
+                for (int v = 0; v < nv; ++v) {
+                    const double nw = w[j][v] + (up[j][v] - w[j][v]);
+                    d.st[size_t(i) * Rec<D>::sr + v] = nw;
+                    if (v == 0) r0 = nw;
+                }
+            }
+            s0 += fabs(r0 - wn[j]);
+            s1 += wn[j];
+        }
     }
     s0 = block_reduce_sum(s0, sh);
     s1 = block_reduce_sum(s1, sh);
