@@ -22,8 +22,8 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
 # MI355X vector peaks: FP64 78.6 TFLOP/s (256 CUs x 2.4 GHz x 64 FMA per
 # clock).  The published FP32 figure, 157.3, counts packed FP32 (two
-# operations per lane per instruction); this build compiles with packed
-# FP32 off, so an FP32 lane operation issues at the FP64 rate and the FP32
+# operations per lane per instruction); the library is compiled with
+# packed FP32 off, so an FP32 lane operation issues at the FP64 rate and the FP32
 # kernels are priced at 78.6 as well.
 VALU_PEAK_TFLOPS = {"fp64": 78.6, "mixed32": 78.6, "mixed32_r64": 78.6}
 FP32_PACKED_PEAK_TFLOPS = 157.3
@@ -455,7 +455,7 @@ def main():
         print(json.dumps(dict(copy_bytes_each=n * 8, copies=5)))
         return
     if args.gpus != 1:
-        print(f"bench.py: this build measures one GPU only; --gpus {args.gpus} is not supported "
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
               "(independent cases shard across GPUs without communication)", file=sys.stderr)
         sys.exit(2)
 

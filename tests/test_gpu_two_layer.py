@@ -1,5 +1,5 @@
 """The paper's practice of running 2-D cases on two-layer 3-D meshes
-(Sec. 4, opening paragraph) against this build's native 2-D path, on the
+(Sec. 4, opening paragraph) against the library's native 2-D path, on the
 GPU: the Re 40 cylinder (64 x 32 ring, no-slip adiabatic wall, Ma 0.15)
 converged both ways.  The two discretisations differ by the cell-size
 scaling of the reconstruction's gradient rows (h of a triangle against h

@@ -1,4 +1,4 @@
-"""The paper's 2-D cases run on two-layer 3-D meshes (Sec. 4); this build
+"""The paper's 2-D cases run on two-layer 3-D meshes (Sec. 4); the library
 runs 2-D natively (K = (4 - 2 gamma)/(gamma - 1) internal degrees of
 freedom, the 3-D total).  Cross-check of that reading on the CPU: on an
 in-plane quadratic field, where every reconstruction is exact, one
