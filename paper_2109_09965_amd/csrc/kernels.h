@@ -1510,9 +1510,12 @@ __device__ __forceinline__ void group_store(R *dst, int q, bool on, Val val) {
 // with weight 0, so every lane runs the same code.  The face sums
 //   sum_g wJ (F0, Ft, W_c n, W_t n)   (global frame)
 // are reduced across the group and written face-major by its first lane.
-// want_grad: 0 = flux sums only (the residual pass), 1 = with the
-// Gauss-Green sums (stage passes), 2 = also keep the wall faces' momentum
-// sums in wallf (stage 0)
+// want_grad: 0 = flux sums only (the residual pass); 2 = the flux sums,
+// both Gauss-Green groups and the wall faces' momentum sums in wallf (stage
+// 0); 1 = the second S2O4 stage, whose update takes only the time
+// derivatives: the F_t sums and the Gauss-Green sums of W_t (the record's
+// F0 and W groups keep the first stage's values, which the cell kernel
+// reads along but does not use)
 // FULL: the launch also serves cases with the full time-dependent solution
 // (flux_full); smooth cases of such a launch take exactly the smooth path.
 template <int D, typename R, bool FULL> __global__ __launch_bounds__(kBlock) void k_flux(Dev d, int want_grad) {
@@ -1728,12 +1731,15 @@ template <int D, typename R, bool FULL> __global__ __launch_bounds__(kBlock) voi
                 });
         }
     };
+    const bool t_only = want_grad == 1;
     if (want_grad) {
         group_store<G, D>(dst + T::fh, q, face_ok && planar, [&](int a) { return n[a]; });
-        R Wz[nv];
+        if (!t_only) {
+            R Wz[nv];
 #pragma unroll
-        for (int v = 0; v < nv; ++v) Wz[v] = ok ? Wc[v] : R(0.0);
-        gauss_green(Wz, 0);
+            for (int v = 0; v < nv; ++v) Wz[v] = ok ? Wc[v] : R(0.0);
+            gauss_green(Wz, 0);
+        }
     }
     R F0[nv], Ft[nv], Wt[nv];
     if (FULL && did_full) {
@@ -1762,11 +1768,15 @@ template <int D, typename R, bool FULL> __global__ __launch_bounds__(kBlock) voi
         fr.to_global(F0, of);
         fr.to_global(Ft, of + nv);
         const bool wall_out = want_grad == 2 && writer && cR < 0 && (bc == 1 || bc == 2 || bc == 3);
-        group_store<G, 2 * nv>(dst, q, face_ok, [&](int v) {
-            const R sum = group_sum<G, R>(wJ * of[v]);
-            if (v >= 1 && v <= D && wall_out) d.wallf[size_t(d.bslot[f]) * 3 + (v - 1)] = double(sum);
-            return sum;
-        });
+        if (t_only) {
+            group_store<G, nv>(dst + nv, q, face_ok, [&](int v) { return group_sum<G, R>(wJ * of[nv + v]); });
+        } else {
+            group_store<G, 2 * nv>(dst, q, face_ok, [&](int v) {
+                const R sum = group_sum<G, R>(wJ * of[v]);
+                if (v >= 1 && v <= D && wall_out) d.wallf[size_t(d.bslot[f]) * 3 + (v - 1)] = double(sum);
+                return sum;
+            });
+        }
     }
     if (want_grad) gauss_green(Wt, nv);
 }
