@@ -32,26 +32,26 @@ FP32_PACKED_PEAK_TFLOPS = 157.3
 # (FMA = 2), from the VALU instruction counters of one launch on the
 # sphere workload (SQ_INSTS_VALU_{FMA,MUL,ADD,TRANS}_F64 resp. _F32, x 64
 # lanes), charged to the lanes that carry a Gauss point.
-FLUX_FLOP_PER_GP = {"fp64": 1541.7, "mixed32": 1412.8, "mixed32_r64": (2 * 1412.8 + 1541.7) / 3.0}
+FLUX_FLOP_PER_GP = {"fp64": 1514.9, "mixed32": 1386.0, "mixed32_r64": (2 * 1386.0 + 1514.9) / 3.0}
 
 # HBM bytes per launch from rocprofv3 FETCH_SIZE (x 2.0) and WRITE_SIZE
 # (x 1.0) on the sphere workload, each factor from a plain device copy of
 # known size.  Valid only for the kernel source they were taken on (its
 # SHA-256); any other source reports null.
-PROFILED_KERNELS_SHA256 = "83da93eb909e76d1a17a9b424d37b34e57aa10b94c9143c86c62f0720d12fa37"
+PROFILED_KERNELS_SHA256 = "fe4ce9ecb9057f0e5c87391572581ae42d665c7ffbb5d20ecdf6f68eca56d9cf"
 PROFILED_TRAFFIC = {           # (kernel kind, precision) -> bytes per launch
-    ("dt", "fp64"): 79183070.5, ("dt", "mixed32"): 79182989.7,
-    ("recon", "fp64"): 679496149.3, ("recon", "mixed32"): 632962342.6,   # with the boundary ghost pre-pass
-    ("flux", "fp64"): 740704235.2, ("flux", "mixed32"): 502848544.0,
-    ("cell", "fp64"): 621932052.3, ("cell", "mixed32"): 382887426.0,
-    ("low_face", "fp64"): 183482206.5, ("low_face", "mixed32"): 175442178.0,
-    ("low_cell", "fp64"): 256464158.5, ("low_cell", "mixed32"): 242148676.1,  # 1 forcing + 5 step launches
-    ("sweep", "fp64"): 56984011.0, ("sweep", "mixed32"): 42721148.4,          # average over colour classes
-    ("prolong", "fp64"): 149466013.0, ("prolong", "mixed32"): 144021139.8,
-    ("dt", "mixed32_r64"): 79183011.0, ("recon", "mixed32_r64"): 647964993.0,
-    ("flux", "mixed32_r64"): 563163492.6, ("cell", "mixed32_r64"): 465189944.9,
-    ("low_face", "mixed32_r64"): 175445790.5, ("low_cell", "mixed32_r64"): 242190893.7,
-    ("sweep", "mixed32_r64"): 42727451.8, ("prolong", "mixed32_r64"): 143995730.3,
+    ("dt", "fp64"): 79187184.8, ("dt", "mixed32"): 79187158.9,
+    ("recon", "fp64"): 679403780.1, ("recon", "mixed32"): 633458015.5,   # with the boundary ghost pre-pass
+    ("flux", "fp64"): 729997176.9, ("flux", "mixed32"): 500402548.3,
+    ("cell", "fp64"): 621961703.6, ("cell", "mixed32"): 383398658.0,
+    ("low_face", "fp64"): 183485511.1, ("low_face", "mixed32"): 175437614.7,
+    ("low_cell", "fp64"): 256286730.2, ("low_cell", "mixed32"): 242320412.4,  # 1 forcing + 5 step launches
+    ("sweep", "fp64"): 56988692.6, ("sweep", "mixed32"): 42739613.8,          # average over colour classes
+    ("prolong", "fp64"): 149430357.3, ("prolong", "mixed32"): 144009106.3,
+    ("dt", "mixed32_r64"): 79187082.7, ("recon", "mixed32_r64"): 648026034.8,
+    ("flux", "mixed32_r64"): 560729567.0, ("cell", "mixed32_r64"): 462545395.8,
+    ("low_face", "mixed32_r64"): 175438678.3, ("low_cell", "mixed32_r64"): 242221633.0,
+    ("sweep", "mixed32_r64"): 42750672.4, ("prolong", "mixed32_r64"): 144051222.9,
 }
 
 
