@@ -38,7 +38,7 @@ FLUX_FLOP_PER_GP = {"fp64": 1514.9, "mixed32": 1386.0, "mixed32_r64": (2 * 1386.
 # (x 1.0) on the sphere workload, each factor from a plain device copy of
 # known size.  Valid only for the kernel source they were taken on (its
 # SHA-256); any other source reports null.
-PROFILED_KERNELS_SHA256 = "fe4ce9ecb9057f0e5c87391572581ae42d665c7ffbb5d20ecdf6f68eca56d9cf"
+PROFILED_KERNELS_SHA256 = "76812734a44f92ed5bd0142bd6939bf990fff9bc9bb09ddf6d2f9d63ced435a6"
 PROFILED_TRAFFIC = {           # (kernel kind, precision) -> bytes per launch
     ("dt", "fp64"): 79187184.8, ("dt", "mixed32"): 79187158.9,
     ("recon", "fp64"): 679403780.1, ("recon", "mixed32"): 633458015.5,   # with the boundary ghost pre-pass

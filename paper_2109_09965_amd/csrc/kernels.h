@@ -1509,7 +1509,8 @@ __device__ __forceinline__ void group_store(R *dst, int q, bool on, Val val) {
 // a lane without a Gauss point (triangles in 3-D) repeats the first point
 // with weight 0, so every lane runs the same code.  The face sums
 //   sum_g wJ (F0, Ft, W_c n, W_t n)   (global frame)
-// are reduced across the group and written face-major by its first lane.
+// are reduced across the group and stored face-major, spread over the
+// group's lanes (group_store).
 // want_grad: 0 = flux sums only (the residual pass); 2 = the flux sums,
 // both Gauss-Green groups and the wall faces' momentum sums in wallf (stage
 // 0); 1 = the second S2O4 stage, whose update takes only the time
@@ -1950,7 +1951,8 @@ template <int D, typename S, int src> __device__ __forceinline__ void low_state(
 }
 
 // lowf[f] = S_f F(U_L, U_R; n_f), F the case's first-order flux (KFVS or
-// Lax-Friedrichs); swp[f] = (S_f n_f, S_f lam_f).
+// Lax-Friedrichs); swp[f][D] = S_f lam_f (the area vector S_f n_f in
+// swp[f][0..D) is written at upload).
 template <int D, typename S, int SRC> __global__ __launch_bounds__(kBlock) void k_low_face(Dev d) {
     constexpr int nv = D + 2, src = SRC;
     // the block's flux records pass through LDS so that its stores to lowf
