@@ -1807,13 +1807,48 @@ template <int D, typename R> __global__ __launch_bounds__(kBlock) void k_cell(De
     const int cs = d.cell_case[i];
     const DevParams &P = d.prm[cs];
     const bool act = P.active;
-    const bool want_g = mode != MODE_R1;
-    // lane 0 sums the flux group (F0, Ft) of the cell's face records, lane
-    // 1 + a the Gauss-Green group of axis a (W_c n_a, W_t n_a): each lane
-    // reads 2 nv values of every face and needs no other lane's sums.  For a
-    // planar face (marked in its slot code) lane 1 + a reads the one plain
-    // group and scales it by n_a.
-    const bool mine = q == 0 || (want_g && q <= D);
+    if (mode == MODE_R1) {
+        // the residual needs only the flux groups (F0, Ft): lane q takes the
+        // cell's slot q (every cell has at least SL faces in 3-D; a missing
+        // one in 2-D reads with weight 0 the cell's first face, written in
+        // the same pass), and slot q + SL only where the cell has it; the
+        // lanes' partial sums meet in a lane-group sum
+        constexpr int NS = T::ns / SL;
+        const int code0 = d.slot[size_t(q) * NC + i].x;
+        const int f_first = slot_face(bcast_i32<SL, 0>(code0));
+        double a[GW];
+        {
+            const bool has = code0 != 0;
+            const int f = has ? slot_face(code0) : f_first;
+            const double sg = has ? (code0 > 0 ? 1.0 : -1.0) : 0.0;
+            const R *rec = HoArrays<R>::fsum(d) + size_t(f) * T::fs;
+#pragma unroll
+            for (int j = 0; j < GW; ++j) a[j] = sg * double(rec[j]);
+        }
+#pragma unroll
+        for (int k = 1; k < NS; ++k) {
+            const int code = d.slot[size_t(q + k * SL) * NC + i].x;
+            if (code != 0) {
+                const double sg = code > 0 ? 1.0 : -1.0;
+                const R *rec = HoArrays<R>::fsum(d) + size_t(slot_face(code)) * T::fs;
+#pragma unroll
+                for (int j = 0; j < GW; ++j) a[j] += sg * double(rec[j]);
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < GW; ++j) a[j] = group_sum<SL, double>(a[j]);
+        if (!ok || !act || q != 0) return;
+        const double dt = d.dt[cs];
+#pragma unroll
+        for (int v = 0; v < nv; ++v) st_nt(-(a[v] + 0.5 * dt * a[nv + v]), d.R1 + size_t(v) * NC + i);
+        return;
+    }
+    // stage passes: lane 0 sums the flux group (F0, Ft) of the cell's face
+    // records, lane 1 + a the Gauss-Green group of axis a (W_c n_a, W_t n_a):
+    // each lane reads 2 nv values of every face and needs no other lane's
+    // sums.  For a planar face (marked in its slot code) lane 1 + a reads the
+    // one plain group and scales it by n_a.
+    const bool mine = q <= D;
     const int ax = q - 1;
     double acc[GW];
 #pragma unroll
@@ -1863,11 +1898,6 @@ template <int D, typename R> __global__ __launch_bounds__(kBlock) void k_cell(De
     }
     const bool live = ok && act;
     const double dt = d.dt[cs];
-    if (mode == MODE_R1) {
-        if (!live || q != 0) return;
-        for (int v = 0; v < nv; ++v) st_nt(-(acc[v] + 0.5 * dt * acc[nv + v]), d.R1 + size_t(v) * NC + i);
-        return;
-    }
     // lane 0: the new W (record positions 0 .. nv-1); lane 1 + a: the new
     // gradient along axis a (positions nv (1 + a) ...)
     double *o = stage + lc * SR + q * nv;
