@@ -38,20 +38,20 @@ FLUX_FLOP_PER_GP = {"fp64": 1514.9, "mixed32": 1386.0, "mixed32_r64": (2 * 1386.
 # (x 1.0) on the sphere workload, each factor from a plain device copy of
 # known size.  Valid only for the kernel source they were taken on (its
 # SHA-256); any other source reports null.
-PROFILED_KERNELS_SHA256 = "76812734a44f92ed5bd0142bd6939bf990fff9bc9bb09ddf6d2f9d63ced435a6"
+PROFILED_KERNELS_SHA256 = "587da4672ae8271f13d071f2ebb32955ec7c8fdf19014b179ced2c7d0fa34b88"
 PROFILED_TRAFFIC = {           # (kernel kind, precision) -> bytes per launch
-    ("dt", "fp64"): 79187184.8, ("dt", "mixed32"): 79187158.9,
-    ("recon", "fp64"): 679403780.1, ("recon", "mixed32"): 633458015.5,   # with the boundary ghost pre-pass
-    ("flux", "fp64"): 729997176.9, ("flux", "mixed32"): 500402548.3,
-    ("cell", "fp64"): 621961703.6, ("cell", "mixed32"): 383398658.0,
-    ("low_face", "fp64"): 183485511.1, ("low_face", "mixed32"): 175437614.7,
-    ("low_cell", "fp64"): 256286730.2, ("low_cell", "mixed32"): 242320412.4,  # 1 forcing + 5 step launches
-    ("sweep", "fp64"): 56988692.6, ("sweep", "mixed32"): 42739613.8,          # average over colour classes
-    ("prolong", "fp64"): 149430357.3, ("prolong", "mixed32"): 144009106.3,
-    ("dt", "mixed32_r64"): 79187082.7, ("recon", "mixed32_r64"): 648026034.8,
-    ("flux", "mixed32_r64"): 560729567.0, ("cell", "mixed32_r64"): 462545395.8,
-    ("low_face", "mixed32_r64"): 175438678.3, ("low_cell", "mixed32_r64"): 242221633.0,
-    ("sweep", "mixed32_r64"): 42750672.4, ("prolong", "mixed32_r64"): 144051222.9,
+    ("dt", "fp64"): 79187186.3, ("dt", "mixed32"): 79187117.7,
+    ("recon", "fp64"): 679224807.6, ("recon", "mixed32"): 632921917.0,   # with the boundary ghost pre-pass
+    ("flux", "fp64"): 727239387.9, ("flux", "mixed32"): 500359022.7,
+    ("cell", "fp64"): 563416994.5, ("cell", "mixed32"): 382768747.7,
+    ("low_face", "fp64"): 183610947.0, ("low_face", "mixed32"): 175542777.9,
+    ("low_cell", "fp64"): 256259519.0, ("low_cell", "mixed32"): 242142920.1,  # 1 forcing + 5 step launches
+    ("sweep", "fp64"): 56983133.4, ("sweep", "mixed32"): 42802570.1,          # average over colour classes
+    ("prolong", "fp64"): 149334136.4, ("prolong", "mixed32"): 144102496.0,
+    ("dt", "mixed32_r64"): 79187140.6, ("recon", "mixed32_r64"): 647552089.4,
+    ("flux", "mixed32_r64"): 560739536.3, ("cell", "mixed32_r64"): 401388582.6,
+    ("low_face", "mixed32_r64"): 175442471.6, ("low_cell", "mixed32_r64"): 242221521.3,
+    ("sweep", "mixed32_r64"): 42814922.6, ("prolong", "mixed32_r64"): 143886307.0,
 }
 
 
